@@ -1,0 +1,173 @@
+/*
+ * selfjoin.h -- C ABI of the MI355X (gfx950) epsilon-distance self-join.
+ *
+ * Problem (Gallet & Gowanlock, "Leveraging GPU Tensor Cores for Double
+ * Precision Euclidean Distance Calculations", Section II-A, Eq. (1)): given n
+ * points V in d dimensions (FP64) and a search distance eps, report every
+ * ordered pair (a, b) of V x V whose Euclidean distance is at most eps; each
+ * point pairs with itself (Section IV-A counts it in |R|).
+ *
+ * Exact result. A pair (i, j) is in R iff d2(i, j) <= fl(eps * eps), where
+ * d2 is accumulated over dimensions in ascending order starting at +0.0, each
+ * step delta = fl(x_i[t] - x_j[t]) then acc = fma(delta, delta, acc)
+ * (Section III-A, Eq. (2): the distance as a chain of multiply-accumulate
+ * steps). Every path below returns exactly this set; the low-precision and
+ * matrix-core paths reach it by re-evaluating, with this chain, every pair
+ * whose fast value lies inside a proven error band around eps^2.
+ *
+ * Method (Sections II-D, III-A, III-B): points are bucketed into a uniform grid
+ * with cells of side eps ("search"), and each group of queries from the same
+ * run of cells is refined against the points of the neighbouring cells with
+ * distance tiles in the expanded form |a|^2 + |b|^2 - 2 a.b (Eq. (3), Fig. 2),
+ * computed as matrix multiply-accumulate tiles on MFMA.
+ *
+ * Conventions for every function:
+ *  - Pointers marked "device" are device memory of the current HIP device
+ *    (e.g. a torch tensor's data_ptr()); "host" pointers are host memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued on it; a function returns after the host-visible
+ *    outputs it names (totals, cursors) are known, which synchronises that
+ *    stream. Device outputs are complete when the stream reaches that point.
+ *  - Calls never throw; they return a status. On error, outputs are left
+ *    unchanged except where stated; selfjoin_last_error() gives detail.
+ *  - Argument validation happens on the host before any device call, so an
+ *    invalid call returns SJ_ERR_INVALID even on a machine without a GPU.
+ */
+#ifndef SELFJOIN_H
+#define SELFJOIN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sj_grid sj_grid; /* opaque grid index handle */
+
+typedef enum {
+    SJ_OK = 0,
+    SJ_ERR_INVALID = 1,     /* bad argument or non-finite coordinate */
+    SJ_ERR_OOM = 2,         /* device allocation failed */
+    SJ_ERR_HIP = 3,         /* a HIP runtime call failed */
+    SJ_ERR_CAPACITY = 4,    /* output buffer too small (see selfjoin_pairs) */
+    SJ_ERR_UNSUPPORTED = 5  /* valid but not supported by this build */
+} sj_status;
+
+/* Distance-tile path. All return the same exact set R.
+ *  SJ_FP64_VALU : direct form of Eq. (1)/(2) on the FP64 vector ALU -- the
+ *                 comparison path (the paper's CUDA-core baseline role).
+ *  SJ_FP64_MFMA : Gram-form tiles (Eq. (3), Fig. 2) on FP64 MFMA.
+ *  SJ_FP32_MFMA : Gram-form tiles on FP32 MFMA with FP32 accumulation, inputs
+ *                 centred per work group; FP64 recheck of the band.
+ *  SJ_BF16_MFMA : as FP32 but BF16 inputs, FP32 accumulation.
+ * (Other MFMA precisions are the paper's future work, Section V.) */
+typedef enum {
+    SJ_FP64_VALU = 0,
+    SJ_FP64_MFMA = 1,
+    SJ_FP32_MFMA = 2,
+    SJ_BF16_MFMA = 3
+} sj_path;
+
+/* Build options; pass NULL for defaults. */
+typedef struct {
+    int32_t index_dims; /* number of leading dimensions indexed by the grid
+                           (Section II-D: fewer than d); 0 = min(d, 4). The
+                           result does not depend on it. */
+    int32_t reserved[7];
+} sj_opts;
+
+/* Statistics of one call (all optional, pass NULL). */
+typedef struct {
+    int64_t cand_ref;    /* C_ref: ordered candidate pairs of the full 3^k
+                            stencil of the reference grid (work unit) */
+    int64_t cand_eval;   /* candidate pairs the path evaluated, tile padding
+                            excluded */
+    int64_t pairs;       /* |R| for count; pairs written for pairs */
+    int64_t band_pairs;  /* pairs whose fast value fell inside the band and
+                            were re-evaluated with the FP64 chain */
+    double band_rel;     /* largest band half-width used, divided by eps^2 */
+    double ms;           /* device time of the call's kernels (ms) */
+} sj_stats;
+
+/* Grid facts (for tests and reports). */
+typedef struct {
+    int64_t n;
+    int32_t d, k;        /* dims, indexed dims */
+    int64_t cells;       /* non-empty cells */
+    int64_t items;       /* query groups (work items) */
+    double eps, eps2, cell_side;
+    int64_t cand_ref;    /* C_ref, as in sj_stats */
+    int64_t cand_items;  /* candidates seen by the work items (>= C_ref) */
+} sj_grid_info;
+
+/* Builds the grid index (Sections II-D, III-B) over `points`.
+ *  points : device, n x d row-major FP64, read during the call's stream work;
+ *           the library copies what it needs (sorted), so the caller may
+ *           release `points` once the stream has passed this call.
+ *  n      : 0 <= n < 2^31 (n = 0 gives an empty index).
+ *  d      : 1 <= d <= 256.
+ *  eps    : finite, > 0.
+ *  opts   : host, nullable.
+ *  out    : host; receives the handle (owned by the caller, release with
+ *           selfjoin_free_grid).
+ * Errors: SJ_ERR_INVALID for bad arguments or any non-finite coordinate
+ * (detected on the device), SJ_ERR_OOM, SJ_ERR_HIP. */
+sj_status selfjoin_build_grid(const double *points, int64_t n, int32_t d, double eps,
+                              const sj_opts *opts, void *stream, sj_grid **out);
+
+/* Counts R (Section IV-A selectivity needs |R|).
+ *  per_point : device int32[n] in the input order, or NULL; entry i receives
+ *              |{j : (i, j) in R}| (>= 1: the self-pair).
+ *  total     : host, receives |R|.
+ *  stats     : host, nullable.
+ * The count is cached on the handle and reused by selfjoin_pairs. */
+sj_status selfjoin_count(sj_grid *g, sj_path path, int32_t *per_point, int64_t *total,
+                         sj_stats *stats, void *stream);
+
+/* Writes pairs of R, one chunk per call (result batching, Section III-B:
+ * the result may exceed device memory).
+ *  cursor      : first query to emit, in the grid's query order (0 = start;
+ *                pass back *next_cursor to continue).
+ *  pairs       : device int32[capacity][2], rows (i, j) in input indices.
+ *  d2          : device double[capacity] or NULL; receives d2(i, j) of each
+ *                written pair, computed with the exact chain above.
+ *  capacity    : rows available in pairs (and d2).
+ *  written     : host, pairs written.
+ *  next_cursor : host, the cursor to pass next; n when done.
+ * Every chunk holds all pairs of whole queries, in query order and, per
+ * query, in candidate order; the order is deterministic. If the next query's
+ * pairs do not fit, returns SJ_ERR_CAPACITY and sets *written to the capacity
+ * that query needs (nothing else is written). */
+sj_status selfjoin_pairs(sj_grid *g, sj_path path, int64_t cursor, int32_t *pairs, double *d2,
+                         int64_t capacity, int64_t *written, int64_t *next_cursor,
+                         sj_stats *stats, void *stream);
+
+/* Debug measurement of a path's fast values against the exact chain: runs the
+ * path over every evaluated candidate pair whose exact d2 is at most
+ * 4 * eps^2 and reports the largest |fast - exact| (max_abs_err), the
+ * largest band half-width used (max_band), and how many pairs had an error
+ * larger than their band (violations; must be 0). Slow; not for timing. */
+sj_status selfjoin_measure_error(sj_grid *g, sj_path path, double *max_abs_err, double *max_band,
+                                 int64_t *violations, void *stream);
+
+/* Grid facts of a built handle. */
+sj_status selfjoin_grid_info(const sj_grid *g, sj_grid_info *info);
+
+/* Releases the handle; its device memory is freed in stream order on
+ * `stream`. NULL is accepted. */
+void selfjoin_free_grid(sj_grid *g, void *stream);
+
+/* Static text for a status. */
+const char *selfjoin_status_string(sj_status s);
+
+/* Detail of the last error on the calling thread ("" if none). */
+const char *selfjoin_last_error(void);
+
+/* Library version string. */
+const char *selfjoin_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SELFJOIN_H */

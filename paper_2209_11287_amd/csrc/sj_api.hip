@@ -1,0 +1,293 @@
+// The C ABI (include/selfjoin.h): validation, error mapping, allocation,
+// counts cache, chunked pair output.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "sj_internal.h"
+
+namespace sj {
+
+namespace {
+thread_local std::string g_err;
+
+__global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
+
+__global__ void k_scatter_counts(const int32_t *__restrict__ cnt, const int32_t *__restrict__ perm, int64_t n,
+                                 int32_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[perm[i]] = cnt[i];
+}
+
+void pool_setup_once() {
+    static thread_local int done_dev = -1;
+    int dev = 0;
+    SJ_HIP(hipGetDevice(&dev));
+    if (done_dev == dev) return;
+    hipMemPool_t pool;
+    SJ_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+    uint64_t thr = UINT64_MAX;
+    SJ_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+    done_dev = dev;
+}
+}  // namespace
+
+void set_error(const std::string &msg) { g_err = msg; }
+const char *last_error() { return g_err.c_str(); }
+
+void *dev_alloc(size_t bytes, hipStream_t s) {
+    pool_setup_once();
+    void *p = nullptr;
+    hipError_t e = hipMallocAsync(&p, bytes, s);
+    if (e == hipErrorOutOfMemory || (e == hipSuccess && !p)) throw OomError{bytes};
+    if (e != hipSuccess) throw HipError{e, "hipMallocAsync"};
+    return p;
+}
+
+void dev_free(void *p, hipStream_t s) {
+    if (p) (void)hipFreeAsync(p, s);
+}
+
+// Computes per-query counts with `path` into the handle's cache (sorted
+// order), their exclusive prefix sums and the total.
+static void compute_counts(Grid &g, sj_path path, RefineOut &ro, hipStream_t s) {
+    if (!g.cnt) {
+        g.cnt = dev_alloc_n<int32_t>((size_t)g.n + 1, s);
+        g.off = dev_alloc_n<int64_t>((size_t)g.n + 1, s);
+    }
+    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, g.cnt + g.n, 0);
+    SJ_HIP(hipGetLastError());
+    if (g.n > 0) refine_count(g, path, g.cnt, ro, s);
+    exclusive_scan_i32_to_i64(g.cnt, g.off, g.n + 1, s);
+    int64_t total = 0;
+    SJ_HIP(hipMemcpyAsync(&total, g.off + g.n, sizeof total, hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    g.total = total;
+    g.have_counts = true;
+}
+
+}  // namespace sj
+
+using namespace sj;
+
+#define SJ_API_BEGIN try {
+#define SJ_API_END                                                                         \
+    }                                                                                      \
+    catch (const HipError &e) {                                                            \
+        set_error(e.where + ": " + hipGetErrorString(e.code));                             \
+        return SJ_ERR_HIP;                                                                 \
+    }                                                                                      \
+    catch (const OomError &e) {                                                            \
+        set_error("device allocation of " + std::to_string(e.bytes) + " bytes failed");    \
+        return SJ_ERR_OOM;                                                                 \
+    }                                                                                      \
+    catch (const std::bad_alloc &) {                                                       \
+        set_error("host allocation failed");                                               \
+        return SJ_ERR_OOM;                                                                 \
+    }                                                                                      \
+    catch (const Unsupported &u) {                                                         \
+        set_error(u.what);                                                                 \
+        return SJ_ERR_UNSUPPORTED;                                                         \
+    }                                                                                      \
+    catch (const std::string &msg) {                                                       \
+        set_error(msg);                                                                    \
+        return SJ_ERR_INVALID;                                                             \
+    }                                                                                      \
+    catch (...) {                                                                          \
+        set_error("unexpected exception");                                                 \
+        return SJ_ERR_HIP;                                                                 \
+    }
+
+static sj_status invalid(const char *msg) {
+    set_error(msg);
+    return SJ_ERR_INVALID;
+}
+
+static bool valid_path(sj_path p) {
+    return p == SJ_FP64_VALU || p == SJ_FP64_MFMA || p == SJ_FP32_MFMA || p == SJ_BF16_MFMA;
+}
+
+extern "C" {
+
+sj_status selfjoin_build_grid(const double *points, int64_t n, int32_t d, double eps, const sj_opts *opts,
+                              void *stream, sj_grid **out) {
+    set_error("");
+    if (!out) return invalid("out is NULL");
+    if (n < 0 || n >= (int64_t(1) << 31)) return invalid("n must be in [0, 2^31)");
+    if (d < 1 || d > kMaxDims) return invalid("d must be in [1, 256]");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return invalid("eps must be finite and > 0");
+    if (n > 0 && !points) return invalid("points is NULL");
+    if (opts && (opts->index_dims < 0 || opts->index_dims > kMaxIndexDims))
+        return invalid("index_dims must be in [0, 4]");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    sj_grid *h = nullptr;
+    SJ_API_BEGIN
+    h = new sj_grid();
+    try {
+        build_grid(h->g, points, n, d, eps, opts ? opts->index_dims : 0, s);
+    } catch (...) {
+        free_grid(h->g, s);
+        delete h;
+        h = nullptr;
+        throw;
+    }
+    *out = h;
+    return SJ_OK;
+    SJ_API_END
+}
+
+sj_status selfjoin_count(sj_grid *gh, sj_path path, int32_t *per_point, int64_t *total, sj_stats *stats,
+                         void *stream) {
+    set_error("");
+    if (!gh) return invalid("grid is NULL");
+    if (!valid_path(path)) return invalid("unknown path");
+    if (!total) return invalid("total is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SJ_API_BEGIN
+    Grid &g = gh->g;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (stats) {
+        SJ_HIP(hipEventCreate(&e0));
+        SJ_HIP(hipEventCreate(&e1));
+        SJ_HIP(hipEventRecord(e0, s));
+    }
+    RefineOut ro;
+    compute_counts(g, path, ro, s);
+    if (per_point && g.n > 0) {
+        hipLaunchKernelGGL(k_scatter_counts, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s, g.cnt, g.perm,
+                           g.n, per_point);
+        SJ_HIP(hipGetLastError());
+    }
+    *total = g.total;
+    if (stats) {
+        SJ_HIP(hipEventRecord(e1, s));
+        SJ_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        SJ_HIP(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        stats->cand_ref = g.cand_ref;
+        stats->cand_eval = ro.cand_eval;
+        stats->pairs = g.total;
+        stats->band_pairs = ro.band_pairs;
+        stats->band_rel = ro.band_rel;
+        stats->ms = ms;
+    }
+    return SJ_OK;
+    SJ_API_END
+}
+
+sj_status selfjoin_pairs(sj_grid *gh, sj_path path, int64_t cursor, int32_t *pairs, double *d2, int64_t capacity,
+                         int64_t *written, int64_t *next_cursor, sj_stats *stats, void *stream) {
+    set_error("");
+    if (!gh) return invalid("grid is NULL");
+    if (!valid_path(path)) return invalid("unknown path");
+    if (!written || !next_cursor) return invalid("written / next_cursor is NULL");
+    if (cursor < 0 || cursor > gh->g.n) return invalid("cursor out of range");
+    if (capacity < 0) return invalid("capacity < 0");
+    if (capacity > 0 && !pairs) return invalid("pairs is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SJ_API_BEGIN
+    Grid &g = gh->g;
+    if (cursor == g.n) {
+        *written = 0;
+        *next_cursor = g.n;
+        return SJ_OK;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (stats) {
+        SJ_HIP(hipEventCreate(&e0));
+        SJ_HIP(hipEventCreate(&e1));
+        SJ_HIP(hipEventRecord(e0, s));
+    }
+    RefineOut ro;
+    if (!g.have_counts) compute_counts(g, path, ro, s);
+    const ChunkPlan p = plan_chunk(g, cursor, capacity, s);
+    if (p.too_small) {
+        *written = p.written;
+        if (stats) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+        }
+        set_error("capacity too small for the next query's pairs");
+        return SJ_ERR_CAPACITY;
+    }
+    refine_pairs(g, path, p, cursor, pairs, d2, s);
+    *written = p.written;
+    *next_cursor = p.next;
+    if (stats) {
+        SJ_HIP(hipEventRecord(e1, s));
+        SJ_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        SJ_HIP(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        stats->cand_ref = g.cand_ref;
+        stats->cand_eval = ro.cand_eval;
+        stats->pairs = p.written;
+        stats->band_pairs = ro.band_pairs;
+        stats->band_rel = ro.band_rel;
+        stats->ms = ms;
+    }
+    return SJ_OK;
+    SJ_API_END
+}
+
+sj_status selfjoin_measure_error(sj_grid *gh, sj_path path, double *max_abs_err, double *max_band,
+                                 int64_t *violations, void *stream) {
+    set_error("");
+    if (!gh) return invalid("grid is NULL");
+    if (!valid_path(path)) return invalid("unknown path");
+    if (!max_abs_err || !max_band || !violations) return invalid("NULL output");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SJ_API_BEGIN
+    refine_measure(gh->g, path, max_abs_err, max_band, violations, s);
+    return SJ_OK;
+    SJ_API_END
+}
+
+sj_status selfjoin_grid_info(const sj_grid *gh, sj_grid_info *info) {
+    if (!gh || !info) return invalid("NULL argument");
+    const Grid &g = gh->g;
+    info->n = g.n;
+    info->d = g.d;
+    info->k = g.k;
+    info->cells = g.cells;
+    info->items = g.items;
+    info->eps = g.eps;
+    info->eps2 = g.eps2;
+    info->cell_side = g.w;
+    info->cand_ref = g.cand_ref;
+    info->cand_items = g.cand_items;
+    return SJ_OK;
+}
+
+void selfjoin_free_grid(sj_grid *gh, void *stream) {
+    if (!gh) return;
+    try {
+        free_grid(gh->g, static_cast<hipStream_t>(stream));
+    } catch (...) {
+    }
+    delete gh;
+}
+
+const char *selfjoin_status_string(sj_status s) {
+    switch (s) {
+        case SJ_OK: return "ok";
+        case SJ_ERR_INVALID: return "invalid argument";
+        case SJ_ERR_OOM: return "out of memory";
+        case SJ_ERR_HIP: return "HIP runtime error";
+        case SJ_ERR_CAPACITY: return "output capacity too small";
+        case SJ_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *selfjoin_last_error(void) { return last_error(); }
+
+const char *selfjoin_version(void) { return "selfjoin-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,761 @@
+// Grid index build on the GPU: the "search" structure of the self-join
+// (Section II-D: a grid is searched for candidates, which are then refined;
+// Section III-B: cells of side eps, every query of a cell shares the cell's
+// candidate set, so queries must be grouped by cell).
+//
+// Steps: bounding box -> cell keys -> LSD radix sort (key, index) -> gather of
+// sorted rows and squared norms (the precomputed P of Section III-A) -> cell
+// table -> grid lines and work items -> per-cell neighbour ranges.
+//
+// Grid geometry (the paper fixes the cell side only): origin = per-dimension
+// minimum, cell side w = eps * (1 + 2^-19) (a pair within eps then never lands
+// two cells apart after rounding), k leading dimensions indexed, last indexed
+// dimension fastest in the key, so the three cells along it that neighbour a
+// cell are contiguous in sorted order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "sj_internal.h"
+
+namespace sj {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ unsigned long long lanemask_lt() {
+    const unsigned lane = threadIdx.x & 63u;
+    return lane ? ((~0ull) >> (64u - lane)) : 0ull;
+}
+
+// Order-preserving integer image of a double (for min/max reductions).
+__device__ __forceinline__ unsigned long long dbl_to_ord(double v) {
+    unsigned long long u = __double_as_longlong(v);
+    return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+__host__ __device__ __forceinline__ double ord_to_dbl(unsigned long long u) {
+    unsigned long long b = (u & 0x8000000000000000ull) ? (u & 0x7fffffffffffffffull) : ~u;
+    double r;
+    std::memcpy(&r, &b, sizeof r);
+    return r;
+}
+
+__global__ void k_fill_u8(unsigned char *p, size_t bytes) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < bytes; i += stride) p[i] = 0;
+}
+
+
+// ---------------------------------------------------------------- bbox ----
+// Each block reduces a contiguous run of rows. Threads walk the run's
+// elements with a stride that is a multiple of d, so each thread sees a single
+// dimension; per-dimension partials then go to memory.
+__global__ void k_bbox_partial(const double *__restrict__ X, int64_t n, int d, int64_t rows_per_block,
+                               double *__restrict__ pmin, double *__restrict__ pmax,
+                               int *__restrict__ bad) {
+    __shared__ double smin[kThreads], smax[kThreads];
+    const int S = (kThreads / d) * d;
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = min(n, r0 + rows_per_block);
+    double mn = INFINITY, mx = -INFINITY;
+    int nonfinite = 0;
+    if (tid < S && r0 < r1) {
+        const int64_t e0 = r0 * d, e1 = r1 * d;
+        for (int64_t e = e0 + tid; e < e1; e += S) {
+            double v = X[e];
+            nonfinite |= !isfinite(v);
+            mn = fmin(mn, v);
+            mx = fmax(mx, v);
+        }
+    }
+    smin[tid] = mn;
+    smax[tid] = mx;
+    if (nonfinite) atomicOr(bad, 1);
+    __syncthreads();
+    if (tid < d) {
+        double a = INFINITY, b = -INFINITY;
+        for (int t = tid; t < S; t += d) {
+            a = fmin(a, smin[t]);
+            b = fmax(b, smax[t]);
+        }
+        pmin[(int64_t)blockIdx.x * d + tid] = a;
+        pmax[(int64_t)blockIdx.x * d + tid] = b;
+    }
+}
+
+__global__ void k_bbox_final(const double *__restrict__ pmin, const double *__restrict__ pmax, int nb,
+                             int d, double *__restrict__ out /* lo[d], hi[d] */) {
+    __shared__ double smin[kThreads], smax[kThreads];
+    const int j = blockIdx.x;
+    double a = INFINITY, b = -INFINITY;
+    for (int t = threadIdx.x; t < nb; t += blockDim.x) {
+        a = fmin(a, pmin[(int64_t)t * d + j]);
+        b = fmax(b, pmax[(int64_t)t * d + j]);
+    }
+    smin[threadIdx.x] = a;
+    smax[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + w]);
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[j] = smin[0];
+        out[d + j] = smax[0];
+    }
+}
+
+// ---------------------------------------------------------------- keys ----
+struct KeyGeom {
+    int k, d;
+    double w;
+    double lo[kMaxIndexDims];
+    int64_t m[kMaxIndexDims];
+    int64_t stride[kMaxIndexDims];
+};
+
+__global__ void k_keys(const double *__restrict__ X, int64_t n, KeyGeom geo,
+                       unsigned long long *__restrict__ key, int32_t *__restrict__ idx) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    unsigned long long kk = 0;
+    for (int j = 0; j < geo.k; ++j) {
+        // c = floor(fl(fl(x - lo) / w)), clamped: the same two roundings as
+        // the reference grid definition.
+        double q = floor(__ddiv_rn(__dsub_rn(X[i * geo.d + j], geo.lo[j]), geo.w));
+        int64_t c = (int64_t)q;
+        c = c < 0 ? 0 : (c > geo.m[j] - 1 ? geo.m[j] - 1 : c);
+        kk += (unsigned long long)c * (unsigned long long)geo.stride[j];
+    }
+    key[i] = kk;
+    idx[i] = (int32_t)i;
+}
+
+// ----------------------------------------------------------- radix sort ----
+// Stable LSD radix sort of (64-bit key, int32 value), 8-bit digits. Each
+// block owns a tile of kThreads * kRsItems keys. Pass = per-tile digit
+// histogram -> exclusive scan in digit-major order -> stable scatter where a
+// key's rank inside its tile comes from a wave-wide match of its digit (eight
+// ballots) plus per-wave digit counts combined in LDS.
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kThreads * kRsItems;
+
+__global__ void k_rs_hist(const unsigned long long *__restrict__ key, int64_t n, int shift,
+                          int32_t *__restrict__ hist, int nblocks) {
+    __shared__ int32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t t0 = (int64_t)blockIdx.x * kRsTile;
+    for (int r = 0; r < kRsItems; ++r) {
+        int64_t i = t0 + (int64_t)r * kThreads + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(key[i] >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ void k_rs_scatter(const unsigned long long *__restrict__ kin, const int32_t *__restrict__ vin,
+                             unsigned long long *__restrict__ kout, int32_t *__restrict__ vout,
+                             int64_t n, int shift, const int32_t *__restrict__ hist_ex, int nblocks) {
+    __shared__ int32_t run[256];
+    __shared__ int32_t wcnt[kThreads / 64][256];
+    __shared__ int32_t wpre[kThreads / 64][256];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    run[tid] = hist_ex[(int64_t)tid * nblocks + blockIdx.x];
+    for (int w = 0; w < kThreads / 64; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const int64_t t0 = (int64_t)blockIdx.x * kRsTile;
+    const unsigned long long lt = lanemask_lt();
+    for (int r = 0; r < kRsItems; ++r) {
+        const int64_t i = t0 + (int64_t)r * kThreads + tid;
+        const bool valid = i < n;
+        unsigned long long kk = 0;
+        int32_t vv = 0;
+        unsigned digit = 0;
+        if (valid) {
+            kk = kin[i];
+            vv = vin[i];
+            digit = (unsigned)((kk >> shift) & 255u);
+        }
+        unsigned long long peers = __ballot(valid);
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (digit >> b) & 1u;
+            const unsigned long long m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const int rank = __popcll(peers & lt);
+        if (valid && rank == 0) wcnt[wave][digit] = __popcll(peers);
+        __syncthreads();
+        {
+            int32_t acc = run[tid];
+            for (int w = 0; w < kThreads / 64; ++w) {
+                wpre[w][tid] = acc;
+                acc += wcnt[w][tid];
+                wcnt[w][tid] = 0;
+            }
+            run[tid] = acc;
+        }
+        __syncthreads();
+        if (valid) {
+            const int32_t pos = wpre[wave][digit] + rank;
+            kout[pos] = kk;
+            vout[pos] = vv;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- scans ----
+// Exclusive scan, three phases: per-tile sums, scan of the tile sums
+// (recursively), per-tile scan plus carry. Tile = kThreads * kScanItems.
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kThreads * kScanItems;
+
+template <typename Tin, typename Tacc>
+__global__ void k_scan_sums(const Tin *__restrict__ in, int64_t n, Tacc *__restrict__ sums) {
+    __shared__ Tacc part[kThreads / 64];
+    const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
+    Tacc acc = 0;
+    for (int r = 0; r < kScanItems; ++r) {
+        int64_t i = t0 + (int64_t)r * kThreads + threadIdx.x;
+        if (i < n) acc += (Tacc)in[i];
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Tacc s = 0;
+        for (int w = 0; w < kThreads / 64; ++w) s += part[w];
+        sums[blockIdx.x] = s;
+    }
+}
+
+// Exclusive scan of one tile with a carry-in from `carry` (nullable).
+template <typename Tin, typename Tacc>
+__global__ void k_scan_tiles(const Tin *__restrict__ in, Tacc *__restrict__ out, int64_t n,
+                             const Tacc *__restrict__ carry) {
+    __shared__ Tacc wtot[kThreads / 64];
+    __shared__ Tacc base;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) base = carry ? carry[blockIdx.x] : (Tacc)0;
+    __syncthreads();
+    const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
+    for (int r = 0; r < kScanItems; ++r) {
+        const int64_t i = t0 + (int64_t)r * kThreads + tid;
+        const Tacc v = i < n ? (Tacc)in[i] : (Tacc)0;
+        Tacc x = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            Tacc y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wtot[wave] = x;
+        __syncthreads();
+        Tacc pre = base;
+        for (int w = 0; w < wave; ++w) pre += wtot[w];
+        if (i < n) out[i] = pre + x - v;
+        __syncthreads();
+        if (tid == kThreads - 1) {
+            Tacc s = base;
+            for (int w = 0; w < kThreads / 64; ++w) s += wtot[w];
+            base = s;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename Tin, typename Tacc>
+void exclusive_scan(const Tin *in, Tacc *out, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+    if (tiles == 1) {
+        hipLaunchKernelGGL((k_scan_tiles<Tin, Tacc>), dim3(1), dim3(kThreads), 0, s, in, out, n,
+                           (const Tacc *)nullptr);
+        SJ_HIP(hipGetLastError());
+        return;
+    }
+    Tacc *sums = dev_alloc_n<Tacc>(tiles, s);
+    Tacc *sums_ex = dev_alloc_n<Tacc>(tiles, s);
+    hipLaunchKernelGGL((k_scan_sums<Tin, Tacc>), dim3((unsigned)tiles), dim3(kThreads), 0, s, in, n, sums);
+    SJ_HIP(hipGetLastError());
+    exclusive_scan<Tacc, Tacc>(sums, sums_ex, tiles, s);
+    hipLaunchKernelGGL((k_scan_tiles<Tin, Tacc>), dim3((unsigned)tiles), dim3(kThreads), 0, s, in, out, n,
+                       (const Tacc *)sums_ex);
+    SJ_HIP(hipGetLastError());
+    dev_free(sums, s);
+    dev_free(sums_ex, s);
+}
+
+// ---------------------------------------------------------- gather/norms ----
+// Sorted copies: xs = original rows (stride dp, zero padded), xa = rows
+// centred on `mid` (stride da); nrm = squared norm of the xa row, the FP64
+// chain over dimensions in order. When d % 4 != 0 the norm also sits in xa's
+// slot d, where the MFMA tile multiplies it by 1 (Eq. (4) keeps the norms off
+// the tensor cores; here a spare K slot takes them).
+struct GatherArgs {
+    int d, dp, da;
+    double mid[kMaxDims];
+};
+
+__global__ void k_gather(const double *__restrict__ X, const int32_t *__restrict__ perm, int64_t n,
+                         const GatherArgs ga_v, double *__restrict__ xs,
+                         double *__restrict__ xa, double *__restrict__ nrm,
+                         unsigned long long *__restrict__ nmax_ord) {
+    const GatherArgs *ga = &ga_v;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double nn = 0.0;
+    if (i < n) {
+        const int d = ga->d, dp = ga->dp, da = ga->da;
+        const double *src = X + (int64_t)perm[i] * d;
+        double *ps = xs + i * dp;
+        double *pa = xa + i * da;
+        for (int t = 0; t < d; ++t) {
+            const double v = src[t];
+            const double c = __dsub_rn(v, ga->mid[t]);
+            ps[t] = v;
+            pa[t] = c;
+            nn = __fma_rn(c, c, nn);
+        }
+        for (int t = d; t < dp; ++t) ps[t] = 0.0;
+        for (int t = d; t < da; ++t) pa[t] = 0.0;
+        if (d & 3) pa[d] = nn;
+        nrm[i] = nn;
+    }
+    // norms are >= 0: their bit patterns order like their values
+    for (int o = 32; o > 0; o >>= 1) nn = fmax(nn, __shfl_xor(nn, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(nmax_ord, (unsigned long long)__double_as_longlong(nn));
+}
+
+// ----------------------------------------------------------- cell table ----
+__global__ void k_cell_flags(const unsigned long long *__restrict__ key, int64_t n,
+                             int32_t *__restrict__ flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+}
+
+__global__ void k_cell_write(const unsigned long long *__restrict__ key, const int32_t *__restrict__ flag,
+                             const int32_t *__restrict__ cid, int64_t n, int64_t *__restrict__ cell_key,
+                             int32_t *__restrict__ cell_start, int32_t *__restrict__ ncells) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (flag[i]) {
+        cell_key[cid[i]] = (int64_t)key[i];
+        cell_start[cid[i]] = (int32_t)i;
+    }
+    if (i == n - 1) {
+        const int32_t c = cid[i] + flag[i];
+        *ncells = c;
+        cell_start[c] = (int32_t)n;
+    }
+}
+
+// Line of a cell: its key without the last indexed coordinate.
+__global__ void k_line_flags(const int64_t *__restrict__ cell_key, const int32_t *__restrict__ ncells_p,
+                             int64_t m_last, int32_t *__restrict__ lflag) {
+    const int64_t ncells = *ncells_p;
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    lflag[c] = (c == 0 || cell_key[c] / m_last != cell_key[c - 1] / m_last) ? 1 : 0;
+}
+
+// Per line: first cell, and the number of work items (ceil(points / kTileQ)).
+__global__ void k_line_write(const int32_t *__restrict__ lflag, const int32_t *__restrict__ lid,
+                             const int32_t *__restrict__ cell_start, const int32_t *__restrict__ ncells_p,
+                             int32_t *__restrict__ line_first, int32_t *__restrict__ nlines_p) {
+    const int64_t ncells = *ncells_p;
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    if (lflag[c]) line_first[lid[c]] = (int32_t)c;
+    if (c == ncells - 1) {
+        const int32_t L = lid[c] + lflag[c];
+        *nlines_p = L;
+        line_first[L] = (int32_t)ncells;
+    }
+}
+
+__global__ void k_line_items(const int32_t *__restrict__ line_first, const int32_t *__restrict__ cell_start,
+                             const int32_t *__restrict__ nlines_p, int32_t *__restrict__ nitem) {
+    const int64_t L = *nlines_p;
+    int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= L) return;
+    const int32_t pts = cell_start[line_first[l + 1]] - cell_start[line_first[l]];
+    nitem[l] = (pts + kTileQ - 1) / kTileQ;
+}
+
+__global__ void k_items_total(const int32_t *__restrict__ nitem, const int32_t *__restrict__ item_off,
+                              const int32_t *__restrict__ nlines_p, int32_t *__restrict__ nitems_p) {
+    const int32_t L = *nlines_p;
+    *nitems_p = L > 0 ? item_off[L - 1] + nitem[L - 1] : 0;
+}
+
+// Largest index p in [a, b) with v[p] <= x (v ascending, v[a] <= x).
+__device__ __forceinline__ int32_t last_le(const int32_t *v, int32_t a, int32_t b, int32_t x) {
+    while (b - a > 1) {
+        const int32_t mid = a + (b - a) / 2;
+        if (v[mid] <= x) a = mid;
+        else b = mid;
+    }
+    return a;
+}
+
+__global__ void k_items(const int32_t *__restrict__ line_first, const int32_t *__restrict__ item_off,
+                        const int32_t *__restrict__ cell_start, const int32_t *__restrict__ nlines_p,
+                        const int32_t *__restrict__ nitems_p, Item *__restrict__ items) {
+    const int32_t L = *nlines_p;
+    const int32_t I = *nitems_p;
+    int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= I) return;
+    // line of this item: last l with item_off[l] <= it
+    const int32_t l = last_le(item_off, 0, L, (int32_t)it);
+    const int32_t c0 = line_first[l], c1 = line_first[l + 1];
+    const int32_t p0 = cell_start[c0], p1 = cell_start[c1];
+    const int32_t qb = p0 + ((int32_t)it - item_off[l]) * kTileQ;
+    const int32_t qe = min(qb + kTileQ, p1);
+    Item r;
+    r.qbegin = qb;
+    r.qend = qe;
+    r.cell_first = last_le(cell_start, c0, c1, qb);
+    r.cell_last = last_le(cell_start, c0, c1, qe - 1);
+    items[it] = r;
+}
+
+// ------------------------------------------------------- neighbour ranges ----
+// For cell c and each offset o in {-1,0,1}^(k-1) of the leading indexed
+// coordinates, the sorted-point range of the cells whose leading coordinates
+// are c's plus o and whose last coordinate is within one of c's (three cells
+// adjacent in key order, hence one contiguous range). Out-of-grid offsets give
+// an empty range. Also accumulates C_ref = sum_c |c| * (candidates of c).
+struct RangeGeom {
+    int k, nranges;
+    int64_t m[kMaxIndexDims];
+    int64_t stride[kMaxIndexDims];
+};
+
+__device__ __forceinline__ int64_t lower_bound_i64(const int64_t *v, int64_t n, int64_t x) {
+    int64_t a = 0, b = n;
+    while (a < b) {
+        const int64_t mid = a + (b - a) / 2;
+        if (v[mid] < x) a = mid + 1;
+        else b = mid;
+    }
+    return a;
+}
+
+__global__ void k_ranges(const int64_t *__restrict__ cell_key, const int32_t *__restrict__ cell_start,
+                         const int32_t *__restrict__ ncells_p, RangeGeom geo, Range *__restrict__ ranges,
+                         unsigned long long *__restrict__ cref) {
+    const int64_t ncells = *ncells_p;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long contrib = 0;
+    if (t < ncells * geo.nranges) {
+        const int64_t c = t / geo.nranges;
+        int o = (int)(t - c * geo.nranges);
+        int64_t key = cell_key[c];
+        int64_t cc[kMaxIndexDims];
+        for (int j = 0; j < geo.k; ++j) {
+            cc[j] = key / geo.stride[j];
+            key -= cc[j] * geo.stride[j];
+        }
+        bool ok = true;
+        int64_t base = 0;
+        for (int j = 0; j < geo.k - 1; ++j) {
+            const int64_t cj = cc[j] + (o % 3) - 1;
+            o /= 3;
+            if (cj < 0 || cj >= geo.m[j]) ok = false;
+            base += cj * geo.stride[j];
+        }
+        Range r{0, 0};
+        if (ok) {
+            const int kl = geo.k - 1;
+            const int64_t lo = base + (cc[kl] > 0 ? cc[kl] - 1 : 0);
+            const int64_t hi = base + (cc[kl] < geo.m[kl] - 1 ? cc[kl] + 1 : cc[kl]);
+            const int64_t a = lower_bound_i64(cell_key, ncells, lo);
+            const int64_t b = lower_bound_i64(cell_key, ncells, hi + 1);
+            r.begin = cell_start[a];
+            r.end = cell_start[b];
+        }
+        ranges[t] = r;
+        contrib = (unsigned long long)(cell_start[c + 1] - cell_start[c]) * (unsigned long long)(r.end - r.begin);
+    }
+    for (int o2 = 32; o2 > 0; o2 >>= 1) contrib += __shfl_xor(contrib, o2);
+    if ((threadIdx.x & 63) == 0 && contrib) atomicAdd(cref, contrib);
+}
+
+// Candidates the work items see: sum over items of |queries| * |union ranges|.
+__global__ void k_item_cands(const Item *__restrict__ items, const int32_t *__restrict__ nitems_p,
+                             const Range *__restrict__ ranges, int nranges, unsigned long long *__restrict__ out) {
+    const int64_t nitems = *nitems_p;
+    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long v = 0;
+    if (it < nitems) {
+        const Item I = items[it];
+        unsigned long long s = 0;
+        for (int o = 0; o < nranges; ++o)
+            s += (unsigned long long)(ranges[(int64_t)I.cell_last * nranges + o].end -
+                                      ranges[(int64_t)I.cell_first * nranges + o].begin);
+        v = s * (unsigned long long)(I.qend - I.qbegin);
+    }
+    for (int o2 = 32; o2 > 0; o2 >>= 1) v += __shfl_xor(v, o2);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(out, v);
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+void fill_zero(void *p, size_t bytes, hipStream_t s) {
+    if (!bytes) return;
+    unsigned blocks = (unsigned)std::min<size_t>((bytes + kThreads - 1) / kThreads, 4096);
+    hipLaunchKernelGGL(k_fill_u8, dim3(blocks), dim3(kThreads), 0, s, (unsigned char *)p, bytes);
+    SJ_HIP(hipGetLastError());
+}
+
+void exclusive_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s) {
+    exclusive_scan<int32_t, int64_t>(in, out, n, s);
+}
+
+void free_grid(Grid &g, hipStream_t s) {
+    void *bufs[] = {g.xs, g.xa, g.nrm, g.perm, g.cell_key, g.cell_start, g.ranges, g.item, g.dev_nmax, g.cnt, g.off};
+    for (void *p : bufs)
+        if (p) dev_free(p, s);
+    g.xs = g.xa = g.nrm = nullptr;
+    g.perm = nullptr;
+    g.cell_key = nullptr;
+    g.cell_start = nullptr;
+    g.ranges = nullptr;
+    g.item = nullptr;
+    g.dev_nmax = nullptr;
+    g.cnt = nullptr;
+    g.off = nullptr;
+}
+
+// Host-side reading of the grid geometry; identical arithmetic to the
+// reference definition (floor((max - min) / w) + 1 cells per dimension).
+static void choose_geometry(Grid &g, int index_dims) {
+    const double w = g.eps * (1.0 + 0x1p-19);
+    g.w = w;
+    int k = index_dims > 0 ? std::min(index_dims, std::min(g.d, kMaxIndexDims))
+                           : std::min(g.d, kMaxIndexDims);
+    for (;;) {
+        double prod = 1.0;
+        for (int j = 0; j < k; ++j) {
+            g.m[j] = (int64_t)std::floor((g.hi[j] - g.lo[j]) / w) + 1;
+            prod *= (double)g.m[j];
+        }
+        if (prod < 0x1p62 || k == 1) break;
+        --k;
+    }
+    if ((double)g.m[0] >= 0x1p62) throw std::string("grid too fine: eps is too small for the data extent");
+    g.k = k;
+    int64_t st = 1;
+    for (int j = k - 1; j >= 0; --j) {
+        g.stride[j] = st;
+        st *= g.m[j];
+    }
+    const unsigned long long maxkey = (unsigned long long)st - 1ull;
+    int bits = 0;
+    while (bits < 64 && (maxkey >> bits) != 0ull) ++bits;
+    g.key_bits = bits;
+    g.nranges = 1;
+    for (int j = 0; j < k - 1; ++j) g.nranges *= 3;
+}
+
+void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int index_dims,
+                hipStream_t s) {
+    g.n = n;
+    g.d = d;
+    g.eps = eps;
+    g.eps2 = eps * eps;
+    g.dp = (d + 3) & ~3;
+    g.da = (d & 3) ? ((d + 1 + 3) & ~3) : d;
+    g.build_stream = s;
+    const size_t rows = (size_t)n + kRowPad;
+
+    // ---- G1: bounding box and finiteness (one host sync) ----
+    if (n == 0) {
+        for (int j = 0; j < d; ++j) g.lo[j] = g.hi[j] = g.mid[j] = 0.0;
+    } else {
+        const int64_t rows_per_block = std::max<int64_t>(1024, (n + 2047) / 2048);
+        const int nb = (int)std::max<int64_t>(1, (n + rows_per_block - 1) / rows_per_block);
+        double *pmin = dev_alloc_n<double>((size_t)nb * d, s);
+        double *pmax = dev_alloc_n<double>((size_t)nb * d, s);
+        double *box = dev_alloc_n<double>(2 * (size_t)d + 1, s);
+        int *bad = reinterpret_cast<int *>(box + 2 * d);
+        fill_zero(bad, sizeof(int), s);
+        hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(kThreads), 0, s, points, n, d, rows_per_block,
+                           pmin, pmax, bad);
+        SJ_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_bbox_final, dim3(d), dim3(kThreads), 0, s, pmin, pmax, nb, d, box);
+        SJ_HIP(hipGetLastError());
+        std::vector<double> hb(2 * (size_t)d + 1);
+        SJ_HIP(hipMemcpyAsync(hb.data(), box, (2 * (size_t)d + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        SJ_HIP(hipStreamSynchronize(s));
+        dev_free(pmin, s);
+        dev_free(pmax, s);
+        dev_free(box, s);
+        int badflag;
+        std::memcpy(&badflag, &hb[2 * d], sizeof(int));
+        if (badflag) throw std::string("non-finite coordinate in points");
+        for (int j = 0; j < d; ++j) {
+            g.lo[j] = hb[j];
+            g.hi[j] = hb[d + j];
+            g.mid[j] = 0.5 * (g.lo[j] + g.hi[j]);
+        }
+    }
+    choose_geometry(g, index_dims);
+
+    // ---- G2: cell keys ----
+    unsigned long long *key_a = dev_alloc_n<unsigned long long>(n, s);
+    unsigned long long *key_b = dev_alloc_n<unsigned long long>(n, s);
+    int32_t *val_a = dev_alloc_n<int32_t>(n, s);
+    int32_t *val_b = dev_alloc_n<int32_t>(n, s);
+    {
+        KeyGeom geo{};
+        geo.k = g.k;
+        geo.d = d;
+        geo.w = g.w;
+        for (int j = 0; j < g.k; ++j) {
+            geo.lo[j] = g.lo[j];
+            geo.m[j] = g.m[j];
+            geo.stride[j] = g.stride[j];
+        }
+        hipLaunchKernelGGL(k_keys, dim3(blocks_for(n)), dim3(kThreads), 0, s, points, n, geo, key_a, val_a);
+        SJ_HIP(hipGetLastError());
+    }
+
+    // ---- G3: radix sort on the key bits in use ----
+    {
+        const int nb = (int)std::max<int64_t>(1, (n + kRsTile - 1) / kRsTile);
+        int32_t *hist = dev_alloc_n<int32_t>((size_t)nb * 256, s);
+        int32_t *hist_ex = dev_alloc_n<int32_t>((size_t)nb * 256, s);
+        for (int shift = 0; shift < g.key_bits; shift += 8) {
+            hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kThreads), 0, s, key_a, n, shift, hist, nb);
+            SJ_HIP(hipGetLastError());
+            exclusive_scan<int32_t, int32_t>(hist, hist_ex, (int64_t)nb * 256, s);
+            hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kThreads), 0, s, key_a, val_a, key_b, val_b, n,
+                               shift, hist_ex, nb);
+            SJ_HIP(hipGetLastError());
+            std::swap(key_a, key_b);
+            std::swap(val_a, val_b);
+        }
+        dev_free(hist, s);
+        dev_free(hist_ex, s);
+    }
+    g.perm = val_a;
+    dev_free(val_b, s);
+
+    // ---- G6: gather sorted rows, centred rows, norms ----
+    g.xs = dev_alloc_n<double>(rows * g.dp, s);
+    g.xa = dev_alloc_n<double>(rows * g.da, s);
+    g.nrm = dev_alloc_n<double>(rows, s);
+    g.dev_nmax = dev_alloc_n<double>(1, s);
+    fill_zero(g.xs + (size_t)n * g.dp, (size_t)kRowPad * g.dp * sizeof(double), s);
+    fill_zero(g.xa + (size_t)n * g.da, (size_t)kRowPad * g.da * sizeof(double), s);
+    fill_zero(g.nrm + n, (size_t)kRowPad * sizeof(double), s);
+    fill_zero(g.dev_nmax, sizeof(double), s);
+    {
+        GatherArgs ga{};
+        ga.d = d;
+        ga.dp = g.dp;
+        ga.da = g.da;
+        for (int j = 0; j < d; ++j) ga.mid[j] = g.mid[j];
+        hipLaunchKernelGGL(k_gather, dim3(blocks_for(n)), dim3(kThreads), 0, s, points, g.perm, n, ga, g.xs,
+                           g.xa, g.nrm, reinterpret_cast<unsigned long long *>(g.dev_nmax));
+        SJ_HIP(hipGetLastError());
+    }
+
+    // ---- G4: cell table, lines, work items ----
+    int32_t *flag = dev_alloc_n<int32_t>(n, s);
+    int32_t *cid = dev_alloc_n<int32_t>(n, s);
+    int32_t *counters = dev_alloc_n<int32_t>(4, s);  // ncells, nlines, nitems
+    fill_zero(counters, 4 * sizeof(int32_t), s);
+    g.cell_key = dev_alloc_n<int64_t>(n + 1, s);
+    g.cell_start = dev_alloc_n<int32_t>(n + 2, s);
+    int32_t *line_first = dev_alloc_n<int32_t>(n + 2, s);
+    int32_t *nitem = dev_alloc_n<int32_t>(n + 1, s);
+    int32_t *item_off = dev_alloc_n<int32_t>(n + 1, s);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_cell_flags, dim3(blocks_for(n)), dim3(kThreads), 0, s, key_a, n, flag);
+        SJ_HIP(hipGetLastError());
+        exclusive_scan<int32_t, int32_t>(flag, cid, n, s);
+        hipLaunchKernelGGL(k_cell_write, dim3(blocks_for(n)), dim3(kThreads), 0, s, key_a, flag, cid, n,
+                           g.cell_key, g.cell_start, counters + 0);
+        SJ_HIP(hipGetLastError());
+        // lines (cells grid-stride bounded by n)
+        hipLaunchKernelGGL(k_line_flags, dim3(blocks_for(n)), dim3(kThreads), 0, s, g.cell_key, counters + 0,
+                           (int64_t)g.m[g.k - 1], flag);
+        SJ_HIP(hipGetLastError());
+        exclusive_scan<int32_t, int32_t>(flag, cid, n, s);  // entries past ncells are ignored
+        hipLaunchKernelGGL(k_line_write, dim3(blocks_for(n)), dim3(kThreads), 0, s, flag, cid, g.cell_start,
+                           counters + 0, line_first, counters + 1);
+        SJ_HIP(hipGetLastError());
+        fill_zero(nitem, (size_t)(n + 1) * sizeof(int32_t), s);
+        hipLaunchKernelGGL(k_line_items, dim3(blocks_for(n)), dim3(kThreads), 0, s, line_first, g.cell_start,
+                           counters + 1, nitem);
+        SJ_HIP(hipGetLastError());
+    }
+    // ---- G5: neighbour ranges per cell + C_ref (tables sized by upper bounds) ----
+    unsigned long long *acc = dev_alloc_n<unsigned long long>(2, s);
+    fill_zero(acc, 2 * sizeof(unsigned long long), s);
+    const int64_t cells_ub = std::max<int64_t>(1, n);
+    g.ranges = dev_alloc_n<Range>((size_t)cells_ub * g.nranges, s);
+    const int64_t items_ub = n + n / kTileQ + 1;  // lines <= cells <= n
+    g.item = dev_alloc_n<Item>((size_t)items_ub, s);
+    if (n > 0) {
+        exclusive_scan<int32_t, int32_t>(nitem, item_off, n, s);  // entries past nlines are ignored
+        hipLaunchKernelGGL(k_items_total, dim3(1), dim3(1), 0, s, nitem, item_off, counters + 1, counters + 2);
+        SJ_HIP(hipGetLastError());
+        RangeGeom rg{};
+        rg.k = g.k;
+        rg.nranges = g.nranges;
+        for (int j = 0; j < g.k; ++j) {
+            rg.m[j] = g.m[j];
+            rg.stride[j] = g.stride[j];
+        }
+        hipLaunchKernelGGL(k_ranges, dim3(blocks_for(cells_ub * g.nranges)), dim3(kThreads), 0, s, g.cell_key,
+                           g.cell_start, counters + 0, rg, g.ranges, acc);
+        SJ_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_items, dim3(blocks_for(items_ub)), dim3(kThreads), 0, s, line_first, item_off,
+                           g.cell_start, counters + 1, counters + 2, g.item);
+        SJ_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_item_cands, dim3(blocks_for(items_ub)), dim3(kThreads), 0, s, g.item,
+                           counters + 2, g.ranges, g.nranges, acc + 1);
+        SJ_HIP(hipGetLastError());
+    }
+    // ---- one host sync: table sizes, C_ref, nmax ----
+    int32_t hc[4] = {0, 0, 0, 0};
+    double hn = 0.0;
+    unsigned long long hacc[2] = {0, 0};
+    if (n > 0) {
+        SJ_HIP(hipMemcpyAsync(hc, counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        SJ_HIP(hipMemcpyAsync(&hn, g.dev_nmax, sizeof(double), hipMemcpyDeviceToHost, s));
+        SJ_HIP(hipMemcpyAsync(hacc, acc, sizeof hacc, hipMemcpyDeviceToHost, s));
+        SJ_HIP(hipStreamSynchronize(s));
+    }
+    g.cells = hc[0];
+    g.items = hc[2];
+    g.nmax = hn;
+    g.cand_ref = (int64_t)hacc[0];
+    g.cand_items = (int64_t)hacc[1];
+
+    dev_free(acc, s);
+    dev_free(key_a, s);
+    dev_free(key_b, s);
+    dev_free(flag, s);
+    dev_free(cid, s);
+    dev_free(counters, s);
+    dev_free(line_first, s);
+    dev_free(nitem, s);
+    dev_free(item_off, s);
+}
+
+}  // namespace sj

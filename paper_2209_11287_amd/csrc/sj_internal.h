@@ -1,0 +1,139 @@
+// Internal definitions shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/selfjoin.h"
+
+namespace sj {
+
+constexpr int kMaxIndexDims = 4;   // default k = min(d, kMaxIndexDims)
+constexpr int kMaxDims = 256;
+constexpr int kTileQ = 16;         // queries per work item (one wave)
+constexpr int kRowPad = 64;        // extra zeroed rows after every point array
+
+// Thread-local error text.
+void set_error(const std::string &msg);
+const char *last_error();
+
+struct HipError {
+    hipError_t code;
+    std::string where;
+};
+
+// Throws HipError on failure; caught at the ABI boundary.
+#define SJ_HIP(call)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess) throw ::sj::HipError{e_, std::string(#call)};       \
+    } while (0)
+
+struct OomError {
+    size_t bytes;
+};
+
+struct Unsupported {
+    std::string what;
+};
+
+// Stream-ordered device allocation from the default memory pool (kept
+// cached: the pool's release threshold is raised on first use).
+void *dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(void *p, hipStream_t s);
+
+template <typename T>
+T *dev_alloc_n(size_t n, hipStream_t s) {
+    return static_cast<T *>(dev_alloc(n * sizeof(T) + 16, s));
+}
+
+// Candidate range of a work item: the union of the neighbouring cells of its
+// first and last cell along one offset of the leading indexed dimensions.
+struct Range {
+    int32_t begin, end;
+};
+
+// A work item: up to kTileQ consecutive queries of one grid line (cells that
+// differ only in the last indexed coordinate), and the cells they lie in.
+struct Item {
+    int32_t qbegin, qend;
+    int32_t cell_first, cell_last;
+};
+
+struct Grid {
+    int64_t n = 0;
+    int32_t d = 0, k = 0;
+    int32_t dp = 0;        // row stride of xs (multiple of 4, >= d)
+    int32_t da = 0;        // row stride of xa (multiple of 4; slot d holds the norm when d % 4 != 0)
+    int32_t nranges = 1;   // 3^(k-1) ranges per cell
+    double eps = 0, eps2 = 0, w = 0;
+    double lo[kMaxDims];   // per-dimension minimum (grid origin on indexed dims)
+    double hi[kMaxDims];
+    double mid[kMaxDims];  // centring reference of xa
+    int64_t m[kMaxIndexDims];
+    int64_t stride[kMaxIndexDims];
+    int32_t key_bits = 0;
+    int64_t cells = 0;
+    int64_t items = 0;
+    int64_t cand_ref = 0, cand_items = 0;
+    double nmax = 0;       // max squared norm of the centred rows of xa
+
+    // device buffers
+    double *xs = nullptr;        // sorted original coordinates, n x dp (+pad rows)
+    double *xa = nullptr;        // sorted centred coordinates (+norm slot), n x da (+pad rows)
+    double *nrm = nullptr;       // squared norms of xa rows (FP64 chain), n (+pad)
+    int32_t *perm = nullptr;     // sorted position -> input index
+    int64_t *cell_key = nullptr; // per non-empty cell
+    int32_t *cell_start = nullptr; // cells + 1 entries
+    Range *ranges = nullptr;     // cells x nranges
+    Item *item = nullptr;        // items
+    double *dev_nmax = nullptr;  // device copy of nmax
+
+    // cached per-query counts (sorted order) and their exclusive prefix sums
+    int32_t *cnt = nullptr;
+    int64_t *off = nullptr;      // n + 1 entries
+    bool have_counts = false;
+    int64_t total = 0;
+
+    hipStream_t build_stream = nullptr;
+};
+
+// Build steps (sj_build.hip).
+void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int index_dims,
+                hipStream_t s);
+void free_grid(Grid &g, hipStream_t s);
+
+// Zero fill by kernel (usable under stream capture, unlike a memset node).
+void fill_zero(void *p, size_t bytes, hipStream_t s);
+
+// Scans (sj_build.hip).
+void exclusive_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
+
+// Refine (sj_refine.hip).
+struct RefineOut {
+    int64_t band_pairs = 0;
+    double band_rel = 0;
+    int64_t cand_eval = 0;
+};
+struct ChunkPlan {
+    bool too_small = false;  // the next query alone needs more than the capacity
+    int64_t written = 0;     // pairs of the chunk (or the capacity needed)
+    int64_t next = 0;        // cursor after the chunk
+    int64_t item_lo = 0, item_hi = 0;  // work items covering the chunk
+    int64_t base = 0;        // prefix count at the cursor
+};
+void refine_count(Grid &g, sj_path path, int32_t *cnt_sorted, RefineOut &ro, hipStream_t s);
+ChunkPlan plan_chunk(Grid &g, int64_t cursor, int64_t capacity, hipStream_t s);
+void refine_pairs(Grid &g, sj_path path, const ChunkPlan &p, int64_t qlo, int32_t *pairs, double *d2,
+                  hipStream_t s);
+void refine_measure(Grid &g, sj_path path, double *max_err, double *max_band, int64_t *viol,
+                    hipStream_t s);
+
+}  // namespace sj
+
+struct sj_grid {
+    sj::Grid g;
+};

@@ -1,0 +1,193 @@
+"""Python binding of the MI355X epsilon-distance self-join (include/selfjoin.h).
+
+PyTorch supplies device memory and the current stream only; every step runs
+in libselfjoin.so. Functions carry the C ABI's names:
+
+    g = selfjoin_build_grid(points_cuda_f64, eps)
+    total, per_point, stats = selfjoin_count(g, "fp64_mfma", per_point=True)
+    written, nxt, stats = selfjoin_pairs(g, "fp64_mfma", cursor, pairs, d2)
+    selfjoin_free_grid(g)
+
+`SelfJoin` wraps the same calls for convenience.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import PATHS, SelfJoinError, check
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _path_id(path) -> int:
+    if isinstance(path, int):
+        return path
+    try:
+        return PATHS[path]
+    except KeyError:
+        raise ValueError(f"unknown path {path!r}; one of {sorted(PATHS)}") from None
+
+
+class GridHandle:
+    """Owns a sj_grid*; freed on close() or garbage collection."""
+
+    def __init__(self, ptr, n, d, eps, device):
+        self.ptr = ptr
+        self.n = n
+        self.d = d
+        self.eps = eps
+        self.device = device
+
+    def close(self, stream=None):
+        if self.ptr:
+            lib = _lib.load()
+            torch = _torch()
+            with torch.cuda.device(self.device):
+                lib.selfjoin_free_grid(self.ptr, _stream_ptr(stream))
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def selfjoin_build_grid(points, eps: float, index_dims: int = 0, stream=None) -> GridHandle:
+    """points: CUDA float64 tensor (n, d), C-contiguous."""
+    torch = _torch()
+    if not isinstance(points, torch.Tensor) or not points.is_cuda:
+        raise ValueError("points must be a CUDA tensor")
+    if points.dtype != torch.float64 or points.dim() != 2:
+        raise ValueError("points must be float64 of shape (n, d)")
+    points = points.contiguous()
+    lib = _lib.load()
+    opts = _lib.sj_opts()
+    opts.index_dims = index_dims
+    out = ctypes.c_void_p()
+    n, d = points.shape
+    with torch.cuda.device(points.device):
+        st = lib.selfjoin_build_grid(ctypes.c_void_p(points.data_ptr()), n, d, float(eps),
+                                     ctypes.byref(opts), _stream_ptr(stream), ctypes.byref(out))
+    check(st, "selfjoin_build_grid")
+    return GridHandle(out, n, d, float(eps), points.device)
+
+
+def selfjoin_count(g: GridHandle, path="fp64_mfma", per_point: bool = False, stream=None):
+    """Returns (total, per_point int32 tensor or None, stats dict)."""
+    torch = _torch()
+    lib = _lib.load()
+    pp = torch.empty(g.n, dtype=torch.int32, device=g.device) if per_point else None
+    total = ctypes.c_int64(0)
+    stats = _lib.sj_stats()
+    with torch.cuda.device(g.device):
+        st = lib.selfjoin_count(g.ptr, _path_id(path),
+                                ctypes.c_void_p(pp.data_ptr()) if pp is not None and g.n else None,
+                                ctypes.byref(total), ctypes.byref(stats), _stream_ptr(stream))
+    check(st, "selfjoin_count")
+    return total.value, pp, stats.as_dict()
+
+
+def selfjoin_pairs(g: GridHandle, path, cursor: int, pairs, d2=None, capacity=None, stream=None):
+    """Writes one chunk into `pairs` (int32 CUDA tensor (capacity, 2)) and
+    optionally `d2` (float64 CUDA tensor (capacity,)). Returns
+    (written, next_cursor, stats dict). Raises SelfJoinError with status
+    SJ_ERR_CAPACITY (attribute `needed`) when the next query does not fit."""
+    torch = _torch()
+    lib = _lib.load()
+    if capacity is None:
+        capacity = pairs.shape[0]
+    if pairs.dtype != torch.int32 or pairs.dim() != 2 or pairs.shape[1] != 2 or pairs.shape[0] < capacity:
+        raise ValueError("pairs must be int32 of shape (>= capacity, 2)")
+    if d2 is not None and (d2.dtype != torch.float64 or d2.shape[0] < capacity):
+        raise ValueError("d2 must be float64 of length >= capacity")
+    written = ctypes.c_int64(0)
+    nxt = ctypes.c_int64(0)
+    stats = _lib.sj_stats()
+    with torch.cuda.device(g.device):
+        st = lib.selfjoin_pairs(g.ptr, _path_id(path), int(cursor),
+                                ctypes.c_void_p(pairs.data_ptr()),
+                                ctypes.c_void_p(d2.data_ptr()) if d2 is not None else None,
+                                int(capacity), ctypes.byref(written), ctypes.byref(nxt),
+                                ctypes.byref(stats), _stream_ptr(stream))
+    if st == _lib.SJ_ERR_CAPACITY:
+        err = SelfJoinError(st, "selfjoin_pairs")
+        err.needed = written.value
+        raise err
+    check(st, "selfjoin_pairs")
+    return written.value, nxt.value, stats.as_dict()
+
+
+def selfjoin_measure_error(g: GridHandle, path, stream=None):
+    """Returns (max |fast - exact|, band half-width, violations)."""
+    torch = _torch()
+    lib = _lib.load()
+    e = ctypes.c_double(0)
+    b = ctypes.c_double(0)
+    v = ctypes.c_int64(0)
+    with torch.cuda.device(g.device):
+        st = lib.selfjoin_measure_error(g.ptr, _path_id(path), ctypes.byref(e), ctypes.byref(b),
+                                        ctypes.byref(v), _stream_ptr(stream))
+    check(st, "selfjoin_measure_error")
+    return e.value, b.value, v.value
+
+
+def selfjoin_grid_info(g: GridHandle) -> dict:
+    lib = _lib.load()
+    info = _lib.sj_grid_info()
+    check(lib.selfjoin_grid_info(g.ptr, ctypes.byref(info)), "selfjoin_grid_info")
+    return info.as_dict()
+
+
+def selfjoin_free_grid(g: GridHandle, stream=None):
+    g.close(stream)
+
+
+class SelfJoin:
+    """Convenience wrapper: grid + count + all pairs."""
+
+    def __init__(self, points, eps, index_dims=0, stream=None):
+        self.grid = selfjoin_build_grid(points, eps, index_dims, stream)
+        self.stream = stream
+
+    def count(self, path="fp64_mfma", per_point=False):
+        return selfjoin_count(self.grid, path, per_point, self.stream)
+
+    def all_pairs(self, path="fp64_mfma", want_d2=False, capacity=None):
+        """All pairs as one (|R|, 2) int32 tensor (and d2), chunked if
+        `capacity` is given."""
+        torch = _torch()
+        total, _, _ = self.count(path)
+        cap = total if capacity is None else capacity
+        dev = self.grid.device
+        out = torch.empty((max(total, 1), 2), dtype=torch.int32, device=dev)
+        dd = torch.empty(max(total, 1), dtype=torch.float64, device=dev) if want_d2 else None
+        buf = out if capacity is None else torch.empty((max(cap, 1), 2), dtype=torch.int32, device=dev)
+        dbuf = dd if (capacity is None or not want_d2) else torch.empty(max(cap, 1), dtype=torch.float64,
+                                                                         device=dev)
+        cursor, pos = 0, 0
+        while cursor < self.grid.n:
+            w, cursor, _ = selfjoin_pairs(self.grid, path, cursor, buf, dbuf, cap, self.stream)
+            if capacity is not None:
+                out[pos:pos + w] = buf[:w]
+                if want_d2:
+                    dd[pos:pos + w] = dbuf[:w]
+            pos += w
+        if capacity is None and pos != total:
+            raise RuntimeError("pair count mismatch")
+        res = out[:total]
+        return (res, dd[:total]) if want_d2 else res
+
+    def close(self):
+        self.grid.close(self.stream)

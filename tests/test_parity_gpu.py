@@ -1,0 +1,207 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the
+same seeded inputs. Pair sets and counts must be identical (bit-exact);
+emitted distances must equal the oracle's chain bitwise (tolerance 0 here;
+the contract allows 1e-12 relative)."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import gpu_join, log, pair_keys
+from workloads import generators as gen
+
+pytestmark = pytest.mark.gpu
+
+PATHS = ["fp64_valu", "fp64_mfma"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2209_11287_amd as p
+    p.load()
+    yield
+
+
+def _oracle_full(X, eps):
+    import oracle
+    cnt, pp, pairs, d2 = oracle.grid_pairs(X, eps, want_d2=True)
+    _, _, cref, k = oracle.grid_count(X, eps)
+    return cnt, pp, pairs, d2, cref, k
+
+
+def _check_against_oracle(X, eps, path, tag, capacity=None):
+    log(f"[parity] {tag} path={path} n={X.shape[0]} d={X.shape[1]} eps={eps}")
+    cnt, pp, pairs, d2, cref, k = _oracle_full(X, eps)
+    g = gpu_join(X, eps, path, want_pairs=True, want_d2=True, capacity=capacity)
+    assert g["total"] == cnt, (g["total"], cnt)
+    assert np.array_equal(g["per_point"], pp)
+    assert g["info"]["cand_ref"] == cref
+    assert g["info"]["k"] == k
+    assert np.array_equal(pair_keys(g["pairs"]), pair_keys(pairs))
+    # d2 of every pair: bitwise equal to the oracle's chain
+    ko = (pairs[:, 0].astype(np.int64) << 32) | pairs[:, 1]
+    kg = (g["pairs"][:, 0].astype(np.int64) << 32) | g["pairs"][:, 1]
+    oo = np.argsort(ko)
+    og = np.argsort(kg)
+    assert np.array_equal(d2[oo].view(np.int64), g["d2"][og].view(np.int64))
+    return g
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_small_parity_config(path):
+    # n = 20,000 uniform points in the unit square, seed 0, eps = 0.0218
+    X = gen.uniform(20000, 2, seed=0)
+    _check_against_oracle(X, 0.0218, path, "uniform-20k-2d")
+
+
+CASES = []
+for _d in (1, 2, 3, 4, 5, 6, 7, 8, 12, 16):
+    for _dist in ("uniform", "expo", "gmm"):
+        CASES.append((_dist, _d))
+
+
+def _eps_for(X, target_s, seed=7):
+    n = X.shape[0]
+    rng = np.random.default_rng(seed)
+    qs = rng.integers(0, n, 30)
+    dd = np.sort(np.concatenate([np.sqrt(((X - X[q]) ** 2).sum(1)) for q in qs]))
+    return float(dd[min(len(dd) - 1, int(len(qs) * (target_s + 1)))])
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("dist,d", CASES)
+def test_parity_distributions_and_dims(path, dist, d):
+    # ragged sizes: not multiples of the 16-query / 16- or 64-candidate tiles
+    n = {1: 5003, 2: 7919, 3: 6007, 4: 5501}.get(d, 3001)
+    X = gen.make(dist, n, d, seed=100 + d)
+    eps = _eps_for(X, 25)
+    _check_against_oracle(X, eps, path, f"{dist}-{d}d")
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_lattice_ties_on_eps(path):
+    # every distance exact; many pairs at exactly eps
+    for L, d, r in [(40, 2, 3), (12, 3, 2), (7, 4, 2), (5, 5, 1)]:
+        X = gen.lattice(L, d, 2.0 ** -6)
+        _check_against_oracle(X, r * 2.0 ** -6, path, f"lattice L={L} d={d} r={r}")
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_adversarial_sets(path):
+    rng = np.random.default_rng(3)
+    base = rng.random((700, 3))
+    sets = [
+        (np.concatenate([base, base, base[:50]]), 0.05, "duplicates"),
+        (1e6 + rng.random((3000, 2)) * 1e-3, 1e-4, "large-offset"),
+        (rng.integers(0, 10, (3000, 3)).astype(np.float64) * 0.1, 0.1, "tenths"),
+        (np.zeros((100, 4)), 1.0, "all-identical"),
+        (np.repeat(rng.random((1, 2)), 1500, 0) + rng.random((1500, 2)) * 1e-9, 1e-3, "one-cell"),
+    ]
+    Y = rng.random((2500, 4)) - 0.5
+    Y[:, 0] *= 1e4
+    sets.append((Y, 0.2, "wide-dim0"))
+    for X, eps, tag in sets:
+        _check_against_oracle(X, eps, path, tag)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_tiny_and_empty(path):
+    import torch
+    from paper_2209_11287_amd import SelfJoin
+    for n in (0, 1, 2, 17):
+        X = gen.uniform(n, 3, seed=n) if n else np.zeros((0, 3))
+        log(f"[parity] tiny n={n} path={path}")
+        sj = SelfJoin(torch.from_numpy(X).to("cuda:0"), 0.3)
+        total, pp, _ = sj.count(path, per_point=True)
+        if n == 0:
+            assert total == 0
+        else:
+            import oracle
+            c, opp, _, _ = oracle.grid_count(X, 0.3)
+            assert total == c
+            assert np.array_equal(pp.cpu().numpy(), opp)
+            pr = sj.all_pairs(path).cpu().numpy()
+            _, _, opairs = oracle.bruteforce(X, 0.3)
+            assert np.array_equal(pair_keys(pr), pair_keys(opairs))
+        sj.close()
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_chunked_pairs_equal_one_shot(path):
+    import torch
+    from paper_2209_11287_amd import SelfJoin, SelfJoinError, selfjoin_pairs
+    X = gen.exponential(30000, 3, seed=4)
+    eps = _eps_for(X, 40)
+    log(f"[parity] chunks path={path}")
+    sj = SelfJoin(torch.from_numpy(X).to("cuda:0"), eps)
+    total, pp, _ = sj.count(path, per_point=True)
+    one = sj.all_pairs(path).cpu().numpy()
+    mx = int(pp.max().item())
+    for cap in (mx, mx + 7, 5000, total // 3 + 1):
+        chunked = sj.all_pairs(path, capacity=cap).cpu().numpy()
+        # same pairs in the same (deterministic) order
+        assert np.array_equal(chunked, one), cap
+    # the next query's pairs do not fit
+    buf = torch.empty((mx - 1, 2), dtype=torch.int32, device="cuda:0")
+    cursor = 0
+    with pytest.raises(SelfJoinError) as ei:
+        while True:
+            _, cursor, _ = selfjoin_pairs(sj.grid, path, cursor, buf, None, mx - 1)
+    assert ei.value.needed >= mx
+    sj.close()
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_deterministic_output(path):
+    X = gen.uniform(50000, 2, seed=9)
+    a = gpu_join(X, 0.01, path)["pairs"]
+    b = gpu_join(X, 0.01, path)["pairs"]
+    assert np.array_equal(a, b)
+
+
+def test_paths_emit_identical_lists():
+    X = gen.gaussian_mixture(20000, 8, seed=2)
+    eps = _eps_for(X, 30)
+    a = gpu_join(X, eps, "fp64_valu")["pairs"]
+    b = gpu_join(X, eps, "fp64_mfma")["pairs"]
+    assert np.array_equal(a, b)
+
+
+def test_mfma_error_within_band():
+    import torch
+    from paper_2209_11287_amd import SelfJoin, selfjoin_measure_error
+    for dist, d in [("uniform", 2), ("expo", 3), ("gmm", 4), ("gmm", 16), ("uniform", 7)]:
+        X = gen.make(dist, 20000, d, seed=d)
+        eps = _eps_for(X, 30)
+        sj = SelfJoin(torch.from_numpy(X).to("cuda:0"), eps)
+        err, band, viol = selfjoin_measure_error(sj.grid, "fp64_mfma")
+        log(f"[band] {dist} d={d} max_err={err:.3e} band={band:.3e} rel={band / eps**2:.3e} viol={viol}")
+        assert viol == 0
+        assert err <= band / 2  # the analysis bound, before its safety factor
+        sj.close()
+
+
+def test_nonfinite_input_rejected():
+    import torch
+    from paper_2209_11287_amd import SelfJoinError, selfjoin_build_grid
+    X = gen.uniform(1000, 3, seed=1)
+    X[500, 1] = np.nan
+    with pytest.raises(SelfJoinError) as ei:
+        selfjoin_build_grid(torch.from_numpy(X).to("cuda:0"), 0.1)
+    assert ei.value.status == 1
+    X[500, 1] = np.inf
+    with pytest.raises(SelfJoinError):
+        selfjoin_build_grid(torch.from_numpy(X).to("cuda:0"), 0.1)
+
+
+def test_index_dims_option_is_result_neutral():
+    import oracle
+    X = gen.gaussian_mixture(15000, 6, seed=5)
+    eps = _eps_for(X, 20)
+    c, pp, _, _ = oracle.grid_count(X, eps)
+    for k in (1, 2, 3, 4):
+        for path in PATHS:
+            g = gpu_join(X, eps, path, want_pairs=False, index_dims=k)
+            assert g["total"] == c
+            assert np.array_equal(g["per_point"], pp)
