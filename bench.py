@@ -1,0 +1,237 @@
+#!/usr/bin/env python
+"""Benchmark of the MI355X epsilon-distance self-join (one GPU).
+
+One step = the whole path over the measured workload: for each of the six
+data sets (n = 2,000,000 points; d in {2, 3, 4}; uniform in [0,1]^d and
+exponential(40) clipped to [0,1]; eps for ~64 mean neighbours), build the
+grid index, count R, and write the full pair list to device memory. Inputs
+are resident in HBM before the timed region.
+
+metric: distance evaluations per second = C_ref / step time, where C_ref is
+the number of ordered candidate pairs of the full 3^k stencil of the
+reference grid (an implementation-independent work unit), plus the
+self-join time. The FP64 MFMA path is the headline; the FP64 vector-ALU path
+runs beside it on the same data (--compare).
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--path fp64_mfma]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "distance evals/s + self-join time, exact pairs; MFMA vs FP64 vector, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--path", default="fp64_mfma")
+    ap.add_argument("--compare", default="fp64_valu", help="second path timed on the same data ('' = none)")
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "small"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def datasets(which):
+    from workloads import configs
+    names = configs.CFG2 if which == "cfg2" else ["small"]
+    return [configs.workload(nm) for nm in names]
+
+
+def load_inputs(wl):
+    import torch
+    from workloads import generators as gen
+    out = []
+    for w in wl:
+        X = gen.make(w["dist"], w["n"], w["d"], seed=w["seed"])
+        out.append((w, X, torch.from_numpy(X).to("cuda:0")))
+    torch.cuda.synchronize()
+    return out
+
+
+def one_pass(inputs, path, bufs, collect=None):
+    """build + count + pairs over every data set. `bufs[i]` is a device
+    buffer able to hold data set i's pairs (None = size from the count)."""
+    import torch
+    from paper_2209_11287_amd import (selfjoin_build_grid, selfjoin_count, selfjoin_free_grid,
+                                      selfjoin_grid_info, selfjoin_pairs)
+    for i, (w, X, xt) in enumerate(inputs):
+        g = selfjoin_build_grid(xt, w["eps"])
+        total, _, st_c = selfjoin_count(g, path, per_point=False)
+        if bufs[i] is None or bufs[i].shape[0] < total:
+            bufs[i] = torch.empty((max(total, 1), 2), dtype=torch.int32, device="cuda:0")
+        written, nxt, st_p = selfjoin_pairs(g, path, 0, bufs[i], None, total)
+        if written != total or nxt != w["n"]:
+            raise RuntimeError(f"pairs chunk incomplete: {written}/{total}, cursor {nxt}")
+        if collect is not None:
+            info = selfjoin_grid_info(g)
+            collect.append({"name": w["name"], "n": w["n"], "d": w["d"], "eps": w["eps"], "pairs": total,
+                            "cand_ref": info["cand_ref"], "cand_eval": info["cand_items"],
+                            "count_kernel_ms": st_c["ms_kernel"], "emit_kernel_ms": st_p["ms_kernel"],
+                            "count_ms": st_c["ms"], "pairs_ms": st_p["ms"], "band_pairs": st_c["band_pairs"],
+                            "band_rel": st_c["band_rel"]})
+        selfjoin_free_grid(g)
+
+
+def timed(inputs, path, steps, warmup, bufs):
+    import torch
+    for _ in range(warmup):
+        one_pass(inputs, path, bufs)
+    torch.cuda.synchronize()
+    recs = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rec = []
+        one_pass(inputs, path, bufs, rec)
+        recs.append(rec)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) / steps, recs
+
+
+def src_hash():
+    h = hashlib.sha256()
+    for f in ("sj_refine.hip", "sj_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2209_11287_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel_key):
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries, only if
+    they were taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        t = json.load(open(p))
+        e = t.get(kernel_key)
+        if e and e.get("src_hash") == src_hash():
+            return e.get("bytes_per_launch")
+    except Exception:
+        return None
+    return None
+
+
+def roofline(recs):
+    """Dominant tile kernel over the timed steps; algorithmic work per launch
+    divided by its mean launch time (HIP events around the launch)."""
+    per = {}
+    for rec in recs:
+        for r in rec:
+            per.setdefault(r["name"], []).append(r)
+    count_ms = sum(r["count_kernel_ms"] for rec in recs for r in rec)
+    emit_ms = sum(r["emit_kernel_ms"] for rec in recs for r in rec)
+    launches = sum(len(rec) for rec in recs)
+    if emit_ms >= count_ms:
+        # emit: pair rows written (8 B each) + each point's row read once
+        byts = sum(8.0 * r["pairs"] + 8.0 * r["n"] * r["d"] + 4.0 * r["n"] for rec in recs for r in rec)
+        avg_ms = emit_ms / launches
+        achieved = byts / launches / (avg_ms * 1e-3) / 1e9
+        return {"kernel": "k_m64 emit (pairs)", "bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic_for("emit"), "avg_launch_ms": round(avg_ms, 4),
+                "algorithmic_bytes_per_launch": round(byts / launches)}
+    flops = sum(2.0 * r["d"] * r["cand_ref"] for rec in recs for r in rec)
+    avg_ms = count_ms / launches
+    achieved = flops / launches / (avg_ms * 1e-3) / 1e12
+    return {"kernel": "k_m64 count", "bound": "mfma", "achieved": round(achieved, 3),
+            "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+            "traffic": traffic_for("count"), "avg_launch_ms": round(avg_ms, 4),
+            "algorithmic_flops_per_launch": round(flops / launches)}
+
+
+def cpu_baseline(inputs):
+    """The oracle (count mode, all host threads) on a bounded sample of the
+    same workload: the first data sets until ~15 s of CPU time."""
+    import oracle
+    # the machine's CPU share: OMP_NUM_THREADS (16 per GPU), not os.cpu_count()
+    nthreads = max(1, min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16"))))
+    done, cref, secs = [], 0, 0.0
+    for w, X, _ in inputs:
+        t0 = time.perf_counter()
+        _, _, c, _ = oracle.grid_count(X, w["eps"], nthreads=nthreads)
+        dt = time.perf_counter() - t0
+        cref += c
+        secs += dt
+        done.append(w["name"])
+        if secs > 15.0:
+            break
+    return {"value": cref / secs, "unit": "distance evals/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"oracle grid count (no pair list), {nthreads} threads, data sets: {', '.join(done)}",
+            "seconds": round(secs, 2)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is described, not implemented)"}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    import paper_2209_11287_amd as pkg
+    pkg.load()
+    wl = datasets(args.workload)
+    log(f"[bench] generating {len(wl)} data sets")
+    inputs = load_inputs(wl)
+    bufs = [None] * len(inputs)
+    log(f"[bench] path {args.path}: warmup {args.warmup}, steps {args.steps}")
+    sec, recs = timed(inputs, args.path, args.steps, args.warmup, bufs)
+    cref = sum(r["cand_ref"] for r in recs[0])
+    pairs = sum(r["pairs"] for r in recs[0])
+    out = {
+        "metric": METRIC,
+        "value": cref / sec,
+        "unit": "distance evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "n=2,000,000 x {uniform, exponential(40)} x d in {2,3,4}, s~64; "
+                               "build + count + full pair list" if args.workload == "cfg2" else "small",
+                   "path": args.path, "cand_ref_per_step": cref, "pairs_per_step": pairs},
+        "per_dataset": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+                        for r in recs[-1]],
+        "roofline": roofline(recs),
+    }
+    if args.compare:
+        log(f"[bench] compare path {args.compare}")
+        bufs2 = [None] * len(inputs)
+        sec2, recs2 = timed(inputs, args.compare, args.steps, args.warmup, bufs2)
+        out["compare"] = {"path": args.compare, "value": cref / sec2, "ms_per_step": round(sec2 * 1e3, 3),
+                          "speedup_of_headline": round(sec2 / sec, 3),
+                          "count_kernel_ms": [round(r["count_kernel_ms"], 4) for r in recs2[-1]],
+                          "emit_kernel_ms": [round(r["emit_kernel_ms"], 4) for r in recs2[-1]]}
+        del bufs2
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(inputs)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -86,7 +86,8 @@ typedef struct {
     int64_t band_pairs;  /* pairs whose fast value fell inside the band and
                             were re-evaluated with the FP64 chain */
     double band_rel;     /* largest band half-width used, divided by eps^2 */
-    double ms;           /* device time of the call's kernels (ms) */
+    double ms;           /* device time of the whole call (ms) */
+    double ms_kernel;    /* device time of the distance-tile kernel alone (ms) */
 } sj_stats;
 
 /* Grid facts (for tests and reports). */

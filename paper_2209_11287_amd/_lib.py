@@ -43,6 +43,7 @@ class sj_stats(ctypes.Structure):
         ("band_pairs", ctypes.c_int64),
         ("band_rel", ctypes.c_double),
         ("ms", ctypes.c_double),
+        ("ms_kernel", ctypes.c_double),
     ]
 
     def as_dict(self):

@@ -155,6 +155,7 @@ sj_status selfjoin_count(sj_grid *gh, sj_path path, int32_t *per_point, int64_t 
         SJ_HIP(hipEventRecord(e0, s));
     }
     RefineOut ro;
+    ro.timed = stats != nullptr;
     compute_counts(g, path, ro, s);
     if (per_point && g.n > 0) {
         hipLaunchKernelGGL(k_scatter_counts, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s, g.cnt, g.perm,
@@ -175,6 +176,7 @@ sj_status selfjoin_count(sj_grid *gh, sj_path path, int32_t *per_point, int64_t 
         stats->band_pairs = ro.band_pairs;
         stats->band_rel = ro.band_rel;
         stats->ms = ms;
+        stats->ms_kernel = ro.ms_kernel;
     }
     return SJ_OK;
     SJ_API_END
@@ -215,7 +217,9 @@ sj_status selfjoin_pairs(sj_grid *gh, sj_path path, int64_t cursor, int32_t *pai
         set_error("capacity too small for the next query's pairs");
         return SJ_ERR_CAPACITY;
     }
-    refine_pairs(g, path, p, cursor, pairs, d2, s);
+    RefineOut re;
+    re.timed = stats != nullptr;
+    refine_pairs(g, path, p, cursor, pairs, d2, re, s);
     *written = p.written;
     *next_cursor = p.next;
     if (stats) {
@@ -229,8 +233,9 @@ sj_status selfjoin_pairs(sj_grid *gh, sj_path path, int64_t cursor, int32_t *pai
         stats->cand_eval = ro.cand_eval;
         stats->pairs = p.written;
         stats->band_pairs = ro.band_pairs;
-        stats->band_rel = ro.band_rel;
+        stats->band_rel = re.band_rel;
         stats->ms = ms;
+        stats->ms_kernel = re.ms_kernel;
     }
     return SJ_OK;
     SJ_API_END

@@ -114,9 +114,43 @@ void exclusive_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipSt
 
 // Refine (sj_refine.hip).
 struct RefineOut {
+    bool timed = false;      // record events around the tile kernel
     int64_t band_pairs = 0;
     double band_rel = 0;
     int64_t cand_eval = 0;
+    float ms_kernel = 0;
+};
+
+// Events bracketing one kernel launch on a stream.
+struct KernelTimer {
+    hipEvent_t a = nullptr, b = nullptr;
+    bool on = false;
+    void start(bool enable, hipStream_t s) {
+        on = enable;
+        if (!on) return;
+        SJ_HIP(hipEventCreate(&a));
+        SJ_HIP(hipEventCreate(&b));
+        SJ_HIP(hipEventRecord(a, s));
+    }
+    void stop(hipStream_t s) {
+        if (on) SJ_HIP(hipEventRecord(b, s));
+    }
+    float ms() {  // waits for the end event
+        if (!on) return 0.f;
+        float v = 0.f;
+        SJ_HIP(hipEventSynchronize(b));
+        SJ_HIP(hipEventElapsedTime(&v, a, b));
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        on = false;
+        return v;
+    }
+    ~KernelTimer() {
+        if (on) {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    }
 };
 struct ChunkPlan {
     bool too_small = false;  // the next query alone needs more than the capacity
@@ -128,7 +162,7 @@ struct ChunkPlan {
 void refine_count(Grid &g, sj_path path, int32_t *cnt_sorted, RefineOut &ro, hipStream_t s);
 ChunkPlan plan_chunk(Grid &g, int64_t cursor, int64_t capacity, hipStream_t s);
 void refine_pairs(Grid &g, sj_path path, const ChunkPlan &p, int64_t qlo, int32_t *pairs, double *d2,
-                  hipStream_t s);
+                  RefineOut &ro, hipStream_t s);
 void refine_measure(Grid &g, sj_path path, double *max_err, double *max_band, int64_t *viol,
                     hipStream_t s);
 

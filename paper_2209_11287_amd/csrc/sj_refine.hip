@@ -233,8 +233,8 @@ __global__ __launch_bounds__(kThreads) void k_m64(DevGrid G, RefOut R, double de
             if (SLOT) {
                 acc = (double4_t){0.0, 0.0, 0.0, 0.0};
             } else {
-                const double *nr = G.nrm + t + 4 * g;
-                acc = (double4_t){nr[0], nr[1], nr[2], nr[3]};
+                const double *nr = G.nrm + t + g;
+                acc = (double4_t){nr[0], nr[4], nr[8], nr[12]};
             }
             const double *__restrict__ arow = xa + (int64_t)(t + j) * da + g;
             if (KS > 0) {
@@ -249,17 +249,19 @@ __global__ __launch_bounds__(kThreads) void k_m64(DevGrid G, RefOut R, double de
                     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[4 * s], b, acc, 0, 0, 0);
                 }
             }
-            // element r of this lane: candidate row t + 4g + r, query column j
-            const int rowlim = ce - t - 4 * g;
+            // Result layout of v_mfma_f64_16x16x4f64: register r of lane
+            // (g, j) holds row g + 4r, column j. Element r is candidate
+            // t + g + 4r against query j.
+            const int rowlim = ce - t;
             unsigned inm = 0, bandm = 0;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const bool valid = qvalid && r < rowlim;
+                const bool valid = qvalid && (g + 4 * r) < rowlim;
                 const double v = acc[r];
                 if (valid && v <= lo) inm |= 1u << r;
                 else if (valid && v <= hi) bandm |= 1u << r;
                 if (MODE == MODE_MEASURE && valid) {
-                    const double ex = exact_d2(xs + (int64_t)qj * dp, xs + (int64_t)(t + 4 * g + r) * dp, d);
+                    const double ex = exact_d2(xs + (int64_t)qj * dp, xs + (int64_t)(t + g + 4 * r) * dp, d);
                     if (ex <= 4.0 * G.eps2) {
                         const double err = fabs(v - (ex - G.nrm[qj]));
                         maxerr = fmax(maxerr, err);
@@ -272,35 +274,40 @@ __global__ __launch_bounds__(kThreads) void k_m64(DevGrid G, RefOut R, double de
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     if (bandm & (1u << r)) {
-                        const double ex = exact_d2(xs + (int64_t)qj * dp, xs + (int64_t)(t + 4 * g + r) * dp, d);
+                        const double ex = exact_d2(xs + (int64_t)qj * dp, xs + (int64_t)(t + g + 4 * r) * dp, d);
                         if (ex <= G.eps2) inm |= 1u << r;
                         ++band;
                     }
                 }
             }
-            const int c = __popc(inm);
-            cnt += c;
+            cnt += __popc(inm);
             if (MODE == MODE_EMIT) {
-                int incl = c;
-                const int u1 = __shfl_up(incl, 16);
-                if (g >= 1) incl += u1;
-                const int u2 = __shfl_up(incl, 32);
-                if (g >= 2) incl += u2;
-                const int tot = __shfl(incl, 48 + j);
-                if (pbase >= 0 && c) {
-                    int64_t pos = pbase + cur + (incl - c);
+                // candidate order per query: row i = g + 4r, so the rank of
+                // (g, r) counts every flagged row of lower level r, then the
+                // flagged rows of level r in lower lane groups.
+                const unsigned long long sel = 0x0001000100010001ull << j;
+                const unsigned long long below = (1ull << (16 * g)) - 1ull;
+                int rank_base = 0;
+                int rank[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const unsigned long long x = __ballot((inm >> r) & 1u) & sel;
+                    rank[r] = rank_base + __popcll(x & below);
+                    rank_base += __popcll(x);
+                }
+                if (pbase >= 0) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        if ((inm & (1u << r)) && pos < pend) {
-                            const int cand = t + 4 * g + r;
+                        const int64_t pos = pbase + cur + rank[r];
+                        if (((inm >> r) & 1u) && pos < pend) {
+                            const int cand = t + g + 4 * r;
                             R.pairs[2 * pos] = pq;
                             R.pairs[2 * pos + 1] = G.perm[cand];
                             if (R.d2) R.d2[pos] = exact_d2(xs + (int64_t)qj * dp, xs + (int64_t)cand * dp, d);
-                            ++pos;
                         }
                     }
                 }
-                cur += tot;
+                cur += rank_base;
             }
         }
     }
@@ -424,17 +431,23 @@ void refine_count(Grid &g, sj_path path, int32_t *cnt_sorted, RefineOut &ro, hip
     R.band = band;
     R.item_lo = 0;
     ro.cand_eval = g.cand_items;
+    KernelTimer kt;
     if (path == SJ_FP64_VALU) {
+        kt.start(ro.timed, s);
         launch_v64<MODE_COUNT>(g, R, (int)g.items, s);
+        kt.stop(s);
         ro.band_rel = 0.0;
     } else if (path == SJ_FP64_MFMA) {
         const double delta = m64_delta(g);
+        kt.start(ro.timed, s);
         launch_m64<MODE_COUNT>(g, R, (int)g.items, delta, s);
+        kt.stop(s);
         ro.band_rel = g.eps2 > 0 ? delta / g.eps2 : 0.0;
     } else {
         dev_free(band, s);
         throw Unsupported{"path not supported by this build"};
     }
+    ro.ms_kernel = kt.ms();
     unsigned long long hb = 0;
     SJ_HIP(hipMemcpyAsync(&hb, band, sizeof hb, hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
@@ -506,7 +519,7 @@ ChunkPlan plan_chunk(Grid &g, int64_t cursor, int64_t capacity, hipStream_t s) {
 }
 
 void refine_pairs(Grid &g, sj_path path, const ChunkPlan &p, int64_t qlo, int32_t *pairs, double *d2,
-                  hipStream_t s) {
+                  RefineOut &ro, hipStream_t s) {
     RefOut R{};
     R.off = g.off;
     R.base = p.base;
@@ -519,15 +532,23 @@ void refine_pairs(Grid &g, sj_path path, const ChunkPlan &p, int64_t qlo, int32_
     fill_zero(band, sizeof(unsigned long long), s);
     R.band = band;
     const int nitems = (int)(p.item_hi - p.item_lo);
+    KernelTimer kt;
     if (path == SJ_FP64_VALU) {
+        kt.start(ro.timed, s);
         launch_v64<MODE_EMIT>(g, R, nitems, s);
+        kt.stop(s);
     } else if (path == SJ_FP64_MFMA) {
-        launch_m64<MODE_EMIT>(g, R, nitems, m64_delta(g), s);
+        const double delta = m64_delta(g);
+        kt.start(ro.timed, s);
+        launch_m64<MODE_EMIT>(g, R, nitems, delta, s);
+        kt.stop(s);
+        ro.band_rel = g.eps2 > 0 ? delta / g.eps2 : 0.0;
     } else {
         dev_free(band, s);
         throw Unsupported{"path not supported by this build"};
     }
     dev_free(band, s);
+    ro.ms_kernel = kt.ms();
 }
 
 void refine_measure(Grid &g, sj_path path, double *max_err, double *max_band, int64_t *viol, hipStream_t s) {
