@@ -79,7 +79,8 @@ typedef struct {
 /* Statistics of one call (all optional, pass NULL). */
 typedef struct {
     int64_t cand_ref;    /* C_ref: ordered candidate pairs of the full 3^k
-                            stencil of the reference grid (work unit) */
+                            stencil of the reference grid (work unit);
+                            -1 until selfjoin_grid_info has computed it */
     int64_t cand_eval;   /* candidate pairs the path evaluated, tile padding
                             excluded */
     int64_t pairs;       /* |R| for count; pairs written for pairs */
@@ -151,8 +152,9 @@ sj_status selfjoin_pairs(sj_grid *g, sj_path path, int64_t cursor, int32_t *pair
 sj_status selfjoin_measure_error(sj_grid *g, sj_path path, double *max_abs_err, double *max_band,
                                  int64_t *violations, void *stream);
 
-/* Grid facts of a built handle. */
-sj_status selfjoin_grid_info(const sj_grid *g, sj_grid_info *info);
+/* Grid facts of a built handle. The first call computes C_ref (one pass over
+ * the cells on `stream`) and caches it on the handle. */
+sj_status selfjoin_grid_info(sj_grid *g, sj_grid_info *info, void *stream);
 
 /* Releases the handle; its device memory is freed in stream order on
  * `stream`. NULL is accepted. */

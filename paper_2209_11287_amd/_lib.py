@@ -101,7 +101,7 @@ def load():
     lib.selfjoin_measure_error.restype = ctypes.c_int
     lib.selfjoin_measure_error.argtypes = [_vp, ctypes.c_int, _dp, _dp, _i64p, _vp]
     lib.selfjoin_grid_info.restype = ctypes.c_int
-    lib.selfjoin_grid_info.argtypes = [_vp, ctypes.POINTER(sj_grid_info)]
+    lib.selfjoin_grid_info.argtypes = [_vp, ctypes.POINTER(sj_grid_info), _vp]
     lib.selfjoin_free_grid.restype = None
     lib.selfjoin_free_grid.argtypes = [_vp, _vp]
     lib.selfjoin_status_string.restype = ctypes.c_char_p

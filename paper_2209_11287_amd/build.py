@@ -21,6 +21,8 @@ FLAGS = [
     "-ffp-contract=off",
     # no packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs (no AGPR copies around each tile)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 

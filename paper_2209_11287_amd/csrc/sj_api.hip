@@ -4,8 +4,11 @@
 
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 
 #include "sj_internal.h"
 
@@ -22,50 +25,121 @@ __global__ void k_scatter_counts(const int32_t *__restrict__ cnt, const int32_t 
     if (i < n) out[perm[i]] = cnt[i];
 }
 
-void pool_setup_once() {
-    static thread_local int done_dev = -1;
-    int dev = 0;
-    SJ_HIP(hipGetDevice(&dev));
-    if (done_dev == dev) return;
-    hipMemPool_t pool;
-    SJ_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
-    uint64_t thr = UINT64_MAX;
-    SJ_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
-    done_dev = dev;
-}
 }  // namespace
 
-void set_error(const std::string &msg) { g_err = msg; }
-const char *last_error() { return g_err.c_str(); }
+// ------------------------------------------------------------------------
+// Device memory: a caching allocator. hipMalloc is slow and synchronising,
+// and a build makes a few dozen temporary allocations, so freed blocks are
+// kept per device (tagged with the stream they were released on) and reused.
+// A block released on another stream is reused only after that stream has
+// drained. The cache is returned to the runtime when an allocation fails.
+// ------------------------------------------------------------------------
+namespace {
+
+struct FreeBlock {
+    void *p;
+    size_t size;
+    hipStream_t s;
+};
+
+struct DevCache {
+    std::multimap<size_t, FreeBlock> free;   // by size
+    std::unordered_map<void *, size_t> live; // allocation sizes
+};
+
+std::mutex g_mu;
+std::unordered_map<int, DevCache> g_cache;
+
+size_t round_size(size_t b) {
+    if (b <= 4096) return 4096;
+    if (b <= (size_t(1) << 20)) return (b + 4095) & ~size_t(4095);
+    // 1/8-octave classes above 1 MiB: at most 12.5% slack
+    int e = 63 - __builtin_clzll(b);
+    size_t step = size_t(1) << (e - 3);
+    return (b + step - 1) / step * step;
+}
+
+void release_cache(DevCache &c) {
+    (void)hipDeviceSynchronize();
+    for (auto &kv : c.free) (void)hipFree(kv.second.p);
+    c.free.clear();
+}
+
+}  // namespace
 
 void *dev_alloc(size_t bytes, hipStream_t s) {
-    pool_setup_once();
+    int dev = 0;
+    SJ_HIP(hipGetDevice(&dev));
+    const size_t sz = round_size(bytes);
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevCache &c = g_cache[dev];
+    // smallest cached block that fits without wasting more than 2x
+    auto it = c.free.lower_bound(sz);
+    auto best = c.free.end();
+    for (auto j = it; j != c.free.end() && j->first <= 2 * sz; ++j) {
+        if (j->second.s == s) {
+            best = j;
+            break;
+        }
+        if (best == c.free.end()) best = j;
+    }
+    if (best != c.free.end()) {
+        FreeBlock fb = best->second;
+        c.free.erase(best);
+        // released on another stream (which may no longer exist): drain the device
+        if (fb.s != s) SJ_HIP(hipDeviceSynchronize());
+        c.live[fb.p] = fb.size;
+        return fb.p;
+    }
     void *p = nullptr;
-    hipError_t e = hipMallocAsync(&p, bytes, s);
-    if (e == hipErrorOutOfMemory || (e == hipSuccess && !p)) throw OomError{bytes};
-    if (e != hipSuccess) throw HipError{e, "hipMallocAsync"};
+    hipError_t e = hipMalloc(&p, sz);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        release_cache(c);
+        e = hipMalloc(&p, sz);
+    }
+    if (e == hipErrorOutOfMemory || (e == hipSuccess && !p)) {
+        (void)hipGetLastError();
+        throw OomError{bytes};
+    }
+    if (e != hipSuccess) throw HipError{e, "hipMalloc"};
+    c.live[p] = sz;
     return p;
 }
 
 void dev_free(void *p, hipStream_t s) {
-    if (p) (void)hipFreeAsync(p, s);
+    if (!p) return;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevCache &c = g_cache[dev];
+    auto it = c.live.find(p);
+    if (it == c.live.end()) return;
+    c.free.insert({it->second, FreeBlock{p, it->second, s}});
+    c.live.erase(it);
 }
+
+void set_error(const std::string &msg) { g_err = msg; }
+const char *last_error() { return g_err.c_str(); }
 
 // Computes per-query counts with `path` into the handle's cache (sorted
 // order), their exclusive prefix sums and the total.
 static void compute_counts(Grid &g, sj_path path, RefineOut &ro, hipStream_t s) {
     if (!g.cnt) {
         g.cnt = dev_alloc_n<int32_t>((size_t)g.n + 1, s);
-        g.off = dev_alloc_n<int64_t>((size_t)g.n + 1, s);
+        g.off = dev_alloc_n<int64_t>((size_t)g.n + 2, s);  // [n + 1]: band counter
     }
+    ro.band_dev = reinterpret_cast<unsigned long long *>(g.off + g.n + 1);
     hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, g.cnt + g.n, 0);
     SJ_HIP(hipGetLastError());
     if (g.n > 0) refine_count(g, path, g.cnt, ro, s);
+    else fill_zero(ro.band_dev, sizeof(unsigned long long), s);
     exclusive_scan_i32_to_i64(g.cnt, g.off, g.n + 1, s);
-    int64_t total = 0;
-    SJ_HIP(hipMemcpyAsync(&total, g.off + g.n, sizeof total, hipMemcpyDeviceToHost, s));
+    int64_t h[2] = {0, 0};  // total, band pairs (one read, one sync)
+    SJ_HIP(hipMemcpyAsync(h, g.off + g.n, sizeof h, hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
-    g.total = total;
+    g.total = h[0];
+    ro.band_pairs = h[1];
     g.have_counts = true;
 }
 
@@ -170,13 +244,13 @@ sj_status selfjoin_count(sj_grid *gh, sj_path path, int32_t *per_point, int64_t 
         SJ_HIP(hipEventElapsedTime(&ms, e0, e1));
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        stats->cand_ref = g.cand_ref;
-        stats->cand_eval = ro.cand_eval;
+        stats->cand_ref = g.cand_ref;  // -1 until selfjoin_grid_info computed it
+        stats->cand_eval = g.cand_items;
         stats->pairs = g.total;
         stats->band_pairs = ro.band_pairs;
         stats->band_rel = ro.band_rel;
         stats->ms = ms;
-        stats->ms_kernel = ro.ms_kernel;
+        stats->ms_kernel = ro.kt.ms();
     }
     return SJ_OK;
     SJ_API_END
@@ -207,7 +281,17 @@ sj_status selfjoin_pairs(sj_grid *gh, sj_path path, int64_t cursor, int32_t *pai
     }
     RefineOut ro;
     if (!g.have_counts) compute_counts(g, path, ro, s);
-    const ChunkPlan p = plan_chunk(g, cursor, capacity, s);
+    ChunkPlan p;
+    if (cursor == 0 && capacity >= g.total) {
+        // the whole result fits: no device search needed
+        p.written = g.total;
+        p.next = g.n;
+        p.item_lo = 0;
+        p.item_hi = g.items;
+        p.base = 0;
+    } else {
+        p = plan_chunk(g, cursor, capacity, s);
+    }
     if (p.too_small) {
         *written = p.written;
         if (stats) {
@@ -219,7 +303,9 @@ sj_status selfjoin_pairs(sj_grid *gh, sj_path path, int64_t cursor, int32_t *pai
     }
     RefineOut re;
     re.timed = stats != nullptr;
+    re.band_dev = dev_alloc_n<unsigned long long>(1, s);
     refine_pairs(g, path, p, cursor, pairs, d2, re, s);
+    dev_free(re.band_dev, s);
     *written = p.written;
     *next_cursor = p.next;
     if (stats) {
@@ -230,12 +316,12 @@ sj_status selfjoin_pairs(sj_grid *gh, sj_path path, int64_t cursor, int32_t *pai
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         stats->cand_ref = g.cand_ref;
-        stats->cand_eval = ro.cand_eval;
+        stats->cand_eval = g.cand_items;
         stats->pairs = p.written;
         stats->band_pairs = ro.band_pairs;
         stats->band_rel = re.band_rel;
         stats->ms = ms;
-        stats->ms_kernel = re.ms_kernel;
+        stats->ms_kernel = re.kt.ms();
     }
     return SJ_OK;
     SJ_API_END
@@ -254,9 +340,12 @@ sj_status selfjoin_measure_error(sj_grid *gh, sj_path path, double *max_abs_err,
     SJ_API_END
 }
 
-sj_status selfjoin_grid_info(const sj_grid *gh, sj_grid_info *info) {
+sj_status selfjoin_grid_info(sj_grid *gh, sj_grid_info *info, void *stream) {
+    set_error("");
     if (!gh || !info) return invalid("NULL argument");
-    const Grid &g = gh->g;
+    SJ_API_BEGIN
+    Grid &g = gh->g;
+    grid_cref(g, static_cast<hipStream_t>(stream));
     info->n = g.n;
     info->d = g.d;
     info->k = g.k;
@@ -268,6 +357,7 @@ sj_status selfjoin_grid_info(const sj_grid *gh, sj_grid_info *info) {
     info->cand_ref = g.cand_ref;
     info->cand_items = g.cand_items;
     return SJ_OK;
+    SJ_API_END
 }
 
 void selfjoin_free_grid(sj_grid *gh, void *stream) {

@@ -44,10 +44,17 @@ __host__ __device__ __forceinline__ double ord_to_dbl(unsigned long long u) {
     return r;
 }
 
-__global__ void k_fill_u8(unsigned char *p, size_t bytes) {
+__global__ void k_fill_u8(unsigned char *p, size_t bytes, unsigned char v) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (; i < bytes; i += stride) p[i] = 0;
+    for (; i < bytes; i += stride) p[i] = v;
+}
+
+void fill_ones(void *p, size_t bytes, hipStream_t s) {
+    if (!bytes) return;
+    unsigned blocks = (unsigned)std::min<size_t>((bytes + kThreads - 1) / kThreads, 4096);
+    hipLaunchKernelGGL(k_fill_u8, dim3(blocks), dim3(kThreads), 0, s, (unsigned char *)p, bytes, (unsigned char)0xff);
+    SJ_HIP(hipGetLastError());
 }
 
 
@@ -240,36 +247,36 @@ __global__ void k_scan_sums(const Tin *__restrict__ in, int64_t n, Tacc *__restr
     }
 }
 
-// Exclusive scan of one tile with a carry-in from `carry` (nullable).
+// Exclusive scan of one tile with a carry-in from `carry` (nullable): each
+// thread scans kScanItems consecutive elements, the thread totals are scanned
+// across the wave and the block.
 template <typename Tin, typename Tacc>
 __global__ void k_scan_tiles(const Tin *__restrict__ in, Tacc *__restrict__ out, int64_t n,
                              const Tacc *__restrict__ carry) {
-    __shared__ Tacc wtot[kThreads / 64];
-    __shared__ Tacc base;
+    __shared__ Tacc wsum[kThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid == 0) base = carry ? carry[blockIdx.x] : (Tacc)0;
+    const int64_t e0 = (int64_t)blockIdx.x * kScanTile + (int64_t)tid * kScanItems;
+    Tacc v[kScanItems];
+    Tacc sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        v[i] = e0 + i < n ? (Tacc)in[e0 + i] : (Tacc)0;
+        sum += v[i];
+    }
+    Tacc x = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+        const Tacc y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
     __syncthreads();
-    const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
-    for (int r = 0; r < kScanItems; ++r) {
-        const int64_t i = t0 + (int64_t)r * kThreads + tid;
-        const Tacc v = i < n ? (Tacc)in[i] : (Tacc)0;
-        Tacc x = v;
-        for (int o = 1; o < 64; o <<= 1) {
-            Tacc y = __shfl_up(x, o);
-            if (lane >= o) x += y;
-        }
-        if (lane == 63) wtot[wave] = x;
-        __syncthreads();
-        Tacc pre = base;
-        for (int w = 0; w < wave; ++w) pre += wtot[w];
-        if (i < n) out[i] = pre + x - v;
-        __syncthreads();
-        if (tid == kThreads - 1) {
-            Tacc s = base;
-            for (int w = 0; w < kThreads / 64; ++w) s += wtot[w];
-            base = s;
-        }
-        __syncthreads();
+    Tacc pre = carry ? carry[blockIdx.x] : (Tacc)0;
+    for (int w = 0; w < wave; ++w) pre += wsum[w];
+    Tacc run = pre + x - sum;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        if (e0 + i < n) out[e0 + i] = run;
+        run += v[i];
     }
 }
 
@@ -331,8 +338,15 @@ __global__ void k_gather(const double *__restrict__ X, const int32_t *__restrict
         nrm[i] = nn;
     }
     // norms are >= 0: their bit patterns order like their values
+    __shared__ double part[kThreads / 64];
     for (int o = 32; o > 0; o >>= 1) nn = fmax(nn, __shfl_xor(nn, o));
-    if ((threadIdx.x & 63) == 0) atomicMax(nmax_ord, (unsigned long long)__double_as_longlong(nn));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = nn;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = part[0];
+        for (int w = 1; w < kThreads / 64; ++w) m = fmax(m, part[w]);
+        atomicMax(nmax_ord, (unsigned long long)__double_as_longlong(m));
+    }
 }
 
 // ----------------------------------------------------------- cell table ----
@@ -429,83 +443,160 @@ __global__ void k_items(const int32_t *__restrict__ line_first, const int32_t *_
 }
 
 // ------------------------------------------------------- neighbour ranges ----
-// For cell c and each offset o in {-1,0,1}^(k-1) of the leading indexed
-// coordinates, the sorted-point range of the cells whose leading coordinates
-// are c's plus o and whose last coordinate is within one of c's (three cells
-// adjacent in key order, hence one contiguous range). Out-of-grid offsets give
-// an empty range. Also accumulates C_ref = sum_c |c| * (candidates of c).
+// For a cell with coordinates c and each offset o in {-1,0,1}^(k-1) of the
+// leading indexed coordinates, the cells whose leading coordinates are c's
+// plus o and whose last coordinate is within one of c's are adjacent in key
+// order, hence one contiguous range of sorted points. A work item (queries of
+// cells first..last of one line) takes, per offset, the union of those
+// ranges of its first and last cell: last coordinates from first - 1 to
+// last + 1. Out-of-grid offsets give an empty range.
 struct RangeGeom {
     int k, nranges;
     int64_t m[kMaxIndexDims];
     int64_t stride[kMaxIndexDims];
 };
 
-__device__ __forceinline__ int64_t lower_bound_i64(const int64_t *v, int64_t n, int64_t x) {
-    int64_t a = 0, b = n;
-    while (a < b) {
-        const int64_t mid = a + (b - a) / 2;
-        if (v[mid] < x) a = mid + 1;
-        else b = mid;
+// Sorted-point range [begin, end) of the cells of line `base` (key of the
+// line with last coordinate 0) whose last coordinate is in [lo_c, hi_c].
+__device__ __forceinline__ Range line_segment(const int64_t *__restrict__ cell_key,
+                                              const int32_t *__restrict__ cell_start, int64_t ncells,
+                                              const int32_t *__restrict__ line_of_key,
+                                              const int32_t *__restrict__ line_first, int64_t base, int64_t mlast,
+                                              int64_t lo_c, int64_t hi_c) {
+    Range r{0, 0};
+    int64_t a = 0, b = ncells;
+    if (line_of_key) {
+        const int32_t lid = line_of_key[base / mlast];
+        if (lid < 0) return r;
+        a = line_first[lid];
+        b = line_first[lid + 1];
     }
-    return a;
+    const int64_t lo = base + lo_c, hi = base + hi_c;
+    int64_t x = a, y = b;  // first cell with key >= lo
+    while (x < y) {
+        const int64_t mid = x + (y - x) / 2;
+        if (cell_key[mid] < lo) x = mid + 1;
+        else y = mid;
+    }
+    const int64_t ca = x;
+    y = b;  // first cell with key > hi
+    while (x < y) {
+        const int64_t mid = x + (y - x) / 2;
+        if (cell_key[mid] <= hi) x = mid + 1;
+        else y = mid;
+    }
+    r.begin = cell_start[ca];
+    r.end = cell_start[x];
+    return r;
 }
 
-__global__ void k_ranges(const int64_t *__restrict__ cell_key, const int32_t *__restrict__ cell_start,
-                         const int32_t *__restrict__ ncells_p, RangeGeom geo, Range *__restrict__ ranges,
-                         unsigned long long *__restrict__ cref) {
+__device__ __forceinline__ void decode_key(int64_t key, const RangeGeom &geo, int64_t *cc) {
+    for (int j = 0; j < geo.k; ++j) {
+        cc[j] = key / geo.stride[j];
+        key -= cc[j] * geo.stride[j];
+    }
+}
+
+// Neighbouring line of offset o (base key, or -1 if outside the grid).
+__device__ __forceinline__ int64_t neighbour_line(const int64_t *cc, int o, const RangeGeom &geo) {
+    int64_t base = 0;
+    for (int j = 0; j < geo.k - 1; ++j) {
+        const int64_t cj = cc[j] + (o % 3) - 1;
+        o /= 3;
+        if (cj < 0 || cj >= geo.m[j]) return -1;
+        base += cj * geo.stride[j];
+    }
+    return base;
+}
+
+// Block sum then one atomic per block.
+__device__ __forceinline__ void block_add(unsigned long long v, unsigned long long *out) {
+    __shared__ unsigned long long part[kThreads / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kThreads / 64; ++w) t += part[w];
+        if (t) atomicAdd(out, t);
+    }
+}
+
+// Ranges of every work item (grid-stride over item x offset), plus the
+// number of candidate pairs the items see.
+__global__ void k_item_ranges(const Item *__restrict__ items, const int32_t *__restrict__ nitems_p,
+                              const int64_t *__restrict__ cell_key, const int32_t *__restrict__ cell_start,
+                              const int32_t *__restrict__ ncells_p, RangeGeom geo,
+                              const int32_t *__restrict__ line_of_key, const int32_t *__restrict__ line_first,
+                              Range *__restrict__ ranges, unsigned long long *__restrict__ cand_items) {
+    const int64_t total = (int64_t)(*nitems_p) * geo.nranges;
     const int64_t ncells = *ncells_p;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long contrib = 0;
-    if (t < ncells * geo.nranges) {
-        const int64_t c = t / geo.nranges;
-        int o = (int)(t - c * geo.nranges);
-        int64_t key = cell_key[c];
-        int64_t cc[kMaxIndexDims];
-        for (int j = 0; j < geo.k; ++j) {
-            cc[j] = key / geo.stride[j];
-            key -= cc[j] * geo.stride[j];
-        }
-        bool ok = true;
-        int64_t base = 0;
-        for (int j = 0; j < geo.k - 1; ++j) {
-            const int64_t cj = cc[j] + (o % 3) - 1;
-            o /= 3;
-            if (cj < 0 || cj >= geo.m[j]) ok = false;
-            base += cj * geo.stride[j];
-        }
+    const int kl = geo.k - 1;
+    const int64_t mlast = geo.m[kl];
+    unsigned long long acc = 0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t it = t / geo.nranges;
+        const int o = (int)(t - it * geo.nranges);
+        const Item I = items[it];
+        int64_t c0[kMaxIndexDims], c1[kMaxIndexDims];
+        decode_key(cell_key[I.cell_first], geo, c0);
+        decode_key(cell_key[I.cell_last], geo, c1);
+        const int64_t base = neighbour_line(c0, o, geo);
         Range r{0, 0};
-        if (ok) {
-            const int kl = geo.k - 1;
-            const int64_t lo = base + (cc[kl] > 0 ? cc[kl] - 1 : 0);
-            const int64_t hi = base + (cc[kl] < geo.m[kl] - 1 ? cc[kl] + 1 : cc[kl]);
-            const int64_t a = lower_bound_i64(cell_key, ncells, lo);
-            const int64_t b = lower_bound_i64(cell_key, ncells, hi + 1);
-            r.begin = cell_start[a];
-            r.end = cell_start[b];
+        if (base >= 0) {
+            const int64_t lo_c = c0[kl] > 0 ? c0[kl] - 1 : 0;
+            const int64_t hi_c = c1[kl] < mlast - 1 ? c1[kl] + 1 : c1[kl];
+            r = line_segment(cell_key, cell_start, ncells, line_of_key, line_first, base, mlast, lo_c, hi_c);
         }
         ranges[t] = r;
-        contrib = (unsigned long long)(cell_start[c + 1] - cell_start[c]) * (unsigned long long)(r.end - r.begin);
+        acc += (unsigned long long)(I.qend - I.qbegin) * (unsigned long long)(r.end - r.begin);
     }
-    for (int o2 = 32; o2 > 0; o2 >>= 1) contrib += __shfl_xor(contrib, o2);
-    if ((threadIdx.x & 63) == 0 && contrib) atomicAdd(cref, contrib);
+    block_add(acc, cand_items);
 }
 
-// Candidates the work items see: sum over items of |queries| * |union ranges|.
-__global__ void k_item_cands(const Item *__restrict__ items, const int32_t *__restrict__ nitems_p,
-                             const Range *__restrict__ ranges, int nranges, unsigned long long *__restrict__ out) {
-    const int64_t nitems = *nitems_p;
-    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long v = 0;
-    if (it < nitems) {
-        const Item I = items[it];
-        unsigned long long s = 0;
-        for (int o = 0; o < nranges; ++o)
-            s += (unsigned long long)(ranges[(int64_t)I.cell_last * nranges + o].end -
-                                      ranges[(int64_t)I.cell_first * nranges + o].begin);
-        v = s * (unsigned long long)(I.qend - I.qbegin);
+// C_ref = sum over non-empty cells c of |c| * (points in the 3^k cells around
+// c): the implementation-free work unit (grid-stride over cell x offset).
+__global__ void k_cell_cref(const int64_t *__restrict__ cell_key, const int32_t *__restrict__ cell_start,
+                            int64_t ncells, RangeGeom geo, const int32_t *__restrict__ line_of_key,
+                            const int32_t *__restrict__ line_first, unsigned long long *__restrict__ cref) {
+    const int64_t total = ncells * geo.nranges;
+    const int kl = geo.k - 1;
+    const int64_t mlast = geo.m[kl];
+    unsigned long long acc = 0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = t / geo.nranges;
+        const int o = (int)(t - c * geo.nranges);
+        int64_t cc[kMaxIndexDims];
+        decode_key(cell_key[c], geo, cc);
+        const int64_t base = neighbour_line(cc, o, geo);
+        if (base < 0) continue;
+        const int64_t lo_c = cc[kl] > 0 ? cc[kl] - 1 : 0;
+        const int64_t hi_c = cc[kl] < mlast - 1 ? cc[kl] + 1 : cc[kl];
+        const Range r = line_segment(cell_key, cell_start, ncells, line_of_key, line_first, base, mlast, lo_c, hi_c);
+        acc += (unsigned long long)(cell_start[c + 1] - cell_start[c]) * (unsigned long long)(r.end - r.begin);
     }
-    for (int o2 = 32; o2 > 0; o2 >>= 1) v += __shfl_xor(v, o2);
-    if ((threadIdx.x & 63) == 0 && v) atomicAdd(out, v);
+    block_add(acc, cref);
+}
+
+// Dense map line key -> compact line id (-1 for empty lines).
+__global__ void k_line_table(const int64_t *__restrict__ cell_key, const int32_t *__restrict__ line_first,
+                             const int32_t *__restrict__ nlines_p, int64_t m_last, int32_t *__restrict__ table) {
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= *nlines_p) return;
+    table[cell_key[line_first[l]] / m_last] = (int32_t)l;
+}
+
+RangeGeom range_geom(const Grid &g) {
+    RangeGeom rg{};
+    rg.k = g.k;
+    rg.nranges = g.nranges;
+    for (int j = 0; j < g.k; ++j) {
+        rg.m[j] = g.m[j];
+        rg.stride[j] = g.stride[j];
+    }
+    return rg;
 }
 
 unsigned blocks_for(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + kThreads - 1) / kThreads); }
@@ -515,7 +606,7 @@ unsigned blocks_for(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + kThr
 void fill_zero(void *p, size_t bytes, hipStream_t s) {
     if (!bytes) return;
     unsigned blocks = (unsigned)std::min<size_t>((bytes + kThreads - 1) / kThreads, 4096);
-    hipLaunchKernelGGL(k_fill_u8, dim3(blocks), dim3(kThreads), 0, s, (unsigned char *)p, bytes);
+    hipLaunchKernelGGL(k_fill_u8, dim3(blocks), dim3(kThreads), 0, s, (unsigned char *)p, bytes, (unsigned char)0);
     SJ_HIP(hipGetLastError());
 }
 
@@ -524,7 +615,8 @@ void exclusive_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipSt
 }
 
 void free_grid(Grid &g, hipStream_t s) {
-    void *bufs[] = {g.xs, g.xa, g.nrm, g.perm, g.cell_key, g.cell_start, g.ranges, g.item, g.dev_nmax, g.cnt, g.off};
+    void *bufs[] = {g.xs,   g.xa,       g.nrm,      g.perm, g.cell_key, g.cell_start, g.ranges,
+                    g.item, g.dev_nmax, g.line_first, g.line_table, g.cnt, g.off};
     for (void *p : bufs)
         if (p) dev_free(p, s);
     g.xs = g.xa = g.nrm = nullptr;
@@ -534,6 +626,8 @@ void free_grid(Grid &g, hipStream_t s) {
     g.ranges = nullptr;
     g.item = nullptr;
     g.dev_nmax = nullptr;
+    g.line_first = nullptr;
+    g.line_table = nullptr;
     g.cnt = nullptr;
     g.off = nullptr;
 }
@@ -703,49 +797,50 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
                            counters + 1, nitem);
         SJ_HIP(hipGetLastError());
     }
-    // ---- G5: neighbour ranges per cell + C_ref (tables sized by upper bounds) ----
-    unsigned long long *acc = dev_alloc_n<unsigned long long>(2, s);
-    fill_zero(acc, 2 * sizeof(unsigned long long), s);
-    const int64_t cells_ub = std::max<int64_t>(1, n);
-    g.ranges = dev_alloc_n<Range>((size_t)cells_ub * g.nranges, s);
+    // ---- G5: work items and their neighbour ranges (tables sized by upper bounds) ----
+    unsigned long long *acc = dev_alloc_n<unsigned long long>(1, s);
+    fill_zero(acc, sizeof(unsigned long long), s);
     const int64_t items_ub = n + n / kTileQ + 1;  // lines <= cells <= n
     g.item = dev_alloc_n<Item>((size_t)items_ub, s);
+    g.ranges = dev_alloc_n<Range>((size_t)items_ub * g.nranges, s);
+    g.line_first = line_first;
+    line_first = nullptr;  // kept by the grid (lazy C_ref)
     if (n > 0) {
         exclusive_scan<int32_t, int32_t>(nitem, item_off, n, s);  // entries past nlines are ignored
         hipLaunchKernelGGL(k_items_total, dim3(1), dim3(1), 0, s, nitem, item_off, counters + 1, counters + 2);
         SJ_HIP(hipGetLastError());
-        RangeGeom rg{};
-        rg.k = g.k;
-        rg.nranges = g.nranges;
-        for (int j = 0; j < g.k; ++j) {
-            rg.m[j] = g.m[j];
-            rg.stride[j] = g.stride[j];
+        // dense line table when the leading indexed dimensions span few lines
+        int64_t nline_keys = 1;
+        for (int j = 0; j < g.k - 1; ++j) nline_keys *= g.m[j];
+        if (nline_keys <= (int64_t(1) << 24)) {
+            g.line_table = dev_alloc_n<int32_t>((size_t)nline_keys, s);
+            fill_ones(g.line_table, (size_t)nline_keys * sizeof(int32_t), s);
+            hipLaunchKernelGGL(k_line_table, dim3(blocks_for(n)), dim3(kThreads), 0, s, g.cell_key, g.line_first,
+                               counters + 1, (int64_t)g.m[g.k - 1], g.line_table);
+            SJ_HIP(hipGetLastError());
         }
-        hipLaunchKernelGGL(k_ranges, dim3(blocks_for(cells_ub * g.nranges)), dim3(kThreads), 0, s, g.cell_key,
-                           g.cell_start, counters + 0, rg, g.ranges, acc);
-        SJ_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_items, dim3(blocks_for(items_ub)), dim3(kThreads), 0, s, line_first, item_off,
+        hipLaunchKernelGGL(k_items, dim3(blocks_for(items_ub)), dim3(kThreads), 0, s, g.line_first, item_off,
                            g.cell_start, counters + 1, counters + 2, g.item);
         SJ_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_item_cands, dim3(blocks_for(items_ub)), dim3(kThreads), 0, s, g.item,
-                           counters + 2, g.ranges, g.nranges, acc + 1);
+        hipLaunchKernelGGL(k_item_ranges, dim3(2048), dim3(kThreads), 0, s, g.item, counters + 2, g.cell_key,
+                           g.cell_start, counters + 0, range_geom(g), g.line_table, g.line_first, g.ranges, acc);
         SJ_HIP(hipGetLastError());
     }
-    // ---- one host sync: table sizes, C_ref, nmax ----
+    // ---- one host sync: table sizes, candidates of the items, nmax ----
     int32_t hc[4] = {0, 0, 0, 0};
     double hn = 0.0;
-    unsigned long long hacc[2] = {0, 0};
+    unsigned long long hacc = 0;
     if (n > 0) {
         SJ_HIP(hipMemcpyAsync(hc, counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         SJ_HIP(hipMemcpyAsync(&hn, g.dev_nmax, sizeof(double), hipMemcpyDeviceToHost, s));
-        SJ_HIP(hipMemcpyAsync(hacc, acc, sizeof hacc, hipMemcpyDeviceToHost, s));
+        SJ_HIP(hipMemcpyAsync(&hacc, acc, sizeof hacc, hipMemcpyDeviceToHost, s));
         SJ_HIP(hipStreamSynchronize(s));
     }
     g.cells = hc[0];
     g.items = hc[2];
     g.nmax = hn;
-    g.cand_ref = (int64_t)hacc[0];
-    g.cand_items = (int64_t)hacc[1];
+    g.cand_ref = -1;  // computed on request (grid_cref)
+    g.cand_items = (int64_t)hacc;
 
     dev_free(acc, s);
     dev_free(key_a, s);
@@ -753,9 +848,24 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     dev_free(flag, s);
     dev_free(cid, s);
     dev_free(counters, s);
-    dev_free(line_first, s);
     dev_free(nitem, s);
     dev_free(item_off, s);
+}
+
+int64_t grid_cref(Grid &g, hipStream_t s) {
+    if (g.cand_ref >= 0) return g.cand_ref;
+    if (g.cells == 0) return g.cand_ref = 0;
+    unsigned long long *acc = dev_alloc_n<unsigned long long>(1, s);
+    fill_zero(acc, sizeof(unsigned long long), s);
+    hipLaunchKernelGGL(k_cell_cref, dim3(2048), dim3(kThreads), 0, s, g.cell_key, g.cell_start, g.cells,
+                       range_geom(g), g.line_table, g.line_first, acc);
+    SJ_HIP(hipGetLastError());
+    unsigned long long h = 0;
+    SJ_HIP(hipMemcpyAsync(&h, acc, sizeof h, hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    dev_free(acc, s);
+    g.cand_ref = (int64_t)h;
+    return g.cand_ref;
 }
 
 }  // namespace sj

@@ -78,7 +78,8 @@ struct Grid {
     int32_t key_bits = 0;
     int64_t cells = 0;
     int64_t items = 0;
-    int64_t cand_ref = 0, cand_items = 0;
+    int64_t cand_ref = -1;   // C_ref (lazily computed; -1 = not yet)
+    int64_t cand_items = 0;  // candidate pairs the work items evaluate
     double nmax = 0;       // max squared norm of the centred rows of xa
 
     // device buffers
@@ -88,8 +89,10 @@ struct Grid {
     int32_t *perm = nullptr;     // sorted position -> input index
     int64_t *cell_key = nullptr; // per non-empty cell
     int32_t *cell_start = nullptr; // cells + 1 entries
-    Range *ranges = nullptr;     // cells x nranges
+    Range *ranges = nullptr;     // items x nranges: candidate ranges of each work item
     Item *item = nullptr;        // items
+    int32_t *line_first = nullptr;  // first cell of each grid line (+ end marker)
+    int32_t *line_table = nullptr;  // dense line key -> line id (or null when too large)
     double *dev_nmax = nullptr;  // device copy of nmax
 
     // cached per-query counts (sorted order) and their exclusive prefix sums
@@ -105,6 +108,8 @@ struct Grid {
 void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int index_dims,
                 hipStream_t s);
 void free_grid(Grid &g, hipStream_t s);
+// C_ref of the reference grid, computed on first request and cached.
+int64_t grid_cref(Grid &g, hipStream_t s);
 
 // Zero fill by kernel (usable under stream capture, unlike a memset node).
 void fill_zero(void *p, size_t bytes, hipStream_t s);
@@ -113,14 +118,6 @@ void fill_zero(void *p, size_t bytes, hipStream_t s);
 void exclusive_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
 
 // Refine (sj_refine.hip).
-struct RefineOut {
-    bool timed = false;      // record events around the tile kernel
-    int64_t band_pairs = 0;
-    double band_rel = 0;
-    int64_t cand_eval = 0;
-    float ms_kernel = 0;
-};
-
 // Events bracketing one kernel launch on a stream.
 struct KernelTimer {
     hipEvent_t a = nullptr, b = nullptr;
@@ -152,6 +149,17 @@ struct KernelTimer {
         }
     }
 };
+
+struct RefineOut {
+    bool timed = false;      // record events around the tile kernel
+    KernelTimer kt;          // those events
+    unsigned long long *band_dev = nullptr;  // device counter of rechecked pairs
+    int64_t band_pairs = 0;
+    double band_rel = 0;
+    int64_t cand_eval = 0;
+};
+
+
 struct ChunkPlan {
     bool too_small = false;  // the next query alone needs more than the capacity
     int64_t written = 0;     // pairs of the chunk (or the capacity needed)

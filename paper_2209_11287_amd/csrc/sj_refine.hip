@@ -94,11 +94,106 @@ __device__ __forceinline__ unsigned long long lanemask_lt() {
     return lane ? ((~0ull) >> (64u - lane)) : 0ull;
 }
 
+// ------------------------------------------------------------ shared parts --
+// Candidate ranges of a work item: lane o (< nranges) holds range o's bounds.
+struct ItemRanges {
+    int rb, re;
+    int nr;
+    __device__ __forceinline__ int begin(int o) const { return __builtin_amdgcn_readlane(rb, o); }
+    __device__ __forceinline__ int end(int o) const { return __builtin_amdgcn_readlane(re, o); }
+    __device__ __forceinline__ int first_nonempty(int o) const {
+        while (o < nr && begin(o) >= end(o)) ++o;
+        return o;
+    }
+};
+
+__device__ __forceinline__ ItemRanges load_ranges(const DevGrid &G, int it, int lane) {
+    ItemRanges r;
+    r.nr = G.nranges;
+    r.rb = 0;
+    r.re = 0;
+    if (lane < G.nranges) {
+        const Range x = G.ranges[(int64_t)it * G.nranges + lane];
+        r.rb = x.begin;
+        r.re = x.end;
+    }
+    return r;
+}
+
+// Walks the item's candidate tiles (all ranges, in order) `step` rows at a time.
+struct TileCursor {
+    int o, t, ce;
+    __device__ __forceinline__ bool live(const ItemRanges &rg) const { return o < rg.nr; }
+    __device__ __forceinline__ void first(const ItemRanges &rg) {
+        o = rg.first_nonempty(0);
+        t = o < rg.nr ? rg.begin(o) : 0;
+        ce = o < rg.nr ? rg.end(o) : 0;
+    }
+    __device__ __forceinline__ void advance(const ItemRanges &rg, int step) {
+        t += step;
+        if (t >= ce) {
+            o = rg.first_nonempty(o + 1);
+            if (o < rg.nr) {
+                t = rg.begin(o);
+                ce = rg.end(o);
+            }
+        }
+    }
+};
+
+// Wave-local LDS ordering (stores by some lanes, loads by others).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Emission. Pairs go to exact offsets (prefix sums of the count pass), so a
+// query's pairs form one run in candidate order. Flagged pairs are first
+// compacted, wave-wide, into an LDS ring (candidate, rank within its query,
+// query column); whenever 64 are queued, one full-width store writes them.
+// This replaces one mostly-idle store instruction per tile and row slice by
+// one fully-populated store per 64 pairs.
+constexpr int kRing = 512;  // > 63 queued + 256 from one tile
+
+struct EmitRing {
+    uint32_t *cand;  // sorted index of the candidate
+    uint32_t *rel;   // rank of the pair within its query's run
+    uint32_t *col;   // query column (0..15)
+    int head, tail;  // wave-uniform counters (entries flushed / appended)
+};
+
+// Writes `n` ring entries starting at head (n <= 64), lane l one entry.
+__device__ __forceinline__ void ring_flush(EmitRing &rb, int n, const DevGrid &G, const RefOut &R, int lane,
+                                           int64_t pbase_of_lane, int32_t pq_of_lane, int q0) {
+    wave_lds_sync();
+    const int e = (rb.head + lane) & (kRing - 1);
+    const uint32_t c = rb.cand[e], rel = rb.rel[e], j = rb.col[e];
+    // the query's output base and input index live in lane j (j < 16)
+    const int64_t pb = __shfl(pbase_of_lane, (int)j);
+    const int32_t pq = __shfl(pq_of_lane, (int)j);
+    if (lane < n) {
+        const int64_t pos = pb + rel;
+        reinterpret_cast<int2 *>(R.pairs)[pos] = make_int2(pq, G.perm[c]);
+        if (R.d2)
+            R.d2[pos] = exact_d2(G.xs + (int64_t)(q0 + (int)j) * G.dp, G.xs + (int64_t)c * G.dp, G.d);
+    }
+    rb.head += n;
+    wave_lds_sync();
+}
+
+__device__ __forceinline__ void ring_drain(EmitRing &rb, bool all, const DevGrid &G, const RefOut &R, int lane,
+                                           int64_t pbase_of_lane, int32_t pq_of_lane, int q0) {
+    while (rb.tail - rb.head >= 64) ring_flush(rb, 64, G, R, lane, pbase_of_lane, pq_of_lane, q0);
+    if (all && rb.tail > rb.head) ring_flush(rb, rb.tail - rb.head, G, R, lane, pbase_of_lane, pq_of_lane, q0);
+}
+
 // --------------------------------------------------------------------- V64 --
-// Candidate coordinates of one lane, D known at compile time (0 = runtime d,
-// read from memory per dimension).
+// lane = candidate (64 per tile), loop over the item's queries. D > 0: the
+// candidate row is held in registers; D = 0: runtime d, read per dimension.
 template <int D, int MODE>
 __global__ __launch_bounds__(kThreads) void k_v64(DevGrid G, RefOut R) {
+    __shared__ uint32_t ring_lds[MODE == MODE_EMIT ? kWaves * 3 * kRing : 1];
     const int lane = threadIdx.x & 63;
     const int wv = uniform_i32(threadIdx.x >> 6);
     const int it = uniform_i32(R.item_lo + xcd_block(blockIdx.x, gridDim.x) * kWaves + wv);
@@ -110,82 +205,219 @@ __global__ __launch_bounds__(kThreads) void k_v64(DevGrid G, RefOut R) {
     const int dp = G.dp;
     const double eps2 = G.eps2;
     const double *__restrict__ xs = G.xs;
+    const ItemRanges rg = load_ranges(G, it, lane);
 
+    // emit state of query `lane` (lanes < nq)
+    int64_t my_pbase = -1;
+    int32_t my_pq = 0;
+    bool emit_q = false;
+    if (MODE == MODE_EMIT && lane < nq && q0 + lane >= R.qlo && q0 + lane < R.qhi) {
+        my_pbase = R.off[q0 + lane] - R.base;
+        my_pq = G.perm[q0 + lane];
+        emit_q = true;
+    }
+    const unsigned long long emit_mask = __ballot(emit_q);
+    EmitRing rb;
+    rb.cand = ring_lds + (MODE == MODE_EMIT ? wv * 3 * kRing : 0);
+    rb.rel = rb.cand + kRing;
+    rb.col = rb.rel + kRing;
+    rb.head = rb.tail = 0;
+    int my_cur = 0;
+    const unsigned long long lt = lanemask_lt();
     int cnt[kTileQ];
 #pragma unroll
     for (int jq = 0; jq < kTileQ; ++jq) cnt[jq] = 0;
-    // emit state of query `lane` (lanes < nq): output window and cursor
-    int64_t my_pbase = -1, my_pend = 0;
-    int my_cur = 0;
-    if (MODE == MODE_EMIT && lane < nq && q0 + lane >= R.qlo && q0 + lane < R.qhi) {
-        my_pbase = R.off[q0 + lane] - R.base;
-        my_pend = R.off[q0 + lane + 1] - R.base;
+
+    TileCursor tc;
+    tc.first(rg);
+    double xn[D > 0 ? D : 1];
+    if (D > 0 && tc.live(rg)) {
+        const double *xc = xs + (int64_t)(tc.t + lane) * dp;  // rows are padded past n
+#pragma unroll
+        for (int u = 0; u < (D > 0 ? D : 1); ++u) xn[u] = xc[u];
     }
-    const unsigned long long lt = lanemask_lt();
-    for (int o = 0; o < G.nranges; ++o) {
-        const int cb = uniform_i32(G.ranges[(int64_t)I.cell_first * G.nranges + o].begin);
-        const int ce = uniform_i32(G.ranges[(int64_t)I.cell_last * G.nranges + o].end);
-        for (int t = cb; t < ce; t += 64) {
-            const int c = t + lane;  // < n + 64: rows are padded
-            const bool valid = c < ce;
-            const double *__restrict__ xc = xs + (int64_t)c * dp;
-            double x[D > 0 ? D : 1];
-            if (D > 0) {
+    while (tc.live(rg)) {
+        const int t = tc.t, ce = tc.ce;
+        const int c = t + lane;
+        const bool valid = c < ce;
+        double x[D > 0 ? D : 1];
 #pragma unroll
-                for (int u = 0; u < (D > 0 ? D : 1); ++u) x[u] = xc[u];
-            }
+        for (int u = 0; u < (D > 0 ? D : 1); ++u) x[u] = xn[u];
+        tc.advance(rg, 64);
+        if (D > 0 && tc.live(rg)) {  // prefetch the next tile
+            const double *xc2 = xs + (int64_t)(tc.t + lane) * dp;
 #pragma unroll
-            for (int jq = 0; jq < kTileQ; ++jq) {
-                if (jq < nq) {
-                    const double *__restrict__ xq = xs + (int64_t)(q0 + jq) * dp;
-                    double acc = 0.0;
-                    if (D > 0) {
+            for (int u = 0; u < (D > 0 ? D : 1); ++u) xn[u] = xc2[u];
+        }
+        const double *__restrict__ xc = xs + (int64_t)c * dp;
 #pragma unroll
-                        for (int u = 0; u < (D > 0 ? D : 1); ++u) {
-                            const double delta = __dsub_rn(xq[u], x[u]);
-                            acc = __fma_rn(delta, delta, acc);
-                        }
-                    } else {
-                        for (int u = 0; u < d; ++u) {
-                            const double delta = __dsub_rn(xq[u], xc[u]);
-                            acc = __fma_rn(delta, delta, acc);
-                        }
+        for (int jq = 0; jq < kTileQ; ++jq) {
+            if (jq < nq) {
+                const double *__restrict__ xq = xs + (int64_t)(q0 + jq) * dp;
+                double acc = 0.0;
+                if (D > 0) {
+#pragma unroll
+                    for (int u = 0; u < (D > 0 ? D : 1); ++u) {
+                        const double delta = __dsub_rn(xq[u], x[u]);
+                        acc = __fma_rn(delta, delta, acc);
                     }
-                    const bool in = valid && acc <= eps2;
-                    if (MODE == MODE_COUNT) {
-                        cnt[jq] += in ? 1 : 0;
-                    } else if (MODE == MODE_EMIT) {
-                        const unsigned long long m = __ballot(in);
-                        const int64_t pb = readlane_i64(my_pbase, jq);
-                        if (pb >= 0) {
-                            const int64_t pos = pb + __builtin_amdgcn_readlane(my_cur, jq) + __popcll(m & lt);
-                            if (in && pos < readlane_i64(my_pend, jq)) {
-                                R.pairs[2 * pos] = G.perm[q0 + jq];
-                                R.pairs[2 * pos + 1] = G.perm[c];
-                                if (R.d2) R.d2[pos] = acc;
+                } else {
+                    for (int u = 0; u < d; ++u) {
+                        const double delta = __dsub_rn(xq[u], xc[u]);
+                        acc = __fma_rn(delta, delta, acc);
+                    }
+                }
+                const bool in = valid && acc <= eps2;
+                if (MODE == MODE_COUNT) {
+                    cnt[jq] += in ? 1 : 0;
+                } else if (MODE == MODE_EMIT) {
+                    const unsigned long long m = __ballot(in);
+                    if ((emit_mask >> jq) & 1ull) {
+                        const int nm = __popcll(m);
+                        if (nm) {
+                            const int cur_j = __builtin_amdgcn_readlane(my_cur, jq);
+                            if (in) {
+                                const int e = (rb.tail + __popcll(m & lt)) & (kRing - 1);
+                                rb.cand[e] = (uint32_t)c;
+                                rb.rel[e] = (uint32_t)(cur_j + __popcll(m & lt));
+                                rb.col[e] = (uint32_t)jq;
                             }
-                            if (lane == jq) my_cur += __popcll(m);
+                            rb.tail += nm;
+                            if (lane == jq) my_cur += nm;
+                            ring_drain(rb, false, G, R, lane, my_pbase, my_pq, q0);
                         }
                     }
                 }
             }
         }
     }
+    if (MODE == MODE_EMIT) ring_drain(rb, true, G, R, lane, my_pbase, my_pq, q0);
     if (MODE == MODE_COUNT) {
 #pragma unroll
         for (int jq = 0; jq < kTileQ; ++jq) {
             int v = cnt[jq];
-            for (int s = 32; s > 0; s >>= 1) v += __shfl_xor(v, s);
+            for (int sh = 32; sh > 0; sh >>= 1) v += __shfl_xor(v, sh);
             if (lane == 0 && jq < nq) R.cnt[q0 + jq] = v;
         }
     }
 }
 
 // --------------------------------------------------------------------- M64 --
-// KS = K-steps of 4 dimensions (0 = runtime, read per step), SLOT = the
-// candidate norm occupies xa slot d (d % 4 != 0).
+// One v_mfma_f64_16x16x4f64 per K-step: rows = the item's 16 queries (the A
+// operand, loaded once per item), columns = 16 candidates (the B operand,
+// one row load per lane per K-step). Result layout (probed on gfx950):
+// register r of lane (g, j) = lane 16g + j holds row g + 4r, column j.
+//  SLOT (d % 4 != 0): the candidate norm rides in K slot d (A holds 1 there),
+//    D = |c|^2 - 2 q.c, and the query norm moves to a per-row threshold:
+//    in iff D <= eps^2 - |q|^2.
+//  no slot (d % 4 == 0): the accumulator starts at |q|^2 (constant per
+//    item), D = |q|^2 - 2 q.c, and the candidate norm moves to a per-column
+//    threshold: in iff D <= eps^2 - |c|^2.
+// KS = K-steps of 4 dimensions (0 = runtime).
+template <int KS>
+struct M64Tile {
+    double b[KS > 0 ? KS : 1];
+    double nc;  // candidate norm (no-slot form)
+};
+
+template <int KS, bool SLOT>
+__device__ __forceinline__ void m64_load(M64Tile<KS> &T, const DevGrid &G, int t, int j, int g) {
+    // rows up to t + 15 < n + 64 exist (padded)
+    const double *__restrict__ brow = G.xa + (int64_t)(t + j) * G.da + g;
+    if (KS > 0) {
+#pragma unroll
+        for (int s = 0; s < (KS > 0 ? KS : 1); ++s) T.b[s] = brow[4 * s];
+    }
+    if (!SLOT) T.nc = G.nrm[t + j];
+}
+
+template <int KS, bool SLOT>
+__device__ __forceinline__ double4_t m64_tile(const M64Tile<KS> &T, const DevGrid &G, const double *aq,
+                                              double4_t cinit, int t, int j, int g, int qa) {
+    double4_t acc = cinit;
+    if (KS > 0) {
+#pragma unroll
+        for (int s = 0; s < (KS > 0 ? KS : 1); ++s)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], T.b[s], acc, 0, 0, 0);
+    } else {
+        const int d = G.d, da = G.da, ks = da >> 2;
+        const double *__restrict__ brow = G.xa + (int64_t)(t + j) * da + g;
+        const double *__restrict__ arow = G.xa + (int64_t)qa * da;
+        for (int s = 0; s < ks; ++s) {
+            const int kk = 4 * s + g;
+            const double a = kk < d ? -2.0 * arow[kk] : ((SLOT && kk == d) ? 1.0 : 0.0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, brow[4 * s], acc, 0, 0, 0);
+        }
+    }
+    return acc;
+}
+
+// Per-lane classification state.
+struct M64Thr {
+    double lo[4], hi[4];  // SLOT: per row r
+    double ecol;          // no slot: eps^2 for the column threshold
+    double nq[4];         // |q|^2 of row r (for the error measurement)
+};
+
+// Returns the in-mask (bit r = row g + 4r) after the exact recheck of band
+// elements. Columns past the range end are masked here.
+template <bool SLOT, int MODE>
+__device__ __forceinline__ unsigned m64_classify(double4_t acc, double nc, int t, int ce, int g, int j, int q0,
+                                                 const M64Thr &th, double delta, const DevGrid &G,
+                                                 unsigned long long &band, unsigned long long &viol,
+                                                 double &maxerr) {
+    double v0 = acc[0], v1 = acc[1], v2 = acc[2], v3 = acc[3];
+    const bool colok = j < ce - t;
+    double l0, l1, l2, l3, h0, h1, h2, h3;
+    if (SLOT) {
+        l0 = th.lo[0]; l1 = th.lo[1]; l2 = th.lo[2]; l3 = th.lo[3];
+        h0 = th.hi[0]; h1 = th.hi[1]; h2 = th.hi[2]; h3 = th.hi[3];
+        if (!colok) v0 = v1 = v2 = v3 = INFINITY;
+    } else {
+        const double tc = th.ecol - nc;
+        const double lc = colok ? tc - delta : -INFINITY;
+        const double hc = colok ? tc + delta : -INFINITY;
+        l0 = l1 = l2 = l3 = lc;
+        h0 = h1 = h2 = h3 = hc;
+    }
+    const bool i0 = v0 <= l0, i1 = v1 <= l1, i2 = v2 <= l2, i3 = v3 <= l3;
+    const bool m0 = v0 <= h0, m1 = v1 <= h1, m2 = v2 <= h2, m3 = v3 <= h3;
+    unsigned inm = (unsigned)i0 | ((unsigned)i1 << 1) | ((unsigned)i2 << 2) | ((unsigned)i3 << 3);
+    if (MODE == MODE_MEASURE) {
+        const double vv[4] = {v0, v1, v2, v3};
+        const double hh[4] = {h0, h1, h2, h3};
+        for (int r = 0; r < 4; ++r) {
+            if (vv[r] < INFINITY && hh[r] > -INFINITY) {
+                const int q = q0 + g + 4 * r;
+                const double ex = exact_d2(G.xs + (int64_t)q * G.dp, G.xs + (int64_t)(t + j) * G.dp, G.d);
+                if (ex <= 4.0 * G.eps2) {
+                    const double err = fabs(vv[r] - (ex - (SLOT ? th.nq[r] : nc)));
+                    maxerr = fmax(maxerr, err);
+                    if (err > delta) ++viol;
+                }
+            }
+        }
+    }
+    const bool anyband = (m0 != i0) | (m1 != i1) | (m2 != i2) | (m3 != i3);
+    if (__builtin_expect(__any(anyband), 0)) {
+        // rare: exact FP64 chain on the original coordinates
+        const unsigned mbm = (unsigned)m0 | ((unsigned)m1 << 1) | ((unsigned)m2 << 2) | ((unsigned)m3 << 3);
+        const unsigned bm = mbm & ~inm;
+        for (int r = 0; r < 4; ++r) {
+            if (bm & (1u << r)) {
+                const int q = q0 + g + 4 * r;
+                const double ex = exact_d2(G.xs + (int64_t)q * G.dp, G.xs + (int64_t)(t + j) * G.dp, G.d);
+                if (ex <= G.eps2) inm |= 1u << r;
+                ++band;
+            }
+        }
+    }
+    return inm;
+}
+
 template <int KS, bool SLOT, int MODE>
 __global__ __launch_bounds__(kThreads) void k_m64(DevGrid G, RefOut R, double delta) {
+    __shared__ uint32_t ring_lds[MODE == MODE_EMIT ? kWaves * 3 * kRing : 1];
     const int lane = threadIdx.x & 63;
     const int wv = uniform_i32(threadIdx.x >> 6);
     const int it = uniform_i32(R.item_lo + xcd_block(blockIdx.x, gridDim.x) * kWaves + wv);
@@ -193,136 +425,156 @@ __global__ __launch_bounds__(kThreads) void k_m64(DevGrid G, RefOut R, double de
     const Item I = G.items[it];
     const int q0 = uniform_i32(I.qbegin);
     const int nq = uniform_i32(I.qend - I.qbegin);
-    const int d = G.d, da = G.da, dp = G.dp;
-    const int ks = KS > 0 ? KS : (da >> 2);
-    const int j = lane & 15;   // query column
+    const int d = G.d, da = G.da;
+    const int j = lane & 15;   // A row (query j) / result column (candidate t + j)
     const int g = lane >> 4;   // K index of the operands; row group of the result
-    const bool qvalid = j < nq;
-    const int qj = q0 + (qvalid ? j : 0);
+    const int qa = q0 + (j < nq ? j : 0);
     const double *__restrict__ xa = G.xa;
-    const double *__restrict__ xs = G.xs;
+    const ItemRanges rg = load_ranges(G, it, lane);
 
-    // B operand (K x 16): B[k][j] = -2 q_j[k] for k < d, 1 in the norm slot.
-    double bq[KS > 0 ? KS : 1];
+    // A operand (16 x K): A[i][k] = -2 q_i[k] for k < d, 1 in the norm slot.
+    double aq[KS > 0 ? KS : 1];
     if (KS > 0) {
 #pragma unroll
         for (int s = 0; s < (KS > 0 ? KS : 1); ++s) {
             const int kk = 4 * s + g;
-            bq[s] = kk < d ? -2.0 * xa[(int64_t)qj * da + kk] : ((SLOT && kk == d) ? 1.0 : 0.0);
+            aq[s] = (j < nq && kk < d) ? -2.0 * xa[(int64_t)qa * da + kk] : ((SLOT && kk == d) ? 1.0 : 0.0);
         }
     }
-    const double thr = G.eps2 - G.nrm[qj];
-    const double lo = thr - delta, hi = thr + delta;
-
-    int64_t pbase = -1, pend = 0;
-    if (MODE == MODE_EMIT && qvalid && qj >= R.qlo && qj < R.qhi) {
-        pbase = R.off[qj] - R.base;
-        pend = R.off[qj + 1] - R.base;
+    // rows of this lane: queries g + 4r
+    M64Thr th;
+    double4_t cinit = (double4_t){0.0, 0.0, 0.0, 0.0};
+    bool emit_r[4];
+    int64_t pbase_lane = -1;  // lanes < 16: output base of query `lane`
+    int32_t pq_lane = 0;      // lanes < 16: input index of query `lane`
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = g + 4 * r;
+        const bool ok = i < nq;
+        const double nq_r = ok ? G.nrm[q0 + i] : 0.0;
+        th.nq[r] = nq_r;
+        const double thr = G.eps2 - nq_r;
+        th.lo[r] = ok ? thr - delta : -INFINITY;
+        th.hi[r] = ok ? thr + delta : -INFINITY;
+        if (!SLOT) cinit[r] = ok ? nq_r : INFINITY;
+        emit_r[r] = MODE == MODE_EMIT && ok && q0 + i >= R.qlo && q0 + i < R.qhi;
     }
-    const int32_t pq = MODE == MODE_EMIT ? G.perm[qj] : 0;
-    int64_t cur = 0;
-    int cnt = 0;
+    th.ecol = G.eps2;
+    if (MODE == MODE_EMIT && lane < nq && q0 + lane >= R.qlo && q0 + lane < R.qhi) {
+        pbase_lane = R.off[q0 + lane] - R.base;
+        pq_lane = G.perm[q0 + lane];
+    }
+    EmitRing rb;
+    rb.cand = ring_lds + (MODE == MODE_EMIT ? wv * 3 * kRing : 0);
+    rb.rel = rb.cand + kRing;
+    rb.col = rb.rel + kRing;
+    rb.head = rb.tail = 0;
+    const unsigned long long lt = lanemask_lt();
+    const unsigned long long grp = 0xffffull << (16 * g);
+    int cur[4] = {0, 0, 0, 0};  // emitted so far for row g + 4r
+    int cnt[4] = {0, 0, 0, 0};
     unsigned long long band = 0, viol = 0;
     double maxerr = 0.0;
 
-    for (int o = 0; o < G.nranges; ++o) {
-        const int cb = uniform_i32(G.ranges[(int64_t)I.cell_first * G.nranges + o].begin);
-        const int ce = uniform_i32(G.ranges[(int64_t)I.cell_last * G.nranges + o].end);
-        for (int t = cb; t < ce; t += 16) {
-            double4_t acc;
-            if (SLOT) {
-                acc = (double4_t){0.0, 0.0, 0.0, 0.0};
-            } else {
-                const double *nr = G.nrm + t + g;
-                acc = (double4_t){nr[0], nr[4], nr[8], nr[12]};
-            }
-            const double *__restrict__ arow = xa + (int64_t)(t + j) * da + g;
-            if (KS > 0) {
+    auto emit = [&](unsigned inm, int t) {
+        unsigned long long bal[4];
+        int base_e = 0;
+        int pre[4];
 #pragma unroll
-                for (int s = 0; s < (KS > 0 ? KS : 1); ++s)
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[4 * s], bq[s], acc, 0, 0, 0);
-            } else {
-                for (int s = 0; s < ks; ++s) {
-                    const int kk = 4 * s + g;
-                    const double b = kk < d ? -2.0 * xa[(int64_t)qj * da + kk]
-                                            : ((SLOT && kk == d) ? 1.0 : 0.0);
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[4 * s], b, acc, 0, 0, 0);
-                }
-            }
-            // Result layout of v_mfma_f64_16x16x4f64: register r of lane
-            // (g, j) holds row g + 4r, column j. Element r is candidate
-            // t + g + 4r against query j.
-            const int rowlim = ce - t;
-            unsigned inm = 0, bandm = 0;
+        for (int r = 0; r < 4; ++r) {
+            bal[r] = __ballot(emit_r[r] && ((inm >> r) & 1u));
+            pre[r] = base_e + __popcll(bal[r] & lt);
+            base_e += __popcll(bal[r]);
+        }
+        if (base_e) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const bool valid = qvalid && (g + 4 * r) < rowlim;
-                const double v = acc[r];
-                if (valid && v <= lo) inm |= 1u << r;
-                else if (valid && v <= hi) bandm |= 1u << r;
-                if (MODE == MODE_MEASURE && valid) {
-                    const double ex = exact_d2(xs + (int64_t)qj * dp, xs + (int64_t)(t + g + 4 * r) * dp, d);
-                    if (ex <= 4.0 * G.eps2) {
-                        const double err = fabs(v - (ex - G.nrm[qj]));
-                        maxerr = fmax(maxerr, err);
-                        if (err > delta) ++viol;
-                    }
+                if (emit_r[r] && ((inm >> r) & 1u)) {
+                    const int e = (rb.tail + pre[r]) & (kRing - 1);
+                    rb.cand[e] = (uint32_t)(t + j);
+                    rb.rel[e] = (uint32_t)(cur[r] + __popcll(bal[r] & lt & grp));
+                    rb.col[e] = (uint32_t)(g + 4 * r);
                 }
             }
-            if (__any(bandm != 0)) {
-                // rare: exact FP64 chain on the original coordinates
+            rb.tail += base_e;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    if (bandm & (1u << r)) {
-                        const double ex = exact_d2(xs + (int64_t)qj * dp, xs + (int64_t)(t + g + 4 * r) * dp, d);
-                        if (ex <= G.eps2) inm |= 1u << r;
-                        ++band;
-                    }
-                }
-            }
-            cnt += __popc(inm);
-            if (MODE == MODE_EMIT) {
-                // candidate order per query: row i = g + 4r, so the rank of
-                // (g, r) counts every flagged row of lower level r, then the
-                // flagged rows of level r in lower lane groups.
-                const unsigned long long sel = 0x0001000100010001ull << j;
-                const unsigned long long below = (1ull << (16 * g)) - 1ull;
-                int rank_base = 0;
-                int rank[4];
+            for (int r = 0; r < 4; ++r) cur[r] += __popcll(bal[r] & grp);
+            ring_drain(rb, false, G, R, lane, pbase_lane, pq_lane, q0);
+        }
+    };
+    auto account = [&](unsigned inm) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const unsigned long long x = __ballot((inm >> r) & 1u) & sel;
-                    rank[r] = rank_base + __popcll(x & below);
-                    rank_base += __popcll(x);
-                }
-                if (pbase >= 0) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int64_t pos = pbase + cur + rank[r];
-                        if (((inm >> r) & 1u) && pos < pend) {
-                            const int cand = t + g + 4 * r;
-                            R.pairs[2 * pos] = pq;
-                            R.pairs[2 * pos + 1] = G.perm[cand];
-                            if (R.d2) R.d2[pos] = exact_d2(xs + (int64_t)qj * dp, xs + (int64_t)cand * dp, d);
-                        }
-                    }
-                }
-                cur += rank_base;
-            }
+        for (int r = 0; r < 4; ++r) cnt[r] += (inm >> r) & 1u;
+    };
+
+    TileCursor tc;
+    tc.first(rg);
+    M64Tile<KS> nA, nB;
+    bool hasB = false;
+    int tB = 0, ceB = 0;
+    int tA = tc.t, ceA = tc.ce;
+    if (tc.live(rg)) {
+        m64_load<KS, SLOT>(nA, G, tA, j, g);
+        tc.advance(rg, 16);
+        hasB = tc.live(rg);
+        if (hasB) {
+            tB = tc.t;
+            ceB = tc.ce;
+            m64_load<KS, SLOT>(nB, G, tB, j, g);
+            tc.advance(rg, 16);
         }
     }
-    if (MODE == MODE_COUNT) {
-        cnt += __shfl_xor(cnt, 16);
-        cnt += __shfl_xor(cnt, 32);
-        if (g == 0 && qvalid) R.cnt[qj] = cnt;
+    bool hasA = tA < ceA;
+    // two tiles in flight per iteration; the next pair is prefetched
+    while (hasA) {
+        const M64Tile<KS> A = nA, B = nB;
+        const int t0 = tA, c0 = ceA, t1 = tB, c1 = ceB;
+        const bool h1 = hasB;
+        hasA = tc.live(rg);
+        if (hasA) {
+            tA = tc.t;
+            ceA = tc.ce;
+            m64_load<KS, SLOT>(nA, G, tA, j, g);
+            tc.advance(rg, 16);
+        }
+        hasB = hasA && tc.live(rg);
+        if (hasB) {
+            tB = tc.t;
+            ceB = tc.ce;
+            m64_load<KS, SLOT>(nB, G, tB, j, g);
+            tc.advance(rg, 16);
+        }
+        const double4_t a0 = m64_tile<KS, SLOT>(A, G, aq, cinit, t0, j, g, qa);
+        double4_t a1;
+        if (h1) a1 = m64_tile<KS, SLOT>(B, G, aq, cinit, t1, j, g, qa);
+        const unsigned in0 = m64_classify<SLOT, MODE>(a0, A.nc, t0, c0, g, j, q0, th, delta, G, band, viol, maxerr);
+        if (MODE == MODE_EMIT) emit(in0, t0);
+        else account(in0);
+        if (h1) {
+            const unsigned in1 =
+                m64_classify<SLOT, MODE>(a1, B.nc, t1, c1, g, j, q0, th, delta, G, band, viol, maxerr);
+            if (MODE == MODE_EMIT) emit(in1, t1);
+            else account(in1);
+        }
     }
-    if (MODE != MODE_MEASURE) {
-        for (int s = 32; s > 0; s >>= 1) band += __shfl_xor(band, s);
+    if (MODE == MODE_EMIT) ring_drain(rb, true, G, R, lane, pbase_lane, pq_lane, q0);
+    if (MODE == MODE_COUNT) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int v = cnt[r];
+            v += __shfl_xor(v, 1);
+            v += __shfl_xor(v, 2);
+            v += __shfl_xor(v, 4);
+            v += __shfl_xor(v, 8);
+            if (j == 0 && g + 4 * r < nq) R.cnt[q0 + g + 4 * r] = v;
+        }
+        for (int sh = 32; sh > 0; sh >>= 1) band += __shfl_xor(band, sh);
         if (lane == 0 && band) atomicAdd(R.band, band);
-    } else {
-        for (int s = 32; s > 0; s >>= 1) {
-            viol += __shfl_xor(viol, s);
-            maxerr = fmax(maxerr, __shfl_xor(maxerr, s));
+    }
+    if (MODE == MODE_MEASURE) {
+        for (int sh = 32; sh > 0; sh >>= 1) {
+            viol += __shfl_xor(viol, sh);
+            maxerr = fmax(maxerr, __shfl_xor(maxerr, sh));
         }
         if (lane == 0) {
             atomicMax(&R.meas[0], (unsigned long long)__double_as_longlong(maxerr));
@@ -423,36 +675,29 @@ void launch_m64(const Grid &g, const RefOut &R, int nitems, double delta, hipStr
 
 }  // namespace
 
+// Enqueues the count kernel; the band counter lands in ro.band_dev (device,
+// zeroed here) and is read by the caller together with the total.
 void refine_count(Grid &g, sj_path path, int32_t *cnt_sorted, RefineOut &ro, hipStream_t s) {
-    unsigned long long *band = dev_alloc_n<unsigned long long>(1, s);
-    fill_zero(band, sizeof(unsigned long long), s);
+    fill_zero(ro.band_dev, sizeof(unsigned long long), s);
     RefOut R{};
     R.cnt = cnt_sorted;
-    R.band = band;
+    R.band = ro.band_dev;
     R.item_lo = 0;
     ro.cand_eval = g.cand_items;
-    KernelTimer kt;
     if (path == SJ_FP64_VALU) {
-        kt.start(ro.timed, s);
+        ro.kt.start(ro.timed, s);
         launch_v64<MODE_COUNT>(g, R, (int)g.items, s);
-        kt.stop(s);
+        ro.kt.stop(s);
         ro.band_rel = 0.0;
     } else if (path == SJ_FP64_MFMA) {
         const double delta = m64_delta(g);
-        kt.start(ro.timed, s);
+        ro.kt.start(ro.timed, s);
         launch_m64<MODE_COUNT>(g, R, (int)g.items, delta, s);
-        kt.stop(s);
+        ro.kt.stop(s);
         ro.band_rel = g.eps2 > 0 ? delta / g.eps2 : 0.0;
     } else {
-        dev_free(band, s);
         throw Unsupported{"path not supported by this build"};
     }
-    ro.ms_kernel = kt.ms();
-    unsigned long long hb = 0;
-    SJ_HIP(hipMemcpyAsync(&hb, band, sizeof hb, hipMemcpyDeviceToHost, s));
-    SJ_HIP(hipStreamSynchronize(s));
-    ro.band_pairs = (int64_t)hb;
-    dev_free(band, s);
 }
 
 namespace {
@@ -528,27 +773,22 @@ void refine_pairs(Grid &g, sj_path path, const ChunkPlan &p, int64_t qlo, int32_
     R.pairs = pairs;
     R.d2 = d2;
     R.item_lo = (int32_t)p.item_lo;
-    unsigned long long *band = dev_alloc_n<unsigned long long>(1, s);
-    fill_zero(band, sizeof(unsigned long long), s);
-    R.band = band;
+    fill_zero(ro.band_dev, sizeof(unsigned long long), s);
+    R.band = ro.band_dev;
     const int nitems = (int)(p.item_hi - p.item_lo);
-    KernelTimer kt;
     if (path == SJ_FP64_VALU) {
-        kt.start(ro.timed, s);
+        ro.kt.start(ro.timed, s);
         launch_v64<MODE_EMIT>(g, R, nitems, s);
-        kt.stop(s);
+        ro.kt.stop(s);
     } else if (path == SJ_FP64_MFMA) {
         const double delta = m64_delta(g);
-        kt.start(ro.timed, s);
+        ro.kt.start(ro.timed, s);
         launch_m64<MODE_EMIT>(g, R, nitems, delta, s);
-        kt.stop(s);
+        ro.kt.stop(s);
         ro.band_rel = g.eps2 > 0 ? delta / g.eps2 : 0.0;
     } else {
-        dev_free(band, s);
         throw Unsupported{"path not supported by this build"};
     }
-    dev_free(band, s);
-    ro.ms_kernel = kt.ms();
 }
 
 void refine_measure(Grid &g, sj_path path, double *max_err, double *max_band, int64_t *viol, hipStream_t s) {

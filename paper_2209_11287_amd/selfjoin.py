@@ -143,10 +143,14 @@ def selfjoin_measure_error(g: GridHandle, path, stream=None):
     return e.value, b.value, v.value
 
 
-def selfjoin_grid_info(g: GridHandle) -> dict:
+def selfjoin_grid_info(g: GridHandle, stream=None) -> dict:
+    """Grid facts; the first call computes C_ref (a pass over the cells)."""
+    torch = _torch()
     lib = _lib.load()
     info = _lib.sj_grid_info()
-    check(lib.selfjoin_grid_info(g.ptr, ctypes.byref(info)), "selfjoin_grid_info")
+    with torch.cuda.device(g.device):
+        st = lib.selfjoin_grid_info(g.ptr, ctypes.byref(info), _stream_ptr(stream))
+    check(st, "selfjoin_grid_info")
     return info.as_dict()
 
 

@@ -84,7 +84,7 @@ def test_calls_on_null_grid_rejected(lib):
     assert lib.selfjoin_measure_error(None, 1, ctypes.byref(e), ctypes.byref(e), ctypes.byref(w),
                                       None) == _lib.SJ_ERR_INVALID
     info = _lib.sj_grid_info()
-    assert lib.selfjoin_grid_info(None, ctypes.byref(info)) == _lib.SJ_ERR_INVALID
+    assert lib.selfjoin_grid_info(None, ctypes.byref(info), None) == _lib.SJ_ERR_INVALID
     lib.selfjoin_free_grid(None, None)  # accepted
 
 
