@@ -145,10 +145,13 @@ sj_status selfjoin_pairs(sj_grid *g, sj_path path, int64_t cursor, int32_t *pair
                          sj_stats *stats, void *stream);
 
 /* Debug measurement of a path's fast values against the exact chain: runs the
- * path over every evaluated candidate pair whose exact d2 is at most
- * 4 * eps^2 and reports the largest |fast - exact| (max_abs_err), the
- * largest band half-width used (max_band), and how many pairs had an error
- * larger than their band (violations; must be 0). Slow; not for timing. */
+ * path over every evaluated candidate pair whose exact d2 is within the
+ * range its band bound covers (d2 <= 4 eps^2 for FP64 MFMA, whose bound is
+ * global; d2 <= eps^2 for FP32/BF16, whose bound is per query and covers the
+ * candidates that can be within eps) and reports the largest
+ * |fast - exact| (max_abs_err), the largest band half-width used (max_band),
+ * and how many pairs had an error larger than their band (violations; must
+ * be 0). Slow; not for timing. */
 sj_status selfjoin_measure_error(sj_grid *g, sj_path path, double *max_abs_err, double *max_band,
                                  int64_t *violations, void *stream);
 

@@ -127,19 +127,28 @@ const char *last_error() { return g_err.c_str(); }
 static void compute_counts(Grid &g, sj_path path, RefineOut &ro, hipStream_t s) {
     if (!g.cnt) {
         g.cnt = dev_alloc_n<int32_t>((size_t)g.n + 1, s);
-        g.off = dev_alloc_n<int64_t>((size_t)g.n + 2, s);  // [n + 1]: band counter
+        g.off = dev_alloc_n<int64_t>((size_t)g.n + 1, s);
+        g.aux = dev_alloc_n<unsigned long long>(4, s);
     }
-    ro.band_dev = reinterpret_cast<unsigned long long *>(g.off + g.n + 1);
+    ro.band_dev = g.aux;
+    ro.aux_dev = g.aux + 1;
+    fill_zero(g.aux, 4 * sizeof(unsigned long long), s);
     hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, g.cnt + g.n, 0);
     SJ_HIP(hipGetLastError());
     if (g.n > 0) refine_count(g, path, g.cnt, ro, s);
-    else fill_zero(ro.band_dev, sizeof(unsigned long long), s);
     exclusive_scan_i32_to_i64(g.cnt, g.off, g.n + 1, s);
-    int64_t h[2] = {0, 0};  // total, band pairs (one read, one sync)
-    SJ_HIP(hipMemcpyAsync(h, g.off + g.n, sizeof h, hipMemcpyDeviceToHost, s));
+    int64_t total = 0;  // total and the band counters: one sync
+    unsigned long long aux[4] = {0, 0, 0, 0};
+    SJ_HIP(hipMemcpyAsync(&total, g.off + g.n, sizeof total, hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipMemcpyAsync(aux, g.aux, sizeof aux, hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
-    g.total = h[0];
-    ro.band_pairs = h[1];
+    g.total = total;
+    ro.band_pairs = (int64_t)aux[0];
+    if (path == SJ_FP32_MFMA || path == SJ_BF16_MFMA) {
+        double dl;
+        std::memcpy(&dl, &aux[3], sizeof dl);
+        ro.band_rel = g.eps2 > 0 ? dl / g.eps2 : 0.0;
+    }
     g.have_counts = true;
 }
 
@@ -288,6 +297,8 @@ sj_status selfjoin_pairs(sj_grid *gh, sj_path path, int64_t cursor, int32_t *pai
         p.next = g.n;
         p.item_lo = 0;
         p.item_hi = g.items;
+        p.block_lo = 0;
+        p.block_hi = g.nblocks;
         p.base = 0;
     } else {
         p = plan_chunk(g, cursor, capacity, s);
@@ -303,7 +314,8 @@ sj_status selfjoin_pairs(sj_grid *gh, sj_path path, int64_t cursor, int32_t *pai
     }
     RefineOut re;
     re.timed = stats != nullptr;
-    re.band_dev = dev_alloc_n<unsigned long long>(1, s);
+    re.band_dev = dev_alloc_n<unsigned long long>(4, s);
+    re.aux_dev = re.band_dev + 1;
     refine_pairs(g, path, p, cursor, pairs, d2, re, s);
     dev_free(re.band_dev, s);
     *written = p.written;

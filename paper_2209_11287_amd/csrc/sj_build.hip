@@ -423,7 +423,8 @@ __device__ __forceinline__ int32_t last_le(const int32_t *v, int32_t a, int32_t 
 
 __global__ void k_items(const int32_t *__restrict__ line_first, const int32_t *__restrict__ item_off,
                         const int32_t *__restrict__ cell_start, const int32_t *__restrict__ nlines_p,
-                        const int32_t *__restrict__ nitems_p, Item *__restrict__ items) {
+                        const int32_t *__restrict__ nitems_p, Item *__restrict__ items,
+                        int32_t *__restrict__ bflag) {
     const int32_t L = *nlines_p;
     const int32_t I = *nitems_p;
     int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -440,6 +441,23 @@ __global__ void k_items(const int32_t *__restrict__ line_first, const int32_t *_
     r.cell_first = last_le(cell_start, c0, c1, qb);
     r.cell_last = last_le(cell_start, c0, c1, qe - 1);
     items[it] = r;
+    // groups of kBlockItems consecutive items of one line form a block item
+    bflag[it] = (((int32_t)it - item_off[l]) % kBlockItems) == 0 ? 1 : 0;
+}
+
+// Block items: first item of each group, and the end sentinel.
+__global__ void k_blocks(const int32_t *__restrict__ bflag, const int32_t *__restrict__ bid,
+                         const int32_t *__restrict__ nitems_p, int32_t *__restrict__ blocks,
+                         int32_t *__restrict__ nblocks_p) {
+    const int32_t I = *nitems_p;
+    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= I) return;
+    if (bflag[it]) blocks[bid[it]] = (int32_t)it;
+    if (it == I - 1) {
+        const int32_t nb = bid[it] + bflag[it];
+        blocks[nb] = I;
+        *nblocks_p = nb;
+    }
 }
 
 // ------------------------------------------------------- neighbour ranges ----
@@ -615,8 +633,8 @@ void exclusive_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipSt
 }
 
 void free_grid(Grid &g, hipStream_t s) {
-    void *bufs[] = {g.xs,   g.xa,       g.nrm,      g.perm, g.cell_key, g.cell_start, g.ranges,
-                    g.item, g.dev_nmax, g.line_first, g.line_table, g.cnt, g.off};
+    void *bufs[] = {g.xs,   g.xa,       g.nrm,        g.perm,       g.cell_key, g.cell_start, g.ranges,
+                    g.item, g.dev_nmax, g.line_first, g.line_table, g.blocks,   g.cnt,        g.off, g.aux};
     for (void *p : bufs)
         if (p) dev_free(p, s);
     g.xs = g.xa = g.nrm = nullptr;
@@ -628,8 +646,10 @@ void free_grid(Grid &g, hipStream_t s) {
     g.dev_nmax = nullptr;
     g.line_first = nullptr;
     g.line_table = nullptr;
+    g.blocks = nullptr;
     g.cnt = nullptr;
     g.off = nullptr;
+    g.aux = nullptr;
 }
 
 // Host-side reading of the grid geometry; identical arithmetic to the
@@ -768,8 +788,9 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     }
 
     // ---- G4: cell table, lines, work items ----
-    int32_t *flag = dev_alloc_n<int32_t>(n, s);
-    int32_t *cid = dev_alloc_n<int32_t>(n, s);
+    // flags / scan scratch, reused for cells (n), lines (<= n) and items (<= n + n/16 + 1)
+    int32_t *flag = dev_alloc_n<int32_t>(n + n / kTileQ + 2, s);
+    int32_t *cid = dev_alloc_n<int32_t>(n + n / kTileQ + 2, s);
     int32_t *counters = dev_alloc_n<int32_t>(4, s);  // ncells, nlines, nitems
     fill_zero(counters, 4 * sizeof(int32_t), s);
     g.cell_key = dev_alloc_n<int64_t>(n + 1, s);
@@ -802,6 +823,7 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     fill_zero(acc, sizeof(unsigned long long), s);
     const int64_t items_ub = n + n / kTileQ + 1;  // lines <= cells <= n
     g.item = dev_alloc_n<Item>((size_t)items_ub, s);
+    g.blocks = dev_alloc_n<int32_t>((size_t)items_ub + 1, s);
     g.ranges = dev_alloc_n<Range>((size_t)items_ub * g.nranges, s);
     g.line_first = line_first;
     line_first = nullptr;  // kept by the grid (lazy C_ref)
@@ -820,7 +842,12 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
             SJ_HIP(hipGetLastError());
         }
         hipLaunchKernelGGL(k_items, dim3(blocks_for(items_ub)), dim3(kThreads), 0, s, g.line_first, item_off,
-                           g.cell_start, counters + 1, counters + 2, g.item);
+                           g.cell_start, counters + 1, counters + 2, g.item, flag);
+        SJ_HIP(hipGetLastError());
+        // block items (groups of up to kBlockItems items of one line)
+        exclusive_scan<int32_t, int32_t>(flag, cid, items_ub, s);
+        hipLaunchKernelGGL(k_blocks, dim3(blocks_for(items_ub)), dim3(kThreads), 0, s, flag, cid, counters + 2,
+                           g.blocks, counters + 3);
         SJ_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_item_ranges, dim3(2048), dim3(kThreads), 0, s, g.item, counters + 2, g.cell_key,
                            g.cell_start, counters + 0, range_geom(g), g.line_table, g.line_first, g.ranges, acc);
@@ -838,6 +865,7 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     }
     g.cells = hc[0];
     g.items = hc[2];
+    g.nblocks = hc[3];
     g.nmax = hn;
     g.cand_ref = -1;  // computed on request (grid_cref)
     g.cand_items = (int64_t)hacc;

@@ -15,6 +15,8 @@ constexpr int kMaxIndexDims = 4;   // default k = min(d, kMaxIndexDims)
 constexpr int kMaxDims = 256;
 constexpr int kTileQ = 16;         // queries per work item (one wave)
 constexpr int kRowPad = 64;        // extra zeroed rows after every point array
+constexpr int kBlockItems = 4;     // work items per block item (low-precision paths)
+constexpr int kLpMaxD = 64;        // largest d of the low-precision paths
 
 // Thread-local error text.
 void set_error(const std::string &msg);
@@ -78,6 +80,7 @@ struct Grid {
     int32_t key_bits = 0;
     int64_t cells = 0;
     int64_t items = 0;
+    int64_t nblocks = 0;
     int64_t cand_ref = -1;   // C_ref (lazily computed; -1 = not yet)
     int64_t cand_items = 0;  // candidate pairs the work items evaluate
     double nmax = 0;       // max squared norm of the centred rows of xa
@@ -93,11 +96,13 @@ struct Grid {
     Item *item = nullptr;        // items
     int32_t *line_first = nullptr;  // first cell of each grid line (+ end marker)
     int32_t *line_table = nullptr;  // dense line key -> line id (or null when too large)
+    int32_t *blocks = nullptr;      // first item of each block item (+ end sentinel)
     double *dev_nmax = nullptr;  // device copy of nmax
 
     // cached per-query counts (sorted order) and their exclusive prefix sums
     int32_t *cnt = nullptr;
     int64_t *off = nullptr;      // n + 1 entries
+    unsigned long long *aux = nullptr;  // 4 counters read with the total
     bool have_counts = false;
     int64_t total = 0;
 
@@ -154,6 +159,7 @@ struct RefineOut {
     bool timed = false;      // record events around the tile kernel
     KernelTimer kt;          // those events
     unsigned long long *band_dev = nullptr;  // device counter of rechecked pairs
+    unsigned long long *aux_dev = nullptr;   // device: [2] largest band half-width (bits)
     int64_t band_pairs = 0;
     double band_rel = 0;
     int64_t cand_eval = 0;
@@ -165,6 +171,7 @@ struct ChunkPlan {
     int64_t written = 0;     // pairs of the chunk (or the capacity needed)
     int64_t next = 0;        // cursor after the chunk
     int64_t item_lo = 0, item_hi = 0;  // work items covering the chunk
+    int64_t block_lo = 0, block_hi = 0;  // block items covering the chunk
     int64_t base = 0;        // prefix count at the cursor
 };
 void refine_count(Grid &g, sj_path path, int32_t *cnt_sorted, RefineOut &ro, hipStream_t s);
@@ -173,6 +180,12 @@ void refine_pairs(Grid &g, sj_path path, const ChunkPlan &p, int64_t qlo, int32_
                   RefineOut &ro, hipStream_t s);
 void refine_measure(Grid &g, sj_path path, double *max_err, double *max_band, int64_t *viol,
                     hipStream_t s);
+
+// Low-precision paths (sj_lowp.hip).
+void lowp_count(Grid &g, sj_path path, int32_t *cnt_sorted, RefineOut &ro, hipStream_t s);
+void lowp_pairs(Grid &g, sj_path path, const ChunkPlan &p, int64_t qlo, int32_t *pairs, double *d2,
+                RefineOut &ro, hipStream_t s);
+void lowp_measure(Grid &g, sj_path path, double *max_err, double *max_band, int64_t *viol, hipStream_t s);
 
 }  // namespace sj
 

@@ -1,0 +1,559 @@
+// Low-precision MFMA paths (FP32 and BF16 inputs, FP32 accumulation) with an
+// exact FP64 recheck. The paper computes its tiles in FP64 and names other
+// tensor-core precisions as future work (Section V); this is that form.
+//
+// Work unit: a block item = up to 4 consecutive 16-query work items of one
+// grid line (64 queries, one per wave row tile) sharing the union of their
+// candidate ranges. Candidates are staged 64 at a time into LDS:
+//  - the FP64 rows (kept for the exact recheck),
+//  - the rows centred on the block's reference point r (its first query)
+//    and rounded to FP32 or BF16 (round to nearest even) -- the MFMA B
+//    operand,
+//  - the FP64 squared norms of the rounded rows.
+// Each wave's A operand holds its 16 queries, centred and rounded the same
+// way, times -2 (exact). The accumulator starts at the candidate norm, so a
+// tile yields D = |c'|^2 - 2 q'.c' (Eq. (3) with |q'|^2 moved to the
+// threshold side): in iff D <= eps^2 - |q'|^2.
+//
+// Proven band, per query row. Let a = |q'|, eta the input rounding unit
+// (subtraction in FP64, then rounding to the tile precision), u_a the FP32
+// accumulation unit taken twice for safety, eps+ = eps (1 + (d + 4) u64),
+// e = eta (2a + eps+) / (1 - 2 eta) and tau = eps+ + e. Only candidates with
+// |c'| <= b = a + tau can be within eps+ of the query; for them the Gram value
+// differs from the exact d2 - |q'|^2 by at most
+//   F = (u32 + g_d + g_{K+1}) b^2 + 2 g_{K+1} a b + g_d a^2 + u32 (eps^2 + a^2)
+// (C-init rounding, FP64 norms, accumulation; g_m = gamma_m) plus the
+// conversion and oracle terms 2 tau e + e^2 + gamma_{d+2} tau^2; Delta is
+// twice their sum. For |c'| > b the value minus its own error still
+// increases with |c'| and exceeds eps^2 - Delta, so such candidates are
+// never taken for in, and their exact distance exceeds eps+. Values with
+// D <= thr - Delta are in, D > thr + Delta out, the rest are re-evaluated
+// with the exact FP64 chain on the original coordinates: the result is the
+// exact set.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "sj_internal.h"
+
+namespace sj {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kTC = 64;            // candidates per staged tile
+constexpr int kRing = 512;
+
+typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef short short8_t __attribute__((ext_vector_type(8)));
+
+enum { MODE_COUNT = 0, MODE_EMIT = 1, MODE_MEASURE = 2 };
+enum { PREC_F32 = 0, PREC_BF16 = 1 };
+
+struct LpGrid {
+    const double *xs;
+    const double *nrm;
+    const int32_t *perm;
+    const Range *ranges;
+    const Item *items;
+    const int32_t *blocks;
+    int32_t nblocks;
+    int32_t d, dp, nranges;
+    double eps, eps2;
+};
+
+struct LpOut {
+    int32_t *cnt;
+    const int64_t *off;
+    int64_t base;
+    int32_t qlo, qhi;
+    int32_t *pairs;
+    double *d2;
+    unsigned long long *band;      // [0] rechecked pairs
+    unsigned long long *meas;      // [0] max err bits, [1] violations, [2] max delta bits
+    int32_t block_lo;              // first block item of this launch
+};
+
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
+__device__ __forceinline__ unsigned long long lanemask_lt() {
+    const unsigned lane = threadIdx.x & 63u;
+    return lane ? ((~0ull) >> (64u - lane)) : 0ull;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The oracle's chain (ascending dimensions from +0.0, fl(a - b) then fma);
+// b may live in LDS.
+__device__ __forceinline__ double exact_d2(const double *a, const double *b, int d) {
+    double acc = 0.0;
+    for (int t = 0; t < d; ++t) {
+        const double delta = __dsub_rn(a[t], b[t]);
+        acc = __fma_rn(delta, delta, acc);
+    }
+    return acc;
+}
+
+// FP32 -> BF16, round to nearest even (finite inputs).
+__device__ __forceinline__ unsigned short f32_to_bf16(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
+
+// Rounds an FP64 value to the tile precision; returns the rounded value as
+// a double (exact) and its storage bits.
+template <int PREC>
+__device__ __forceinline__ double round_in(double y, unsigned &bits) {
+    const float f = (float)y;  // RNE
+    if (PREC == PREC_F32) {
+        bits = __float_as_uint(f);
+        return (double)f;
+    }
+    const unsigned short h = f32_to_bf16(f);
+    bits = h;
+    return (double)bf16_to_f32(h);
+}
+
+__device__ __forceinline__ double gam(double m, double u) { return m * u / (1.0 - m * u); }
+
+// Band half-width of one query row (see the file comment): a2 = |q'|^2.
+template <int PREC>
+__device__ __forceinline__ double lp_delta(double a2, double eps, double eps2, int d, int K) {
+    const double u64 = 0x1p-53, u32 = 0x1p-24;
+    const double uin = PREC == PREC_F32 ? 0x1p-24 : (0x1p-8 + 0x1p-24);  // BF16 via FP32: two roundings
+    const double eta = uin + u64 + uin * u64;
+    const double ua = 2.0 * 0x1p-24;
+    const double a = sqrt(a2 * (1.0 + 1e-12));
+    const double epsp = eps * (1.0 + (d + 4) * u64);
+    const double e = eta * (2.0 * a + epsp) / (1.0 - 2.0 * eta);  // conversion error at |c'| = a + tau
+    const double tau = epsp + e;
+    const double b = a + tau;  // candidates beyond cannot be near the threshold
+    const double A2 = a * a, B2 = b * b;
+    const double F = (u32 + gam(d, u64) + gam(K + 1, ua)) * B2 + 2.0 * gam(K + 1, ua) * a * b  // accumulation
+                     + gam(d, u64) * A2 + u32 * (eps2 + A2);                                    // threshold
+    return 2.0 * (F + 2.0 * tau * e + e * e + gam(d + 2, u64) * tau * tau) + (d + 2) * 0x1p-1021;
+}
+
+template <int PREC>
+struct Prec;
+template <>
+struct Prec<PREC_F32> {
+    static constexpr int kstep = 4;
+    typedef float operand_t;
+};
+template <>
+struct Prec<PREC_BF16> {
+    static constexpr int kstep = 32;
+    typedef short8_t operand_t;
+};
+
+// K padded to the instruction's K-step; LDS row strides padded against bank
+// conflicts.
+template <int PREC>
+constexpr int lp_kmax() {
+    return PREC == PREC_F32 ? kLpMaxD : ((kLpMaxD + 31) / 32) * 32;
+}
+template <int PREC>
+constexpr int lp_stride() {  // in 32-bit words
+    return PREC == PREC_F32 ? lp_kmax<PREC>() + 1 : lp_kmax<PREC>() / 2 + 4;
+}
+
+template <int PREC>
+__device__ __forceinline__ float4_t lp_mfma(typename Prec<PREC>::operand_t a, typename Prec<PREC>::operand_t b,
+                                            float4_t c);
+template <>
+__device__ __forceinline__ float4_t lp_mfma<PREC_F32>(float a, float b, float4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ float4_t lp_mfma<PREC_BF16>(short8_t a, short8_t b, float4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+template <int PREC, int MODE>
+__global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
+    constexpr int KMAX = lp_kmax<PREC>();
+    constexpr int STR = lp_stride<PREC>();
+    constexpr int KSTEP = Prec<PREC>::kstep;
+    __shared__ double xr[kLpMaxD];                   // reference row
+    __shared__ double f64t[kTC][kLpMaxD + 1];        // FP64 candidate rows
+    __shared__ uint32_t lpt[kTC * STR];              // rounded, centred rows
+    __shared__ float nc32[kTC];                      // their norms (FP32, accumulator init)
+    __shared__ uint32_t ring_lds[MODE == MODE_EMIT ? kWaves * 3 * kRing : 1];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
+    const int bi = R.block_lo + xcd_block(blockIdx.x, gridDim.x);
+    if (bi >= G.nblocks) return;  // whole block
+    const int ib = G.blocks[bi], ie = G.blocks[bi + 1];
+    const int d = G.d, dp = G.dp;
+    const int K = ((d + KSTEP - 1) / KSTEP) * KSTEP;
+    const int ks = K / KSTEP;
+
+    // reference point: the block's first query
+    const int qref = G.items[ib].qbegin;
+    if (tid < d) xr[tid] = G.xs[(int64_t)qref * dp + tid];
+    __syncthreads();
+
+    // this wave's queries
+    const bool has_q = ib + wv < ie;
+    int q0 = 0, nq = 0;
+    if (has_q) {
+        const Item I = G.items[ib + wv];
+        q0 = I.qbegin;
+        nq = I.qend - I.qbegin;
+    }
+    q0 = uniform_i32(q0);
+    nq = uniform_i32(nq);
+    const int j = lane & 15;
+    const int g = lane >> 4;
+    // A operand: -2 * round(q_j - r) over K (zeros past d or for absent rows)
+    typename Prec<PREC>::operand_t aq[(KMAX + KSTEP - 1) / KSTEP];
+    double nq_part = 0.0;
+    {
+        const double *qrow = G.xs + (int64_t)(q0 + (j < nq ? j : 0)) * dp;
+#pragma unroll
+        for (int s = 0; s < (KMAX + KSTEP - 1) / KSTEP; ++s) {
+            if constexpr (PREC == PREC_F32) {
+                const int k = KSTEP * s + g;
+                float v = 0.f;
+                if (s < ks && j < nq && k < d) {
+                    unsigned bits;
+                    const double y = round_in<PREC>(__dsub_rn(qrow[k], xr[k]), bits);
+                    nq_part = __fma_rn(y, y, nq_part);
+                    v = -2.0f * __uint_as_float(bits);
+                }
+                aq[s] = v;
+            } else {
+                short8_t v;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int k = KSTEP * s + 8 * g + e;
+                    unsigned short h = 0;
+                    if (s < ks && j < nq && k < d) {
+                        unsigned bits;
+                        const double y = round_in<PREC>(__dsub_rn(qrow[k], xr[k]), bits);
+                        nq_part = __fma_rn(y, y, nq_part);
+                        h = f32_to_bf16(-2.0f * bf16_to_f32((unsigned short)bits));  // exact
+                    }
+                    v[e] = (short)h;
+                }
+                aq[s] = v;
+            }
+        }
+    }
+    // |q'|^2 of query j: sum of the four K slices (lanes j, j+16, j+32, j+48)
+    double nqj = nq_part;
+    nqj += __shfl_xor(nqj, 16);
+    nqj += __shfl_xor(nqj, 32);
+    // rows of this lane in the result: 4g + r (16x16 FP32 / BF16 layouts)
+    float lo[4], hi[4];
+    double nqr[4], dlt[4];
+    double maxdelta = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = 4 * g + r;
+        const double v = __shfl(nqj, i);
+        nqr[r] = v;
+        dlt[r] = lp_delta<PREC>(v, G.eps, G.eps2, d, K);
+        const double thr = G.eps2 - v;
+        lo[r] = i < nq ? (float)(thr - dlt[r]) : -INFINITY;
+        hi[r] = i < nq ? (float)(thr + dlt[r]) : -INFINITY;
+        if (i < nq) maxdelta = fmax(maxdelta, dlt[r]);
+    }
+    // emission state
+    bool emit_r[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = 4 * g + r;
+        emit_r[r] = MODE == MODE_EMIT && i < nq && q0 + i >= R.qlo && q0 + i < R.qhi;
+    }
+    int64_t pbase_lane = -1;
+    int32_t pq_lane = 0;
+    if (MODE == MODE_EMIT && lane < nq && q0 + lane >= R.qlo && q0 + lane < R.qhi) {
+        pbase_lane = R.off[q0 + lane] - R.base;
+        pq_lane = G.perm[q0 + lane];
+    }
+    uint32_t *rcand = ring_lds + (MODE == MODE_EMIT ? wv * 3 * kRing : 0);
+    uint32_t *rrel = rcand + kRing;
+    uint32_t *rcol = rrel + kRing;
+    int head = 0, tail = 0;
+    const unsigned long long lt = lanemask_lt();
+    const unsigned long long grp = 0xffffull << (16 * g);
+    int cur[4] = {0, 0, 0, 0};
+    int cnt[4] = {0, 0, 0, 0};
+    unsigned long long band = 0, viol = 0;
+    double maxerr = 0.0;
+
+    auto flush = [&](int nflush) {
+        wave_lds_sync();
+        const int e = (head + lane) & (kRing - 1);
+        const uint32_t c = rcand[e], rel = rrel[e], col = rcol[e];
+        const int64_t pb = __shfl(pbase_lane, (int)col);
+        const int32_t pq = __shfl(pq_lane, (int)col);
+        if (lane < nflush) {
+            const int64_t pos = pb + rel;
+            reinterpret_cast<int2 *>(R.pairs)[pos] = make_int2(pq, G.perm[c]);
+            if (R.d2) R.d2[pos] = exact_d2(G.xs + (int64_t)(q0 + (int)col) * dp, G.xs + (int64_t)c * dp, d);
+        }
+        head += nflush;
+        wave_lds_sync();
+    };
+
+    // union of the ranges of the block's items (same line: contiguous)
+    int rb = 0, re = 0;
+    if (lane < G.nranges) {
+        rb = G.ranges[(int64_t)ib * G.nranges + lane].begin;
+        re = G.ranges[(int64_t)(ie - 1) * G.nranges + lane].end;
+    }
+    for (int o = 0; o < G.nranges; ++o) {
+        const int cb = __builtin_amdgcn_readlane(rb, o);
+        const int ce = __builtin_amdgcn_readlane(re, o);
+        for (int t = cb; t < ce; t += kTC) {
+            const int nvalid = min(kTC, ce - t);
+            __syncthreads();  // previous tile consumed
+            // ---- stage: 4 threads per row, K/4 columns each ----
+            {
+                const int row = tid >> 2, part = tid & 3;
+                const bool rowok = row < nvalid;
+                const double *src = G.xs + (int64_t)(t + row) * dp;  // rows < n + 64 exist
+                double np = 0.0;
+                const int cpt = KMAX / 4;  // columns per thread (upper bound)
+                for (int cc = 0; cc < cpt; ++cc) {
+                    const int k = part * cpt + cc;
+                    if (k >= K) break;
+                    const double x = (rowok && k < d) ? src[k] : 0.0;
+                    if (k < d) f64t[row][k] = x;
+                    unsigned bits = 0;
+                    double y = 0.0;
+                    if (rowok && k < d) y = round_in<PREC>(__dsub_rn(x, xr[k]), bits);
+                    np = __fma_rn(y, y, np);
+                    if constexpr (PREC == PREC_F32) {
+                        lpt[row * STR + k] = bits;
+                    } else {
+                        unsigned short *h = reinterpret_cast<unsigned short *>(lpt + row * STR);
+                        h[k] = (unsigned short)bits;
+                    }
+                }
+                np += __shfl_xor(np, 1);
+                np += __shfl_xor(np, 2);
+                if (part == 0) nc32[row] = rowok ? (float)np : INFINITY;
+            }
+            __syncthreads();
+            if (!has_q) continue;
+            for (int sub = 0; sub < kTC / 16; ++sub) {
+                if (16 * sub >= nvalid) break;
+                const int crow = 16 * sub + j;  // candidate column j of this sub-tile
+                const float nc = nc32[crow];
+                float4_t acc = (float4_t){nc, nc, nc, nc};
+                for (int s = 0; s < ks; ++s) {
+                    typename Prec<PREC>::operand_t b;
+                    if constexpr (PREC == PREC_F32) {
+                        b = __uint_as_float(lpt[crow * STR + KSTEP * s + g]);
+                    } else {
+                        const uint32_t *w = lpt + crow * STR + (KSTEP * s + 8 * g) / 2;
+                        short8_t v;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const uint32_t x = w[e];
+                            v[2 * e] = (short)(x & 0xffffu);
+                            v[2 * e + 1] = (short)(x >> 16);
+                        }
+                        b = v;
+                    }
+                    acc = lp_mfma<PREC>(aq[s], b, acc);
+                }
+                // element r: query 4g + r, candidate t + crow
+                unsigned inm = 0, mbm = 0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    inm |= (acc[r] <= lo[r] ? 1u : 0u) << r;
+                    mbm |= (acc[r] <= hi[r] ? 1u : 0u) << r;
+                }
+                if (MODE == MODE_MEASURE) {
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = 4 * g + r;
+                        if (i < nq && crow < nvalid) {
+                            const double ex = exact_d2(G.xs + (int64_t)(q0 + i) * dp, &f64t[crow][0], d);
+                            if (ex <= G.eps2) {  // the per-row bound covers pairs within eps
+                                const double err = fabs((double)acc[r] - (ex - nqr[r]));
+                                maxerr = fmax(maxerr, err);
+                                if (err > dlt[r]) ++viol;
+                            }
+                        }
+                    }
+                }
+                const unsigned bm = mbm & ~inm;
+                if (__any(bm != 0)) {
+                    for (int r = 0; r < 4; ++r) {
+                        if (bm & (1u << r)) {
+                            const int i = 4 * g + r;
+                            const double ex = exact_d2(G.xs + (int64_t)(q0 + i) * dp, &f64t[crow][0], d);
+                            if (ex <= G.eps2) inm |= 1u << r;
+                            ++band;
+                        }
+                    }
+                }
+                if (MODE == MODE_EMIT) {
+                    unsigned long long bal[4];
+                    int base_e = 0;
+                    int pre[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        bal[r] = __ballot(emit_r[r] && ((inm >> r) & 1u));
+                        pre[r] = base_e + __popcll(bal[r] & lt);
+                        base_e += __popcll(bal[r]);
+                    }
+                    if (base_e) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            if (emit_r[r] && ((inm >> r) & 1u)) {
+                                const int e = (tail + pre[r]) & (kRing - 1);
+                                rcand[e] = (uint32_t)(t + crow);
+                                rrel[e] = (uint32_t)(cur[r] + __popcll(bal[r] & lt & grp));
+                                rcol[e] = (uint32_t)(4 * g + r);
+                            }
+                        }
+                        tail += base_e;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) cur[r] += __popcll(bal[r] & grp);
+                        while (tail - head >= 64) flush(64);
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) cnt[r] += (inm >> r) & 1u;
+                }
+            }
+        }
+    }
+    if (MODE == MODE_EMIT && has_q && tail > head) flush(tail - head);
+    if (MODE == MODE_COUNT && has_q) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int v = cnt[r];
+            v += __shfl_xor(v, 1);
+            v += __shfl_xor(v, 2);
+            v += __shfl_xor(v, 4);
+            v += __shfl_xor(v, 8);
+            if (j == 0 && 4 * g + r < nq) R.cnt[q0 + 4 * g + r] = v;
+        }
+    }
+    if (MODE != MODE_EMIT) {
+        for (int sh = 32; sh > 0; sh >>= 1) {
+            band += __shfl_xor(band, sh);
+            viol += __shfl_xor(viol, sh);
+            maxerr = fmax(maxerr, __shfl_xor(maxerr, sh));
+        }
+        if (lane == 0) {
+            if (band) atomicAdd(R.band, band);
+            if (MODE == MODE_MEASURE) {
+                atomicMax(&R.meas[0], (unsigned long long)__double_as_longlong(maxerr));
+                if (viol) atomicAdd(&R.meas[1], viol);
+            }
+            atomicMax(&R.meas[2], (unsigned long long)__double_as_longlong(maxdelta));
+        }
+    }
+}
+
+LpGrid lp_grid(const Grid &g) {
+    LpGrid G;
+    G.xs = g.xs;
+    G.nrm = g.nrm;
+    G.perm = g.perm;
+    G.ranges = g.ranges;
+    G.items = g.item;
+    G.blocks = g.blocks;
+    G.nblocks = (int32_t)g.nblocks;
+    G.d = g.d;
+    G.dp = g.dp;
+    G.nranges = g.nranges;
+    G.eps = g.eps;
+    G.eps2 = g.eps2;
+    return G;
+}
+
+template <int MODE>
+void launch_lowp(const Grid &g, sj_path path, const LpOut &R, int nblocks, hipStream_t s) {
+    if (g.d > kLpMaxD) throw Unsupported{"FP32/BF16 MFMA paths support d <= 64"};
+    if (nblocks <= 0) return;
+    const LpGrid G = lp_grid(g);
+    if (path == SJ_FP32_MFMA)
+        hipLaunchKernelGGL((k_lowp<PREC_F32, MODE>), dim3(nblocks), dim3(kThreads), 0, s, G, R);
+    else
+        hipLaunchKernelGGL((k_lowp<PREC_BF16, MODE>), dim3(nblocks), dim3(kThreads), 0, s, G, R);
+    SJ_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+// Count: per-query counts into cnt_sorted; band counter in ro.band_dev;
+// largest band half-width in ro.aux_dev[0] (bits).
+void lowp_count(Grid &g, sj_path path, int32_t *cnt_sorted, RefineOut &ro, hipStream_t s) {
+    fill_zero(ro.band_dev, sizeof(unsigned long long), s);
+    fill_zero(ro.aux_dev, 3 * sizeof(unsigned long long), s);
+    LpOut R{};
+    R.cnt = cnt_sorted;
+    R.band = ro.band_dev;
+    R.meas = ro.aux_dev;
+    R.block_lo = 0;
+    ro.kt.start(ro.timed, s);
+    launch_lowp<MODE_COUNT>(g, path, R, (int)g.nblocks, s);
+    ro.kt.stop(s);
+}
+
+void lowp_pairs(Grid &g, sj_path path, const ChunkPlan &p, int64_t qlo, int32_t *pairs, double *d2, RefineOut &ro,
+                hipStream_t s) {
+    // block items covering the chunk's work items
+    LpOut R{};
+    R.off = g.off;
+    R.base = p.base;
+    R.qlo = (int32_t)qlo;
+    R.qhi = (int32_t)p.next;
+    R.pairs = pairs;
+    R.d2 = d2;
+    R.band = ro.band_dev;
+    R.meas = ro.aux_dev;
+    fill_zero(ro.band_dev, sizeof(unsigned long long), s);
+    fill_zero(ro.aux_dev, 3 * sizeof(unsigned long long), s);
+    R.block_lo = (int32_t)p.block_lo;
+    ro.kt.start(ro.timed, s);
+    launch_lowp<MODE_EMIT>(g, path, R, (int)(p.block_hi - p.block_lo), s);
+    ro.kt.stop(s);
+}
+
+void lowp_measure(Grid &g, sj_path path, double *max_err, double *max_band, int64_t *viol, hipStream_t s) {
+    unsigned long long *m = dev_alloc_n<unsigned long long>(4, s);
+    fill_zero(m, 4 * sizeof(unsigned long long), s);
+    LpOut R{};
+    R.band = m + 3;
+    R.meas = m;
+    R.block_lo = 0;
+    launch_lowp<MODE_MEASURE>(g, path, R, (int)g.nblocks, s);
+    unsigned long long h[3] = {0, 0, 0};
+    SJ_HIP(hipMemcpyAsync(h, m, sizeof h, hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    dev_free(m, s);
+    double e, b;
+    std::memcpy(&e, &h[0], sizeof e);
+    std::memcpy(&b, &h[2], sizeof b);
+    *max_err = e;
+    *max_band = b;
+    *viol = (int64_t)h[1];
+}
+
+}  // namespace sj

@@ -696,7 +696,7 @@ void refine_count(Grid &g, sj_path path, int32_t *cnt_sorted, RefineOut &ro, hip
         ro.kt.stop(s);
         ro.band_rel = g.eps2 > 0 ? delta / g.eps2 : 0.0;
     } else {
-        throw Unsupported{"path not supported by this build"};
+        lowp_count(g, path, cnt_sorted, ro, s);
     }
 }
 
@@ -706,7 +706,8 @@ namespace {
 // of whole queries whose pairs fit in `capacity`, and the work items that
 // cover it. One thread; binary searches over the prefix sums and the items.
 __global__ void k_chunk_plan(const int64_t *__restrict__ off, const Item *__restrict__ items, int64_t n,
-                             int64_t nitems, int64_t cursor, int64_t capacity, int64_t *__restrict__ out) {
+                             int64_t nitems, const int32_t *__restrict__ blocks, int64_t nblocks, int64_t cursor,
+                             int64_t capacity, int64_t *__restrict__ out) {
     const int64_t base = off[cursor];
     const int64_t need = off[cursor + 1] - base;
     if (need > capacity) {
@@ -735,22 +736,40 @@ __global__ void k_chunk_plan(const int64_t *__restrict__ off, const Item *__rest
         if (items[mid].qbegin < next) lo = mid + 1;
         else hi = mid;
     }
+    const int64_t ihi = lo;
+    // block items: first with blocks[b + 1] > ilo; end = first with blocks[b] >= ihi
+    int64_t x = 0, y = nblocks;
+    while (x < y) {
+        const int64_t mid = x + (y - x) / 2;
+        if (blocks[mid + 1] <= ilo) x = mid + 1;
+        else y = mid;
+    }
+    const int64_t blo = x;
+    y = nblocks;
+    while (x < y) {
+        const int64_t mid = x + (y - x) / 2;
+        if (blocks[mid] < ihi) x = mid + 1;
+        else y = mid;
+    }
     out[0] = 0;
     out[1] = off[next] - base;
     out[2] = next;
     out[3] = ilo;
-    out[4] = lo;
+    out[4] = ihi;
     out[5] = base;
+    out[6] = blo;
+    out[7] = x;
 }
 
 }  // namespace
 
 ChunkPlan plan_chunk(Grid &g, int64_t cursor, int64_t capacity, hipStream_t s) {
     int64_t *d = dev_alloc_n<int64_t>(8, s);
-    hipLaunchKernelGGL(k_chunk_plan, dim3(1), dim3(1), 0, s, g.off, g.item, g.n, g.items, cursor, capacity, d);
+    hipLaunchKernelGGL(k_chunk_plan, dim3(1), dim3(1), 0, s, g.off, g.item, g.n, g.items, g.blocks, g.nblocks,
+                       cursor, capacity, d);
     SJ_HIP(hipGetLastError());
     int64_t h[8] = {0};
-    SJ_HIP(hipMemcpyAsync(h, d, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipMemcpyAsync(h, d, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
     dev_free(d, s);
     ChunkPlan p;
@@ -760,6 +779,8 @@ ChunkPlan plan_chunk(Grid &g, int64_t cursor, int64_t capacity, hipStream_t s) {
     p.item_lo = h[3];
     p.item_hi = h[4];
     p.base = h[5];
+    p.block_lo = h[6];
+    p.block_hi = h[7];
     return p;
 }
 
@@ -787,7 +808,7 @@ void refine_pairs(Grid &g, sj_path path, const ChunkPlan &p, int64_t qlo, int32_
         ro.kt.stop(s);
         ro.band_rel = g.eps2 > 0 ? delta / g.eps2 : 0.0;
     } else {
-        throw Unsupported{"path not supported by this build"};
+        lowp_pairs(g, path, p, qlo, pairs, d2, ro, s);
     }
 }
 
@@ -811,7 +832,8 @@ void refine_measure(Grid &g, sj_path path, double *max_err, double *max_band, in
         launch_m64<MODE_MEASURE>(g, R, (int)g.items, delta, s);
     } else {
         dev_free(meas, s);
-        throw Unsupported{"path not supported by this build"};
+        lowp_measure(g, path, max_err, max_band, viol, s);
+        return;
     }
     unsigned long long h[2] = {0, 0};
     SJ_HIP(hipMemcpyAsync(h, meas, sizeof h, hipMemcpyDeviceToHost, s));

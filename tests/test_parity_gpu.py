@@ -10,7 +10,8 @@ from workloads import generators as gen
 
 pytestmark = pytest.mark.gpu
 
-PATHS = ["fp64_valu", "fp64_mfma"]
+PATHS = ["fp64_valu", "fp64_mfma", "fp32_mfma", "bf16_mfma"]
+LOWP = ["fp32_mfma", "bf16_mfma"]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -164,19 +165,42 @@ def test_paths_emit_identical_lists():
     X = gen.gaussian_mixture(20000, 8, seed=2)
     eps = _eps_for(X, 30)
     a = gpu_join(X, eps, "fp64_valu")["pairs"]
-    b = gpu_join(X, eps, "fp64_mfma")["pairs"]
-    assert np.array_equal(a, b)
+    for p in PATHS[1:]:
+        b = gpu_join(X, eps, p)["pairs"]
+        assert np.array_equal(a, b), p
 
 
-def test_mfma_error_within_band():
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("d", [24, 32, 48, 64])
+def test_parity_high_dimensions(path, d):
+    # Gaussian mixture as in the precision workload, small n
+    X = gen.gaussian_mixture(4000, d, clusters=20, seed=d)
+    eps = _eps_for(X, 40)
+    _check_against_oracle(X, eps, path, f"gmm-{d}d")
+
+
+@pytest.mark.parametrize("path", LOWP)
+def test_lowp_rejects_large_d(path):
+    import torch
+    from paper_2209_11287_amd import SelfJoin, SelfJoinError
+    X = gen.uniform(500, 80, seed=1)
+    sj = SelfJoin(torch.from_numpy(X).to("cuda:0"), 1.0)
+    with pytest.raises(SelfJoinError) as ei:
+        sj.count(path)
+    assert ei.value.status == 5
+    sj.close()
+
+
+@pytest.mark.parametrize("path", ["fp64_mfma", "fp32_mfma", "bf16_mfma"])
+def test_mfma_error_within_band(path):
     import torch
     from paper_2209_11287_amd import SelfJoin, selfjoin_measure_error
-    for dist, d in [("uniform", 2), ("expo", 3), ("gmm", 4), ("gmm", 16), ("uniform", 7)]:
-        X = gen.make(dist, 20000, d, seed=d)
+    for dist, d in [("uniform", 2), ("expo", 3), ("gmm", 4), ("gmm", 16), ("uniform", 7), ("gmm", 64)]:
+        X = gen.make(dist, 20000 if d < 64 else 5000, d, seed=d)
         eps = _eps_for(X, 30)
         sj = SelfJoin(torch.from_numpy(X).to("cuda:0"), eps)
-        err, band, viol = selfjoin_measure_error(sj.grid, "fp64_mfma")
-        log(f"[band] {dist} d={d} max_err={err:.3e} band={band:.3e} rel={band / eps**2:.3e} viol={viol}")
+        err, band, viol = selfjoin_measure_error(sj.grid, path)
+        log(f"[band] {path} {dist} d={d} max_err={err:.3e} band={band:.3e} rel={band / eps**2:.3e} viol={viol}")
         assert viol == 0
         assert err <= band / 2  # the analysis bound, before its safety factor
         sj.close()
