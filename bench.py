@@ -29,6 +29,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "distance evals/s + self-join time, exact pairs; MFMA vs FP64 vector, 1 GPU"
+WORKLOAD_TEXT = {
+    "cfg2": "n=2,000,000 x {uniform, exponential(40)} x d in {2,3,4}, s~64; build + count + full pair list",
+    "small": "n=20,000 uniform d=2 eps=0.0218 (parity size); build + count + full pair list",
+    "prec": "n=1,000,000 Gaussian mixture (100 clusters, sigma 0.02) x d in {16,32,64}, s~50; "
+            "build + count + full pair list",
+    "skewed": "n=10,000,000 exponential(40) d=3, s~100; build + count + pair list in chunks",
+    "batched": "256 independent self-joins, n log-uniform in [1e3, 2e5], d in {2,3,4,8,16}, uniform, s~32; "
+               "one persistent work-queue launch (HIP graph) for count, one for pairs",
+}
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
@@ -44,14 +53,15 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--path", default="fp64_mfma")
     ap.add_argument("--compare", default="fp64_valu", help="second path timed on the same data ('' = none)")
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "small"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "small", "prec", "skewed", "batched"])
+    ap.add_argument("--chunk", type=int, default=0, help="pairs per output chunk (0 = one chunk)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     return ap.parse_args()
 
 
 def datasets(which):
     from workloads import configs
-    names = configs.CFG2 if which == "cfg2" else ["small"]
+    names = {"cfg2": configs.CFG2, "small": ["small"], "prec": configs.PREC, "skewed": configs.SKEWED}[which]
     return [configs.workload(nm) for nm in names]
 
 
@@ -66,7 +76,7 @@ def load_inputs(wl):
     return out
 
 
-def one_pass(inputs, path, bufs, collect=None, cref=None):
+def one_pass(inputs, path, bufs, collect=None, cref=None, chunk=0):
     """build + count + pairs over every data set. `bufs[i]` is a device
     buffer able to hold data set i's pairs (None = size from the count).
     `cref` (dict, optional): filled with C_ref per data set (an extra pass
@@ -77,11 +87,20 @@ def one_pass(inputs, path, bufs, collect=None, cref=None):
     for i, (w, X, xt) in enumerate(inputs):
         g = selfjoin_build_grid(xt, w["eps"])
         total, _, st_c = selfjoin_count(g, path, per_point=False)
-        if bufs[i] is None or bufs[i].shape[0] < total:
-            bufs[i] = torch.empty((max(total, 1), 2), dtype=torch.int32, device="cuda:0")
-        written, nxt, st_p = selfjoin_pairs(g, path, 0, bufs[i], None, total)
-        if written != total or nxt != w["n"]:
-            raise RuntimeError(f"pairs chunk incomplete: {written}/{total}, cursor {nxt}")
+        cap = total if chunk <= 0 else min(total, chunk)
+        if bufs[i] is None or bufs[i].shape[0] < cap:
+            bufs[i] = torch.empty((max(cap, 1), 2), dtype=torch.int32, device="cuda:0")
+        cursor, done, emit_ms = 0, 0, 0.0
+        st_p = None
+        while cursor < w["n"]:
+            written, cursor, st = selfjoin_pairs(g, path, cursor, bufs[i], None, cap)
+            done += written
+            emit_ms += st["ms_kernel"]
+            st_p = st if st_p is None else st_p
+        if done != total:
+            raise RuntimeError(f"pairs incomplete: {done}/{total}")
+        st_p = dict(st_p or {"ms": 0.0})
+        st_p["ms_kernel"] = emit_ms
         if cref is not None:
             cref[w["name"]] = selfjoin_grid_info(g)["cand_ref"]
         if collect is not None:
@@ -93,16 +112,16 @@ def one_pass(inputs, path, bufs, collect=None, cref=None):
         selfjoin_free_grid(g)
 
 
-def timed(inputs, path, steps, warmup, bufs, cref):
+def timed(inputs, path, steps, warmup, bufs, cref, chunk=0):
     import torch
     for i in range(warmup):
-        one_pass(inputs, path, bufs, cref=cref if i == 0 else None)
+        one_pass(inputs, path, bufs, cref=cref if i == 0 else None, chunk=chunk)
     torch.cuda.synchronize()
     recs = []
     t0 = time.perf_counter()
     for _ in range(steps):
         rec = []
-        one_pass(inputs, path, bufs, rec)
+        one_pass(inputs, path, bufs, rec, chunk=chunk)
         for r in rec:
             r["cand_ref"] = cref[r["name"]]
         recs.append(rec)
@@ -134,7 +153,7 @@ def traffic_for(kernel_key):
     return None
 
 
-def roofline(recs):
+def roofline(recs, path="fp64_mfma"):
     """Dominant tile kernel over the timed steps; algorithmic work per launch
     divided by its mean launch time (HIP events around the launch)."""
     per = {}
@@ -149,15 +168,22 @@ def roofline(recs):
         byts = sum(8.0 * r["pairs"] + 8.0 * r["n"] * r["d"] + 4.0 * r["n"] for rec in recs for r in rec)
         avg_ms = emit_ms / launches
         achieved = byts / launches / (avg_ms * 1e-3) / 1e9
-        return {"kernel": "k_m64 emit (pairs)", "bound": "hbm", "achieved": round(achieved, 1),
+        kname = {"fp64_mfma": "k_m64", "fp64_valu": "k_v64", "fp32_mfma": "k_lowp<F32>",
+                 "bf16_mfma": "k_lowp<BF16>"}[path]
+        return {"kernel": kname + " emit (pairs)", "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic_for("emit"), "avg_launch_ms": round(avg_ms, 4),
                 "algorithmic_bytes_per_launch": round(byts / launches)}
     flops = sum(2.0 * r["d"] * r["cand_ref"] for rec in recs for r in rec)
     avg_ms = count_ms / launches
     achieved = flops / launches / (avg_ms * 1e-3) / 1e12
-    return {"kernel": "k_m64 count", "bound": "mfma", "achieved": round(achieved, 3),
-            "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+    peak = {"fp64_mfma": FP64_PEAK_TFLOPS, "fp64_valu": FP64_PEAK_TFLOPS, "fp32_mfma": 157.3,
+            "bf16_mfma": 2500.0}[path]
+    kname = {"fp64_mfma": "k_m64", "fp64_valu": "k_v64", "fp32_mfma": "k_lowp<F32>",
+             "bf16_mfma": "k_lowp<BF16>"}[path]
+    return {"kernel": kname + " count", "bound": "mfma" if path != "fp64_valu" else "alu",
+            "achieved": round(achieved, 3),
+            "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
             "traffic": traffic_for("count"), "avg_launch_ms": round(avg_ms, 4),
             "algorithmic_flops_per_launch": round(flops / launches)}
 
@@ -183,6 +209,64 @@ def cpu_baseline(inputs):
             "seconds": round(secs, 2)}
 
 
+def batched_main(args):
+    """The batched workload: 256 problems through the batched C ABI."""
+    import math
+
+    import torch
+    from paper_2209_11287_amd import (selfjoin_batch_build, selfjoin_batch_count, selfjoin_batch_free,
+                                      selfjoin_batch_info, selfjoin_batch_pairs, selfjoin_build_grid,
+                                      selfjoin_free_grid, selfjoin_grid_info)
+    from workloads import generators as gen
+    params = gen.batch_problems(256, seed=0)
+    pts, eps = [], []
+    for b, (n, d) in enumerate(params):
+        pts.append(torch.from_numpy(gen.uniform(n, d, seed=[0, b])).to("cuda:0"))
+        vol = math.pi ** (d / 2) / math.gamma(d / 2 + 1)
+        eps.append((32.0 / max(n - 1, 1) / vol) ** (1.0 / d))
+    torch.cuda.synchronize()
+    # C_ref per problem (work unit), outside the timed region
+    cref = 0
+    for p, e in zip(pts, eps):
+        g = selfjoin_build_grid(p, e)
+        cref += selfjoin_grid_info(g)["cand_ref"]
+        selfjoin_free_grid(g)
+
+    def run(path, tune):
+        b = selfjoin_batch_build(pts, eps, tune=tune)
+        totals, _ = selfjoin_batch_count(b, path)
+        buf = torch.empty((max(1, sum(totals)), 2), dtype=torch.int32, device="cuda:0")
+        for _ in range(max(1, args.warmup)):
+            selfjoin_batch_count(b, path)
+            selfjoin_batch_pairs(b, path, buf)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kms = 0.0
+        for _ in range(args.steps):
+            _, st = selfjoin_batch_count(b, path)
+            _, st2 = selfjoin_batch_pairs(b, path, buf)
+            kms += st["ms"]
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / args.steps
+        ks = sorted({(p.shape[1], selfjoin_batch_info(b, i)["index_dims"]) for i, p in enumerate(pts)})
+        selfjoin_batch_free(b)
+        return sec, kms / args.steps, sum(totals), ks
+
+    sec, count_ms, pairs, ks = run(args.path, True)
+    out = {"metric": METRIC, "value": cref / sec, "unit": "distance evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": WORKLOAD_TEXT["batched"], "path": args.path, "cand_ref_per_step": cref,
+                      "pairs_per_step": pairs, "tuned_index_dims": ks,
+                      "note": "grid builds are outside the timed steps; count graph + pairs launch inside"},
+           "count_graph_ms": round(count_ms, 3)}
+    if args.compare:
+        sec2, _, _, _ = run(args.compare, False)
+        out["compare"] = {"path": args.compare, "value": cref / sec2, "ms_per_step": round(sec2 * 1e3, 3),
+                          "speedup_of_headline": round(sec2 / sec, 3)}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -195,13 +279,16 @@ def main():
         sys.exit(1)
     import paper_2209_11287_amd as pkg
     pkg.load()
+    if args.workload == "batched":
+        batched_main(args)
+        return
     wl = datasets(args.workload)
     log(f"[bench] generating {len(wl)} data sets")
     inputs = load_inputs(wl)
     bufs = [None] * len(inputs)
     log(f"[bench] path {args.path}: warmup {args.warmup}, steps {args.steps}")
     cref_map = {}
-    sec, recs = timed(inputs, args.path, args.steps, max(1, args.warmup), bufs, cref_map)
+    sec, recs = timed(inputs, args.path, args.steps, max(1, args.warmup), bufs, cref_map, args.chunk)
     cref = sum(r["cand_ref"] for r in recs[0])
     pairs = sum(r["pairs"] for r in recs[0])
     out = {
@@ -217,17 +304,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "n=2,000,000 x {uniform, exponential(40)} x d in {2,3,4}, s~64; "
-                               "build + count + full pair list" if args.workload == "cfg2" else "small",
-                   "path": args.path, "cand_ref_per_step": cref, "pairs_per_step": pairs},
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
+                   "path": args.path, "cand_ref_per_step": cref, "pairs_per_step": pairs,
+                   "chunk": args.chunk},
         "per_dataset": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
                         for r in recs[-1]],
-        "roofline": roofline(recs),
+        "roofline": roofline(recs, args.path),
     }
     if args.compare:
         log(f"[bench] compare path {args.compare}")
         bufs2 = [None] * len(inputs)
-        sec2, recs2 = timed(inputs, args.compare, args.steps, max(1, args.warmup), bufs2, {})
+        sec2, recs2 = timed(inputs, args.compare, args.steps, max(1, args.warmup), bufs2, {}, args.chunk)
         for rec in recs2:
             for r in rec:
                 r["cand_ref"] = cref_map[r["name"]]

@@ -70,10 +70,16 @@ typedef enum {
 
 /* Build options; pass NULL for defaults. */
 typedef struct {
-    int32_t index_dims; /* number of leading dimensions indexed by the grid
-                           (Section II-D: fewer than d); 0 = min(d, 4). The
-                           result does not depend on it. */
-    int32_t reserved[7];
+    int32_t index_dims;     /* number of leading dimensions indexed by the grid
+                               (Section II-D: fewer than d); 0 = min(d, 4). The
+                               result does not depend on it. */
+    int32_t tune;           /* batched form only: nonzero = choose index_dims per
+                               d by timing the FP64 MFMA count on the largest
+                               problem of that d (result-neutral) */
+    const char *tune_cache; /* batched form only: text file of tuned choices,
+                               read before and written after tuning; NULL =
+                               in-process cache only */
+    int64_t reserved[4];
 } sj_opts;
 
 /* Statistics of one call (all optional, pass NULL). */
@@ -162,6 +168,38 @@ sj_status selfjoin_grid_info(sj_grid *g, sj_grid_info *info, void *stream);
 /* Releases the handle; its device memory is freed in stream order on
  * `stream`. NULL is accepted. */
 void selfjoin_free_grid(sj_grid *g, void *stream);
+
+/* ---- Batched form: B independent self-joins of uneven n and d ----------
+ * All problems' work items are refined by one persistent work-queue kernel
+ * that takes the costliest items first; the count pipeline (queue reset,
+ * persistent kernel, per-problem prefix sums) is captured into a HIP graph
+ * on first use and replayed afterwards. FP64 paths only (SJ_FP64_MFMA,
+ * SJ_FP64_VALU); other paths return SJ_ERR_UNSUPPORTED. */
+typedef struct sj_batch sj_batch;
+
+/* points : host array of B device pointers, problem i is n[i] x d[i]
+ *          row-major FP64 (validated like selfjoin_build_grid).
+ * n, d, eps : host arrays of B entries. opts: index_dims / tune / tune_cache.
+ * out    : host; receives the handle (release with selfjoin_batch_free). */
+sj_status selfjoin_batch_build(int32_t B, const double *const *points, const int64_t *n,
+                               const int32_t *d, const double *eps, const sj_opts *opts,
+                               void *stream, sj_batch **out);
+
+/* totals : host int64[B], |R| of each problem. */
+sj_status selfjoin_batch_count(sj_batch *b, sj_path path, int64_t *totals, sj_stats *stats,
+                               void *stream);
+
+/* Writes every problem's pairs into one device buffer, problem i's rows
+ * (input indices of problem i) at [offsets[i], offsets[i + 1]), each in the
+ * order selfjoin_pairs would give. offsets: host int64[B + 1]. If the sum
+ * exceeds capacity, returns SJ_ERR_CAPACITY with offsets[B] = the sum. */
+sj_status selfjoin_batch_pairs(sj_batch *b, sj_path path, int32_t *pairs, int64_t capacity,
+                               int64_t *offsets, sj_stats *stats, void *stream);
+
+/* Indexed dimensions and work items of problem i. */
+sj_status selfjoin_batch_info(const sj_batch *b, int32_t i, int32_t *index_dims, int64_t *items);
+
+void selfjoin_batch_free(sj_batch *b, void *stream);
 
 /* Static text for a status. */
 const char *selfjoin_status_string(sj_status s);

@@ -28,11 +28,17 @@ EXPORTS = [
     "selfjoin_status_string",
     "selfjoin_last_error",
     "selfjoin_version",
+    "selfjoin_batch_build",
+    "selfjoin_batch_count",
+    "selfjoin_batch_pairs",
+    "selfjoin_batch_info",
+    "selfjoin_batch_free",
 ]
 
 
 class sj_opts(ctypes.Structure):
-    _fields_ = [("index_dims", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("index_dims", ctypes.c_int32), ("tune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
+                ("reserved", ctypes.c_int64 * 4)]
 
 
 class sj_stats(ctypes.Structure):
@@ -110,6 +116,17 @@ def load():
     lib.selfjoin_last_error.argtypes = []
     lib.selfjoin_version.restype = ctypes.c_char_p
     lib.selfjoin_version.argtypes = []
+    lib.selfjoin_batch_build.restype = ctypes.c_int
+    lib.selfjoin_batch_build.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp), _i64p, ctypes.POINTER(ctypes.c_int32),
+                                         _dp, ctypes.POINTER(sj_opts), _vp, ctypes.POINTER(_vp)]
+    lib.selfjoin_batch_count.restype = ctypes.c_int
+    lib.selfjoin_batch_count.argtypes = [_vp, ctypes.c_int, _i64p, ctypes.POINTER(sj_stats), _vp]
+    lib.selfjoin_batch_pairs.restype = ctypes.c_int
+    lib.selfjoin_batch_pairs.argtypes = [_vp, ctypes.c_int, _vp, _i64, _i64p, ctypes.POINTER(sj_stats), _vp]
+    lib.selfjoin_batch_info.restype = ctypes.c_int
+    lib.selfjoin_batch_info.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _i64p]
+    lib.selfjoin_batch_free.restype = None
+    lib.selfjoin_batch_free.argtypes = [_vp, _vp]
     _lib = lib
     return lib
 

@@ -628,6 +628,31 @@ void fill_zero(void *p, size_t bytes, hipStream_t s) {
     SJ_HIP(hipGetLastError());
 }
 
+// Stable sort of (key, value) pairs by the low `bits` key bits. On return
+// *key_a / *val_a point at the sorted arrays (buffers may be swapped).
+void radix_sort_pairs(unsigned long long **key_a, int32_t **val_a, unsigned long long *key_b, int32_t *val_b,
+                      int64_t n, int bits, hipStream_t s) {
+    if (n <= 0) return;
+    const int nb = (int)std::max<int64_t>(1, (n + kRsTile - 1) / kRsTile);
+    int32_t *hist = dev_alloc_n<int32_t>((size_t)nb * 256, s);
+    int32_t *hist_ex = dev_alloc_n<int32_t>((size_t)nb * 256, s);
+    unsigned long long *ka = *key_a, *kb = key_b;
+    int32_t *va = *val_a, *vb = val_b;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kThreads), 0, s, ka, n, shift, hist, nb);
+        SJ_HIP(hipGetLastError());
+        exclusive_scan<int32_t, int32_t>(hist, hist_ex, (int64_t)nb * 256, s);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kThreads), 0, s, ka, va, kb, vb, n, shift, hist_ex, nb);
+        SJ_HIP(hipGetLastError());
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    dev_free(hist, s);
+    dev_free(hist_ex, s);
+    *key_a = ka;
+    *val_a = va;
+}
+
 void exclusive_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s) {
     exclusive_scan<int32_t, int64_t>(in, out, n, s);
 }

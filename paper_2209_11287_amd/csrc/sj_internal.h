@@ -65,6 +65,30 @@ struct Item {
     int32_t cell_first, cell_last;
 };
 
+// Device-side view of a grid (kernel argument).
+struct DevGrid {
+    const double *xs;
+    const double *xa;
+    const double *nrm;
+    const int32_t *perm;
+    const Range *ranges;
+    const Item *items;
+    int64_t n;
+    int32_t d, dp, da, nranges;
+    int32_t nitems;
+    double eps2;
+};
+
+// One problem of a batch, as the persistent kernel sees it.
+struct BProb {
+    DevGrid G;
+    double delta;      // FP64 MFMA band half-width
+    int32_t ks, slot;  // FP64 MFMA K-steps and norm-slot form
+    int32_t *cnt;      // per-query counts (sorted order), n + 1
+    int64_t *off;      // exclusive prefix of cnt, n + 1
+    int64_t pout;      // first output row of this problem
+};
+
 struct Grid {
     int64_t n = 0;
     int32_t d = 0, k = 0;
@@ -119,8 +143,10 @@ int64_t grid_cref(Grid &g, hipStream_t s);
 // Zero fill by kernel (usable under stream capture, unlike a memset node).
 void fill_zero(void *p, size_t bytes, hipStream_t s);
 
-// Scans (sj_build.hip).
+// Scans and sort (sj_build.hip).
 void exclusive_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
+void radix_sort_pairs(unsigned long long **key_a, int32_t **val_a, unsigned long long *key_b, int32_t *val_b,
+                      int64_t n, int bits, hipStream_t s);
 
 // Refine (sj_refine.hip).
 // Events bracketing one kernel launch on a stream.
@@ -180,6 +206,14 @@ void refine_pairs(Grid &g, sj_path path, const ChunkPlan &p, int64_t qlo, int32_
                   RefineOut &ro, hipStream_t s);
 void refine_measure(Grid &g, sj_path path, double *max_err, double *max_band, int64_t *viol,
                     hipStream_t s);
+
+// Batched form (sj_refine.hip).
+void launch_batch(bool emit, sj_path path, const BProb *probs, const int64_t *item_base, int B,
+                  const int32_t *queue, int total, int *counter, int32_t *pairs, unsigned long long *band,
+                  hipStream_t s);
+void launch_seg_scan(const BProb *probs, int B, int64_t *totals, hipStream_t s);
+DevGrid make_dev_grid(const Grid &g);
+double fp64_mfma_delta(const Grid &g);
 
 // Low-precision paths (sj_lowp.hip).
 void lowp_count(Grid &g, sj_path path, int32_t *cnt_sorted, RefineOut &ro, hipStream_t s);

@@ -35,18 +35,6 @@ constexpr int kWaves = kThreads / 64;
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
-struct DevGrid {
-    const double *xs;
-    const double *xa;
-    const double *nrm;
-    const int32_t *perm;
-    const Range *ranges;
-    const Item *items;
-    int64_t n;
-    int32_t d, dp, da, nranges;
-    int32_t nitems;
-    double eps2;
-};
 
 // Output side of a refine launch.
 struct RefOut {
@@ -192,12 +180,9 @@ __device__ __forceinline__ void ring_drain(EmitRing &rb, bool all, const DevGrid
 // lane = candidate (64 per tile), loop over the item's queries. D > 0: the
 // candidate row is held in registers; D = 0: runtime d, read per dimension.
 template <int D, int MODE>
-__global__ __launch_bounds__(kThreads) void k_v64(DevGrid G, RefOut R) {
-    __shared__ uint32_t ring_lds[MODE == MODE_EMIT ? kWaves * 3 * kRing : 1];
+__device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int it, uint32_t *ring_lds) {
     const int lane = threadIdx.x & 63;
     const int wv = uniform_i32(threadIdx.x >> 6);
-    const int it = uniform_i32(R.item_lo + xcd_block(blockIdx.x, gridDim.x) * kWaves + wv);
-    if (it >= G.nitems) return;
     const Item I = G.items[it];
     const int q0 = uniform_i32(I.qbegin);
     const int nq = uniform_i32(I.qend - I.qbegin);
@@ -300,6 +285,15 @@ __global__ __launch_bounds__(kThreads) void k_v64(DevGrid G, RefOut R) {
             if (lane == 0 && jq < nq) R.cnt[q0 + jq] = v;
         }
     }
+}
+
+template <int D, int MODE>
+__global__ __launch_bounds__(kThreads) void k_v64(DevGrid G, RefOut R) {
+    __shared__ uint32_t ring_lds[MODE == MODE_EMIT ? kWaves * 3 * kRing : 1];
+    const int wv = uniform_i32(threadIdx.x >> 6);
+    const int it = uniform_i32(R.item_lo + xcd_block(blockIdx.x, gridDim.x) * kWaves + wv);
+    if (it >= G.nitems) return;
+    v64_item<D, MODE>(G, R, it, ring_lds);
 }
 
 // --------------------------------------------------------------------- M64 --
@@ -416,12 +410,9 @@ __device__ __forceinline__ unsigned m64_classify(double4_t acc, double nc, int t
 }
 
 template <int KS, bool SLOT, int MODE>
-__global__ __launch_bounds__(kThreads) void k_m64(DevGrid G, RefOut R, double delta) {
-    __shared__ uint32_t ring_lds[MODE == MODE_EMIT ? kWaves * 3 * kRing : 1];
+__device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, double delta, int it, uint32_t *ring_lds) {
     const int lane = threadIdx.x & 63;
     const int wv = uniform_i32(threadIdx.x >> 6);
-    const int it = uniform_i32(R.item_lo + xcd_block(blockIdx.x, gridDim.x) * kWaves + wv);
-    if (it >= G.nitems) return;
     const Item I = G.items[it];
     const int q0 = uniform_i32(I.qbegin);
     const int nq = uniform_i32(I.qend - I.qbegin);
@@ -583,6 +574,117 @@ __global__ __launch_bounds__(kThreads) void k_m64(DevGrid G, RefOut R, double de
     }
 }
 
+template <int KS, bool SLOT, int MODE>
+__global__ __launch_bounds__(kThreads) void k_m64(DevGrid G, RefOut R, double delta) {
+    __shared__ uint32_t ring_lds[MODE == MODE_EMIT ? kWaves * 3 * kRing : 1];
+    const int wv = uniform_i32(threadIdx.x >> 6);
+    const int it = uniform_i32(R.item_lo + xcd_block(blockIdx.x, gridDim.x) * kWaves + wv);
+    if (it >= G.nitems) return;
+    m64_item<KS, SLOT, MODE>(G, R, delta, it, ring_lds);
+}
+
+// ------------------------------------------------------------------ batch --
+// Persistent work-queue kernel over the work items of many independent
+// self-joins. Waves pop global item indices (ordered by descending cost: the
+// longest items start first) and run the same per-item tile code as the
+// single-problem kernels, with that problem's grid and outputs.
+template <int MODE, int PATHV>
+__global__ __launch_bounds__(kThreads) void k_batch(const BProb *__restrict__ probs,
+                                                    const int64_t *__restrict__ item_base, int B,
+                                                    const int32_t *__restrict__ queue, int total,
+                                                    int *__restrict__ counter, int32_t *__restrict__ pairs,
+                                                    unsigned long long *__restrict__ band) {
+    __shared__ uint32_t ring_lds[MODE == MODE_EMIT ? kWaves * 3 * kRing : 1];
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        int w = 0;
+        if (lane == 0) w = atomicAdd(counter, 1);
+        w = uniform_i32(__shfl(w, 0));
+        if (w >= total) break;
+        const int gi = queue[w];
+        int lo = 0, hi = B;  // last problem p with item_base[p] <= gi
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (item_base[mid] <= gi) lo = mid;
+            else hi = mid;
+        }
+        const int p = uniform_i32(lo);
+        const BProb P = probs[p];
+        RefOut R{};
+        R.cnt = P.cnt;
+        R.off = P.off;
+        R.base = 0;
+        R.qlo = 0;
+        R.qhi = (int32_t)P.G.n;
+        R.pairs = pairs + 2 * P.pout;
+        R.d2 = nullptr;
+        R.band = band;
+        R.item_lo = 0;
+        const int it = uniform_i32(gi - (int)item_base[p]);
+        if (PATHV == SJ_FP64_MFMA) {
+            switch (P.ks * 2 + P.slot) {
+                case 3: m64_item<1, true, MODE>(P.G, R, P.delta, it, ring_lds); break;
+                case 2: m64_item<1, false, MODE>(P.G, R, P.delta, it, ring_lds); break;
+                case 5: m64_item<2, true, MODE>(P.G, R, P.delta, it, ring_lds); break;
+                case 4: m64_item<2, false, MODE>(P.G, R, P.delta, it, ring_lds); break;
+                case 7: m64_item<3, true, MODE>(P.G, R, P.delta, it, ring_lds); break;
+                case 6: m64_item<3, false, MODE>(P.G, R, P.delta, it, ring_lds); break;
+                case 9: m64_item<4, true, MODE>(P.G, R, P.delta, it, ring_lds); break;
+                case 8: m64_item<4, false, MODE>(P.G, R, P.delta, it, ring_lds); break;
+                default:
+                    if (P.slot) m64_item<0, true, MODE>(P.G, R, P.delta, it, ring_lds);
+                    else m64_item<0, false, MODE>(P.G, R, P.delta, it, ring_lds);
+                    break;
+            }
+        } else {
+            switch (P.G.d) {
+                case 1: v64_item<1, MODE>(P.G, R, it, ring_lds); break;
+                case 2: v64_item<2, MODE>(P.G, R, it, ring_lds); break;
+                case 3: v64_item<3, MODE>(P.G, R, it, ring_lds); break;
+                case 4: v64_item<4, MODE>(P.G, R, it, ring_lds); break;
+                case 8: v64_item<8, MODE>(P.G, R, it, ring_lds); break;
+                default: v64_item<0, MODE>(P.G, R, it, ring_lds); break;
+            }
+        }
+    }
+}
+
+// One block per problem: exclusive scan of its counts (n + 1 entries, the
+// last taken as 0) into its prefix array, and its total.
+__global__ __launch_bounds__(kThreads) void k_seg_scan(const BProb *__restrict__ probs,
+                                                       int64_t *__restrict__ totals) {
+    __shared__ int64_t wsum[kWaves];
+    __shared__ int64_t carry;
+    const BProb P = probs[blockIdx.x];
+    const int64_t n1 = P.G.n + 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int64_t t0 = 0; t0 < n1; t0 += kThreads) {
+        const int64_t i = t0 + tid;
+        const int64_t v = (i < P.G.n) ? (int64_t)P.cnt[i] : 0;
+        int64_t x = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        int64_t pre = carry;
+        for (int w = 0; w < wave; ++w) pre += wsum[w];
+        if (i < n1) const_cast<int64_t *>(P.off)[i] = pre + x - v;
+        __syncthreads();
+        if (tid == kThreads - 1) carry = pre + x;
+        __syncthreads();
+    }
+    if (tid == 0) totals[blockIdx.x] = carry;
+}
+
+__global__ void k_batch_reset(int *counter, unsigned long long *band) {
+    *counter = 0;
+    *band = 0;
+}
+
 DevGrid dev_grid(const Grid &g) {
     DevGrid G;
     G.xs = g.xs;
@@ -674,6 +776,38 @@ void launch_m64(const Grid &g, const RefOut &R, int nitems, double delta, hipStr
 }
 
 }  // namespace
+
+void launch_batch(bool emit, sj_path path, const BProb *probs, const int64_t *item_base, int B,
+                  const int32_t *queue, int total, int *counter, int32_t *pairs, unsigned long long *band,
+                  hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, counter, band);
+    SJ_HIP(hipGetLastError());
+    if (total <= 0) return;
+    int dev = 0, ncu = 256;
+    SJ_HIP(hipGetDevice(&dev));
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const unsigned blocks = (unsigned)std::min<int64_t>((total + kWaves - 1) / kWaves, (int64_t)ncu * 8);
+#define SJ_B(M, P) hipLaunchKernelGGL((k_batch<M, P>), dim3(blocks), dim3(kThreads), 0, s, probs, item_base, B, queue, \
+                                      total, counter, pairs, band)
+    if (path == SJ_FP64_MFMA) {
+        if (emit) SJ_B(MODE_EMIT, SJ_FP64_MFMA);
+        else SJ_B(MODE_COUNT, SJ_FP64_MFMA);
+    } else {
+        if (emit) SJ_B(MODE_EMIT, SJ_FP64_VALU);
+        else SJ_B(MODE_COUNT, SJ_FP64_VALU);
+    }
+#undef SJ_B
+    SJ_HIP(hipGetLastError());
+}
+
+DevGrid make_dev_grid(const Grid &g) { return dev_grid(g); }
+double fp64_mfma_delta(const Grid &g) { return m64_delta(g); }
+
+void launch_seg_scan(const BProb *probs, int B, int64_t *totals, hipStream_t s) {
+    if (B <= 0) return;
+    hipLaunchKernelGGL(k_seg_scan, dim3(B), dim3(kThreads), 0, s, probs, totals);
+    SJ_HIP(hipGetLastError());
+}
 
 // Enqueues the count kernel; the band counter lands in ro.band_dev (device,
 // zeroed here) and is read by the caller together with the total.

@@ -195,3 +195,102 @@ class SelfJoin:
 
     def close(self):
         self.grid.close(self.stream)
+
+
+# ------------------------------------------------------------- batched form --
+
+class BatchHandle:
+    """Owns a sj_batch*; the input tensors are kept alive with it."""
+
+    def __init__(self, ptr, ns, device, keep):
+        self.ptr = ptr
+        self.ns = list(ns)
+        self.device = device
+        self._keep = keep
+
+    def close(self, stream=None):
+        if self.ptr:
+            lib = _lib.load()
+            torch = _torch()
+            with torch.cuda.device(self.device):
+                lib.selfjoin_batch_free(self.ptr, _stream_ptr(stream))
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def selfjoin_batch_build(points_list, eps_list, index_dims: int = 0, tune: bool = False, tune_cache=None,
+                         stream=None) -> BatchHandle:
+    """points_list: list of CUDA float64 (n_i, d_i) tensors; eps_list: floats."""
+    torch = _torch()
+    pts = [p.contiguous() for p in points_list]
+    B = len(pts)
+    if len(eps_list) != B:
+        raise ValueError("one eps per problem")
+    for p in pts:
+        if not p.is_cuda or p.dtype != torch.float64 or p.dim() != 2:
+            raise ValueError("every problem must be a CUDA float64 (n, d) tensor")
+    lib = _lib.load()
+    ptrs = (ctypes.c_void_p * max(B, 1))(*[p.data_ptr() for p in pts])
+    ns = (ctypes.c_int64 * max(B, 1))(*[p.shape[0] for p in pts])
+    ds = (ctypes.c_int32 * max(B, 1))(*[p.shape[1] for p in pts])
+    es = (ctypes.c_double * max(B, 1))(*[float(e) for e in eps_list])
+    opts = _lib.sj_opts()
+    opts.index_dims = index_dims
+    opts.tune = 1 if tune else 0
+    opts.tune_cache = tune_cache.encode() if tune_cache else None
+    out = ctypes.c_void_p()
+    dev = pts[0].device if B else torch.device("cuda:0")
+    with torch.cuda.device(dev):
+        st = lib.selfjoin_batch_build(B, ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p)), ns, ds, es,
+                                      ctypes.byref(opts), _stream_ptr(stream), ctypes.byref(out))
+    check(st, "selfjoin_batch_build")
+    return BatchHandle(out, [p.shape[0] for p in pts], dev, pts)
+
+
+def selfjoin_batch_count(b: BatchHandle, path="fp64_mfma", stream=None):
+    """Returns (list of |R| per problem, stats dict)."""
+    torch = _torch()
+    lib = _lib.load()
+    B = len(b.ns)
+    totals = (ctypes.c_int64 * max(B, 1))()
+    stats = _lib.sj_stats()
+    with torch.cuda.device(b.device):
+        st = lib.selfjoin_batch_count(b.ptr, _path_id(path), totals, ctypes.byref(stats), _stream_ptr(stream))
+    check(st, "selfjoin_batch_count")
+    return [totals[i] for i in range(B)], stats.as_dict()
+
+
+def selfjoin_batch_pairs(b: BatchHandle, path, pairs, stream=None):
+    """Writes all problems' pairs into `pairs` (int32 CUDA (capacity, 2)).
+    Returns (offsets list of B + 1, stats dict)."""
+    torch = _torch()
+    lib = _lib.load()
+    B = len(b.ns)
+    offs = (ctypes.c_int64 * (B + 1))()
+    stats = _lib.sj_stats()
+    with torch.cuda.device(b.device):
+        st = lib.selfjoin_batch_pairs(b.ptr, _path_id(path), ctypes.c_void_p(pairs.data_ptr()),
+                                      int(pairs.shape[0]), offs, ctypes.byref(stats), _stream_ptr(stream))
+    if st == _lib.SJ_ERR_CAPACITY:
+        err = SelfJoinError(st, "selfjoin_batch_pairs")
+        err.needed = offs[B]
+        raise err
+    check(st, "selfjoin_batch_pairs")
+    return [offs[i] for i in range(B + 1)], stats.as_dict()
+
+
+def selfjoin_batch_info(b: BatchHandle, i: int):
+    lib = _lib.load()
+    k = ctypes.c_int32(0)
+    items = ctypes.c_int64(0)
+    check(lib.selfjoin_batch_info(b.ptr, i, ctypes.byref(k), ctypes.byref(items)), "selfjoin_batch_info")
+    return {"index_dims": k.value, "items": items.value}
+
+
+def selfjoin_batch_free(b: BatchHandle, stream=None):
+    b.close(stream)

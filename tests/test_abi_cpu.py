@@ -103,3 +103,28 @@ def test_product_package_does_not_import_oracle():
                 src = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(import|from)\s+oracle\b", src, flags=re.M), f
                 assert "liboracle" not in src and "selfjoin_oracle" not in src, f
+
+
+def test_batch_calls_reject_invalid_arguments(lib):
+    h = ctypes.c_void_p()
+    opts = _lib.sj_opts()
+    # B < 0, NULL out
+    assert lib.selfjoin_batch_build(-1, None, None, None, None, None, None, ctypes.byref(h)) == _lib.SJ_ERR_INVALID
+    assert lib.selfjoin_batch_build(0, None, None, None, None, None, None, None) == _lib.SJ_ERR_INVALID
+    # a bad problem in the list
+    ptrs = (ctypes.c_void_p * 2)(0x1000, 0x2000)
+    ns = (ctypes.c_int64 * 2)(10, 10)
+    ds = (ctypes.c_int32 * 2)(2, 0)
+    es = (ctypes.c_double * 2)(0.1, 0.1)
+    assert lib.selfjoin_batch_build(2, ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p)), ns, ds, es,
+                                    ctypes.byref(opts), None, ctypes.byref(h)) == _lib.SJ_ERR_INVALID
+    ds[1] = 2
+    es[0] = float("nan")
+    assert lib.selfjoin_batch_build(2, ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p)), ns, ds, es,
+                                    ctypes.byref(opts), None, ctypes.byref(h)) == _lib.SJ_ERR_INVALID
+    tot = (ctypes.c_int64 * 1)()
+    assert lib.selfjoin_batch_count(None, 1, tot, None, None) == _lib.SJ_ERR_INVALID
+    offs = (ctypes.c_int64 * 2)()
+    assert lib.selfjoin_batch_pairs(None, 1, None, 0, offs, None, None) == _lib.SJ_ERR_INVALID
+    assert lib.selfjoin_batch_info(None, 0, None, None) == _lib.SJ_ERR_INVALID
+    lib.selfjoin_batch_free(None, None)

@@ -1,0 +1,114 @@
+"""GPU parity of the batched form: each problem of a batch (uneven n and d)
+against the oracle run on that problem alone; HIP-graph replays; tuning."""
+import os
+
+import numpy as np
+import pytest
+
+from tests.gpu_util import log, pair_keys
+from workloads import generators as gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2209_11287_amd as p
+    p.load()
+    yield
+
+
+def _problems(count=24, seed=0):
+    """A small batch shaped like the batched workload: n log-uniform, d from
+    {2, 3, 4, 8, 16}, uniform points, eps for ~20 neighbours (estimated from
+    the unit-cube volume)."""
+    import math
+    params = gen.batch_problems(count, seed=seed, n_lo=50, n_hi=4000)
+    probs = []
+    for b, (n, d) in enumerate(params):
+        X = gen.uniform(n, d, seed=[seed, b])
+        vol_unit = math.pi ** (d / 2) / math.gamma(d / 2 + 1)
+        eps = (20.0 / max(n - 1, 1) / vol_unit) ** (1.0 / d)
+        probs.append((X, float(eps)))
+    return probs
+
+
+@pytest.mark.parametrize("path", ["fp64_mfma", "fp64_valu"])
+def test_batch_matches_oracle_per_problem(path):
+    import torch
+
+    import oracle
+    from paper_2209_11287_amd import (selfjoin_batch_build, selfjoin_batch_count, selfjoin_batch_free,
+                                      selfjoin_batch_pairs)
+    probs = _problems()
+    log(f"[batch] {len(probs)} problems path={path}")
+    pts = [torch.from_numpy(X).to("cuda:0") for X, _ in probs]
+    b = selfjoin_batch_build(pts, [e for _, e in probs])
+    totals, st = selfjoin_batch_count(b, path)
+    want = [oracle.grid_count(X, e)[0] for X, e in probs]
+    assert totals == want
+    buf = torch.empty((sum(totals), 2), dtype=torch.int32, device="cuda:0")
+    offs, _ = selfjoin_batch_pairs(b, path, buf)
+    out = buf.cpu().numpy()
+    for i, (X, e) in enumerate(probs):
+        _, _, opairs = oracle.grid_pairs(X, e)
+        got = out[offs[i]:offs[i + 1]]
+        assert np.array_equal(pair_keys(got), pair_keys(opairs)), i
+    selfjoin_batch_free(b)
+
+
+def test_batch_graph_replays_are_identical():
+    import torch
+
+    from paper_2209_11287_amd import selfjoin_batch_build, selfjoin_batch_count, selfjoin_batch_free
+    probs = _problems(16, seed=3)
+    pts = [torch.from_numpy(X).to("cuda:0") for X, _ in probs]
+    b = selfjoin_batch_build(pts, [e for _, e in probs])
+    first, _ = selfjoin_batch_count(b, "fp64_mfma")
+    for rep in range(4):
+        # eager work of the program between replays
+        junk = torch.randn(1 << 20, device="cuda:0").sum().item()
+        del junk
+        torch.cuda.synchronize()
+        again, _ = selfjoin_batch_count(b, "fp64_mfma")
+        assert again == first, rep
+    selfjoin_batch_free(b)
+
+
+def test_batch_tuning_is_result_neutral(tmp_path):
+    import torch
+
+    from paper_2209_11287_amd import (selfjoin_batch_build, selfjoin_batch_count, selfjoin_batch_free,
+                                      selfjoin_batch_info)
+    probs = _problems(12, seed=5)
+    pts = [torch.from_numpy(X).to("cuda:0") for X, _ in probs]
+    eps = [e for _, e in probs]
+    b0 = selfjoin_batch_build(pts, eps)
+    t0, _ = selfjoin_batch_count(b0, "fp64_mfma")
+    selfjoin_batch_free(b0)
+    cache = str(tmp_path / "tune.txt")
+    b1 = selfjoin_batch_build(pts, eps, tune=True, tune_cache=cache)
+    t1, _ = selfjoin_batch_count(b1, "fp64_mfma")
+    assert t0 == t1
+    assert os.path.exists(cache) and os.path.getsize(cache) > 0
+    ks = [selfjoin_batch_info(b1, i)["index_dims"] for i in range(len(probs))]
+    assert all(1 <= k <= 4 for k in ks)
+    selfjoin_batch_free(b1)
+
+
+def test_batch_capacity_error():
+    import torch
+
+    from paper_2209_11287_amd import SelfJoinError, selfjoin_batch_build, selfjoin_batch_count, selfjoin_batch_pairs
+    probs = _problems(6, seed=7)
+    pts = [torch.from_numpy(X).to("cuda:0") for X, _ in probs]
+    b = selfjoin_batch_build(pts, [e for _, e in probs])
+    totals, _ = selfjoin_batch_count(b, "fp64_mfma")
+    small = torch.empty((max(1, sum(totals) // 2), 2), dtype=torch.int32, device="cuda:0")
+    with pytest.raises(SelfJoinError) as ei:
+        selfjoin_batch_pairs(b, "fp64_mfma", small)
+    assert ei.value.needed == sum(totals)
+    b.close()
