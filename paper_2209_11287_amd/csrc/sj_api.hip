@@ -132,6 +132,12 @@ static void compute_counts(Grid &g, sj_path path, RefineOut &ro, hipStream_t s) 
     }
     ro.band_dev = g.aux;
     ro.aux_dev = g.aux + 1;
+    // FP64 count passes record per-tile in-masks; emission then reuses them
+    const bool fp64 = path == SJ_FP64_VALU || path == SJ_FP64_MFMA;
+    g.masks_valid = false;
+    if (fp64 && !g.masks && g.tiles > 0 && g.tiles * 32 <= kMaskBudget)
+        g.masks = dev_alloc_n<unsigned long long>((size_t)g.tiles * 4, s);
+    ro.masks = fp64 ? g.masks : nullptr;
     fill_zero(g.aux, 4 * sizeof(unsigned long long), s);
     hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, g.cnt + g.n, 0);
     SJ_HIP(hipGetLastError());
@@ -143,6 +149,7 @@ static void compute_counts(Grid &g, sj_path path, RefineOut &ro, hipStream_t s) 
     SJ_HIP(hipMemcpyAsync(aux, g.aux, sizeof aux, hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
     g.total = total;
+    g.masks_valid = ro.masks != nullptr;
     ro.band_pairs = (int64_t)aux[0];
     if (path == SJ_FP32_MFMA || path == SJ_BF16_MFMA) {
         double dl;

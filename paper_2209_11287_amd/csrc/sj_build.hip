@@ -573,6 +573,27 @@ __global__ void k_item_ranges(const Item *__restrict__ items, const int32_t *__r
     block_add(acc, cand_items);
 }
 
+// 16-candidate tiles of each work item (sum over its ranges of ceil(len / 16));
+// entry nitems is 0 so that an exclusive scan ends with the total.
+__global__ void k_item_tiles(const Range *__restrict__ ranges, const int32_t *__restrict__ nitems_p, int nranges,
+                             int32_t *__restrict__ tiles) {
+    const int64_t I = *nitems_p;
+    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it > I) return;
+    int32_t c = 0;
+    if (it < I)
+        for (int o = 0; o < nranges; ++o) {
+            const Range r = ranges[it * nranges + o];
+            c += (r.end - r.begin + 15) / 16;
+        }
+    tiles[it] = c;
+}
+
+__global__ void k_tiles_total(const int64_t *__restrict__ tile_off, const int32_t *__restrict__ nitems_p,
+                              unsigned long long *__restrict__ out) {
+    *out = (unsigned long long)tile_off[*nitems_p];
+}
+
 // C_ref = sum over non-empty cells c of |c| * (points in the 3^k cells around
 // c): the implementation-free work unit (grid-stride over cell x offset).
 __global__ void k_cell_cref(const int64_t *__restrict__ cell_key, const int32_t *__restrict__ cell_start,
@@ -659,7 +680,8 @@ void exclusive_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipSt
 
 void free_grid(Grid &g, hipStream_t s) {
     void *bufs[] = {g.xs,   g.xa,       g.nrm,        g.perm,       g.cell_key, g.cell_start, g.ranges,
-                    g.item, g.dev_nmax, g.line_first, g.line_table, g.blocks,   g.cnt,        g.off, g.aux};
+                    g.item, g.dev_nmax, g.line_first, g.line_table, g.blocks,   g.cnt,        g.off, g.aux,
+                    g.tile_off, g.masks};
     for (void *p : bufs)
         if (p) dev_free(p, s);
     g.xs = g.xa = g.nrm = nullptr;
@@ -675,6 +697,9 @@ void free_grid(Grid &g, hipStream_t s) {
     g.cnt = nullptr;
     g.off = nullptr;
     g.aux = nullptr;
+    g.tile_off = nullptr;
+    g.masks = nullptr;
+    g.masks_valid = false;
 }
 
 // Host-side reading of the grid geometry; identical arithmetic to the
@@ -844,9 +869,11 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
         SJ_HIP(hipGetLastError());
     }
     // ---- G5: work items and their neighbour ranges (tables sized by upper bounds) ----
-    unsigned long long *acc = dev_alloc_n<unsigned long long>(1, s);
-    fill_zero(acc, sizeof(unsigned long long), s);
+    unsigned long long *acc = dev_alloc_n<unsigned long long>(2, s);  // [0] item candidates, [1] tiles
+    fill_zero(acc, 2 * sizeof(unsigned long long), s);
     const int64_t items_ub = n + n / kTileQ + 1;  // lines <= cells <= n
+    g.tile_off = dev_alloc_n<int64_t>((size_t)items_ub + 1, s);
+    int32_t *item_tiles = dev_alloc_n<int32_t>((size_t)items_ub + 1, s);
     g.item = dev_alloc_n<Item>((size_t)items_ub, s);
     g.blocks = dev_alloc_n<int32_t>((size_t)items_ub + 1, s);
     g.ranges = dev_alloc_n<Range>((size_t)items_ub * g.nranges, s);
@@ -877,15 +904,22 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
         hipLaunchKernelGGL(k_item_ranges, dim3(2048), dim3(kThreads), 0, s, g.item, counters + 2, g.cell_key,
                            g.cell_start, counters + 0, range_geom(g), g.line_table, g.line_first, g.ranges, acc);
         SJ_HIP(hipGetLastError());
+        // tile offsets of the items (for the per-tile in-masks of the count pass)
+        hipLaunchKernelGGL(k_item_tiles, dim3(blocks_for(items_ub + 1)), dim3(kThreads), 0, s, g.ranges,
+                           counters + 2, g.nranges, item_tiles);
+        SJ_HIP(hipGetLastError());
+        exclusive_scan<int32_t, int64_t>(item_tiles, g.tile_off, items_ub + 1, s);
+        hipLaunchKernelGGL(k_tiles_total, dim3(1), dim3(1), 0, s, g.tile_off, counters + 2, acc + 1);
+        SJ_HIP(hipGetLastError());
     }
     // ---- one host sync: table sizes, candidates of the items, nmax ----
     int32_t hc[4] = {0, 0, 0, 0};
     double hn = 0.0;
-    unsigned long long hacc = 0;
+    unsigned long long hacc[2] = {0, 0};
     if (n > 0) {
         SJ_HIP(hipMemcpyAsync(hc, counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         SJ_HIP(hipMemcpyAsync(&hn, g.dev_nmax, sizeof(double), hipMemcpyDeviceToHost, s));
-        SJ_HIP(hipMemcpyAsync(&hacc, acc, sizeof hacc, hipMemcpyDeviceToHost, s));
+        SJ_HIP(hipMemcpyAsync(hacc, acc, sizeof hacc, hipMemcpyDeviceToHost, s));
         SJ_HIP(hipStreamSynchronize(s));
     }
     g.cells = hc[0];
@@ -893,9 +927,11 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     g.nblocks = hc[3];
     g.nmax = hn;
     g.cand_ref = -1;  // computed on request (grid_cref)
-    g.cand_items = (int64_t)hacc;
+    g.cand_items = (int64_t)hacc[0];
+    g.tiles = (int64_t)hacc[1];
 
     dev_free(acc, s);
+    dev_free(item_tiles, s);
     dev_free(key_a, s);
     dev_free(key_b, s);
     dev_free(flag, s);

@@ -17,6 +17,7 @@ constexpr int kTileQ = 16;         // queries per work item (one wave)
 constexpr int kRowPad = 64;        // extra zeroed rows after every point array
 constexpr int kBlockItems = 4;     // work items per block item (low-precision paths)
 constexpr int kLpMaxD = 64;        // largest d of the low-precision paths
+constexpr int64_t kMaskBudget = int64_t(16) << 30;  // largest in-mask buffer (bytes)
 
 // Thread-local error text.
 void set_error(const std::string &msg);
@@ -77,6 +78,7 @@ struct DevGrid {
     int32_t d, dp, da, nranges;
     int32_t nitems;
     double eps2;
+    const int64_t *tile_off;
 };
 
 // One problem of a batch, as the persistent kernel sees it.
@@ -121,6 +123,12 @@ struct Grid {
     int32_t *line_first = nullptr;  // first cell of each grid line (+ end marker)
     int32_t *line_table = nullptr;  // dense line key -> line id (or null when too large)
     int32_t *blocks = nullptr;      // first item of each block item (+ end sentinel)
+    int64_t *tile_off = nullptr;    // first 16-candidate tile of each item (+ total)
+    int64_t tiles = 0;              // 16-candidate tiles over all items
+    // per-tile in-masks written by the FP64 count passes (4 x 64 bits per tile:
+    // word r, bit 16g + j = query g + 4r of the item, candidate j of the tile)
+    unsigned long long *masks = nullptr;
+    bool masks_valid = false;
     double *dev_nmax = nullptr;  // device copy of nmax
 
     // cached per-query counts (sorted order) and their exclusive prefix sums
@@ -186,6 +194,7 @@ struct RefineOut {
     KernelTimer kt;          // those events
     unsigned long long *band_dev = nullptr;  // device counter of rechecked pairs
     unsigned long long *aux_dev = nullptr;   // device: [2] largest band half-width (bits)
+    unsigned long long *masks = nullptr;     // per-tile in-masks to record (FP64 count), nullable
     int64_t band_pairs = 0;
     double band_rel = 0;
     int64_t cand_eval = 0;

@@ -47,6 +47,7 @@ struct RefOut {
     unsigned long long *band;     // band pairs re-evaluated
     unsigned long long *meas;     // measure: [0] max err bits, [1] violations
     int32_t item_lo;              // first item of this launch
+    unsigned long long *masks;    // count: per-tile in-masks to record (nullable)
 };
 
 enum { MODE_COUNT = 0, MODE_EMIT = 1, MODE_MEASURE = 2 };
@@ -213,8 +214,13 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
 #pragma unroll
     for (int jq = 0; jq < kTileQ; ++jq) cnt[jq] = 0;
 
+    // in-mask recording (count): 16-candidate tile numbering of the item
+    const bool rec = MODE == MODE_COUNT && R.masks != nullptr;
+    const int64_t tile_base = rec ? G.tile_off[it] : 0;
+    int kb = 0;  // tiles of the ranges before the current one
     TileCursor tc;
     tc.first(rg);
+    int cur_o = tc.o, cur_cb = tc.t;
     double xn[D > 0 ? D : 1];
     if (D > 0 && tc.live(rg)) {
         const double *xc = xs + (int64_t)(tc.t + lane) * dp;  // rows are padded past n
@@ -223,6 +229,15 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
     }
     while (tc.live(rg)) {
         const int t = tc.t, ce = tc.ce;
+        if (rec && tc.o != cur_o) {
+            kb += (rg.end(cur_o) - rg.begin(cur_o) + 15) / 16;
+            cur_o = tc.o;
+            cur_cb = tc.t;
+        }
+        const int k16 = kb + (t - cur_cb) / 16;  // first 16-tile of this 64-candidate tile
+        unsigned long long qm[kTileQ];
+#pragma unroll
+        for (int jq = 0; jq < kTileQ; ++jq) qm[jq] = 0ull;
         const int c = t + lane;
         const bool valid = c < ce;
         double x[D > 0 ? D : 1];
@@ -255,6 +270,7 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
                 const bool in = valid && acc <= eps2;
                 if (MODE == MODE_COUNT) {
                     cnt[jq] += in ? 1 : 0;
+                    if (rec) qm[jq] = __ballot(in);
                 } else if (MODE == MODE_EMIT) {
                     const unsigned long long m = __ballot(in);
                     if ((emit_mask >> jq) & 1ull) {
@@ -274,6 +290,24 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
                     }
                 }
             }
+        }
+        if (rec) {
+            // four 16-candidate tiles: word r of sub-tile s collects the
+            // 16-bit slices of queries 4r .. 4r + 3 (query g + 4r at bits
+            // 16g); lane 4s + r stores it (the 16 words are contiguous)
+            const int nsub = (min(64, ce - t) + 15) / 16;
+            unsigned long long wl = 0;
+#pragma unroll
+            for (int sub = 0; sub < 4; ++sub) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    unsigned long long w = 0;
+#pragma unroll
+                    for (int gg = 0; gg < 4; ++gg) w |= ((qm[gg + 4 * r] >> (16 * sub)) & 0xffffull) << (16 * gg);
+                    if (lane == 4 * sub + r) wl = w;
+                }
+            }
+            if (lane < 4 * nsub) R.masks[(tile_base + k16) * 4 + lane] = wl;
         }
     }
     if (MODE == MODE_EMIT) ring_drain(rb, true, G, R, lane, my_pbase, my_pq, q0);
@@ -493,9 +527,24 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
             ring_drain(rb, false, G, R, lane, pbase_lane, pq_lane, q0);
         }
     };
+    const int64_t tile_base = (MODE == MODE_COUNT && R.masks) ? G.tile_off[it] : 0;
+    int kseq = 0;  // sequence number of the tile within the item
     auto account = [&](unsigned inm) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) cnt[r] += (inm >> r) & 1u;
+        if (MODE == MODE_COUNT && R.masks) {
+            // canonical in-mask: word r, bit 16g + j = query g + 4r, candidate j
+            const unsigned long long w0 = __ballot(inm & 1u), w1 = __ballot((inm >> 1) & 1u);
+            const unsigned long long w2 = __ballot((inm >> 2) & 1u), w3 = __ballot((inm >> 3) & 1u);
+            if (lane == 0) {
+                unsigned long long *m = R.masks + (tile_base + kseq) * 4;
+                m[0] = w0;
+                m[1] = w1;
+                m[2] = w2;
+                m[3] = w3;
+            }
+        }
+        ++kseq;
     };
 
     TileCursor tc;
@@ -581,6 +630,91 @@ __global__ __launch_bounds__(kThreads) void k_m64(DevGrid G, RefOut R, double de
     const int it = uniform_i32(R.item_lo + xcd_block(blockIdx.x, gridDim.x) * kWaves + wv);
     if (it >= G.nitems) return;
     m64_item<KS, SLOT, MODE>(G, R, delta, it, ring_lds);
+}
+
+// ------------------------------------------------------------ mask emit --
+// Emission from the in-masks recorded by an FP64 count pass (FP64 VALU or
+// FP64 MFMA: both record the same canonical masks): per 16 x 16 tile of an
+// item, word r, bit 16g + j says whether query g + 4r is within eps of
+// candidate j. This pass evaluates no distance; it expands the masks into
+// pairs at the exact offsets of the count, through the same LDS ring.
+__device__ __forceinline__ void mask_item(const DevGrid &G, const RefOut &R, const unsigned long long *masks, int it,
+                                          uint32_t *ring_lds) {
+    const int lane = threadIdx.x & 63;
+    const int wv = uniform_i32(threadIdx.x >> 6);
+    const Item I = G.items[it];
+    const int q0 = uniform_i32(I.qbegin);
+    const int nq = uniform_i32(I.qend - I.qbegin);
+    const int j = lane & 15;
+    const int g = lane >> 4;
+    const ItemRanges rg = load_ranges(G, it, lane);
+    bool emit_r[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = g + 4 * r;
+        emit_r[r] = i < nq && q0 + i >= R.qlo && q0 + i < R.qhi;
+    }
+    int64_t pbase_lane = -1;
+    int32_t pq_lane = 0;
+    if (lane < nq && q0 + lane >= R.qlo && q0 + lane < R.qhi) {
+        pbase_lane = R.off[q0 + lane] - R.base;
+        pq_lane = G.perm[q0 + lane];
+    }
+    unsigned long long ebal[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ebal[r] = __ballot(emit_r[r]);
+    EmitRing rb;
+    rb.cand = ring_lds + wv * 3 * kRing;
+    rb.rel = rb.cand + kRing;
+    rb.col = rb.rel + kRing;
+    rb.head = rb.tail = 0;
+    const unsigned long long lt = lanemask_lt();
+    const unsigned long long grp = 0xffffull << (16 * g);
+    const unsigned long long me = 1ull << lane;
+    int cur[4] = {0, 0, 0, 0};
+    const int64_t tile_base = G.tile_off[it];
+    int kseq = 0;
+    TileCursor tc;
+    tc.first(rg);
+    while (tc.live(rg)) {
+        const int t = tc.t;
+        const unsigned long long *m = masks + (tile_base + kseq) * 4;
+        unsigned long long bal[4];
+        int base_e = 0;
+        int pre[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            bal[r] = m[r] & ebal[r];
+            pre[r] = base_e + __popcll(bal[r] & lt);
+            base_e += __popcll(bal[r]);
+        }
+        if (base_e) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (bal[r] & me) {
+                    const int e = (rb.tail + pre[r]) & (kRing - 1);
+                    rb.cand[e] = (uint32_t)(t + j);
+                    rb.rel[e] = (uint32_t)(cur[r] + __popcll(bal[r] & lt & grp));
+                    rb.col[e] = (uint32_t)(g + 4 * r);
+                }
+            }
+            rb.tail += base_e;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) cur[r] += __popcll(bal[r] & grp);
+            ring_drain(rb, false, G, R, lane, pbase_lane, pq_lane, q0);
+        }
+        ++kseq;
+        tc.advance(rg, 16);
+    }
+    ring_drain(rb, true, G, R, lane, pbase_lane, pq_lane, q0);
+}
+
+__global__ __launch_bounds__(kThreads) void k_mask_emit(DevGrid G, RefOut R, const unsigned long long *masks) {
+    __shared__ uint32_t ring_lds[kWaves * 3 * kRing];
+    const int wv = uniform_i32(threadIdx.x >> 6);
+    const int it = uniform_i32(R.item_lo + xcd_block(blockIdx.x, gridDim.x) * kWaves + wv);
+    if (it >= G.nitems) return;
+    mask_item(G, R, masks, it, ring_lds);
 }
 
 // ------------------------------------------------------------------ batch --
@@ -700,6 +834,7 @@ DevGrid dev_grid(const Grid &g) {
     G.nranges = g.nranges;
     G.nitems = (int32_t)g.items;
     G.eps2 = g.eps2;
+    G.tile_off = g.tile_off;
     return G;
 }
 
@@ -817,6 +952,7 @@ void refine_count(Grid &g, sj_path path, int32_t *cnt_sorted, RefineOut &ro, hip
     R.cnt = cnt_sorted;
     R.band = ro.band_dev;
     R.item_lo = 0;
+    R.masks = ro.masks;
     ro.cand_eval = g.cand_items;
     if (path == SJ_FP64_VALU) {
         ro.kt.start(ro.timed, s);
@@ -931,7 +1067,16 @@ void refine_pairs(Grid &g, sj_path path, const ChunkPlan &p, int64_t qlo, int32_
     fill_zero(ro.band_dev, sizeof(unsigned long long), s);
     R.band = ro.band_dev;
     const int nitems = (int)(p.item_hi - p.item_lo);
-    if (path == SJ_FP64_VALU) {
+    if ((path == SJ_FP64_VALU || path == SJ_FP64_MFMA) && g.masks_valid && g.masks) {
+        ro.kt.start(ro.timed, s);
+        const unsigned blocks = (unsigned)((nitems + kWaves - 1) / kWaves);
+        if (blocks) {
+            hipLaunchKernelGGL(k_mask_emit, dim3(blocks), dim3(kThreads), 0, s, dev_grid(g), R,
+                               (const unsigned long long *)g.masks);
+            SJ_HIP(hipGetLastError());
+        }
+        ro.kt.stop(s);
+    } else if (path == SJ_FP64_VALU) {
         ro.kt.start(ro.timed, s);
         launch_v64<MODE_EMIT>(g, R, nitems, s);
         ro.kt.stop(s);
