@@ -52,10 +52,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--path", default="fp64_mfma")
-    ap.add_argument("--compare", default="fp64_valu", help="second path timed on the same data ('' = none)")
+    ap.add_argument("--compare", default="fp64_valu", help="second path timed on the same data ('none' = none)")
     ap.add_argument("--workload", default="cfg2", choices=["cfg2", "small", "prec", "skewed", "batched"])
     ap.add_argument("--chunk", type=int, default=0, help="pairs per output chunk (0 = one chunk)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -269,6 +271,8 @@ def batched_main(args):
 
 def main():
     args = parse()
+    if args.compare in ("", "none"):
+        args.compare = ""
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is described, not implemented)"}))
@@ -286,6 +290,12 @@ def main():
     log(f"[bench] generating {len(wl)} data sets")
     inputs = load_inputs(wl)
     bufs = [None] * len(inputs)
+    if args.copy_probe_mb > 0:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE calibrate the counters
+        src = torch.ones(args.copy_probe_mb * (1 << 20) // 8, dtype=torch.float64, device="cuda:0")
+        dst = src.clone()
+        torch.cuda.synchronize()
+        del src, dst
     log(f"[bench] path {args.path}: warmup {args.warmup}, steps {args.steps}")
     cref_map = {}
     sec, recs = timed(inputs, args.path, args.steps, max(1, args.warmup), bufs, cref_map, args.chunk)

@@ -308,6 +308,35 @@ void exclusive_scan(const Tin *in, Tacc *out, int64_t n, hipStream_t s) {
 // chain over dimensions in order. When d % 4 != 0 the norm also sits in xa's
 // slot d, where the MFMA tile multiplies it by 1 (Eq. (4) keeps the norms off
 // the tensor cores; here a spare K slot takes them).
+// Per-block maximum of non-negative doubles into part[blockIdx.x] (a
+// single-address atomic from tens of thousands of blocks serialises).
+__device__ __forceinline__ void block_max_out(double v, double *__restrict__ part_out) {
+    __shared__ double part[kThreads / 64];
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = part[0];
+        for (int w = 1; w < kThreads / 64; ++w) m = fmax(m, part[w]);
+        part_out[blockIdx.x] = m;
+    }
+}
+
+// One block: maximum of `nb` partials into *out.
+__global__ void k_max_final(const double *__restrict__ part, int64_t nb, double *__restrict__ out) {
+    double v = 0.0;
+    for (int64_t i = threadIdx.x; i < nb; i += blockDim.x) v = fmax(v, part[i]);
+    __shared__ double red[kThreads / 64];
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < kThreads / 64; ++w) m = fmax(m, red[w]);
+        *out = m;
+    }
+}
+
 struct GatherArgs {
     int d, dp, da;
     double mid[kMaxDims];
@@ -316,7 +345,7 @@ struct GatherArgs {
 __global__ void k_gather(const double *__restrict__ X, const int32_t *__restrict__ perm, int64_t n,
                          const GatherArgs ga_v, double *__restrict__ xs,
                          double *__restrict__ xa, double *__restrict__ nrm,
-                         unsigned long long *__restrict__ nmax_ord) {
+                         double *__restrict__ nmax_part) {
     const GatherArgs *ga = &ga_v;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double nn = 0.0;
@@ -337,16 +366,46 @@ __global__ void k_gather(const double *__restrict__ X, const int32_t *__restrict
         if (d & 3) pa[d] = nn;
         nrm[i] = nn;
     }
-    // norms are >= 0: their bit patterns order like their values
-    __shared__ double part[kThreads / 64];
-    for (int o = 32; o > 0; o >>= 1) nn = fmax(nn, __shfl_xor(nn, o));
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = nn;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = part[0];
-        for (int w = 1; w < kThreads / 64; ++w) m = fmax(m, part[w]);
-        atomicMax(nmax_ord, (unsigned long long)__double_as_longlong(m));
+    block_max_out(nn, nmax_part);
+}
+
+// d <= 4 (dp = da = 4): four lanes per point, lane t = dimension t, so each
+// wave stores 16 whole rows of xs and of xa contiguously. Same values as
+// k_gather (the norm chain runs over the dimensions in order in every lane).
+struct Mid4 {
+    double m[4];
+};
+
+__global__ void k_gather4(const double *__restrict__ X, const int32_t *__restrict__ perm, int64_t n, int d,
+                          Mid4 mid, double *__restrict__ xs, double *__restrict__ xa, double *__restrict__ nrm,
+                          double *__restrict__ nmax_part) {
+    const int t = threadIdx.x & 3;
+    double mx = 0.0;
+    // grid-stride over elements (point e / 4, dimension e % 4); the stride is
+    // a multiple of 4, so a lane keeps its dimension
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < 4 * ((n + 63) & ~int64_t(63));
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e >> 2;
+        double v = 0.0, c = 0.0;
+        if (i < n && t < d) {
+            v = X[(int64_t)perm[i] * d + t];
+            c = __dsub_rn(v, mid.m[t]);
+        }
+        double cc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cc[u] = __shfl(c, u, 4);
+        double nn = 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (u < d) nn = __fma_rn(cc[u], cc[u], nn);
+        if (i < n) {
+            xs[e] = t < d ? v : 0.0;
+            xa[e] = t < d ? c : ((t == d) ? nn : 0.0);
+            if (t == 0) nrm[i] = nn;
+            mx = fmax(mx, nn);
+        }
     }
+    block_max_out(mx, nmax_part);
 }
 
 // ----------------------------------------------------------- cell table ----
@@ -825,16 +884,28 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     fill_zero(g.xs + (size_t)n * g.dp, (size_t)kRowPad * g.dp * sizeof(double), s);
     fill_zero(g.xa + (size_t)n * g.da, (size_t)kRowPad * g.da * sizeof(double), s);
     fill_zero(g.nrm + n, (size_t)kRowPad * sizeof(double), s);
-    fill_zero(g.dev_nmax, sizeof(double), s);
-    {
-        GatherArgs ga{};
-        ga.d = d;
-        ga.dp = g.dp;
-        ga.da = g.da;
-        for (int j = 0; j < d; ++j) ga.mid[j] = g.mid[j];
-        hipLaunchKernelGGL(k_gather, dim3(blocks_for(n)), dim3(kThreads), 0, s, points, g.perm, n, ga, g.xs,
-                           g.xa, g.nrm, reinterpret_cast<unsigned long long *>(g.dev_nmax));
+    fill_zero(g.dev_nmax, sizeof(double), s);  // n = 0
+    if (n > 0) {
+        const unsigned nb = d <= 4 ? std::min(blocks_for(4 * n), 4096u) : blocks_for(n);
+        double *part = dev_alloc_n<double>(nb, s);
+        if (d <= 4) {
+            Mid4 mid{};
+            for (int j = 0; j < d; ++j) mid.m[j] = g.mid[j];
+            hipLaunchKernelGGL(k_gather4, dim3(nb), dim3(kThreads), 0, s, points, g.perm, n, d, mid, g.xs, g.xa,
+                               g.nrm, part);
+        } else {
+            GatherArgs ga{};
+            ga.d = d;
+            ga.dp = g.dp;
+            ga.da = g.da;
+            for (int j = 0; j < d; ++j) ga.mid[j] = g.mid[j];
+            hipLaunchKernelGGL(k_gather, dim3(nb), dim3(kThreads), 0, s, points, g.perm, n, ga, g.xs, g.xa, g.nrm,
+                               part);
+        }
         SJ_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kThreads), 0, s, part, (int64_t)nb, g.dev_nmax);
+        SJ_HIP(hipGetLastError());
+        dev_free(part, s);
     }
 
     // ---- G4: cell table, lines, work items ----

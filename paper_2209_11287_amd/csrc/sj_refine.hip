@@ -26,6 +26,9 @@
 
 #include "sj_internal.h"
 
+// v_writelane_b32: lane `lane` of `old` takes the wave-uniform `val`.
+__device__ int amdgcn_writelane(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
 namespace sj {
 
 namespace {
@@ -106,6 +109,11 @@ __device__ __forceinline__ ItemRanges load_ranges(const DevGrid &G, int it, int 
         r.rb = x.begin;
         r.re = x.end;
     }
+    // Wait for the bounds once, here. The tile loops read them with
+    // v_readlane while tile loads are in flight; without this the compiler
+    // cannot tell those reads from the newer loads and waits for the
+    // prefetched tiles at every range step.
+    __asm__ volatile("" : "+v"(r.rb), "+v"(r.re));
     return r;
 }
 
@@ -138,11 +146,12 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // Emission. Pairs go to exact offsets (prefix sums of the count pass), so a
-// query's pairs form one run in candidate order. Flagged pairs are first
-// compacted, wave-wide, into an LDS ring (candidate, rank within its query,
-// query column); whenever 64 are queued, one full-width store writes them.
-// This replaces one mostly-idle store instruction per tile and row slice by
-// one fully-populated store per 64 pairs.
+// query's pairs form one run in candidate order.
+//
+// V64 (lane = candidate, one query at a time): flagged pairs are compacted,
+// wave-wide, into an LDS ring (candidate, rank within its query, query
+// column); whenever 64 are queued, one full-width store writes them, instead
+// of one store per query with a few lanes active.
 constexpr int kRing = 512;  // > 63 queued + 256 from one tile
 
 struct EmitRing {
@@ -150,9 +159,41 @@ struct EmitRing {
     uint32_t *rel;   // rank of the pair within its query's run
     uint32_t *col;   // query column (0..15)
     int head, tail;  // wave-uniform counters (entries flushed / appended)
+    // The batch taken from the ring by the previous flush: its candidates'
+    // input indices were requested then and are stored one flush later, so
+    // that gather's latency overlaps the work in between.
+    int pend_n;        // wave-uniform, 0 = none
+    int64_t pend_pos;  // output row of lane's pair
+    int32_t pend_pq;   // input index of the query
+    int32_t pend_pc;   // input index of the candidate (in flight)
+    uint32_t pend_c;   // sorted index of the candidate (distances)
+    uint32_t pend_j;   // query column (distances)
 };
 
-// Writes `n` ring entries starting at head (n <= 64), lane l one entry.
+__device__ __forceinline__ void ring_init(EmitRing &rb, uint32_t *base) {
+    rb.cand = base;
+    rb.rel = base + kRing;
+    rb.col = base + 2 * kRing;
+    rb.head = rb.tail = 0;
+    rb.pend_n = 0;
+    rb.pend_pos = 0;
+    rb.pend_pq = rb.pend_pc = 0;
+    rb.pend_c = rb.pend_j = 0;
+}
+
+// Stores the pending batch.
+__device__ __forceinline__ void ring_store_pending(EmitRing &rb, const DevGrid &G, const RefOut &R, int lane, int q0) {
+    if (lane < rb.pend_n) {
+        reinterpret_cast<int2 *>(R.pairs)[rb.pend_pos] = make_int2(rb.pend_pq, rb.pend_pc);
+        if (R.d2)
+            R.d2[rb.pend_pos] = exact_d2(G.xs + (int64_t)(q0 + (int)rb.pend_j) * G.dp,
+                                         G.xs + (int64_t)rb.pend_c * G.dp, G.d);
+    }
+    rb.pend_n = 0;
+}
+
+// Takes `n` ring entries starting at head (n <= 64), lane l one entry:
+// stores the previous batch and leaves this one pending.
 __device__ __forceinline__ void ring_flush(EmitRing &rb, int n, const DevGrid &G, const RefOut &R, int lane,
                                            int64_t pbase_of_lane, int32_t pq_of_lane, int q0) {
     wave_lds_sync();
@@ -161,20 +202,67 @@ __device__ __forceinline__ void ring_flush(EmitRing &rb, int n, const DevGrid &G
     // the query's output base and input index live in lane j (j < 16)
     const int64_t pb = __shfl(pbase_of_lane, (int)j);
     const int32_t pq = __shfl(pq_of_lane, (int)j);
-    if (lane < n) {
-        const int64_t pos = pb + rel;
-        reinterpret_cast<int2 *>(R.pairs)[pos] = make_int2(pq, G.perm[c]);
-        if (R.d2)
-            R.d2[pos] = exact_d2(G.xs + (int64_t)(q0 + (int)j) * G.dp, G.xs + (int64_t)c * G.dp, G.d);
-    }
+    int32_t pc = 0;
+    if (lane < n) pc = G.perm[c];
     rb.head += n;
     wave_lds_sync();
+    ring_store_pending(rb, G, R, lane, q0);
+    rb.pend_n = n;
+    rb.pend_pos = pb + rel;
+    rb.pend_pq = pq;
+    rb.pend_pc = pc;
+    rb.pend_c = c;
+    rb.pend_j = j;
 }
 
 __device__ __forceinline__ void ring_drain(EmitRing &rb, bool all, const DevGrid &G, const RefOut &R, int lane,
                                            int64_t pbase_of_lane, int32_t pq_of_lane, int q0) {
     while (rb.tail - rb.head >= 64) ring_flush(rb, 64, G, R, lane, pbase_of_lane, pq_of_lane, q0);
-    if (all && rb.tail > rb.head) ring_flush(rb, rb.tail - rb.head, G, R, lane, pbase_of_lane, pq_of_lane, q0);
+    if (all) {
+        if (rb.tail > rb.head) ring_flush(rb, rb.tail - rb.head, G, R, lane, pbase_of_lane, pq_of_lane, q0);
+        ring_store_pending(rb, G, R, lane, q0);
+    }
+}
+
+// Direct emission of one 16 x 16 tile from its mask words (canonical
+// layout, already restricted to the queries this launch emits): lane (g, j)
+// writes pair (query g + 4r, candidate t + j) for each r whose bit it holds,
+// at the query's base + pairs so far + the pair's rank among the set bits
+// of its 16-bit group. `pc` = input index of candidate t + j.
+struct RowOut {
+    int64_t qb[4];  // output row of the first pair of query g + 4r (this launch)
+    int32_t pq[4];  // input index of query g + 4r
+    int cur[4];     // pairs of query g + 4r written so far
+    unsigned jlt;   // (1 << j) - 1
+};
+
+__device__ __forceinline__ void row_out_init(RowOut &ro, const bool emit_r[4], const DevGrid &G, const RefOut &R,
+                                             int q0, int g, int j) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int q = q0 + g + 4 * r;
+        ro.qb[r] = emit_r[r] ? R.off[q] - R.base : 0;
+        ro.pq[r] = emit_r[r] ? G.perm[q] : 0;
+        ro.cur[r] = 0;
+    }
+    ro.jlt = (1u << j) - 1u;
+}
+
+__device__ __forceinline__ void tile_store(const unsigned long long w[4], int t, int32_t pc, RowOut &ro, int g,
+                                           int j, const DevGrid &G, const RefOut &R, int q0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const unsigned long long m = w[r];
+        if (!m) continue;
+        const unsigned ch = (unsigned)(m >> (16 * g)) & 0xffffu;
+        if (__builtin_amdgcn_inverse_ballot_w64(m)) {
+            const int64_t pos = ro.qb[r] + (ro.cur[r] + __popc(ch & ro.jlt));
+            reinterpret_cast<int2 *>(R.pairs)[pos] = make_int2(ro.pq[r], pc);
+            if (R.d2)
+                R.d2[pos] = exact_d2(G.xs + (int64_t)(q0 + g + 4 * r) * G.dp, G.xs + (int64_t)(t + j) * G.dp, G.d);
+        }
+        ro.cur[r] += __popc(ch);
+    }
 }
 
 // --------------------------------------------------------------------- V64 --
@@ -204,10 +292,7 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
     }
     const unsigned long long emit_mask = __ballot(emit_q);
     EmitRing rb;
-    rb.cand = ring_lds + (MODE == MODE_EMIT ? wv * 3 * kRing : 0);
-    rb.rel = rb.cand + kRing;
-    rb.col = rb.rel + kRing;
-    rb.head = rb.tail = 0;
+    ring_init(rb, ring_lds + (MODE == MODE_EMIT ? wv * 3 * kRing : 0));
     int my_cur = 0;
     const unsigned long long lt = lanemask_lt();
     int cnt[kTileQ];
@@ -345,18 +430,22 @@ __global__ __launch_bounds__(kThreads) void k_v64(DevGrid G, RefOut R) {
 template <int KS>
 struct M64Tile {
     double b[KS > 0 ? KS : 1];
-    double nc;  // candidate norm (no-slot form)
+    double nc;   // candidate norm (no-slot form)
+    int32_t pc;  // emit: input index of candidate t + j
 };
 
-template <int KS, bool SLOT>
-__device__ __forceinline__ void m64_load(M64Tile<KS> &T, const DevGrid &G, int t, int j, int g) {
-    // rows up to t + 15 < n + 64 exist (padded)
-    const double *__restrict__ brow = G.xa + (int64_t)(t + j) * G.da + g;
+template <int KS, bool SLOT, int MODE>
+__device__ __forceinline__ void m64_load(M64Tile<KS> &T, const DevGrid &G, int t, int ce, unsigned boff, int j) {
+    // rows up to t + 15 < n + 64 exist (padded). The tile's base address is
+    // wave-uniform; the lane part (j * da + g doubles) is a fixed offset.
     if (KS > 0) {
+        const char *__restrict__ base = reinterpret_cast<const char *>(G.xa + (int64_t)t * G.da);
 #pragma unroll
-        for (int s = 0; s < (KS > 0 ? KS : 1); ++s) T.b[s] = brow[4 * s];
+        for (int s = 0; s < (KS > 0 ? KS : 1); ++s)
+            T.b[s] = *reinterpret_cast<const double *>(base + boff + 32u * (unsigned)s);
     }
-    if (!SLOT) T.nc = G.nrm[t + j];
+    if (!SLOT) T.nc = (G.nrm + t)[j];
+    if (MODE == MODE_EMIT) T.pc = t + j < ce ? G.perm[t + j] : 0;
 }
 
 template <int KS, bool SLOT>
@@ -384,6 +473,7 @@ __device__ __forceinline__ double4_t m64_tile(const M64Tile<KS> &T, const DevGri
 struct M64Thr {
     double lo[4], hi[4];  // SLOT: per row r
     double ecol;          // no slot: eps^2 for the column threshold
+    double clo, chi;      // no slot: eps^2 - Delta, eps^2 + Delta
     double nq[4];         // |q|^2 of row r (for the error measurement)
 };
 
@@ -443,10 +533,69 @@ __device__ __forceinline__ unsigned m64_classify(double4_t acc, double nc, int t
     return inm;
 }
 
+// Columns [0, n) of each 16-lane group (n = candidates left in the range).
+__device__ __forceinline__ unsigned long long col_mask(int n) {
+    if (n >= 16) return ~0ull;
+    return ((1ull << n) - 1ull) * 0x0001000100010001ull;
+}
+
+// Count / emit classification on wave-wide compare masks: word r, bit
+// 16g + j = (query g + 4r, candidate t + j) is within eps. Values at or
+// below threshold - Delta are in, above threshold + Delta out; the rest are
+// decided by the exact FP64 chain. `band` (wave-uniform) counts rechecks.
+template <bool SLOT>
+__device__ __forceinline__ void m64_words(double4_t acc, double nc, unsigned long long cm, int t, int g, int j,
+                                          int q0, const M64Thr &th, const DevGrid &G, unsigned long long &band,
+                                          unsigned long long w[4]) {
+    double h[4], l[4];
+    if (SLOT) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            h[r] = th.hi[r];
+            l[r] = th.lo[r];
+        }
+    } else {
+        const double hc = th.chi - nc, lc = th.clo - nc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            h[r] = hc;
+            l[r] = lc;
+        }
+    }
+    unsigned long long m[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) m[r] = __ballot(acc[r] <= h[r]);
+    if (!((m[0] | m[1] | m[2] | m[3]) & cm)) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) w[r] = 0ull;
+        return;
+    }
+    unsigned long long bd = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        w[r] = __ballot(acc[r] <= l[r]) & cm;
+        m[r] &= cm & ~w[r];
+        bd |= m[r];
+    }
+    if (__builtin_expect(bd != 0ull, 0)) {
+        // rare: exact FP64 chain on the original coordinates
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (!m[r]) continue;
+            bool ok = false;
+            if (__builtin_amdgcn_inverse_ballot_w64(m[r])) {
+                const int q = q0 + g + 4 * r;
+                ok = exact_d2(G.xs + (int64_t)q * G.dp, G.xs + (int64_t)(t + j) * G.dp, G.d) <= G.eps2;
+            }
+            w[r] |= __ballot(ok);
+            band += (unsigned long long)__popcll(m[r]);
+        }
+    }
+}
+
 template <int KS, bool SLOT, int MODE>
-__device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, double delta, int it, uint32_t *ring_lds) {
+__device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, double delta, int it) {
     const int lane = threadIdx.x & 63;
-    const int wv = uniform_i32(threadIdx.x >> 6);
     const Item I = G.items[it];
     const int q0 = uniform_i32(I.qbegin);
     const int nq = uniform_i32(I.qend - I.qbegin);
@@ -456,6 +605,7 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
     const int qa = q0 + (j < nq ? j : 0);
     const double *__restrict__ xa = G.xa;
     const ItemRanges rg = load_ranges(G, it, lane);
+    const unsigned boff = (unsigned)(j * da + g) * 8u;  // lane's B element within a tile
 
     // A operand (16 x K): A[i][k] = -2 q_i[k] for k < d, 1 in the norm slot.
     double aq[KS > 0 ? KS : 1];
@@ -470,8 +620,6 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
     M64Thr th;
     double4_t cinit = (double4_t){0.0, 0.0, 0.0, 0.0};
     bool emit_r[4];
-    int64_t pbase_lane = -1;  // lanes < 16: output base of query `lane`
-    int32_t pq_lane = 0;      // lanes < 16: input index of query `lane`
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = g + 4 * r;
@@ -485,63 +633,46 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
         emit_r[r] = MODE == MODE_EMIT && ok && q0 + i >= R.qlo && q0 + i < R.qhi;
     }
     th.ecol = G.eps2;
-    if (MODE == MODE_EMIT && lane < nq && q0 + lane >= R.qlo && q0 + lane < R.qhi) {
-        pbase_lane = R.off[q0 + lane] - R.base;
-        pq_lane = G.perm[q0 + lane];
-    }
-    EmitRing rb;
-    rb.cand = ring_lds + (MODE == MODE_EMIT ? wv * 3 * kRing : 0);
-    rb.rel = rb.cand + kRing;
-    rb.col = rb.rel + kRing;
-    rb.head = rb.tail = 0;
-    const unsigned long long lt = lanemask_lt();
-    const unsigned long long grp = 0xffffull << (16 * g);
-    int cur[4] = {0, 0, 0, 0};  // emitted so far for row g + 4r
-    int cnt[4] = {0, 0, 0, 0};
-    unsigned long long band = 0, viol = 0;
+    th.clo = G.eps2 - delta;
+    th.chi = G.eps2 + delta;
+    unsigned long long ebal[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ebal[r] = __ballot(emit_r[r]);
+    RowOut ro;
+    if (MODE == MODE_EMIT) row_out_init(ro, emit_r, G, R, q0, g, j);
+    int cnt[4] = {0, 0, 0, 0};  // in-pairs of row g + 4r in this lane's column
+    unsigned long long band = 0, viol = 0;  // band: wave-uniform in count / emit
     double maxerr = 0.0;
 
-    auto emit = [&](unsigned inm, int t) {
-        unsigned long long bal[4];
-        int base_e = 0;
-        int pre[4];
+    // in-mask recording (count): the words of 16 consecutive tiles gather in
+    // one register pair (lane 4s + r = word r of tile s of the group) and
+    // leave in one coalesced store
+    const bool rec = MODE == MODE_COUNT && R.masks != nullptr;
+    const int64_t tile_base = rec ? G.tile_off[it] : 0;
+    int kseq = 0;  // sequence number of the tile within the item
+    unsigned mlo = 0, mhi = 0;
+    auto consume = [&](const unsigned long long w[4], int t, int32_t pc) {
+        if (MODE == MODE_EMIT) {
+            unsigned long long bal[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            bal[r] = __ballot(emit_r[r] && ((inm >> r) & 1u));
-            pre[r] = base_e + __popcll(bal[r] & lt);
-            base_e += __popcll(bal[r]);
-        }
-        if (base_e) {
+            for (int r = 0; r < 4; ++r) bal[r] = w[r] & ebal[r];
+            tile_store(bal, t, pc, ro, g, j, G, R, q0);
+        } else {
+            if ((w[0] | w[1] | w[2] | w[3]) != 0ull) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (emit_r[r] && ((inm >> r) & 1u)) {
-                    const int e = (rb.tail + pre[r]) & (kRing - 1);
-                    rb.cand[e] = (uint32_t)(t + j);
-                    rb.rel[e] = (uint32_t)(cur[r] + __popcll(bal[r] & lt & grp));
-                    rb.col[e] = (uint32_t)(g + 4 * r);
+                for (int r = 0; r < 4; ++r) cnt[r] += __builtin_amdgcn_inverse_ballot_w64(w[r]) ? 1 : 0;
+                if (rec) {
+                    const int sl = 4 * (kseq & 15);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        mlo = amdgcn_writelane((int)(unsigned)w[r], sl + r, (int)mlo);
+                        mhi = amdgcn_writelane((int)(unsigned)(w[r] >> 32), sl + r, (int)mhi);
+                    }
                 }
             }
-            rb.tail += base_e;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) cur[r] += __popcll(bal[r] & grp);
-            ring_drain(rb, false, G, R, lane, pbase_lane, pq_lane, q0);
-        }
-    };
-    const int64_t tile_base = (MODE == MODE_COUNT && R.masks) ? G.tile_off[it] : 0;
-    int kseq = 0;  // sequence number of the tile within the item
-    auto account = [&](unsigned inm) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) cnt[r] += (inm >> r) & 1u;
-        if (MODE == MODE_COUNT && R.masks) {
-            // canonical in-mask: word r, bit 16g + j = query g + 4r, candidate j
-            const unsigned long long w0 = __ballot(inm & 1u), w1 = __ballot((inm >> 1) & 1u);
-            const unsigned long long w2 = __ballot((inm >> 2) & 1u), w3 = __ballot((inm >> 3) & 1u);
-            if (lane == 0) {
-                unsigned long long *m = R.masks + (tile_base + kseq) * 4;
-                m[0] = w0;
-                m[1] = w1;
-                m[2] = w2;
-                m[3] = w3;
+            if (rec && (kseq & 15) == 15) {
+                R.masks[(tile_base + kseq - 15) * 4 + lane] = ((unsigned long long)mhi << 32) | mlo;
+                mlo = mhi = 0;
             }
         }
         ++kseq;
@@ -554,13 +685,13 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
     int tB = 0, ceB = 0;
     int tA = tc.t, ceA = tc.ce;
     if (tc.live(rg)) {
-        m64_load<KS, SLOT>(nA, G, tA, j, g);
+        m64_load<KS, SLOT, MODE>(nA, G, tA, ceA, boff, j);
         tc.advance(rg, 16);
         hasB = tc.live(rg);
         if (hasB) {
             tB = tc.t;
             ceB = tc.ce;
-            m64_load<KS, SLOT>(nB, G, tB, j, g);
+            m64_load<KS, SLOT, MODE>(nB, G, tB, ceB, boff, j);
             tc.advance(rg, 16);
         }
     }
@@ -574,31 +705,35 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
         if (hasA) {
             tA = tc.t;
             ceA = tc.ce;
-            m64_load<KS, SLOT>(nA, G, tA, j, g);
+            m64_load<KS, SLOT, MODE>(nA, G, tA, ceA, boff, j);
             tc.advance(rg, 16);
         }
         hasB = hasA && tc.live(rg);
         if (hasB) {
             tB = tc.t;
             ceB = tc.ce;
-            m64_load<KS, SLOT>(nB, G, tB, j, g);
+            m64_load<KS, SLOT, MODE>(nB, G, tB, ceB, boff, j);
             tc.advance(rg, 16);
         }
         const double4_t a0 = m64_tile<KS, SLOT>(A, G, aq, cinit, t0, j, g, qa);
         double4_t a1;
         if (h1) a1 = m64_tile<KS, SLOT>(B, G, aq, cinit, t1, j, g, qa);
-        const unsigned in0 = m64_classify<SLOT, MODE>(a0, A.nc, t0, c0, g, j, q0, th, delta, G, band, viol, maxerr);
-        if (MODE == MODE_EMIT) emit(in0, t0);
-        else account(in0);
-        if (h1) {
-            const unsigned in1 =
-                m64_classify<SLOT, MODE>(a1, B.nc, t1, c1, g, j, q0, th, delta, G, band, viol, maxerr);
-            if (MODE == MODE_EMIT) emit(in1, t1);
-            else account(in1);
+        if (MODE == MODE_MEASURE) {
+            (void)m64_classify<SLOT, MODE>(a0, A.nc, t0, c0, g, j, q0, th, delta, G, band, viol, maxerr);
+            if (h1) (void)m64_classify<SLOT, MODE>(a1, B.nc, t1, c1, g, j, q0, th, delta, G, band, viol, maxerr);
+        } else {
+            unsigned long long w[4];
+            m64_words<SLOT>(a0, A.nc, col_mask(c0 - t0), t0, g, j, q0, th, G, band, w);
+            consume(w, t0, A.pc);
+            if (h1) {
+                m64_words<SLOT>(a1, B.nc, col_mask(c1 - t1), t1, g, j, q0, th, G, band, w);
+                consume(w, t1, B.pc);
+            }
         }
     }
-    if (MODE == MODE_EMIT) ring_drain(rb, true, G, R, lane, pbase_lane, pq_lane, q0);
     if (MODE == MODE_COUNT) {
+        if (rec && (kseq & 15) != 0 && lane < 4 * (kseq & 15))
+            R.masks[(tile_base + (kseq & ~15)) * 4 + lane] = ((unsigned long long)mhi << 32) | mlo;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             int v = cnt[r];
@@ -608,7 +743,6 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
             v += __shfl_xor(v, 8);
             if (j == 0 && g + 4 * r < nq) R.cnt[q0 + g + 4 * r] = v;
         }
-        for (int sh = 32; sh > 0; sh >>= 1) band += __shfl_xor(band, sh);
         if (lane == 0 && band) atomicAdd(R.band, band);
     }
     if (MODE == MODE_MEASURE) {
@@ -625,11 +759,10 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
 
 template <int KS, bool SLOT, int MODE>
 __global__ __launch_bounds__(kThreads) void k_m64(DevGrid G, RefOut R, double delta) {
-    __shared__ uint32_t ring_lds[MODE == MODE_EMIT ? kWaves * 3 * kRing : 1];
     const int wv = uniform_i32(threadIdx.x >> 6);
     const int it = uniform_i32(R.item_lo + xcd_block(blockIdx.x, gridDim.x) * kWaves + wv);
     if (it >= G.nitems) return;
-    m64_item<KS, SLOT, MODE>(G, R, delta, it, ring_lds);
+    m64_item<KS, SLOT, MODE>(G, R, delta, it);
 }
 
 // ------------------------------------------------------------ mask emit --
@@ -638,10 +771,36 @@ __global__ __launch_bounds__(kThreads) void k_m64(DevGrid G, RefOut R, double de
 // item, word r, bit 16g + j says whether query g + 4r is within eps of
 // candidate j. This pass evaluates no distance; it expands the masks into
 // pairs at the exact offsets of the count, through the same LDS ring.
-__device__ __forceinline__ void mask_item(const DevGrid &G, const RefOut &R, const unsigned long long *masks, int it,
-                                          uint32_t *ring_lds) {
+//
+// The masks of 16 consecutive tiles arrive in one coalesced vector load (lane
+// l holds word l % 4 of tile l / 4), the next 16 are loaded while these are
+// expanded, and all-zero tiles are skipped without touching the ring.
+
+// Moves the cursor forward by n >= 0 tiles of 16 candidates.
+__device__ __forceinline__ void skip_tiles(TileCursor &tc, const ItemRanges &rg, int n) {
+    while (n > 0) {
+        const int rem = (tc.ce - tc.t + 15) >> 4;  // tiles left in this range, current included
+        if (n < rem) {
+            tc.t += 16 * n;
+            return;
+        }
+        n -= rem;
+        tc.o = rg.first_nonempty(tc.o + 1);
+        if (tc.o >= rg.nr) return;
+        tc.t = rg.begin(tc.o);
+        tc.ce = rg.end(tc.o);
+    }
+}
+
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int lane) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ void mask_item(const DevGrid &G, const RefOut &R, const unsigned long long *masks,
+                                          int it) {
     const int lane = threadIdx.x & 63;
-    const int wv = uniform_i32(threadIdx.x >> 6);
     const Item I = G.items[it];
     const int q0 = uniform_i32(I.qbegin);
     const int nq = uniform_i32(I.qend - I.qbegin);
@@ -654,67 +813,60 @@ __device__ __forceinline__ void mask_item(const DevGrid &G, const RefOut &R, con
         const int i = g + 4 * r;
         emit_r[r] = i < nq && q0 + i >= R.qlo && q0 + i < R.qhi;
     }
-    int64_t pbase_lane = -1;
-    int32_t pq_lane = 0;
-    if (lane < nq && q0 + lane >= R.qlo && q0 + lane < R.qhi) {
-        pbase_lane = R.off[q0 + lane] - R.base;
-        pq_lane = G.perm[q0 + lane];
-    }
     unsigned long long ebal[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) ebal[r] = __ballot(emit_r[r]);
-    EmitRing rb;
-    rb.cand = ring_lds + wv * 3 * kRing;
-    rb.rel = rb.cand + kRing;
-    rb.col = rb.rel + kRing;
-    rb.head = rb.tail = 0;
-    const unsigned long long lt = lanemask_lt();
-    const unsigned long long grp = 0xffffull << (16 * g);
-    const unsigned long long me = 1ull << lane;
-    int cur[4] = {0, 0, 0, 0};
+    RowOut ro;
+    row_out_init(ro, emit_r, G, R, q0, g, j);
     const int64_t tile_base = G.tile_off[it];
-    int kseq = 0;
+    const int ntiles = uniform_i32((int)(G.tile_off[it + 1] - tile_base));
+    const int nwords = 4 * ntiles;
+    const unsigned long long *mb = masks + tile_base * 4;
+    unsigned long long wnext = lane < nwords ? mb[lane] : 0ull;
     TileCursor tc;
     tc.first(rg);
-    while (tc.live(rg)) {
-        const int t = tc.t;
-        const unsigned long long *m = masks + (tile_base + kseq) * 4;
-        unsigned long long bal[4];
-        int base_e = 0;
-        int pre[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            bal[r] = m[r] & ebal[r];
-            pre[r] = base_e + __popcll(bal[r] & lt);
-            base_e += __popcll(bal[r]);
+    int at = 0;  // tile the cursor points at
+    // one tile in hand: its candidates' input indices load while the next
+    // non-empty tile is found
+    bool hp = false;
+    int tp = 0;
+    int32_t pcp = 0;
+    unsigned long long wp[4] = {0ull, 0ull, 0ull, 0ull};
+    for (int b = 0; b < ntiles; b += 16) {
+        const unsigned long long w = wnext;
+        if (b + 16 < ntiles) {
+            const int idx = 4 * (b + 16) + lane;
+            wnext = idx < nwords ? mb[idx] : 0ull;
         }
-        if (base_e) {
+        unsigned long long nz = __ballot(w != 0ull);
+        while (nz) {
+            const int k = uniform_i32(__builtin_ctzll(nz) >> 2);
+            nz &= ~(0xfull << (4 * k));
+            unsigned long long wk[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (bal[r] & me) {
-                    const int e = (rb.tail + pre[r]) & (kRing - 1);
-                    rb.cand[e] = (uint32_t)(t + j);
-                    rb.rel[e] = (uint32_t)(cur[r] + __popcll(bal[r] & lt & grp));
-                    rb.col[e] = (uint32_t)(g + 4 * r);
-                }
-            }
-            rb.tail += base_e;
+            for (int r = 0; r < 4; ++r) wk[r] = readlane_u64(w, 4 * k + r) & ebal[r];
+            if (!(wk[0] | wk[1] | wk[2] | wk[3])) continue;
+            skip_tiles(tc, rg, b + k - at);
+            at = b + k;
+            const int t = tc.t;
+            int32_t pck = 0;
+            if (t + j < tc.ce) pck = G.perm[t + j];
+            if (hp) tile_store(wp, tp, pcp, ro, g, j, G, R, q0);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) cur[r] += __popcll(bal[r] & grp);
-            ring_drain(rb, false, G, R, lane, pbase_lane, pq_lane, q0);
+            for (int r = 0; r < 4; ++r) wp[r] = wk[r];
+            tp = t;
+            pcp = pck;
+            hp = true;
         }
-        ++kseq;
-        tc.advance(rg, 16);
     }
-    ring_drain(rb, true, G, R, lane, pbase_lane, pq_lane, q0);
+    if (hp) tile_store(wp, tp, pcp, ro, g, j, G, R, q0);
 }
 
 __global__ __launch_bounds__(kThreads) void k_mask_emit(DevGrid G, RefOut R, const unsigned long long *masks) {
-    __shared__ uint32_t ring_lds[kWaves * 3 * kRing];
     const int wv = uniform_i32(threadIdx.x >> 6);
     const int it = uniform_i32(R.item_lo + xcd_block(blockIdx.x, gridDim.x) * kWaves + wv);
     if (it >= G.nitems) return;
-    mask_item(G, R, masks, it, ring_lds);
+    mask_item(G, R, masks, it);
 }
 
 // ------------------------------------------------------------------ batch --
@@ -757,17 +909,17 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BProb *__restrict__ pr
         const int it = uniform_i32(gi - (int)item_base[p]);
         if (PATHV == SJ_FP64_MFMA) {
             switch (P.ks * 2 + P.slot) {
-                case 3: m64_item<1, true, MODE>(P.G, R, P.delta, it, ring_lds); break;
-                case 2: m64_item<1, false, MODE>(P.G, R, P.delta, it, ring_lds); break;
-                case 5: m64_item<2, true, MODE>(P.G, R, P.delta, it, ring_lds); break;
-                case 4: m64_item<2, false, MODE>(P.G, R, P.delta, it, ring_lds); break;
-                case 7: m64_item<3, true, MODE>(P.G, R, P.delta, it, ring_lds); break;
-                case 6: m64_item<3, false, MODE>(P.G, R, P.delta, it, ring_lds); break;
-                case 9: m64_item<4, true, MODE>(P.G, R, P.delta, it, ring_lds); break;
-                case 8: m64_item<4, false, MODE>(P.G, R, P.delta, it, ring_lds); break;
+                case 3: m64_item<1, true, MODE>(P.G, R, P.delta, it); break;
+                case 2: m64_item<1, false, MODE>(P.G, R, P.delta, it); break;
+                case 5: m64_item<2, true, MODE>(P.G, R, P.delta, it); break;
+                case 4: m64_item<2, false, MODE>(P.G, R, P.delta, it); break;
+                case 7: m64_item<3, true, MODE>(P.G, R, P.delta, it); break;
+                case 6: m64_item<3, false, MODE>(P.G, R, P.delta, it); break;
+                case 9: m64_item<4, true, MODE>(P.G, R, P.delta, it); break;
+                case 8: m64_item<4, false, MODE>(P.G, R, P.delta, it); break;
                 default:
-                    if (P.slot) m64_item<0, true, MODE>(P.G, R, P.delta, it, ring_lds);
-                    else m64_item<0, false, MODE>(P.G, R, P.delta, it, ring_lds);
+                    if (P.slot) m64_item<0, true, MODE>(P.G, R, P.delta, it);
+                    else m64_item<0, false, MODE>(P.G, R, P.delta, it);
                     break;
             }
         } else {
