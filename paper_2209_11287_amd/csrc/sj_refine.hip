@@ -427,43 +427,107 @@ __global__ __launch_bounds__(kThreads) void k_v64(DevGrid G, RefOut R) {
 //    item), D = |q|^2 - 2 q.c, and the candidate norm moves to a per-column
 //    threshold: in iff D <= eps^2 - |c|^2.
 // KS = K-steps of 4 dimensions (0 = runtime).
+// The 16-candidate tiles of a work item, in order (its ranges in order,
+// ceil(len / 16) tiles each), as a table in registers: lane l holds the first
+// candidate and the number of valid columns of tile 64c + l (chunk c). Tile
+// loops then read a tile's bounds with two v_readlane instead of walking the
+// ranges with scalar code.
+struct TileTable {
+    int tp;      // lane o < nr: first tile of range o
+    int ntiles;  // tiles of the item (wave-uniform)
+    int tt, tn;  // lane l: first candidate / valid columns of tile 64 * chunk + l
+    int chunk;   // chunk held in tt / tn (-1: none)
+};
+
+__device__ __forceinline__ void tile_table_init(TileTable &T, const ItemRanges &rg, int lane) {
+    int cnt = 0;
+    if (lane < rg.nr) {
+        const int len = rg.re - rg.rb;
+        cnt = len > 0 ? (len + 15) >> 4 : 0;
+    }
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    T.tp = incl - cnt;
+    T.ntiles = __builtin_amdgcn_readlane(incl, 63);
+    T.tt = T.tn = 0;
+    T.chunk = -1;
+}
+
+__device__ __forceinline__ void tile_table_chunk(TileTable &T, const ItemRanges &rg, int c, int lane) {
+    const int K = 64 * c + lane;
+    int oo = 0;  // last range whose first tile is <= K (empty ranges share it)
+    for (int o = 1; o < rg.nr; ++o)
+        if (K >= __builtin_amdgcn_readlane(T.tp, o)) oo = o;
+    const int b = __shfl(rg.rb, oo), e = __shfl(rg.re, oo), p = __shfl(T.tp, oo);
+    int t = b + 16 * (K - p);
+    int n = min(16, e - t);
+    if (K >= T.ntiles) t = n = 0;
+    T.tt = t;
+    T.tn = n;
+    T.chunk = c;
+}
+
+// Tile k of the item: first candidate and valid columns (wave-uniform).
+__device__ __forceinline__ void tile_at(TileTable &T, const ItemRanges &rg, int k, int lane, int &t, int &n) {
+    if ((k >> 6) != T.chunk) tile_table_chunk(T, rg, k >> 6, lane);
+    t = __builtin_amdgcn_readlane(T.tt, k & 63);
+    n = __builtin_amdgcn_readlane(T.tn, k & 63);
+}
+
 template <int KS>
 struct M64Tile {
     double b[KS > 0 ? KS : 1];
     double nc;   // candidate norm (no-slot form)
     int32_t pc;  // emit: input index of candidate t + j
+    int t, n;    // first candidate, valid columns
 };
 
+// Issues the loads of tile (t, n); nothing here waits for them.
 template <int KS, bool SLOT, int MODE>
-__device__ __forceinline__ void m64_load(M64Tile<KS> &T, const DevGrid &G, int t, int ce, unsigned boff, int j) {
+__device__ __forceinline__ void m64_load(M64Tile<KS> &T, const DevGrid &G, int t, int n, unsigned boff, int j) {
     // rows up to t + 15 < n + 64 exist (padded). The tile's base address is
     // wave-uniform; the lane part (j * da + g doubles) is a fixed offset.
+    T.t = t;
+    T.n = n;
     if (KS > 0) {
         const char *__restrict__ base = reinterpret_cast<const char *>(G.xa + (int64_t)t * G.da);
 #pragma unroll
         for (int s = 0; s < (KS > 0 ? KS : 1); ++s)
             T.b[s] = *reinterpret_cast<const double *>(base + boff + 32u * (unsigned)s);
     }
-    if (!SLOT) T.nc = (G.nrm + t)[j];
-    if (MODE == MODE_EMIT) T.pc = t + j < ce ? G.perm[t + j] : 0;
+    T.nc = SLOT ? 0.0 : (G.nrm + t)[j];
+    if (MODE == MODE_EMIT) T.pc = G.perm[t + min(j, n - 1)];  // n >= 1
 }
 
+// Columns j >= n (past the range) must fail every test: SLOT puts +inf into
+// the norm slot (the value becomes +inf), no-slot sets the column threshold
+// to -inf (m64_colthr).
 template <int KS, bool SLOT>
 __device__ __forceinline__ double4_t m64_tile(const M64Tile<KS> &T, const DevGrid &G, const double *aq,
-                                              double4_t cinit, int t, int j, int g, int qa) {
+                                              double4_t cinit, int j, int g, int qa, bool slot_lane) {
     double4_t acc = cinit;
     if (KS > 0) {
 #pragma unroll
-        for (int s = 0; s < (KS > 0 ? KS : 1); ++s)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], T.b[s], acc, 0, 0, 0);
+        for (int s = 0; s < (KS > 0 ? KS : 1); ++s) {
+            double bv = T.b[s];
+            if (SLOT && s == (KS > 0 ? KS : 1) - 1 && slot_lane && j >= T.n) bv = INFINITY;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], bv, acc, 0, 0, 0);
+        }
     } else {
         const int d = G.d, da = G.da, ks = da >> 2;
-        const double *__restrict__ brow = G.xa + (int64_t)(t + j) * da + g;
+        const double *__restrict__ brow = G.xa + (int64_t)(T.t + j) * da + g;
         const double *__restrict__ arow = G.xa + (int64_t)qa * da;
+        const bool colok = j < T.n;
         for (int s = 0; s < ks; ++s) {
             const int kk = 4 * s + g;
             const double a = kk < d ? -2.0 * arow[kk] : ((SLOT && kk == d) ? 1.0 : 0.0);
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, brow[4 * s], acc, 0, 0, 0);
+            double bv = brow[4 * s];
+            if (SLOT && kk == d && !colok) bv = INFINITY;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
         }
     }
     return acc;
@@ -471,9 +535,9 @@ __device__ __forceinline__ double4_t m64_tile(const M64Tile<KS> &T, const DevGri
 
 // Per-lane classification state.
 struct M64Thr {
-    double lo[4], hi[4];  // SLOT: per row r
+    double mid[4];        // SLOT: threshold of row r, eps^2 - |q|^2 (-inf for absent rows)
+    double lo[4], hi[4];  // SLOT: mid -/+ Delta (error measurement)
     double ecol;          // no slot: eps^2 for the column threshold
-    double clo, chi;      // no slot: eps^2 - Delta, eps^2 + Delta
     double nq[4];         // |q|^2 of row r (for the error measurement)
 };
 
@@ -533,62 +597,40 @@ __device__ __forceinline__ unsigned m64_classify(double4_t acc, double nc, int t
     return inm;
 }
 
-// Columns [0, n) of each 16-lane group (n = candidates left in the range).
-__device__ __forceinline__ unsigned long long col_mask(int n) {
-    if (n >= 16) return ~0ull;
-    return ((1ull << n) - 1ull) * 0x0001000100010001ull;
+// Count / emit classification on wave-wide compare masks: word r, bit
+// 16g + j = (query g + 4r, candidate t + j) is within eps. A value at most
+// Delta away from its threshold is decided by the exact FP64 chain; the rest
+// by the threshold. `band` (wave-uniform) counts the rechecks.
+template <int KS>
+__device__ __forceinline__ double m64_colthr(const M64Tile<KS> &T, int j, double eps2) {
+    return j < T.n ? eps2 - T.nc : -INFINITY;
 }
 
-// Count / emit classification on wave-wide compare masks: word r, bit
-// 16g + j = (query g + 4r, candidate t + j) is within eps. Values at or
-// below threshold - Delta are in, above threshold + Delta out; the rest are
-// decided by the exact FP64 chain. `band` (wave-uniform) counts rechecks.
 template <bool SLOT>
-__device__ __forceinline__ void m64_words(double4_t acc, double nc, unsigned long long cm, int t, int g, int j,
-                                          int q0, const M64Thr &th, const DevGrid &G, unsigned long long &band,
-                                          unsigned long long w[4]) {
-    double h[4], l[4];
-    if (SLOT) {
+__device__ __forceinline__ void m64_words(double4_t acc, double thr_col, int t, int g, int j, int q0,
+                                          const M64Thr &th, double delta, const DevGrid &G,
+                                          unsigned long long &band, unsigned long long w[4]) {
+    double thr[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            h[r] = th.hi[r];
-            l[r] = th.lo[r];
-        }
-    } else {
-        const double hc = th.chi - nc, lc = th.clo - nc;
+    for (int r = 0; r < 4; ++r) thr[r] = SLOT ? th.mid[r] : thr_col;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            h[r] = hc;
-            l[r] = lc;
-        }
-    }
-    unsigned long long m[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) m[r] = __ballot(acc[r] <= h[r]);
-    if (!((m[0] | m[1] | m[2] | m[3]) & cm)) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) w[r] = 0ull;
-        return;
-    }
-    unsigned long long bd = 0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        w[r] = __ballot(acc[r] <= l[r]) & cm;
-        m[r] &= cm & ~w[r];
-        bd |= m[r];
-    }
-    if (__builtin_expect(bd != 0ull, 0)) {
+    for (int r = 0; r < 4; ++r) w[r] = __ballot(acc[r] <= thr[r]);
+    const double u = fmin(fmin(fabs(acc[0] - thr[0]), fabs(acc[1] - thr[1])),
+                          fmin(fabs(acc[2] - thr[2]), fabs(acc[3] - thr[3])));
+    if (__builtin_expect(__ballot(u <= delta) != 0ull, 0)) {
         // rare: exact FP64 chain on the original coordinates
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            if (!m[r]) continue;
+            const bool bl = fabs(acc[r] - thr[r]) <= delta;
+            const unsigned long long bm = __ballot(bl);
+            if (!bm) continue;
             bool ok = false;
-            if (__builtin_amdgcn_inverse_ballot_w64(m[r])) {
+            if (bl) {
                 const int q = q0 + g + 4 * r;
                 ok = exact_d2(G.xs + (int64_t)q * G.dp, G.xs + (int64_t)(t + j) * G.dp, G.d) <= G.eps2;
             }
-            w[r] |= __ballot(ok);
-            band += (unsigned long long)__popcll(m[r]);
+            w[r] = (w[r] & ~bm) | __ballot(ok);
+            band += (unsigned long long)__popcll(bm);
         }
     }
 }
@@ -606,6 +648,8 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
     const double *__restrict__ xa = G.xa;
     const ItemRanges rg = load_ranges(G, it, lane);
     const unsigned boff = (unsigned)(j * da + g) * 8u;  // lane's B element within a tile
+    const bool slot_lane = SLOT && g == (d & 3);         // lane holding the norm slot's K index
+    const double eps2 = G.eps2;
 
     // A operand (16 x K): A[i][k] = -2 q_i[k] for k < d, 1 in the norm slot.
     double aq[KS > 0 ? KS : 1];
@@ -626,15 +670,14 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
         const bool ok = i < nq;
         const double nq_r = ok ? G.nrm[q0 + i] : 0.0;
         th.nq[r] = nq_r;
-        const double thr = G.eps2 - nq_r;
+        const double thr = eps2 - nq_r;
+        th.mid[r] = ok ? thr : -INFINITY;
         th.lo[r] = ok ? thr - delta : -INFINITY;
         th.hi[r] = ok ? thr + delta : -INFINITY;
         if (!SLOT) cinit[r] = ok ? nq_r : INFINITY;
         emit_r[r] = MODE == MODE_EMIT && ok && q0 + i >= R.qlo && q0 + i < R.qhi;
     }
-    th.ecol = G.eps2;
-    th.clo = G.eps2 - delta;
-    th.chi = G.eps2 + delta;
+    th.ecol = eps2;
     unsigned long long ebal[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) ebal[r] = __ballot(emit_r[r]);
@@ -649,9 +692,8 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
     // leave in one coalesced store
     const bool rec = MODE == MODE_COUNT && R.masks != nullptr;
     const int64_t tile_base = rec ? G.tile_off[it] : 0;
-    int kseq = 0;  // sequence number of the tile within the item
     unsigned mlo = 0, mhi = 0;
-    auto consume = [&](const unsigned long long w[4], int t, int32_t pc) {
+    auto consume = [&](const unsigned long long w[4], int k, int t, int32_t pc) {
         if (MODE == MODE_EMIT) {
             unsigned long long bal[4];
 #pragma unroll
@@ -662,7 +704,7 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
 #pragma unroll
                 for (int r = 0; r < 4; ++r) cnt[r] += __builtin_amdgcn_inverse_ballot_w64(w[r]) ? 1 : 0;
                 if (rec) {
-                    const int sl = 4 * (kseq & 15);
+                    const int sl = 4 * (k & 15);
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         mlo = amdgcn_writelane((int)(unsigned)w[r], sl + r, (int)mlo);
@@ -670,70 +712,62 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
                     }
                 }
             }
-            if (rec && (kseq & 15) == 15) {
-                R.masks[(tile_base + kseq - 15) * 4 + lane] = ((unsigned long long)mhi << 32) | mlo;
+            if (rec && (k & 15) == 15) {
+                R.masks[(tile_base + k - 15) * 4 + lane] = ((unsigned long long)mhi << 32) | mlo;
                 mlo = mhi = 0;
             }
         }
-        ++kseq;
     };
 
-    TileCursor tc;
-    tc.first(rg);
-    M64Tile<KS> nA, nB;
-    bool hasB = false;
-    int tB = 0, ceB = 0;
-    int tA = tc.t, ceA = tc.ce;
-    if (tc.live(rg)) {
-        m64_load<KS, SLOT, MODE>(nA, G, tA, ceA, boff, j);
-        tc.advance(rg, 16);
-        hasB = tc.live(rg);
-        if (hasB) {
-            tB = tc.t;
-            ceB = tc.ce;
-            m64_load<KS, SLOT, MODE>(nB, G, tB, ceB, boff, j);
-            tc.advance(rg, 16);
-        }
-    }
-    bool hasA = tA < ceA;
-    // two tiles in flight per iteration; the next pair is prefetched
-    while (hasA) {
-        const M64Tile<KS> A = nA, B = nB;
-        const int t0 = tA, c0 = ceA, t1 = tB, c1 = ceB;
-        const bool h1 = hasB;
-        hasA = tc.live(rg);
-        if (hasA) {
-            tA = tc.t;
-            ceA = tc.ce;
-            m64_load<KS, SLOT, MODE>(nA, G, tA, ceA, boff, j);
-            tc.advance(rg, 16);
-        }
-        hasB = hasA && tc.live(rg);
-        if (hasB) {
-            tB = tc.t;
-            ceB = tc.ce;
-            m64_load<KS, SLOT, MODE>(nB, G, tB, ceB, boff, j);
-            tc.advance(rg, 16);
-        }
-        const double4_t a0 = m64_tile<KS, SLOT>(A, G, aq, cinit, t0, j, g, qa);
-        double4_t a1;
-        if (h1) a1 = m64_tile<KS, SLOT>(B, G, aq, cinit, t1, j, g, qa);
+    TileTable TT;
+    tile_table_init(TT, rg, lane);
+    const int ntiles = TT.ntiles;
+    auto load = [&](M64Tile<KS> &T, int k) {
+        int tt, tn;
+        tile_at(TT, rg, k, lane, tt, tn);
+        m64_load<KS, SLOT, MODE>(T, G, tt, tn, boff, j);
+    };
+    auto classify = [&](const double4_t &acc, const M64Tile<KS> &T, int k) {
         if (MODE == MODE_MEASURE) {
-            (void)m64_classify<SLOT, MODE>(a0, A.nc, t0, c0, g, j, q0, th, delta, G, band, viol, maxerr);
-            if (h1) (void)m64_classify<SLOT, MODE>(a1, B.nc, t1, c1, g, j, q0, th, delta, G, band, viol, maxerr);
+            (void)m64_classify<SLOT, MODE>(acc, T.nc, T.t, T.t + T.n, g, j, q0, th, delta, G, band, viol, maxerr);
         } else {
             unsigned long long w[4];
-            m64_words<SLOT>(a0, A.nc, col_mask(c0 - t0), t0, g, j, q0, th, G, band, w);
-            consume(w, t0, A.pc);
-            if (h1) {
-                m64_words<SLOT>(a1, B.nc, col_mask(c1 - t1), t1, g, j, q0, th, G, band, w);
-                consume(w, t1, B.pc);
-            }
+            m64_words<SLOT>(acc, SLOT ? 0.0 : m64_colthr(T, j, eps2), T.t, g, j, q0, th, delta, G, band, w);
+            consume(w, k, T.t, T.pc);
         }
+    };
+    // both products first, then both classifications
+    auto run = [&](const M64Tile<KS> &TA, const M64Tile<KS> &TB, int k) {
+        const bool h1 = k + 1 < ntiles;
+        const double4_t a0 = m64_tile<KS, SLOT>(TA, G, aq, cinit, j, g, qa, slot_lane);
+        double4_t a1;
+        if (h1) a1 = m64_tile<KS, SLOT>(TB, G, aq, cinit, j, g, qa, slot_lane);
+        classify(a0, TA, k);
+        if (h1) classify(a1, TB, k + 1);
+    };
+    // Four tile buffers, two stages per iteration: a stage runs two tiles
+    // while the next two load into the other pair of buffers (fixed roles, so
+    // no register copies wait on loads in flight).
+    // Loads past the last tile repeat the last tile (same instruction count
+    // on every path, so each wait covers exactly the older tiles).
+    M64Tile<KS> T0, T1, T2, T3;
+    const int klast = ntiles - 1;
+    if (ntiles > 0) {
+        load(T0, 0);
+        load(T1, min(1, klast));
+    }
+    for (int k = 0; k < ntiles; k += 4) {
+        load(T2, min(k + 2, klast));
+        load(T3, min(k + 3, klast));
+        run(T0, T1, k);
+        if (k + 2 >= ntiles) break;
+        load(T0, min(k + 4, klast));
+        load(T1, min(k + 5, klast));
+        run(T2, T3, k + 2);
     }
     if (MODE == MODE_COUNT) {
-        if (rec && (kseq & 15) != 0 && lane < 4 * (kseq & 15))
-            R.masks[(tile_base + (kseq & ~15)) * 4 + lane] = ((unsigned long long)mhi << 32) | mlo;
+        if (rec && (ntiles & 15) != 0 && lane < 4 * (ntiles & 15))
+            R.masks[(tile_base + (ntiles & ~15)) * 4 + lane] = ((unsigned long long)mhi << 32) | mlo;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             int v = cnt[r];
