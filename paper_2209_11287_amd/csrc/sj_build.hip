@@ -632,20 +632,21 @@ __global__ void k_item_ranges(const Item *__restrict__ items, const int32_t *__r
     block_add(acc, cand_items);
 }
 
-// 16-candidate tiles of each work item (sum over its ranges of ceil(len / 16));
-// entry nitems is 0 so that an exclusive scan ends with the total.
+// 16-candidate tiles of each work item: its candidates (the ranges in order)
+// form one packed list, so ceil(sum of range lengths / 16); entry nitems is 0
+// so that an exclusive scan ends with the total.
 __global__ void k_item_tiles(const Range *__restrict__ ranges, const int32_t *__restrict__ nitems_p, int nranges,
                              int32_t *__restrict__ tiles) {
     const int64_t I = *nitems_p;
     const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (it > I) return;
-    int32_t c = 0;
+    int64_t c = 0;
     if (it < I)
         for (int o = 0; o < nranges; ++o) {
             const Range r = ranges[it * nranges + o];
-            c += (r.end - r.begin + 15) / 16;
+            c += r.end > r.begin ? r.end - r.begin : 0;
         }
-    tiles[it] = c;
+    tiles[it] = (int32_t)((c + 15) / 16);
 }
 
 __global__ void k_tiles_total(const int64_t *__restrict__ tile_off, const int32_t *__restrict__ nitems_p,

@@ -91,12 +91,6 @@ __device__ __forceinline__ unsigned long long lanemask_lt() {
 struct ItemRanges {
     int rb, re;
     int nr;
-    __device__ __forceinline__ int begin(int o) const { return __builtin_amdgcn_readlane(rb, o); }
-    __device__ __forceinline__ int end(int o) const { return __builtin_amdgcn_readlane(re, o); }
-    __device__ __forceinline__ int first_nonempty(int o) const {
-        while (o < nr && begin(o) >= end(o)) ++o;
-        return o;
-    }
 };
 
 __device__ __forceinline__ ItemRanges load_ranges(const DevGrid &G, int it, int lane) {
@@ -117,26 +111,62 @@ __device__ __forceinline__ ItemRanges load_ranges(const DevGrid &G, int it, int 
     return r;
 }
 
-// Walks the item's candidate tiles (all ranges, in order) `step` rows at a time.
-struct TileCursor {
-    int o, t, ce;
-    __device__ __forceinline__ bool live(const ItemRanges &rg) const { return o < rg.nr; }
-    __device__ __forceinline__ void first(const ItemRanges &rg) {
-        o = rg.first_nonempty(0);
-        t = o < rg.nr ? rg.begin(o) : 0;
-        ce = o < rg.nr ? rg.end(o) : 0;
-    }
-    __device__ __forceinline__ void advance(const ItemRanges &rg, int step) {
-        t += step;
-        if (t >= ce) {
-            o = rg.first_nonempty(o + 1);
-            if (o < rg.nr) {
-                t = rg.begin(o);
-                ce = rg.end(o);
-            }
-        }
-    }
+// The candidates of a work item as one list: its ranges in order, packed
+// (a 16-candidate tile may span the end of one range and the start of the
+// next; only the item's last tile can be partial). Lane l of chunk c holds
+// the sorted index at list position 64c + l, so tile k (positions 16k ..
+// 16k + 15) is lanes 16 (k % 4) .. + 15 of chunk k / 4. Chunks are built in
+// increasing order from the ranges' first list positions.
+struct CandTable {
+    int cp;      // lane o < nr: first list position of range o
+    int total;   // candidates of the item (wave-uniform)
+    int ntiles;  // ceil(total / 16)
+    int ocur;    // last range starting at or before the current chunk
+    int chunk;   // chunk held in `cand` (-1: none)
+    int cand;    // lane l: sorted index at position 64 * chunk + l
+    int fill;    // a valid sorted index (< n) for positions past the end
 };
+
+__device__ __forceinline__ void cand_init(CandTable &T, const ItemRanges &rg, int lane, int fill) {
+    int len = 0;
+    if (lane < rg.nr) len = max(0, rg.re - rg.rb);
+    int incl = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    T.cp = incl - len;
+    T.total = __builtin_amdgcn_readlane(incl, 63);
+    T.ntiles = (T.total + 15) >> 4;
+    T.ocur = 0;
+    T.chunk = -1;
+    T.cand = fill;
+    T.fill = fill;
+}
+
+// Builds chunk c (c >= the chunk held).
+__device__ __forceinline__ void cand_chunk(CandTable &T, const ItemRanges &rg, int c, int lane) {
+    const int base = 64 * c, P = base + lane;
+    while (T.ocur + 1 < rg.nr && __builtin_amdgcn_readlane(T.cp, T.ocur + 1) <= base) ++T.ocur;
+    const int cp0 = __builtin_amdgcn_readlane(T.cp, T.ocur);
+    int delta = __builtin_amdgcn_readlane(rg.rb, T.ocur) - cp0;
+    for (int o = T.ocur + 1; o < rg.nr; ++o) {
+        const int cpo = __builtin_amdgcn_readlane(T.cp, o);
+        if (cpo >= base + 64) break;
+        const int d = __builtin_amdgcn_readlane(rg.rb, o) - cpo;
+        if (P >= cpo) delta = d;
+    }
+    T.cand = P < T.total ? P + delta : T.fill;
+    T.chunk = c;
+}
+
+// Sorted index of column j of tile k for lane (g, j); valid columns: n.
+__device__ __forceinline__ int cand_of_tile(CandTable &T, const ItemRanges &rg, int k, int lane, int &n) {
+    if ((k >> 2) != T.chunk) cand_chunk(T, rg, k >> 2, lane);
+    n = min(16, T.total - 16 * k);
+    return __shfl(T.cand, ((k & 3) << 4) | (lane & 15));
+}
 
 // Wave-local LDS ordering (stores by some lanes, loads by others).
 __device__ __forceinline__ void wave_lds_sync() {
@@ -226,9 +256,10 @@ __device__ __forceinline__ void ring_drain(EmitRing &rb, bool all, const DevGrid
 
 // Direct emission of one 16 x 16 tile from its mask words (canonical
 // layout, already restricted to the queries this launch emits): lane (g, j)
-// writes pair (query g + 4r, candidate t + j) for each r whose bit it holds,
-// at the query's base + pairs so far + the pair's rank among the set bits
-// of its 16-bit group. `pc` = input index of candidate t + j.
+// writes pair (query g + 4r, candidate of column j) for each r whose bit it
+// holds, at the query's base + pairs so far + the pair's rank among the set
+// bits of its 16-bit group. `c` / `pc` = sorted / input index of the lane's
+// candidate.
 struct RowOut {
     int64_t qb[4];  // output row of the first pair of query g + 4r (this launch)
     int32_t pq[4];  // input index of query g + 4r
@@ -248,7 +279,7 @@ __device__ __forceinline__ void row_out_init(RowOut &ro, const bool emit_r[4], c
     ro.jlt = (1u << j) - 1u;
 }
 
-__device__ __forceinline__ void tile_store(const unsigned long long w[4], int t, int32_t pc, RowOut &ro, int g,
+__device__ __forceinline__ void tile_store(const unsigned long long w[4], int c, int32_t pc, RowOut &ro, int g,
                                            int j, const DevGrid &G, const RefOut &R, int q0) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -259,7 +290,7 @@ __device__ __forceinline__ void tile_store(const unsigned long long w[4], int t,
             const int64_t pos = ro.qb[r] + (ro.cur[r] + __popc(ch & ro.jlt));
             reinterpret_cast<int2 *>(R.pairs)[pos] = make_int2(ro.pq[r], pc);
             if (R.d2)
-                R.d2[pos] = exact_d2(G.xs + (int64_t)(q0 + g + 4 * r) * G.dp, G.xs + (int64_t)(t + j) * G.dp, G.d);
+                R.d2[pos] = exact_d2(G.xs + (int64_t)(q0 + g + 4 * r) * G.dp, G.xs + (int64_t)c * G.dp, G.d);
         }
         ro.cur[r] += __popc(ch);
     }
@@ -299,40 +330,42 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
 #pragma unroll
     for (int jq = 0; jq < kTileQ; ++jq) cnt[jq] = 0;
 
-    // in-mask recording (count): 16-candidate tile numbering of the item
+    // 64 candidates of the item's list per step (one chunk); in-mask
+    // recording numbers the 16-candidate tiles of that list
     const bool rec = MODE == MODE_COUNT && R.masks != nullptr;
     const int64_t tile_base = rec ? G.tile_off[it] : 0;
-    int kb = 0;  // tiles of the ranges before the current one
-    TileCursor tc;
-    tc.first(rg);
-    int cur_o = tc.o, cur_cb = tc.t;
+    CandTable CT;
+    cand_init(CT, rg, lane, q0);
+    const int nchunks = (CT.total + 63) >> 6;
     double xn[D > 0 ? D : 1];
-    if (D > 0 && tc.live(rg)) {
-        const double *xc = xs + (int64_t)(tc.t + lane) * dp;  // rows are padded past n
+    int cn = q0;
+    if (nchunks > 0) {
+        cand_chunk(CT, rg, 0, lane);
+        cn = CT.cand;
+        if (D > 0) {
+            const double *xc = xs + (int64_t)cn * dp;
 #pragma unroll
-        for (int u = 0; u < (D > 0 ? D : 1); ++u) xn[u] = xc[u];
-    }
-    while (tc.live(rg)) {
-        const int t = tc.t, ce = tc.ce;
-        if (rec && tc.o != cur_o) {
-            kb += (rg.end(cur_o) - rg.begin(cur_o) + 15) / 16;
-            cur_o = tc.o;
-            cur_cb = tc.t;
+            for (int u = 0; u < (D > 0 ? D : 1); ++u) xn[u] = xc[u];
         }
-        const int k16 = kb + (t - cur_cb) / 16;  // first 16-tile of this 64-candidate tile
+    }
+    for (int ch = 0; ch < nchunks; ++ch) {
+        const int k16 = 4 * ch;  // first 16-tile of this chunk
         unsigned long long qm[kTileQ];
 #pragma unroll
         for (int jq = 0; jq < kTileQ; ++jq) qm[jq] = 0ull;
-        const int c = t + lane;
-        const bool valid = c < ce;
+        const int c = cn;
+        const bool valid = 64 * ch + lane < CT.total;
         double x[D > 0 ? D : 1];
 #pragma unroll
         for (int u = 0; u < (D > 0 ? D : 1); ++u) x[u] = xn[u];
-        tc.advance(rg, 64);
-        if (D > 0 && tc.live(rg)) {  // prefetch the next tile
-            const double *xc2 = xs + (int64_t)(tc.t + lane) * dp;
+        if (ch + 1 < nchunks) {  // the next chunk and its rows
+            cand_chunk(CT, rg, ch + 1, lane);
+            cn = CT.cand;
+            if (D > 0) {
+                const double *xc2 = xs + (int64_t)cn * dp;
 #pragma unroll
-            for (int u = 0; u < (D > 0 ? D : 1); ++u) xn[u] = xc2[u];
+                for (int u = 0; u < (D > 0 ? D : 1); ++u) xn[u] = xc2[u];
+            }
         }
         const double *__restrict__ xc = xs + (int64_t)c * dp;
 #pragma unroll
@@ -380,7 +413,7 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
             // four 16-candidate tiles: word r of sub-tile s collects the
             // 16-bit slices of queries 4r .. 4r + 3 (query g + 4r at bits
             // 16g); lane 4s + r stores it (the 16 words are contiguous)
-            const int nsub = (min(64, ce - t) + 15) / 16;
+            const int nsub = (min(64, CT.total - 64 * ch) + 15) / 16;
             unsigned long long wl = 0;
 #pragma unroll
             for (int sub = 0; sub < 4; ++sub) {
@@ -427,107 +460,45 @@ __global__ __launch_bounds__(kThreads) void k_v64(DevGrid G, RefOut R) {
 //    item), D = |q|^2 - 2 q.c, and the candidate norm moves to a per-column
 //    threshold: in iff D <= eps^2 - |c|^2.
 // KS = K-steps of 4 dimensions (0 = runtime).
-// The 16-candidate tiles of a work item, in order (its ranges in order,
-// ceil(len / 16) tiles each), as a table in registers: lane l holds the first
-// candidate and the number of valid columns of tile 64c + l (chunk c). Tile
-// loops then read a tile's bounds with two v_readlane instead of walking the
-// ranges with scalar code.
-struct TileTable {
-    int tp;      // lane o < nr: first tile of range o
-    int ntiles;  // tiles of the item (wave-uniform)
-    int tt, tn;  // lane l: first candidate / valid columns of tile 64 * chunk + l
-    int chunk;   // chunk held in tt / tn (-1: none)
-};
-
-__device__ __forceinline__ void tile_table_init(TileTable &T, const ItemRanges &rg, int lane) {
-    int cnt = 0;
-    if (lane < rg.nr) {
-        const int len = rg.re - rg.rb;
-        cnt = len > 0 ? (len + 15) >> 4 : 0;
-    }
-    int incl = cnt;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(incl, o);
-        if (lane >= o) incl += y;
-    }
-    T.tp = incl - cnt;
-    T.ntiles = __builtin_amdgcn_readlane(incl, 63);
-    T.tt = T.tn = 0;
-    T.chunk = -1;
-}
-
-__device__ __forceinline__ void tile_table_chunk(TileTable &T, const ItemRanges &rg, int c, int lane) {
-    const int K = 64 * c + lane;
-    int oo = 0;  // last range whose first tile is <= K (empty ranges share it)
-    for (int o = 1; o < rg.nr; ++o)
-        if (K >= __builtin_amdgcn_readlane(T.tp, o)) oo = o;
-    const int b = __shfl(rg.rb, oo), e = __shfl(rg.re, oo), p = __shfl(T.tp, oo);
-    int t = b + 16 * (K - p);
-    int n = min(16, e - t);
-    if (K >= T.ntiles) t = n = 0;
-    T.tt = t;
-    T.tn = n;
-    T.chunk = c;
-}
-
-// Tile k of the item: first candidate and valid columns (wave-uniform).
-__device__ __forceinline__ void tile_at(TileTable &T, const ItemRanges &rg, int k, int lane, int &t, int &n) {
-    if ((k >> 6) != T.chunk) tile_table_chunk(T, rg, k >> 6, lane);
-    t = __builtin_amdgcn_readlane(T.tt, k & 63);
-    n = __builtin_amdgcn_readlane(T.tn, k & 63);
-}
-
 template <int KS>
 struct M64Tile {
     double b[KS > 0 ? KS : 1];
     double nc;   // candidate norm (no-slot form)
-    int32_t pc;  // emit: input index of candidate t + j
-    int t, n;    // first candidate, valid columns
+    int32_t c;   // sorted index of the lane's column (a valid row past the end)
+    int32_t pc;  // emit: input index of that candidate
+    int n;       // valid columns (wave-uniform)
 };
 
-// Issues the loads of tile (t, n); nothing here waits for them.
+// Issues the loads of tile k; nothing here waits for them.
 template <int KS, bool SLOT, int MODE>
-__device__ __forceinline__ void m64_load(M64Tile<KS> &T, const DevGrid &G, int t, int n, unsigned boff, int j) {
-    // rows up to t + 15 < n + 64 exist (padded). The tile's base address is
-    // wave-uniform; the lane part (j * da + g doubles) is a fixed offset.
-    T.t = t;
-    T.n = n;
+__device__ __forceinline__ void m64_load(M64Tile<KS> &T, CandTable &CT, const ItemRanges &rg, int k, int lane,
+                                         const DevGrid &G, int g) {
+    T.c = cand_of_tile(CT, rg, k, lane, T.n);
     if (KS > 0) {
-        const char *__restrict__ base = reinterpret_cast<const char *>(G.xa + (int64_t)t * G.da);
+        const double *__restrict__ brow = G.xa + (int64_t)T.c * G.da + g;
 #pragma unroll
-        for (int s = 0; s < (KS > 0 ? KS : 1); ++s)
-            T.b[s] = *reinterpret_cast<const double *>(base + boff + 32u * (unsigned)s);
+        for (int s = 0; s < (KS > 0 ? KS : 1); ++s) T.b[s] = brow[4 * s];
     }
-    T.nc = SLOT ? 0.0 : (G.nrm + t)[j];
-    if (MODE == MODE_EMIT) T.pc = G.perm[t + min(j, n - 1)];  // n >= 1
+    T.nc = SLOT ? 0.0 : G.nrm[T.c];
+    if (MODE == MODE_EMIT) T.pc = G.perm[T.c];
 }
 
-// Columns j >= n (past the range) must fail every test: SLOT puts +inf into
-// the norm slot (the value becomes +inf), no-slot sets the column threshold
-// to -inf (m64_colthr).
 template <int KS, bool SLOT>
 __device__ __forceinline__ double4_t m64_tile(const M64Tile<KS> &T, const DevGrid &G, const double *aq,
-                                              double4_t cinit, int j, int g, int qa, bool slot_lane) {
+                                              double4_t cinit, int g, int qa) {
     double4_t acc = cinit;
     if (KS > 0) {
 #pragma unroll
-        for (int s = 0; s < (KS > 0 ? KS : 1); ++s) {
-            double bv = T.b[s];
-            if (SLOT && s == (KS > 0 ? KS : 1) - 1 && slot_lane && j >= T.n) bv = INFINITY;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], bv, acc, 0, 0, 0);
-        }
+        for (int s = 0; s < (KS > 0 ? KS : 1); ++s)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], T.b[s], acc, 0, 0, 0);
     } else {
         const int d = G.d, da = G.da, ks = da >> 2;
-        const double *__restrict__ brow = G.xa + (int64_t)(T.t + j) * da + g;
+        const double *__restrict__ brow = G.xa + (int64_t)T.c * da + g;
         const double *__restrict__ arow = G.xa + (int64_t)qa * da;
-        const bool colok = j < T.n;
         for (int s = 0; s < ks; ++s) {
             const int kk = 4 * s + g;
             const double a = kk < d ? -2.0 * arow[kk] : ((SLOT && kk == d) ? 1.0 : 0.0);
-            double bv = brow[4 * s];
-            if (SLOT && kk == d && !colok) bv = INFINITY;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, brow[4 * s], acc, 0, 0, 0);
         }
     }
     return acc;
@@ -535,104 +506,107 @@ __device__ __forceinline__ double4_t m64_tile(const M64Tile<KS> &T, const DevGri
 
 // Per-lane classification state.
 struct M64Thr {
-    double mid[4];        // SLOT: threshold of row r, eps^2 - |q|^2 (-inf for absent rows)
-    double lo[4], hi[4];  // SLOT: mid -/+ Delta (error measurement)
-    double ecol;          // no slot: eps^2 for the column threshold
-    double nq[4];         // |q|^2 of row r (for the error measurement)
+    double lo[4], hi[4];  // SLOT: threshold of row r -/+ Delta (-inf for absent rows)
+    double clo, chi;      // no slot: eps^2 -/+ Delta (the column norm is subtracted per tile)
+    double nq[4];         // |q|^2 of row r (error measurement)
 };
 
-// Returns the in-mask (bit r = row g + 4r) after the exact recheck of band
-// elements. Columns past the range end are masked here.
-template <bool SLOT, int MODE>
-__device__ __forceinline__ unsigned m64_classify(double4_t acc, double nc, int t, int ce, int g, int j, int q0,
-                                                 const M64Thr &th, double delta, const DevGrid &G,
-                                                 unsigned long long &band, unsigned long long &viol,
-                                                 double &maxerr) {
-    double v0 = acc[0], v1 = acc[1], v2 = acc[2], v3 = acc[3];
-    const bool colok = j < ce - t;
-    double l0, l1, l2, l3, h0, h1, h2, h3;
-    if (SLOT) {
-        l0 = th.lo[0]; l1 = th.lo[1]; l2 = th.lo[2]; l3 = th.lo[3];
-        h0 = th.hi[0]; h1 = th.hi[1]; h2 = th.hi[2]; h3 = th.hi[3];
-        if (!colok) v0 = v1 = v2 = v3 = INFINITY;
-    } else {
-        const double tc = th.ecol - nc;
-        const double lc = colok ? tc - delta : -INFINITY;
-        const double hc = colok ? tc + delta : -INFINITY;
-        l0 = l1 = l2 = l3 = lc;
-        h0 = h1 = h2 = h3 = hc;
-    }
-    const bool i0 = v0 <= l0, i1 = v1 <= l1, i2 = v2 <= l2, i3 = v3 <= l3;
-    const bool m0 = v0 <= h0, m1 = v1 <= h1, m2 = v2 <= h2, m3 = v3 <= h3;
-    unsigned inm = (unsigned)i0 | ((unsigned)i1 << 1) | ((unsigned)i2 << 2) | ((unsigned)i3 << 3);
-    if (MODE == MODE_MEASURE) {
-        const double vv[4] = {v0, v1, v2, v3};
-        const double hh[4] = {h0, h1, h2, h3};
-        for (int r = 0; r < 4; ++r) {
-            if (vv[r] < INFINITY && hh[r] > -INFINITY) {
-                const int q = q0 + g + 4 * r;
-                const double ex = exact_d2(G.xs + (int64_t)q * G.dp, G.xs + (int64_t)(t + j) * G.dp, G.d);
-                if (ex <= 4.0 * G.eps2) {
-                    const double err = fabs(vv[r] - (ex - (SLOT ? th.nq[r] : nc)));
-                    maxerr = fmax(maxerr, err);
-                    if (err > delta) ++viol;
-                }
-            }
+// Columns [0, n) of each 16-lane group.
+__device__ __forceinline__ unsigned long long col_mask(int n) {
+    if (n >= 16) return ~0ull;
+    return ((1ull << n) - 1ull) * 0x0001000100010001ull;
+}
+
+// Error measurement: for every value whose exact distance is within 2 eps,
+// the difference between the Gram value and the exact value (on the same
+// side of the threshold equation), its maximum and the count above Delta.
+template <bool SLOT, int KS>
+__device__ __forceinline__ void m64_measure(double4_t acc, const M64Tile<KS> &T, int g, int j, int q0,
+                                            const M64Thr &th, double delta, const DevGrid &G,
+                                            unsigned long long &viol, double &maxerr) {
+    if (j >= T.n) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (th.hi[r] == -INFINITY && SLOT) continue;  // absent row
+        if (!SLOT && acc[r] == INFINITY) continue;      // absent row
+        const int q = q0 + g + 4 * r;
+        const double ex = exact_d2(G.xs + (int64_t)q * G.dp, G.xs + (int64_t)T.c * G.dp, G.d);
+        if (ex <= 4.0 * G.eps2) {
+            const double err = fabs(acc[r] - (ex - (SLOT ? th.nq[r] : T.nc)));
+            maxerr = fmax(maxerr, err);
+            if (err > delta) ++viol;
         }
     }
-    const bool anyband = (m0 != i0) | (m1 != i1) | (m2 != i2) | (m3 != i3);
-    if (__builtin_expect(__any(anyband), 0)) {
-        // rare: exact FP64 chain on the original coordinates
-        const unsigned mbm = (unsigned)m0 | ((unsigned)m1 << 1) | ((unsigned)m2 << 2) | ((unsigned)m3 << 3);
-        const unsigned bm = mbm & ~inm;
-        for (int r = 0; r < 4; ++r) {
-            if (bm & (1u << r)) {
-                const int q = q0 + g + 4 * r;
-                const double ex = exact_d2(G.xs + (int64_t)q * G.dp, G.xs + (int64_t)(t + j) * G.dp, G.d);
-                if (ex <= G.eps2) inm |= 1u << r;
-                ++band;
-            }
-        }
-    }
-    return inm;
 }
 
 // Count / emit classification on wave-wide compare masks: word r, bit
-// 16g + j = (query g + 4r, candidate t + j) is within eps. A value at most
-// Delta away from its threshold is decided by the exact FP64 chain; the rest
-// by the threshold. `band` (wave-uniform) counts the rechecks.
-template <int KS>
-__device__ __forceinline__ double m64_colthr(const M64Tile<KS> &T, int j, double eps2) {
-    return j < T.n ? eps2 - T.nc : -INFINITY;
-}
-
-template <bool SLOT>
-__device__ __forceinline__ void m64_words(double4_t acc, double thr_col, int t, int g, int j, int q0,
-                                          const M64Thr &th, double delta, const DevGrid &G,
-                                          unsigned long long &band, unsigned long long w[4]) {
-    double thr[4];
+// 16g + j = (query g + 4r, candidate of column j) is within eps. Values at
+// or below threshold - Delta are in, above threshold + Delta out; the rest
+// are decided by the exact FP64 chain. `band` (wave-uniform) counts them.
+template <bool SLOT, int KS>
+__device__ __forceinline__ void m64_words(double4_t acc, const M64Tile<KS> &T, int g, int q0, const M64Thr &th,
+                                          const DevGrid &G, unsigned long long &band, unsigned long long w[4]) {
+    double lo[4], hi[4];
+    if (SLOT) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) thr[r] = SLOT ? th.mid[r] : thr_col;
+        for (int r = 0; r < 4; ++r) {
+            lo[r] = th.lo[r];
+            hi[r] = th.hi[r];
+        }
+    } else {
+        const double l = th.clo - T.nc, h = th.chi - T.nc;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) w[r] = __ballot(acc[r] <= thr[r]);
-    const double u = fmin(fmin(fabs(acc[0] - thr[0]), fabs(acc[1] - thr[1])),
-                          fmin(fabs(acc[2] - thr[2]), fabs(acc[3] - thr[3])));
-    if (__builtin_expect(__ballot(u <= delta) != 0ull, 0)) {
+        for (int r = 0; r < 4; ++r) {
+            lo[r] = l;
+            hi[r] = h;
+        }
+    }
+    unsigned long long m[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        w[r] = __ballot(acc[r] <= lo[r]);
+        m[r] = __ballot(acc[r] <= hi[r]);
+    }
+    if (T.n < 16) {  // the item's last tile: columns past the end
+        const unsigned long long cm = col_mask(T.n);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            w[r] &= cm;
+            m[r] &= cm;
+        }
+    }
+    if (__builtin_expect(((m[0] ^ w[0]) | (m[1] ^ w[1]) | (m[2] ^ w[2]) | (m[3] ^ w[3])) != 0ull, 0)) {
         // rare: exact FP64 chain on the original coordinates
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const bool bl = fabs(acc[r] - thr[r]) <= delta;
-            const unsigned long long bm = __ballot(bl);
+            const unsigned long long bm = m[r] & ~w[r];
             if (!bm) continue;
             bool ok = false;
-            if (bl) {
+            if (__builtin_amdgcn_inverse_ballot_w64(bm)) {
                 const int q = q0 + g + 4 * r;
-                ok = exact_d2(G.xs + (int64_t)q * G.dp, G.xs + (int64_t)(t + j) * G.dp, G.d) <= G.eps2;
+                ok = exact_d2(G.xs + (int64_t)q * G.dp, G.xs + (int64_t)T.c * G.dp, G.d) <= G.eps2;
             }
-            w[r] = (w[r] & ~bm) | __ballot(ok);
+            w[r] |= __ballot(ok);
             band += (unsigned long long)__popcll(bm);
         }
     }
+}
+
+// Per-query counts of 16 tiles from their mask words gathered in (mhi, mlo):
+// lane 4s + r holds word r of tile s; adds the pairs of query g + 4r to
+// tot[g] of lane r (lanes 0..3).
+__device__ __forceinline__ void count_words(unsigned mlo, unsigned mhi, int tot[4]) {
+    unsigned p01 = __popc(mlo & 0xffffu) | (__popc(mlo >> 16) << 16);
+    unsigned p23 = __popc(mhi & 0xffffu) | (__popc(mhi >> 16) << 16);
+#pragma unroll
+    for (int o = 4; o < 64; o <<= 1) {
+        p01 += __shfl_xor(p01, o);
+        p23 += __shfl_xor(p23, o);
+    }
+    tot[0] += (int)(p01 & 0xffffu);
+    tot[1] += (int)(p01 >> 16);
+    tot[2] += (int)(p23 & 0xffffu);
+    tot[3] += (int)(p23 >> 16);
 }
 
 template <int KS, bool SLOT, int MODE>
@@ -642,13 +616,11 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
     const int q0 = uniform_i32(I.qbegin);
     const int nq = uniform_i32(I.qend - I.qbegin);
     const int d = G.d, da = G.da;
-    const int j = lane & 15;   // A row (query j) / result column (candidate t + j)
+    const int j = lane & 15;   // A row (query j) / result column (candidate of column j)
     const int g = lane >> 4;   // K index of the operands; row group of the result
     const int qa = q0 + (j < nq ? j : 0);
     const double *__restrict__ xa = G.xa;
     const ItemRanges rg = load_ranges(G, it, lane);
-    const unsigned boff = (unsigned)(j * da + g) * 8u;  // lane's B element within a tile
-    const bool slot_lane = SLOT && g == (d & 3);         // lane holding the norm slot's K index
     const double eps2 = G.eps2;
 
     // A operand (16 x K): A[i][k] = -2 q_i[k] for k < d, 1 in the norm slot.
@@ -671,85 +643,75 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
         const double nq_r = ok ? G.nrm[q0 + i] : 0.0;
         th.nq[r] = nq_r;
         const double thr = eps2 - nq_r;
-        th.mid[r] = ok ? thr : -INFINITY;
         th.lo[r] = ok ? thr - delta : -INFINITY;
         th.hi[r] = ok ? thr + delta : -INFINITY;
         if (!SLOT) cinit[r] = ok ? nq_r : INFINITY;
         emit_r[r] = MODE == MODE_EMIT && ok && q0 + i >= R.qlo && q0 + i < R.qhi;
     }
-    th.ecol = eps2;
+    th.clo = eps2 - delta;
+    th.chi = eps2 + delta;
     unsigned long long ebal[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) ebal[r] = __ballot(emit_r[r]);
     RowOut ro;
     if (MODE == MODE_EMIT) row_out_init(ro, emit_r, G, R, q0, g, j);
-    int cnt[4] = {0, 0, 0, 0};  // in-pairs of row g + 4r in this lane's column
-    unsigned long long band = 0, viol = 0;  // band: wave-uniform in count / emit
+    int tot[4] = {0, 0, 0, 0};  // count: lanes 0..3 (r = lane), pairs of query g + 4r
+    unsigned long long band = 0, viol = 0;  // band: wave-uniform
     double maxerr = 0.0;
 
-    // in-mask recording (count): the words of 16 consecutive tiles gather in
-    // one register pair (lane 4s + r = word r of tile s of the group) and
-    // leave in one coalesced store
+    // count: the words of 16 consecutive tiles gather in one register pair
+    // (lane 4s + r = word r of tile s); the per-query counts are taken from
+    // it, and with recording on it leaves in one coalesced store
     const bool rec = MODE == MODE_COUNT && R.masks != nullptr;
     const int64_t tile_base = rec ? G.tile_off[it] : 0;
     unsigned mlo = 0, mhi = 0;
-    auto consume = [&](const unsigned long long w[4], int k, int t, int32_t pc) {
-        if (MODE == MODE_EMIT) {
-            unsigned long long bal[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) bal[r] = w[r] & ebal[r];
-            tile_store(bal, t, pc, ro, g, j, G, R, q0);
-        } else {
-            if ((w[0] | w[1] | w[2] | w[3]) != 0ull) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) cnt[r] += __builtin_amdgcn_inverse_ballot_w64(w[r]) ? 1 : 0;
-                if (rec) {
-                    const int sl = 4 * (k & 15);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        mlo = amdgcn_writelane((int)(unsigned)w[r], sl + r, (int)mlo);
-                        mhi = amdgcn_writelane((int)(unsigned)(w[r] >> 32), sl + r, (int)mhi);
-                    }
-                }
-            }
-            if (rec && (k & 15) == 15) {
-                R.masks[(tile_base + k - 15) * 4 + lane] = ((unsigned long long)mhi << 32) | mlo;
-                mlo = mhi = 0;
-            }
-        }
-    };
-
-    TileTable TT;
-    tile_table_init(TT, rg, lane);
-    const int ntiles = TT.ntiles;
-    auto load = [&](M64Tile<KS> &T, int k) {
-        int tt, tn;
-        tile_at(TT, rg, k, lane, tt, tn);
-        m64_load<KS, SLOT, MODE>(T, G, tt, tn, boff, j);
+    CandTable CT;
+    cand_init(CT, rg, lane, q0);
+    const int ntiles = CT.ntiles;
+    auto flush = [&](int k0) {  // tiles k0 .. k0 + 15 (those that exist)
+        count_words(mlo, mhi, tot);
+        if (rec && lane < 4 * min(16, ntiles - k0))
+            R.masks[(tile_base + k0) * 4 + lane] = ((unsigned long long)mhi << 32) | mlo;
+        mlo = mhi = 0;
     };
     auto classify = [&](const double4_t &acc, const M64Tile<KS> &T, int k) {
         if (MODE == MODE_MEASURE) {
-            (void)m64_classify<SLOT, MODE>(acc, T.nc, T.t, T.t + T.n, g, j, q0, th, delta, G, band, viol, maxerr);
+            m64_measure<SLOT, KS>(acc, T, g, j, q0, th, delta, G, viol, maxerr);
+            return;
+        }
+        unsigned long long w[4];
+        m64_words<SLOT, KS>(acc, T, g, q0, th, G, band, w);
+        if (MODE == MODE_EMIT) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) w[r] &= ebal[r];
+            tile_store(w, T.c, T.pc, ro, g, j, G, R, q0);
         } else {
-            unsigned long long w[4];
-            m64_words<SLOT>(acc, SLOT ? 0.0 : m64_colthr(T, j, eps2), T.t, g, j, q0, th, delta, G, band, w);
-            consume(w, k, T.t, T.pc);
+            if ((w[0] | w[1] | w[2] | w[3]) != 0ull) {
+                const int sl = 4 * (k & 15);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    mlo = amdgcn_writelane((int)(unsigned)w[r], sl + r, (int)mlo);
+                    mhi = amdgcn_writelane((int)(unsigned)(w[r] >> 32), sl + r, (int)mhi);
+                }
+            }
+            if ((k & 15) == 15) flush(k - 15);
         }
     };
+    auto load = [&](M64Tile<KS> &T, int k) { m64_load<KS, SLOT, MODE>(T, CT, rg, k, lane, G, g); };
     // both products first, then both classifications
     auto run = [&](const M64Tile<KS> &TA, const M64Tile<KS> &TB, int k) {
         const bool h1 = k + 1 < ntiles;
-        const double4_t a0 = m64_tile<KS, SLOT>(TA, G, aq, cinit, j, g, qa, slot_lane);
+        const double4_t a0 = m64_tile<KS, SLOT>(TA, G, aq, cinit, g, qa);
         double4_t a1;
-        if (h1) a1 = m64_tile<KS, SLOT>(TB, G, aq, cinit, j, g, qa, slot_lane);
+        if (h1) a1 = m64_tile<KS, SLOT>(TB, G, aq, cinit, g, qa);
         classify(a0, TA, k);
         if (h1) classify(a1, TB, k + 1);
     };
     // Four tile buffers, two stages per iteration: a stage runs two tiles
     // while the next two load into the other pair of buffers (fixed roles, so
-    // no register copies wait on loads in flight).
-    // Loads past the last tile repeat the last tile (same instruction count
-    // on every path, so each wait covers exactly the older tiles).
+    // no register copies wait on loads in flight). Loads past the last tile
+    // repeat the last tile (same instruction count on every path, so each
+    // wait covers exactly the older tiles).
     M64Tile<KS> T0, T1, T2, T3;
     const int klast = ntiles - 1;
     if (ntiles > 0) {
@@ -766,16 +728,11 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
         run(T2, T3, k + 2);
     }
     if (MODE == MODE_COUNT) {
-        if (rec && (ntiles & 15) != 0 && lane < 4 * (ntiles & 15))
-            R.masks[(tile_base + (ntiles & ~15)) * 4 + lane] = ((unsigned long long)mhi << 32) | mlo;
+        if (ntiles & 15) flush(ntiles & ~15);
+        if (lane < 4) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int v = cnt[r];
-            v += __shfl_xor(v, 1);
-            v += __shfl_xor(v, 2);
-            v += __shfl_xor(v, 4);
-            v += __shfl_xor(v, 8);
-            if (j == 0 && g + 4 * r < nq) R.cnt[q0 + g + 4 * r] = v;
+            for (int gg = 0; gg < 4; ++gg)
+                if (gg + 4 * lane < nq) R.cnt[q0 + gg + 4 * lane] = tot[gg];
         }
         if (lane == 0 && band) atomicAdd(R.band, band);
     }
@@ -804,32 +761,40 @@ __global__ __launch_bounds__(kThreads) void k_m64(DevGrid G, RefOut R, double de
 // FP64 MFMA: both record the same canonical masks): per 16 x 16 tile of an
 // item, word r, bit 16g + j says whether query g + 4r is within eps of
 // candidate j. This pass evaluates no distance; it expands the masks into
-// pairs at the exact offsets of the count, through the same LDS ring.
+// pairs at the exact offsets of the count (tile_store).
 //
 // The masks of 16 consecutive tiles arrive in one coalesced vector load (lane
 // l holds word l % 4 of tile l / 4), the next 16 are loaded while these are
-// expanded, and all-zero tiles are skipped without touching the ring.
-
-// Moves the cursor forward by n >= 0 tiles of 16 candidates.
-__device__ __forceinline__ void skip_tiles(TileCursor &tc, const ItemRanges &rg, int n) {
-    while (n > 0) {
-        const int rem = (tc.ce - tc.t + 15) >> 4;  // tiles left in this range, current included
-        if (n < rem) {
-            tc.t += 16 * n;
-            return;
-        }
-        n -= rem;
-        tc.o = rg.first_nonempty(tc.o + 1);
-        if (tc.o >= rg.nr) return;
-        tc.t = rg.begin(tc.o);
-        tc.ce = rg.end(tc.o);
-    }
-}
+// expanded, and tiles with no pair to write are skipped.
 
 __device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int lane) {
     const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
     const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
     return ((unsigned long long)hi << 32) | lo;
+}
+
+// Tiles are taken 16 at a time (a batch). The batch's mask words arrive in
+// one vector load (lane 4s + r = word r of tile s) and the input indices of
+// its candidates in four (load q = chunk b / 4 + q of the candidate list:
+// lane 16s + j = column j of tile b + 4q + s), all issued one batch ahead.
+struct MaskBatch {
+    unsigned long long w;
+    int32_t pc[4];  // input index of the candidate
+    int32_t c[4];   // sorted index of the candidate
+};
+
+__device__ __forceinline__ void mask_batch_load(MaskBatch &B, CandTable &CT, const ItemRanges &rg,
+                                                const unsigned long long *mb, const DevGrid &G, int b, int lane) {
+    const int nwords = 4 * CT.ntiles;
+    const int idx = 4 * b + lane;
+    B.w = idx < nwords ? mb[idx] : 0ull;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int c = (b >> 2) + q;
+        if (c != CT.chunk) cand_chunk(CT, rg, c, lane);
+        B.c[q] = CT.cand;
+        B.pc[q] = G.perm[CT.cand];
+    }
 }
 
 __device__ __forceinline__ void mask_item(const DevGrid &G, const RefOut &R, const unsigned long long *masks,
@@ -852,48 +817,29 @@ __device__ __forceinline__ void mask_item(const DevGrid &G, const RefOut &R, con
     for (int r = 0; r < 4; ++r) ebal[r] = __ballot(emit_r[r]);
     RowOut ro;
     row_out_init(ro, emit_r, G, R, q0, g, j);
-    const int64_t tile_base = G.tile_off[it];
-    const int ntiles = uniform_i32((int)(G.tile_off[it + 1] - tile_base));
-    const int nwords = 4 * ntiles;
-    const unsigned long long *mb = masks + tile_base * 4;
-    unsigned long long wnext = lane < nwords ? mb[lane] : 0ull;
-    TileCursor tc;
-    tc.first(rg);
-    int at = 0;  // tile the cursor points at
-    // one tile in hand: its candidates' input indices load while the next
-    // non-empty tile is found
-    bool hp = false;
-    int tp = 0;
-    int32_t pcp = 0;
-    unsigned long long wp[4] = {0ull, 0ull, 0ull, 0ull};
+    CandTable CT;
+    cand_init(CT, rg, lane, q0);
+    const int ntiles = CT.ntiles;
+    const unsigned long long *mb = masks + G.tile_off[it] * 4;
+    MaskBatch nxt;
+    if (ntiles > 0) mask_batch_load(nxt, CT, rg, mb, G, 0, lane);
     for (int b = 0; b < ntiles; b += 16) {
-        const unsigned long long w = wnext;
-        if (b + 16 < ntiles) {
-            const int idx = 4 * (b + 16) + lane;
-            wnext = idx < nwords ? mb[idx] : 0ull;
-        }
-        unsigned long long nz = __ballot(w != 0ull);
+        const MaskBatch cur = nxt;
+        if (b + 16 < ntiles) mask_batch_load(nxt, CT, rg, mb, G, b + 16, lane);
+        unsigned long long nz = __ballot(cur.w != 0ull);
         while (nz) {
             const int k = uniform_i32(__builtin_ctzll(nz) >> 2);
             nz &= ~(0xfull << (4 * k));
             unsigned long long wk[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) wk[r] = readlane_u64(w, 4 * k + r) & ebal[r];
+            for (int r = 0; r < 4; ++r) wk[r] = readlane_u64(cur.w, 4 * k + r) & ebal[r];
             if (!(wk[0] | wk[1] | wk[2] | wk[3])) continue;
-            skip_tiles(tc, rg, b + k - at);
-            at = b + k;
-            const int t = tc.t;
-            int32_t pck = 0;
-            if (t + j < tc.ce) pck = G.perm[t + j];
-            if (hp) tile_store(wp, tp, pcp, ro, g, j, G, R, q0);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) wp[r] = wk[r];
-            tp = t;
-            pcp = pck;
-            hp = true;
+            const int q = k >> 2, src = ((k & 3) << 4) | j;
+            const int32_t pcq = q < 2 ? (q == 0 ? cur.pc[0] : cur.pc[1]) : (q == 2 ? cur.pc[2] : cur.pc[3]);
+            const int32_t cq = q < 2 ? (q == 0 ? cur.c[0] : cur.c[1]) : (q == 2 ? cur.c[2] : cur.c[3]);
+            tile_store(wk, __shfl(cq, src), __shfl(pcq, src), ro, g, j, G, R, q0);
         }
     }
-    if (hp) tile_store(wp, tp, pcp, ro, g, j, G, R, q0);
 }
 
 __global__ __launch_bounds__(kThreads) void k_mask_emit(DevGrid G, RefOut R, const unsigned long long *masks) {
