@@ -632,9 +632,10 @@ __global__ void k_item_ranges(const Item *__restrict__ items, const int32_t *__r
     block_add(acc, cand_items);
 }
 
-// 16-candidate tiles of each work item: its candidates (the ranges in order)
-// form one packed list, so ceil(sum of range lengths / 16); entry nitems is 0
-// so that an exclusive scan ends with the total.
+// Mask slots of each work item: its candidates (the ranges in order) form one
+// packed list of ceil(sum of range lengths / 16) tiles, and its in-masks take
+// whole groups of 16 tile slots (64 words of 64 bits per group); entry nitems
+// is 0 so that an exclusive scan ends with the total.
 __global__ void k_item_tiles(const Range *__restrict__ ranges, const int32_t *__restrict__ nitems_p, int nranges,
                              int32_t *__restrict__ tiles) {
     const int64_t I = *nitems_p;
@@ -646,7 +647,8 @@ __global__ void k_item_tiles(const Range *__restrict__ ranges, const int32_t *__
             const Range r = ranges[it * nranges + o];
             c += r.end > r.begin ? r.end - r.begin : 0;
         }
-    tiles[it] = (int32_t)((c + 15) / 16);
+    const int64_t nt = (c + 15) / 16;
+    tiles[it] = (int32_t)((nt + 15) / 16 * 16);
 }
 
 __global__ void k_tiles_total(const int64_t *__restrict__ tile_off, const int32_t *__restrict__ nitems_p,

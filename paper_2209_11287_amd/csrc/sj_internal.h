@@ -123,8 +123,8 @@ struct Grid {
     int32_t *line_first = nullptr;  // first cell of each grid line (+ end marker)
     int32_t *line_table = nullptr;  // dense line key -> line id (or null when too large)
     int32_t *blocks = nullptr;      // first item of each block item (+ end sentinel)
-    int64_t *tile_off = nullptr;    // first 16-candidate tile of each item (+ total)
-    int64_t tiles = 0;              // 16-candidate tiles over all items
+    int64_t *tile_off = nullptr;    // first in-mask tile slot of each item, whole groups of 16 (+ total)
+    int64_t tiles = 0;              // in-mask tile slots over all items (32 bytes each)
     // per-tile in-masks written by the FP64 count passes (4 x 64 bits per tile:
     // word r, bit 16g + j = query g + 4r of the item, candidate j of the tile)
     unsigned long long *masks = nullptr;

@@ -3,21 +3,26 @@
 // queries of one cell share one candidate set, so a tile's queries come from
 // one run of cells).
 //
-// One wave (64 lanes) owns one work item of up to 16 queries.
+// One wave (64 lanes) owns one work item of up to 16 queries; its candidates
+// form one packed list walked in 16 x 16 tiles (rows = queries, columns =
+// candidates). Lane (g, j) holds rows g + 4r (r = 0..3) of column j.
 //
 //  V64 -- FP64 vector ALU, direct form (Eq. (1) in the order of Eq. (2)):
-//         lane = candidate, loop over the item's queries; bit-exact with the
-//         oracle's chain by construction. The paper's CUDA-core baseline role.
+//         each lane evaluates its four pairs with the oracle's chain, so the
+//         result is bit-exact by construction. The paper's CUDA-core
+//         baseline role.
 //  M64 -- FP64 MFMA, expanded form (Eq. (3), Fig. 2): one
-//         v_mfma_f64_16x16x4_f64 per K-step computes, for 16 candidates (rows)
-//         x 16 queries (columns), D' = |c|^2 - 2 c.q. The candidate norm rides
-//         in a spare K slot (or the accumulator init when d % 4 == 0); the
-//         query norm moves to the threshold side: in iff D' <= eps^2 - |q|^2.
-//         A proven error bound Delta splits each value into in / out / band;
-//         band pairs are re-evaluated with the exact FP64 chain, so the
-//         result is the exact set. Fig. 2 needs CUDA-core steps because FP64
-//         WMMA cannot feed an accumulator back; here the norms fold into the
-//         contraction and only the threshold test stays on the vector ALU.
+//         v_mfma_f64_16x16x4_f64 per K-step computes the tile's Gram part;
+//         the candidate norm rides in a spare K slot (or the query norm in the
+//         accumulator init when d % 4 == 0) and the other norm moves to the
+//         threshold side. A proven error bound Delta splits each value into
+//         in / out / band; band pairs are re-evaluated with the exact FP64
+//         chain, so the result is the exact set. Fig. 2 needs CUDA-core steps
+//         because FP64 WMMA cannot feed an accumulator back; here the norms
+//         fold into the contraction and only the threshold test stays on the
+//         vector ALU.
+// Count passes record per-tile in-masks (nibble words); the pairs pass expands
+// them (k_mask_emit) or, without masks, re-runs the tiles in emit mode.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,9 +30,6 @@
 #include <cstring>
 
 #include "sj_internal.h"
-
-// v_writelane_b32: lane `lane` of `old` takes the wave-uniform `val`.
-__device__ int amdgcn_writelane(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 
 namespace sj {
 
@@ -81,10 +83,6 @@ __device__ __forceinline__ int64_t readlane_i64(int64_t v, int lane) {
     return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-__device__ __forceinline__ unsigned long long lanemask_lt() {
-    const unsigned lane = threadIdx.x & 63u;
-    return lane ? ((~0ull) >> (64u - lane)) : 0ull;
-}
 
 // ------------------------------------------------------------ shared parts --
 // Candidate ranges of a work item: lane o (< nranges) holds range o's bounds.
@@ -113,21 +111,22 @@ __device__ __forceinline__ ItemRanges load_ranges(const DevGrid &G, int it, int 
 
 // The candidates of a work item as one list: its ranges in order, packed
 // (a 16-candidate tile may span the end of one range and the start of the
-// next; only the item's last tile can be partial). Lane l of chunk c holds
-// the sorted index at list position 64c + l, so tile k (positions 16k ..
-// 16k + 15) is lanes 16 (k % 4) .. + 15 of chunk k / 4. Chunks are built in
-// increasing order from the ranges' first list positions.
-struct CandTable {
-    int cp;      // lane o < nr: first list position of range o
-    int total;   // candidates of the item (wave-uniform)
-    int ntiles;  // ceil(total / 16)
-    int ocur;    // last range starting at or before the current chunk
-    int chunk;   // chunk held in `cand` (-1: none)
-    int cand;    // lane l: sorted index at position 64 * chunk + l
-    int fill;    // a valid sorted index (< n) for positions past the end
+// next; only the item's last tile can be partial). Tile k = list positions
+// 16k .. 16k + 15; chunk c = positions 64c .. 64c + 63 (tiles 4c .. 4c + 3).
+// A lane finds the sorted index at position P from the range holding P:
+// index = P + (begin - first position) of that range. Chunks are visited in
+// increasing order; only the ranges that start inside a chunk are read for
+// it (typically one or two), the range carried over from the previous chunk
+// covers the positions before them.
+struct CandList {
+    int cp, dlt;                  // lane o < nr: first list position of range o, begin - cp
+    unsigned long long nonempty;  // ranges with candidates (wave-uniform)
+    int total, ntiles;            // candidates, ceil(total / 16) (wave-uniform)
+    int carry;                    // begin - cp of the range holding the next chunk's start
+    int fill;                     // a valid sorted index (< n) for positions past the end
 };
 
-__device__ __forceinline__ void cand_init(CandTable &T, const ItemRanges &rg, int lane, int fill) {
+__device__ __forceinline__ void cand_init(CandList &L, const ItemRanges &rg, int lane, int fill) {
     int len = 0;
     if (lane < rg.nr) len = max(0, rg.re - rg.rb);
     int incl = len;
@@ -136,124 +135,45 @@ __device__ __forceinline__ void cand_init(CandTable &T, const ItemRanges &rg, in
         const int y = __shfl_up(incl, o);
         if (lane >= o) incl += y;
     }
-    T.cp = incl - len;
-    T.total = __builtin_amdgcn_readlane(incl, 63);
-    T.ntiles = (T.total + 15) >> 4;
-    T.ocur = 0;
-    T.chunk = -1;
-    T.cand = fill;
-    T.fill = fill;
+    L.cp = incl - len;
+    L.dlt = rg.rb - L.cp;
+    L.nonempty = __ballot(len > 0);
+    L.total = __builtin_amdgcn_readlane(incl, 63);
+    L.ntiles = (L.total + 15) >> 4;
+    L.carry = 0;
+    L.fill = fill;
 }
 
-// Builds chunk c (c >= the chunk held).
-__device__ __forceinline__ void cand_chunk(CandTable &T, const ItemRanges &rg, int c, int lane) {
-    const int base = 64 * c, P = base + lane;
-    while (T.ocur + 1 < rg.nr && __builtin_amdgcn_readlane(T.cp, T.ocur + 1) <= base) ++T.ocur;
-    const int cp0 = __builtin_amdgcn_readlane(T.cp, T.ocur);
-    int delta = __builtin_amdgcn_readlane(rg.rb, T.ocur) - cp0;
-    for (int o = T.ocur + 1; o < rg.nr; ++o) {
-        const int cpo = __builtin_amdgcn_readlane(T.cp, o);
-        if (cpo >= base + 64) break;
-        const int d = __builtin_amdgcn_readlane(rg.rb, o) - cpo;
-        if (P >= cpo) delta = d;
+// Sorted indices at positions P[0..NP) (all inside chunk c) into idx[].
+template <int NP>
+__device__ __forceinline__ void cand_chunk(CandList &L, int c, const int P[NP], int idx[NP]) {
+    const int base = 64 * c;
+    unsigned long long st = __ballot(L.cp >= base && L.cp < base + 64) & L.nonempty;
+    int dl[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) dl[p] = L.carry;
+    while (st) {
+        const int o = __builtin_ctzll(st);
+        st &= st - 1;
+        const int cpo = __builtin_amdgcn_readlane(L.cp, o);
+        const int d = __builtin_amdgcn_readlane(L.dlt, o);
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+            if (P[p] >= cpo) dl[p] = d;
+        L.carry = d;
     }
-    T.cand = P < T.total ? P + delta : T.fill;
-    T.chunk = c;
+    if (base + 64 <= L.total) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) idx[p] = P[p] + dl[p];
+    } else {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) idx[p] = P[p] < L.total ? P[p] + dl[p] : L.fill;
+    }
 }
 
-// Sorted index of column j of tile k for lane (g, j); valid columns: n.
-__device__ __forceinline__ int cand_of_tile(CandTable &T, const ItemRanges &rg, int k, int lane, int &n) {
-    if ((k >> 2) != T.chunk) cand_chunk(T, rg, k >> 2, lane);
-    n = min(16, T.total - 16 * k);
-    return __shfl(T.cand, ((k & 3) << 4) | (lane & 15));
-}
-
-// Wave-local LDS ordering (stores by some lanes, loads by others).
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Emission. Pairs go to exact offsets (prefix sums of the count pass), so a
 // query's pairs form one run in candidate order.
-//
-// V64 (lane = candidate, one query at a time): flagged pairs are compacted,
-// wave-wide, into an LDS ring (candidate, rank within its query, query
-// column); whenever 64 are queued, one full-width store writes them, instead
-// of one store per query with a few lanes active.
-constexpr int kRing = 512;  // > 63 queued + 256 from one tile
-
-struct EmitRing {
-    uint32_t *cand;  // sorted index of the candidate
-    uint32_t *rel;   // rank of the pair within its query's run
-    uint32_t *col;   // query column (0..15)
-    int head, tail;  // wave-uniform counters (entries flushed / appended)
-    // The batch taken from the ring by the previous flush: its candidates'
-    // input indices were requested then and are stored one flush later, so
-    // that gather's latency overlaps the work in between.
-    int pend_n;        // wave-uniform, 0 = none
-    int64_t pend_pos;  // output row of lane's pair
-    int32_t pend_pq;   // input index of the query
-    int32_t pend_pc;   // input index of the candidate (in flight)
-    uint32_t pend_c;   // sorted index of the candidate (distances)
-    uint32_t pend_j;   // query column (distances)
-};
-
-__device__ __forceinline__ void ring_init(EmitRing &rb, uint32_t *base) {
-    rb.cand = base;
-    rb.rel = base + kRing;
-    rb.col = base + 2 * kRing;
-    rb.head = rb.tail = 0;
-    rb.pend_n = 0;
-    rb.pend_pos = 0;
-    rb.pend_pq = rb.pend_pc = 0;
-    rb.pend_c = rb.pend_j = 0;
-}
-
-// Stores the pending batch.
-__device__ __forceinline__ void ring_store_pending(EmitRing &rb, const DevGrid &G, const RefOut &R, int lane, int q0) {
-    if (lane < rb.pend_n) {
-        reinterpret_cast<int2 *>(R.pairs)[rb.pend_pos] = make_int2(rb.pend_pq, rb.pend_pc);
-        if (R.d2)
-            R.d2[rb.pend_pos] = exact_d2(G.xs + (int64_t)(q0 + (int)rb.pend_j) * G.dp,
-                                         G.xs + (int64_t)rb.pend_c * G.dp, G.d);
-    }
-    rb.pend_n = 0;
-}
-
-// Takes `n` ring entries starting at head (n <= 64), lane l one entry:
-// stores the previous batch and leaves this one pending.
-__device__ __forceinline__ void ring_flush(EmitRing &rb, int n, const DevGrid &G, const RefOut &R, int lane,
-                                           int64_t pbase_of_lane, int32_t pq_of_lane, int q0) {
-    wave_lds_sync();
-    const int e = (rb.head + lane) & (kRing - 1);
-    const uint32_t c = rb.cand[e], rel = rb.rel[e], j = rb.col[e];
-    // the query's output base and input index live in lane j (j < 16)
-    const int64_t pb = __shfl(pbase_of_lane, (int)j);
-    const int32_t pq = __shfl(pq_of_lane, (int)j);
-    int32_t pc = 0;
-    if (lane < n) pc = G.perm[c];
-    rb.head += n;
-    wave_lds_sync();
-    ring_store_pending(rb, G, R, lane, q0);
-    rb.pend_n = n;
-    rb.pend_pos = pb + rel;
-    rb.pend_pq = pq;
-    rb.pend_pc = pc;
-    rb.pend_c = c;
-    rb.pend_j = j;
-}
-
-__device__ __forceinline__ void ring_drain(EmitRing &rb, bool all, const DevGrid &G, const RefOut &R, int lane,
-                                           int64_t pbase_of_lane, int32_t pq_of_lane, int q0) {
-    while (rb.tail - rb.head >= 64) ring_flush(rb, 64, G, R, lane, pbase_of_lane, pq_of_lane, q0);
-    if (all) {
-        if (rb.tail > rb.head) ring_flush(rb, rb.tail - rb.head, G, R, lane, pbase_of_lane, pq_of_lane, q0);
-        ring_store_pending(rb, G, R, lane, q0);
-    }
-}
-
 // Direct emission of one 16 x 16 tile from its mask words (canonical
 // layout, already restricted to the queries this launch emits): lane (g, j)
 // writes pair (query g + 4r, candidate of column j) for each r whose bit it
@@ -296,158 +216,6 @@ __device__ __forceinline__ void tile_store(const unsigned long long w[4], int c,
     }
 }
 
-// --------------------------------------------------------------------- V64 --
-// lane = candidate (64 per tile), loop over the item's queries. D > 0: the
-// candidate row is held in registers; D = 0: runtime d, read per dimension.
-template <int D, int MODE>
-__device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int it, uint32_t *ring_lds) {
-    const int lane = threadIdx.x & 63;
-    const int wv = uniform_i32(threadIdx.x >> 6);
-    const Item I = G.items[it];
-    const int q0 = uniform_i32(I.qbegin);
-    const int nq = uniform_i32(I.qend - I.qbegin);
-    const int d = D > 0 ? D : G.d;
-    const int dp = G.dp;
-    const double eps2 = G.eps2;
-    const double *__restrict__ xs = G.xs;
-    const ItemRanges rg = load_ranges(G, it, lane);
-
-    // emit state of query `lane` (lanes < nq)
-    int64_t my_pbase = -1;
-    int32_t my_pq = 0;
-    bool emit_q = false;
-    if (MODE == MODE_EMIT && lane < nq && q0 + lane >= R.qlo && q0 + lane < R.qhi) {
-        my_pbase = R.off[q0 + lane] - R.base;
-        my_pq = G.perm[q0 + lane];
-        emit_q = true;
-    }
-    const unsigned long long emit_mask = __ballot(emit_q);
-    EmitRing rb;
-    ring_init(rb, ring_lds + (MODE == MODE_EMIT ? wv * 3 * kRing : 0));
-    int my_cur = 0;
-    const unsigned long long lt = lanemask_lt();
-    int cnt[kTileQ];
-#pragma unroll
-    for (int jq = 0; jq < kTileQ; ++jq) cnt[jq] = 0;
-
-    // 64 candidates of the item's list per step (one chunk); in-mask
-    // recording numbers the 16-candidate tiles of that list
-    const bool rec = MODE == MODE_COUNT && R.masks != nullptr;
-    const int64_t tile_base = rec ? G.tile_off[it] : 0;
-    CandTable CT;
-    cand_init(CT, rg, lane, q0);
-    const int nchunks = (CT.total + 63) >> 6;
-    double xn[D > 0 ? D : 1];
-    int cn = q0;
-    if (nchunks > 0) {
-        cand_chunk(CT, rg, 0, lane);
-        cn = CT.cand;
-        if (D > 0) {
-            const double *xc = xs + (int64_t)cn * dp;
-#pragma unroll
-            for (int u = 0; u < (D > 0 ? D : 1); ++u) xn[u] = xc[u];
-        }
-    }
-    for (int ch = 0; ch < nchunks; ++ch) {
-        const int k16 = 4 * ch;  // first 16-tile of this chunk
-        unsigned long long qm[kTileQ];
-#pragma unroll
-        for (int jq = 0; jq < kTileQ; ++jq) qm[jq] = 0ull;
-        const int c = cn;
-        const bool valid = 64 * ch + lane < CT.total;
-        double x[D > 0 ? D : 1];
-#pragma unroll
-        for (int u = 0; u < (D > 0 ? D : 1); ++u) x[u] = xn[u];
-        if (ch + 1 < nchunks) {  // the next chunk and its rows
-            cand_chunk(CT, rg, ch + 1, lane);
-            cn = CT.cand;
-            if (D > 0) {
-                const double *xc2 = xs + (int64_t)cn * dp;
-#pragma unroll
-                for (int u = 0; u < (D > 0 ? D : 1); ++u) xn[u] = xc2[u];
-            }
-        }
-        const double *__restrict__ xc = xs + (int64_t)c * dp;
-#pragma unroll
-        for (int jq = 0; jq < kTileQ; ++jq) {
-            if (jq < nq) {
-                const double *__restrict__ xq = xs + (int64_t)(q0 + jq) * dp;
-                double acc = 0.0;
-                if (D > 0) {
-#pragma unroll
-                    for (int u = 0; u < (D > 0 ? D : 1); ++u) {
-                        const double delta = __dsub_rn(xq[u], x[u]);
-                        acc = __fma_rn(delta, delta, acc);
-                    }
-                } else {
-                    for (int u = 0; u < d; ++u) {
-                        const double delta = __dsub_rn(xq[u], xc[u]);
-                        acc = __fma_rn(delta, delta, acc);
-                    }
-                }
-                const bool in = valid && acc <= eps2;
-                if (MODE == MODE_COUNT) {
-                    cnt[jq] += in ? 1 : 0;
-                    if (rec) qm[jq] = __ballot(in);
-                } else if (MODE == MODE_EMIT) {
-                    const unsigned long long m = __ballot(in);
-                    if ((emit_mask >> jq) & 1ull) {
-                        const int nm = __popcll(m);
-                        if (nm) {
-                            const int cur_j = __builtin_amdgcn_readlane(my_cur, jq);
-                            if (in) {
-                                const int e = (rb.tail + __popcll(m & lt)) & (kRing - 1);
-                                rb.cand[e] = (uint32_t)c;
-                                rb.rel[e] = (uint32_t)(cur_j + __popcll(m & lt));
-                                rb.col[e] = (uint32_t)jq;
-                            }
-                            rb.tail += nm;
-                            if (lane == jq) my_cur += nm;
-                            ring_drain(rb, false, G, R, lane, my_pbase, my_pq, q0);
-                        }
-                    }
-                }
-            }
-        }
-        if (rec) {
-            // four 16-candidate tiles: word r of sub-tile s collects the
-            // 16-bit slices of queries 4r .. 4r + 3 (query g + 4r at bits
-            // 16g); lane 4s + r stores it (the 16 words are contiguous)
-            const int nsub = (min(64, CT.total - 64 * ch) + 15) / 16;
-            unsigned long long wl = 0;
-#pragma unroll
-            for (int sub = 0; sub < 4; ++sub) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    unsigned long long w = 0;
-#pragma unroll
-                    for (int gg = 0; gg < 4; ++gg) w |= ((qm[gg + 4 * r] >> (16 * sub)) & 0xffffull) << (16 * gg);
-                    if (lane == 4 * sub + r) wl = w;
-                }
-            }
-            if (lane < 4 * nsub) R.masks[(tile_base + k16) * 4 + lane] = wl;
-        }
-    }
-    if (MODE == MODE_EMIT) ring_drain(rb, true, G, R, lane, my_pbase, my_pq, q0);
-    if (MODE == MODE_COUNT) {
-#pragma unroll
-        for (int jq = 0; jq < kTileQ; ++jq) {
-            int v = cnt[jq];
-            for (int sh = 32; sh > 0; sh >>= 1) v += __shfl_xor(v, sh);
-            if (lane == 0 && jq < nq) R.cnt[q0 + jq] = v;
-        }
-    }
-}
-
-template <int D, int MODE>
-__global__ __launch_bounds__(kThreads) void k_v64(DevGrid G, RefOut R) {
-    __shared__ uint32_t ring_lds[MODE == MODE_EMIT ? kWaves * 3 * kRing : 1];
-    const int wv = uniform_i32(threadIdx.x >> 6);
-    const int it = uniform_i32(R.item_lo + xcd_block(blockIdx.x, gridDim.x) * kWaves + wv);
-    if (it >= G.nitems) return;
-    v64_item<D, MODE>(G, R, it, ring_lds);
-}
-
 // --------------------------------------------------------------------- M64 --
 // One v_mfma_f64_16x16x4f64 per K-step: rows = the item's 16 queries (the A
 // operand, loaded once per item), columns = 16 candidates (the B operand,
@@ -469,18 +237,19 @@ struct M64Tile {
     int n;       // valid columns (wave-uniform)
 };
 
-// Issues the loads of tile k; nothing here waits for them.
+// Issues the loads of a tile whose column j is candidate c (n valid
+// columns); nothing here waits for them.
 template <int KS, bool SLOT, int MODE>
-__device__ __forceinline__ void m64_load(M64Tile<KS> &T, CandTable &CT, const ItemRanges &rg, int k, int lane,
-                                         const DevGrid &G, int g) {
-    T.c = cand_of_tile(CT, rg, k, lane, T.n);
+__device__ __forceinline__ void m64_load(M64Tile<KS> &T, int c, int n, const DevGrid &G, int g) {
+    T.c = c;
+    T.n = n;
     if (KS > 0) {
-        const double *__restrict__ brow = G.xa + (int64_t)T.c * G.da + g;
+        const double *__restrict__ brow = G.xa + (int64_t)c * G.da + g;
 #pragma unroll
         for (int s = 0; s < (KS > 0 ? KS : 1); ++s) T.b[s] = brow[4 * s];
     }
-    T.nc = SLOT ? 0.0 : G.nrm[T.c];
-    if (MODE == MODE_EMIT) T.pc = G.perm[T.c];
+    T.nc = SLOT ? 0.0 : G.nrm[c];
+    if (MODE == MODE_EMIT) T.pc = G.perm[c];
 }
 
 template <int KS, bool SLOT>
@@ -592,21 +361,22 @@ __device__ __forceinline__ void m64_words(double4_t acc, const M64Tile<KS> &T, i
     }
 }
 
-// Per-query counts of 16 tiles from their mask words gathered in (mhi, mlo):
-// lane 4s + r holds word r of tile s; adds the pairs of query g + 4r to
-// tot[g] of lane r (lanes 0..3).
-__device__ __forceinline__ void count_words(unsigned mlo, unsigned mhi, int tot[4]) {
-    unsigned p01 = __popc(mlo & 0xffffu) | (__popc(mlo >> 16) << 16);
-    unsigned p23 = __popc(mhi & 0xffffu) | (__popc(mhi >> 16) << 16);
+// In-mask words, nibble layout. A group of 16 consecutive tiles of an item
+// is 64 words, one per lane (g, j): bit 4s + r says whether query g + 4r is
+// within eps of the candidate in column j of tile s of the group. The lane's
+// 4-bit row mask of one tile from the tile's four row words:
+__device__ __forceinline__ unsigned nibble_of(const unsigned long long w[4]) {
+    unsigned nb = 0;
 #pragma unroll
-    for (int o = 4; o < 64; o <<= 1) {
-        p01 += __shfl_xor(p01, o);
-        p23 += __shfl_xor(p23, o);
-    }
-    tot[0] += (int)(p01 & 0xffffu);
-    tot[1] += (int)(p01 >> 16);
-    tot[2] += (int)(p23 & 0xffffu);
-    tot[3] += (int)(p23 >> 16);
+    for (int r = 0; r < 4; ++r) nb |= __builtin_amdgcn_inverse_ballot_w64(w[r]) ? (1u << r) : 0u;
+    return nb;
+}
+
+// Pairs of the lane's rows r (queries g + 4r, column j) in a nibble word.
+__device__ __forceinline__ void nibble_count(unsigned long long nib, int tot[4]) {
+    const unsigned lo = (unsigned)nib, hi = (unsigned)(nib >> 32);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) tot[r] += __popc(lo & (0x11111111u << r)) + __popc(hi & (0x11111111u << r));
 }
 
 template <int KS, bool SLOT, int MODE>
@@ -655,24 +425,26 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
     for (int r = 0; r < 4; ++r) ebal[r] = __ballot(emit_r[r]);
     RowOut ro;
     if (MODE == MODE_EMIT) row_out_init(ro, emit_r, G, R, q0, g, j);
-    int tot[4] = {0, 0, 0, 0};  // count: lanes 0..3 (r = lane), pairs of query g + 4r
+    int tot[4] = {0, 0, 0, 0};  // count: pairs of query g + 4r in this lane's column
     unsigned long long band = 0, viol = 0;  // band: wave-uniform
     double maxerr = 0.0;
 
-    // count: the words of 16 consecutive tiles gather in one register pair
-    // (lane 4s + r = word r of tile s); the per-query counts are taken from
-    // it, and with recording on it leaves in one coalesced store
+    // count: the lane's nibbles of 16 consecutive tiles (one group) gather in
+    // one 64-bit register; the counts come from it, and with recording on it
+    // is stored (64 lanes = one coalesced 512-byte store per group)
     const bool rec = MODE == MODE_COUNT && R.masks != nullptr;
     const int64_t tile_base = rec ? G.tile_off[it] : 0;
-    unsigned mlo = 0, mhi = 0;
-    CandTable CT;
-    cand_init(CT, rg, lane, q0);
-    const int ntiles = CT.ntiles;
-    auto flush = [&](int k0) {  // tiles k0 .. k0 + 15 (those that exist)
-        count_words(mlo, mhi, tot);
-        if (rec && lane < 4 * min(16, ntiles - k0))
-            R.masks[(tile_base + k0) * 4 + lane] = ((unsigned long long)mhi << 32) | mlo;
-        mlo = mhi = 0;
+    unsigned long long nib = 0;
+    CandList L;
+    cand_init(L, rg, lane, q0);
+    const int ntiles = L.ntiles;
+    const int nchunks = (ntiles + 3) >> 2;
+    int flushed = 0;  // tiles whose group is counted (and stored)
+    auto group_done = [&](int k0) {  // tiles k0 .. k0 + 15
+        nibble_count(nib, tot);
+        if (rec) R.masks[(tile_base + k0) * 4 + lane] = nib;
+        nib = 0;
+        flushed = k0 + 16;
     };
     auto classify = [&](const double4_t &acc, const M64Tile<KS> &T, int k) {
         if (MODE == MODE_MEASURE) {
@@ -686,18 +458,20 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
             for (int r = 0; r < 4; ++r) w[r] &= ebal[r];
             tile_store(w, T.c, T.pc, ro, g, j, G, R, q0);
         } else {
-            if ((w[0] | w[1] | w[2] | w[3]) != 0ull) {
-                const int sl = 4 * (k & 15);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    mlo = amdgcn_writelane((int)(unsigned)w[r], sl + r, (int)mlo);
-                    mhi = amdgcn_writelane((int)(unsigned)(w[r] >> 32), sl + r, (int)mhi);
-                }
-            }
-            if ((k & 15) == 15) flush(k - 15);
+            nib |= (unsigned long long)nibble_of(w) << (4 * (k & 15));
         }
     };
-    auto load = [&](M64Tile<KS> &T, int k) { m64_load<KS, SLOT, MODE>(T, CT, rg, k, lane, G, g); };
+    // chunk c: lane (g, j) takes column j of its four tiles, positions 64c + 16s + j
+    int cand[4];
+    auto chunk = [&](int c) {
+        int P[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) P[t] = 64 * c + 16 * t + j;
+        cand_chunk<4>(L, c, P, cand);
+    };
+    auto load = [&](M64Tile<KS> &T, int k, int c) {
+        m64_load<KS, SLOT, MODE>(T, c, min(16, L.total - 16 * k), G, g);
+    };
     // both products first, then both classifications
     auto run = [&](const M64Tile<KS> &TA, const M64Tile<KS> &TB, int k) {
         const bool h1 = k + 1 < ntiles;
@@ -707,32 +481,40 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
         classify(a0, TA, k);
         if (h1) classify(a1, TB, k + 1);
     };
-    // Four tile buffers, two stages per iteration: a stage runs two tiles
-    // while the next two load into the other pair of buffers (fixed roles, so
-    // no register copies wait on loads in flight). Loads past the last tile
-    // repeat the last tile (same instruction count on every path, so each
-    // wait covers exactly the older tiles).
+    // Four tile buffers, two stages per chunk: a stage runs two tiles while
+    // the next two load into the other pair of buffers (fixed roles, so no
+    // register copy waits on a load in flight). Past the item's last tile the
+    // loads repeat valid rows (same instruction count on every path, so each
+    // wait covers exactly the older tiles) and nothing runs.
     M64Tile<KS> T0, T1, T2, T3;
-    const int klast = ntiles - 1;
-    if (ntiles > 0) {
-        load(T0, 0);
-        load(T1, min(1, klast));
+    if (nchunks > 0) {
+        chunk(0);
+        load(T0, 0, cand[0]);
+        load(T1, 1, cand[1]);
     }
-    for (int k = 0; k < ntiles; k += 4) {
-        load(T2, min(k + 2, klast));
-        load(T3, min(k + 3, klast));
+    for (int c = 0; c < nchunks; ++c) {
+        const int k = 4 * c;
+        load(T2, k + 2, cand[2]);
+        load(T3, k + 3, cand[3]);
         run(T0, T1, k);
         if (k + 2 >= ntiles) break;
-        load(T0, min(k + 4, klast));
-        load(T1, min(k + 5, klast));
+        if (c + 1 < nchunks) chunk(c + 1);
+        load(T0, k + 4, cand[0]);
+        load(T1, k + 5, cand[1]);
         run(T2, T3, k + 2);
+        if (MODE == MODE_COUNT && (c & 3) == 3) group_done(k - 12);
     }
     if (MODE == MODE_COUNT) {
-        if (ntiles & 15) flush(ntiles & ~15);
-        if (lane < 4) {
+        if (flushed < ntiles) group_done(flushed);  // the last, partial group
+        // the 16 lanes of row group g hold the columns of queries g + 4r
 #pragma unroll
-            for (int gg = 0; gg < 4; ++gg)
-                if (gg + 4 * lane < nq) R.cnt[q0 + gg + 4 * lane] = tot[gg];
+        for (int r = 0; r < 4; ++r) {
+            int v = tot[r];
+            v += __shfl_xor(v, 1);
+            v += __shfl_xor(v, 2);
+            v += __shfl_xor(v, 4);
+            v += __shfl_xor(v, 8);
+            if (j == 0 && g + 4 * r < nq) R.cnt[q0 + g + 4 * r] = v;
         }
         if (lane == 0 && band) atomicAdd(R.band, band);
     }
@@ -756,45 +538,201 @@ __global__ __launch_bounds__(kThreads) void k_m64(DevGrid G, RefOut R, double de
     m64_item<KS, SLOT, MODE>(G, R, delta, it);
 }
 
+// --------------------------------------------------------------------- V64 --
+// The FP64 vector-ALU path, direct form (Eq. (1) in the order of Eq. (2)):
+// the same 16 x 16 tiles, lane layout and in-mask words as M64, but every
+// distance is the oracle's chain (fl(a - b), fma, dimensions ascending), so
+// the result needs no band. Lane (g, j) evaluates its four rows (queries
+// g + 4r) against its column's candidate. D > 0: the query rows sit in
+// registers; D = 0: runtime d, read per dimension.
+template <int D>
+struct V64Tile {
+    double x[D > 0 ? D : 1];
+    int32_t c, pc;
+    int n;
+};
+
+template <int D, int MODE>
+__device__ __forceinline__ void v64_load(V64Tile<D> &T, int c, int n, const DevGrid &G) {
+    T.c = c;
+    T.n = n;
+    if (D > 0) {
+        const double *__restrict__ xc = G.xs + (int64_t)c * G.dp;
+#pragma unroll
+        for (int u = 0; u < (D > 0 ? D : 1); ++u) T.x[u] = xc[u];
+    }
+    if (MODE == MODE_EMIT) T.pc = G.perm[c];
+}
+
+template <int D, int MODE>
+__device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int it) {
+    const int lane = threadIdx.x & 63;
+    const Item I = G.items[it];
+    const int q0 = uniform_i32(I.qbegin);
+    const int nq = uniform_i32(I.qend - I.qbegin);
+    const int j = lane & 15;
+    const int g = lane >> 4;
+    const int d = D > 0 ? D : G.d;
+    const int dp = G.dp;
+    const double eps2 = G.eps2;
+    const double *__restrict__ xs = G.xs;
+    const ItemRanges rg = load_ranges(G, it, lane);
+
+    bool rowok[4], emit_r[4];
+    int qrow[4];
+    double xq[4][D > 0 ? D : 1];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = g + 4 * r;
+        rowok[r] = i < nq;
+        qrow[r] = q0 + (rowok[r] ? i : 0);
+        emit_r[r] = MODE == MODE_EMIT && rowok[r] && q0 + i >= R.qlo && q0 + i < R.qhi;
+        if (D > 0) {
+#pragma unroll
+            for (int u = 0; u < (D > 0 ? D : 1); ++u) xq[r][u] = xs[(int64_t)qrow[r] * dp + u];
+        }
+    }
+    unsigned long long ebal[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ebal[r] = __ballot(emit_r[r]);
+    RowOut ro;
+    if (MODE == MODE_EMIT) row_out_init(ro, emit_r, G, R, q0, g, j);
+    int tot[4] = {0, 0, 0, 0};
+    const bool rec = MODE == MODE_COUNT && R.masks != nullptr;
+    const int64_t tile_base = rec ? G.tile_off[it] : 0;
+    unsigned long long nib = 0;
+    int flushed = 0;
+    CandList L;
+    cand_init(L, rg, lane, q0);
+    const int ntiles = L.ntiles;
+    const int nchunks = (ntiles + 3) >> 2;
+    auto group_done = [&](int k0) {
+        nibble_count(nib, tot);
+        if (rec) R.masks[(tile_base + k0) * 4 + lane] = nib;
+        nib = 0;
+        flushed = k0 + 16;
+    };
+    auto run1 = [&](const V64Tile<D> &T, int k) {
+        unsigned long long w[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double acc = 0.0;
+            if (D > 0) {
+#pragma unroll
+                for (int u = 0; u < (D > 0 ? D : 1); ++u) {
+                    const double dl = __dsub_rn(xq[r][u], T.x[u]);
+                    acc = __fma_rn(dl, dl, acc);
+                }
+            } else {
+                const double *__restrict__ a = xs + (int64_t)qrow[r] * dp;
+                const double *__restrict__ b = xs + (int64_t)T.c * dp;
+                for (int u = 0; u < d; ++u) {
+                    const double dl = __dsub_rn(a[u], b[u]);
+                    acc = __fma_rn(dl, dl, acc);
+                }
+            }
+            w[r] = __ballot(rowok[r] && acc <= eps2);
+        }
+        if (T.n < 16) {
+            const unsigned long long cm = col_mask(T.n);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) w[r] &= cm;
+        }
+        if (MODE == MODE_EMIT) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) w[r] &= ebal[r];
+            tile_store(w, T.c, T.pc, ro, g, j, G, R, q0);
+        } else {
+            nib |= (unsigned long long)nibble_of(w) << (4 * (k & 15));
+        }
+    };
+    int cand[4];
+    auto chunk = [&](int c) {
+        int P[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) P[t] = 64 * c + 16 * t + j;
+        cand_chunk<4>(L, c, P, cand);
+    };
+    auto load = [&](V64Tile<D> &T, int k, int c) { v64_load<D, MODE>(T, c, min(16, L.total - 16 * k), G); };
+    auto run = [&](const V64Tile<D> &TA, const V64Tile<D> &TB, int k) {
+        run1(TA, k);
+        if (k + 1 < ntiles) run1(TB, k + 1);
+    };
+    // the M64 pipeline: four tile buffers, two stages per chunk
+    V64Tile<D> T0, T1, T2, T3;
+    if (nchunks > 0) {
+        chunk(0);
+        load(T0, 0, cand[0]);
+        load(T1, 1, cand[1]);
+    }
+    for (int c = 0; c < nchunks; ++c) {
+        const int k = 4 * c;
+        load(T2, k + 2, cand[2]);
+        load(T3, k + 3, cand[3]);
+        run(T0, T1, k);
+        if (k + 2 >= ntiles) break;
+        if (c + 1 < nchunks) chunk(c + 1);
+        load(T0, k + 4, cand[0]);
+        load(T1, k + 5, cand[1]);
+        run(T2, T3, k + 2);
+        if (MODE == MODE_COUNT && (c & 3) == 3) group_done(k - 12);
+    }
+    if (MODE == MODE_COUNT) {
+        if (flushed < ntiles) group_done(flushed);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int v = tot[r];
+            v += __shfl_xor(v, 1);
+            v += __shfl_xor(v, 2);
+            v += __shfl_xor(v, 4);
+            v += __shfl_xor(v, 8);
+            if (j == 0 && g + 4 * r < nq) R.cnt[q0 + g + 4 * r] = v;
+        }
+    }
+}
+
+template <int D, int MODE>
+__global__ __launch_bounds__(kThreads) void k_v64(DevGrid G, RefOut R) {
+    const int wv = uniform_i32(threadIdx.x >> 6);
+    const int it = uniform_i32(R.item_lo + xcd_block(blockIdx.x, gridDim.x) * kWaves + wv);
+    if (it >= G.nitems) return;
+    v64_item<D, MODE>(G, R, it);
+}
+
 // ------------------------------------------------------------ mask emit --
 // Emission from the in-masks recorded by an FP64 count pass (FP64 VALU or
-// FP64 MFMA: both record the same canonical masks): per 16 x 16 tile of an
-// item, word r, bit 16g + j says whether query g + 4r is within eps of
-// candidate j. This pass evaluates no distance; it expands the masks into
-// pairs at the exact offsets of the count (tile_store).
+// FP64 MFMA: both record the same nibble words, see nibble_of). This pass
+// evaluates no distance; it expands the masks into pairs at the exact offsets
+// of the count (tile_store).
 //
-// The masks of 16 consecutive tiles arrive in one coalesced vector load (lane
-// l holds word l % 4 of tile l / 4), the next 16 are loaded while these are
-// expanded, and tiles with no pair to write are skipped.
+// Tiles are taken one group (16 tiles) at a time: the lane's nibble word in
+// one coalesced load and the input indices of the group's candidates in four
+// (load q = chunk 4G + q of the candidate list, lane l = position 64 (4G + q)
+// + l), all issued one group ahead; tiles with nothing to write are skipped.
+struct MaskBatch {
+    unsigned long long w;  // the lane's nibble word
+    int32_t pc[4];         // input index of the candidate
+    int32_t c[4];          // sorted index of the candidate
+};
+
+__device__ __forceinline__ void mask_batch_load(MaskBatch &B, CandList &L, const unsigned long long *mb,
+                                                const DevGrid &G, int gi, int lane) {
+    B.w = mb[64 * gi + lane];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int c = 4 * gi + q;
+        const int P[1] = {64 * c + lane};
+        int idx[1];
+        cand_chunk<1>(L, c, P, idx);
+        B.c[q] = idx[0];
+        B.pc[q] = G.perm[idx[0]];
+    }
+}
 
 __device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int lane) {
     const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
     const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
     return ((unsigned long long)hi << 32) | lo;
-}
-
-// Tiles are taken 16 at a time (a batch). The batch's mask words arrive in
-// one vector load (lane 4s + r = word r of tile s) and the input indices of
-// its candidates in four (load q = chunk b / 4 + q of the candidate list:
-// lane 16s + j = column j of tile b + 4q + s), all issued one batch ahead.
-struct MaskBatch {
-    unsigned long long w;
-    int32_t pc[4];  // input index of the candidate
-    int32_t c[4];   // sorted index of the candidate
-};
-
-__device__ __forceinline__ void mask_batch_load(MaskBatch &B, CandTable &CT, const ItemRanges &rg,
-                                                const unsigned long long *mb, const DevGrid &G, int b, int lane) {
-    const int nwords = 4 * CT.ntiles;
-    const int idx = 4 * b + lane;
-    B.w = idx < nwords ? mb[idx] : 0ull;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int c = (b >> 2) + q;
-        if (c != CT.chunk) cand_chunk(CT, rg, c, lane);
-        B.c[q] = CT.cand;
-        B.pc[q] = G.perm[CT.cand];
-    }
 }
 
 __device__ __forceinline__ void mask_item(const DevGrid &G, const RefOut &R, const unsigned long long *masks,
@@ -807,34 +745,41 @@ __device__ __forceinline__ void mask_item(const DevGrid &G, const RefOut &R, con
     const int g = lane >> 4;
     const ItemRanges rg = load_ranges(G, it, lane);
     bool emit_r[4];
+    unsigned erows = 0;  // rows of this lane that this launch emits
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = g + 4 * r;
         emit_r[r] = i < nq && q0 + i >= R.qlo && q0 + i < R.qhi;
+        erows |= emit_r[r] ? 1u << r : 0u;
     }
-    unsigned long long ebal[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) ebal[r] = __ballot(emit_r[r]);
+    const unsigned long long ekeep = 0x1111111111111111ull * erows;
     RowOut ro;
     row_out_init(ro, emit_r, G, R, q0, g, j);
-    CandTable CT;
-    cand_init(CT, rg, lane, q0);
-    const int ntiles = CT.ntiles;
+    CandList L;
+    cand_init(L, rg, lane, q0);
+    const int ngroups = (L.ntiles + 15) >> 4;
     const unsigned long long *mb = masks + G.tile_off[it] * 4;
     MaskBatch nxt;
-    if (ntiles > 0) mask_batch_load(nxt, CT, rg, mb, G, 0, lane);
-    for (int b = 0; b < ntiles; b += 16) {
+    if (ngroups > 0) mask_batch_load(nxt, L, mb, G, 0, lane);
+    for (int gi = 0; gi < ngroups; ++gi) {
         const MaskBatch cur = nxt;
-        if (b + 16 < ntiles) mask_batch_load(nxt, CT, rg, mb, G, b + 16, lane);
-        unsigned long long nz = __ballot(cur.w != 0ull);
+        if (gi + 1 < ngroups) mask_batch_load(nxt, L, mb, G, gi + 1, lane);
+        const unsigned long long w = cur.w & ekeep;
+        // tiles with any bit: OR of the 64 words, then one bit per nibble
+        unsigned long long o = w;
+#pragma unroll
+        for (int sh = 32; sh > 0; sh >>= 1) o |= __shfl_xor(o, sh);
+        o = readlane_u64(o, 0);
+        o |= o >> 1;
+        o |= o >> 2;
+        unsigned long long nz = o & 0x1111111111111111ull;
         while (nz) {
-            const int k = uniform_i32(__builtin_ctzll(nz) >> 2);
-            nz &= ~(0xfull << (4 * k));
+            const int t = uniform_i32(__builtin_ctzll(nz) >> 2);
+            nz &= nz - 1;
             unsigned long long wk[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) wk[r] = readlane_u64(cur.w, 4 * k + r) & ebal[r];
-            if (!(wk[0] | wk[1] | wk[2] | wk[3])) continue;
-            const int q = k >> 2, src = ((k & 3) << 4) | j;
+            for (int r = 0; r < 4; ++r) wk[r] = __ballot((w >> (4 * t + r)) & 1ull);
+            const int q = t >> 2, src = ((t & 3) << 4) | j;
             const int32_t pcq = q < 2 ? (q == 0 ? cur.pc[0] : cur.pc[1]) : (q == 2 ? cur.pc[2] : cur.pc[3]);
             const int32_t cq = q < 2 ? (q == 0 ? cur.c[0] : cur.c[1]) : (q == 2 ? cur.c[2] : cur.c[3]);
             tile_store(wk, __shfl(cq, src), __shfl(pcq, src), ro, g, j, G, R, q0);
@@ -860,7 +805,6 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BProb *__restrict__ pr
                                                     const int32_t *__restrict__ queue, int total,
                                                     int *__restrict__ counter, int32_t *__restrict__ pairs,
                                                     unsigned long long *__restrict__ band) {
-    __shared__ uint32_t ring_lds[MODE == MODE_EMIT ? kWaves * 3 * kRing : 1];
     const int lane = threadIdx.x & 63;
     for (;;) {
         int w = 0;
@@ -904,12 +848,12 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BProb *__restrict__ pr
             }
         } else {
             switch (P.G.d) {
-                case 1: v64_item<1, MODE>(P.G, R, it, ring_lds); break;
-                case 2: v64_item<2, MODE>(P.G, R, it, ring_lds); break;
-                case 3: v64_item<3, MODE>(P.G, R, it, ring_lds); break;
-                case 4: v64_item<4, MODE>(P.G, R, it, ring_lds); break;
-                case 8: v64_item<8, MODE>(P.G, R, it, ring_lds); break;
-                default: v64_item<0, MODE>(P.G, R, it, ring_lds); break;
+                case 1: v64_item<1, MODE>(P.G, R, it); break;
+                case 2: v64_item<2, MODE>(P.G, R, it); break;
+                case 3: v64_item<3, MODE>(P.G, R, it); break;
+                case 4: v64_item<4, MODE>(P.G, R, it); break;
+                case 8: v64_item<8, MODE>(P.G, R, it); break;
+                default: v64_item<0, MODE>(P.G, R, it); break;
             }
         }
     }
