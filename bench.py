@@ -5,7 +5,10 @@ One step = the whole path over the measured workload: for each of the six
 data sets (n = 2,000,000 points; d in {2, 3, 4}; uniform in [0,1]^d and
 exponential(40) clipped to [0,1]; eps for ~64 mean neighbours), build the
 grid index, count R, and write the full pair list to device memory. Inputs
-are resident in HBM before the timed region.
+are resident in HBM before the timed region. The six independent joins are
+dealt to --streams host threads, one HIP stream each (default 2), so one
+set's small build kernels overlap another's refine kernels; the per-launch
+kernel times of the roofline then include that sharing.
 
 metric: distance evaluations per second = C_ref / step time, where C_ref is
 the number of ordered candidate pairs of the full 3^k stencil of the
@@ -56,6 +59,8 @@ def parse():
     ap.add_argument("--workload", default="cfg2", choices=["cfg2", "small", "prec", "skewed", "batched"])
     ap.add_argument("--chunk", type=int, default=0, help="pairs per output chunk (0 = one chunk)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--streams", type=int, default=2,
+                    help="data sets run concurrently, one host thread and HIP stream each")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -78,52 +83,87 @@ def load_inputs(wl):
     return out
 
 
-def one_pass(inputs, path, bufs, collect=None, cref=None, chunk=0):
-    """build + count + pairs over every data set. `bufs[i]` is a device
-    buffer able to hold data set i's pairs (None = size from the count).
-    `cref` (dict, optional): filled with C_ref per data set (an extra pass
-    over the cells; done outside the timed steps)."""
+def one_dataset(i, w, xt, path, bufs, collect, cref, chunk, stream):
+    """build + count + pairs of data set i on `stream`."""
     import torch
     from paper_2209_11287_amd import (selfjoin_build_grid, selfjoin_count, selfjoin_free_grid,
                                       selfjoin_grid_info, selfjoin_pairs)
-    for i, (w, X, xt) in enumerate(inputs):
-        g = selfjoin_build_grid(xt, w["eps"])
-        total, _, st_c = selfjoin_count(g, path, per_point=False)
-        cap = total if chunk <= 0 else min(total, chunk)
-        if bufs[i] is None or bufs[i].shape[0] < cap:
+    g = selfjoin_build_grid(xt, w["eps"], stream=stream)
+    total, _, st_c = selfjoin_count(g, path, per_point=False, stream=stream)
+    cap = total if chunk <= 0 else min(total, chunk)
+    if bufs[i] is None or bufs[i].shape[0] < cap:
+        with torch.cuda.stream(stream):
             bufs[i] = torch.empty((max(cap, 1), 2), dtype=torch.int32, device="cuda:0")
-        cursor, done, emit_ms = 0, 0, 0.0
-        st_p = None
-        while cursor < w["n"]:
-            written, cursor, st = selfjoin_pairs(g, path, cursor, bufs[i], None, cap)
-            done += written
-            emit_ms += st["ms_kernel"]
-            st_p = st if st_p is None else st_p
-        if done != total:
-            raise RuntimeError(f"pairs incomplete: {done}/{total}")
-        st_p = dict(st_p or {"ms": 0.0})
-        st_p["ms_kernel"] = emit_ms
-        if cref is not None:
-            cref[w["name"]] = selfjoin_grid_info(g)["cand_ref"]
-        if collect is not None:
-            collect.append({"name": w["name"], "n": w["n"], "d": w["d"], "eps": w["eps"], "pairs": total,
-                            "cand_eval": st_c["cand_eval"],
-                            "count_kernel_ms": st_c["ms_kernel"], "emit_kernel_ms": st_p["ms_kernel"],
-                            "count_ms": st_c["ms"], "pairs_ms": st_p["ms"], "band_pairs": st_c["band_pairs"],
-                            "band_rel": st_c["band_rel"]})
-        selfjoin_free_grid(g)
+    cursor, done, emit_ms = 0, 0, 0.0
+    st_p = None
+    while cursor < w["n"]:
+        written, cursor, st = selfjoin_pairs(g, path, cursor, bufs[i], None, cap, stream=stream)
+        done += written
+        emit_ms += st["ms_kernel"]
+        st_p = st if st_p is None else st_p
+    if done != total:
+        raise RuntimeError(f"pairs incomplete: {done}/{total}")
+    st_p = dict(st_p or {"ms": 0.0})
+    st_p["ms_kernel"] = emit_ms
+    if cref is not None:
+        cref[w["name"]] = selfjoin_grid_info(g, stream=stream)["cand_ref"]
+    if collect is not None:
+        collect[i] = {"name": w["name"], "n": w["n"], "d": w["d"], "eps": w["eps"], "pairs": total,
+                      "cand_eval": st_c["cand_eval"],
+                      "count_kernel_ms": st_c["ms_kernel"], "emit_kernel_ms": st_p["ms_kernel"],
+                      "count_ms": st_c["ms"], "pairs_ms": st_p["ms"], "band_pairs": st_c["band_pairs"],
+                      "band_rel": st_c["band_rel"]}
+    selfjoin_free_grid(g, stream=stream)
 
 
-def timed(inputs, path, steps, warmup, bufs, cref, chunk=0):
+def one_pass(inputs, path, bufs, collect=None, cref=None, chunk=0, streams=None):
+    """build + count + pairs over every data set. `bufs[i]` is a device
+    buffer able to hold data set i's pairs (None = size from the count).
+    `cref` (dict, optional): filled with C_ref per data set (an extra pass
+    over the cells; done outside the timed steps). With several streams the
+    data sets are dealt round-robin to one host thread per stream (the
+    library's host waits release the interpreter, so the GPU interleaves the
+    independent joins)."""
+    import threading
+
+    import torch
+    streams = streams or [torch.cuda.current_stream()]
+    rec = [None] * len(inputs) if collect is not None else None
+    errors = []
+
+    def work(t):
+        try:
+            with torch.cuda.stream(streams[t]):
+                for i in range(t, len(inputs), len(streams)):
+                    w, _, xt = inputs[i]
+                    one_dataset(i, w, xt, path, bufs, rec, cref, chunk, streams[t])
+        except Exception as e:  # surfaced after join
+            errors.append(e)
+
+    if len(streams) == 1:
+        work(0)
+    else:
+        th = [threading.Thread(target=work, args=(t,)) for t in range(len(streams))]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+    if errors:
+        raise errors[0]
+    if collect is not None:
+        collect.extend(rec)
+
+
+def timed(inputs, path, steps, warmup, bufs, cref, chunk=0, streams=None):
     import torch
     for i in range(warmup):
-        one_pass(inputs, path, bufs, cref=cref if i == 0 else None, chunk=chunk)
+        one_pass(inputs, path, bufs, cref=cref if i == 0 else None, chunk=chunk, streams=streams)
     torch.cuda.synchronize()
     recs = []
     t0 = time.perf_counter()
     for _ in range(steps):
         rec = []
-        one_pass(inputs, path, bufs, rec, chunk=chunk)
+        one_pass(inputs, path, bufs, rec, chunk=chunk, streams=streams)
         for r in rec:
             r["cand_ref"] = cref[r["name"]]
         recs.append(rec)
@@ -296,9 +336,10 @@ def main():
         dst = src.clone()
         torch.cuda.synchronize()
         del src, dst
-    log(f"[bench] path {args.path}: warmup {args.warmup}, steps {args.steps}")
+    streams = [torch.cuda.Stream() for _ in range(max(1, args.streams))] if args.streams > 1 else None
+    log(f"[bench] path {args.path}: warmup {args.warmup}, steps {args.steps}, streams {max(1, args.streams)}")
     cref_map = {}
-    sec, recs = timed(inputs, args.path, args.steps, max(1, args.warmup), bufs, cref_map, args.chunk)
+    sec, recs = timed(inputs, args.path, args.steps, max(1, args.warmup), bufs, cref_map, args.chunk, streams)
     cref = sum(r["cand_ref"] for r in recs[0])
     pairs = sum(r["pairs"] for r in recs[0])
     out = {
@@ -316,15 +357,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "path": args.path, "cand_ref_per_step": cref, "pairs_per_step": pairs,
-                   "chunk": args.chunk},
+                   "chunk": args.chunk, "streams": max(1, args.streams)},
         "per_dataset": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
                         for r in recs[-1]],
-        "roofline": roofline(recs, args.path),
+        "roofline": dict(roofline(recs, args.path),
+                         note="launch times measured on the caller's stream in the timed steps; with "
+                              "several streams they include sharing the GPU with the other stream's kernels"),
     }
     if args.compare:
         log(f"[bench] compare path {args.compare}")
         bufs2 = [None] * len(inputs)
-        sec2, recs2 = timed(inputs, args.compare, args.steps, max(1, args.warmup), bufs2, {}, args.chunk)
+        sec2, recs2 = timed(inputs, args.compare, args.steps, max(1, args.warmup), bufs2, {}, args.chunk, streams)
         for rec in recs2:
             for r in rec:
                 r["cand_ref"] = cref_map[r["name"]]

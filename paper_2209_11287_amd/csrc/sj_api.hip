@@ -30,9 +30,9 @@ __global__ void k_scatter_counts(const int32_t *__restrict__ cnt, const int32_t 
 // ------------------------------------------------------------------------
 // Device memory: a caching allocator. hipMalloc is slow and synchronising,
 // and a build makes a few dozen temporary allocations, so freed blocks are
-// kept per device (tagged with the stream they were released on) and reused.
-// A block released on another stream is reused only after that stream has
-// drained. The cache is returned to the runtime when an allocation fails.
+// kept per device (tagged with the stream they were released on) and reused
+// on that stream only (work on several streams never waits on each other
+// here). The cache is returned to the runtime when an allocation fails.
 // ------------------------------------------------------------------------
 namespace {
 
@@ -73,27 +73,20 @@ void *dev_alloc(size_t bytes, hipStream_t s) {
     const size_t sz = round_size(bytes);
     std::lock_guard<std::mutex> lk(g_mu);
     DevCache &c = g_cache[dev];
-    // smallest cached block that fits without wasting more than 2x
+    // smallest cached block of this stream that fits without wasting more than 2x
     auto it = c.free.lower_bound(sz);
-    auto best = c.free.end();
     for (auto j = it; j != c.free.end() && j->first <= 2 * sz; ++j) {
         if (j->second.s == s) {
-            best = j;
-            break;
+            const FreeBlock fb = j->second;
+            c.free.erase(j);
+            c.live[fb.p] = fb.size;
+            return fb.p;
         }
-        if (best == c.free.end()) best = j;
-    }
-    if (best != c.free.end()) {
-        FreeBlock fb = best->second;
-        c.free.erase(best);
-        // released on another stream (which may no longer exist): drain the device
-        if (fb.s != s) SJ_HIP(hipDeviceSynchronize());
-        c.live[fb.p] = fb.size;
-        return fb.p;
     }
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, sz);
     if (e == hipErrorOutOfMemory) {
+        // blocks cached for other streams: drain the device and return them
         (void)hipGetLastError();
         release_cache(c);
         e = hipMalloc(&p, sz);
