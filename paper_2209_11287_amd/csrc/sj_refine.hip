@@ -481,6 +481,37 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
         classify(a0, TA, k);
         if (h1) classify(a1, TB, k + 1);
     };
+    if (KS > 4) {
+        // Many K-steps (d > 16): a tile's KS MFMAs dominate, so one tile is
+        // in flight while the other runs (two buffers of KS operands each).
+        int have = -1;
+        auto cand_for = [&](int kk) -> int {
+            const int c = kk >> 2;
+            if (c != have) {
+                chunk(c);
+                have = c;
+            }
+            const int t = kk & 3;
+            return t == 0 ? cand[0] : t == 1 ? cand[1] : t == 2 ? cand[2] : cand[3];
+        };
+        auto run1 = [&](const M64Tile<KS> &T, int k) {
+            const double4_t a = m64_tile<KS, SLOT>(T, G, aq, cinit, g, qa);
+            classify(a, T, k);
+            if (MODE == MODE_COUNT && (k & 15) == 15) group_done(k - 15);
+        };
+        const int klast = ntiles - 1;
+        M64Tile<KS> TA, TB;
+        if (ntiles > 0) load(TA, 0, cand_for(0));
+        for (int k = 0; k < ntiles; k += 2) {
+            const int k1 = min(k + 1, klast);
+            load(TB, k1, cand_for(k1));
+            run1(TA, k);
+            if (k + 1 >= ntiles) break;
+            const int k2 = min(k + 2, klast);
+            load(TA, k2, cand_for(k2));
+            run1(TB, k + 1);
+        }
+    } else {
     // Four tile buffers, two stages per chunk: a stage runs two tiles while
     // the next two load into the other pair of buffers (fixed roles, so no
     // register copy waits on a load in flight). Past the item's last tile the
@@ -503,6 +534,7 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
         load(T1, k + 5, cand[1]);
         run(T2, T3, k + 2);
         if (MODE == MODE_COUNT && (c & 3) == 3) group_done(k - 12);
+    }
     }
     if (MODE == MODE_COUNT) {
         if (flushed < ntiles) group_done(flushed);  // the last, partial group
@@ -564,8 +596,13 @@ __device__ __forceinline__ void v64_load(V64Tile<D> &T, int c, int n, const DevG
     if (MODE == MODE_EMIT) T.pc = G.perm[c];
 }
 
+// Runtime d (D = 0) up to this many dimensions: the item's query rows are
+// staged in LDS (16 rows per wave) and each candidate value is read once per
+// dimension for all four rows of the lane.
+constexpr int kV64LdsD = 64;
+
 template <int D, int MODE>
-__device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int it) {
+__device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int it, double *qlds) {
     const int lane = threadIdx.x & 63;
     const Item I = G.items[it];
     const int q0 = uniform_i32(I.qbegin);
@@ -592,6 +629,14 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
             for (int u = 0; u < (D > 0 ? D : 1); ++u) xq[r][u] = xs[(int64_t)qrow[r] * dp + u];
         }
     }
+    const bool use_lds = D == 0 && qlds != nullptr && d <= kV64LdsD;
+    if (use_lds) {
+        for (int i = 0; i < nq; ++i)
+            for (int u = lane; u < d; u += 64) qlds[i * kV64LdsD + u] = xs[(int64_t)(q0 + i) * dp + u];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     unsigned long long ebal[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) ebal[r] = __ballot(emit_r[r]);
@@ -614,25 +659,39 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
     };
     auto run1 = [&](const V64Tile<D> &T, int k) {
         unsigned long long w[4];
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (D > 0) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            double acc = 0.0;
-            if (D > 0) {
+            for (int r = 0; r < 4; ++r)
 #pragma unroll
                 for (int u = 0; u < (D > 0 ? D : 1); ++u) {
                     const double dl = __dsub_rn(xq[r][u], T.x[u]);
-                    acc = __fma_rn(dl, dl, acc);
+                    acc[r] = __fma_rn(dl, dl, acc[r]);
                 }
-            } else {
-                const double *__restrict__ a = xs + (int64_t)qrow[r] * dp;
-                const double *__restrict__ b = xs + (int64_t)T.c * dp;
-                for (int u = 0; u < d; ++u) {
-                    const double dl = __dsub_rn(a[u], b[u]);
-                    acc = __fma_rn(dl, dl, acc);
+        } else if (use_lds) {
+            // every pair's chain still runs over the dimensions in order
+            const double *__restrict__ b = xs + (int64_t)T.c * dp;
+            for (int u = 0; u < d; ++u) {
+                const double bv = b[u];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double dl = __dsub_rn(qlds[(g + 4 * r) * kV64LdsD + u], bv);
+                    acc[r] = __fma_rn(dl, dl, acc[r]);
                 }
             }
-            w[r] = __ballot(rowok[r] && acc <= eps2);
+        } else {
+            const double *__restrict__ b = xs + (int64_t)T.c * dp;
+            for (int u = 0; u < d; ++u) {
+                const double bv = b[u];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double dl = __dsub_rn(xs[(int64_t)qrow[r] * dp + u], bv);
+                    acc[r] = __fma_rn(dl, dl, acc[r]);
+                }
+            }
         }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) w[r] = __ballot(rowok[r] && acc[r] <= eps2);
         if (T.n < 16) {
             const unsigned long long cm = col_mask(T.n);
 #pragma unroll
@@ -693,10 +752,11 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
 
 template <int D, int MODE>
 __global__ __launch_bounds__(kThreads) void k_v64(DevGrid G, RefOut R) {
+    __shared__ double qbuf[D == 0 ? kWaves * 16 * kV64LdsD : 1];
     const int wv = uniform_i32(threadIdx.x >> 6);
     const int it = uniform_i32(R.item_lo + xcd_block(blockIdx.x, gridDim.x) * kWaves + wv);
     if (it >= G.nitems) return;
-    v64_item<D, MODE>(G, R, it);
+    v64_item<D, MODE>(G, R, it, D == 0 ? qbuf + wv * 16 * kV64LdsD : nullptr);
 }
 
 // ------------------------------------------------------------ mask emit --
@@ -805,6 +865,8 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BProb *__restrict__ pr
                                                     const int32_t *__restrict__ queue, int total,
                                                     int *__restrict__ counter, int32_t *__restrict__ pairs,
                                                     unsigned long long *__restrict__ band) {
+    __shared__ double vbuf[PATHV == SJ_FP64_VALU ? kWaves * 16 * kV64LdsD : 1];
+    double *vq = PATHV == SJ_FP64_VALU ? vbuf + (threadIdx.x >> 6) * 16 * kV64LdsD : nullptr;
     const int lane = threadIdx.x & 63;
     for (;;) {
         int w = 0;
@@ -848,12 +910,12 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BProb *__restrict__ pr
             }
         } else {
             switch (P.G.d) {
-                case 1: v64_item<1, MODE>(P.G, R, it); break;
-                case 2: v64_item<2, MODE>(P.G, R, it); break;
-                case 3: v64_item<3, MODE>(P.G, R, it); break;
-                case 4: v64_item<4, MODE>(P.G, R, it); break;
-                case 8: v64_item<8, MODE>(P.G, R, it); break;
-                default: v64_item<0, MODE>(P.G, R, it); break;
+                case 1: v64_item<1, MODE>(P.G, R, it, nullptr); break;
+                case 2: v64_item<2, MODE>(P.G, R, it, nullptr); break;
+                case 3: v64_item<3, MODE>(P.G, R, it, nullptr); break;
+                case 4: v64_item<4, MODE>(P.G, R, it, nullptr); break;
+                case 8: v64_item<8, MODE>(P.G, R, it, nullptr); break;
+                default: v64_item<0, MODE>(P.G, R, it, vq); break;
             }
         }
     }
@@ -979,6 +1041,10 @@ void launch_m64(const Grid &g, const RefOut &R, int nitems, double delta, hipStr
             case 2: SJ_M64(2, false); break;
             case 3: SJ_M64(3, false); break;
             case 4: SJ_M64(4, false); break;
+            case 6: SJ_M64(6, false); break;
+            case 8: SJ_M64(8, false); break;
+            case 12: SJ_M64(12, false); break;
+            case 16: SJ_M64(16, false); break;
             default: SJ_M64(0, false); break;
         }
     }
