@@ -789,14 +789,144 @@ __device__ __forceinline__ void mask_batch_load(MaskBatch &B, CandList &L, const
     }
 }
 
-__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int lane) {
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
-    return ((unsigned long long)hi << 32) | lo;
+// Orders one wave's LDS writes before its later reads of other lanes' slots
+// (and those reads before the next writes).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp(unsigned x) {
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, true);
+}
+
+// Value of lane (lane ^ B), B in {1, 2, 4, 8}: quad permutes, a half-row
+// mirror followed by a quad reversal (i ^ 7 ^ 3 = i ^ 4), a row rotate by 8.
+template <int B>
+__device__ __forceinline__ unsigned lane_xor(unsigned x) {
+    if constexpr (B == 1) return dpp<0xB1>(x);
+    else if constexpr (B == 2) return dpp<0x4E>(x);
+    else if constexpr (B == 4) return dpp<0x1B>(dpp<0x141>(x));
+    else return dpp<0x128>(x);
+}
+
+// Exchanges bit positions p and p + D of v for the positions p in M.
+template <int D, unsigned M>
+__device__ __forceinline__ unsigned delta_swap(unsigned v) {
+    const unsigned t = ((v >> D) ^ v) & M;
+    return v ^ t ^ (t << D);
+}
+
+// 32 bits as 8 nibbles (bit 4s + r) to 4 bytes (bit 8r + s): the bit index
+// [s2 s1 s0 r1 r0] rotated to [r1 r0 s2 s1 s0] by four index-bit exchanges.
+__device__ __forceinline__ unsigned nibbles_to_bytes(unsigned v) {
+    v = delta_swap<14, 0x0000CCCCu>(v);  // index bits 4 and 1
+    v = delta_swap<7, 0x00AA00AAu>(v);   // 3 and 0
+    v = delta_swap<2, 0x0C0C0C0Cu>(v);   // 2 and 1
+    return delta_swap<1, 0x22222222u>(v);  // 1 and 0
+}
+
+// One step of a 16 x 16 bit transpose across the lanes of each row (two
+// matrices, one per 16-bit half): lanes with bit B set take the partner's
+// bits of the other column block, rotated into place.
+template <int B, unsigned LO>
+__device__ __forceinline__ unsigned transpose_step(unsigned x, int lane) {
+    const unsigned p = lane_xor<B>(x);
+    const bool up = (lane & B) != 0;
+    const unsigned rot = __builtin_amdgcn_alignbit(p, p, up ? B : 32 - B);
+    const unsigned m = up ? LO : ~LO;
+    return (rot & m) | (x & ~m);
+}
+
+__device__ __forceinline__ unsigned transpose16x2(unsigned x, int lane) {
+    x = transpose_step<8, 0x00FF00FFu>(x, lane);
+    x = transpose_step<4, 0x0F0F0F0Fu>(x, lane);
+    x = transpose_step<2, 0x33333333u>(x, lane);
+    return transpose_step<1, 0x55555555u>(x, lane);
+}
+
+__device__ __forceinline__ unsigned popc16x2(unsigned v) {
+    return (unsigned)__popc(v & 0xFFFFu) | ((unsigned)__popc(v >> 16) << 16);
+}
+
+// Per (query row, tile) entry of a group: output row of the tile's first pair
+// of that query, the query's column bits in the tile, the query's input index.
+struct alignas(16) EmitInfo {
+    int64_t base;
+    uint32_t y;
+    int32_t pq;
+};
+
+// The pairs of one group of 16 tiles. Lane (g, j) holds the nibble word w
+// (bit 4s + r: query g + 4r, column j of tile s). Per-lane nibbles become
+// row-major bits (x_r, bit s), a transpose within each row group gives lane
+// (g, s) the column bits y_r of tile s, and a scan over s the rank of the
+// tile's first pair in the query's run. Those land in LDS with the group's
+// candidates; then every lane walks its own set bits, one pair per step, at
+// rank = tile rank + set columns of the tile left of j (candidate order).
+__device__ __forceinline__ void emit_group(unsigned long long w, const MaskBatch &cur, int64_t base[4],
+                                           const int32_t pq[4], int g, int j, int lane, const DevGrid &G,
+                                           const RefOut &R, int q0, EmitInfo *info, int32_t *stage) {
+    if (__ballot(w != 0ull) == 0ull) return;
+    const unsigned rl = nibbles_to_bytes((unsigned)w), rh = nibbles_to_bytes((unsigned)(w >> 32));
+    const unsigned y01 = transpose16x2(__builtin_amdgcn_perm(rh, rl, 0x05010400u), lane);
+    const unsigned y23 = transpose16x2(__builtin_amdgcn_perm(rh, rl, 0x07030602u), lane);
+    const unsigned c01 = popc16x2(y01), c23 = popc16x2(y23);
+    unsigned i01 = c01, i23 = c23;  // inclusive scans over s (16-bit halves)
+    i01 += dpp<0x111>(i01);
+    i23 += dpp<0x111>(i23);
+    i01 += dpp<0x112>(i01);
+    i23 += dpp<0x112>(i23);
+    i01 += dpp<0x114>(i01);
+    i23 += dpp<0x114>(i23);
+    i01 += dpp<0x118>(i01);
+    i23 += dpp<0x118>(i23);
+    unsigned t01 = c01, t23 = c23;  // row totals
+    t01 += lane_xor<1>(t01);
+    t23 += lane_xor<1>(t23);
+    t01 += lane_xor<2>(t01);
+    t23 += lane_xor<2>(t23);
+    t01 += lane_xor<4>(t01);
+    t23 += lane_xor<4>(t23);
+    t01 += lane_xor<8>(t01);
+    t23 += lane_xor<8>(t23);
+    const unsigned p01 = i01 - c01, p23 = i23 - c23;
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int sh = 16 * (r & 1);
+        EmitInfo e;
+        e.base = base[r] + (int64_t)(((r < 2 ? p01 : p23) >> sh) & 0xFFFFu);
+        e.y = ((r < 2 ? y01 : y23) >> sh) & 0xFFFFu;
+        e.pq = pq[r];
+        info[64 * g + 16 * r + j] = e;
+        base[r] += (int64_t)(((r < 2 ? t01 : t23) >> sh) & 0xFFFFu);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        stage[64 * q + lane] = cur.pc[q];
+        if (R.d2) stage[256 + 64 * q + lane] = cur.c[q];
+    }
+    wave_lds_sync();
+    const unsigned jlt = (1u << j) - 1u;
+    while (w) {
+        const int b = __builtin_ctzll(w);
+        w &= w - 1ull;
+        const int s = b >> 2, r = b & 3;
+        const EmitInfo e = info[64 * g + 16 * r + s];
+        const int32_t pc = stage[16 * s + j];
+        const int64_t pos = e.base + __popc(e.y & jlt);
+        reinterpret_cast<int2 *>(R.pairs)[pos] = make_int2(e.pq, pc);
+        if (R.d2)
+            R.d2[pos] = exact_d2(G.xs + (int64_t)(q0 + g + 4 * r) * G.dp, G.xs + (int64_t)stage[256 + 16 * s + j] * G.dp,
+                                 G.d);
+    }
 }
 
 __device__ __forceinline__ void mask_item(const DevGrid &G, const RefOut &R, const unsigned long long *masks,
-                                          int it) {
+                                          int it, EmitInfo *info, int32_t *stage) {
     const int lane = threadIdx.x & 63;
     const Item I = G.items[it];
     const int q0 = uniform_i32(I.qbegin);
@@ -815,6 +945,7 @@ __device__ __forceinline__ void mask_item(const DevGrid &G, const RefOut &R, con
     const unsigned long long ekeep = 0x1111111111111111ull * erows;
     RowOut ro;
     row_out_init(ro, emit_r, G, R, q0, g, j);
+    int64_t base[4] = {ro.qb[0], ro.qb[1], ro.qb[2], ro.qb[3]};
     CandList L;
     cand_init(L, rg, lane, q0);
     const int ngroups = (L.ntiles + 15) >> 4;
@@ -824,34 +955,17 @@ __device__ __forceinline__ void mask_item(const DevGrid &G, const RefOut &R, con
     for (int gi = 0; gi < ngroups; ++gi) {
         const MaskBatch cur = nxt;
         if (gi + 1 < ngroups) mask_batch_load(nxt, L, mb, G, gi + 1, lane);
-        const unsigned long long w = cur.w & ekeep;
-        // tiles with any bit: OR of the 64 words, then one bit per nibble
-        unsigned long long o = w;
-#pragma unroll
-        for (int sh = 32; sh > 0; sh >>= 1) o |= __shfl_xor(o, sh);
-        o = readlane_u64(o, 0);
-        o |= o >> 1;
-        o |= o >> 2;
-        unsigned long long nz = o & 0x1111111111111111ull;
-        while (nz) {
-            const int t = uniform_i32(__builtin_ctzll(nz) >> 2);
-            nz &= nz - 1;
-            unsigned long long wk[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) wk[r] = __ballot((w >> (4 * t + r)) & 1ull);
-            const int q = t >> 2, src = ((t & 3) << 4) | j;
-            const int32_t pcq = q < 2 ? (q == 0 ? cur.pc[0] : cur.pc[1]) : (q == 2 ? cur.pc[2] : cur.pc[3]);
-            const int32_t cq = q < 2 ? (q == 0 ? cur.c[0] : cur.c[1]) : (q == 2 ? cur.c[2] : cur.c[3]);
-            tile_store(wk, __shfl(cq, src), __shfl(pcq, src), ro, g, j, G, R, q0);
-        }
+        emit_group(cur.w & ekeep, cur, base, ro.pq, g, j, lane, G, R, q0, info, stage);
     }
 }
 
 __global__ __launch_bounds__(kThreads) void k_mask_emit(DevGrid G, RefOut R, const unsigned long long *masks) {
     const int wv = uniform_i32(threadIdx.x >> 6);
     const int it = uniform_i32(R.item_lo + xcd_block(blockIdx.x, gridDim.x) * kWaves + wv);
+    __shared__ EmitInfo info[kWaves * 256];
+    __shared__ int32_t stage[kWaves * 512];
     if (it >= G.nitems) return;
-    mask_item(G, R, masks, it);
+    mask_item(G, R, masks, it, info + 256 * wv, stage + 512 * wv);
 }
 
 // ------------------------------------------------------------------ batch --
