@@ -851,24 +851,19 @@ __device__ __forceinline__ unsigned popc16x2(unsigned v) {
     return (unsigned)__popc(v & 0xFFFFu) | ((unsigned)__popc(v >> 16) << 16);
 }
 
-// Per (query row, tile) entry of a group: output row of the tile's first pair
-// of that query, the query's column bits in the tile, the query's input index.
-struct alignas(16) EmitInfo {
-    int64_t base;
-    uint32_t y;
-    int32_t pq;
-};
+constexpr int kSlot = 256;  // LDS pair slots per row group (one query's pairs of a group)
 
 // The pairs of one group of 16 tiles. Lane (g, j) holds the nibble word w
 // (bit 4s + r: query g + 4r, column j of tile s). Per-lane nibbles become
-// row-major bits (x_r, bit s), a transpose within each row group gives lane
+// row-major bits (x_r, bit s); a transpose within each row group gives lane
 // (g, s) the column bits y_r of tile s, and a scan over s the rank of the
-// tile's first pair in the query's run. Those land in LDS with the group's
-// candidates; then every lane walks its own set bits, one pair per step, at
-// rank = tile rank + set columns of the tile left of j (candidate order).
+// tile's first pair in the query's run. Then, row by row, each lane (g, s)
+// drops its tile's candidates at consecutive ranks in the row group's LDS
+// slot (candidate order), and the query's run leaves the slot as contiguous
+// stores, 16 lanes per row group.
 __device__ __forceinline__ void emit_group(unsigned long long w, const MaskBatch &cur, int64_t base[4],
                                            const int32_t pq[4], int g, int j, int lane, const DevGrid &G,
-                                           const RefOut &R, int q0, EmitInfo *info, int32_t *stage) {
+                                           const RefOut &R, int q0, int32_t *stage, int32_t *slot) {
     if (__ballot(w != 0ull) == 0ull) return;
     const unsigned rl = nibbles_to_bytes((unsigned)w), rh = nibbles_to_bytes((unsigned)(w >> 32));
     const unsigned y01 = transpose16x2(__builtin_amdgcn_perm(rh, rl, 0x05010400u), lane);
@@ -883,7 +878,7 @@ __device__ __forceinline__ void emit_group(unsigned long long w, const MaskBatch
     i23 += dpp<0x114>(i23);
     i01 += dpp<0x118>(i01);
     i23 += dpp<0x118>(i23);
-    unsigned t01 = c01, t23 = c23;  // row totals
+    unsigned t01 = c01, t23 = c23;  // pairs per query of the row group
     t01 += lane_xor<1>(t01);
     t23 += lane_xor<1>(t23);
     t01 += lane_xor<2>(t01);
@@ -895,38 +890,42 @@ __device__ __forceinline__ void emit_group(unsigned long long w, const MaskBatch
     const unsigned p01 = i01 - c01, p23 = i23 - c23;
     wave_lds_sync();
 #pragma unroll
+    for (int q = 0; q < 4; ++q) stage[64 * q + lane] = R.d2 ? cur.c[q] : cur.pc[q];
+    int32_t *const own = slot + kSlot * g;
+#pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int sh = 16 * (r & 1);
-        EmitInfo e;
-        e.base = base[r] + (int64_t)(((r < 2 ? p01 : p23) >> sh) & 0xFFFFu);
-        e.y = ((r < 2 ? y01 : y23) >> sh) & 0xFFFFu;
-        e.pq = pq[r];
-        info[64 * g + 16 * r + j] = e;
-        base[r] += (int64_t)(((r < 2 ? t01 : t23) >> sh) & 0xFFFFu);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        stage[64 * q + lane] = cur.pc[q];
-        if (R.d2) stage[256 + 64 * q + lane] = cur.c[q];
-    }
-    wave_lds_sync();
-    const unsigned jlt = (1u << j) - 1u;
-    while (w) {
-        const int b = __builtin_ctzll(w);
-        w &= w - 1ull;
-        const int s = b >> 2, r = b & 3;
-        const EmitInfo e = info[64 * g + 16 * r + s];
-        const int32_t pc = stage[16 * s + j];
-        const int64_t pos = e.base + __popc(e.y & jlt);
-        reinterpret_cast<int2 *>(R.pairs)[pos] = make_int2(e.pq, pc);
-        if (R.d2)
-            R.d2[pos] = exact_d2(G.xs + (int64_t)(q0 + g + 4 * r) * G.dp, G.xs + (int64_t)stage[256 + 16 * s + j] * G.dp,
-                                 G.d);
+        const unsigned T = ((r < 2 ? t01 : t23) >> sh) & 0xFFFFu;
+        if (__ballot(T != 0u) == 0ull) continue;
+        wave_lds_sync();
+        unsigned yy = ((r < 2 ? y01 : y23) >> sh) & 0xFFFFu;
+        int32_t *at = own + (((r < 2 ? p01 : p23) >> sh) & 0xFFFFu);
+        const int32_t *const tile = stage + 16 * j;
+        while (yy) {
+            const int col = __builtin_ctz(yy);
+            yy &= yy - 1u;
+            *at++ = tile[col];
+        }
+        wave_lds_sync();
+        for (unsigned m = 0; m < T; m += 16) {
+            const unsigned k = m + j;
+            if (k < T) {
+                const int32_t v = own[k];
+                const int64_t pos = base[r] + k;
+                if (R.d2) {
+                    reinterpret_cast<int2 *>(R.pairs)[pos] = make_int2(pq[r], G.perm[v]);
+                    R.d2[pos] = exact_d2(G.xs + (int64_t)(q0 + g + 4 * r) * G.dp, G.xs + (int64_t)v * G.dp, G.d);
+                } else {
+                    reinterpret_cast<int2 *>(R.pairs)[pos] = make_int2(pq[r], v);
+                }
+            }
+        }
+        base[r] += T;
     }
 }
 
 __device__ __forceinline__ void mask_item(const DevGrid &G, const RefOut &R, const unsigned long long *masks,
-                                          int it, EmitInfo *info, int32_t *stage) {
+                                          int it, int32_t *stage, int32_t *slot) {
     const int lane = threadIdx.x & 63;
     const Item I = G.items[it];
     const int q0 = uniform_i32(I.qbegin);
@@ -955,17 +954,17 @@ __device__ __forceinline__ void mask_item(const DevGrid &G, const RefOut &R, con
     for (int gi = 0; gi < ngroups; ++gi) {
         const MaskBatch cur = nxt;
         if (gi + 1 < ngroups) mask_batch_load(nxt, L, mb, G, gi + 1, lane);
-        emit_group(cur.w & ekeep, cur, base, ro.pq, g, j, lane, G, R, q0, info, stage);
+        emit_group(cur.w & ekeep, cur, base, ro.pq, g, j, lane, G, R, q0, stage, slot);
     }
 }
 
 __global__ __launch_bounds__(kThreads) void k_mask_emit(DevGrid G, RefOut R, const unsigned long long *masks) {
     const int wv = uniform_i32(threadIdx.x >> 6);
     const int it = uniform_i32(R.item_lo + xcd_block(blockIdx.x, gridDim.x) * kWaves + wv);
-    __shared__ EmitInfo info[kWaves * 256];
-    __shared__ int32_t stage[kWaves * 512];
+    __shared__ int32_t stage[kWaves * 256];
+    __shared__ int32_t slot[kWaves * 4 * kSlot];
     if (it >= G.nitems) return;
-    mask_item(G, R, masks, it, info + 256 * wv, stage + 512 * wv);
+    mask_item(G, R, masks, it, stage + 256 * wv, slot + 4 * kSlot * wv);
 }
 
 // ------------------------------------------------------------------ batch --
