@@ -6,9 +6,10 @@ data sets (n = 2,000,000 points; d in {2, 3, 4}; uniform in [0,1]^d and
 exponential(40) clipped to [0,1]; eps for ~64 mean neighbours), build the
 grid index, count R, and write the full pair list to device memory. Inputs
 are resident in HBM before the timed region. The six independent joins are
-dealt to --streams host threads, one HIP stream each (default 2), so one
-set's small build kernels overlap another's refine kernels; the per-launch
-kernel times of the roofline then include that sharing.
+taken by --streams host threads from a shared queue (longest first), one HIP
+stream each (default 3), so one set's small build kernels overlap another's
+refine kernels; the per-launch kernel times of the roofline then include that
+sharing.
 
 metric: distance evaluations per second = C_ref / step time, where C_ref is
 the number of ordered candidate pairs of the full 3^k stencil of the
@@ -59,7 +60,7 @@ def parse():
     ap.add_argument("--workload", default="cfg2", choices=["cfg2", "small", "prec", "skewed", "batched"])
     ap.add_argument("--chunk", type=int, default=0, help="pairs per output chunk (0 = one chunk)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--streams", type=int, default=2,
+    ap.add_argument("--streams", type=int, default=3,
                     help="data sets run concurrently, one host thread and HIP stream each")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -116,27 +117,39 @@ def one_dataset(i, w, xt, path, bufs, collect, cref, chunk, stream):
     selfjoin_free_grid(g, stream=stream)
 
 
-def one_pass(inputs, path, bufs, collect=None, cref=None, chunk=0, streams=None):
+def one_pass(inputs, path, bufs, collect=None, cref=None, chunk=0, streams=None, order=None, cost=None):
     """build + count + pairs over every data set. `bufs[i]` is a device
     buffer able to hold data set i's pairs (None = size from the count).
     `cref` (dict, optional): filled with C_ref per data set (an extra pass
-    over the cells; done outside the timed steps). With several streams the
-    data sets are dealt round-robin to one host thread per stream (the
-    library's host waits release the interpreter, so the GPU interleaves the
-    independent joins)."""
+    over the cells; done outside the timed steps). With several streams one
+    host thread per stream takes the next data set from a shared queue
+    (`order`: longest first, from the warmup's per-set times) and runs it on
+    its stream; the library's host waits release the interpreter, so the GPU
+    interleaves the independent joins. `cost` (list, optional) receives each
+    set's host wall time."""
     import threading
+    import time
 
     import torch
     streams = streams or [torch.cuda.current_stream()]
     rec = [None] * len(inputs) if collect is not None else None
     errors = []
+    queue = list(order if order is not None else range(len(inputs)))
+    lock = threading.Lock()
 
     def work(t):
         try:
             with torch.cuda.stream(streams[t]):
-                for i in range(t, len(inputs), len(streams)):
+                while True:
+                    with lock:
+                        if not queue:
+                            return
+                        i = queue.pop(0)
                     w, _, xt = inputs[i]
+                    t0 = time.perf_counter()
                     one_dataset(i, w, xt, path, bufs, rec, cref, chunk, streams[t])
+                    if cost is not None:
+                        cost[i] = time.perf_counter() - t0
         except Exception as e:  # surfaced after join
             errors.append(e)
 
@@ -156,14 +169,16 @@ def one_pass(inputs, path, bufs, collect=None, cref=None, chunk=0, streams=None)
 
 def timed(inputs, path, steps, warmup, bufs, cref, chunk=0, streams=None):
     import torch
+    cost = [0.0] * len(inputs)
     for i in range(warmup):
-        one_pass(inputs, path, bufs, cref=cref if i == 0 else None, chunk=chunk, streams=streams)
+        one_pass(inputs, path, bufs, cref=cref if i == 0 else None, chunk=chunk, streams=streams, cost=cost)
     torch.cuda.synchronize()
+    order = sorted(range(len(inputs)), key=lambda i: -cost[i])
     recs = []
     t0 = time.perf_counter()
     for _ in range(steps):
         rec = []
-        one_pass(inputs, path, bufs, rec, chunk=chunk, streams=streams)
+        one_pass(inputs, path, bufs, rec, chunk=chunk, streams=streams, order=order)
         for r in rec:
             r["cand_ref"] = cref[r["name"]]
         recs.append(rec)
