@@ -363,13 +363,27 @@ __device__ __forceinline__ void m64_words(double4_t acc, const M64Tile<KS> &T, i
 
 // In-mask words, nibble layout. A group of 16 consecutive tiles of an item
 // is 64 words, one per lane (g, j): bit 4s + r says whether query g + 4r is
-// within eps of the candidate in column j of tile s of the group. The lane's
-// 4-bit row mask of one tile from the tile's four row words:
-__device__ __forceinline__ unsigned nibble_of(const unsigned long long w[4]) {
-    unsigned nb = 0;
+// within eps of the candidate in column j of tile s of the group.
+// Built 8 tiles at a time in a 32-bit register: each tile's four row bits
+// enter at the bottom through an add with carry (acc + acc + the lane's bit
+// of the row's compare mask), so after t tiles bit 4t - 1 - (4s + r) holds
+// (tile s, row r); shifted up and bit-reversed that is bit 4s + r.
+__device__ __forceinline__ unsigned shift_in(unsigned acc, unsigned long long mask) {
+    unsigned out;
+    unsigned long long carry;
+    __asm__("v_addc_co_u32_e64 %0, %1, %2, %2, %3" : "=v"(out), "=s"(carry) : "v"(acc), "s"(mask));
+    return out;
+}
+
+__device__ __forceinline__ void nib_push(unsigned &acc, const unsigned long long w[4]) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) nb |= __builtin_amdgcn_inverse_ballot_w64(w[r]) ? (1u << r) : 0u;
-    return nb;
+    for (int r = 0; r < 4; ++r) acc = shift_in(acc, w[r]);
+}
+
+// t (1..8) tiles pushed since the last flush, into half h of the group word.
+__device__ __forceinline__ void nib_flush(unsigned long long &nib, unsigned &acc, int t, int h) {
+    nib |= (unsigned long long)__builtin_bitreverse32(acc << (32 - 4 * t)) << (32 * h);
+    acc = 0;
 }
 
 // Pairs of the lane's rows r (queries g + 4r, column j) in a nibble word.
@@ -435,12 +449,15 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
     const bool rec = MODE == MODE_COUNT && R.masks != nullptr;
     const int64_t tile_base = rec ? G.tile_off[it] : 0;
     unsigned long long nib = 0;
+    unsigned nacc = 0;  // bits of the current half group
     CandList L;
     cand_init(L, rg, lane, q0);
     const int ntiles = L.ntiles;
     const int nchunks = (ntiles + 3) >> 2;
     int flushed = 0;  // tiles whose group is counted (and stored)
     auto group_done = [&](int k0) {  // tiles k0 .. k0 + 15
+        const int tg = min(ntiles - k0, 16);  // tiles of this group; those past the last flush are pending
+        if (tg & 7) nib_flush(nib, nacc, tg & 7, (tg - 1) >> 3);
         nibble_count(nib, tot);
         if (rec) R.masks[(tile_base + k0) * 4 + lane] = nib;
         nib = 0;
@@ -458,7 +475,8 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
             for (int r = 0; r < 4; ++r) w[r] &= ebal[r];
             tile_store(w, T.c, T.pc, ro, g, j, G, R, q0);
         } else {
-            nib |= (unsigned long long)nibble_of(w) << (4 * (k & 15));
+            nib_push(nacc, w);
+            if ((k & 7) == 7) nib_flush(nib, nacc, 8, (k >> 3) & 1);
         }
     };
     // chunk c: lane (g, j) takes column j of its four tiles, positions 64c + 16s + j
@@ -646,12 +664,15 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
     const bool rec = MODE == MODE_COUNT && R.masks != nullptr;
     const int64_t tile_base = rec ? G.tile_off[it] : 0;
     unsigned long long nib = 0;
+    unsigned nacc = 0;  // bits of the current half group
     int flushed = 0;
     CandList L;
     cand_init(L, rg, lane, q0);
     const int ntiles = L.ntiles;
     const int nchunks = (ntiles + 3) >> 2;
     auto group_done = [&](int k0) {
+        const int tg = min(ntiles - k0, 16);  // tiles of this group; those past the last flush are pending
+        if (tg & 7) nib_flush(nib, nacc, tg & 7, (tg - 1) >> 3);
         nibble_count(nib, tot);
         if (rec) R.masks[(tile_base + k0) * 4 + lane] = nib;
         nib = 0;
@@ -702,7 +723,8 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
             for (int r = 0; r < 4; ++r) w[r] &= ebal[r];
             tile_store(w, T.c, T.pc, ro, g, j, G, R, q0);
         } else {
-            nib |= (unsigned long long)nibble_of(w) << (4 * (k & 15));
+            nib_push(nacc, w);
+            if ((k & 7) == 7) nib_flush(nib, nacc, 8, (k >> 3) & 1);
         }
     };
     int cand[4];
@@ -761,14 +783,14 @@ __global__ __launch_bounds__(kThreads) void k_v64(DevGrid G, RefOut R) {
 
 // ------------------------------------------------------------ mask emit --
 // Emission from the in-masks recorded by an FP64 count pass (FP64 VALU or
-// FP64 MFMA: both record the same nibble words, see nibble_of). This pass
-// evaluates no distance; it expands the masks into pairs at the exact offsets
-// of the count (tile_store).
+// FP64 MFMA: both record the same nibble words). This pass evaluates no
+// distance; it expands the masks into pairs at the exact offsets of the
+// count.
 //
 // Tiles are taken one group (16 tiles) at a time: the lane's nibble word in
 // one coalesced load and the input indices of the group's candidates in four
 // (load q = chunk 4G + q of the candidate list, lane l = position 64 (4G + q)
-// + l), all issued one group ahead; tiles with nothing to write are skipped.
+// + l), all issued one group ahead; groups with nothing to write are skipped.
 struct MaskBatch {
     unsigned long long w;  // the lane's nibble word
     int32_t pc[4];         // input index of the candidate
