@@ -173,7 +173,8 @@ def timed(inputs, path, steps, warmup, bufs, cref, chunk=0, streams=None):
     for i in range(warmup):
         one_pass(inputs, path, bufs, cref=cref if i == 0 else None, chunk=chunk, streams=streams, cost=cost)
     torch.cuda.synchronize()
-    order = sorted(range(len(inputs)), key=lambda i: -cost[i])
+    # longest first balances several streams; one stream keeps the listed order
+    order = sorted(range(len(inputs)), key=lambda i: -cost[i]) if streams and len(streams) > 1 else None
     recs = []
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -210,9 +211,10 @@ def traffic_for(kernel_key):
     return None
 
 
-def roofline(recs, path="fp64_mfma"):
-    """Dominant tile kernel over the timed steps; algorithmic work per launch
-    divided by its mean launch time (HIP events around the launch)."""
+def roofline(recs, path="fp64_mfma", which=None):
+    """Dominant tile kernel over the timed steps (or `which`: "emit" /
+    "count"); algorithmic work per launch divided by its mean launch time
+    (HIP events around the launch)."""
     per = {}
     for rec in recs:
         for r in rec:
@@ -220,7 +222,7 @@ def roofline(recs, path="fp64_mfma"):
     count_ms = sum(r["count_kernel_ms"] for rec in recs for r in rec)
     emit_ms = sum(r["emit_kernel_ms"] for rec in recs for r in rec)
     launches = sum(len(rec) for rec in recs)
-    if emit_ms >= count_ms:
+    if which == "emit" or (which is None and emit_ms >= count_ms):
         # emit: pair rows written (8 B each) + each point's row read once
         byts = sum(8.0 * r["pairs"] + 8.0 * r["n"] * r["d"] + 4.0 * r["n"] for rec in recs for r in rec)
         avg_ms = emit_ms / launches
@@ -379,6 +381,18 @@ def main():
                          note="launch times measured on the caller's stream in the timed steps; with "
                               "several streams they include sharing the GPU with the other stream's kernels"),
     }
+    if streams:
+        # the same kernel's launches with nothing else on the GPU: one more
+        # pass on a single stream after the timed steps
+        iso = []
+        one_pass(inputs, args.path, bufs, iso, chunk=args.chunk)
+        for r in iso:
+            r["cand_ref"] = cref_map[r["name"]]
+        kind = "emit" if out["roofline"]["kernel"].endswith("(pairs)") else "count"
+        ri = roofline([iso], args.path, which=kind)
+        out["roofline"]["isolated"] = {"avg_launch_ms": ri["avg_launch_ms"], "achieved": ri["achieved"],
+                                       "frac": ri["frac"],
+                                       "note": "one pass on a single stream after the timed steps"}
     if args.compare:
         log(f"[bench] compare path {args.compare}")
         bufs2 = [None] * len(inputs)
