@@ -95,6 +95,13 @@ typedef struct {
     double band_rel;     /* largest band half-width used, divided by eps^2 */
     double ms;           /* device time of the whole call (ms) */
     double ms_kernel;    /* device time of the distance-tile kernel alone (ms) */
+    int64_t tiles_pruned; /* count, FP64 paths, d > 16: 16 x 16 tiles left
+                            early because every value's partial distance
+                            already exceeded the threshold (Section IV's
+                            short-circuit): FP64 MFMA after the first 16
+                            dimensions against eps^2 + Delta, FP64 VALU every
+                            16 dimensions against eps^2 (its chain is
+                            monotone); 0 elsewhere */
 } sj_stats;
 
 /* Grid facts (for tests and reports). */

@@ -50,6 +50,7 @@ class sj_stats(ctypes.Structure):
         ("band_rel", ctypes.c_double),
         ("ms", ctypes.c_double),
         ("ms_kernel", ctypes.c_double),
+        ("tiles_pruned", ctypes.c_int64),
     ]
 
     def as_dict(self):

@@ -144,6 +144,7 @@ static void compute_counts(Grid &g, sj_path path, RefineOut &ro, hipStream_t s) 
     g.total = total;
     g.masks_valid = ro.masks != nullptr;
     ro.band_pairs = (int64_t)aux[0];
+    ro.tiles_pruned = (path == SJ_FP64_MFMA || path == SJ_FP64_VALU) ? (int64_t)aux[1] : 0;
     if (path == SJ_FP32_MFMA || path == SJ_BF16_MFMA) {
         double dl;
         std::memcpy(&dl, &aux[3], sizeof dl);
@@ -260,6 +261,7 @@ sj_status selfjoin_count(sj_grid *gh, sj_path path, int32_t *per_point, int64_t 
         stats->band_rel = ro.band_rel;
         stats->ms = ms;
         stats->ms_kernel = ro.kt.ms();
+        stats->tiles_pruned = ro.tiles_pruned;
     }
     return SJ_OK;
     SJ_API_END
@@ -334,6 +336,7 @@ sj_status selfjoin_pairs(sj_grid *gh, sj_path path, int64_t cursor, int32_t *pai
         stats->band_rel = re.band_rel;
         stats->ms = ms;
         stats->ms_kernel = re.kt.ms();
+        stats->tiles_pruned = 0;
     }
     return SJ_OK;
     SJ_API_END

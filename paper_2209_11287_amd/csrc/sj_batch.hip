@@ -392,6 +392,7 @@ sj_status selfjoin_batch_count(sj_batch *bh, sj_path path, int64_t *totals, sj_s
         stats->band_rel = 0;
         stats->ms = ms;
         stats->ms_kernel = ms;
+        stats->tiles_pruned = 0;
     }
     return SJ_OK;
     SJB_CATCH
@@ -441,6 +442,7 @@ sj_status selfjoin_batch_pairs(sj_batch *bh, sj_path path, int32_t *pairs, int64
         stats->band_rel = 0;
         stats->ms = ms;
         stats->ms_kernel = ms;
+        stats->tiles_pruned = 0;
     }
     return SJ_OK;
     SJB_CATCH

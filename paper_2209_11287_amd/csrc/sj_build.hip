@@ -305,7 +305,9 @@ void exclusive_scan(const Tin *in, Tacc *out, int64_t n, hipStream_t s) {
 // ---------------------------------------------------------- gather/norms ----
 // Sorted copies: xs = original rows (stride dp, zero padded), xa = rows
 // centred on `mid` (stride da); nrm = squared norm of the xa row, the FP64
-// chain over dimensions in order. When d % 4 != 0 the norm also sits in xa's
+// chain over dimensions in order; pn (d > 16, else null) = that chain after
+// the first 16 and the first 32 dimensions (the full norm when d < 32): the
+// prefix norms of the refine pass's partial-distance bound. When d % 4 != 0 the norm also sits in xa's
 // slot d, where the MFMA tile multiplies it by 1 (Eq. (4) keeps the norms off
 // the tensor cores; here a spare K slot takes them).
 // Per-block maximum of non-negative doubles into part[blockIdx.x] (a
@@ -344,7 +346,7 @@ struct GatherArgs {
 
 __global__ void k_gather(const double *__restrict__ X, const int32_t *__restrict__ perm, int64_t n,
                          const GatherArgs ga_v, double *__restrict__ xs,
-                         double *__restrict__ xa, double *__restrict__ nrm,
+                         double *__restrict__ xa, double *__restrict__ nrm, double *__restrict__ pn,
                          double *__restrict__ nmax_part) {
     const GatherArgs *ga = &ga_v;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -360,7 +362,9 @@ __global__ void k_gather(const double *__restrict__ X, const int32_t *__restrict
             ps[t] = v;
             pa[t] = c;
             nn = __fma_rn(c, c, nn);
+            if (pn && (t == 15 || t == 31)) pn[2 * i + (t >> 4)] = nn;
         }
+        if (pn && d < 32) pn[2 * i + 1] = nn;
         for (int t = d; t < dp; ++t) ps[t] = 0.0;
         for (int t = d; t < da; ++t) pa[t] = 0.0;
         if (d & 3) pa[d] = nn;
@@ -743,10 +747,10 @@ void exclusive_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipSt
 void free_grid(Grid &g, hipStream_t s) {
     void *bufs[] = {g.xs,   g.xa,       g.nrm,        g.perm,       g.cell_key, g.cell_start, g.ranges,
                     g.item, g.dev_nmax, g.line_first, g.line_table, g.blocks,   g.cnt,        g.off, g.aux,
-                    g.tile_off, g.masks};
+                    g.tile_off, g.masks, g.pn};
     for (void *p : bufs)
         if (p) dev_free(p, s);
-    g.xs = g.xa = g.nrm = nullptr;
+    g.xs = g.xa = g.nrm = g.pn = nullptr;
     g.perm = nullptr;
     g.cell_key = nullptr;
     g.cell_start = nullptr;
@@ -883,6 +887,10 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     g.xs = dev_alloc_n<double>(rows * g.dp, s);
     g.xa = dev_alloc_n<double>(rows * g.da, s);
     g.nrm = dev_alloc_n<double>(rows, s);
+    if (g.da > 16) {
+        g.pn = dev_alloc_n<double>(2 * rows, s);
+        fill_zero(g.pn + 2 * (size_t)n, (size_t)2 * kRowPad * sizeof(double), s);
+    }
     g.dev_nmax = dev_alloc_n<double>(1, s);
     fill_zero(g.xs + (size_t)n * g.dp, (size_t)kRowPad * g.dp * sizeof(double), s);
     fill_zero(g.xa + (size_t)n * g.da, (size_t)kRowPad * g.da * sizeof(double), s);
@@ -903,7 +911,7 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
             ga.da = g.da;
             for (int j = 0; j < d; ++j) ga.mid[j] = g.mid[j];
             hipLaunchKernelGGL(k_gather, dim3(nb), dim3(kThreads), 0, s, points, g.perm, n, ga, g.xs, g.xa, g.nrm,
-                               part);
+                               g.pn, part);
         }
         SJ_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kThreads), 0, s, part, (int64_t)nb, g.dev_nmax);

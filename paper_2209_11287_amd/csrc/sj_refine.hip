@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "sj_internal.h"
 
@@ -51,6 +52,7 @@ struct RefOut {
     double *d2;                   // emit: exact d2 per pair (nullable)
     unsigned long long *band;     // band pairs re-evaluated
     unsigned long long *meas;     // measure: [0] max err bits, [1] violations
+    unsigned long long *pruned;   // count: tiles dropped by the partial-distance bound (nullable)
     int32_t item_lo;              // first item of this launch
     unsigned long long *masks;    // count: per-tile in-masks to record (nullable)
 };
@@ -231,6 +233,7 @@ __device__ __forceinline__ void tile_store(const unsigned long long w[4], int c,
 template <int KS>
 struct M64Tile {
     double b[KS > 0 ? KS : 1];
+    double pn;   // KS > 4: candidate prefix norm over the first 16 dimensions
     double nc;   // candidate norm (no-slot form)
     int32_t c;   // sorted index of the lane's column (a valid row past the end)
     int32_t pc;  // emit: input index of that candidate
@@ -244,11 +247,15 @@ __device__ __forceinline__ void m64_load(M64Tile<KS> &T, int c, int n, const Dev
     T.c = c;
     T.n = n;
     if (KS > 0) {
+        // KS > 4 (count / emit): only the first 4 K-steps ahead of time; the
+        // rest load after the partial-distance test, for tiles that pass it
+        constexpr int KL = (KS > 4 && MODE != MODE_MEASURE) ? 4 : (KS > 0 ? KS : 1);
         const double *__restrict__ brow = G.xa + (int64_t)c * G.da + g;
 #pragma unroll
-        for (int s = 0; s < (KS > 0 ? KS : 1); ++s) T.b[s] = brow[4 * s];
+        for (int s = 0; s < KL; ++s) T.b[s] = brow[4 * s];
     }
     T.nc = SLOT ? 0.0 : G.nrm[c];
+    if (KS > 4 && MODE != MODE_MEASURE) T.pn = G.pn[2 * (int64_t)c];  // set for every grid with da > 16
     if (MODE == MODE_EMIT) T.pc = G.perm[c];
 }
 
@@ -434,6 +441,23 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
     }
     th.clo = eps2 - delta;
     th.chi = eps2 + delta;
+    // Partial-distance bound (KS > 4, Section IV's short-circuit, filter
+    // only): after the first 16 dimensions (4 K-steps) the accumulator of row
+    // r is cinit_r - 2 q.c over those dimensions, so their squared distance
+    // is acc - cinit_r + pq_r + pc with prefix norms pq_r, pc. If it exceeds
+    // eps^2 + Delta for every value of the tile (Delta also bounds the
+    // rounding of this partial form, which has fewer terms and smaller norms
+    // than the full one), no pair of the tile is within eps: the remaining
+    // K-steps are skipped. Per row: acc > tq_r - pc. Absent rows never block.
+    double tq[4];
+    if (KS > 4 && MODE != MODE_MEASURE) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = g + 4 * r;
+            tq[r] = i < nq ? eps2 + delta + (SLOT ? 0.0 : th.nq[r]) - G.pn[2 * (int64_t)(q0 + i)] : -INFINITY;
+        }
+    }
+    unsigned long long npruned = 0;  // wave-uniform
     unsigned long long ebal[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) ebal[r] = __ballot(emit_r[r]);
@@ -513,8 +537,39 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
             return t == 0 ? cand[0] : t == 1 ? cand[1] : t == 2 ? cand[2] : cand[3];
         };
         auto run1 = [&](const M64Tile<KS> &T, int k) {
-            const double4_t a = m64_tile<KS, SLOT>(T, G, aq, cinit, g, qa);
-            classify(a, T, k);
+            bool dropped = false;
+            double4_t a = cinit;
+            if (MODE == MODE_MEASURE) {
+                a = m64_tile<KS, SLOT>(T, G, aq, cinit, g, qa);
+            } else {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) a = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], T.b[s], a, 0, 0, 0);
+                bool far = j >= T.n;  // columns past the item's end never block
+                if (!far) {
+                    far = true;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) far = far && a[r] > tq[r] - T.pn;
+                }
+                dropped = __ballot(!far) == 0ull;
+                if (!dropped) {
+                    const double *__restrict__ brow = G.xa + (int64_t)T.c * G.da + g;
+                    double rest[KS > 4 ? KS - 4 : 1];
+#pragma unroll
+                    for (int s = 4; s < (KS > 4 ? KS : 4); ++s) rest[s - 4] = brow[4 * s];
+#pragma unroll
+                    for (int s = 4; s < (KS > 4 ? KS : 4); ++s)
+                        a = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], rest[s - 4], a, 0, 0, 0);
+                }
+            }
+            if (dropped) {
+                ++npruned;
+                if (MODE == MODE_COUNT) {
+                    nacc <<= 4;  // the tile's four row bits are zero
+                    if ((k & 7) == 7) nib_flush(nib, nacc, 8, (k >> 3) & 1);
+                }
+            } else {
+                classify(a, T, k);
+            }
             if (MODE == MODE_COUNT && (k & 15) == 15) group_done(k - 15);
         };
         const int klast = ntiles - 1;
@@ -567,6 +622,7 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
             if (j == 0 && g + 4 * r < nq) R.cnt[q0 + g + 4 * r] = v;
         }
         if (lane == 0 && band) atomicAdd(R.band, band);
+        if (lane == 0 && npruned && R.pruned) atomicAdd(R.pruned, npruned);
     }
     if (MODE == MODE_MEASURE) {
         for (int sh = 32; sh > 0; sh >>= 1) {
@@ -655,6 +711,7 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    unsigned long long npruned = 0;  // wave-uniform: tiles left early
     unsigned long long ebal[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) ebal[r] = __ballot(emit_r[r]);
@@ -689,27 +746,47 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
                     const double dl = __dsub_rn(xq[r][u], T.x[u]);
                     acc[r] = __fma_rn(dl, dl, acc[r]);
                 }
-        } else if (use_lds) {
-            // every pair's chain still runs over the dimensions in order
-            const double *__restrict__ b = xs + (int64_t)T.c * dp;
-            for (int u = 0; u < d; ++u) {
-                const double bv = b[u];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const double dl = __dsub_rn(qlds[(g + 4 * r) * kV64LdsD + u], bv);
-                    acc[r] = __fma_rn(dl, dl, acc[r]);
-                }
-            }
         } else {
+            // Every pair's chain runs over the dimensions in order. Each step
+            // adds a non-negative square with round-to-nearest, so the chain
+            // never decreases: once every value of the tile is above eps^2
+            // (checked every 16 dimensions) the tile is out, exactly
+            // (Section IV's short-circuit, with no margin needed).
             const double *__restrict__ b = xs + (int64_t)T.c * dp;
-            for (int u = 0; u < d; ++u) {
-                const double bv = b[u];
+            auto chain = [&](auto from_lds) {
+                for (int u0 = 0; u0 < d; u0 += 16) {
+                    // the block's 16 candidate values in flight together
+                    // (indices clamped into the row; steps past d skipped)
+                    double bv[16];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const double dl = __dsub_rn(xs[(int64_t)qrow[r] * dp + u], bv);
-                    acc[r] = __fma_rn(dl, dl, acc[r]);
+                    for (int t = 0; t < 16; ++t) bv[t] = b[min(u0 + t, d - 1)];
+#pragma unroll
+                    for (int t = 0; t < 16; ++t) {
+                        const int u = u0 + t;
+                        if (u < d) {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                double qv;
+                                if constexpr (decltype(from_lds)::value) qv = qlds[(g + 4 * r) * kV64LdsD + u];
+                                else qv = xs[(int64_t)qrow[r] * dp + u];
+                                const double dl = __dsub_rn(qv, bv[t]);
+                                acc[r] = __fma_rn(dl, dl, acc[r]);
+                            }
+                        }
+                    }
+                    if (u0 + 16 < d) {
+                        bool far = true;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) far = far && (!rowok[r] || acc[r] > eps2);
+                        if (__ballot(!(far || j >= T.n)) == 0ull) {
+                            ++npruned;
+                            return;
+                        }
+                    }
                 }
-            }
+            };
+            if (use_lds) chain(std::true_type{});
+            else chain(std::false_type{});
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) w[r] = __ballot(rowok[r] && acc[r] <= eps2);
@@ -769,6 +846,7 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
             v += __shfl_xor(v, 8);
             if (j == 0 && g + 4 * r < nq) R.cnt[q0 + g + 4 * r] = v;
         }
+        if (lane == 0 && npruned && R.pruned) atomicAdd(R.pruned, npruned);
     }
 }
 
@@ -1097,6 +1175,7 @@ DevGrid dev_grid(const Grid &g) {
     G.xs = g.xs;
     G.xa = g.xa;
     G.nrm = g.nrm;
+    G.pn = g.pn;
     G.perm = g.perm;
     G.ranges = g.ranges;
     G.items = g.item;
@@ -1222,7 +1301,8 @@ void launch_seg_scan(const BProb *probs, int B, int64_t *totals, hipStream_t s) 
 }
 
 // Enqueues the count kernel; the band counter lands in ro.band_dev (device,
-// zeroed here) and is read by the caller together with the total.
+// zeroed here) and is read by the caller together with the total; the FP64
+// paths count their pruned tiles in ro.aux_dev[0] (zeroed by the caller).
 void refine_count(Grid &g, sj_path path, int32_t *cnt_sorted, RefineOut &ro, hipStream_t s) {
     fill_zero(ro.band_dev, sizeof(unsigned long long), s);
     RefOut R{};
@@ -1232,12 +1312,14 @@ void refine_count(Grid &g, sj_path path, int32_t *cnt_sorted, RefineOut &ro, hip
     R.masks = ro.masks;
     ro.cand_eval = g.cand_items;
     if (path == SJ_FP64_VALU) {
+        R.pruned = ro.aux_dev;  // zeroed by the caller with the band counter
         ro.kt.start(ro.timed, s);
         launch_v64<MODE_COUNT>(g, R, (int)g.items, s);
         ro.kt.stop(s);
         ro.band_rel = 0.0;
     } else if (path == SJ_FP64_MFMA) {
         const double delta = m64_delta(g);
+        R.pruned = ro.aux_dev;  // zeroed by the caller with the band counter
         ro.kt.start(ro.timed, s);
         launch_m64<MODE_COUNT>(g, R, (int)g.items, delta, s);
         ro.kt.stop(s);

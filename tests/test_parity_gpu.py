@@ -179,6 +179,27 @@ def test_parity_high_dimensions(path, d):
     _check_against_oracle(X, eps, path, f"gmm-{d}d")
 
 
+@pytest.mark.parametrize("path", ["fp64_mfma", "fp64_valu"])
+@pytest.mark.parametrize("d", [16, 24, 64])
+def test_short_circuit_drops_tiles_and_keeps_results(path, d):
+    """Section IV's short-circuit on clustered data, where most candidate
+    tiles of the 4-D grid neighbourhood belong to other clusters: past 16
+    dimensions the FP64 paths leave such tiles early (MFMA after its first
+    16 dimensions against eps^2 + Delta, VALU every 16 dimensions against
+    eps^2). Pair sets, counts and distances stay identical to the oracle's;
+    with d <= 16 nothing is left early."""
+    X = gen.gaussian_mixture(6000, d, clusters=40, seed=300 + d)
+    eps = _eps_for(X, 20)
+    g = _check_against_oracle(X, eps, path, f"short-circuit-{d}d")
+    tiles = g["stats"]["cand_eval"] / 256.0
+    frac = g["stats"]["tiles_pruned"] / tiles
+    log(f"[short-circuit] d={d} path={path} tiles~{tiles:.0f} left early {frac:.3f}")
+    if d <= 16:
+        assert g["stats"]["tiles_pruned"] == 0
+    else:
+        assert frac > 0.1
+
+
 @pytest.mark.parametrize("path", LOWP)
 def test_lowp_rejects_large_d(path):
     import torch
