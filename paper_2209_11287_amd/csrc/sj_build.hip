@@ -306,8 +306,8 @@ void exclusive_scan(const Tin *in, Tacc *out, int64_t n, hipStream_t s) {
 // Sorted copies: xs = original rows (stride dp, zero padded), xa = rows
 // centred on `mid` (stride da); nrm = squared norm of the xa row, the FP64
 // chain over dimensions in order; pn (d > 16, else null) = that chain after
-// the first 16 and the first 32 dimensions (the full norm when d < 32): the
-// prefix norms of the refine pass's partial-distance bound. When d % 4 != 0 the norm also sits in xa's
+// the first 16 dimensions: the prefix norm of the refine pass's
+// partial-distance bound. When d % 4 != 0 the norm also sits in xa's
 // slot d, where the MFMA tile multiplies it by 1 (Eq. (4) keeps the norms off
 // the tensor cores; here a spare K slot takes them).
 // Per-block maximum of non-negative doubles into part[blockIdx.x] (a
@@ -362,9 +362,8 @@ __global__ void k_gather(const double *__restrict__ X, const int32_t *__restrict
             ps[t] = v;
             pa[t] = c;
             nn = __fma_rn(c, c, nn);
-            if (pn && (t == 15 || t == 31)) pn[2 * i + (t >> 4)] = nn;
+            if (pn && t == 15) pn[i] = nn;
         }
-        if (pn && d < 32) pn[2 * i + 1] = nn;
         for (int t = d; t < dp; ++t) ps[t] = 0.0;
         for (int t = d; t < da; ++t) pa[t] = 0.0;
         if (d & 3) pa[d] = nn;
@@ -888,8 +887,8 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     g.xa = dev_alloc_n<double>(rows * g.da, s);
     g.nrm = dev_alloc_n<double>(rows, s);
     if (g.da > 16) {
-        g.pn = dev_alloc_n<double>(2 * rows, s);
-        fill_zero(g.pn + 2 * (size_t)n, (size_t)2 * kRowPad * sizeof(double), s);
+        g.pn = dev_alloc_n<double>(rows, s);
+        fill_zero(g.pn + n, (size_t)kRowPad * sizeof(double), s);
     }
     g.dev_nmax = dev_alloc_n<double>(1, s);
     fill_zero(g.xs + (size_t)n * g.dp, (size_t)kRowPad * g.dp * sizeof(double), s);

@@ -71,7 +71,7 @@ struct DevGrid {
     const double *xs;
     const double *xa;
     const double *nrm;
-    const double *pn;  // prefix norms over the first 16 / 32 dimensions (da > 16), else null
+    const double *pn;  // prefix norms over the first 16 dimensions (da > 16), else null
     const int32_t *perm;
     const Range *ranges;
     const Item *items;
@@ -116,8 +116,8 @@ struct Grid {
     double *xs = nullptr;        // sorted original coordinates, n x dp (+pad rows)
     double *xa = nullptr;        // sorted centred coordinates (+norm slot), n x da (+pad rows)
     double *nrm = nullptr;       // squared norms of xa rows (FP64 chain), n (+pad)
-    double *pn = nullptr;        // da > 16: squared norms of xa rows over their first 16 and 32
-                                 // dimensions (FP64 chain), n x 2 (+pad); else null
+    double *pn = nullptr;        // da > 16: squared norms of xa rows over their first 16
+                                 // dimensions (FP64 chain), n (+pad); else null
     int32_t *perm = nullptr;     // sorted position -> input index
     int64_t *cell_key = nullptr; // per non-empty cell
     int32_t *cell_start = nullptr; // cells + 1 entries

@@ -255,7 +255,7 @@ __device__ __forceinline__ void m64_load(M64Tile<KS> &T, int c, int n, const Dev
         for (int s = 0; s < KL; ++s) T.b[s] = brow[4 * s];
     }
     T.nc = SLOT ? 0.0 : G.nrm[c];
-    if (KS > 4 && MODE != MODE_MEASURE) T.pn = G.pn[2 * (int64_t)c];  // set for every grid with da > 16
+    if (KS > 4 && MODE != MODE_MEASURE) T.pn = G.pn[c];  // set for every grid with da > 16
     if (MODE == MODE_EMIT) T.pc = G.perm[c];
 }
 
@@ -454,7 +454,7 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = g + 4 * r;
-            tq[r] = i < nq ? eps2 + delta + (SLOT ? 0.0 : th.nq[r]) - G.pn[2 * (int64_t)(q0 + i)] : -INFINITY;
+            tq[r] = i < nq ? eps2 + delta + (SLOT ? 0.0 : th.nq[r]) - G.pn[q0 + i] : -INFINITY;
         }
     }
     unsigned long long npruned = 0;  // wave-uniform
