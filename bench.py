@@ -41,6 +41,8 @@ WORKLOAD_TEXT = {
     "skewed": "n=10,000,000 exponential(40) d=3, s~100; build + count + pair list in chunks",
     "batched": "256 independent self-joins, n log-uniform in [1e3, 2e5], d in {2,3,4,8,16}, uniform, s~32; "
                "one persistent work-queue launch (HIP graph) for count, one for pairs",
+    "brute": "index-free (brute-force) mode, exponential(40) d=16, n = 2^11 .. 2^17, one eps (s~64 at 2^17); "
+             "build + count + full pair list; C_ref = n^2",
 }
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
@@ -57,7 +59,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--path", default="fp64_mfma")
     ap.add_argument("--compare", default="fp64_valu", help="second path timed on the same data ('none' = none)")
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "small", "prec", "skewed", "batched"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "small", "prec", "skewed", "batched", "brute"])
     ap.add_argument("--chunk", type=int, default=0, help="pairs per output chunk (0 = one chunk)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--streams", type=int, default=3,
@@ -69,6 +71,8 @@ def parse():
 
 def datasets(which):
     from workloads import configs
+    if which == "brute":
+        return [dict(w, index_dims=-1) for w in configs.brute_workloads()]
     names = {"cfg2": configs.CFG2, "small": ["small"], "prec": configs.PREC, "skewed": configs.SKEWED}[which]
     return [configs.workload(nm) for nm in names]
 
@@ -89,7 +93,7 @@ def one_dataset(i, w, xt, path, bufs, collect, cref, chunk, stream):
     import torch
     from paper_2209_11287_amd import (selfjoin_build_grid, selfjoin_count, selfjoin_free_grid,
                                       selfjoin_grid_info, selfjoin_pairs)
-    g = selfjoin_build_grid(xt, w["eps"], stream=stream)
+    g = selfjoin_build_grid(xt, w["eps"], index_dims=w.get("index_dims", 0), stream=stream)
     total, _, st_c = selfjoin_count(g, path, per_point=False, stream=stream)
     cap = total if chunk <= 0 else min(total, chunk)
     if bufs[i] is None or bufs[i].shape[0] < cap:
@@ -268,6 +272,48 @@ def cpu_baseline(inputs):
             "seconds": round(secs, 2)}
 
 
+def brute_compare(inputs, path, bufs, reps=3):
+    """Index-free workload, per size: our build + count + pairs (index_dims =
+    -1) and a dense reference in the role of the paper's WMMA-Ref -- the
+    distance matrix |q|^2 + |c|^2 - 2 Q C^T from an FP64 GEMM (torch.matmul,
+    rocBLAS / hipBLASLt) in blocks of 8192 rows, thresholded and counted on the
+    device. Its rounding differs from the exact chain, so its count is
+    reported, not compared. Median of `reps` runs each."""
+    import statistics
+
+    import torch
+    out = []
+    for i, (w, _, xt) in enumerate(inputs):
+        n, eps2 = w["n"], w["eps"] * w["eps"]
+        ours, ref = [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            one_dataset(i, w, xt, path, bufs, None, None, 0, torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            ours.append(time.perf_counter() - t0)
+        xT = xt.t().contiguous()
+        nrm = (xt * xt).sum(1)
+        cnt = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c = torch.zeros((), dtype=torch.int64, device=xt.device)
+            for b0 in range(0, n, 8192):
+                q = xt[b0:b0 + 8192]
+                dmat = torch.matmul(q, xT).mul_(-2.0).add_(nrm[b0:b0 + 8192, None]).add_(nrm[None, :])
+                c += (dmat <= eps2).sum()
+                del dmat
+            cnt = int(c)
+            torch.cuda.synchronize()
+            ref.append(time.perf_counter() - t0)
+        del xT
+        out.append({"n": n, "ms": round(statistics.median(ours) * 1e3, 3),
+                    "gemm_reference_ms": round(statistics.median(ref) * 1e3, 3),
+                    "gemm_reference_count": cnt})
+    return out
+
+
 def batched_main(args):
     """The batched workload: 256 problems through the batched C ABI."""
     import math
@@ -393,6 +439,12 @@ def main():
         out["roofline"]["isolated"] = {"avg_launch_ms": ri["avg_launch_ms"], "achieved": ri["achieved"],
                                        "frac": ri["frac"],
                                        "note": "one pass on a single stream after the timed steps"}
+    if args.workload == "brute":
+        log("[bench] per-size times and the dense GEMM reference")
+        per = brute_compare(inputs, args.path, bufs)
+        for r, rec in zip(per, recs[-1]):
+            r["pairs"] = rec["pairs"]
+        out["per_size"] = per
     if args.compare:
         log(f"[bench] compare path {args.compare}")
         bufs2 = [None] * len(inputs)

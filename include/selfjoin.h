@@ -71,8 +71,12 @@ typedef enum {
 /* Build options; pass NULL for defaults. */
 typedef struct {
     int32_t index_dims;     /* number of leading dimensions indexed by the grid
-                               (Section II-D: fewer than d); 0 = min(d, 4). The
-                               result does not depend on it. */
+                               (Section II-D: fewer than d); 0 = min(d, 4);
+                               -1 = no index (selfjoin_build_grid only): one
+                               cell holds every point, so every ordered pair
+                               is a candidate -- the brute-force mode of
+                               Section IV (Fig. 3), C_ref = n^2. The result
+                               does not depend on it. */
     int32_t tune;           /* batched form only: nonzero = choose index_dims per
                                d by timing the FP64 MFMA count on the largest
                                problem of that d (result-neutral) */

@@ -204,8 +204,8 @@ sj_status selfjoin_build_grid(const double *points, int64_t n, int32_t d, double
     if (d < 1 || d > kMaxDims) return invalid("d must be in [1, 256]");
     if (!(eps > 0.0) || !std::isfinite(eps)) return invalid("eps must be finite and > 0");
     if (n > 0 && !points) return invalid("points is NULL");
-    if (opts && (opts->index_dims < 0 || opts->index_dims > kMaxIndexDims))
-        return invalid("index_dims must be in [0, 4]");
+    if (opts && (opts->index_dims < -1 || opts->index_dims > kMaxIndexDims))
+        return invalid("index_dims must be in [-1, 4]");
     hipStream_t s = static_cast<hipStream_t>(stream);
     sj_grid *h = nullptr;
     SJ_API_BEGIN

@@ -769,11 +769,16 @@ void free_grid(Grid &g, hipStream_t s) {
 
 // Host-side reading of the grid geometry; identical arithmetic to the
 // reference definition (floor((max - min) / w) + 1 cells per dimension).
+// index_dims < 0 (no index): one indexed dimension with a cell wider than
+// the data, so a single cell, one line and one candidate range [0, n) per
+// work item (every ordered pair is a candidate).
 static void choose_geometry(Grid &g, int index_dims) {
-    const double w = g.eps * (1.0 + 0x1p-19);
+    double w = g.eps * (1.0 + 0x1p-19);
+    if (index_dims < 0) w = std::max(w, 2.0 * (g.hi[0] - g.lo[0]));
     g.w = w;
-    int k = index_dims > 0 ? std::min(index_dims, std::min(g.d, kMaxIndexDims))
-                           : std::min(g.d, kMaxIndexDims);
+    int k = index_dims < 0   ? 1
+            : index_dims > 0 ? std::min(index_dims, std::min(g.d, kMaxIndexDims))
+                             : std::min(g.d, kMaxIndexDims);
     for (;;) {
         double prod = 1.0;
         for (int j = 0; j < k; ++j) {

@@ -70,7 +70,7 @@ def test_build_rejects_null_pointers_and_bad_options(lib):
     assert _build(lib, None, 10, 2, 0.1) == _lib.SJ_ERR_INVALID
     assert _build(lib, FAKE, 10, 2, 0.1, out=False) == _lib.SJ_ERR_INVALID
     assert _build(lib, FAKE, 10, 2, 0.1, index_dims=5) == _lib.SJ_ERR_INVALID
-    assert _build(lib, FAKE, 10, 2, 0.1, index_dims=-1) == _lib.SJ_ERR_INVALID
+    assert _build(lib, FAKE, 10, 2, 0.1, index_dims=-2) == _lib.SJ_ERR_INVALID  # -1 = no index
 
 
 def test_calls_on_null_grid_rejected(lib):

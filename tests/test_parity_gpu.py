@@ -200,6 +200,30 @@ def test_short_circuit_drops_tiles_and_keeps_results(path, d):
         assert frac > 0.1
 
 
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("dist,n,d", [("expo", 2048, 16), ("uniform", 3001, 3), ("gmm", 1000, 64)])
+def test_index_free_mode_matches_oracle(path, dist, n, d):
+    """index_dims = -1 (the brute-force mode of Section IV, Fig. 3): one cell,
+    every ordered pair a candidate (C_ref = n^2); the pair set, per-point
+    counts and distances are the oracle's (whose grid index does not change
+    the result)."""
+    import oracle
+    from workloads import configs
+    X = gen.make(dist, n, d, seed=17)
+    eps = configs.brute_workloads()[0]["eps"] if dist == "expo" else _eps_for(X, 20)
+    log(f"[index-free] {dist} n={n} d={d} path={path} eps={eps}")
+    cnt, pp, pairs, d2 = oracle.grid_pairs(X, eps, want_d2=True)
+    g = gpu_join(X, eps, path, want_pairs=True, want_d2=True, index_dims=-1)
+    assert g["info"]["cells"] == 1
+    assert g["info"]["cand_ref"] == n * n
+    assert g["total"] == cnt
+    assert np.array_equal(g["per_point"], pp)
+    assert np.array_equal(pair_keys(g["pairs"]), pair_keys(pairs))
+    ko = (pairs[:, 0].astype(np.int64) << 32) | pairs[:, 1]
+    kg = (g["pairs"][:, 0].astype(np.int64) << 32) | g["pairs"][:, 1]
+    assert np.array_equal(d2[np.argsort(ko)].view(np.int64), g["d2"][np.argsort(kg)].view(np.int64))
+
+
 @pytest.mark.parametrize("path", LOWP)
 def test_lowp_rejects_large_d(path):
     import torch

@@ -8,6 +8,9 @@ only) and frozen in eps.json.
             eps for s ~ 64 -- the measured workload
   prec    : n = 1,000,000, d in {16, 32, 64}, Gaussian mixture, s ~ 50
   skewed  : n = 10,000,000, d = 3, exponential(40), s ~ 100
+  brute   : index-free mode (one cell, every ordered pair a candidate) on
+            d = 16, exponential(40), n = 2^11 .. 2^17 (Fig. 3's sizes), one
+            eps for all sizes, calibrated for s ~ 64 at n = 2^17
 """
 from __future__ import annotations
 
@@ -23,6 +26,7 @@ _GUESS = {
     "expo_d2_n2M": 1.600e-4, "expo_d3_n2M": 9.996e-4, "expo_d4_n2M": 2.614e-3,
     "gmm_d16_n1M": 0.0641, "gmm_d32_n1M": 0.1100, "gmm_d64_n1M": 0.1757,
     "expo_d3_n10M": 6.750e-4,
+    "expo_d16_n131072": 0.05,
 }
 
 
@@ -39,6 +43,7 @@ def calibration_list():
     for d in (16, 32, 64):
         out.append(_entry(f"gmm_d{d}_n1M", "gmm", 1_000_000, d, 50.0))
     out.append(_entry("expo_d3_n10M", "expo", 10_000_000, 3, 100.0))
+    out.append(_entry("expo_d16_n131072", "expo", 1 << 17, 16, 64.0))
     return out
 
 
@@ -59,6 +64,13 @@ def workload(name):
             return {"name": name, "dist": w["dist"], "n": w["n"], "d": w["d"], "seed": w["seed"],
                     "eps": eps}
     raise KeyError(name)
+
+
+def brute_workloads():
+    """The index-free sizes: 16-D exponential(40), n = 2^11 .. 2^17, one eps."""
+    eps = workload("expo_d16_n131072")["eps"]
+    return [{"name": f"brute_expo_d16_n{1 << e}", "dist": "expo", "n": 1 << e, "d": 16, "seed": 0,
+             "eps": eps} for e in range(11, 18)]
 
 
 CFG2 = [f"{dist}_d{d}_n2M" for dist in ("uniform", "expo") for d in (2, 3, 4)]
