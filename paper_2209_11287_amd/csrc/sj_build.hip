@@ -124,26 +124,38 @@ __global__ void k_bbox_final(const double *__restrict__ pmin, const double *__re
 // ---------------------------------------------------------------- keys ----
 struct KeyGeom {
     int k, d;
+    int sb;  // sub-cell bits appended (last indexed dimension)
     double w;
     double lo[kMaxIndexDims];
     int64_t m[kMaxIndexDims];
     int64_t stride[kMaxIndexDims];
 };
 
+// Position of t = fl(fl(x - lo) / w) inside cell c in 2^sb steps, clamped
+// (monotone in x, like the cell itself).
+__device__ __forceinline__ unsigned long long sub_cell(double t, int64_t c, int sb) {
+    if (sb == 0) return 0;
+    const double f = floor((t - (double)c) * (double)(1ull << sb));
+    const double top = (double)((1ull << sb) - 1);
+    return (unsigned long long)(f < 0.0 ? 0.0 : (f > top ? top : f));
+}
+
 __global__ void k_keys(const double *__restrict__ X, int64_t n, KeyGeom geo,
                        unsigned long long *__restrict__ key, int32_t *__restrict__ idx) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    unsigned long long kk = 0;
+    unsigned long long kk = 0, sub = 0;
     for (int j = 0; j < geo.k; ++j) {
         // c = floor(fl(fl(x - lo) / w)), clamped: the same two roundings as
         // the reference grid definition.
-        double q = floor(__ddiv_rn(__dsub_rn(X[i * geo.d + j], geo.lo[j]), geo.w));
+        const double t = __ddiv_rn(__dsub_rn(X[i * geo.d + j], geo.lo[j]), geo.w);
+        double q = floor(t);
         int64_t c = (int64_t)q;
         c = c < 0 ? 0 : (c > geo.m[j] - 1 ? geo.m[j] - 1 : c);
         kk += (unsigned long long)c * (unsigned long long)geo.stride[j];
+        if (j == geo.k - 1) sub = sub_cell(t, c, geo.sb);
     }
-    key[i] = kk;
+    key[i] = (kk << geo.sb) | sub;
     idx[i] = (int32_t)i;
 }
 
@@ -412,19 +424,20 @@ __global__ void k_gather4(const double *__restrict__ X, const int32_t *__restric
 }
 
 // ----------------------------------------------------------- cell table ----
-__global__ void k_cell_flags(const unsigned long long *__restrict__ key, int64_t n,
+// Sorted keys carry `sb` sub-cell bits below the cell key.
+__global__ void k_cell_flags(const unsigned long long *__restrict__ key, int64_t n, int sb,
                              int32_t *__restrict__ flag) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) flag[i] = (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+    if (i < n) flag[i] = (i == 0 || (key[i] >> sb) != (key[i - 1] >> sb)) ? 1 : 0;
 }
 
-__global__ void k_cell_write(const unsigned long long *__restrict__ key, const int32_t *__restrict__ flag,
+__global__ void k_cell_write(const unsigned long long *__restrict__ key, int sb, const int32_t *__restrict__ flag,
                              const int32_t *__restrict__ cid, int64_t n, int64_t *__restrict__ cell_key,
                              int32_t *__restrict__ cell_start, int32_t *__restrict__ ncells) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (flag[i]) {
-        cell_key[cid[i]] = (int64_t)key[i];
+        cell_key[cid[i]] = (int64_t)(key[i] >> sb);
         cell_start[cid[i]] = (int32_t)i;
     }
     if (i == n - 1) {
@@ -534,7 +547,20 @@ struct RangeGeom {
     int k, nranges;
     int64_t m[kMaxIndexDims];
     int64_t stride[kMaxIndexDims];
+    int sb;          // sub-cell bits of the sorted keys (0: no trimming)
+    double lo_last;  // grid origin on the last indexed dimension
+    double w;        // cell side
 };
+
+// Sort key (cell key and sub-cell bits) of coordinate x on line `base`, by
+// the same arithmetic as k_keys (monotone in x).
+__device__ __forceinline__ unsigned long long line_pos_key(int64_t base, double x, const RangeGeom &geo) {
+    const int kl = geo.k - 1;
+    const double t = __ddiv_rn(__dsub_rn(x, geo.lo_last), geo.w);
+    int64_t c = (int64_t)floor(t);
+    c = c < 0 ? 0 : (c > geo.m[kl] - 1 ? geo.m[kl] - 1 : c);
+    return ((unsigned long long)(base + c) << geo.sb) | sub_cell(t, c, geo.sb);
+}
 
 // Sorted-point range [begin, end) of the cells of line `base` (key of the
 // line with last coordinate 0) whose last coordinate is in [lo_c, hi_c].
@@ -603,11 +629,16 @@ __device__ __forceinline__ void block_add(unsigned long long v, unsigned long lo
 }
 
 // Ranges of every work item (grid-stride over item x offset), plus the
-// number of candidate pairs the items see.
+// number of candidate pairs the items see. A range starts as the cells
+// c_first - 1 .. c_last + 1 of a neighbour line; with sub-cell bits it is cut
+// to the points whose last indexed coordinate lies within w (1 + 2^-20) of
+// the item's queries' (any pair within eps differs by at most eps < w there),
+// by two binary searches over the sorted keys.
 __global__ void k_item_ranges(const Item *__restrict__ items, const int32_t *__restrict__ nitems_p,
                               const int64_t *__restrict__ cell_key, const int32_t *__restrict__ cell_start,
                               const int32_t *__restrict__ ncells_p, RangeGeom geo,
                               const int32_t *__restrict__ line_of_key, const int32_t *__restrict__ line_first,
+                              const unsigned long long *__restrict__ skey, const double *__restrict__ xs, int dp,
                               Range *__restrict__ ranges, unsigned long long *__restrict__ cand_items) {
     const int64_t total = (int64_t)(*nitems_p) * geo.nranges;
     const int64_t ncells = *ncells_p;
@@ -628,6 +659,31 @@ __global__ void k_item_ranges(const Item *__restrict__ items, const int32_t *__r
             const int64_t lo_c = c0[kl] > 0 ? c0[kl] - 1 : 0;
             const int64_t hi_c = c1[kl] < mlast - 1 ? c1[kl] + 1 : c1[kl];
             r = line_segment(cell_key, cell_start, ncells, line_of_key, line_first, base, mlast, lo_c, hi_c);
+            if (geo.sb > 0 && r.end > r.begin) {
+                double xmin = INFINITY, xmax = -INFINITY;
+                for (int q = I.qbegin; q < I.qend; ++q) {
+                    const double x = xs[(int64_t)q * dp + kl];
+                    xmin = fmin(xmin, x);
+                    xmax = fmax(xmax, x);
+                }
+                const double wm = geo.w * (1.0 + 0x1p-20);
+                const unsigned long long klo = line_pos_key(base, xmin - wm, geo);
+                const unsigned long long khi = line_pos_key(base, xmax + wm, geo);
+                int32_t x0 = r.begin, y0 = r.end;  // first key >= klo
+                while (x0 < y0) {
+                    const int32_t mid = x0 + (y0 - x0) / 2;
+                    if (skey[mid] < klo) x0 = mid + 1;
+                    else y0 = mid;
+                }
+                int32_t x1 = x0, y1 = r.end;  // first key > khi
+                while (x1 < y1) {
+                    const int32_t mid = x1 + (y1 - x1) / 2;
+                    if (skey[mid] <= khi) x1 = mid + 1;
+                    else y1 = mid;
+                }
+                r.begin = x0;
+                r.end = x1;
+            }
         }
         ranges[t] = r;
         acc += (unsigned long long)(I.qend - I.qbegin) * (unsigned long long)(r.end - r.begin);
@@ -700,6 +756,9 @@ RangeGeom range_geom(const Grid &g) {
         rg.m[j] = g.m[j];
         rg.stride[j] = g.stride[j];
     }
+    rg.sb = g.sub_bits;
+    rg.lo_last = g.k > 0 ? g.lo[g.k - 1] : 0.0;
+    rg.w = g.w;
     return rg;
 }
 
@@ -799,6 +858,11 @@ static void choose_geometry(Grid &g, int index_dims) {
     int bits = 0;
     while (bits < 64 && (maxkey >> bits) != 0ull) ++bits;
     g.key_bits = bits;
+    // sub-cell bits fill the last 8-bit radix digit (at least 5 of them: one
+    // more digit when fewer are free); none in the index-free form
+    int sb = (bits + 7) / 8 * 8 - bits;
+    if (sb < 5) sb += 8;
+    g.sub_bits = index_dims < 0 ? 0 : std::min(sb, 64 - bits);
     g.nranges = 1;
     for (int j = 0; j < k - 1; ++j) g.nranges *= 3;
 }
@@ -856,6 +920,7 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
         KeyGeom geo{};
         geo.k = g.k;
         geo.d = d;
+        geo.sb = g.sub_bits;
         geo.w = g.w;
         for (int j = 0; j < g.k; ++j) {
             geo.lo[j] = g.lo[j];
@@ -871,7 +936,7 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
         const int nb = (int)std::max<int64_t>(1, (n + kRsTile - 1) / kRsTile);
         int32_t *hist = dev_alloc_n<int32_t>((size_t)nb * 256, s);
         int32_t *hist_ex = dev_alloc_n<int32_t>((size_t)nb * 256, s);
-        for (int shift = 0; shift < g.key_bits; shift += 8) {
+        for (int shift = 0; shift < g.key_bits + g.sub_bits; shift += 8) {
             hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kThreads), 0, s, key_a, n, shift, hist, nb);
             SJ_HIP(hipGetLastError());
             exclusive_scan<int32_t, int32_t>(hist, hist_ex, (int64_t)nb * 256, s);
@@ -935,10 +1000,10 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     int32_t *nitem = dev_alloc_n<int32_t>(n + 1, s);
     int32_t *item_off = dev_alloc_n<int32_t>(n + 1, s);
     if (n > 0) {
-        hipLaunchKernelGGL(k_cell_flags, dim3(blocks_for(n)), dim3(kThreads), 0, s, key_a, n, flag);
+        hipLaunchKernelGGL(k_cell_flags, dim3(blocks_for(n)), dim3(kThreads), 0, s, key_a, n, g.sub_bits, flag);
         SJ_HIP(hipGetLastError());
         exclusive_scan<int32_t, int32_t>(flag, cid, n, s);
-        hipLaunchKernelGGL(k_cell_write, dim3(blocks_for(n)), dim3(kThreads), 0, s, key_a, flag, cid, n,
+        hipLaunchKernelGGL(k_cell_write, dim3(blocks_for(n)), dim3(kThreads), 0, s, key_a, g.sub_bits, flag, cid, n,
                            g.cell_key, g.cell_start, counters + 0);
         SJ_HIP(hipGetLastError());
         // lines (cells grid-stride bounded by n)
@@ -988,7 +1053,8 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
                            g.blocks, counters + 3);
         SJ_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_item_ranges, dim3(2048), dim3(kThreads), 0, s, g.item, counters + 2, g.cell_key,
-                           g.cell_start, counters + 0, range_geom(g), g.line_table, g.line_first, g.ranges, acc);
+                           g.cell_start, counters + 0, range_geom(g), g.line_table, g.line_first, key_a, g.xs,
+                           g.dp, g.ranges, acc);
         SJ_HIP(hipGetLastError());
         // tile offsets of the items (for the per-tile in-masks of the count pass)
         hipLaunchKernelGGL(k_item_tiles, dim3(blocks_for(items_ub + 1)), dim3(kThreads), 0, s, g.ranges,

@@ -104,7 +104,9 @@ struct Grid {
     double mid[kMaxDims];  // centring reference of xa
     int64_t m[kMaxIndexDims];
     int64_t stride[kMaxIndexDims];
-    int32_t key_bits = 0;
+    int32_t key_bits = 0;  // bits of the cell key
+    int32_t sub_bits = 0;  // bits appended to the sort key: position inside the cell along the last
+                           // indexed dimension, so a line's points are in coordinate order there
     int64_t cells = 0;
     int64_t items = 0;
     int64_t nblocks = 0;

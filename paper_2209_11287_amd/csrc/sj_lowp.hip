@@ -315,11 +315,17 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
         wave_lds_sync();
     };
 
-    // union of the ranges of the block's items (same line: contiguous)
+    // per neighbour line, the span of the block's items' ranges (the items'
+    // ranges may be cut to their own coordinate extents)
     int rb = 0, re = 0;
     if (lane < G.nranges) {
         rb = G.ranges[(int64_t)ib * G.nranges + lane].begin;
-        re = G.ranges[(int64_t)(ie - 1) * G.nranges + lane].end;
+        re = G.ranges[(int64_t)ib * G.nranges + lane].end;
+        for (int it = ib + 1; it < ie; ++it) {
+            const Range r = G.ranges[(int64_t)it * G.nranges + lane];
+            rb = min(rb, r.begin);
+            re = max(re, r.end);
+        }
     }
     for (int o = 0; o < G.nranges; ++o) {
         const int cb = __builtin_amdgcn_readlane(rb, o);
