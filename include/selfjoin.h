@@ -143,6 +143,20 @@ sj_status selfjoin_build_grid(const double *points, int64_t n, int32_t d, double
 sj_status selfjoin_count(sj_grid *g, sj_path path, int32_t *per_point, int64_t *total,
                          sj_stats *stats, void *stream);
 
+/* Core points of density-based clustering (DBSCAN, named in Section I as a
+ * consumer of these distance calculations): point i is core when its
+ * eps-neighbourhood, itself included, holds at least min_pts points, i.e.
+ * the per-point count of selfjoin_count is >= min_pts.
+ *  min_pts : >= 1.
+ *  is_core : device uint8[n] in the input order (1 = core, 0 = not), or NULL
+ *            when n = 0.
+ *  ncore   : host, receives the number of core points.
+ * Uses the handle's cached counts (any path gives the same exact counts) or
+ * runs the count with `path` first. Errors: SJ_ERR_INVALID for bad
+ * arguments, SJ_ERR_OOM, SJ_ERR_HIP. */
+sj_status selfjoin_core_points(sj_grid *g, sj_path path, int32_t min_pts, uint8_t *is_core, int64_t *ncore,
+                               void *stream);
+
 /* Writes pairs of R, one chunk per call (result batching, Section III-B:
  * the result may exceed device memory).
  *  cursor      : first query to emit, in the grid's query order (0 = start;

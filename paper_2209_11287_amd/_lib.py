@@ -21,6 +21,7 @@ PATHS = {"fp64_valu": 0, "fp64_mfma": 1, "fp32_mfma": 2, "bf16_mfma": 3}
 EXPORTS = [
     "selfjoin_build_grid",
     "selfjoin_count",
+    "selfjoin_core_points",
     "selfjoin_pairs",
     "selfjoin_measure_error",
     "selfjoin_grid_info",
@@ -102,6 +103,8 @@ def load():
                                         ctypes.POINTER(sj_opts), _vp, ctypes.POINTER(_vp)]
     lib.selfjoin_count.restype = ctypes.c_int
     lib.selfjoin_count.argtypes = [_vp, ctypes.c_int, _vp, _i64p, ctypes.POINTER(sj_stats), _vp]
+    lib.selfjoin_core_points.restype = ctypes.c_int
+    lib.selfjoin_core_points.argtypes = [_vp, ctypes.c_int, ctypes.c_int32, _vp, _i64p, _vp]
     lib.selfjoin_pairs.restype = ctypes.c_int
     lib.selfjoin_pairs.argtypes = [_vp, ctypes.c_int, _i64, _vp, _vp, _i64, _i64p, _i64p,
                                    ctypes.POINTER(sj_stats), _vp]

@@ -19,6 +19,27 @@ thread_local std::string g_err;
 
 __global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
 
+// Core flags in the input order and their number (one counter atomic per
+// block).
+__global__ void k_core_flags(const int32_t *__restrict__ cnt, const int32_t *__restrict__ perm, int64_t n,
+                             int32_t min_pts, uint8_t *__restrict__ is_core, unsigned long long *__restrict__ ncore) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool core = false;
+    if (i < n) {
+        core = cnt[i] >= min_pts;
+        is_core[perm[i]] = core ? 1 : 0;
+    }
+    __shared__ unsigned part[256 / 64];
+    const unsigned c = (unsigned)__popcll(__ballot(core));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned t = 0;
+        for (int w = 0; w < 256 / 64; ++w) t += part[w];
+        if (t) atomicAdd(ncore, (unsigned long long)t);
+    }
+}
+
 __global__ void k_scatter_counts(const int32_t *__restrict__ cnt, const int32_t *__restrict__ perm, int64_t n,
                                  int32_t *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -263,6 +284,37 @@ sj_status selfjoin_count(sj_grid *gh, sj_path path, int32_t *per_point, int64_t 
         stats->ms_kernel = ro.kt.ms();
         stats->tiles_pruned = ro.tiles_pruned;
     }
+    return SJ_OK;
+    SJ_API_END
+}
+
+sj_status selfjoin_core_points(sj_grid *gh, sj_path path, int32_t min_pts, uint8_t *is_core, int64_t *ncore,
+                               void *stream) {
+    set_error("");
+    if (!gh) return invalid("grid is NULL");
+    if (!valid_path(path)) return invalid("unknown path");
+    if (min_pts < 1) return invalid("min_pts must be >= 1");
+    if (!ncore) return invalid("ncore is NULL");
+    if (gh->g.n > 0 && !is_core) return invalid("is_core is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SJ_API_BEGIN
+    Grid &g = gh->g;
+    if (!g.have_counts) {
+        RefineOut ro;
+        compute_counts(g, path, ro, s);
+    }
+    unsigned long long hc = 0;
+    if (g.n > 0) {
+        unsigned long long *dc = dev_alloc_n<unsigned long long>(1, s);
+        fill_zero(dc, sizeof(unsigned long long), s);
+        hipLaunchKernelGGL(k_core_flags, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s, g.cnt, g.perm, g.n,
+                           min_pts, is_core, dc);
+        SJ_HIP(hipGetLastError());
+        SJ_HIP(hipMemcpyAsync(&hc, dc, sizeof hc, hipMemcpyDeviceToHost, s));
+        SJ_HIP(hipStreamSynchronize(s));
+        dev_free(dc, s);
+    }
+    *ncore = (int64_t)hc;
     return SJ_OK;
     SJ_API_END
 }

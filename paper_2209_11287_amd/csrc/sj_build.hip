@@ -628,6 +628,23 @@ __device__ __forceinline__ void block_add(unsigned long long v, unsigned long lo
     }
 }
 
+// Extent of each work item's queries along the last indexed dimension
+// (xs: sorted rows, stride dp): ext[2 it] = min, ext[2 it + 1] = max.
+__global__ void k_item_extent(const Item *__restrict__ items, const int32_t *__restrict__ nitems_p,
+                              const double *__restrict__ xs, int dp, int kl, double *__restrict__ ext) {
+    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= *nitems_p) return;
+    const Item I = items[it];
+    double lo = INFINITY, hi = -INFINITY;
+    for (int q = I.qbegin; q < I.qend; ++q) {
+        const double x = xs[(int64_t)q * dp + kl];
+        lo = fmin(lo, x);
+        hi = fmax(hi, x);
+    }
+    ext[2 * it] = lo;
+    ext[2 * it + 1] = hi;
+}
+
 // Ranges of every work item (grid-stride over item x offset), plus the
 // number of candidate pairs the items see. A range starts as the cells
 // c_first - 1 .. c_last + 1 of a neighbour line; with sub-cell bits it is cut
@@ -638,7 +655,7 @@ __global__ void k_item_ranges(const Item *__restrict__ items, const int32_t *__r
                               const int64_t *__restrict__ cell_key, const int32_t *__restrict__ cell_start,
                               const int32_t *__restrict__ ncells_p, RangeGeom geo,
                               const int32_t *__restrict__ line_of_key, const int32_t *__restrict__ line_first,
-                              const unsigned long long *__restrict__ skey, const double *__restrict__ xs, int dp,
+                              const unsigned long long *__restrict__ skey, const double *__restrict__ ext,
                               Range *__restrict__ ranges, unsigned long long *__restrict__ cand_items) {
     const int64_t total = (int64_t)(*nitems_p) * geo.nranges;
     const int64_t ncells = *ncells_p;
@@ -660,12 +677,7 @@ __global__ void k_item_ranges(const Item *__restrict__ items, const int32_t *__r
             const int64_t hi_c = c1[kl] < mlast - 1 ? c1[kl] + 1 : c1[kl];
             r = line_segment(cell_key, cell_start, ncells, line_of_key, line_first, base, mlast, lo_c, hi_c);
             if (geo.sb > 0 && r.end > r.begin) {
-                double xmin = INFINITY, xmax = -INFINITY;
-                for (int q = I.qbegin; q < I.qend; ++q) {
-                    const double x = xs[(int64_t)q * dp + kl];
-                    xmin = fmin(xmin, x);
-                    xmax = fmax(xmax, x);
-                }
+                const double xmin = ext[2 * it], xmax = ext[2 * it + 1];
                 const double wm = geo.w * (1.0 + 0x1p-20);
                 const unsigned long long klo = line_pos_key(base, xmin - wm, geo);
                 const unsigned long long khi = line_pos_key(base, xmax + wm, geo);
@@ -1052,10 +1064,18 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
         hipLaunchKernelGGL(k_blocks, dim3(blocks_for(items_ub)), dim3(kThreads), 0, s, flag, cid, counters + 2,
                            g.blocks, counters + 3);
         SJ_HIP(hipGetLastError());
+        double *ext = nullptr;  // item extents on the last indexed dimension (range trimming)
+        if (g.sub_bits > 0) {
+            ext = dev_alloc_n<double>(2 * (size_t)items_ub, s);
+            hipLaunchKernelGGL(k_item_extent, dim3(blocks_for(items_ub)), dim3(kThreads), 0, s, g.item,
+                               counters + 2, g.xs, g.dp, g.k - 1, ext);
+            SJ_HIP(hipGetLastError());
+        }
         hipLaunchKernelGGL(k_item_ranges, dim3(2048), dim3(kThreads), 0, s, g.item, counters + 2, g.cell_key,
-                           g.cell_start, counters + 0, range_geom(g), g.line_table, g.line_first, key_a, g.xs,
-                           g.dp, g.ranges, acc);
+                           g.cell_start, counters + 0, range_geom(g), g.line_table, g.line_first, key_a, ext,
+                           g.ranges, acc);
         SJ_HIP(hipGetLastError());
+        if (ext) dev_free(ext, s);
         // tile offsets of the items (for the per-tile in-masks of the count pass)
         hipLaunchKernelGGL(k_item_tiles, dim3(blocks_for(items_ub + 1)), dim3(kThreads), 0, s, g.ranges,
                            counters + 2, g.nranges, item_tiles);

@@ -99,6 +99,21 @@ def selfjoin_count(g: GridHandle, path="fp64_mfma", per_point: bool = False, str
     return total.value, pp, stats.as_dict()
 
 
+def selfjoin_core_points(g: GridHandle, min_pts: int, path="fp64_mfma", stream=None):
+    """DBSCAN core points: returns (uint8 CUDA tensor, 1 = core, input order;
+    number of core points). Reuses the handle's counts or counts with `path`."""
+    torch = _torch()
+    lib = _lib.load()
+    flags = torch.empty(g.n, dtype=torch.uint8, device=g.device)
+    ncore = ctypes.c_int64(0)
+    with torch.cuda.device(g.device):
+        st = lib.selfjoin_core_points(g.ptr, _path_id(path), int(min_pts),
+                                      ctypes.c_void_p(flags.data_ptr()) if g.n else None, ctypes.byref(ncore),
+                                      _stream_ptr(stream))
+    check(st, "selfjoin_core_points")
+    return flags, ncore.value
+
+
 def selfjoin_pairs(g: GridHandle, path, cursor: int, pairs, d2=None, capacity=None, stream=None):
     """Writes one chunk into `pairs` (int32 CUDA tensor (capacity, 2)) and
     optionally `d2` (float64 CUDA tensor (capacity,)). Returns
@@ -167,6 +182,9 @@ class SelfJoin:
 
     def count(self, path="fp64_mfma", per_point=False):
         return selfjoin_count(self.grid, path, per_point, self.stream)
+
+    def core_points(self, min_pts, path="fp64_mfma"):
+        return selfjoin_core_points(self.grid, min_pts, path, self.stream)
 
     def all_pairs(self, path="fp64_mfma", want_d2=False, capacity=None):
         """All pairs as one (|R|, 2) int32 tensor (and d2), chunked if

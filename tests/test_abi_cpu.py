@@ -85,6 +85,7 @@ def test_calls_on_null_grid_rejected(lib):
                                       None) == _lib.SJ_ERR_INVALID
     info = _lib.sj_grid_info()
     assert lib.selfjoin_grid_info(None, ctypes.byref(info), None) == _lib.SJ_ERR_INVALID
+    assert lib.selfjoin_core_points(None, 1, 4, None, ctypes.byref(w), None) == _lib.SJ_ERR_INVALID
     lib.selfjoin_free_grid(None, None)  # accepted
 
 

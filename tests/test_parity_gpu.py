@@ -224,6 +224,31 @@ def test_index_free_mode_matches_oracle(path, dist, n, d):
     assert np.array_equal(d2[np.argsort(ko)].view(np.int64), g["d2"][np.argsort(kg)].view(np.int64))
 
 
+@pytest.mark.parametrize("path", ["fp64_mfma", "bf16_mfma"])
+def test_core_points_match_oracle_counts(path):
+    """DBSCAN core points (point i is core iff its eps-neighbourhood, itself
+    included, holds >= min_pts points) from the oracle's per-point counts;
+    min_pts below, at and above the typical count, and min_pts = 1 (every
+    point is core: the self-pair)."""
+    import torch
+    import oracle
+    from paper_2209_11287_amd import SelfJoin
+    X = gen.make("expo", 6007, 3, seed=23)
+    eps = _eps_for(X, 12)
+    _, pp = oracle.grid_count(X, eps)[:2]
+    sj = SelfJoin(torch.from_numpy(X).to("cuda:0"), eps)
+    try:
+        for i, m in enumerate([1, 5, int(np.median(pp)), int(pp.max()), int(pp.max()) + 1]):
+            if i == 1:
+                sj.count(path)  # later calls reuse the cached counts
+            flags, ncore = sj.core_points(m, path)
+            want = (pp >= m).astype(np.uint8)
+            assert ncore == int(want.sum()), m
+            assert np.array_equal(flags.cpu().numpy(), want), m
+    finally:
+        sj.close()
+
+
 @pytest.mark.parametrize("path", LOWP)
 def test_lowp_rejects_large_d(path):
     import torch
