@@ -78,10 +78,16 @@ struct LpOut {
 
 __device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Hardware block b runs on XCD b % 8: chunks of kXcdChunk consecutive logical
+// blocks (adjacent block items share candidates in one L2) are dealt
+// round-robin to the XCDs, spreading dense regions of the index; a final
+// partial round keeps the hardware order.
+constexpr int kXcdChunk = 16;
 __device__ __forceinline__ int xcd_block(int b, int nb) {
-    const int q = nb >> 3, r = nb & 7;
-    const int x = b & 7;
-    return x * q + min(x, r) + (b >> 3);
+    const int full = nb / (8 * kXcdChunk) * (8 * kXcdChunk);
+    if (b >= full) return b;
+    const int x = b & 7, k = b >> 3;
+    return ((k / kXcdChunk) * 8 + x) * kXcdChunk + (k % kXcdChunk);
 }
 
 __device__ __forceinline__ unsigned long long lanemask_lt() {

@@ -59,12 +59,18 @@ struct RefOut {
 
 enum { MODE_COUNT = 0, MODE_EMIT = 1, MODE_MEASURE = 2 };
 
-// Blocks go round-robin over the 8 XCDs; give each XCD a contiguous run of
-// logical blocks so spatially adjacent work items share that XCD's L2.
+// Blocks go round-robin over the 8 XCDs (hardware block b runs on XCD b % 8).
+// Logical blocks come in chunks of kXcdChunk consecutive ones, so spatially
+// adjacent work items (which share candidates) share one XCD's L2; the chunks
+// are dealt round-robin to the XCDs, so dense regions of the index (whose
+// items are long) spread over all of them. A final partial round keeps the
+// hardware order.
+constexpr int kXcdChunk = 16;
 __device__ __forceinline__ int xcd_block(int b, int nb) {
-    const int q = nb >> 3, r = nb & 7;
-    const int x = b & 7;
-    return x * q + min(x, r) + (b >> 3);
+    const int full = nb / (8 * kXcdChunk) * (8 * kXcdChunk);
+    if (b >= full) return b;
+    const int x = b & 7, k = b >> 3;
+    return ((k / kXcdChunk) * 8 + x) * kXcdChunk + (k % kXcdChunk);
 }
 
 __device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
