@@ -259,14 +259,22 @@ __global__ void k_scan_sums(const Tin *__restrict__ in, int64_t n, Tacc *__restr
     }
 }
 
-// Exclusive scan of one tile with a carry-in from `carry` (nullable): each
-// thread scans kScanItems consecutive elements, the thread totals are scanned
-// across the wave and the block.
+// Exclusive scan of one tile with a carry-in: carry[tile] (scanned tile
+// sums), or the sum of sums[0 .. tile) taken here (raw tile sums), or none.
+// Each thread scans kScanItems consecutive elements, the thread totals are
+// scanned across the wave and the block.
 template <typename Tin, typename Tacc>
 __global__ void k_scan_tiles(const Tin *__restrict__ in, Tacc *__restrict__ out, int64_t n,
-                             const Tacc *__restrict__ carry) {
+                             const Tacc *__restrict__ carry, const Tacc *__restrict__ sums) {
     __shared__ Tacc wsum[kThreads / 64];
+    __shared__ Tacc csum[kThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    Tacc c = 0;
+    if (!carry && sums) {
+        for (int64_t t = tid; t < (int64_t)blockIdx.x; t += kThreads) c += sums[t];
+        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+        if (lane == 0) csum[wave] = c;
+    }
     const int64_t e0 = (int64_t)blockIdx.x * kScanTile + (int64_t)tid * kScanItems;
     Tacc v[kScanItems];
     Tacc sum = 0;
@@ -282,7 +290,10 @@ __global__ void k_scan_tiles(const Tin *__restrict__ in, Tacc *__restrict__ out,
     }
     if (lane == 63) wsum[wave] = x;
     __syncthreads();
-    Tacc pre = carry ? carry[blockIdx.x] : (Tacc)0;
+    Tacc pre = 0;
+    if (carry) pre = carry[blockIdx.x];
+    else if (sums)
+        for (int w = 0; w < kThreads / 64; ++w) pre += csum[w];
     for (int w = 0; w < wave; ++w) pre += wsum[w];
     Tacc run = pre + x - sum;
 #pragma unroll
@@ -298,8 +309,18 @@ void exclusive_scan(const Tin *in, Tacc *out, int64_t n, hipStream_t s) {
     const int64_t tiles = (n + kScanTile - 1) / kScanTile;
     if (tiles == 1) {
         hipLaunchKernelGGL((k_scan_tiles<Tin, Tacc>), dim3(1), dim3(kThreads), 0, s, in, out, n,
-                           (const Tacc *)nullptr);
+                           (const Tacc *)nullptr, (const Tacc *)nullptr);
         SJ_HIP(hipGetLastError());
+        return;
+    }
+    if (tiles <= 8192) {  // two launches: tile sums, then tiles that add up the sums before them
+        Tacc *sums = dev_alloc_n<Tacc>(tiles, s);
+        hipLaunchKernelGGL((k_scan_sums<Tin, Tacc>), dim3((unsigned)tiles), dim3(kThreads), 0, s, in, n, sums);
+        SJ_HIP(hipGetLastError());
+        hipLaunchKernelGGL((k_scan_tiles<Tin, Tacc>), dim3((unsigned)tiles), dim3(kThreads), 0, s, in, out, n,
+                           (const Tacc *)nullptr, (const Tacc *)sums);
+        SJ_HIP(hipGetLastError());
+        dev_free(sums, s);
         return;
     }
     Tacc *sums = dev_alloc_n<Tacc>(tiles, s);
@@ -308,7 +329,7 @@ void exclusive_scan(const Tin *in, Tacc *out, int64_t n, hipStream_t s) {
     SJ_HIP(hipGetLastError());
     exclusive_scan<Tacc, Tacc>(sums, sums_ex, tiles, s);
     hipLaunchKernelGGL((k_scan_tiles<Tin, Tacc>), dim3((unsigned)tiles), dim3(kThreads), 0, s, in, out, n,
-                       (const Tacc *)sums_ex);
+                       (const Tacc *)sums_ex, (const Tacc *)nullptr);
     SJ_HIP(hipGetLastError());
     dev_free(sums, s);
     dev_free(sums_ex, s);
@@ -547,20 +568,8 @@ struct RangeGeom {
     int k, nranges;
     int64_t m[kMaxIndexDims];
     int64_t stride[kMaxIndexDims];
-    int sb;          // sub-cell bits of the sorted keys (0: no trimming)
-    double lo_last;  // grid origin on the last indexed dimension
-    double w;        // cell side
+    int sb;  // sub-cell bits of the sorted keys (0: no trimming)
 };
-
-// Sort key (cell key and sub-cell bits) of coordinate x on line `base`, by
-// the same arithmetic as k_keys (monotone in x).
-__device__ __forceinline__ unsigned long long line_pos_key(int64_t base, double x, const RangeGeom &geo) {
-    const int kl = geo.k - 1;
-    const double t = __ddiv_rn(__dsub_rn(x, geo.lo_last), geo.w);
-    int64_t c = (int64_t)floor(t);
-    c = c < 0 ? 0 : (c > geo.m[kl] - 1 ? geo.m[kl] - 1 : c);
-    return ((unsigned long long)(base + c) << geo.sb) | sub_cell(t, c, geo.sb);
-}
 
 // Sorted-point range [begin, end) of the cells of line `base` (key of the
 // line with last coordinate 0) whose last coordinate is in [lo_c, hi_c].
@@ -628,35 +637,21 @@ __device__ __forceinline__ void block_add(unsigned long long v, unsigned long lo
     }
 }
 
-// Extent of each work item's queries along the last indexed dimension
-// (xs: sorted rows, stride dp): ext[2 it] = min, ext[2 it + 1] = max.
-__global__ void k_item_extent(const Item *__restrict__ items, const int32_t *__restrict__ nitems_p,
-                              const double *__restrict__ xs, int dp, int kl, double *__restrict__ ext) {
-    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (it >= *nitems_p) return;
-    const Item I = items[it];
-    double lo = INFINITY, hi = -INFINITY;
-    for (int q = I.qbegin; q < I.qend; ++q) {
-        const double x = xs[(int64_t)q * dp + kl];
-        lo = fmin(lo, x);
-        hi = fmax(hi, x);
-    }
-    ext[2 * it] = lo;
-    ext[2 * it + 1] = hi;
-}
-
 // Ranges of every work item (grid-stride over item x offset), plus the
 // number of candidate pairs the items see. A range starts as the cells
-// c_first - 1 .. c_last + 1 of a neighbour line; with sub-cell bits it is cut
-// to the points whose last indexed coordinate lies within w (1 + 2^-20) of
-// the item's queries' (any pair within eps differs by at most eps < w there),
-// by two binary searches over the sorted keys.
+// c_first - 1 .. c_last + 1 of a neighbour line. With sub-cell bits a point's
+// position along the line is p = c_last * 2^sb + sub = floor(t 2^sb) (clamped,
+// monotone), t = fl(fl(x - lo) / w); a pair within eps differs by less than
+// w on the last indexed dimension, so by at most 2^sb in p. The range is cut
+// to positions [p(first query) - 2^sb - 1, p(last query) + 2^sb + 1] (the
+// item's queries are in key order) by two binary searches over the sorted
+// keys.
 __global__ void k_item_ranges(const Item *__restrict__ items, const int32_t *__restrict__ nitems_p,
                               const int64_t *__restrict__ cell_key, const int32_t *__restrict__ cell_start,
                               const int32_t *__restrict__ ncells_p, RangeGeom geo,
                               const int32_t *__restrict__ line_of_key, const int32_t *__restrict__ line_first,
-                              const unsigned long long *__restrict__ skey, const double *__restrict__ ext,
-                              Range *__restrict__ ranges, unsigned long long *__restrict__ cand_items) {
+                              const unsigned long long *__restrict__ skey, Range *__restrict__ ranges,
+                              unsigned long long *__restrict__ cand_items) {
     const int64_t total = (int64_t)(*nitems_p) * geo.nranges;
     const int64_t ncells = *ncells_p;
     const int kl = geo.k - 1;
@@ -677,10 +672,14 @@ __global__ void k_item_ranges(const Item *__restrict__ items, const int32_t *__r
             const int64_t hi_c = c1[kl] < mlast - 1 ? c1[kl] + 1 : c1[kl];
             r = line_segment(cell_key, cell_start, ncells, line_of_key, line_first, base, mlast, lo_c, hi_c);
             if (geo.sb > 0 && r.end > r.begin) {
-                const double xmin = ext[2 * it], xmax = ext[2 * it + 1];
-                const double wm = geo.w * (1.0 + 0x1p-20);
-                const unsigned long long klo = line_pos_key(base, xmin - wm, geo);
-                const unsigned long long khi = line_pos_key(base, xmax + wm, geo);
+                const unsigned long long sub = (1ull << geo.sb) - 1ull;
+                const unsigned long long kf = skey[I.qbegin], kb = skey[I.qend - 1];
+                const int64_t pf = (int64_t)((((kf >> geo.sb) % (unsigned long long)mlast) << geo.sb) | (kf & sub));
+                const int64_t pb = (int64_t)((((kb >> geo.sb) % (unsigned long long)mlast) << geo.sb) | (kb & sub));
+                const int64_t span = int64_t(1) << geo.sb, pmax = mlast * span - 1;
+                const int64_t plo = max(pf - span - 1, int64_t(0)), phi = min(pb + span + 1, pmax);
+                const unsigned long long klo = ((unsigned long long)base << geo.sb) + (unsigned long long)plo;
+                const unsigned long long khi = ((unsigned long long)base << geo.sb) + (unsigned long long)phi;
                 int32_t x0 = r.begin, y0 = r.end;  // first key >= klo
                 while (x0 < y0) {
                     const int32_t mid = x0 + (y0 - x0) / 2;
@@ -769,8 +768,6 @@ RangeGeom range_geom(const Grid &g) {
         rg.stride[j] = g.stride[j];
     }
     rg.sb = g.sub_bits;
-    rg.lo_last = g.k > 0 ? g.lo[g.k - 1] : 0.0;
-    rg.w = g.w;
     return rg;
 }
 
@@ -1064,18 +1061,10 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
         hipLaunchKernelGGL(k_blocks, dim3(blocks_for(items_ub)), dim3(kThreads), 0, s, flag, cid, counters + 2,
                            g.blocks, counters + 3);
         SJ_HIP(hipGetLastError());
-        double *ext = nullptr;  // item extents on the last indexed dimension (range trimming)
-        if (g.sub_bits > 0) {
-            ext = dev_alloc_n<double>(2 * (size_t)items_ub, s);
-            hipLaunchKernelGGL(k_item_extent, dim3(blocks_for(items_ub)), dim3(kThreads), 0, s, g.item,
-                               counters + 2, g.xs, g.dp, g.k - 1, ext);
-            SJ_HIP(hipGetLastError());
-        }
         hipLaunchKernelGGL(k_item_ranges, dim3(2048), dim3(kThreads), 0, s, g.item, counters + 2, g.cell_key,
-                           g.cell_start, counters + 0, range_geom(g), g.line_table, g.line_first, key_a, ext,
+                           g.cell_start, counters + 0, range_geom(g), g.line_table, g.line_first, key_a,
                            g.ranges, acc);
         SJ_HIP(hipGetLastError());
-        if (ext) dev_free(ext, s);
         // tile offsets of the items (for the per-tile in-masks of the count pass)
         hipLaunchKernelGGL(k_item_tiles, dim3(blocks_for(items_ub + 1)), dim3(kThreads), 0, s, g.ranges,
                            counters + 2, g.nranges, item_tiles);
