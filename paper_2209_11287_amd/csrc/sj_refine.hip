@@ -884,6 +884,9 @@ struct MaskBatch {
     int32_t c[4];          // sorted index of the candidate
 };
 
+// D2 (distances requested): the sorted indices (rows for the exact chain;
+// the input index is looked up per pair); otherwise the input indices.
+template <bool D2>
 __device__ __forceinline__ void mask_batch_load(MaskBatch &B, CandList &L, const unsigned long long *mb,
                                                 const DevGrid &G, int gi, int lane) {
     B.w = mb[64 * gi + lane];
@@ -893,8 +896,8 @@ __device__ __forceinline__ void mask_batch_load(MaskBatch &B, CandList &L, const
         const int P[1] = {64 * c + lane};
         int idx[1];
         cand_chunk<1>(L, c, P, idx);
-        B.c[q] = idx[0];
-        B.pc[q] = G.perm[idx[0]];
+        if (D2) B.c[q] = idx[0];
+        else B.pc[q] = G.perm[idx[0]];
     }
 }
 
@@ -970,6 +973,7 @@ constexpr int kSlot = 256;  // LDS pair slots per row group (one query's pairs o
 // drops its tile's candidates at consecutive ranks in the row group's LDS
 // slot (candidate order), and the query's run leaves the slot as contiguous
 // stores, 16 lanes per row group.
+template <bool D2>
 __device__ __forceinline__ void emit_group(unsigned long long w, const MaskBatch &cur, int64_t base[4],
                                            const int32_t pq[4], int g, int j, int lane, const DevGrid &G,
                                            const RefOut &R, int q0, int32_t *stage, int32_t *slot) {
@@ -999,7 +1003,7 @@ __device__ __forceinline__ void emit_group(unsigned long long w, const MaskBatch
     const unsigned p01 = i01 - c01, p23 = i23 - c23;
     wave_lds_sync();
 #pragma unroll
-    for (int q = 0; q < 4; ++q) stage[64 * q + lane] = R.d2 ? cur.c[q] : cur.pc[q];
+    for (int q = 0; q < 4; ++q) stage[64 * q + lane] = D2 ? cur.c[q] : cur.pc[q];
     int32_t *const own = slot + kSlot * g;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -1021,7 +1025,7 @@ __device__ __forceinline__ void emit_group(unsigned long long w, const MaskBatch
             if (k < T) {
                 const int32_t v = own[k];
                 const int64_t pos = base[r] + k;
-                if (R.d2) {
+                if (D2) {
                     reinterpret_cast<int2 *>(R.pairs)[pos] = make_int2(pq[r], G.perm[v]);
                     R.d2[pos] = exact_d2(G.xs + (int64_t)(q0 + g + 4 * r) * G.dp, G.xs + (int64_t)v * G.dp, G.d);
                 } else {
@@ -1033,6 +1037,7 @@ __device__ __forceinline__ void emit_group(unsigned long long w, const MaskBatch
     }
 }
 
+template <bool D2>
 __device__ __forceinline__ void mask_item(const DevGrid &G, const RefOut &R, const unsigned long long *masks,
                                           int it, int32_t *stage, int32_t *slot) {
     const int lane = threadIdx.x & 63;
@@ -1059,21 +1064,22 @@ __device__ __forceinline__ void mask_item(const DevGrid &G, const RefOut &R, con
     const int ngroups = (L.ntiles + 15) >> 4;
     const unsigned long long *mb = masks + G.tile_off[it] * 4;
     MaskBatch nxt;
-    if (ngroups > 0) mask_batch_load(nxt, L, mb, G, 0, lane);
+    if (ngroups > 0) mask_batch_load<D2>(nxt, L, mb, G, 0, lane);
     for (int gi = 0; gi < ngroups; ++gi) {
         const MaskBatch cur = nxt;
-        if (gi + 1 < ngroups) mask_batch_load(nxt, L, mb, G, gi + 1, lane);
-        emit_group(cur.w & ekeep, cur, base, ro.pq, g, j, lane, G, R, q0, stage, slot);
+        if (gi + 1 < ngroups) mask_batch_load<D2>(nxt, L, mb, G, gi + 1, lane);
+        emit_group<D2>(cur.w & ekeep, cur, base, ro.pq, g, j, lane, G, R, q0, stage, slot);
     }
 }
 
+template <bool D2>
 __global__ __launch_bounds__(kThreads) void k_mask_emit(DevGrid G, RefOut R, const unsigned long long *masks) {
     const int wv = uniform_i32(threadIdx.x >> 6);
     const int it = uniform_i32(R.item_lo + xcd_block(blockIdx.x, gridDim.x) * kWaves + wv);
     __shared__ int32_t stage[kWaves * 256];
     __shared__ int32_t slot[kWaves * 4 * kSlot];
     if (it >= G.nitems) return;
-    mask_item(G, R, masks, it, stage + 256 * wv, slot + 4 * kSlot * wv);
+    mask_item<D2>(G, R, masks, it, stage + 256 * wv, slot + 4 * kSlot * wv);
 }
 
 // ------------------------------------------------------------------ batch --
@@ -1439,8 +1445,12 @@ void refine_pairs(Grid &g, sj_path path, const ChunkPlan &p, int64_t qlo, int32_
         ro.kt.start(ro.timed, s);
         const unsigned blocks = (unsigned)((nitems + kWaves - 1) / kWaves);
         if (blocks) {
-            hipLaunchKernelGGL(k_mask_emit, dim3(blocks), dim3(kThreads), 0, s, dev_grid(g), R,
-                               (const unsigned long long *)g.masks);
+            if (R.d2)
+                hipLaunchKernelGGL(k_mask_emit<true>, dim3(blocks), dim3(kThreads), 0, s, dev_grid(g), R,
+                                   (const unsigned long long *)g.masks);
+            else
+                hipLaunchKernelGGL(k_mask_emit<false>, dim3(blocks), dim3(kThreads), 0, s, dev_grid(g), R,
+                                   (const unsigned long long *)g.masks);
             SJ_HIP(hipGetLastError());
         }
         ro.kt.stop(s);
