@@ -75,6 +75,14 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 
 __device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Orders one wave's LDS writes before its later reads of other lanes' slots
+// (and those reads before the next writes).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // The oracle's chain: ascending dimensions from +0.0, fl(a - b) then fma.
 __device__ __forceinline__ double exact_d2(const double *__restrict__ a, const double *__restrict__ b, int d) {
     double acc = 0.0;
@@ -685,7 +693,7 @@ __device__ __forceinline__ void v64_load(V64Tile<D> &T, int c, int n, const DevG
 constexpr int kV64LdsD = 64;
 
 template <int D, int MODE>
-__device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int it, double *qlds) {
+__device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int it, double *qlds, double *cst) {
     const int lane = threadIdx.x & 63;
     const Item I = G.items[it];
     const int q0 = uniform_i32(I.qbegin);
@@ -764,11 +772,32 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
             const double *__restrict__ b = xs + (int64_t)T.c * dp;
             auto chain = [&](auto from_lds) {
                 for (int u0 = 0; u0 < d; u0 += 16) {
-                    // the block's 16 candidate values in flight together
-                    // (indices clamped into the row; steps past d skipped)
+                    // the block's 16 candidate values of the lane's column
                     double bv[16];
+                    if (cst) {
+                        // lane (g, j) fetches dimensions u0 + 4g .. + 3 of its
+                        // candidate in two 16-byte loads (rows are 32-byte
+                        // aligned, zero-padded to dp, and followed by padding
+                        // rows); the column's 16 values meet in LDS
+                        const double2 *__restrict__ src = reinterpret_cast<const double2 *>(b + u0 + 4 * g);
+                        const double2 v0 = src[0], v1 = src[1];
+                        wave_lds_sync();
+                        double2 *dst = reinterpret_cast<double2 *>(cst + 16 * j + 4 * g);
+                        dst[0] = v0;
+                        dst[1] = v1;
+                        wave_lds_sync();
+                        const double2 *rd = reinterpret_cast<const double2 *>(cst + 16 * j);
 #pragma unroll
-                    for (int t = 0; t < 16; ++t) bv[t] = b[min(u0 + t, d - 1)];
+                        for (int t = 0; t < 8; ++t) {
+                            const double2 pr = rd[t];
+                            bv[2 * t] = pr.x;
+                            bv[2 * t + 1] = pr.y;
+                        }
+                    } else {
+                        // indices clamped into the row; steps past d skipped
+#pragma unroll
+                        for (int t = 0; t < 16; ++t) bv[t] = b[min(u0 + t, d - 1)];
+                    }
 #pragma unroll
                     for (int t = 0; t < 16; ++t) {
                         const int u = u0 + t;
@@ -862,10 +891,11 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
 template <int D, int MODE>
 __global__ __launch_bounds__(kThreads) void k_v64(DevGrid G, RefOut R) {
     __shared__ double qbuf[D == 0 ? kWaves * 16 * kV64LdsD : 1];
+    __shared__ double cbuf[D == 0 ? kWaves * 256 : 1];
     const int wv = uniform_i32(threadIdx.x >> 6);
     const int it = uniform_i32(R.item_lo + xcd_block(blockIdx.x, gridDim.x) * kWaves + wv);
     if (it >= G.nitems) return;
-    v64_item<D, MODE>(G, R, it, D == 0 ? qbuf + wv * 16 * kV64LdsD : nullptr);
+    v64_item<D, MODE>(G, R, it, D == 0 ? qbuf + wv * 16 * kV64LdsD : nullptr, D == 0 ? cbuf + wv * 256 : nullptr);
 }
 
 // ------------------------------------------------------------ mask emit --
@@ -899,14 +929,6 @@ __device__ __forceinline__ void mask_batch_load(MaskBatch &B, CandList &L, const
         if (D2) B.c[q] = idx[0];
         else B.pc[q] = G.perm[idx[0]];
     }
-}
-
-// Orders one wave's LDS writes before its later reads of other lanes' slots
-// (and those reads before the next writes).
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <int CTRL>
@@ -1099,6 +1121,8 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BProb *__restrict__ pr
                                                     unsigned long long *__restrict__ band) {
     __shared__ double vbuf[PATHV == SJ_FP64_VALU ? kWaves * 16 * kV64LdsD : 1];
     double *vq = PATHV == SJ_FP64_VALU ? vbuf + (threadIdx.x >> 6) * 16 * kV64LdsD : nullptr;
+    __shared__ double cbuf[PATHV == SJ_FP64_VALU ? kWaves * 256 : 1];
+    double *vc = PATHV == SJ_FP64_VALU ? cbuf + (threadIdx.x >> 6) * 256 : nullptr;
     const int lane = threadIdx.x & 63;
     for (;;) {
         int w = 0;
@@ -1142,12 +1166,12 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BProb *__restrict__ pr
             }
         } else {
             switch (P.G.d) {
-                case 1: v64_item<1, MODE>(P.G, R, it, nullptr); break;
-                case 2: v64_item<2, MODE>(P.G, R, it, nullptr); break;
-                case 3: v64_item<3, MODE>(P.G, R, it, nullptr); break;
-                case 4: v64_item<4, MODE>(P.G, R, it, nullptr); break;
-                case 8: v64_item<8, MODE>(P.G, R, it, nullptr); break;
-                default: v64_item<0, MODE>(P.G, R, it, vq); break;
+                case 1: v64_item<1, MODE>(P.G, R, it, nullptr, nullptr); break;
+                case 2: v64_item<2, MODE>(P.G, R, it, nullptr, nullptr); break;
+                case 3: v64_item<3, MODE>(P.G, R, it, nullptr, nullptr); break;
+                case 4: v64_item<4, MODE>(P.G, R, it, nullptr, nullptr); break;
+                case 8: v64_item<8, MODE>(P.G, R, it, nullptr, nullptr); break;
+                default: v64_item<0, MODE>(P.G, R, it, vq, vc); break;
             }
         }
     }
