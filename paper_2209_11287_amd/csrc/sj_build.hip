@@ -571,6 +571,29 @@ struct RangeGeom {
     int sb;  // sub-cell bits of the sorted keys (0: no trimming)
 };
 
+// In the sorted v[a, b): x = first index with v >= lo, y = first index with
+// v > hi (lo <= hi). The two binary searches run in lock-step, so their loads
+// issue together (these searches are latency chains).
+template <typename T>
+__device__ __forceinline__ void bounds2(const T *__restrict__ v, int64_t a, int64_t b, T lo, T hi, int64_t &x,
+                                        int64_t &y) {
+    int64_t x0 = a, y0 = b, x1 = a, y1 = b;
+    while (x0 < y0 || x1 < y1) {
+        const int64_t m0 = x0 + (y0 - x0) / 2, m1 = x1 + (y1 - x1) / 2;
+        const T v0 = v[min(m0, b - 1)], v1 = v[min(m1, b - 1)];  // b > a here
+        if (x0 < y0) {
+            if (v0 < lo) x0 = m0 + 1;
+            else y0 = m0;
+        }
+        if (x1 < y1) {
+            if (v1 <= hi) x1 = m1 + 1;
+            else y1 = m1;
+        }
+    }
+    x = x0;
+    y = x1;
+}
+
 // Sorted-point range [begin, end) of the cells of line `base` (key of the
 // line with last coordinate 0) whose last coordinate is in [lo_c, hi_c].
 __device__ __forceinline__ Range line_segment(const int64_t *__restrict__ cell_key,
@@ -586,22 +609,10 @@ __device__ __forceinline__ Range line_segment(const int64_t *__restrict__ cell_k
         a = line_first[lid];
         b = line_first[lid + 1];
     }
-    const int64_t lo = base + lo_c, hi = base + hi_c;
-    int64_t x = a, y = b;  // first cell with key >= lo
-    while (x < y) {
-        const int64_t mid = x + (y - x) / 2;
-        if (cell_key[mid] < lo) x = mid + 1;
-        else y = mid;
-    }
-    const int64_t ca = x;
-    y = b;  // first cell with key > hi
-    while (x < y) {
-        const int64_t mid = x + (y - x) / 2;
-        if (cell_key[mid] <= hi) x = mid + 1;
-        else y = mid;
-    }
+    int64_t ca, cb;  // first cell with key >= base + lo_c, first with key > base + hi_c
+    bounds2<int64_t>(cell_key, a, b, base + lo_c, base + hi_c, ca, cb);
     r.begin = cell_start[ca];
-    r.end = cell_start[x];
+    r.end = cell_start[cb];
     return r;
 }
 
@@ -662,6 +673,9 @@ __global__ void k_item_ranges(const Item *__restrict__ items, const int32_t *__r
         const int64_t it = t / geo.nranges;
         const int o = (int)(t - it * geo.nranges);
         const Item I = items[it];
+        // keys of the item's first and last query (read ahead of the searches)
+        const unsigned long long kf = geo.sb > 0 ? skey[I.qbegin] : 0ull;
+        const unsigned long long kb = geo.sb > 0 ? skey[I.qend - 1] : 0ull;
         int64_t c0[kMaxIndexDims], c1[kMaxIndexDims];
         decode_key(cell_key[I.cell_first], geo, c0);
         decode_key(cell_key[I.cell_last], geo, c1);
@@ -673,27 +687,16 @@ __global__ void k_item_ranges(const Item *__restrict__ items, const int32_t *__r
             r = line_segment(cell_key, cell_start, ncells, line_of_key, line_first, base, mlast, lo_c, hi_c);
             if (geo.sb > 0 && r.end > r.begin) {
                 const unsigned long long sub = (1ull << geo.sb) - 1ull;
-                const unsigned long long kf = skey[I.qbegin], kb = skey[I.qend - 1];
                 const int64_t pf = (int64_t)((((kf >> geo.sb) % (unsigned long long)mlast) << geo.sb) | (kf & sub));
                 const int64_t pb = (int64_t)((((kb >> geo.sb) % (unsigned long long)mlast) << geo.sb) | (kb & sub));
                 const int64_t span = int64_t(1) << geo.sb, pmax = mlast * span - 1;
                 const int64_t plo = max(pf - span - 1, int64_t(0)), phi = min(pb + span + 1, pmax);
                 const unsigned long long klo = ((unsigned long long)base << geo.sb) + (unsigned long long)plo;
                 const unsigned long long khi = ((unsigned long long)base << geo.sb) + (unsigned long long)phi;
-                int32_t x0 = r.begin, y0 = r.end;  // first key >= klo
-                while (x0 < y0) {
-                    const int32_t mid = x0 + (y0 - x0) / 2;
-                    if (skey[mid] < klo) x0 = mid + 1;
-                    else y0 = mid;
-                }
-                int32_t x1 = x0, y1 = r.end;  // first key > khi
-                while (x1 < y1) {
-                    const int32_t mid = x1 + (y1 - x1) / 2;
-                    if (skey[mid] <= khi) x1 = mid + 1;
-                    else y1 = mid;
-                }
-                r.begin = x0;
-                r.end = x1;
+                int64_t x0, x1;  // first key >= klo, first key > khi
+                bounds2<unsigned long long>(skey, r.begin, r.end, klo, khi, x0, x1);
+                r.begin = (int32_t)x0;
+                r.end = (int32_t)x1;
             }
         }
         ranges[t] = r;
