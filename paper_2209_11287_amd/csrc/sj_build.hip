@@ -278,10 +278,26 @@ __global__ void k_scan_tiles(const Tin *__restrict__ in, Tacc *__restrict__ out,
     const int64_t e0 = (int64_t)blockIdx.x * kScanTile + (int64_t)tid * kScanItems;
     Tacc v[kScanItems];
     Tacc sum = 0;
+    const bool full = e0 + kScanItems <= n;
+    if (full && sizeof(Tin) == 4) {
+        // whole run of 16: four 16-byte loads (the run starts at a 64-byte offset)
+        const int4 *p4 = reinterpret_cast<const int4 *>(in + e0);
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        v[i] = e0 + i < n ? (Tacc)in[e0 + i] : (Tacc)0;
-        sum += v[i];
+        for (int q = 0; q < kScanItems / 4; ++q) {
+            const int4 w = p4[q];
+            v[4 * q] = (Tacc)w.x;
+            v[4 * q + 1] = (Tacc)w.y;
+            v[4 * q + 2] = (Tacc)w.z;
+            v[4 * q + 3] = (Tacc)w.w;
+        }
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) sum += v[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            v[i] = e0 + i < n ? (Tacc)in[e0 + i] : (Tacc)0;
+            sum += v[i];
+        }
     }
     Tacc x = sum;
     for (int o = 1; o < 64; o <<= 1) {
@@ -296,10 +312,38 @@ __global__ void k_scan_tiles(const Tin *__restrict__ in, Tacc *__restrict__ out,
         for (int w = 0; w < kThreads / 64; ++w) pre += csum[w];
     for (int w = 0; w < wave; ++w) pre += wsum[w];
     Tacc run = pre + x - sum;
+    if (full && sizeof(Tacc) == 4) {
+        int4 *o4 = reinterpret_cast<int4 *>(out + e0);
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        if (e0 + i < n) out[e0 + i] = run;
-        run += v[i];
+        for (int q = 0; q < kScanItems / 4; ++q) {
+            int4 w;
+            w.x = (int)run;
+            run += v[4 * q];
+            w.y = (int)run;
+            run += v[4 * q + 1];
+            w.z = (int)run;
+            run += v[4 * q + 2];
+            w.w = (int)run;
+            run += v[4 * q + 3];
+            o4[q] = w;
+        }
+    } else if (full && sizeof(Tacc) == 8) {
+        longlong2 *o2 = reinterpret_cast<longlong2 *>(out + e0);
+#pragma unroll
+        for (int q = 0; q < kScanItems / 2; ++q) {
+            longlong2 w;
+            w.x = (long long)run;
+            run += v[2 * q];
+            w.y = (long long)run;
+            run += v[2 * q + 1];
+            o2[q] = w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            if (e0 + i < n) out[e0 + i] = run;
+            run += v[i];
+        }
     }
 }
 
