@@ -152,7 +152,6 @@ static void compute_counts(Grid &g, sj_path path, RefineOut &ro, hipStream_t s) 
     if (fp64 && !g.masks && g.tiles > 0 && g.tiles * 32 <= kMaskBudget)
         g.masks = dev_alloc_n<unsigned long long>((size_t)g.tiles * 4, s);
     ro.masks = fp64 ? g.masks : nullptr;
-    fill_zero(g.aux, 4 * sizeof(unsigned long long), s);
     hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, g.cnt + g.n, 0);
     SJ_HIP(hipGetLastError());
     if (g.n > 0) refine_count(g, path, g.cnt, ro, s);

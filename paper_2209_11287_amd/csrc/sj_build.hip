@@ -17,6 +17,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
+#include <utility>
 #include <vector>
 
 #include "sj_internal.h"
@@ -48,6 +50,36 @@ __global__ void k_fill_u8(unsigned char *p, size_t bytes, unsigned char v) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     size_t stride = (size_t)gridDim.x * blockDim.x;
     for (; i < bytes; i += stride) p[i] = v;
+}
+
+// Zeroes up to eight segments (4-byte aligned, whole 4-byte words) in one
+// launch: the build's small pads and counters.
+struct FillList {
+    uint32_t *p[8];
+    unsigned long long words[8];
+    int n;
+};
+
+__global__ void k_fill_many(FillList L) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (int k = 0; k < L.n; ++k)
+        for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.words[k]; i += stride) L.p[k][i] = 0u;
+}
+
+static void fill_zero_many(std::initializer_list<std::pair<void *, size_t>> segs, hipStream_t s) {
+    FillList L{};
+    size_t most = 0;
+    for (const auto &sg : segs) {
+        if (!sg.first || !sg.second) continue;
+        L.p[L.n] = static_cast<uint32_t *>(sg.first);
+        L.words[L.n] = sg.second / 4;
+        most = std::max(most, sg.second / 4);
+        ++L.n;
+    }
+    if (!L.n) return;
+    const unsigned blocks = (unsigned)std::min<size_t>((most + kThreads - 1) / kThreads, 1024);
+    hipLaunchKernelGGL(k_fill_many, dim3(blocks), dim3(kThreads), 0, s, L);
+    SJ_HIP(hipGetLastError());
 }
 
 void fill_ones(void *p, size_t bytes, hipStream_t s) {
@@ -1012,15 +1044,19 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     g.xs = dev_alloc_n<double>(rows * g.dp, s);
     g.xa = dev_alloc_n<double>(rows * g.da, s);
     g.nrm = dev_alloc_n<double>(rows, s);
-    if (g.da > 16) {
-        g.pn = dev_alloc_n<double>(rows, s);
-        fill_zero(g.pn + n, (size_t)kRowPad * sizeof(double), s);
-    }
+    if (g.da > 16) g.pn = dev_alloc_n<double>(rows, s);
     g.dev_nmax = dev_alloc_n<double>(1, s);
-    fill_zero(g.xs + (size_t)n * g.dp, (size_t)kRowPad * g.dp * sizeof(double), s);
-    fill_zero(g.xa + (size_t)n * g.da, (size_t)kRowPad * g.da * sizeof(double), s);
-    fill_zero(g.nrm + n, (size_t)kRowPad * sizeof(double), s);
-    fill_zero(g.dev_nmax, sizeof(double), s);  // n = 0
+    int32_t *counters = dev_alloc_n<int32_t>(4, s);                    // ncells, nlines, nitems
+    unsigned long long *acc = dev_alloc_n<unsigned long long>(2, s);  // [0] item candidates, [1] tiles
+    // padding rows, nmax (n = 0), counters: one launch
+    fill_zero_many({{g.xs + (size_t)n * g.dp, (size_t)kRowPad * g.dp * sizeof(double)},
+                    {g.xa + (size_t)n * g.da, (size_t)kRowPad * g.da * sizeof(double)},
+                    {g.nrm + n, (size_t)kRowPad * sizeof(double)},
+                    {g.pn ? g.pn + n : nullptr, (size_t)kRowPad * sizeof(double)},
+                    {g.dev_nmax, sizeof(double)},
+                    {counters, 4 * sizeof(int32_t)},
+                    {acc, 2 * sizeof(unsigned long long)}},
+                   s);
     if (n > 0) {
         const unsigned nb = d <= 4 ? std::min(blocks_for(4 * n), 4096u) : blocks_for(n);
         double *part = dev_alloc_n<double>(nb, s);
@@ -1048,8 +1084,6 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     // flags / scan scratch, reused for cells (n), lines (<= n) and items (<= n + n/16 + 1)
     int32_t *flag = dev_alloc_n<int32_t>(n + n / kTileQ + 2, s);
     int32_t *cid = dev_alloc_n<int32_t>(n + n / kTileQ + 2, s);
-    int32_t *counters = dev_alloc_n<int32_t>(4, s);  // ncells, nlines, nitems
-    fill_zero(counters, 4 * sizeof(int32_t), s);
     g.cell_key = dev_alloc_n<int64_t>(n + 1, s);
     g.cell_start = dev_alloc_n<int32_t>(n + 2, s);
     int32_t *line_first = dev_alloc_n<int32_t>(n + 2, s);
@@ -1076,8 +1110,6 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
         SJ_HIP(hipGetLastError());
     }
     // ---- G5: work items and their neighbour ranges (tables sized by upper bounds) ----
-    unsigned long long *acc = dev_alloc_n<unsigned long long>(2, s);  // [0] item candidates, [1] tiles
-    fill_zero(acc, 2 * sizeof(unsigned long long), s);
     const int64_t items_ub = n + n / kTileQ + 1;  // lines <= cells <= n
     g.tile_off = dev_alloc_n<int64_t>((size_t)items_ub + 1, s);
     int32_t *item_tiles = dev_alloc_n<int32_t>((size_t)items_ub + 1, s);

@@ -1345,9 +1345,10 @@ void launch_seg_scan(const BProb *probs, int B, int64_t *totals, hipStream_t s) 
 
 // Enqueues the count kernel; the band counter lands in ro.band_dev (device,
 // zeroed here) and is read by the caller together with the total; the FP64
-// paths count their pruned tiles in ro.aux_dev[0] (zeroed by the caller).
+// paths count their pruned tiles in ro.aux_dev[0] (= band_dev + 1, zeroed
+// here too).
 void refine_count(Grid &g, sj_path path, int32_t *cnt_sorted, RefineOut &ro, hipStream_t s) {
-    fill_zero(ro.band_dev, sizeof(unsigned long long), s);
+    fill_zero(ro.band_dev, 2 * sizeof(unsigned long long), s);  // band counter and ro.aux_dev[0] behind it
     RefOut R{};
     R.cnt = cnt_sorted;
     R.band = ro.band_dev;
@@ -1355,14 +1356,14 @@ void refine_count(Grid &g, sj_path path, int32_t *cnt_sorted, RefineOut &ro, hip
     R.masks = ro.masks;
     ro.cand_eval = g.cand_items;
     if (path == SJ_FP64_VALU) {
-        R.pruned = ro.aux_dev;  // zeroed by the caller with the band counter
+        R.pruned = ro.aux_dev;  // zeroed above with the band counter
         ro.kt.start(ro.timed, s);
         launch_v64<MODE_COUNT>(g, R, (int)g.items, s);
         ro.kt.stop(s);
         ro.band_rel = 0.0;
     } else if (path == SJ_FP64_MFMA) {
         const double delta = m64_delta(g);
-        R.pruned = ro.aux_dev;  // zeroed by the caller with the band counter
+        R.pruned = ro.aux_dev;  // zeroed above with the band counter
         ro.kt.start(ro.timed, s);
         launch_m64<MODE_COUNT>(g, R, (int)g.items, delta, s);
         ro.kt.stop(s);
