@@ -106,6 +106,7 @@ __global__ void k_bbox_partial(const double *__restrict__ X, int64_t n, int d, i
     int nonfinite = 0;
     if (tid < S && r0 < r1) {
         const int64_t e0 = r0 * d, e1 = r1 * d;
+#pragma unroll 4
         for (int64_t e = e0 + tid; e < e1; e += S) {
             double v = X[e];
             nonfinite |= !isfinite(v);
