@@ -199,23 +199,23 @@ def src_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel_key):
+def traffic_for(kernel_key, path, workload):
     """HBM bytes per launch from committed rocprofv3 --pmc summaries, only if
-    they were taken on the current kernel source."""
+    they were taken on the current kernel source, path and workload."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     try:
         t = json.load(open(p))
         e = t.get(kernel_key)
-        if e and e.get("src_hash") == src_hash():
+        if e and e.get("src_hash") == src_hash() and e.get("path") == path and e.get("workload") == workload:
             return e.get("bytes_per_launch")
     except Exception:
         return None
     return None
 
 
-def roofline(recs, path="fp64_mfma", which=None):
+def roofline(recs, path="fp64_mfma", which=None, workload="cfg2"):
     """Dominant tile kernel over the timed steps (or `which`: "emit" /
     "count"); algorithmic work per launch divided by its mean launch time
     (HIP events around the launch)."""
@@ -232,22 +232,22 @@ def roofline(recs, path="fp64_mfma", which=None):
         avg_ms = emit_ms / launches
         achieved = byts / launches / (avg_ms * 1e-3) / 1e9
         kname = {"fp64_mfma": "k_m64", "fp64_valu": "k_v64", "fp32_mfma": "k_lowp<F32>",
-                 "bf16_mfma": "k_lowp<BF16>"}[path]
+                 "bf16_mfma": "k_lowp<BF16>", "bf16x3_mfma": "k_lowp<BF16X3>"}[path]
         return {"kernel": kname + " emit (pairs)", "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic_for("emit"), "avg_launch_ms": round(avg_ms, 4),
+                "traffic": traffic_for("emit", path, workload), "avg_launch_ms": round(avg_ms, 4),
                 "algorithmic_bytes_per_launch": round(byts / launches)}
     flops = sum(2.0 * r["d"] * r["cand_ref"] for rec in recs for r in rec)
     avg_ms = count_ms / launches
     achieved = flops / launches / (avg_ms * 1e-3) / 1e12
     peak = {"fp64_mfma": FP64_PEAK_TFLOPS, "fp64_valu": FP64_PEAK_TFLOPS, "fp32_mfma": 157.3,
-            "bf16_mfma": 2500.0}[path]
+            "bf16_mfma": 2500.0, "bf16x3_mfma": 2500.0}[path]
     kname = {"fp64_mfma": "k_m64", "fp64_valu": "k_v64", "fp32_mfma": "k_lowp<F32>",
-             "bf16_mfma": "k_lowp<BF16>"}[path]
+             "bf16_mfma": "k_lowp<BF16>", "bf16x3_mfma": "k_lowp<BF16X3>"}[path]
     return {"kernel": kname + " count", "bound": "mfma" if path != "fp64_valu" else "alu",
             "achieved": round(achieved, 3),
             "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-            "traffic": traffic_for("count"), "avg_launch_ms": round(avg_ms, 4),
+            "traffic": traffic_for("count", path, workload), "avg_launch_ms": round(avg_ms, 4),
             "algorithmic_flops_per_launch": round(flops / launches)}
 
 
@@ -416,14 +416,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        # tiles in the path's precision, FP64 recheck of the band
+        "dtype": {"fp32_mfma": "f32+f64", "bf16_mfma": "bf16+f64", "bf16x3_mfma": "bf16x3+f64"}.get(args.path, "f64"),
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "path": args.path, "cand_ref_per_step": cref, "pairs_per_step": pairs,
                    "chunk": args.chunk, "streams": max(1, args.streams)},
         "per_dataset": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
                         for r in recs[-1]],
-        "roofline": dict(roofline(recs, args.path),
+        "roofline": dict(roofline(recs, args.path, workload=args.workload),
                          note="launch times measured on the caller's stream in the timed steps; with "
                               "several streams they include sharing the GPU with the other stream's kernels"),
     }
@@ -435,7 +436,7 @@ def main():
         for r in iso:
             r["cand_ref"] = cref_map[r["name"]]
         kind = "emit" if out["roofline"]["kernel"].endswith("(pairs)") else "count"
-        ri = roofline([iso], args.path, which=kind)
+        ri = roofline([iso], args.path, which=kind, workload=args.workload)
         out["roofline"]["isolated"] = {"avg_launch_ms": ri["avg_launch_ms"], "achieved": ri["achieved"],
                                        "frac": ri["frac"],
                                        "note": "one pass on a single stream after the timed steps"}

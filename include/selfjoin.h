@@ -60,12 +60,17 @@ typedef enum {
  *  SJ_FP32_MFMA : Gram-form tiles on FP32 MFMA with FP32 accumulation, inputs
  *                 centred per work group; FP64 recheck of the band.
  *  SJ_BF16_MFMA : as FP32 but BF16 inputs, FP32 accumulation.
+ *  SJ_BF16X3_MFMA : split BF16 -- each centred coordinate as hi + lo BF16
+ *                 parts (about 16 significant bits), three BF16 MFMAs per
+ *                 tile (lo.hi, hi.lo, hi.hi), FP32 accumulation; a band about
+ *                 2^5-2^8 narrower than SJ_BF16_MFMA's, same FP64 recheck.
  * (Other MFMA precisions are the paper's future work, Section V.) */
 typedef enum {
     SJ_FP64_VALU = 0,
     SJ_FP64_MFMA = 1,
     SJ_FP32_MFMA = 2,
-    SJ_BF16_MFMA = 3
+    SJ_BF16_MFMA = 3,
+    SJ_BF16X3_MFMA = 4
 } sj_path;
 
 /* Build options; pass NULL for defaults. */

@@ -165,7 +165,7 @@ static void compute_counts(Grid &g, sj_path path, RefineOut &ro, hipStream_t s) 
     g.masks_valid = ro.masks != nullptr;
     ro.band_pairs = (int64_t)aux[0];
     ro.tiles_pruned = (path == SJ_FP64_MFMA || path == SJ_FP64_VALU) ? (int64_t)aux[1] : 0;
-    if (path == SJ_FP32_MFMA || path == SJ_BF16_MFMA) {
+    if (path == SJ_FP32_MFMA || path == SJ_BF16_MFMA || path == SJ_BF16X3_MFMA) {
         double dl;
         std::memcpy(&dl, &aux[3], sizeof dl);
         ro.band_rel = g.eps2 > 0 ? dl / g.eps2 : 0.0;
@@ -211,7 +211,8 @@ static sj_status invalid(const char *msg) {
 }
 
 static bool valid_path(sj_path p) {
-    return p == SJ_FP64_VALU || p == SJ_FP64_MFMA || p == SJ_FP32_MFMA || p == SJ_BF16_MFMA;
+    return p == SJ_FP64_VALU || p == SJ_FP64_MFMA || p == SJ_FP32_MFMA || p == SJ_BF16_MFMA ||
+           p == SJ_BF16X3_MFMA;
 }
 
 extern "C" {

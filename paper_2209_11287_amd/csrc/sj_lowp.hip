@@ -1,6 +1,13 @@
-// Low-precision MFMA paths (FP32 and BF16 inputs, FP32 accumulation) with an
-// exact FP64 recheck. The paper computes its tiles in FP64 and names other
-// tensor-core precisions as future work (Section V); this is that form.
+// Low-precision MFMA paths (FP32, BF16 and split BF16 inputs, FP32
+// accumulation) with an exact FP64 recheck. The paper computes its tiles in
+// FP64 and names other tensor-core precisions as future work (Section V);
+// this is that form.
+//
+// Split BF16: each centred coordinate y is carried as hi = bf16(fl32(y)) and
+// lo = bf16(fl32(y) - hi) (the difference is exact in FP32), so hi + lo holds
+// y to about 2^-16 relative instead of BF16's 2^-8. A tile takes three BF16
+// MFMAs (lo.hi, hi.lo, hi.hi, small terms first); the lo.lo products are
+// dropped and covered by the band.
 //
 // Work unit: a block item = up to 4 consecutive 16-query work items of one
 // grid line (64 queries, one per wave row tile) sharing the union of their
@@ -50,7 +57,7 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef short short8_t __attribute__((ext_vector_type(8)));
 
 enum { MODE_COUNT = 0, MODE_EMIT = 1, MODE_MEASURE = 2 };
-enum { PREC_F32 = 0, PREC_BF16 = 1 };
+enum { PREC_F32 = 0, PREC_BF16 = 1, PREC_BF16X3 = 2 };
 
 struct LpGrid {
     const double *xs;
@@ -121,7 +128,8 @@ __device__ __forceinline__ unsigned short f32_to_bf16(float f) {
 __device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
 
 // Rounds an FP64 value to the tile precision; returns the rounded value as
-// a double (exact) and its storage bits.
+// a double (exact) and its storage bits (split BF16: hi in the low half, lo
+// in the high half; the value is hi + lo).
 template <int PREC>
 __device__ __forceinline__ double round_in(double y, unsigned &bits) {
     const float f = (float)y;  // RNE
@@ -130,8 +138,14 @@ __device__ __forceinline__ double round_in(double y, unsigned &bits) {
         return (double)f;
     }
     const unsigned short h = f32_to_bf16(f);
-    bits = h;
-    return (double)bf16_to_f32(h);
+    const float fh = bf16_to_f32(h);
+    if (PREC == PREC_BF16) {
+        bits = h;
+        return (double)fh;
+    }
+    const unsigned short l = f32_to_bf16(f - fh);  // f - fh exact
+    bits = (unsigned)h | ((unsigned)l << 16);
+    return (double)fh + (double)bf16_to_f32(l);
 }
 
 __device__ __forceinline__ double gam(double m, double u) { return m * u / (1.0 - m * u); }
@@ -140,7 +154,9 @@ __device__ __forceinline__ double gam(double m, double u) { return m * u / (1.0 
 template <int PREC>
 __device__ __forceinline__ double lp_delta(double a2, double eps, double eps2, int d, int K) {
     const double u64 = 0x1p-53, u32 = 0x1p-24;
-    const double uin = PREC == PREC_F32 ? 0x1p-24 : (0x1p-8 + 0x1p-24);  // BF16 via FP32: two roundings
+    // input rounding unit: FP32; BF16 via FP32 (two roundings); split BF16:
+    // |fl32(y) - hi| <= 2^-8 |fl32(y)| and lo rounds that to 2^-8 of itself
+    const double uin = PREC == PREC_F32 ? 0x1p-24 : PREC == PREC_BF16 ? (0x1p-8 + 0x1p-24) : (0x1p-16 + 0x1p-24 + 0x1p-39);
     const double eta = uin + u64 + uin * u64;
     const double ua = 2.0 * 0x1p-24;
     const double a = sqrt(a2 * (1.0 + 1e-12));
@@ -149,8 +165,16 @@ __device__ __forceinline__ double lp_delta(double a2, double eps, double eps2, i
     const double tau = epsp + e;
     const double b = a + tau;  // candidates beyond cannot be near the threshold
     const double A2 = a * a, B2 = b * b;
-    const double F = (u32 + gam(d, u64) + gam(K + 1, ua)) * B2 + 2.0 * gam(K + 1, ua) * a * b  // accumulation
-                     + gam(d, u64) * A2 + u32 * (eps2 + A2);                                    // threshold
+    // split BF16: 3d non-zero products per tile (the zero padding adds
+    // exactly); sum_k (|hi|+|lo|)(|hi|+|lo|) over both rows is at most
+    // (1 + 2^-6)^2 |q'||c'|, and the dropped 2 sum_k lo_q lo_c at most
+    // 2 (2^-8 (1 + 2^-6))^2 |q'||c'| <= 2^-14 a b
+    const int nt = PREC == PREC_BF16X3 ? 3 * d : K;
+    const double gk = gam(nt + 1, ua);
+    const double sp = PREC == PREC_BF16X3 ? (1.0 + 0x1p-6) * (1.0 + 0x1p-6) : 1.0;
+    const double drop = PREC == PREC_BF16X3 ? 0x1p-14 : 0.0;
+    const double F = (u32 + gam(d, u64) + gk) * B2 + (2.0 * gk * sp + drop) * a * b  // accumulation
+                     + gam(d, u64) * A2 + u32 * (eps2 + A2);                       // threshold
     return 2.0 * (F + 2.0 * tau * e + e * e + gam(d + 2, u64) * tau * tau) + (d + 2) * 0x1p-1021;
 }
 
@@ -163,6 +187,11 @@ struct Prec<PREC_F32> {
 };
 template <>
 struct Prec<PREC_BF16> {
+    static constexpr int kstep = 32;
+    typedef short8_t operand_t;
+};
+template <>
+struct Prec<PREC_BF16X3> {
     static constexpr int kstep = 32;
     typedef short8_t operand_t;
 };
@@ -189,6 +218,22 @@ template <>
 __device__ __forceinline__ float4_t lp_mfma<PREC_BF16>(short8_t a, short8_t b, float4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
+template <>
+__device__ __forceinline__ float4_t lp_mfma<PREC_BF16X3>(short8_t a, short8_t b, float4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Reads the 8 BF16 values of one lane's K slice from a row of 16-bit halves.
+__device__ __forceinline__ short8_t lds_bf16x8(const uint32_t *w) {
+    short8_t v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const uint32_t x = w[e];
+        v[2 * e] = (short)(x & 0xffffu);
+        v[2 * e + 1] = (short)(x >> 16);
+    }
+    return v;
+}
 
 template <int PREC, int MODE>
 __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
@@ -197,7 +242,8 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
     constexpr int KSTEP = Prec<PREC>::kstep;
     __shared__ double xr[kLpMaxD];                   // reference row
     __shared__ double f64t[kTC][kLpMaxD + 1];        // FP64 candidate rows
-    __shared__ uint32_t lpt[kTC * STR];              // rounded, centred rows
+    __shared__ uint32_t lpt[kTC * STR];              // rounded, centred rows (split BF16: hi)
+    __shared__ uint32_t lptl[PREC == PREC_BF16X3 ? kTC * STR : 1];  // split BF16: lo
     __shared__ float nc32[kTC];                      // their norms (FP32, accumulator init)
     __shared__ uint32_t ring_lds[MODE == MODE_EMIT ? kWaves * 3 * kRing : 1];
 
@@ -230,6 +276,7 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
     const int g = lane >> 4;
     // A operand: -2 * round(q_j - r) over K (zeros past d or for absent rows)
     typename Prec<PREC>::operand_t aq[(KMAX + KSTEP - 1) / KSTEP];
+    short8_t aql[PREC == PREC_BF16X3 ? (KMAX + KSTEP - 1) / KSTEP : 1];  // split BF16: -2 lo
     double nq_part = 0.0;
     {
         const double *qrow = G.xs + (int64_t)(q0 + (j < nq ? j : 0)) * dp;
@@ -246,20 +293,23 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
                 }
                 aq[s] = v;
             } else {
-                short8_t v;
+                short8_t v, vl;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     const int k = KSTEP * s + 8 * g + e;
-                    unsigned short h = 0;
+                    unsigned short h = 0, l = 0;
                     if (s < ks && j < nq && k < d) {
                         unsigned bits;
                         const double y = round_in<PREC>(__dsub_rn(qrow[k], xr[k]), bits);
                         nq_part = __fma_rn(y, y, nq_part);
-                        h = f32_to_bf16(-2.0f * bf16_to_f32((unsigned short)bits));  // exact
+                        h = f32_to_bf16(-2.0f * bf16_to_f32((unsigned short)(bits & 0xffffu)));  // exact
+                        l = f32_to_bf16(-2.0f * bf16_to_f32((unsigned short)(bits >> 16)));
                     }
                     v[e] = (short)h;
+                    vl[e] = (short)l;
                 }
                 aq[s] = v;
+                if constexpr (PREC == PREC_BF16X3) aql[s] = vl;
             }
         }
     }
@@ -359,7 +409,11 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
                         lpt[row * STR + k] = bits;
                     } else {
                         unsigned short *h = reinterpret_cast<unsigned short *>(lpt + row * STR);
-                        h[k] = (unsigned short)bits;
+                        h[k] = (unsigned short)(bits & 0xffffu);
+                        if constexpr (PREC == PREC_BF16X3) {
+                            unsigned short *l = reinterpret_cast<unsigned short *>(lptl + row * STR);
+                            l[k] = (unsigned short)(bits >> 16);
+                        }
                     }
                 }
                 np += __shfl_xor(np, 1);
@@ -374,21 +428,17 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
                 const float nc = nc32[crow];
                 float4_t acc = (float4_t){nc, nc, nc, nc};
                 for (int s = 0; s < ks; ++s) {
-                    typename Prec<PREC>::operand_t b;
                     if constexpr (PREC == PREC_F32) {
-                        b = __uint_as_float(lpt[crow * STR + KSTEP * s + g]);
+                        acc = lp_mfma<PREC>(aq[s], __uint_as_float(lpt[crow * STR + KSTEP * s + g]), acc);
+                    } else if constexpr (PREC == PREC_BF16) {
+                        acc = lp_mfma<PREC>(aq[s], lds_bf16x8(lpt + crow * STR + (KSTEP * s + 8 * g) / 2), acc);
                     } else {
-                        const uint32_t *w = lpt + crow * STR + (KSTEP * s + 8 * g) / 2;
-                        short8_t v;
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const uint32_t x = w[e];
-                            v[2 * e] = (short)(x & 0xffffu);
-                            v[2 * e + 1] = (short)(x >> 16);
-                        }
-                        b = v;
+                        const int o = crow * STR + (KSTEP * s + 8 * g) / 2;
+                        const short8_t bh = lds_bf16x8(lpt + o), bl = lds_bf16x8(lptl + o);
+                        acc = lp_mfma<PREC>(aql[s], bh, acc);
+                        acc = lp_mfma<PREC>(aq[s], bl, acc);
+                        acc = lp_mfma<PREC>(aq[s], bh, acc);
                     }
-                    acc = lp_mfma<PREC>(aq[s], b, acc);
                 }
                 // element r: query 4g + r, candidate t + crow
                 unsigned inm = 0, mbm = 0;
@@ -506,8 +556,10 @@ void launch_lowp(const Grid &g, sj_path path, const LpOut &R, int nblocks, hipSt
     const LpGrid G = lp_grid(g);
     if (path == SJ_FP32_MFMA)
         hipLaunchKernelGGL((k_lowp<PREC_F32, MODE>), dim3(nblocks), dim3(kThreads), 0, s, G, R);
-    else
+    else if (path == SJ_BF16_MFMA)
         hipLaunchKernelGGL((k_lowp<PREC_BF16, MODE>), dim3(nblocks), dim3(kThreads), 0, s, G, R);
+    else
+        hipLaunchKernelGGL((k_lowp<PREC_BF16X3, MODE>), dim3(nblocks), dim3(kThreads), 0, s, G, R);
     SJ_HIP(hipGetLastError());
 }
 
