@@ -383,123 +383,149 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
             re = max(re, r.end);
         }
     }
-    for (int o = 0; o < G.nranges; ++o) {
-        const int cb = __builtin_amdgcn_readlane(rb, o);
-        const int ce = __builtin_amdgcn_readlane(re, o);
-        for (int t = cb; t < ce; t += kTC) {
-            const int nvalid = min(kTC, ce - t);
-            __syncthreads();  // previous tile consumed
-            // ---- stage: 4 threads per row, K/4 columns each ----
-            {
-                const int row = tid >> 2, part = tid & 3;
-                const bool rowok = row < nvalid;
-                const double *src = G.xs + (int64_t)(t + row) * dp;  // rows < n + 64 exist
-                double np = 0.0;
-                const int cpt = KMAX / 4;  // columns per thread (upper bound)
-                for (int cc = 0; cc < cpt; ++cc) {
-                    const int k = part * cpt + cc;
-                    if (k >= K) break;
-                    const double x = (rowok && k < d) ? src[k] : 0.0;
-                    if (k < d) f64t[row][k] = x;
+    // Tiles of 64 candidates over the block's ranges, in order. The next
+    // tile's FP64 rows are loaded into registers while the current one is
+    // computed; 4 threads per row, thread `part` holding dimensions
+    // part, part + 4, ... (coalesced 32-byte runs per row).
+    constexpr int CPT = KMAX / 4;
+    const int srow = tid >> 2, part = tid & 3;
+    double pre[CPT];
+    int o_next = -1, t_next = 0, e_next = 0;
+    auto advance = [&]() -> bool {  // block-uniform
+        t_next += kTC;
+        while (t_next >= e_next) {
+            if (++o_next >= G.nranges) return false;
+            t_next = __builtin_amdgcn_readlane(rb, o_next);
+            e_next = __builtin_amdgcn_readlane(re, o_next);
+        }
+        return true;
+    };
+    auto prefetch = [&]() {
+        const bool rowok = srow < e_next - t_next;
+        const double *src = G.xs + (int64_t)(t_next + (rowok ? srow : 0)) * dp;
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) {
+            const int k = part + 4 * cc;
+            pre[cc] = (rowok && k < d) ? src[k] : 0.0;
+        }
+    };
+    bool have = advance();
+    if (have) prefetch();
+    while (have) {
+        const int t = t_next;
+        const int nvalid = min(kTC, e_next - t_next);
+        __syncthreads();  // previous tile consumed
+        // ---- stage the prefetched rows: FP64, rounded, norms ----
+        {
+            const bool rowok = srow < nvalid;
+            double np = 0.0;
+#pragma unroll
+            for (int cc = 0; cc < CPT; ++cc) {
+                const int k = part + 4 * cc;
+                if (k < K) {  // K is a multiple of 4: uniform over the row's threads
+                    const double x = pre[cc];
+                    if (k < d) f64t[srow][k] = x;
                     unsigned bits = 0;
                     double y = 0.0;
                     if (rowok && k < d) y = round_in<PREC>(__dsub_rn(x, xr[k]), bits);
                     np = __fma_rn(y, y, np);
                     if constexpr (PREC == PREC_F32) {
-                        lpt[row * STR + k] = bits;
+                        lpt[srow * STR + k] = bits;
                     } else {
-                        unsigned short *h = reinterpret_cast<unsigned short *>(lpt + row * STR);
+                        unsigned short *h = reinterpret_cast<unsigned short *>(lpt + srow * STR);
                         h[k] = (unsigned short)(bits & 0xffffu);
                         if constexpr (PREC == PREC_BF16X3) {
-                            unsigned short *l = reinterpret_cast<unsigned short *>(lptl + row * STR);
+                            unsigned short *l = reinterpret_cast<unsigned short *>(lptl + srow * STR);
                             l[k] = (unsigned short)(bits >> 16);
                         }
                     }
                 }
-                np += __shfl_xor(np, 1);
-                np += __shfl_xor(np, 2);
-                if (part == 0) nc32[row] = rowok ? (float)np : INFINITY;
             }
-            __syncthreads();
-            if (!has_q) continue;
-            for (int sub = 0; sub < kTC / 16; ++sub) {
-                if (16 * sub >= nvalid) break;
-                const int crow = 16 * sub + j;  // candidate column j of this sub-tile
-                const float nc = nc32[crow];
-                float4_t acc = (float4_t){nc, nc, nc, nc};
-                for (int s = 0; s < ks; ++s) {
-                    if constexpr (PREC == PREC_F32) {
-                        acc = lp_mfma<PREC>(aq[s], __uint_as_float(lpt[crow * STR + KSTEP * s + g]), acc);
-                    } else if constexpr (PREC == PREC_BF16) {
-                        acc = lp_mfma<PREC>(aq[s], lds_bf16x8(lpt + crow * STR + (KSTEP * s + 8 * g) / 2), acc);
-                    } else {
-                        const int o = crow * STR + (KSTEP * s + 8 * g) / 2;
-                        const short8_t bh = lds_bf16x8(lpt + o), bl = lds_bf16x8(lptl + o);
-                        acc = lp_mfma<PREC>(aql[s], bh, acc);
-                        acc = lp_mfma<PREC>(aq[s], bl, acc);
-                        acc = lp_mfma<PREC>(aq[s], bh, acc);
+            np += __shfl_xor(np, 1);
+            np += __shfl_xor(np, 2);
+            if (part == 0) nc32[srow] = rowok ? (float)np : INFINITY;
+        }
+        __syncthreads();
+        have = advance();
+        if (have) prefetch();  // in flight during this tile's MFMAs
+        if (!has_q) continue;
+        for (int sub = 0; sub < kTC / 16; ++sub) {
+            if (16 * sub >= nvalid) break;
+            const int crow = 16 * sub + j;  // candidate column j of this sub-tile
+            const float nc = nc32[crow];
+            float4_t acc = (float4_t){nc, nc, nc, nc};
+            for (int s = 0; s < ks; ++s) {
+                if constexpr (PREC == PREC_F32) {
+                    acc = lp_mfma<PREC>(aq[s], __uint_as_float(lpt[crow * STR + KSTEP * s + g]), acc);
+                } else if constexpr (PREC == PREC_BF16) {
+                    acc = lp_mfma<PREC>(aq[s], lds_bf16x8(lpt + crow * STR + (KSTEP * s + 8 * g) / 2), acc);
+                } else {
+                    const int o = crow * STR + (KSTEP * s + 8 * g) / 2;
+                    const short8_t bh = lds_bf16x8(lpt + o), bl = lds_bf16x8(lptl + o);
+                    acc = lp_mfma<PREC>(aql[s], bh, acc);
+                    acc = lp_mfma<PREC>(aq[s], bl, acc);
+                    acc = lp_mfma<PREC>(aq[s], bh, acc);
+                }
+            }
+            // element r: query 4g + r, candidate t + crow
+            unsigned inm = 0, mbm = 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                inm |= (acc[r] <= lo[r] ? 1u : 0u) << r;
+                mbm |= (acc[r] <= hi[r] ? 1u : 0u) << r;
+            }
+            if (MODE == MODE_MEASURE) {
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 4 * g + r;
+                    if (i < nq && crow < nvalid) {
+                        const double ex = exact_d2(G.xs + (int64_t)(q0 + i) * dp, &f64t[crow][0], d);
+                        if (ex <= G.eps2) {  // the per-row bound covers pairs within eps
+                            const double err = fabs((double)acc[r] - (ex - nqr[r]));
+                            maxerr = fmax(maxerr, err);
+                            if (err > dlt[r]) ++viol;
+                        }
                     }
                 }
-                // element r: query 4g + r, candidate t + crow
-                unsigned inm = 0, mbm = 0;
+            }
+            const unsigned bm = mbm & ~inm;
+            if (__any(bm != 0)) {
+                for (int r = 0; r < 4; ++r) {
+                    if (bm & (1u << r)) {
+                        const int i = 4 * g + r;
+                        const double ex = exact_d2(G.xs + (int64_t)(q0 + i) * dp, &f64t[crow][0], d);
+                        if (ex <= G.eps2) inm |= 1u << r;
+                        ++band;
+                    }
+                }
+            }
+            if (MODE == MODE_EMIT) {
+                unsigned long long bal[4];
+                int base_e = 0;
+                int pre[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    inm |= (acc[r] <= lo[r] ? 1u : 0u) << r;
-                    mbm |= (acc[r] <= hi[r] ? 1u : 0u) << r;
+                    bal[r] = __ballot(emit_r[r] && ((inm >> r) & 1u));
+                    pre[r] = base_e + __popcll(bal[r] & lt);
+                    base_e += __popcll(bal[r]);
                 }
-                if (MODE == MODE_MEASURE) {
-                    for (int r = 0; r < 4; ++r) {
-                        const int i = 4 * g + r;
-                        if (i < nq && crow < nvalid) {
-                            const double ex = exact_d2(G.xs + (int64_t)(q0 + i) * dp, &f64t[crow][0], d);
-                            if (ex <= G.eps2) {  // the per-row bound covers pairs within eps
-                                const double err = fabs((double)acc[r] - (ex - nqr[r]));
-                                maxerr = fmax(maxerr, err);
-                                if (err > dlt[r]) ++viol;
-                            }
-                        }
-                    }
-                }
-                const unsigned bm = mbm & ~inm;
-                if (__any(bm != 0)) {
-                    for (int r = 0; r < 4; ++r) {
-                        if (bm & (1u << r)) {
-                            const int i = 4 * g + r;
-                            const double ex = exact_d2(G.xs + (int64_t)(q0 + i) * dp, &f64t[crow][0], d);
-                            if (ex <= G.eps2) inm |= 1u << r;
-                            ++band;
-                        }
-                    }
-                }
-                if (MODE == MODE_EMIT) {
-                    unsigned long long bal[4];
-                    int base_e = 0;
-                    int pre[4];
+                if (base_e) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        bal[r] = __ballot(emit_r[r] && ((inm >> r) & 1u));
-                        pre[r] = base_e + __popcll(bal[r] & lt);
-                        base_e += __popcll(bal[r]);
-                    }
-                    if (base_e) {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            if (emit_r[r] && ((inm >> r) & 1u)) {
-                                const int e = (tail + pre[r]) & (kRing - 1);
-                                rcand[e] = (uint32_t)(t + crow);
-                                rrel[e] = (uint32_t)(cur[r] + __popcll(bal[r] & lt & grp));
-                                rcol[e] = (uint32_t)(4 * g + r);
-                            }
+                        if (emit_r[r] && ((inm >> r) & 1u)) {
+                            const int e = (tail + pre[r]) & (kRing - 1);
+                            rcand[e] = (uint32_t)(t + crow);
+                            rrel[e] = (uint32_t)(cur[r] + __popcll(bal[r] & lt & grp));
+                            rcol[e] = (uint32_t)(4 * g + r);
                         }
-                        tail += base_e;
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) cur[r] += __popcll(bal[r] & grp);
-                        while (tail - head >= 64) flush(64);
                     }
-                } else {
+                    tail += base_e;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) cnt[r] += (inm >> r) & 1u;
+                    for (int r = 0; r < 4; ++r) cur[r] += __popcll(bal[r] & grp);
+                    while (tail - head >= 64) flush(64);
                 }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) cnt[r] += (inm >> r) & 1u;
             }
         }
     }
