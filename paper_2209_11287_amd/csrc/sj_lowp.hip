@@ -454,7 +454,11 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
             const int crow = 16 * sub + j;  // candidate column j of this sub-tile
             const float nc = nc32[crow];
             float4_t acc = (float4_t){nc, nc, nc, nc};
-            for (int s = 0; s < ks; ++s) {
+            // unrolled over the largest K so that aq / aql are indexed
+            // statically (a runtime index selects through every register)
+#pragma unroll
+            for (int s = 0; s < (KMAX + KSTEP - 1) / KSTEP; ++s) {
+                if (s >= ks) break;  // block-uniform
                 if constexpr (PREC == PREC_F32) {
                     acc = lp_mfma<PREC>(aq[s], __uint_as_float(lpt[crow * STR + KSTEP * s + g]), acc);
                 } else if constexpr (PREC == PREC_BF16) {
