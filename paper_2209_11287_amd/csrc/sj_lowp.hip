@@ -454,21 +454,27 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
             const int crow = 16 * sub + j;  // candidate column j of this sub-tile
             const float nc = nc32[crow];
             float4_t acc = (float4_t){nc, nc, nc, nc};
-            // unrolled over the largest K so that aq / aql are indexed
-            // statically (a runtime index selects through every register)
-#pragma unroll
-            for (int s = 0; s < (KMAX + KSTEP - 1) / KSTEP; ++s) {
-                if (s >= ks) break;  // block-uniform
-                if constexpr (PREC == PREC_F32) {
+            if constexpr (PREC == PREC_F32) {
+                // up to 16 K-steps: a rolled loop, aq read by indexed moves
+                for (int s = 0; s < ks; ++s)
                     acc = lp_mfma<PREC>(aq[s], __uint_as_float(lpt[crow * STR + KSTEP * s + g]), acc);
-                } else if constexpr (PREC == PREC_BF16) {
-                    acc = lp_mfma<PREC>(aq[s], lds_bf16x8(lpt + crow * STR + (KSTEP * s + 8 * g) / 2), acc);
-                } else {
+            } else {
+                // at most 2 K-steps: unrolled over the largest K so that aq /
+                // aql are indexed statically (a runtime index would select
+                // through every register of the arrays)
+#pragma unroll
+                for (int s = 0; s < (KMAX + KSTEP - 1) / KSTEP; ++s) {
+                    if (s >= ks) break;  // block-uniform
                     const int o = crow * STR + (KSTEP * s + 8 * g) / 2;
-                    const short8_t bh = lds_bf16x8(lpt + o), bl = lds_bf16x8(lptl + o);
-                    acc = lp_mfma<PREC>(aql[s], bh, acc);
-                    acc = lp_mfma<PREC>(aq[s], bl, acc);
-                    acc = lp_mfma<PREC>(aq[s], bh, acc);
+                    const short8_t bh = lds_bf16x8(lpt + o);
+                    if constexpr (PREC == PREC_BF16) {
+                        acc = lp_mfma<PREC>(aq[s], bh, acc);
+                    } else {
+                        const short8_t bl = lds_bf16x8(lptl + o);
+                        acc = lp_mfma<PREC>(aql[s], bh, acc);
+                        acc = lp_mfma<PREC>(aq[s], bl, acc);
+                        acc = lp_mfma<PREC>(aq[s], bh, acc);
+                    }
                 }
             }
             // element r: query 4g + r, candidate t + crow
