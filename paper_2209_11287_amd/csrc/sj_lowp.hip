@@ -455,9 +455,21 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
             const float nc = nc32[crow];
             float4_t acc = (float4_t){nc, nc, nc, nc};
             if constexpr (PREC == PREC_F32) {
-                // up to 16 K-steps: a rolled loop, aq read by indexed moves
-                for (int s = 0; s < ks; ++s)
-                    acc = lp_mfma<PREC>(aq[s], __uint_as_float(lpt[crow * STR + KSTEP * s + g]), acc);
+                // up to 16 K-steps: a rolled loop (aq read by indexed moves),
+                // four K-steps per trip so their LDS reads are in flight together
+                const uint32_t *brow = lpt + crow * STR + g;
+                int s = 0;
+                for (; s + 4 <= ks; s += 4) {
+                    const float b0 = __uint_as_float(brow[KSTEP * s]);
+                    const float b1 = __uint_as_float(brow[KSTEP * (s + 1)]);
+                    const float b2 = __uint_as_float(brow[KSTEP * (s + 2)]);
+                    const float b3 = __uint_as_float(brow[KSTEP * (s + 3)]);
+                    acc = lp_mfma<PREC>(aq[s], b0, acc);
+                    acc = lp_mfma<PREC>(aq[s + 1], b1, acc);
+                    acc = lp_mfma<PREC>(aq[s + 2], b2, acc);
+                    acc = lp_mfma<PREC>(aq[s + 3], b3, acc);
+                }
+                for (; s < ks; ++s) acc = lp_mfma<PREC>(aq[s], __uint_as_float(brow[KSTEP * s]), acc);
             } else {
                 // at most 2 K-steps: unrolled over the largest K so that aq /
                 // aql are indexed statically (a runtime index would select
