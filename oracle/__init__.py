@@ -175,3 +175,31 @@ def grid_count_sample(X, eps, queries):
     if t < 0:
         raise ValueError("invalid input")
     return counts[:len(q)], cref.value
+
+
+def knn_within_eps(X, eps, k):
+    """k nearest neighbours of every point among the points within eps of it
+    (the self-join result R of Eq. (1), Section II-A, reused for kNN as
+    Section I names it), the point itself excluded, ordered by the exact
+    squared distance of Eq. (2) and then by the smaller index.
+    Returns (nbr [n, k] int32, -1 past the end; d2 [n, k], +inf past the
+    end; found [n] int32)."""
+    X = _pts(X)
+    n = X.shape[0]
+    _, _, pairs, dd = grid_pairs(X, eps, want_d2=True)
+    i, j = pairs[:, 0].astype(np.int64), pairs[:, 1].astype(np.int64)
+    keep = i != j
+    i, j, dd = i[keep], j[keep], dd[keep]
+    order = np.lexsort((j, dd, i))  # by query, then distance, then index
+    i, j, dd = i[order], j[order], dd[order]
+    nbr = np.full((n, k), -1, dtype=np.int32)
+    out_d2 = np.full((n, k), np.inf, dtype=np.float64)
+    found = np.zeros(n, dtype=np.int32)
+    starts = np.searchsorted(i, np.arange(n))
+    ends = np.searchsorted(i, np.arange(n), side="right")
+    for q in range(n):
+        m = min(k, ends[q] - starts[q])
+        nbr[q, :m] = j[starts[q]:starts[q] + m]
+        out_d2[q, :m] = dd[starts[q]:starts[q] + m]
+        found[q] = m
+    return nbr, out_d2, found

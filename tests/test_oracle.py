@@ -393,3 +393,48 @@ def test_invalid_inputs_rejected():
     # n = 0 is an empty result
     cnt, pp, _, _ = oracle.grid_count(np.zeros((0, 3)), 0.1)
     assert cnt == 0 and len(pp) == 0
+
+
+# --------------------------------------------------------------------------
+# kNN within eps (reuse of the self-join result)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d,k", [(2, 1), (3, 8), (5, 20)])
+def test_knn_within_eps_matches_kdtree(d, k):
+    """Against scipy's k-d tree (its own distance code and search): the k
+    nearest within eps, self excluded, in distance order. Rows with a
+    distance within 1e-9 of eps or a near-tie inside the list are skipped
+    (rounding decides those differently in the two codes)."""
+    from scipy.spatial import cKDTree
+    X = gen.uniform(3000, d, seed=40 + d)
+    eps = 0.12 if d < 5 else 0.35
+    nbr, dd, found = oracle.knn_within_eps(X, eps, k)
+    dist, idx = cKDTree(X).query(X, k=k + 1, distance_upper_bound=eps * (1 + 1e-9))
+    checked = 0
+    for i in range(len(X)):
+        got = [j for j in idx[i] if j < len(X) and j != i][:k]
+        dk = np.sort(np.sqrt(((X - X[i]) ** 2).sum(1)))
+        if np.any(np.abs(dk - eps) < 1e-9 * eps) or np.any(np.diff(dk[:k + 2]) < 1e-12):
+            continue
+        assert found[i] == len(got), i
+        assert list(nbr[i, :found[i]]) == got, i
+        assert np.allclose(np.sqrt(dd[i, :found[i]]), [dist[i][list(idx[i]).index(j)] for j in got], rtol=1e-12)
+        assert np.all(nbr[i, found[i]:] == -1) and np.all(np.isinf(dd[i, found[i]:]))
+        checked += 1
+    assert checked > 0.95 * len(X)
+
+
+def test_knn_within_eps_ties_by_index():
+    """Lattice points have many equal distances: each list must be sorted by
+    (distance, index), hold only points within eps, exclude the point, and
+    be the k smallest of the brute-force neighbour set."""
+    g = np.arange(6, dtype=np.float64)
+    X = np.array(list(itertools.product(g, g)), dtype=np.float64)
+    eps, k = 1.5, 6
+    nbr, dd, found = oracle.knn_within_eps(X, eps, k)
+    for i in range(len(X)):
+        d2 = ((X - X[i]) ** 2).sum(1)
+        cand = sorted((d2[j], j) for j in range(len(X)) if j != i and d2[j] <= eps * eps)
+        want = cand[:k]
+        assert found[i] == len(want)
+        assert [(dd[i, r], nbr[i, r]) for r in range(found[i])] == [(float(a), b) for a, b in want]
