@@ -162,6 +162,26 @@ sj_status selfjoin_count(sj_grid *g, sj_path path, int32_t *per_point, int64_t *
 sj_status selfjoin_core_points(sj_grid *g, sj_path path, int32_t min_pts, uint8_t *is_core, int64_t *ncore,
                                void *stream);
 
+/* k nearest neighbours within eps (kNN, named in Section I as a consumer of
+ * these distance calculations), from the pairs of R: for point i, the points
+ * j != i with d2(i, j) <= eps^2 ordered by the exact squared distance of
+ * Eq. (2) and then by the smaller index j; the first k of them.
+ *  k           : in [1, 64].
+ *  pair_budget : most pairs (with their distances) held in device memory at
+ *                once, 16 bytes each, allocated and freed by the call; 0 =
+ *                2^26. Fewer than the total runs several chunks.
+ *  nbr         : device int32[n * k], row i (input order) = the indices of
+ *                i's neighbours, -1 past nfound[i].
+ *  nbr_d2      : device double[n * k] or NULL: their squared distances, +inf
+ *                past nfound[i].
+ *  nfound      : device int32[n]: min(k, neighbours of i within eps).
+ * nbr / nfound may be NULL when n = 0. Uses the handle's cached counts or
+ * counts with `path` first. Errors: SJ_ERR_INVALID for bad arguments,
+ * SJ_ERR_UNSUPPORTED when one point has more pairs than pair_budget,
+ * SJ_ERR_OOM, SJ_ERR_HIP. */
+sj_status selfjoin_knn(sj_grid *g, sj_path path, int32_t k, int64_t pair_budget, int32_t *nbr, double *nbr_d2,
+                       int32_t *nfound, void *stream);
+
 /* Writes pairs of R, one chunk per call (result batching, Section III-B:
  * the result may exceed device memory).
  *  cursor      : first query to emit, in the grid's query order (0 = start;

@@ -22,6 +22,7 @@ EXPORTS = [
     "selfjoin_build_grid",
     "selfjoin_count",
     "selfjoin_core_points",
+    "selfjoin_knn",
     "selfjoin_pairs",
     "selfjoin_measure_error",
     "selfjoin_grid_info",
@@ -105,6 +106,8 @@ def load():
     lib.selfjoin_count.argtypes = [_vp, ctypes.c_int, _vp, _i64p, ctypes.POINTER(sj_stats), _vp]
     lib.selfjoin_core_points.restype = ctypes.c_int
     lib.selfjoin_core_points.argtypes = [_vp, ctypes.c_int, ctypes.c_int32, _vp, _i64p, _vp]
+    lib.selfjoin_knn.restype = ctypes.c_int
+    lib.selfjoin_knn.argtypes = [_vp, ctypes.c_int, ctypes.c_int32, _i64, _vp, _vp, _vp, _vp]
     lib.selfjoin_pairs.restype = ctypes.c_int
     lib.selfjoin_pairs.argtypes = [_vp, ctypes.c_int, _i64, _vp, _vp, _i64, _i64p, _i64p,
                                    ctypes.POINTER(sj_stats), _vp]

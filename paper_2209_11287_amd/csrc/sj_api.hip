@@ -2,6 +2,8 @@
 // counts cache, chunked pair output.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -38,6 +40,62 @@ __global__ void k_core_flags(const int32_t *__restrict__ cnt, const int32_t *__r
         for (int w = 0; w < 256 / 64; ++w) t += part[w];
         if (t) atomicAdd(ncore, (unsigned long long)t);
     }
+}
+
+constexpr int32_t kKnnMax = 64;                  // largest k of selfjoin_knn
+constexpr int64_t kKnnBudget = int64_t(1) << 26;  // default pairs held at once (1 GiB with d2)
+
+// k nearest within eps for sorted queries [qlo, qhi) of one pair chunk, one
+// wave per query: k rounds, each taking the smallest (d2, index) key above
+// the previous round's over the query's pairs (the point itself skipped).
+// Rows are written in the input order; unused slots get -1 / +inf.
+__global__ void k_knn_select(const int2 *__restrict__ pairs, const double *__restrict__ d2,
+                             const int64_t *__restrict__ off, int64_t base, const int32_t *__restrict__ perm,
+                             int64_t qlo, int64_t qhi, int32_t k, int32_t *__restrict__ nbr,
+                             double *__restrict__ nbr_d2, int32_t *__restrict__ nfound) {
+    const int lane = threadIdx.x & 63;
+    const int64_t q = qlo + (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (q >= qhi) return;  // whole wave
+    const int64_t b = off[q] - base, e = off[q + 1] - base;
+    const int32_t self = perm[q];
+    int64_t row = (int64_t)self * k;
+    double pd = -1.0;  // previous key (d2 >= 0)
+    int32_t pj = -1;
+    int found = 0;
+    for (; found < k; ++found) {
+        double bd = INFINITY;
+        int32_t bj = INT_MAX;
+        for (int64_t p = b + lane; p < e; p += 64) {
+            const int32_t j = pairs[p].y;
+            if (j == self) continue;
+            const double x = d2[p];
+            const bool above = x > pd || (x == pd && j > pj);
+            if (above && (x < bd || (x == bd && j < bj))) {
+                bd = x;
+                bj = j;
+            }
+        }
+        for (int sh = 32; sh > 0; sh >>= 1) {
+            const double od = __shfl_xor(bd, sh);
+            const int32_t oj = __shfl_xor(bj, sh);
+            if (od < bd || (od == bd && oj < bj)) {
+                bd = od;
+                bj = oj;
+            }
+        }
+        if (bj == INT_MAX) break;  // wave-uniform after the reduction
+        if (lane == 0) {
+            nbr[row + found] = bj;
+            if (nbr_d2) nbr_d2[row + found] = bd;
+        }
+        pd = bd;
+        pj = bj;
+    }
+    for (int r = found + lane; r < k; r += 64) {
+        nbr[row + r] = -1;
+        if (nbr_d2) nbr_d2[row + r] = INFINITY;
+    }
+    if (lane == 0) nfound[self] = found;
 }
 
 __global__ void k_scatter_counts(const int32_t *__restrict__ cnt, const int32_t *__restrict__ perm, int64_t n,
@@ -284,6 +342,62 @@ sj_status selfjoin_count(sj_grid *gh, sj_path path, int32_t *per_point, int64_t 
         stats->ms_kernel = ro.kt.ms();
         stats->tiles_pruned = ro.tiles_pruned;
     }
+    return SJ_OK;
+    SJ_API_END
+}
+
+sj_status selfjoin_knn(sj_grid *gh, sj_path path, int32_t k, int64_t pair_budget, int32_t *nbr, double *nbr_d2,
+                       int32_t *nfound, void *stream) {
+    set_error("");
+    if (!gh) return invalid("grid is NULL");
+    if (!valid_path(path)) return invalid("unknown path");
+    if (k < 1 || k > kKnnMax) return invalid("k must be in [1, 64]");
+    if (pair_budget < 0) return invalid("pair_budget < 0");
+    if (gh->g.n > 0 && (!nbr || !nfound)) return invalid("nbr / nfound is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SJ_API_BEGIN
+    Grid &g = gh->g;
+    if (g.n == 0) return SJ_OK;
+    if (!g.have_counts) {
+        RefineOut ro;
+        compute_counts(g, path, ro, s);
+    }
+    const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(g.total, pair_budget ? pair_budget : kKnnBudget));
+    int32_t *pairs = dev_alloc_n<int32_t>(2 * cap, s);
+    double *pd2 = dev_alloc_n<double>(cap, s);
+    int64_t cursor = 0;
+    while (cursor < g.n) {
+        ChunkPlan p;
+        if (cursor == 0 && cap >= g.total) {
+            p.written = g.total;
+            p.next = g.n;
+            p.item_lo = 0;
+            p.item_hi = g.items;
+            p.block_lo = 0;
+            p.block_hi = g.nblocks;
+            p.base = 0;
+        } else {
+            p = plan_chunk(g, cursor, cap, s);
+        }
+        if (p.too_small) {
+            dev_free(pd2, s);
+            dev_free(pairs, s);
+            throw Unsupported{"a point has more pairs than pair_budget"};
+        }
+        RefineOut re;
+        re.band_dev = dev_alloc_n<unsigned long long>(4, s);
+        re.aux_dev = re.band_dev + 1;
+        refine_pairs(g, path, p, cursor, pairs, pd2, re, s);
+        dev_free(re.band_dev, s);
+        const int64_t nq = p.next - cursor;
+        hipLaunchKernelGGL(k_knn_select, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s,
+                           reinterpret_cast<const int2 *>(pairs), pd2, g.off, p.base, g.perm, cursor, p.next, k, nbr,
+                           nbr_d2, nfound);
+        SJ_HIP(hipGetLastError());
+        cursor = p.next;
+    }
+    dev_free(pd2, s);
+    dev_free(pairs, s);
     return SJ_OK;
     SJ_API_END
 }

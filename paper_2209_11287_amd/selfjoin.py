@@ -114,6 +114,23 @@ def selfjoin_core_points(g: GridHandle, min_pts: int, path="fp64_mfma", stream=N
     return flags, ncore.value
 
 
+def selfjoin_knn(g: GridHandle, k: int, path="fp64_mfma", want_d2=True, pair_budget=0, stream=None):
+    """k nearest neighbours within eps (self excluded, by distance then
+    index): returns (nbr int32 [n, k], d2 float64 [n, k] or None, nfound
+    int32 [n]) as CUDA tensors in the input order."""
+    torch = _torch()
+    lib = _lib.load()
+    nbr = torch.empty((g.n, int(k)), dtype=torch.int32, device=g.device)
+    d2 = torch.empty((g.n, int(k)), dtype=torch.float64, device=g.device) if want_d2 else None
+    nfound = torch.empty(g.n, dtype=torch.int32, device=g.device)
+    vp = lambda t: ctypes.c_void_p(t.data_ptr()) if (t is not None and g.n) else None
+    with torch.cuda.device(g.device):
+        st = lib.selfjoin_knn(g.ptr, _path_id(path), int(k), int(pair_budget), vp(nbr), vp(d2), vp(nfound),
+                              _stream_ptr(stream))
+    check(st, "selfjoin_knn")
+    return nbr, d2, nfound
+
+
 def selfjoin_pairs(g: GridHandle, path, cursor: int, pairs, d2=None, capacity=None, stream=None):
     """Writes one chunk into `pairs` (int32 CUDA tensor (capacity, 2)) and
     optionally `d2` (float64 CUDA tensor (capacity,)). Returns
@@ -185,6 +202,9 @@ class SelfJoin:
 
     def core_points(self, min_pts, path="fp64_mfma"):
         return selfjoin_core_points(self.grid, min_pts, path, self.stream)
+
+    def knn(self, k, path="fp64_mfma", want_d2=True, pair_budget=0):
+        return selfjoin_knn(self.grid, k, path, want_d2, pair_budget, self.stream)
 
     def all_pairs(self, path="fp64_mfma", want_d2=False, capacity=None):
         """All pairs as one (|R|, 2) int32 tensor (and d2), chunked if

@@ -86,6 +86,7 @@ def test_calls_on_null_grid_rejected(lib):
     info = _lib.sj_grid_info()
     assert lib.selfjoin_grid_info(None, ctypes.byref(info), None) == _lib.SJ_ERR_INVALID
     assert lib.selfjoin_core_points(None, 1, 4, None, ctypes.byref(w), None) == _lib.SJ_ERR_INVALID
+    assert lib.selfjoin_knn(None, 1, 4, 0, None, None, None, None) == _lib.SJ_ERR_INVALID
     lib.selfjoin_free_grid(None, None)  # accepted
 
 

@@ -299,3 +299,41 @@ def test_index_dims_option_is_result_neutral():
             g = gpu_join(X, eps, path, want_pairs=False, index_dims=k)
             assert g["total"] == c
             assert np.array_equal(g["per_point"], pp)
+
+
+@pytest.mark.parametrize("dist,n,d,k,path,budget", [
+    ("uniform", 20000, 2, 8, "fp64_mfma", 0),
+    ("expo", 12007, 3, 1, "fp64_valu", 0),
+    ("expo", 12007, 3, 16, "fp64_mfma", -1),   # chunked: a few times the largest neighbourhood
+    ("gmm", 6001, 16, 64, "bf16x3_mfma", 0),
+    ("lattice", 0, 2, 6, "fp32_mfma", 0),
+])
+def test_knn_within_eps_matches_oracle(dist, n, d, k, path, budget):
+    """kNN reuse of the pair list: neighbour indices, their squared distances
+    and the number found, bit-exact against the oracle (self excluded, order
+    by distance then index), including equal-distance ties on a lattice and
+    a pair budget that forces several chunks."""
+    import itertools
+    import torch
+    import oracle
+    from paper_2209_11287_amd import SelfJoin
+    if dist == "lattice":
+        g = np.arange(40, dtype=np.float64)
+        X = np.array(list(itertools.product(g, g)), dtype=np.float64)
+        eps = 2.0
+    else:
+        X = gen.make(dist, n, d, seed=31 + d)
+        eps = _eps_for(X, 24)
+    log(f"[knn] {dist} n={len(X)} d={d} k={k} path={path}")
+    want_nbr, want_d2, want_found = oracle.knn_within_eps(X, eps, k)
+    if budget < 0:
+        _, pp = oracle.grid_count(X, eps)[:2]
+        budget = 3 * int(pp.max())
+    sj = SelfJoin(torch.from_numpy(X).to("cuda:0"), eps)
+    try:
+        nbr, d2, found = sj.knn(k, path, pair_budget=budget)
+        assert np.array_equal(found.cpu().numpy(), want_found)
+        assert np.array_equal(nbr.cpu().numpy(), want_nbr)
+        assert np.array_equal(d2.cpu().numpy(), want_d2)
+    finally:
+        sj.close()
