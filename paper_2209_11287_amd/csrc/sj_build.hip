@@ -278,9 +278,20 @@ __global__ void k_scan_sums(const Tin *__restrict__ in, int64_t n, Tacc *__restr
     __shared__ Tacc part[kThreads / 64];
     const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
     Tacc acc = 0;
-    for (int r = 0; r < kScanItems; ++r) {
-        int64_t i = t0 + (int64_t)r * kThreads + threadIdx.x;
-        if (i < n) acc += (Tacc)in[i];
+    if (sizeof(Tin) == 4 && t0 + kScanTile <= n) {
+        // whole tile: 16-byte loads, each wave reading 1 KB runs (the tile
+        // starts at a 16 KB offset)
+        const int4 *p4 = reinterpret_cast<const int4 *>(in + t0);
+#pragma unroll
+        for (int r = 0; r < kScanItems / 4; ++r) {
+            const int4 w = p4[r * kThreads + threadIdx.x];
+            acc += (Tacc)w.x + (Tacc)w.y + (Tacc)w.z + (Tacc)w.w;
+        }
+    } else {
+        for (int r = 0; r < kScanItems; ++r) {
+            int64_t i = t0 + (int64_t)r * kThreads + threadIdx.x;
+            if (i < n) acc += (Tacc)in[i];
+        }
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
