@@ -62,8 +62,10 @@ typedef enum {
  *  SJ_BF16_MFMA : as FP32 but BF16 inputs, FP32 accumulation.
  *  SJ_BF16X3_MFMA : split BF16 -- each centred coordinate as hi + lo BF16
  *                 parts (about 16 significant bits), three BF16 MFMAs per
- *                 tile (lo.hi, hi.lo, hi.hi), FP32 accumulation; a band about
- *                 2^5-2^8 narrower than SJ_BF16_MFMA's, same FP64 recheck.
+ *                 tile (lo.hi, hi.lo, hi.hi), FP32 accumulation; its band is
+ *                 about an order of magnitude narrower than SJ_BF16_MFMA's
+ *                 (the dropped lo.lo products and the FP32 accumulation set
+ *                 it), same FP64 recheck.
  * (Other MFMA precisions are the paper's future work, Section V.) */
 typedef enum {
     SJ_FP64_VALU = 0,
