@@ -11,8 +11,10 @@
 //
 // Work unit: a block item = up to 4 consecutive 16-query work items of one
 // grid line (64 queries, one per wave row tile) sharing the union of their
-// candidate ranges. Candidates are staged 64 at a time into LDS:
-//  - the FP64 rows (kept for the exact recheck),
+// candidate ranges. Candidates are staged 64 at a time into LDS (the exact
+// recheck of the FP32 and split-BF16 paths reads the FP64 rows from global
+// memory, where the staging has just brought them into the caches; plain
+// BF16, with its wide band, keeps them in LDS):
 //  - the rows centred on the block's reference point r (its first query)
 //    and rounded to FP32 or BF16 (round to nearest even) -- the MFMA B
 //    operand,
@@ -108,8 +110,7 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The oracle's chain (ascending dimensions from +0.0, fl(a - b) then fma);
-// b may live in LDS.
+// The exact chain (ascending dimensions from +0.0, fl(a - b) then fma).
 __device__ __forceinline__ double exact_d2(const double *a, const double *b, int d) {
     double acc = 0.0;
     for (int t = 0; t < d; ++t) {
@@ -241,7 +242,10 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
     constexpr int STR = lp_stride<PREC>();
     constexpr int KSTEP = Prec<PREC>::kstep;
     __shared__ double xr[kLpMaxD];                   // reference row
-    __shared__ double f64t[kTC][kLpMaxD + 1];        // FP64 candidate rows
+    // plain BF16 rechecks tens of percent of its pairs: it keeps the FP64
+    // rows in LDS; the narrower-band paths read them from global memory
+    constexpr bool kRowsInLds = PREC == PREC_BF16;
+    __shared__ double f64t[kRowsInLds ? kTC : 1][kLpMaxD + 1];
     __shared__ uint32_t lpt[kTC * STR];              // rounded, centred rows (split BF16: hi)
     __shared__ uint32_t lptl[PREC == PREC_BF16X3 ? kTC * STR : 1];  // split BF16: lo
     __shared__ float nc32[kTC];                      // their norms (FP32, accumulator init)
@@ -424,7 +428,9 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
                 const int k = part + 4 * cc;
                 if (k < K) {  // K is a multiple of 4: uniform over the row's threads
                     const double x = pre[cc];
-                    if (k < d) f64t[srow][k] = x;
+                    if constexpr (kRowsInLds) {
+                        if (k < d) f64t[srow][k] = x;
+                    }
                     unsigned bits = 0;
                     double y = 0.0;
                     if (rowok && k < d) y = round_in<PREC>(__dsub_rn(x, xr[k]), bits);
@@ -500,7 +506,8 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
                 for (int r = 0; r < 4; ++r) {
                     const int i = 4 * g + r;
                     if (i < nq && crow < nvalid) {
-                        const double ex = exact_d2(G.xs + (int64_t)(q0 + i) * dp, &f64t[crow][0], d);
+                        const double ex = exact_d2(G.xs + (int64_t)(q0 + i) * dp,
+                                                   kRowsInLds ? &f64t[crow][0] : G.xs + (int64_t)(t + crow) * dp, d);
                         if (ex <= G.eps2) {  // the per-row bound covers pairs within eps
                             const double err = fabs((double)acc[r] - (ex - nqr[r]));
                             maxerr = fmax(maxerr, err);
@@ -514,7 +521,8 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
                 for (int r = 0; r < 4; ++r) {
                     if (bm & (1u << r)) {
                         const int i = 4 * g + r;
-                        const double ex = exact_d2(G.xs + (int64_t)(q0 + i) * dp, &f64t[crow][0], d);
+                        const double ex = exact_d2(G.xs + (int64_t)(q0 + i) * dp,
+                                                   kRowsInLds ? &f64t[crow][0] : G.xs + (int64_t)(t + crow) * dp, d);
                         if (ex <= G.eps2) inm |= 1u << r;
                         ++band;
                     }
