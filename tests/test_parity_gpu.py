@@ -274,6 +274,18 @@ def test_mfma_error_within_band(path):
         assert viol == 0
         assert err <= band / 2  # the analysis bound, before its safety factor
         sj.close()
+    # queries far from their block's reference point (a wide dimension, a
+    # large common offset): the band grows with |q'|, the bound must hold
+    rng = np.random.default_rng(11)
+    Y = rng.random((6000, 4)) - 0.5
+    Y[:, 0] *= 1e3
+    for X, eps, tag in [(Y, 0.05, "wide-dim0"), (1e6 + rng.random((6000, 3)) * 1e-2, 1e-3, "large-offset")]:
+        sj = SelfJoin(torch.from_numpy(X).to("cuda:0"), eps)
+        err, band, viol = selfjoin_measure_error(sj.grid, path)
+        log(f"[band] {path} {tag} max_err={err:.3e} band={band:.3e} rel={band / eps**2:.3e} viol={viol}")
+        assert viol == 0
+        assert err <= band / 2
+        sj.close()
 
 
 def test_nonfinite_input_rejected():
