@@ -377,7 +377,7 @@ def main():
     if args.compare in ("", "none"):
         args.compare = ""
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is described, not implemented)"}))
         sys.exit(2)
     import torch

@@ -50,7 +50,7 @@ typedef enum {
     SJ_ERR_OOM = 2,         /* device allocation failed */
     SJ_ERR_HIP = 3,         /* a HIP runtime call failed */
     SJ_ERR_CAPACITY = 4,    /* output buffer too small (see selfjoin_pairs) */
-    SJ_ERR_UNSUPPORTED = 5  /* valid but not supported by this build */
+    SJ_ERR_UNSUPPORTED = 5  /* valid but not supported by this library */
 } sj_status;
 
 /* Distance-tile path. All return the same exact set R.
