@@ -349,3 +349,26 @@ def test_knn_within_eps_matches_oracle(dist, n, d, k, path, budget):
         assert np.array_equal(d2.cpu().numpy(), want_d2)
     finally:
         sj.close()
+
+
+def test_knn_rejects_bad_arguments():
+    """k outside [1, 64] is invalid; a pair budget below one point's
+    neighbourhood is reported as unsupported (a host-side check), and the
+    handle stays usable afterwards."""
+    import torch
+    from paper_2209_11287_amd import SelfJoin, SelfJoinError
+    X = gen.uniform(4000, 2, seed=9)
+    eps = _eps_for(X, 20)
+    sj = SelfJoin(torch.from_numpy(X).to("cuda:0"), eps)
+    try:
+        for k in (0, 65):
+            with pytest.raises(SelfJoinError) as ei:
+                sj.knn(k)
+            assert ei.value.status == 1
+        with pytest.raises(SelfJoinError) as ei:
+            sj.knn(4, pair_budget=2)
+        assert ei.value.status == 5
+        nbr, d2, found = sj.knn(4)
+        assert int(found.min()) >= 0 and int(found.max()) <= 4
+    finally:
+        sj.close()
