@@ -27,6 +27,7 @@ _i64 = ctypes.c_int64
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _f64p = ctypes.POINTER(ctypes.c_double)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
 
 
 def build(force: bool = True) -> str:
@@ -65,6 +66,12 @@ def _load():
         lib.oracle_grid_pairs.restype = _i64
         lib.oracle_grid_pairs.argtypes = [_f64p, _i64, ctypes.c_int, ctypes.c_double,
                                           _i32p, _i32p, _f64p, _i64]
+        lib.oracle_grid_digest.restype = _i64
+        lib.oracle_grid_digest.argtypes = [_f64p, _i64, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_int, _i32p, _i64p,
+                                           ctypes.POINTER(ctypes.c_int), _u64p]
+        lib.oracle_pairs_digest.restype = None
+        lib.oracle_pairs_digest.argtypes = [_i32p, _i64, _u64p]
         lib.oracle_grid_count_sample.restype = _i64
         lib.oracle_grid_count_sample.argtypes = [_f64p, _i64, ctypes.c_int, ctypes.c_double,
                                                  _i64p, _i64, _i32p, _i64p]
@@ -160,6 +167,35 @@ def grid_pairs(X, eps, want_d2=False):
     if want_d2:
         return total, pp, pairs[:total], dd[:total]
     return total, pp, pairs[:total]
+
+
+def grid_digest(X, eps, nthreads=None):
+    """Grid self-join count with the pair-set checksums (test bookkeeping: the
+    sums modulo 2^64 of two SplitMix64 mixes of key = i * 2^32 + j over the
+    pairs (i, j); independent of pair order and chunking).
+    Returns (count, per_point, C_ref, k, (sum0, sum1))."""
+    X = _pts(X)
+    n, d = X.shape
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    lib = _load()
+    pp = np.zeros(n, dtype=np.int32)
+    cref = ctypes.c_int64(0)
+    k = ctypes.c_int(0)
+    sums = np.zeros(2, dtype=np.uint64)
+    total = lib.oracle_grid_digest(_ptr(X, _f64p), n, d, eps, int(nthreads), _ptr(pp, _i32p),
+                                   ctypes.byref(cref), ctypes.byref(k), _ptr(sums, _u64p))
+    if total < 0:
+        raise ValueError("invalid input")
+    return total, pp, cref.value, k.value, (int(sums[0]), int(sums[1]))
+
+
+def pairs_digest(pairs):
+    """The same two checksums of an explicit (m, 2) int32 pair list."""
+    p = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    sums = np.zeros(2, dtype=np.uint64)
+    _load().oracle_pairs_digest(_ptr(p, _i32p), p.shape[0], _ptr(sums, _u64p))
+    return int(sums[0]), int(sums[1])
 
 
 def grid_count_sample(X, eps, queries):

@@ -27,7 +27,10 @@
  *                        side eps (Section II-D "search" then "refine";
  *                        Section III-B, the grid of cells of size eps^d whose
  *                        neighbouring cells hold every candidate). Pinned to
- *                        the brute force by the tests.
+ *                        the brute force by the tests. oracle_grid_digest
+ *                        adds two order-independent checksums of the pair
+ *                        set, so that results too large to store can be
+ *                        compared whole.
  *
  * Grid readings (the paper gives cell side eps, not origin or rounding):
  * origin = per-dimension minimum; cell side w = eps * (1 + 2^-19) so that the
@@ -165,18 +168,22 @@ static int grid_build(grid_t *g, const double *X, int64_t n, int d, double eps)
         }
         if (n == 0) lo[j] = hi[j] = 0.0;
     }
-    /* Cells per dimension; drop trailing indexed dimensions until the total
-     * cell count fits in 62 bits. */
+    /* Cells per dimension (counted in double: an extent of 2^63 cells or more
+     * must not wrap); drop trailing indexed dimensions until the total cell
+     * count fits in 62 bits. If the first dimension alone needs 2^62 cells or
+     * more, the grid is a single cell: every pair is a candidate. */
+    double mc[ORACLE_KMAX];
     for (;;) {
         double prod = 1.0;
         for (int j = 0; j < k; ++j) {
-            g->m[j] = (int64_t)floor((hi[j] - lo[j]) / w) + 1;
-            prod *= (double)g->m[j];
+            mc[j] = floor((hi[j] - lo[j]) / w) + 1.0;
+            prod *= mc[j];
         }
         if (prod < 0x1p62 || k == 1) break;
         --k;
     }
-    if ((double)g->m[0] >= 0x1p62) return -1;
+    if (!(mc[0] < 0x1p62)) mc[0] = 1.0;
+    for (int j = 0; j < k; ++j) g->m[j] = (int64_t)mc[j];
     g->k = k;
     int64_t s = 1;
     for (int j = k - 1; j >= 0; --j) {
@@ -188,11 +195,12 @@ static int grid_build(grid_t *g, const double *X, int64_t n, int d, double eps)
     for (int64_t i = 0; i < n; ++i) {
         int64_t key = 0;
         for (int j = 0; j < k; ++j) {
+            /* clamped in double before the conversion, so no value (an
+             * infinite quotient included) is converted out of range */
             double q = floor((X[i * d + j] - lo[j]) / w);
-            int64_t c = (int64_t)q;
-            if (c < 0) c = 0;
-            if (c > g->m[j] - 1) c = g->m[j] - 1;
-            key += c * g->stride[j];
+            if (!(q >= 0.0)) q = 0.0;
+            if (q > (double)(g->m[j] - 1)) q = (double)(g->m[j] - 1);
+            key += (int64_t)q * g->stride[j];
         }
         g->sorted[i].key = key;
         g->sorted[i].idx = (int32_t)i;
@@ -268,11 +276,41 @@ static int neighbours(const grid_t *g, int64_t ci, int64_t *out)
     return cnt;
 }
 
+/* Order-independent checksums of a pair set (test bookkeeping, not part of
+ * the self-join): two pair lists of hundreds of millions of pairs are compared
+ * through the sums, modulo 2^64, of mix(key) and mix(key + G) over their pairs
+ * (i, j), key = i * 2^32 + j, G = 0x9e3779b97f4a7c15, where mix is the 64-bit
+ * finaliser of SplitMix64 (Steele, Lea and Flood, "Fast splittable
+ * pseudorandom number generators", OOPSLA 2014). Sums do not depend on the
+ * order of the pairs or on how the list is split into chunks. */
+static uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+static void digest_add(uint64_t sums[2], int32_t i, int32_t j)
+{
+    const uint64_t key = ((uint64_t)(uint32_t)i << 32) | (uint64_t)(uint32_t)j;
+    sums[0] += mix64(key);
+    sums[1] += mix64(key + 0x9e3779b97f4a7c15ull);
+}
+
+/* Checksums of an explicit pair list (rows (i, j)), for the tests. */
+void oracle_pairs_digest(const int32_t *pairs, int64_t npairs, uint64_t *sums)
+{
+    sums[0] = sums[1] = 0;
+    for (int64_t p = 0; p < npairs; ++p) digest_add(sums, pairs[2 * p], pairs[2 * p + 1]);
+}
+
 typedef struct {
     const grid_t *g;
     int tid, nthreads;
     int32_t *per_point;
     int64_t total, cref;
+    int digest;       /* also accumulate the pair checksums */
+    uint64_t sums[2];
 } count_job_t;
 
 static void *count_worker(void *arg)
@@ -294,7 +332,10 @@ static void *count_worker(void *arg)
                 int64_t ni = nb[t];
                 for (int64_t b = g->cell_start[ni]; b < g->cell_start[ni] + g->cell_count[ni]; ++b) {
                     const double *xc = g->X + (int64_t)g->sorted[b].idx * d;
-                    if (oracle_d2(xq, xc, d) <= g->eps2) ++cnt;
+                    if (oracle_d2(xq, xc, d) <= g->eps2) {
+                        ++cnt;
+                        if (job->digest) digest_add(job->sums, qi, g->sorted[b].idx);
+                    }
                 }
             }
             if (job->per_point) job->per_point[qi] = cnt;
@@ -304,11 +345,28 @@ static void *count_worker(void *arg)
     return NULL;
 }
 
+static int64_t grid_count_impl(const double *X, int64_t n, int d, double eps, int nthreads,
+                               int32_t *per_point, int64_t *cref, int *kdims, uint64_t *sums);
+
 /* Grid self-join, count only. per_point (n, original order) may be NULL.
  * cref (nullable) receives C_ref; kdims (nullable) the indexed dimension
  * count. Threads split the query cells. Returns |R| or -1. */
 int64_t oracle_grid_count(const double *X, int64_t n, int d, double eps, int nthreads,
                           int32_t *per_point, int64_t *cref, int *kdims)
+{
+    return grid_count_impl(X, n, d, eps, nthreads, per_point, cref, kdims, NULL);
+}
+
+/* As oracle_grid_count, plus the two pair checksums of R (see mix64) in
+ * sums[0..1]. */
+int64_t oracle_grid_digest(const double *X, int64_t n, int d, double eps, int nthreads,
+                           int32_t *per_point, int64_t *cref, int *kdims, uint64_t *sums)
+{
+    return grid_count_impl(X, n, d, eps, nthreads, per_point, cref, kdims, sums);
+}
+
+static int64_t grid_count_impl(const double *X, int64_t n, int d, double eps, int nthreads,
+                               int32_t *per_point, int64_t *cref, int *kdims, uint64_t *sums)
 {
     if (!valid_input(X, n, d, eps) || n >= ((int64_t)1 << 31)) return -1;
     grid_t g;
@@ -324,14 +382,23 @@ int64_t oracle_grid_count(const double *X, int64_t n, int d, double eps, int nth
         jobs[t].per_point = per_point;
         jobs[t].total = 0;
         jobs[t].cref = 0;
+        jobs[t].digest = sums != NULL;
+        jobs[t].sums[0] = jobs[t].sums[1] = 0;
     }
     for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, count_worker, &jobs[t]);
     count_worker(&jobs[0]);
     for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
     int64_t total = 0, cr = 0;
+    uint64_t s0 = 0, s1 = 0;
     for (int t = 0; t < nthreads; ++t) {
         total += jobs[t].total;
         cr += jobs[t].cref;
+        s0 += jobs[t].sums[0];
+        s1 += jobs[t].sums[1];
+    }
+    if (sums) {
+        sums[0] = s0;
+        sums[1] = s1;
     }
     if (cref) *cref = cr;
     if (kdims) *kdims = g.k;

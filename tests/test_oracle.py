@@ -248,6 +248,24 @@ def test_grid_adversarial_sets():
         assert np.array_equal(_pairset(pairs_bf), _pairset(pairs_g))
 
 
+def test_grid_extents_beyond_the_cell_count_range():
+    # extent / eps of 1e19 (more cells than an int64 holds) or infinite
+    # (max - min overflows): the grid drops indexed dimensions, down to a
+    # single cell, and stays equal to brute force
+    sets = [np.array([[0.0, 0.0], [0.0, 1e20]]), np.array([[0.0, 0.0], [1e20, 0.0]]),
+            np.array([[-1e308, 0.0], [1e308, 0.0], [1e308, 5.0]]),
+            np.array([[0.0, 0.0], [1e20, 0.0], [1e20, 5.0], [3.0, 1e25]])]
+    rng = np.random.default_rng(12)
+    Y = rng.random((400, 3))
+    Y[:7, 0] = [1e19, -1e19, 4e18, 1e300, -1e300, 2.5, 1e200]
+    sets.append(Y)
+    for X in sets:
+        cb, pb, rb = oracle.bruteforce(X, 10.0 if X.shape[0] < 10 else 0.2)
+        cg, pg, rg = oracle.grid_pairs(X, 10.0 if X.shape[0] < 10 else 0.2)
+        assert cb == cg and np.array_equal(pb, pg)
+        assert np.array_equal(_pairset(rb), _pairset(rg))
+
+
 def test_cell_side_margin_is_needed():
     """With cells of side exactly eps, rounding of the cell coordinate can put a
     pair that is exactly eps apart two cells apart. Find such pairs with plain
@@ -357,6 +375,104 @@ def test_cref_counts_chebyshev_adjacent_pairs(dist, d):
 
 
 # --------------------------------------------------------------------------
+# Sampled counts: per-point counts of listed queries through the grid
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dist,d", [("uniform", 2), ("expo", 3), ("uniform", 4), ("gmm", 6), ("gmm", 16)])
+def test_grid_count_sample_equals_full_count_and_bruteforce(dist, d):
+    X = gen.make(dist, 1500, d, seed=d + 11)
+    eps = _eps_for(X, 10)
+    rng = np.random.default_rng(d)
+    q = np.concatenate([rng.integers(0, X.shape[0], 200), [0, X.shape[0] - 1, 5, 5]])  # repeats allowed
+    counts, cref_s = oracle.grid_count_sample(X, eps, q)
+    _, pp_grid, _, k = oracle.grid_count(X, eps)
+    _, pp_bf, _ = oracle.bruteforce(X, eps, want_pairs=False)
+    assert np.array_equal(counts, pp_bf[q])
+    assert np.array_equal(counts, pp_grid[q])
+    # restricted C_ref: for each listed query, the points whose cells are
+    # Chebyshev-adjacent (|dc| <= 1 on every indexed dimension) to its cell
+    w = oracle.cell_side(eps)
+    lo = X[:, :k].min(0)
+    hi = X[:, :k].max(0)
+    m = np.floor((hi - lo) / w).astype(np.int64) + 1
+    c = np.clip(np.floor((X[:, :k] - lo) / w).astype(np.int64), 0, m - 1)
+    adj = [(np.abs(c - c[i]).max(-1) <= 1).sum() for i in q]
+    assert cref_s == int(np.sum(adj))
+
+
+def test_grid_count_sample_lattice_ties():
+    # every neighbour of an interior lattice point lies exactly on eps or
+    # inside: d = 2, r = 2 gives the Gauss-circle number 13 in the interior
+    h = 2.0 ** -6
+    X = gen.lattice(12, 2, h)
+    interior = [i for i in range(X.shape[0]) if (X[i] >= 2 * h).all() and (X[i] <= 9 * h).all()]
+    counts, _ = oracle.grid_count_sample(X, 2 * h, interior)
+    assert (counts == 13).all()
+
+
+# --------------------------------------------------------------------------
+# Pair-set checksums (test bookkeeping for results too large to store)
+# --------------------------------------------------------------------------
+
+_M1 = np.uint64(0xbf58476d1ce4e5b9)
+_M2 = np.uint64(0x94d049bb133111eb)
+_G = np.uint64(0x9e3779b97f4a7c15)
+
+
+def _mix_np(z):
+    """SplitMix64's 64-bit finaliser in numpy uint64 (wrapping arithmetic)."""
+    z = z.astype(np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def _digest_np(pairs):
+    p = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    key = (p[:, 0].astype(np.uint64) << np.uint64(32)) | p[:, 1].astype(np.uint64)
+    with np.errstate(over="ignore"):
+        a = int(np.sum(_mix_np(key), dtype=np.uint64))
+        b = int(np.sum(_mix_np(key + _G), dtype=np.uint64))
+    return a, b
+
+
+def test_mix_matches_published_splitmix64_outputs():
+    # SplitMix64 with seed 0: state += 0x9e3779b97f4a7c15, output = mix(state);
+    # its first outputs are the published test values of the generator
+    state = np.uint64(0)
+    outs = []
+    for _ in range(3):
+        with np.errstate(over="ignore"):
+            state = state + _G
+        outs.append(int(_mix_np(np.array([state]))[0]))
+    assert outs == [0xe220a8397b1dcdaf, 0x6e789e6aa1b965f4, 0x06c45d188009454f]
+
+
+@pytest.mark.parametrize("dist,d", [("uniform", 2), ("expo", 3), ("gmm", 8)])
+def test_grid_digest_equals_digest_of_bruteforce_pairs(dist, d):
+    X = gen.make(dist, 1200, d, seed=d + 3)
+    eps = _eps_for(X, 9)
+    cnt, pp, pairs = oracle.bruteforce(X, eps)
+    tot, pp_g, cref, k, sums = oracle.grid_digest(X, eps, nthreads=3)
+    assert tot == cnt and np.array_equal(pp_g, pp)
+    assert sums == _digest_np(pairs)
+    assert oracle.pairs_digest(pairs) == sums
+    # order and chunking do not matter; one dropped or altered pair does
+    perm = np.random.default_rng(0).permutation(len(pairs))
+    assert oracle.pairs_digest(pairs[perm]) == sums
+    half = len(pairs) // 2
+    a, b = oracle.pairs_digest(pairs[:half]), oracle.pairs_digest(pairs[half:])
+    assert ((a[0] + b[0]) % 2 ** 64, (a[1] + b[1]) % 2 ** 64) == sums
+    assert oracle.pairs_digest(pairs[1:]) != sums
+    bad = pairs.copy()
+    bad[7, 1] ^= 1
+    assert oracle.pairs_digest(bad) != sums
+    # the same results as the plain grid count
+    assert oracle.grid_count(X, eps, nthreads=2)[:1] == (tot,)
+
+
+# --------------------------------------------------------------------------
 # Statistical sanity on the small parity workload
 # --------------------------------------------------------------------------
 
@@ -438,3 +554,18 @@ def test_knn_within_eps_ties_by_index():
         want = cand[:k]
         assert found[i] == len(want)
         assert [(dd[i, r], nbr[i, r]) for r in range(found[i])] == [(float(a), b) for a, b in want]
+
+
+def test_device_digest_helper_matches_oracle_on_cpu():
+    # the GPU tests checksum the library's pairs with this torch helper; here
+    # (torch on the CPU) it must agree with the oracle's C routine
+    import torch
+
+    from tests.gpu_util import add_digest, digest_pairs_t
+    rng = np.random.default_rng(5)
+    pairs = rng.integers(0, 2 ** 31 - 1, (10007, 2)).astype(np.int32)
+    want = oracle.pairs_digest(pairs)
+    t = torch.from_numpy(pairs)
+    assert digest_pairs_t(t) == want
+    assert digest_pairs_t(t, step=1000) == want
+    assert add_digest(digest_pairs_t(t[:5000]), digest_pairs_t(t[5000:])) == want
