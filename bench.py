@@ -104,19 +104,21 @@ def one_dataset(i, w, xt, path, bufs, collect, cref, chunk, stream):
     while cursor < w["n"]:
         written, cursor, st = selfjoin_pairs(g, path, cursor, bufs[i], None, cap, stream=stream)
         done += written
-        emit_ms += st["ms_kernel"]
+        emit_ms += st["ms_emit"]
         st_p = st if st_p is None else st_p
     if done != total:
         raise RuntimeError(f"pairs incomplete: {done}/{total}")
     st_p = dict(st_p or {"ms": 0.0})
-    st_p["ms_kernel"] = emit_ms
+    st_p["ms_emit"] = emit_ms
     if cref is not None:
         cref[w["name"]] = selfjoin_grid_info(g, stream=stream)["cand_ref"]
     if collect is not None:
         collect[i] = {"name": w["name"], "n": w["n"], "d": w["d"], "eps": w["eps"], "pairs": total,
                       "cand_eval": st_c["cand_eval"],
-                      "count_kernel_ms": st_c["ms_kernel"], "emit_kernel_ms": st_p["ms_kernel"],
-                      "count_ms": st_c["ms"], "pairs_ms": st_p["ms"], "band_pairs": st_c["band_pairs"],
+                      "build_ms": st_c["ms_build"],
+                      "count_kernel_ms": st_c["ms_refine"], "emit_kernel_ms": st_p["ms_emit"],
+                      "count_ms": st_c["ms"], "pairs_ms": st_p["ms"], "rechecked": st_c["rechecked"],
+                      "path_run": st_c["path_run"],
                       "band_rel": st_c["band_rel"]}
     selfjoin_free_grid(g, stream=stream)
 

@@ -36,6 +36,7 @@
 #ifndef SELFJOIN_H
 #define SELFJOIN_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -66,7 +67,19 @@ typedef enum {
  *                 about an order of magnitude narrower than SJ_BF16_MFMA's
  *                 (the dropped lo.lo products and the FP32 accumulation set
  *                 it), same FP64 recheck.
- * (Other MFMA precisions are the paper's future work, Section V.) */
+ * (Other MFMA precisions are the paper's future work, Section V.)
+ *
+ * Range guards. Every path returns the exact set for every finite input; a
+ * path whose arithmetic could overflow on the given data hands the call to
+ * the next path down, which returns the same set (sj_stats.path_run says
+ * which ran):
+ *  - FP32 / BF16 / split BF16: the tiles work on centred coordinates scaled
+ *    by a power of two that puts eps in [1, 2); they run when eps is in
+ *    [2^-500, 2^500] and every dimension's extent (max - min) is at most
+ *    2^40 eps, otherwise FP64 MFMA runs;
+ *  - FP64 MFMA: runs when the largest squared norm of the rows centred on
+ *    the bounding-box midpoint is at most 2^1000, otherwise FP64 VALU runs
+ *    (the exact chain itself, which has no range limit). */
 typedef enum {
     SJ_FP64_VALU = 0,
     SJ_FP64_MFMA = 1,
@@ -90,6 +103,17 @@ typedef struct {
     const char *tune_cache; /* batched form only: text file of tuned choices,
                                read before and written after tuning; NULL =
                                in-process cache only */
+    /* Device allocator for every buffer the library creates for this handle
+     * (the grid index, counts, in-masks, per-call temporaries), e.g. a
+     * framework's caching allocator. alloc returns `bytes` of device memory
+     * usable in stream order on `stream` (NULL = failure, reported as
+     * SJ_ERR_OOM); free releases a pointer alloc returned, in stream order.
+     * Both are called from the calling thread of the library call, with
+     * `alloc_ctx`. alloc NULL = the library's own caching allocator. The
+     * hook must stay callable until the handle is freed. */
+    void *(*alloc)(size_t bytes, void *stream, void *ctx);
+    void (*free)(void *ptr, void *stream, void *ctx);
+    void *alloc_ctx;
     int64_t reserved[4];
 } sj_opts;
 
@@ -101,18 +125,31 @@ typedef struct {
     int64_t cand_eval;   /* candidate pairs the path evaluated, tile padding
                             excluded */
     int64_t pairs;       /* |R| for count; pairs written for pairs */
-    int64_t band_pairs;  /* pairs whose fast value fell inside the band and
-                            were re-evaluated with the FP64 chain */
+    int64_t rechecked;   /* pairs of this call's tile kernels whose fast value
+                            fell inside the error band and were re-evaluated
+                            with the exact FP64 chain (0 on the FP64 VALU
+                            path, and for pairs expanded from the in-masks a
+                            count recorded) */
+    int64_t rechecked_in; /* of those, the pairs found within eps */
     double band_rel;     /* largest band half-width used, divided by eps^2 */
     double ms;           /* device time of the whole call (ms) */
-    double ms_kernel;    /* device time of the distance-tile kernel alone (ms) */
-    int64_t tiles_pruned; /* count, FP64 paths, d > 16: 16 x 16 tiles left
-                            early because every value's partial distance
-                            already exceeded the threshold (Section IV's
-                            short-circuit): FP64 MFMA after the first 16
-                            dimensions against eps^2 + Delta, FP64 VALU every
-                            16 dimensions against eps^2 (its chain is
+    double ms_build;     /* device time of the grid build of this handle (ms) */
+    double ms_refine;    /* device time of the count pass (distance tiles)
+                            run by this call; 0 when the counts were cached */
+    double ms_emit;      /* pairs: device time of the emission kernel (the
+                            recorded in-masks expanded, or the tiles re-run
+                            in emission form); 0 for count */
+    int64_t tiles_pruned; /* count, d > 16: 16 x 16 tiles left early because
+                            every value's partial distance already exceeded
+                            the threshold (the short-circuit of Section
+                            III-B): FP64 MFMA after the first 16 dimensions
+                            against eps^2 + Delta, FP64 VALU every 16
+                            dimensions against eps^2 (its chain is
                             monotone); 0 elsewhere */
+    int32_t path_run;    /* the path whose kernels ran (an sj_path): the
+                            requested one unless its range guard routed the
+                            call to the next exact path (see sj_path) */
+    int32_t reserved;
 } sj_stats;
 
 /* Grid facts (for tests and reports). */

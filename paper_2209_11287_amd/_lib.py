@@ -16,6 +16,7 @@ SJ_ERR_CAPACITY = 4
 SJ_ERR_UNSUPPORTED = 5
 
 PATHS = {"fp64_valu": 0, "fp64_mfma": 1, "fp32_mfma": 2, "bf16_mfma": 3, "bf16x3_mfma": 4}
+PATH_NAMES = {v: k for k, v in PATHS.items()}
 
 # Every symbol include/selfjoin.h declares.
 EXPORTS = [
@@ -38,8 +39,14 @@ EXPORTS = [
 ]
 
 
+# sj_opts.alloc / sj_opts.free
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class sj_opts(ctypes.Structure):
     _fields_ = [("index_dims", ctypes.c_int32), ("tune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
                 ("reserved", ctypes.c_int64 * 4)]
 
 
@@ -48,15 +55,22 @@ class sj_stats(ctypes.Structure):
         ("cand_ref", ctypes.c_int64),
         ("cand_eval", ctypes.c_int64),
         ("pairs", ctypes.c_int64),
-        ("band_pairs", ctypes.c_int64),
+        ("rechecked", ctypes.c_int64),
+        ("rechecked_in", ctypes.c_int64),
         ("band_rel", ctypes.c_double),
         ("ms", ctypes.c_double),
-        ("ms_kernel", ctypes.c_double),
+        ("ms_build", ctypes.c_double),
+        ("ms_refine", ctypes.c_double),
+        ("ms_emit", ctypes.c_double),
         ("tiles_pruned", ctypes.c_int64),
+        ("path_run", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        d["path_run"] = PATH_NAMES.get(d["path_run"], d["path_run"])
+        return d
 
 
 class sj_grid_info(ctypes.Structure):

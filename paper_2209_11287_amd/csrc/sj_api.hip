@@ -146,7 +146,45 @@ void release_cache(DevCache &c) {
 
 }  // namespace
 
+thread_local AllocScope *tl_scope = nullptr;
+
+AllocScope::AllocScope(const AllocHook &h) : hook(h.alloc ? &h : nullptr), prev(tl_scope) { tl_scope = this; }
+AllocScope::AllocScope(Arena *a) : arena(a), prev(tl_scope) { tl_scope = this; }
+AllocScope::~AllocScope() { tl_scope = prev; }
+
+static void *cache_alloc(size_t bytes, hipStream_t s);
+static void cache_free(void *p, hipStream_t s);
+
 void *dev_alloc(size_t bytes, hipStream_t s) {
+    AllocScope *sc = tl_scope;
+    if (sc && sc->arena) {
+        Arena &a = *sc->arena;
+        const size_t off = (a.used + 255) & ~size_t(255);
+        if (off > a.size || bytes > a.size - off) throw ArenaFull{off + bytes, a.size};
+        a.used = off + bytes;
+        a.peak = std::max(a.peak, a.used);
+        return a.base + off;
+    }
+    if (sc && sc->hook) {
+        void *p = sc->hook->alloc(bytes, static_cast<void *>(s), sc->hook->ctx);
+        if (!p) throw OomError{bytes};
+        return p;
+    }
+    return cache_alloc(bytes, s);
+}
+
+void dev_free(void *p, hipStream_t s) {
+    if (!p) return;
+    AllocScope *sc = tl_scope;
+    if (sc && sc->arena) return;  // released with the arena
+    if (sc && sc->hook) {
+        if (sc->hook->free) sc->hook->free(p, static_cast<void *>(s), sc->hook->ctx);
+        return;
+    }
+    cache_free(p, s);
+}
+
+static void *cache_alloc(size_t bytes, hipStream_t s) {
     int dev = 0;
     SJ_HIP(hipGetDevice(&dev));
     const size_t sz = round_size(bytes);
@@ -179,8 +217,7 @@ void *dev_alloc(size_t bytes, hipStream_t s) {
     return p;
 }
 
-void dev_free(void *p, hipStream_t s) {
-    if (!p) return;
+static void cache_free(void *p, hipStream_t s) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return;
     std::lock_guard<std::mutex> lk(g_mu);
@@ -194,16 +231,61 @@ void dev_free(void *p, hipStream_t s) {
 void set_error(const std::string &msg) { g_err = msg; }
 const char *last_error() { return g_err.c_str(); }
 
-// Computes per-query counts with `path` into the handle's cache (sorted
-// order), their exclusive prefix sums and the total.
-static void compute_counts(Grid &g, sj_path path, RefineOut &ro, hipStream_t s) {
+// A device buffer released (in stream order) when it goes out of scope.
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    hipStream_t s = nullptr;
+    DevBuf(size_t n, hipStream_t st) : p(dev_alloc_n<T>(n, st)), s(st) {}
+    ~DevBuf() {
+        if (p) dev_free(p, s);
+    }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+};
+
+// Device time between two events recorded on one stream.
+struct CallTimer {
+    hipEvent_t a = nullptr, b = nullptr;
+    explicit CallTimer(bool on, hipStream_t s) {
+        if (!on) return;
+        SJ_HIP(hipEventCreate(&a));
+        SJ_HIP(hipEventCreate(&b));
+        SJ_HIP(hipEventRecord(a, s));
+    }
+    float stop(hipStream_t s) {
+        if (!a) return 0.f;
+        SJ_HIP(hipEventRecord(b, s));
+        SJ_HIP(hipEventSynchronize(b));
+        float ms = 0;
+        SJ_HIP(hipEventElapsedTime(&ms, a, b));
+        return ms;
+    }
+    ~CallTimer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+// Counts of one count pass, as the calls report them.
+struct CountRun {
+    bool ran = false;  // false: the counts were cached
+    HostCounters hc;
+    double band_rel = 0;
+    float ms_refine = 0;
+};
+
+// Computes per-query counts with `path` (range-checked) into the handle's
+// cache (sorted order), their exclusive prefix sums and the total.
+static void compute_counts(Grid &g, sj_path path, bool timed, CountRun &cr, hipStream_t s) {
     if (!g.cnt) {
         g.cnt = dev_alloc_n<int32_t>((size_t)g.n + 1, s);
         g.off = dev_alloc_n<int64_t>((size_t)g.n + 1, s);
-        g.aux = dev_alloc_n<unsigned long long>(4, s);
+        g.ctr = dev_alloc_n<DevCounters>(1, s);
     }
-    ro.band_dev = g.aux;
-    ro.aux_dev = g.aux + 1;
+    RefineOut ro;
+    ro.timed = timed;
+    ro.ctr = g.ctr;
     // FP64 count passes record per-tile in-masks; emission then reuses them
     const bool fp64 = path == SJ_FP64_VALU || path == SJ_FP64_MFMA;
     g.masks_valid = false;
@@ -213,22 +295,64 @@ static void compute_counts(Grid &g, sj_path path, RefineOut &ro, hipStream_t s) 
     hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, g.cnt + g.n, 0);
     SJ_HIP(hipGetLastError());
     if (g.n > 0) refine_count(g, path, g.cnt, ro, s);
+    else fill_zero(g.ctr, sizeof(DevCounters), s);
     exclusive_scan_i32_to_i64(g.cnt, g.off, g.n + 1, s);
-    int64_t total = 0;  // total and the band counters: one sync
-    unsigned long long aux[4] = {0, 0, 0, 0};
+    int64_t total = 0;  // total and the counters: one sync
+    DevCounters hctr{};
     SJ_HIP(hipMemcpyAsync(&total, g.off + g.n, sizeof total, hipMemcpyDeviceToHost, s));
-    SJ_HIP(hipMemcpyAsync(aux, g.aux, sizeof aux, hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipMemcpyAsync(&hctr, g.ctr, sizeof hctr, hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
     g.total = total;
     g.masks_valid = ro.masks != nullptr;
-    ro.band_pairs = (int64_t)aux[0];
-    ro.tiles_pruned = (path == SJ_FP64_MFMA || path == SJ_FP64_VALU) ? (int64_t)aux[1] : 0;
+    g.count_path = path;
+    cr.ran = true;
+    cr.hc = read_counters(hctr);
+    cr.band_rel = ro.band_rel;
     if (path == SJ_FP32_MFMA || path == SJ_BF16_MFMA || path == SJ_BF16X3_MFMA) {
-        double dl;
-        std::memcpy(&dl, &aux[3], sizeof dl);
-        ro.band_rel = g.eps2 > 0 ? dl / g.eps2 : 0.0;
+        const double sc = lowp_scale(g);  // the band is in the tiles' scaled units
+        cr.band_rel = g.eps2 > 0 ? cr.hc.max_delta / (g.eps2 * sc * sc) : 0.0;
     }
+    cr.ms_refine = ro.kt.ms();
     g.have_counts = true;
+}
+
+// The path that runs a request: unsupported d for the low-precision tiles is
+// an error; otherwise the range guards pick the first exact path that fits.
+static sj_path path_for(const Grid &g, sj_path path) {
+    if ((path == SJ_FP32_MFMA || path == SJ_BF16_MFMA || path == SJ_BF16X3_MFMA) && g.d > kLpMaxD)
+        throw Unsupported{"FP32/BF16 MFMA paths support d <= 64"};
+    return effective_path(g, path);
+}
+
+static void fill_stats(sj_stats *st, const Grid &g, int64_t pairs, const CountRun &cr, sj_path run, float ms,
+                       float ms_emit, const HostCounters *emit_ctr, double emit_band_rel) {
+    if (!st) return;
+    std::memset(st, 0, sizeof *st);
+    st->cand_ref = g.cand_ref;  // -1 until selfjoin_grid_info computed it
+    st->cand_eval = g.cand_items;
+    st->pairs = pairs;
+    st->rechecked = (cr.ran ? cr.hc.rechecked : 0) + (emit_ctr ? emit_ctr->rechecked : 0);
+    st->rechecked_in = (cr.ran ? cr.hc.rechecked_in : 0) + (emit_ctr ? emit_ctr->rechecked_in : 0);
+    st->band_rel = std::max(cr.ran ? cr.band_rel : 0.0, emit_band_rel);
+    st->ms = ms;
+    st->ms_build = g.ms_build;
+    st->ms_refine = cr.ran ? cr.ms_refine : 0.0;
+    st->ms_emit = ms_emit;
+    st->tiles_pruned = cr.ran ? cr.hc.pruned : 0;
+    st->path_run = (int32_t)run;
+}
+
+// The whole result in one chunk (no device search needed).
+static ChunkPlan whole_plan(const Grid &g) {
+    ChunkPlan p;
+    p.written = g.total;
+    p.next = g.n;
+    p.item_lo = 0;
+    p.item_hi = g.items;
+    p.block_lo = 0;
+    p.block_hi = g.nblocks;
+    p.base = 0;
+    return p;
 }
 
 }  // namespace sj
@@ -245,6 +369,11 @@ using namespace sj;
     catch (const OomError &e) {                                                            \
         set_error("device allocation of " + std::to_string(e.bytes) + " bytes failed");    \
         return SJ_ERR_OOM;                                                                 \
+    }                                                                                      \
+    catch (const ArenaFull &e) {                                                           \
+        set_error("the work needs " + std::to_string(e.need) + " bytes of the " +          \
+                  std::to_string(e.size) + "-byte static scratch");                        \
+        return SJ_ERR_CAPACITY;                                                            \
     }                                                                                      \
     catch (const std::bad_alloc &) {                                                       \
         set_error("host allocation failed");                                               \
@@ -285,10 +414,17 @@ sj_status selfjoin_build_grid(const double *points, int64_t n, int32_t d, double
     if (n > 0 && !points) return invalid("points is NULL");
     if (opts && (opts->index_dims < -1 || opts->index_dims > kMaxIndexDims))
         return invalid("index_dims must be in [-1, 4]");
+    if (opts && !opts->alloc != !opts->free) return invalid("alloc and free must be given together");
     hipStream_t s = static_cast<hipStream_t>(stream);
     sj_grid *h = nullptr;
     SJ_API_BEGIN
     h = new sj_grid();
+    if (opts && opts->alloc) {
+        h->g.hook.alloc = opts->alloc;
+        h->g.hook.free = opts->free;
+        h->g.hook.ctx = opts->alloc_ctx;
+    }
+    AllocScope scope(h->g.hook);
     try {
         build_grid(h->g, points, n, d, eps, opts ? opts->index_dims : 0, s);
     } catch (...) {
@@ -311,37 +447,18 @@ sj_status selfjoin_count(sj_grid *gh, sj_path path, int32_t *per_point, int64_t 
     hipStream_t s = static_cast<hipStream_t>(stream);
     SJ_API_BEGIN
     Grid &g = gh->g;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (stats) {
-        SJ_HIP(hipEventCreate(&e0));
-        SJ_HIP(hipEventCreate(&e1));
-        SJ_HIP(hipEventRecord(e0, s));
-    }
-    RefineOut ro;
-    ro.timed = stats != nullptr;
-    compute_counts(g, path, ro, s);
+    AllocScope scope(g.hook);
+    const sj_path run = path_for(g, path);
+    CallTimer tm(stats != nullptr, s);
+    CountRun cr;
+    compute_counts(g, run, stats != nullptr, cr, s);
     if (per_point && g.n > 0) {
         hipLaunchKernelGGL(k_scatter_counts, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s, g.cnt, g.perm,
                            g.n, per_point);
         SJ_HIP(hipGetLastError());
     }
     *total = g.total;
-    if (stats) {
-        SJ_HIP(hipEventRecord(e1, s));
-        SJ_HIP(hipEventSynchronize(e1));
-        float ms = 0;
-        SJ_HIP(hipEventElapsedTime(&ms, e0, e1));
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        stats->cand_ref = g.cand_ref;  // -1 until selfjoin_grid_info computed it
-        stats->cand_eval = g.cand_items;
-        stats->pairs = g.total;
-        stats->band_pairs = ro.band_pairs;
-        stats->band_rel = ro.band_rel;
-        stats->ms = ms;
-        stats->ms_kernel = ro.kt.ms();
-        stats->tiles_pruned = ro.tiles_pruned;
-    }
+    if (stats) fill_stats(stats, g, g.total, cr, run, tm.stop(s), 0.f, nullptr, 0.0);
     return SJ_OK;
     SJ_API_END
 }
@@ -358,46 +475,28 @@ sj_status selfjoin_knn(sj_grid *gh, sj_path path, int32_t k, int64_t pair_budget
     SJ_API_BEGIN
     Grid &g = gh->g;
     if (g.n == 0) return SJ_OK;
-    if (!g.have_counts) {
-        RefineOut ro;
-        compute_counts(g, path, ro, s);
-    }
+    AllocScope scope(g.hook);
+    const sj_path run = path_for(g, path);  // checked before anything is allocated
+    CountRun cr;
+    if (!g.have_counts) compute_counts(g, run, false, cr, s);
     const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(g.total, pair_budget ? pair_budget : kKnnBudget));
-    int32_t *pairs = dev_alloc_n<int32_t>(2 * cap, s);
-    double *pd2 = dev_alloc_n<double>(cap, s);
+    DevBuf<int32_t> pairs(2 * (size_t)cap, s);
+    DevBuf<double> pd2((size_t)cap, s);
+    DevBuf<DevCounters> ctr(1, s);
     int64_t cursor = 0;
     while (cursor < g.n) {
-        ChunkPlan p;
-        if (cursor == 0 && cap >= g.total) {
-            p.written = g.total;
-            p.next = g.n;
-            p.item_lo = 0;
-            p.item_hi = g.items;
-            p.block_lo = 0;
-            p.block_hi = g.nblocks;
-            p.base = 0;
-        } else {
-            p = plan_chunk(g, cursor, cap, s);
-        }
-        if (p.too_small) {
-            dev_free(pd2, s);
-            dev_free(pairs, s);
-            throw Unsupported{"a point has more pairs than pair_budget"};
-        }
+        const ChunkPlan p = (cursor == 0 && cap >= g.total) ? whole_plan(g) : plan_chunk(g, cursor, cap, s);
+        if (p.too_small) throw Unsupported{"a point has more pairs than pair_budget"};
         RefineOut re;
-        re.band_dev = dev_alloc_n<unsigned long long>(4, s);
-        re.aux_dev = re.band_dev + 1;
-        refine_pairs(g, path, p, cursor, pairs, pd2, re, s);
-        dev_free(re.band_dev, s);
+        re.ctr = ctr.p;
+        refine_pairs(g, run, p, cursor, pairs.p, pd2.p, re, s);
         const int64_t nq = p.next - cursor;
         hipLaunchKernelGGL(k_knn_select, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s,
-                           reinterpret_cast<const int2 *>(pairs), pd2, g.off, p.base, g.perm, cursor, p.next, k, nbr,
-                           nbr_d2, nfound);
+                           reinterpret_cast<const int2 *>(pairs.p), pd2.p, g.off, p.base, g.perm, cursor, p.next, k,
+                           nbr, nbr_d2, nfound);
         SJ_HIP(hipGetLastError());
         cursor = p.next;
     }
-    dev_free(pd2, s);
-    dev_free(pairs, s);
     return SJ_OK;
     SJ_API_END
 }
@@ -413,20 +512,19 @@ sj_status selfjoin_core_points(sj_grid *gh, sj_path path, int32_t min_pts, uint8
     hipStream_t s = static_cast<hipStream_t>(stream);
     SJ_API_BEGIN
     Grid &g = gh->g;
-    if (!g.have_counts) {
-        RefineOut ro;
-        compute_counts(g, path, ro, s);
-    }
+    AllocScope scope(g.hook);
+    const sj_path run = path_for(g, path);
+    CountRun cr;
+    if (!g.have_counts) compute_counts(g, run, false, cr, s);
     unsigned long long hc = 0;
     if (g.n > 0) {
-        unsigned long long *dc = dev_alloc_n<unsigned long long>(1, s);
-        fill_zero(dc, sizeof(unsigned long long), s);
+        DevBuf<unsigned long long> dc(1, s);
+        fill_zero(dc.p, sizeof(unsigned long long), s);
         hipLaunchKernelGGL(k_core_flags, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s, g.cnt, g.perm, g.n,
-                           min_pts, is_core, dc);
+                           min_pts, is_core, dc.p);
         SJ_HIP(hipGetLastError());
-        SJ_HIP(hipMemcpyAsync(&hc, dc, sizeof hc, hipMemcpyDeviceToHost, s));
+        SJ_HIP(hipMemcpyAsync(&hc, dc.p, sizeof hc, hipMemcpyDeviceToHost, s));
         SJ_HIP(hipStreamSynchronize(s));
-        dev_free(dc, s);
     }
     *ncore = (int64_t)hc;
     return SJ_OK;
@@ -445,64 +543,41 @@ sj_status selfjoin_pairs(sj_grid *gh, sj_path path, int64_t cursor, int32_t *pai
     hipStream_t s = static_cast<hipStream_t>(stream);
     SJ_API_BEGIN
     Grid &g = gh->g;
+    AllocScope scope(g.hook);
+    const sj_path run = path_for(g, path);
     if (cursor == g.n) {
         *written = 0;
         *next_cursor = g.n;
+        if (stats) fill_stats(stats, g, 0, CountRun{}, run, 0.f, 0.f, nullptr, 0.0);
         return SJ_OK;
     }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (stats) {
-        SJ_HIP(hipEventCreate(&e0));
-        SJ_HIP(hipEventCreate(&e1));
-        SJ_HIP(hipEventRecord(e0, s));
-    }
-    RefineOut ro;
-    if (!g.have_counts) compute_counts(g, path, ro, s);
-    ChunkPlan p;
-    if (cursor == 0 && capacity >= g.total) {
-        // the whole result fits: no device search needed
-        p.written = g.total;
-        p.next = g.n;
-        p.item_lo = 0;
-        p.item_hi = g.items;
-        p.block_lo = 0;
-        p.block_hi = g.nblocks;
-        p.base = 0;
-    } else {
-        p = plan_chunk(g, cursor, capacity, s);
-    }
+    CallTimer tm(stats != nullptr, s);
+    CountRun cr;
+    if (!g.have_counts) compute_counts(g, run, stats != nullptr, cr, s);
+    const ChunkPlan p = (cursor == 0 && capacity >= g.total) ? whole_plan(g) : plan_chunk(g, cursor, capacity, s);
     if (p.too_small) {
         *written = p.written;
-        if (stats) {
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-        }
         set_error("capacity too small for the next query's pairs");
         return SJ_ERR_CAPACITY;
     }
+    DevBuf<DevCounters> ctr(1, s);
     RefineOut re;
     re.timed = stats != nullptr;
-    re.band_dev = dev_alloc_n<unsigned long long>(4, s);
-    re.aux_dev = re.band_dev + 1;
-    refine_pairs(g, path, p, cursor, pairs, d2, re, s);
-    dev_free(re.band_dev, s);
+    re.ctr = ctr.p;
+    refine_pairs(g, run, p, cursor, pairs, d2, re, s);
     *written = p.written;
     *next_cursor = p.next;
     if (stats) {
-        SJ_HIP(hipEventRecord(e1, s));
-        SJ_HIP(hipEventSynchronize(e1));
-        float ms = 0;
-        SJ_HIP(hipEventElapsedTime(&ms, e0, e1));
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        stats->cand_ref = g.cand_ref;
-        stats->cand_eval = g.cand_items;
-        stats->pairs = p.written;
-        stats->band_pairs = ro.band_pairs;
-        stats->band_rel = re.band_rel;
-        stats->ms = ms;
-        stats->ms_kernel = re.kt.ms();
-        stats->tiles_pruned = 0;
+        DevCounters h{};
+        SJ_HIP(hipMemcpyAsync(&h, ctr.p, sizeof h, hipMemcpyDeviceToHost, s));
+        const float ms = tm.stop(s);  // synchronises the stream
+        const HostCounters he = read_counters(h);
+        double brel = re.band_rel;
+        if (run == SJ_FP32_MFMA || run == SJ_BF16_MFMA || run == SJ_BF16X3_MFMA) {
+            const double sc = lowp_scale(g);
+            brel = g.eps2 > 0 ? he.max_delta / (g.eps2 * sc * sc) : 0.0;
+        }
+        fill_stats(stats, g, p.written, cr, run, ms, re.kt.ms(), &he, brel);
     }
     return SJ_OK;
     SJ_API_END
@@ -516,7 +591,8 @@ sj_status selfjoin_measure_error(sj_grid *gh, sj_path path, double *max_abs_err,
     if (!max_abs_err || !max_band || !violations) return invalid("NULL output");
     hipStream_t s = static_cast<hipStream_t>(stream);
     SJ_API_BEGIN
-    refine_measure(gh->g, path, max_abs_err, max_band, violations, s);
+    AllocScope scope(gh->g.hook);
+    refine_measure(gh->g, path_for(gh->g, path), max_abs_err, max_band, violations, s);
     return SJ_OK;
     SJ_API_END
 }
@@ -526,6 +602,7 @@ sj_status selfjoin_grid_info(sj_grid *gh, sj_grid_info *info, void *stream) {
     if (!gh || !info) return invalid("NULL argument");
     SJ_API_BEGIN
     Grid &g = gh->g;
+    AllocScope scope(g.hook);
     grid_cref(g, static_cast<hipStream_t>(stream));
     info->n = g.n;
     info->d = g.d;
@@ -544,6 +621,7 @@ sj_status selfjoin_grid_info(sj_grid *gh, sj_grid_info *info, void *stream) {
 void selfjoin_free_grid(sj_grid *gh, void *stream) {
     if (!gh) return;
     try {
+        AllocScope scope(gh->g.hook);
         free_grid(gh->g, static_cast<hipStream_t>(stream));
     } catch (...) {
     }
@@ -564,6 +642,6 @@ const char *selfjoin_status_string(sj_status s) {
 
 const char *selfjoin_last_error(void) { return last_error(); }
 
-const char *selfjoin_version(void) { return "selfjoin-mi355x 0.1 (gfx950)"; }
+const char *selfjoin_version(void) { return "selfjoin-mi355x 0.2 (gfx950)"; }
 
 }  // extern "C"

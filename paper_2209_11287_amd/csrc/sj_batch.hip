@@ -82,14 +82,13 @@ int tune_index_dims(const double *pts, int64_t n, int d, double eps, hipStream_t
             int32_t *cnt = dev_alloc_n<int32_t>((size_t)n + 1, s);
             RefineOut ro;
             ro.timed = true;
-            ro.band_dev = dev_alloc_n<unsigned long long>(4, s);
-            ro.aux_dev = ro.band_dev + 1;
+            ro.ctr = dev_alloc_n<DevCounters>(1, s);
             refine_count(g, SJ_FP64_MFMA, cnt, ro, s);  // warm
             ro.kt.ms();
             refine_count(g, SJ_FP64_MFMA, cnt, ro, s);
             const float ms = ro.kt.ms();
             dev_free(cnt, s);
-            dev_free(ro.band_dev, s);
+            dev_free(ro.ctr, s);
             if (ms < best) {
                 best = ms;
                 best_k = k;
@@ -114,7 +113,7 @@ struct Batch {
     int64_t *item_base_dev = nullptr;     // B + 1
     int32_t *queue = nullptr;             // global item indices, longest first
     int *counter = nullptr;
-    unsigned long long *band = nullptr;
+    DevCounters *ctr = nullptr;
     BProb *probs_dev = nullptr;
     std::vector<BProb> probs;
     int64_t *totals_dev = nullptr;
@@ -142,7 +141,7 @@ void batch_free(Batch &b, hipStream_t s) {
         delete g;
     }
     b.grids.clear();
-    void *bufs[] = {b.item_base_dev, b.queue, b.counter, b.band, b.probs_dev, b.totals_dev};
+    void *bufs[] = {b.item_base_dev, b.queue, b.counter, b.ctr, b.probs_dev, b.totals_dev};
     for (void *p : bufs)
         if (p) dev_free(p, s);
 }
@@ -205,7 +204,7 @@ void batch_build(Batch &b, int B, const double *const *points, const int64_t *n,
     dev_free(ka, s);
     dev_free(kb, s);
     b.counter = dev_alloc_n<int>(1, s);
-    b.band = dev_alloc_n<unsigned long long>(1, s);
+    b.ctr = dev_alloc_n<DevCounters>(1, s);
     b.totals_dev = dev_alloc_n<int64_t>(B, s);
     b.probs.resize(B);
     for (int i = 0; i < B; ++i) {
@@ -227,7 +226,7 @@ void batch_build(Batch &b, int B, const double *const *points, const int64_t *n,
 
 // Count pipeline: captured into a graph on first use per (path, stream), then
 // replayed. The graph holds only kernel nodes (no memset or copy nodes).
-float batch_count(Batch &b, sj_path path, hipStream_t s, int64_t *band_pairs) {
+float batch_count(Batch &b, sj_path path, hipStream_t s, HostCounters *hc) {
     const int pi = path == SJ_FP64_MFMA ? 1 : 0;
     hipEvent_t e0, e1;
     SJ_HIP(hipEventCreate(&e0));
@@ -244,7 +243,7 @@ float batch_count(Batch &b, sj_path path, hipStream_t s, int64_t *band_pairs) {
         hipGraph_t graph;
         SJ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         launch_batch(false, path, b.probs_dev, b.item_base_dev, b.B, b.queue, (int)b.total_items, b.counter, nullptr,
-                     b.band, cs);
+                     b.ctr, cs);
         launch_seg_scan(b.probs_dev, b.B, b.totals_dev, cs);
         SJ_HIP(hipStreamEndCapture(cs, &graph));
         SJ_HIP(hipGraphInstantiate(&b.exec[pi], graph, nullptr, nullptr, 0));
@@ -255,15 +254,15 @@ float batch_count(Batch &b, sj_path path, hipStream_t s, int64_t *band_pairs) {
     SJ_HIP(hipEventRecord(e0, s));
     SJ_HIP(hipGraphLaunch(b.exec[pi], s));
     SJ_HIP(hipEventRecord(e1, s));
-    unsigned long long hb = 0;
+    DevCounters hb{};
     SJ_HIP(hipMemcpyAsync(b.totals.data(), b.totals_dev, b.B * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    SJ_HIP(hipMemcpyAsync(&hb, b.band, sizeof hb, hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipMemcpyAsync(&hb, b.ctr, sizeof hb, hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
     float ms = 0;
     SJ_HIP(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    *band_pairs = (int64_t)hb;
+    *hc = read_counters(hb);
     for (int i = 0; i < b.B; ++i) {
         b.grids[i]->total = b.totals[i];
         b.grids[i]->have_counts = true;
@@ -286,7 +285,7 @@ float batch_pairs(Batch &b, sj_path path, int32_t *pairs, hipStream_t s) {
     SJ_HIP(hipEventCreate(&e1));
     SJ_HIP(hipEventRecord(e0, s));
     launch_batch(true, path, b.probs_dev, b.item_base_dev, b.B, b.queue, (int)b.total_items, b.counter, pairs,
-                 b.band, s);
+                 b.ctr, s);
     SJ_HIP(hipEventRecord(e1, s));
     SJ_HIP(hipEventSynchronize(e1));
     float ms = 0;
@@ -376,8 +375,8 @@ sj_status selfjoin_batch_count(sj_batch *bh, sj_path path, int64_t *totals, sj_s
     hipStream_t s = static_cast<hipStream_t>(stream);
     SJB_TRY
     Batch &b = bh->b;
-    int64_t band = 0;
-    const float ms = batch_count(b, path, s, &band);
+    HostCounters hc;
+    const float ms = batch_count(b, path, s, &hc);
     int64_t sum = 0, cev = 0;
     for (int i = 0; i < b.B; ++i) {
         totals[i] = b.totals[i];
@@ -385,14 +384,16 @@ sj_status selfjoin_batch_count(sj_batch *bh, sj_path path, int64_t *totals, sj_s
         cev += b.grids[i]->cand_items;
     }
     if (stats) {
+        std::memset(stats, 0, sizeof *stats);
         stats->cand_ref = -1;
         stats->cand_eval = cev;
         stats->pairs = sum;
-        stats->band_pairs = band;
-        stats->band_rel = 0;
+        stats->rechecked = hc.rechecked;
+        stats->rechecked_in = hc.rechecked_in;
         stats->ms = ms;
-        stats->ms_kernel = ms;
-        stats->tiles_pruned = 0;
+        stats->ms_refine = ms;
+        stats->tiles_pruned = hc.pruned;
+        stats->path_run = (int32_t)path;
     }
     return SJ_OK;
     SJB_CATCH
@@ -413,8 +414,8 @@ sj_status selfjoin_batch_pairs(sj_batch *bh, sj_path path, int32_t *pairs, int64
     SJB_TRY
     Batch &b = bh->b;
     if (!b.counted) {
-        int64_t band = 0;
-        batch_count(b, path, s, &band);
+        HostCounters hc;
+        batch_count(b, path, s, &hc);
     }
     int64_t sum = 0;
     for (int i = 0; i < b.B; ++i) sum += b.totals[i];
@@ -435,14 +436,12 @@ sj_status selfjoin_batch_pairs(sj_batch *bh, sj_path path, int32_t *pairs, int64
     }
     offsets[b.B] = off;
     if (stats) {
+        std::memset(stats, 0, sizeof *stats);
         stats->cand_ref = -1;
-        stats->cand_eval = 0;
         stats->pairs = sum;
-        stats->band_pairs = 0;
-        stats->band_rel = 0;
         stats->ms = ms;
-        stats->ms_kernel = ms;
-        stats->tiles_pruned = 0;
+        stats->ms_emit = ms;
+        stats->path_run = (int32_t)path;
     }
     return SJ_OK;
     SJB_CATCH

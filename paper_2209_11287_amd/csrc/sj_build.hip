@@ -181,10 +181,12 @@ __global__ void k_keys(const double *__restrict__ X, int64_t n, KeyGeom geo,
     for (int j = 0; j < geo.k; ++j) {
         // c = floor(fl(fl(x - lo) / w)), clamped: the same two roundings as
         // the reference grid definition.
+        // (clamped in double before the conversion: an infinite quotient
+        // converts to nothing out of range)
         const double t = __ddiv_rn(__dsub_rn(X[i * geo.d + j], geo.lo[j]), geo.w);
         double q = floor(t);
-        int64_t c = (int64_t)q;
-        c = c < 0 ? 0 : (c > geo.m[j] - 1 ? geo.m[j] - 1 : c);
+        q = !(q >= 0.0) ? 0.0 : (q > (double)(geo.m[j] - 1) ? (double)(geo.m[j] - 1) : q);
+        const int64_t c = (int64_t)q;
         kk += (unsigned long long)c * (unsigned long long)geo.stride[j];
         if (j == geo.k - 1) sub = sub_cell(t, c, geo.sb);
     }
@@ -904,7 +906,7 @@ void exclusive_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipSt
 
 void free_grid(Grid &g, hipStream_t s) {
     void *bufs[] = {g.xs,   g.xa,       g.nrm,        g.perm,       g.cell_key, g.cell_start, g.ranges,
-                    g.item, g.dev_nmax, g.line_first, g.line_table, g.blocks,   g.cnt,        g.off, g.aux,
+                    g.item, g.dev_nmax, g.line_first, g.line_table, g.blocks,   g.cnt,        g.off, g.ctr,
                     g.tile_off, g.masks, g.pn};
     for (void *p : bufs)
         if (p) dev_free(p, s);
@@ -920,7 +922,7 @@ void free_grid(Grid &g, hipStream_t s) {
     g.blocks = nullptr;
     g.cnt = nullptr;
     g.off = nullptr;
-    g.aux = nullptr;
+    g.ctr = nullptr;
     g.tile_off = nullptr;
     g.masks = nullptr;
     g.masks_valid = false;
@@ -938,16 +940,22 @@ static void choose_geometry(Grid &g, int index_dims) {
     int k = index_dims < 0   ? 1
             : index_dims > 0 ? std::min(index_dims, std::min(g.d, kMaxIndexDims))
                              : std::min(g.d, kMaxIndexDims);
+    // cells per dimension counted in double (an extent of 2^63 cells or more
+    // must not wrap); if the first dimension alone needs 2^62 cells or more,
+    // the grid is one cell (every key clamps to 0)
+    double mc[kMaxIndexDims];
     for (;;) {
         double prod = 1.0;
         for (int j = 0; j < k; ++j) {
-            g.m[j] = (int64_t)std::floor((g.hi[j] - g.lo[j]) / w) + 1;
-            prod *= (double)g.m[j];
+            mc[j] = std::floor((g.hi[j] - g.lo[j]) / w) + 1.0;
+            prod *= mc[j];
         }
         if (prod < 0x1p62 || k == 1) break;
         --k;
     }
-    if ((double)g.m[0] >= 0x1p62) throw std::string("grid too fine: eps is too small for the data extent");
+    const bool one_cell = !(mc[0] < 0x1p62);
+    if (one_cell) mc[0] = 1.0;
+    for (int j = 0; j < k; ++j) g.m[j] = (int64_t)mc[j];
     g.k = k;
     int64_t st = 1;
     for (int j = k - 1; j >= 0; --j) {
@@ -962,7 +970,7 @@ static void choose_geometry(Grid &g, int index_dims) {
     // more digit when fewer are free); none in the index-free form
     int sb = (bits + 7) / 8 * 8 - bits;
     if (sb < 5) sb += 8;
-    g.sub_bits = index_dims < 0 ? 0 : std::min(sb, 64 - bits);
+    g.sub_bits = (index_dims < 0 || one_cell) ? 0 : std::min(sb, 64 - bits);
     g.nranges = 1;
     for (int j = 0; j < k - 1; ++j) g.nranges *= 3;
 }
@@ -977,6 +985,17 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     g.da = (d & 3) ? ((d + 1 + 3) & ~3) : d;
     g.build_stream = s;
     const size_t rows = (size_t)n + kRowPad;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // device time of the build
+    SJ_HIP(hipEventCreate(&ev0));
+    SJ_HIP(hipEventCreate(&ev1));
+    struct EvGuard {
+        hipEvent_t &a, &b;
+        ~EvGuard() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } evg{ev0, ev1};
+    SJ_HIP(hipEventRecord(ev0, s));
 
     // ---- G1: bounding box and finiteness (one host sync) ----
     if (n == 0) {
@@ -1006,7 +1025,7 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
         for (int j = 0; j < d; ++j) {
             g.lo[j] = hb[j];
             g.hi[j] = hb[d + j];
-            g.mid[j] = 0.5 * (g.lo[j] + g.hi[j]);
+            g.mid[j] = 0.5 * g.lo[j] + 0.5 * g.hi[j];  // no overflow for any finite lo, hi
         }
     }
     choose_geometry(g, index_dims);
@@ -1172,7 +1191,13 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
         SJ_HIP(hipMemcpyAsync(hc, counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         SJ_HIP(hipMemcpyAsync(&hn, g.dev_nmax, sizeof(double), hipMemcpyDeviceToHost, s));
         SJ_HIP(hipMemcpyAsync(hacc, acc, sizeof hacc, hipMemcpyDeviceToHost, s));
-        SJ_HIP(hipStreamSynchronize(s));
+    }
+    SJ_HIP(hipEventRecord(ev1, s));
+    SJ_HIP(hipEventSynchronize(ev1));
+    {
+        float ms = 0.f;
+        SJ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+        g.ms_build = ms;
     }
     g.cells = hc[0];
     g.items = hc[2];

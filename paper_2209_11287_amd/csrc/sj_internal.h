@@ -43,8 +43,42 @@ struct Unsupported {
     std::string what;
 };
 
-// Stream-ordered device allocation from the default memory pool (kept
-// cached: the pool's release threshold is raised on first use).
+// Device allocation. Every device buffer of the library comes from
+// dev_alloc / dev_free, which serve it from one of three sources, chosen per
+// thread by the innermost live AllocScope:
+//  - none (the default): the library's caching allocator (blocks kept per
+//    device and stream and reused; hipMalloc only on a miss);
+//  - a caller's hook (sj_opts.alloc / free / alloc_ctx): every allocation
+//    and release goes to the hook, with the stream;
+//  - an arena (a fixed device buffer): bump allocation, release is a no-op,
+//    exhaustion throws ArenaFull; nothing is allocated from the runtime.
+struct AllocHook {
+    void *(*alloc)(size_t bytes, void *stream, void *ctx) = nullptr;
+    void (*free)(void *p, void *stream, void *ctx) = nullptr;
+    void *ctx = nullptr;
+};
+
+struct Arena {
+    char *base = nullptr;
+    size_t size = 0, used = 0, peak = 0;
+};
+
+struct ArenaFull {
+    size_t need, size;
+};
+
+class AllocScope {
+public:
+    explicit AllocScope(const AllocHook &h);  // h.alloc null: the caching allocator
+    explicit AllocScope(Arena *a);
+    ~AllocScope();
+    AllocScope(const AllocScope &) = delete;
+    AllocScope &operator=(const AllocScope &) = delete;
+    const AllocHook *hook = nullptr;
+    Arena *arena = nullptr;
+    AllocScope *prev = nullptr;
+};
+
 void *dev_alloc(size_t bytes, hipStream_t s);
 void dev_free(void *p, hipStream_t s);
 
@@ -52,6 +86,18 @@ template <typename T>
 T *dev_alloc_n(size_t n, hipStream_t s) {
     return static_cast<T *>(dev_alloc(n * sizeof(T) + 16, s));
 }
+
+// Device counters of one refine launch (zeroed before it). Non-negative
+// doubles are kept as their bit patterns, whose integer order is theirs.
+struct DevCounters {
+    unsigned long long rechecked;     // band pairs re-evaluated with the exact chain
+    unsigned long long rechecked_in;  // of those, within eps
+    unsigned long long pruned;        // tiles left early by the partial-distance bound
+    unsigned long long max_delta;     // largest band half-width used (bits)
+    unsigned long long max_err;       // measure: largest |fast - exact| (bits)
+    unsigned long long violations;    // measure: errors above their band
+    unsigned long long spare[2];
+};
 
 // Candidate range of a work item: the union of the neighbouring cells of its
 // first and last cell along one offset of the leading indexed dimensions.
@@ -139,10 +185,13 @@ struct Grid {
     // cached per-query counts (sorted order) and their exclusive prefix sums
     int32_t *cnt = nullptr;
     int64_t *off = nullptr;      // n + 1 entries
-    unsigned long long *aux = nullptr;  // 4 counters read with the total
+    DevCounters *ctr = nullptr;  // counters of the count pass, read with the total
     bool have_counts = false;
     int64_t total = 0;
+    sj_path count_path = SJ_FP64_VALU;  // the path whose kernels made the cached counts
 
+    AllocHook hook;              // the handle's device allocator (alloc null: the caching allocator)
+    double ms_build = 0;         // device time of the build
     hipStream_t build_stream = nullptr;
 };
 
@@ -197,14 +246,19 @@ struct KernelTimer {
 struct RefineOut {
     bool timed = false;      // record events around the tile kernel
     KernelTimer kt;          // those events
-    unsigned long long *band_dev = nullptr;  // device counter of rechecked pairs
-    unsigned long long *aux_dev = nullptr;   // device: [2] largest band half-width (bits)
-    unsigned long long *masks = nullptr;     // per-tile in-masks to record (FP64 count), nullable
-    int64_t band_pairs = 0;
-    double band_rel = 0;
+    DevCounters *ctr = nullptr;            // device counters (zeroed by the launcher)
+    unsigned long long *masks = nullptr;   // per-tile in-masks to record (FP64 count), nullable
+    double band_rel = 0;     // largest band half-width / eps^2
     int64_t cand_eval = 0;
-    int64_t tiles_pruned = 0;  // FP64 MFMA count: tiles dropped by the partial-distance bound
 };
+
+// Host copy of a launch's counters (one device-to-host copy with the
+// caller's other readbacks).
+struct HostCounters {
+    int64_t rechecked = 0, rechecked_in = 0, pruned = 0, violations = 0;
+    double max_delta = 0, max_err = 0;
+};
+HostCounters read_counters(const DevCounters &c);
 
 
 struct ChunkPlan {
@@ -224,11 +278,22 @@ void refine_measure(Grid &g, sj_path path, double *max_err, double *max_band, in
 
 // Batched form (sj_refine.hip).
 void launch_batch(bool emit, sj_path path, const BProb *probs, const int64_t *item_base, int B,
-                  const int32_t *queue, int total, int *counter, int32_t *pairs, unsigned long long *band,
+                  const int32_t *queue, int total, int *counter, int32_t *pairs, DevCounters *ctr,
                   hipStream_t s);
 void launch_seg_scan(const BProb *probs, int B, int64_t *totals, hipStream_t s);
 DevGrid make_dev_grid(const Grid &g);
 double fp64_mfma_delta(const Grid &g);
+
+// Range guards. FP64 MFMA: the Gram form over centred rows stays finite
+// when the largest centred squared norm is at most 2^1000. FP32 / BF16 tiles
+// (scaled by lowp_scale, a power of two putting eps in [1, 2)): eps in
+// [2^-500, 2^500] and every dimension's extent at most 2^40 eps. A request
+// for a path whose guard fails runs the next path that passes (low
+// precision -> FP64 MFMA -> FP64 VALU, which is the exact chain itself).
+bool m64_in_range(const Grid &g);
+bool lowp_in_range(const Grid &g);
+double lowp_scale(const Grid &g);
+sj_path effective_path(const Grid &g, sj_path requested);
 
 // Low-precision paths (sj_lowp.hip).
 void lowp_count(Grid &g, sj_path path, int32_t *cnt_sorted, RefineOut &ro, hipStream_t s);

@@ -24,6 +24,13 @@
 // tile yields D = |c'|^2 - 2 q'.c' (Eq. (3) with |q'|^2 moved to the
 // threshold side): in iff D <= eps^2 - |q'|^2.
 //
+// Scale. The tiles work on centred coordinates times sc = 2^-ilogb(eps), a
+// power of two that puts eps in [1, 2) (exact in FP64), so the FP32 / BF16
+// values keep their precision whatever the data's units; the band below is
+// in those units. The grid's range guard (lowp_in_range) sends data whose
+// extent exceeds 2^40 eps in some dimension, or eps outside [2^-500, 2^500],
+// to the FP64 paths instead, so no scaled value approaches the FP32 range.
+//
 // Proven band, per query row. Let a = |q'|, eta the input rounding unit
 // (subtraction in FP64, then rounding to the tile precision), u_a the FP32
 // accumulation unit taken twice for safety, eps+ = eps (1 + (d + 4) u64),
@@ -70,7 +77,9 @@ struct LpGrid {
     const int32_t *blocks;
     int32_t nblocks;
     int32_t d, dp, nranges;
-    double eps, eps2;
+    double eps2;         // fl(eps^2): the exact test of the recheck
+    double sc;           // power of two with eps * sc in [1, 2): the tiles work on scaled centred coordinates
+    double eps_s, eps2_s;  // eps * sc, eps2 * sc^2 (exact)
 };
 
 struct LpOut {
@@ -80,8 +89,7 @@ struct LpOut {
     int32_t qlo, qhi;
     int32_t *pairs;
     double *d2;
-    unsigned long long *band;      // [0] rechecked pairs
-    unsigned long long *meas;      // [0] max err bits, [1] violations, [2] max delta bits
+    DevCounters *ctr;              // rechecks, band widths (scaled units), measurements
     int32_t block_lo;              // first block item of this launch
 };
 
@@ -151,7 +159,11 @@ __device__ __forceinline__ double round_in(double y, unsigned &bits) {
 
 __device__ __forceinline__ double gam(double m, double u) { return m * u / (1.0 - m * u); }
 
-// Band half-width of one query row (see the file comment): a2 = |q'|^2.
+// Band half-width of one query row (see the file comment), in the scaled
+// units of the tiles (eps in [1, 2)): a2 = |q'|^2. Besides the relative
+// terms, FP32 / BF16 values below the normal range (2^-126) may be flushed:
+// at most 2^-126 per coordinate (2^-123 per vector of d <= 64) on the inputs
+// and 2^-126 per product or partial sum, norm and threshold conversion.
 template <int PREC>
 __device__ __forceinline__ double lp_delta(double a2, double eps, double eps2, int d, int K) {
     const double u64 = 0x1p-53, u32 = 0x1p-24;
@@ -162,7 +174,7 @@ __device__ __forceinline__ double lp_delta(double a2, double eps, double eps2, i
     const double ua = 2.0 * 0x1p-24;
     const double a = sqrt(a2 * (1.0 + 1e-12));
     const double epsp = eps * (1.0 + (d + 4) * u64);
-    const double e = eta * (2.0 * a + epsp) / (1.0 - 2.0 * eta);  // conversion error at |c'| = a + tau
+    const double e = eta * (2.0 * a + epsp) / (1.0 - 2.0 * eta) + 0x1p-122;  // conversion error at |c'| = a + tau
     const double tau = epsp + e;
     const double b = a + tau;  // candidates beyond cannot be near the threshold
     const double A2 = a * a, B2 = b * b;
@@ -175,7 +187,8 @@ __device__ __forceinline__ double lp_delta(double a2, double eps, double eps2, i
     const double sp = PREC == PREC_BF16X3 ? (1.0 + 0x1p-6) * (1.0 + 0x1p-6) : 1.0;
     const double drop = PREC == PREC_BF16X3 ? 0x1p-14 : 0.0;
     const double F = (u32 + gam(d, u64) + gk) * B2 + (2.0 * gk * sp + drop) * a * b  // accumulation
-                     + gam(d, u64) * A2 + u32 * (eps2 + A2);                       // threshold
+                     + gam(d, u64) * A2 + u32 * (eps2 + A2)                        // threshold
+                     + (2.0 * nt + 16.0) * 0x1p-126;                               // flushed tiny values
     return 2.0 * (F + 2.0 * tau * e + e * e + gam(d + 2, u64) * tau * tau) + (d + 2) * 0x1p-1021;
 }
 
@@ -291,7 +304,7 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
                 float v = 0.f;
                 if (s < ks && j < nq && k < d) {
                     unsigned bits;
-                    const double y = round_in<PREC>(__dsub_rn(qrow[k], xr[k]), bits);
+                    const double y = round_in<PREC>(__dsub_rn(qrow[k], xr[k]) * G.sc, bits);
                     nq_part = __fma_rn(y, y, nq_part);
                     v = -2.0f * __uint_as_float(bits);
                 }
@@ -304,7 +317,7 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
                     unsigned short h = 0, l = 0;
                     if (s < ks && j < nq && k < d) {
                         unsigned bits;
-                        const double y = round_in<PREC>(__dsub_rn(qrow[k], xr[k]), bits);
+                        const double y = round_in<PREC>(__dsub_rn(qrow[k], xr[k]) * G.sc, bits);
                         nq_part = __fma_rn(y, y, nq_part);
                         h = f32_to_bf16(-2.0f * bf16_to_f32((unsigned short)(bits & 0xffffu)));  // exact
                         l = f32_to_bf16(-2.0f * bf16_to_f32((unsigned short)(bits >> 16)));
@@ -330,8 +343,8 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
         const int i = 4 * g + r;
         const double v = __shfl(nqj, i);
         nqr[r] = v;
-        dlt[r] = lp_delta<PREC>(v, G.eps, G.eps2, d, K);
-        const double thr = G.eps2 - v;
+        dlt[r] = lp_delta<PREC>(v, G.eps_s, G.eps2_s, d, K);
+        const double thr = G.eps2_s - v;
         lo[r] = i < nq ? (float)(thr - dlt[r]) : -INFINITY;
         hi[r] = i < nq ? (float)(thr + dlt[r]) : -INFINITY;
         if (i < nq) maxdelta = fmax(maxdelta, dlt[r]);
@@ -357,7 +370,7 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
     const unsigned long long grp = 0xffffull << (16 * g);
     int cur[4] = {0, 0, 0, 0};
     int cnt[4] = {0, 0, 0, 0};
-    unsigned long long band = 0, viol = 0;
+    unsigned long long band = 0, band_in = 0, viol = 0;
     double maxerr = 0.0;
 
     auto flush = [&](int nflush) {
@@ -433,7 +446,7 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
                     }
                     unsigned bits = 0;
                     double y = 0.0;
-                    if (rowok && k < d) y = round_in<PREC>(__dsub_rn(x, xr[k]), bits);
+                    if (rowok && k < d) y = round_in<PREC>(__dsub_rn(x, xr[k]) * G.sc, bits);
                     np = __fma_rn(y, y, np);
                     if constexpr (PREC == PREC_F32) {
                         lpt[srow * STR + k] = bits;
@@ -509,7 +522,7 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
                         const double ex = exact_d2(G.xs + (int64_t)(q0 + i) * dp,
                                                    kRowsInLds ? &f64t[crow][0] : G.xs + (int64_t)(t + crow) * dp, d);
                         if (ex <= G.eps2) {  // the per-row bound covers pairs within eps
-                            const double err = fabs((double)acc[r] - (ex - nqr[r]));
+                            const double err = fabs((double)acc[r] - (ex * G.sc * G.sc - nqr[r]));
                             maxerr = fmax(maxerr, err);
                             if (err > dlt[r]) ++viol;
                         }
@@ -523,7 +536,10 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
                         const int i = 4 * g + r;
                         const double ex = exact_d2(G.xs + (int64_t)(q0 + i) * dp,
                                                    kRowsInLds ? &f64t[crow][0] : G.xs + (int64_t)(t + crow) * dp, d);
-                        if (ex <= G.eps2) inm |= 1u << r;
+                        if (ex <= G.eps2) {
+                            inm |= 1u << r;
+                            ++band_in;
+                        }
                         ++band;
                     }
                 }
@@ -571,20 +587,25 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
             if (j == 0 && 4 * g + r < nq) R.cnt[q0 + 4 * g + r] = v;
         }
     }
-    if (MODE != MODE_EMIT) {
-        for (int sh = 32; sh > 0; sh >>= 1) {
-            band += __shfl_xor(band, sh);
+    for (int sh = 32; sh > 0; sh >>= 1) {
+        band += __shfl_xor(band, sh);
+        band_in += __shfl_xor(band_in, sh);
+        if (MODE == MODE_MEASURE) {
             viol += __shfl_xor(viol, sh);
             maxerr = fmax(maxerr, __shfl_xor(maxerr, sh));
         }
-        if (lane == 0) {
-            if (band) atomicAdd(R.band, band);
-            if (MODE == MODE_MEASURE) {
-                atomicMax(&R.meas[0], (unsigned long long)__double_as_longlong(maxerr));
-                if (viol) atomicAdd(&R.meas[1], viol);
-            }
-            atomicMax(&R.meas[2], (unsigned long long)__double_as_longlong(maxdelta));
+        maxdelta = fmax(maxdelta, __shfl_xor(maxdelta, sh));
+    }
+    if (lane == 0) {
+        if (band) {
+            atomicAdd(&R.ctr->rechecked, band);
+            atomicAdd(&R.ctr->rechecked_in, band_in);
         }
+        if (MODE == MODE_MEASURE) {
+            atomicMax(&R.ctr->max_err, (unsigned long long)__double_as_longlong(maxerr));
+            if (viol) atomicAdd(&R.ctr->violations, viol);
+        }
+        atomicMax(&R.ctr->max_delta, (unsigned long long)__double_as_longlong(maxdelta));
     }
 }
 
@@ -600,8 +621,10 @@ LpGrid lp_grid(const Grid &g) {
     G.d = g.d;
     G.dp = g.dp;
     G.nranges = g.nranges;
-    G.eps = g.eps;
     G.eps2 = g.eps2;
+    G.sc = lowp_scale(g);
+    G.eps_s = g.eps * G.sc;
+    G.eps2_s = g.eps2 * G.sc * G.sc;
     return G;
 }
 
@@ -621,15 +644,23 @@ void launch_lowp(const Grid &g, sj_path path, const LpOut &R, int nblocks, hipSt
 
 }  // namespace
 
-// Count: per-query counts into cnt_sorted; band counter in ro.band_dev;
-// largest band half-width in ro.aux_dev[0] (bits).
+double lowp_scale(const Grid &g) { return std::ldexp(1.0, -std::ilogb(g.eps)); }
+
+bool lowp_in_range(const Grid &g) {
+    if (!(g.eps >= 0x1p-500 && g.eps <= 0x1p500)) return false;
+    const double lim = std::ldexp(g.eps, 40);
+    for (int j = 0; j < g.d; ++j)
+        if (!(g.hi[j] - g.lo[j] <= lim)) return false;  // also false for an infinite extent
+    return true;
+}
+
+// Count: per-query counts into cnt_sorted; counters (band half-widths in
+// the tiles' scaled units) in ro.ctr, zeroed here.
 void lowp_count(Grid &g, sj_path path, int32_t *cnt_sorted, RefineOut &ro, hipStream_t s) {
-    fill_zero(ro.band_dev, sizeof(unsigned long long), s);
-    fill_zero(ro.aux_dev, 3 * sizeof(unsigned long long), s);
+    fill_zero(ro.ctr, sizeof(DevCounters), s);
     LpOut R{};
     R.cnt = cnt_sorted;
-    R.band = ro.band_dev;
-    R.meas = ro.aux_dev;
+    R.ctr = ro.ctr;
     R.block_lo = 0;
     ro.kt.start(ro.timed, s);
     launch_lowp<MODE_COUNT>(g, path, R, (int)g.nblocks, s);
@@ -646,10 +677,8 @@ void lowp_pairs(Grid &g, sj_path path, const ChunkPlan &p, int64_t qlo, int32_t 
     R.qhi = (int32_t)p.next;
     R.pairs = pairs;
     R.d2 = d2;
-    R.band = ro.band_dev;
-    R.meas = ro.aux_dev;
-    fill_zero(ro.band_dev, sizeof(unsigned long long), s);
-    fill_zero(ro.aux_dev, 3 * sizeof(unsigned long long), s);
+    R.ctr = ro.ctr;
+    fill_zero(ro.ctr, sizeof(DevCounters), s);
     R.block_lo = (int32_t)p.block_lo;
     ro.kt.start(ro.timed, s);
     launch_lowp<MODE_EMIT>(g, path, R, (int)(p.block_hi - p.block_lo), s);
@@ -657,23 +686,21 @@ void lowp_pairs(Grid &g, sj_path path, const ChunkPlan &p, int64_t qlo, int32_t 
 }
 
 void lowp_measure(Grid &g, sj_path path, double *max_err, double *max_band, int64_t *viol, hipStream_t s) {
-    unsigned long long *m = dev_alloc_n<unsigned long long>(4, s);
-    fill_zero(m, 4 * sizeof(unsigned long long), s);
+    DevCounters *ctr = dev_alloc_n<DevCounters>(1, s);
+    fill_zero(ctr, sizeof(DevCounters), s);
     LpOut R{};
-    R.band = m + 3;
-    R.meas = m;
+    R.ctr = ctr;
     R.block_lo = 0;
     launch_lowp<MODE_MEASURE>(g, path, R, (int)g.nblocks, s);
-    unsigned long long h[3] = {0, 0, 0};
-    SJ_HIP(hipMemcpyAsync(h, m, sizeof h, hipMemcpyDeviceToHost, s));
+    DevCounters h{};
+    SJ_HIP(hipMemcpyAsync(&h, ctr, sizeof h, hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
-    dev_free(m, s);
-    double e, b;
-    std::memcpy(&e, &h[0], sizeof e);
-    std::memcpy(&b, &h[2], sizeof b);
-    *max_err = e;
-    *max_band = b;
-    *viol = (int64_t)h[1];
+    dev_free(ctr, s);
+    const HostCounters hc = read_counters(h);
+    const double sc = lowp_scale(g);  // back to the data's units
+    *max_err = hc.max_err / (sc * sc);
+    *max_band = hc.max_delta / (sc * sc);
+    *viol = hc.violations;
 }
 
 }  // namespace sj

@@ -50,9 +50,7 @@ struct RefOut {
     int32_t qlo, qhi;             // emit: queries [qlo, qhi) write pairs
     int32_t *pairs;               // emit: rows (i, j), input indices
     double *d2;                   // emit: exact d2 per pair (nullable)
-    unsigned long long *band;     // band pairs re-evaluated
-    unsigned long long *meas;     // measure: [0] max err bits, [1] violations
-    unsigned long long *pruned;   // count: tiles dropped by the partial-distance bound (nullable)
+    DevCounters *ctr;             // rechecks, pruned tiles, measurements
     int32_t item_lo;              // first item of this launch
     unsigned long long *masks;    // count: per-tile in-masks to record (nullable)
 };
@@ -335,7 +333,8 @@ __device__ __forceinline__ void m64_measure(double4_t acc, const M64Tile<KS> &T,
 // are decided by the exact FP64 chain. `band` (wave-uniform) counts them.
 template <bool SLOT, int KS>
 __device__ __forceinline__ void m64_words(double4_t acc, const M64Tile<KS> &T, int g, int q0, const M64Thr &th,
-                                          const DevGrid &G, unsigned long long &band, unsigned long long w[4]) {
+                                          const DevGrid &G, unsigned long long &band, unsigned long long &band_in,
+                                          unsigned long long w[4]) {
     double lo[4], hi[4];
     if (SLOT) {
 #pragma unroll
@@ -376,8 +375,10 @@ __device__ __forceinline__ void m64_words(double4_t acc, const M64Tile<KS> &T, i
                 const int q = q0 + g + 4 * r;
                 ok = exact_d2(G.xs + (int64_t)q * G.dp, G.xs + (int64_t)T.c * G.dp, G.d) <= G.eps2;
             }
-            w[r] |= __ballot(ok);
+            const unsigned long long okm = __ballot(ok);
+            w[r] |= okm;
             band += (unsigned long long)__popcll(bm);
+            band_in += (unsigned long long)__popcll(okm);
         }
     }
 }
@@ -478,7 +479,7 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
     RowOut ro;
     if (MODE == MODE_EMIT) row_out_init(ro, emit_r, G, R, q0, g, j);
     int tot[4] = {0, 0, 0, 0};  // count: pairs of query g + 4r in this lane's column
-    unsigned long long band = 0, viol = 0;  // band: wave-uniform
+    unsigned long long band = 0, band_in = 0, viol = 0;  // band, band_in: wave-uniform
     double maxerr = 0.0;
 
     // count: the lane's nibbles of 16 consecutive tiles (one group) gather in
@@ -507,7 +508,7 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
             return;
         }
         unsigned long long w[4];
-        m64_words<SLOT, KS>(acc, T, g, q0, th, G, band, w);
+        m64_words<SLOT, KS>(acc, T, g, q0, th, G, band, band_in, w);
         if (MODE == MODE_EMIT) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) w[r] &= ebal[r];
@@ -635,8 +636,11 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
             v += __shfl_xor(v, 8);
             if (j == 0 && g + 4 * r < nq) R.cnt[q0 + g + 4 * r] = v;
         }
-        if (lane == 0 && band) atomicAdd(R.band, band);
-        if (lane == 0 && npruned && R.pruned) atomicAdd(R.pruned, npruned);
+        if (lane == 0 && npruned) atomicAdd(&R.ctr->pruned, npruned);
+    }
+    if (MODE != MODE_MEASURE && lane == 0 && band) {
+        atomicAdd(&R.ctr->rechecked, band);
+        atomicAdd(&R.ctr->rechecked_in, band_in);
     }
     if (MODE == MODE_MEASURE) {
         for (int sh = 32; sh > 0; sh >>= 1) {
@@ -644,8 +648,8 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
             maxerr = fmax(maxerr, __shfl_xor(maxerr, sh));
         }
         if (lane == 0) {
-            atomicMax(&R.meas[0], (unsigned long long)__double_as_longlong(maxerr));
-            if (viol) atomicAdd(&R.meas[1], viol);
+            atomicMax(&R.ctr->max_err, (unsigned long long)__double_as_longlong(maxerr));
+            if (viol) atomicAdd(&R.ctr->violations, viol);
         }
     }
 }
@@ -884,7 +888,7 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
             v += __shfl_xor(v, 8);
             if (j == 0 && g + 4 * r < nq) R.cnt[q0 + g + 4 * r] = v;
         }
-        if (lane == 0 && npruned && R.pruned) atomicAdd(R.pruned, npruned);
+        if (lane == 0 && npruned) atomicAdd(&R.ctr->pruned, npruned);
     }
 }
 
@@ -1118,7 +1122,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BProb *__restrict__ pr
                                                     const int64_t *__restrict__ item_base, int B,
                                                     const int32_t *__restrict__ queue, int total,
                                                     int *__restrict__ counter, int32_t *__restrict__ pairs,
-                                                    unsigned long long *__restrict__ band) {
+                                                    DevCounters *__restrict__ ctr) {
     __shared__ double vbuf[PATHV == SJ_FP64_VALU ? kWaves * 16 * kV64LdsD : 1];
     double *vq = PATHV == SJ_FP64_VALU ? vbuf + (threadIdx.x >> 6) * 16 * kV64LdsD : nullptr;
     __shared__ double cbuf[PATHV == SJ_FP64_VALU ? kWaves * 256 : 1];
@@ -1146,7 +1150,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BProb *__restrict__ pr
         R.qhi = (int32_t)P.G.n;
         R.pairs = pairs + 2 * P.pout;
         R.d2 = nullptr;
-        R.band = band;
+        R.ctr = ctr;
         R.item_lo = 0;
         const int it = uniform_i32(gi - (int)item_base[p]);
         if (PATHV == SJ_FP64_MFMA) {
@@ -1208,9 +1212,9 @@ __global__ __launch_bounds__(kThreads) void k_seg_scan(const BProb *__restrict__
     if (tid == 0) totals[blockIdx.x] = carry;
 }
 
-__global__ void k_batch_reset(int *counter, unsigned long long *band) {
+__global__ void k_batch_reset(int *counter, DevCounters *ctr) {
     *counter = 0;
-    *band = 0;
+    *ctr = DevCounters{};
 }
 
 DevGrid dev_grid(const Grid &g) {
@@ -1254,6 +1258,20 @@ double m64_delta(const Grid &g) {
     const double tiny = (d + 2) * 0x1p-1021;  // products flushed below the normal range
     return 2.0 * (E1 + 2.0 * tau * e + e * e + gam(d + 2, u) * tau * tau + tiny);
 }
+
+}  // namespace
+
+bool m64_in_range(const Grid &g) { return g.nmax >= 0.0 && g.nmax <= 0x1p1000; }
+
+sj_path effective_path(const Grid &g, sj_path requested) {
+    sj_path p = requested;
+    if ((p == SJ_FP32_MFMA || p == SJ_BF16_MFMA || p == SJ_BF16X3_MFMA) && g.d <= kLpMaxD && !lowp_in_range(g))
+        p = SJ_FP64_MFMA;
+    if (p == SJ_FP64_MFMA && !m64_in_range(g)) p = SJ_FP64_VALU;
+    return p;
+}
+
+namespace {
 
 template <int MODE>
 void launch_v64(const Grid &g, const RefOut &R, int nitems, hipStream_t s) {
@@ -1312,9 +1330,9 @@ void launch_m64(const Grid &g, const RefOut &R, int nitems, double delta, hipStr
 }  // namespace
 
 void launch_batch(bool emit, sj_path path, const BProb *probs, const int64_t *item_base, int B,
-                  const int32_t *queue, int total, int *counter, int32_t *pairs, unsigned long long *band,
+                  const int32_t *queue, int total, int *counter, int32_t *pairs, DevCounters *ctr,
                   hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, counter, band);
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, counter, ctr);
     SJ_HIP(hipGetLastError());
     if (total <= 0) return;
     int dev = 0, ncu = 256;
@@ -1322,7 +1340,7 @@ void launch_batch(bool emit, sj_path path, const BProb *probs, const int64_t *it
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     const unsigned blocks = (unsigned)std::min<int64_t>((total + kWaves - 1) / kWaves, (int64_t)ncu * 8);
 #define SJ_B(M, P) hipLaunchKernelGGL((k_batch<M, P>), dim3(blocks), dim3(kThreads), 0, s, probs, item_base, B, queue, \
-                                      total, counter, pairs, band)
+                                      total, counter, pairs, ctr)
     if (path == SJ_FP64_MFMA) {
         if (emit) SJ_B(MODE_EMIT, SJ_FP64_MFMA);
         else SJ_B(MODE_COUNT, SJ_FP64_MFMA);
@@ -1343,27 +1361,35 @@ void launch_seg_scan(const BProb *probs, int B, int64_t *totals, hipStream_t s) 
     SJ_HIP(hipGetLastError());
 }
 
-// Enqueues the count kernel; the band counter lands in ro.band_dev (device,
-// zeroed here) and is read by the caller together with the total; the FP64
-// paths count their pruned tiles in ro.aux_dev[0] (= band_dev + 1, zeroed
-// here too).
+HostCounters read_counters(const DevCounters &c) {
+    HostCounters h;
+    h.rechecked = (int64_t)c.rechecked;
+    h.rechecked_in = (int64_t)c.rechecked_in;
+    h.pruned = (int64_t)c.pruned;
+    h.violations = (int64_t)c.violations;
+    std::memcpy(&h.max_delta, &c.max_delta, sizeof(double));
+    std::memcpy(&h.max_err, &c.max_err, sizeof(double));
+    return h;
+}
+
+// Enqueues the count kernel of `path` (already range-checked); its counters
+// land in ro.ctr (device, zeroed here), read back by the caller with the
+// total.
 void refine_count(Grid &g, sj_path path, int32_t *cnt_sorted, RefineOut &ro, hipStream_t s) {
-    fill_zero(ro.band_dev, 2 * sizeof(unsigned long long), s);  // band counter and ro.aux_dev[0] behind it
+    fill_zero(ro.ctr, sizeof(DevCounters), s);
     RefOut R{};
     R.cnt = cnt_sorted;
-    R.band = ro.band_dev;
+    R.ctr = ro.ctr;
     R.item_lo = 0;
     R.masks = ro.masks;
     ro.cand_eval = g.cand_items;
     if (path == SJ_FP64_VALU) {
-        R.pruned = ro.aux_dev;  // zeroed above with the band counter
         ro.kt.start(ro.timed, s);
         launch_v64<MODE_COUNT>(g, R, (int)g.items, s);
         ro.kt.stop(s);
         ro.band_rel = 0.0;
     } else if (path == SJ_FP64_MFMA) {
         const double delta = m64_delta(g);
-        R.pruned = ro.aux_dev;  // zeroed above with the band counter
         ro.kt.start(ro.timed, s);
         launch_m64<MODE_COUNT>(g, R, (int)g.items, delta, s);
         ro.kt.stop(s);
@@ -1467,8 +1493,8 @@ void refine_pairs(Grid &g, sj_path path, const ChunkPlan &p, int64_t qlo, int32_
     R.pairs = pairs;
     R.d2 = d2;
     R.item_lo = (int32_t)p.item_lo;
-    fill_zero(ro.band_dev, sizeof(unsigned long long), s);
-    R.band = ro.band_dev;
+    fill_zero(ro.ctr, sizeof(DevCounters), s);
+    R.ctr = ro.ctr;
     const int nitems = (int)(p.item_hi - p.item_lo);
     if ((path == SJ_FP64_VALU || path == SJ_FP64_MFMA) && g.masks_valid && g.masks) {
         ro.kt.start(ro.timed, s);
@@ -1499,37 +1525,32 @@ void refine_pairs(Grid &g, sj_path path, const ChunkPlan &p, int64_t qlo, int32_
 }
 
 void refine_measure(Grid &g, sj_path path, double *max_err, double *max_band, int64_t *viol, hipStream_t s) {
-    unsigned long long *meas = dev_alloc_n<unsigned long long>(3, s);
-    fill_zero(meas, 3 * sizeof(unsigned long long), s);
-    RefOut R{};
-    R.meas = meas;
-    R.band = meas + 2;
-    R.item_lo = 0;
-    double delta = 0.0;
     if (path == SJ_FP64_VALU) {
         // the direct form is the exact chain: no band, no error
         *max_err = 0.0;
         *max_band = 0.0;
         *viol = 0;
-        dev_free(meas, s);
         return;
-    } else if (path == SJ_FP64_MFMA) {
-        delta = m64_delta(g);
-        launch_m64<MODE_MEASURE>(g, R, (int)g.items, delta, s);
-    } else {
-        dev_free(meas, s);
+    }
+    if (path != SJ_FP64_MFMA) {
         lowp_measure(g, path, max_err, max_band, viol, s);
         return;
     }
-    unsigned long long h[2] = {0, 0};
-    SJ_HIP(hipMemcpyAsync(h, meas, sizeof h, hipMemcpyDeviceToHost, s));
+    DevCounters *ctr = dev_alloc_n<DevCounters>(1, s);
+    fill_zero(ctr, sizeof(DevCounters), s);
+    RefOut R{};
+    R.ctr = ctr;
+    R.item_lo = 0;
+    const double delta = m64_delta(g);
+    launch_m64<MODE_MEASURE>(g, R, (int)g.items, delta, s);
+    DevCounters h{};
+    SJ_HIP(hipMemcpyAsync(&h, ctr, sizeof h, hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
-    double e;
-    std::memcpy(&e, &h[0], sizeof e);
-    *max_err = e;
+    dev_free(ctr, s);
+    const HostCounters hc = read_counters(h);
+    *max_err = hc.max_err;
     *max_band = delta;
-    *viol = (int64_t)h[1];
-    dev_free(meas, s);
+    *viol = hc.violations;
 }
 
 }  // namespace sj

@@ -48,6 +48,7 @@ class GridHandle:
         self.d = d
         self.eps = eps
         self.device = device
+        self.hook = None  # allocator hook of the handle (must outlive it)
 
     def close(self, stream=None):
         if self.ptr:
@@ -64,8 +65,33 @@ class GridHandle:
             pass
 
 
-def selfjoin_build_grid(points, eps: float, index_dims: int = 0, stream=None) -> GridHandle:
-    """points: CUDA float64 tensor (n, d), C-contiguous."""
+class TorchAllocHook:
+    """sj_opts.alloc / free served by torch's caching allocator on one device
+    (the library then allocates nothing itself for the handle). Keep the
+    object alive as long as the handle: GridHandle holds it."""
+
+    def __init__(self, device):
+        torch = _torch()
+        self.device = torch.device(device).index or 0
+
+        def _alloc(nbytes, stream, ctx):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), self.device, int(stream or 0))
+            except Exception:
+                return None
+
+        def _free(ptr, stream, ctx):
+            if ptr:
+                torch.cuda.caching_allocator_delete(int(ptr))
+
+        self.alloc = _lib.ALLOC_FN(_alloc)
+        self.free = _lib.FREE_FN(_free)
+
+
+def selfjoin_build_grid(points, eps: float, index_dims: int = 0, stream=None, torch_alloc: bool = False) -> GridHandle:
+    """points: CUDA float64 tensor (n, d), C-contiguous. torch_alloc: every
+    device buffer of the handle comes from torch's caching allocator through
+    the sj_opts allocator hook."""
     torch = _torch()
     if not isinstance(points, torch.Tensor) or not points.is_cuda:
         raise ValueError("points must be a CUDA tensor")
@@ -75,13 +101,19 @@ def selfjoin_build_grid(points, eps: float, index_dims: int = 0, stream=None) ->
     lib = _lib.load()
     opts = _lib.sj_opts()
     opts.index_dims = index_dims
+    hook = TorchAllocHook(points.device) if torch_alloc else None
+    if hook is not None:
+        opts.alloc = hook.alloc
+        opts.free = hook.free
     out = ctypes.c_void_p()
     n, d = points.shape
     with torch.cuda.device(points.device):
         st = lib.selfjoin_build_grid(ctypes.c_void_p(points.data_ptr()), n, d, float(eps),
                                      ctypes.byref(opts), _stream_ptr(stream), ctypes.byref(out))
     check(st, "selfjoin_build_grid")
-    return GridHandle(out, n, d, float(eps), points.device)
+    h = GridHandle(out, n, d, float(eps), points.device)
+    h.hook = hook
+    return h
 
 
 def selfjoin_count(g: GridHandle, path="fp64_mfma", per_point: bool = False, stream=None):
@@ -193,8 +225,8 @@ def selfjoin_free_grid(g: GridHandle, stream=None):
 class SelfJoin:
     """Convenience wrapper: grid + count + all pairs."""
 
-    def __init__(self, points, eps, index_dims=0, stream=None):
-        self.grid = selfjoin_build_grid(points, eps, index_dims, stream)
+    def __init__(self, points, eps, index_dims=0, stream=None, torch_alloc=False):
+        self.grid = selfjoin_build_grid(points, eps, index_dims, stream, torch_alloc=torch_alloc)
         self.stream = stream
 
     def count(self, path="fp64_mfma", per_point=False):
