@@ -76,3 +76,22 @@ def brute_workloads():
 CFG2 = [f"{dist}_d{d}_n2M" for dist in ("uniform", "expo") for d in (2, 3, 4)]
 PREC = [f"gmm_d{d}_n1M" for d in (16, 32, 64)]
 SKEWED = ["expo_d3_n10M"]
+
+
+def batch_eps(n: int, d: int, s: float) -> float:
+    """Search distance for about `s` mean neighbours among n uniform points in
+    [0,1]^d, from the volume of the d-ball (boundary losses ignored)."""
+    import math
+    vol = math.pi ** (d / 2) / math.gamma(d / 2 + 1)
+    return float((s / max(n - 1, 1) / vol) ** (1.0 / d))
+
+
+def batched_workload(count: int = 256, seed: int = 0, s: float = 32.0):
+    """The batched workload: `count` independent problems, n log-uniform in
+    [1e3, 2e5], d from {2, 3, 4, 8, 16}, uniform points (problem b drawn with
+    seed [seed, b]), eps for ~s mean neighbours each. Returns a list of dicts
+    with n, d, seed, eps."""
+    from workloads import generators as gen
+    return [{"name": f"batch{b}", "dist": "uniform", "n": n, "d": d, "seed": [seed, b],
+             "eps": batch_eps(n, d, s)}
+            for b, (n, d) in enumerate(gen.batch_problems(count, seed=seed))]
