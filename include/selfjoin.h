@@ -258,6 +258,31 @@ sj_status selfjoin_grid_info(sj_grid *g, sj_grid_info *info, void *stream);
  * `stream`. NULL is accepted. */
 void selfjoin_free_grid(sj_grid *g, void *stream);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): build + count in one call, with every
+ * temporary taken from a static device scratch array of 256 MiB that the
+ * library holds on each GPU it runs on until the process ends. Nothing is
+ * allocated (no hipMalloc / hipFree, no allocator hook, no events).
+ *  points, n, d, eps : as selfjoin_build_grid (device, n x d row-major FP64).
+ *  path      : as selfjoin_count; the same exact set and counts.
+ *  per_point : device int32[n] in the input order, or NULL (as
+ *              selfjoin_count).
+ *  total     : host, receives |R|.
+ * The call returns after its stream work has finished, so the scratch is
+ * free again on return. Calls on one GPU share its array: the library runs
+ * them one at a time (a per-device lock), and work that overlaps with a call
+ * on the same GPU from outside the library must not touch that array (it
+ * cannot: its address is private to the library).
+ * Limit: inputs whose worst-case need exceeds the array return
+ * SJ_ERR_CAPACITY before any device work (about n <= 1.26M at d = 2, 640k
+ * at d = 4, 190k at d = 64, 57k at d = 256; selfjoin_last_error states the
+ * need).
+ * Errors: SJ_ERR_INVALID (bad argument or non-finite coordinate),
+ * SJ_ERR_UNSUPPORTED (low-precision path with d > 64), SJ_ERR_CAPACITY,
+ * SJ_ERR_HIP. No pair list: use the handle-based calls for pairs. */
+sj_status selfjoin_count_noalloc(const double *points, int64_t n, int32_t d, double eps, sj_path path,
+                                 int32_t *per_point, int64_t *total, void *stream);
+
 /* ---- Batched form: B independent self-joins of uneven n and d ----------
  * All problems' work items are refined by one persistent work-queue kernel
  * that takes the costliest items first; the count pipeline (queue reset,

@@ -36,6 +36,7 @@ EXPORTS = [
     "selfjoin_batch_pairs",
     "selfjoin_batch_info",
     "selfjoin_batch_free",
+    "selfjoin_count_noalloc",
 ]
 
 
@@ -148,6 +149,9 @@ def load():
     lib.selfjoin_batch_info.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _i64p]
     lib.selfjoin_batch_free.restype = None
     lib.selfjoin_batch_free.argtypes = [_vp, _vp]
+    lib.selfjoin_count_noalloc.restype = ctypes.c_int
+    lib.selfjoin_count_noalloc.argtypes = [_vp, _i64, ctypes.c_int32, ctypes.c_double, ctypes.c_int, _vp, _i64p,
+                                           _vp]
     _lib = lib
     return lib
 

@@ -289,7 +289,7 @@ static void compute_counts(Grid &g, sj_path path, bool timed, CountRun &cr, hipS
     // FP64 count passes record per-tile in-masks; emission then reuses them
     const bool fp64 = path == SJ_FP64_VALU || path == SJ_FP64_MFMA;
     g.masks_valid = false;
-    if (fp64 && !g.masks && g.tiles > 0 && g.tiles * 32 <= kMaskBudget)
+    if (fp64 && !g.lean && !g.masks && g.tiles > 0 && g.tiles * 32 <= kMaskBudget)
         g.masks = dev_alloc_n<unsigned long long>((size_t)g.tiles * 4, s);
     ro.masks = fp64 ? g.masks : nullptr;
     hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, g.cnt + g.n, 0);
@@ -354,6 +354,77 @@ static ChunkPlan whole_plan(const Grid &g) {
     p.base = 0;
     return p;
 }
+
+// ------------------------------------------------------------------------
+// Static scratch for selfjoin_count_noalloc: every temporary of a lean build
+// and count is bump-allocated from one file-scope device array (each GPU the
+// library runs on holds its own copy until the process ends). Host code never
+// passes the array's name to a kernel: its device address, taken per device
+// with hipGetSymbolAddress on the first call there, is the arena's base.
+// ------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(256) << 20;
+
+}  // namespace sj
+
+static __device__ __align__(256) unsigned char scratch[sj::kScratchBytes];
+
+namespace sj {
+namespace {
+
+struct ScratchDev {
+    void *ptr = nullptr;
+    std::mutex mu;  // one call at a time per device (the array is shared)
+};
+std::mutex g_scratch_mu;
+std::unordered_map<int, ScratchDev> g_scratch;
+
+// The current device's scratch entry, its address looked up once.
+ScratchDev &scratch_for_current_device() {
+    int dev = 0;
+    SJ_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    ScratchDev &e = g_scratch[dev];
+    if (!e.ptr) {
+        void *p = nullptr;
+        SJ_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw HipError{hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)"};
+        e.ptr = p;
+    }
+    return e;
+}
+
+// Upper bound of the scratch bytes a lean build + count of n points in d
+// dimensions takes: the sum of every allocation the two make (the arena
+// releases nothing), each with its 16-byte tail and 256-byte alignment.
+// Table sizes use the build's own upper bounds (items <= n + n/16 + 1,
+// 3^(k-1) ranges per item with k <= min(d, 4)); each exclusive scan of L
+// entries is charged L/256 + 4096 bytes of tile sums.
+size_t lean_need(int64_t n, int32_t d) {
+    const size_t N = (size_t)n;
+    const size_t dp = (size_t)((d + 3) & ~3);
+    const size_t da = (d & 3) ? (size_t)((d + 1 + 3) & ~3) : (size_t)d;
+    const size_t rows = N + kRowPad;
+    const size_t items_ub = N + N / kTileQ + 1;
+    size_t nr = 1;
+    for (int j = 0; j < std::min(d, kMaxIndexDims) - 1; ++j) nr *= 3;
+    auto A = [](size_t b) { return (b + 16 + 255) & ~size_t(255); };
+    auto scan = [](size_t L) { return L / 256 + 4096; };
+    const size_t nb_rs = (N + 4095) / 4096 + 1;
+    size_t need = 0;
+    need += 2 * A(2048 * (size_t)d * 8) + A((2 * (size_t)d + 1) * 8);              // bounding box
+    need += 2 * A(8 * N) + 2 * A(4 * N);                                             // keys, indices
+    need += 2 * A(nb_rs * 256 * 4) + 8 * scan(nb_rs * 256);                         // radix sort
+    need += A(rows * dp * 8) + A(rows * da * 8) + 2 * A(rows * 8) + 3 * A(16);      // rows, norms
+    need += A(std::max<size_t>(4096, N / 256 + 1) * 8);                              // norm maxima
+    need += 2 * A((N + N / kTileQ + 2) * 4);                                         // flags, ids
+    need += A(8 * (N + 1)) + 4 * A(4 * (N + 2)) + 3 * scan(N + 1);                   // cells, lines
+    need += A(8 * (items_ub + 1)) + 2 * A(4 * (items_ub + 1)) + A(16 * items_ub);    // items
+    need += A(8 * items_ub * nr) + A(4 * (size_t)kLeanLineTable) + 2 * scan(items_ub + 1);
+    need += A(4 * (N + 1)) + A(8 * (N + 1)) + A(sizeof(DevCounters)) + scan(N + 1);  // counts
+    return need;
+}
+
+}  // namespace
 
 }  // namespace sj
 
@@ -626,6 +697,52 @@ void selfjoin_free_grid(sj_grid *gh, void *stream) {
     } catch (...) {
     }
     delete gh;
+}
+
+sj_status selfjoin_count_noalloc(const double *points, int64_t n, int32_t d, double eps, sj_path path,
+                                 int32_t *per_point, int64_t *total, void *stream) {
+    set_error("");
+    if (n < 0 || n >= (int64_t(1) << 31)) return invalid("n must be in [0, 2^31)");
+    if (d < 1 || d > kMaxDims) return invalid("d must be in [1, 256]");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return invalid("eps must be finite and > 0");
+    if (n > 0 && !points) return invalid("points is NULL");
+    if (!valid_path(path)) return invalid("unknown path");
+    if (!total) return invalid("total is NULL");
+    if ((path == SJ_FP32_MFMA || path == SJ_BF16_MFMA || path == SJ_BF16X3_MFMA) && d > kLpMaxD) {
+        set_error("FP32/BF16 MFMA paths support d <= 64");
+        return SJ_ERR_UNSUPPORTED;
+    }
+    const size_t need = lean_need(n, d);
+    if (need > kScratchBytes) {
+        set_error("n = " + std::to_string(n) + ", d = " + std::to_string(d) + " needs up to " +
+                  std::to_string(need) + " bytes of scratch; the static scratch holds " +
+                  std::to_string(kScratchBytes));
+        return SJ_ERR_CAPACITY;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SJ_API_BEGIN
+    ScratchDev &sd = scratch_for_current_device();
+    std::lock_guard<std::mutex> lk(sd.mu);
+    Arena arena;
+    arena.base = static_cast<char *>(sd.ptr);
+    arena.size = kScratchBytes;
+    AllocScope scope(&arena);
+    Grid g;
+    g.lean = true;
+    build_grid(g, points, n, d, eps, 0, s);
+    const sj_path run = path_for(g, path);
+    CountRun cr;
+    compute_counts(g, run, false, cr, s);
+    if (per_point && g.n > 0) {
+        hipLaunchKernelGGL(k_scatter_counts, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s, g.cnt, g.perm,
+                           g.n, per_point);
+        SJ_HIP(hipGetLastError());
+    }
+    // the next call may reuse the scratch as soon as this one returns
+    SJ_HIP(hipStreamSynchronize(s));
+    *total = g.total;
+    return SJ_OK;
+    SJ_API_END
 }
 
 const char *selfjoin_status_string(sj_status s) {

@@ -985,9 +985,11 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     g.da = (d & 3) ? ((d + 1 + 3) & ~3) : d;
     g.build_stream = s;
     const size_t rows = (size_t)n + kRowPad;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // device time of the build
-    SJ_HIP(hipEventCreate(&ev0));
-    SJ_HIP(hipEventCreate(&ev1));
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // device time of the build (not in a lean build)
+    if (!g.lean) {
+        SJ_HIP(hipEventCreate(&ev0));
+        SJ_HIP(hipEventCreate(&ev1));
+    }
     struct EvGuard {
         hipEvent_t &a, &b;
         ~EvGuard() {
@@ -995,7 +997,7 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
             if (b) (void)hipEventDestroy(b);
         }
     } evg{ev0, ev1};
-    SJ_HIP(hipEventRecord(ev0, s));
+    if (ev0) SJ_HIP(hipEventRecord(ev0, s));
 
     // ---- G1: bounding box and finiteness (one host sync) ----
     if (n == 0) {
@@ -1156,7 +1158,7 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
         // dense line table when the leading indexed dimensions span few lines
         int64_t nline_keys = 1;
         for (int j = 0; j < g.k - 1; ++j) nline_keys *= g.m[j];
-        if (nline_keys <= (int64_t(1) << 24)) {
+        if (nline_keys <= (g.lean ? kLeanLineTable : (int64_t(1) << 24))) {
             g.line_table = dev_alloc_n<int32_t>((size_t)nline_keys, s);
             fill_ones(g.line_table, (size_t)nline_keys * sizeof(int32_t), s);
             hipLaunchKernelGGL(k_line_table, dim3(blocks_for(n)), dim3(kThreads), 0, s, g.cell_key, g.line_first,
@@ -1192,12 +1194,14 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
         SJ_HIP(hipMemcpyAsync(&hn, g.dev_nmax, sizeof(double), hipMemcpyDeviceToHost, s));
         SJ_HIP(hipMemcpyAsync(hacc, acc, sizeof hacc, hipMemcpyDeviceToHost, s));
     }
-    SJ_HIP(hipEventRecord(ev1, s));
-    SJ_HIP(hipEventSynchronize(ev1));
-    {
+    if (ev1) {
+        SJ_HIP(hipEventRecord(ev1, s));
+        SJ_HIP(hipEventSynchronize(ev1));
         float ms = 0.f;
         SJ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
         g.ms_build = ms;
+    } else {
+        SJ_HIP(hipStreamSynchronize(s));
     }
     g.cells = hc[0];
     g.items = hc[2];

@@ -18,6 +18,7 @@ constexpr int kRowPad = 64;        // extra zeroed rows after every point array
 constexpr int kBlockItems = 4;     // work items per block item (low-precision paths)
 constexpr int kLpMaxD = 64;        // largest d of the low-precision paths
 constexpr int64_t kMaskBudget = int64_t(16) << 30;  // largest in-mask buffer (bytes)
+constexpr int64_t kLeanLineTable = int64_t(1) << 20;  // largest dense line table of a lean build
 
 // Thread-local error text.
 void set_error(const std::string &msg);
@@ -191,7 +192,9 @@ struct Grid {
     sj_path count_path = SJ_FP64_VALU;  // the path whose kernels made the cached counts
 
     AllocHook hook;              // the handle's device allocator (alloc null: the caching allocator)
-    double ms_build = 0;         // device time of the build
+    bool lean = false;           // build and count without events or in-masks, dense line table
+                                 // only up to kLeanLineTable entries (static-scratch calls)
+    double ms_build = 0;         // device time of the build (0 when lean)
     hipStream_t build_stream = nullptr;
 };
 

@@ -131,6 +131,29 @@ def selfjoin_count(g: GridHandle, path="fp64_mfma", per_point: bool = False, str
     return total.value, pp, stats.as_dict()
 
 
+def selfjoin_count_noalloc(points, eps: float, path="fp64_mfma", per_point: bool = False, stream=None):
+    """Build + count in one call with every temporary in the library's static
+    device scratch (nothing allocated by the library; `per_point`, if asked,
+    is allocated here by torch). Returns (total, per_point int32 tensor or
+    None)."""
+    torch = _torch()
+    if not isinstance(points, torch.Tensor) or not points.is_cuda:
+        raise ValueError("points must be a CUDA tensor")
+    if points.dtype != torch.float64 or points.dim() != 2:
+        raise ValueError("points must be float64 of shape (n, d)")
+    points = points.contiguous()
+    lib = _lib.load()
+    n, d = points.shape
+    pp = torch.empty(n, dtype=torch.int32, device=points.device) if per_point else None
+    total = ctypes.c_int64(0)
+    with torch.cuda.device(points.device):
+        st = lib.selfjoin_count_noalloc(ctypes.c_void_p(points.data_ptr()), n, d, float(eps), _path_id(path),
+                                        ctypes.c_void_p(pp.data_ptr()) if pp is not None and n else None,
+                                        ctypes.byref(total), _stream_ptr(stream))
+    check(st, "selfjoin_count_noalloc")
+    return total.value, pp
+
+
 def selfjoin_core_points(g: GridHandle, min_pts: int, path="fp64_mfma", stream=None):
     """DBSCAN core points: returns (uint8 CUDA tensor, 1 = core, input order;
     number of core points). Reuses the handle's counts or counts with `path`."""
