@@ -62,6 +62,7 @@ def parse():
     ap.add_argument("--workload", default="cfg2", choices=["cfg2", "small", "prec", "skewed", "batched", "brute"])
     ap.add_argument("--chunk", type=int, default=0, help="pairs per output chunk (0 = one chunk)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-set", action="store_true", help="skip the per-set single-stream path comparison")
     ap.add_argument("--streams", type=int, default=3,
                     help="data sets run concurrently, one host thread and HIP stream each")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -253,25 +254,64 @@ def roofline(recs, path="fp64_mfma", which=None, workload="cfg2"):
             "algorithmic_flops_per_launch": round(flops / launches)}
 
 
-def cpu_baseline(inputs):
-    """The oracle (count mode, all host threads) on a bounded sample of the
-    same workload: the first data sets until ~15 s of CPU time."""
+def isolated(inputs, path, bufs, cref_map, chunk=0):
+    """One pass over every data set on a single stream with nothing else on
+    the GPU: per-set kernel times of `path` (HIP events around each launch)."""
+    iso = []
+    one_pass(inputs, path, bufs, iso, chunk=chunk)
+    for r in iso:
+        r["cand_ref"] = cref_map[r["name"]]
+    return iso
+
+
+def cpu_baseline(inputs, budget_s=10.0):
+    """The oracle, as it stands, on a bounded sample of the same workload:
+    per data set (in order, until `budget_s` of CPU time), its self-join --
+    build + count with all host threads of the box's share, then build +
+    pair list into a preallocated host buffer (the oracle writes pairs on
+    one thread) -- and the same count on one thread. Also the small parity
+    workload (n = 20,000, d = 2) on one thread and on all."""
+    import numpy as np
+
     import oracle
+    from workloads import configs
+    from workloads import generators as gen
     # the box's CPU share: OMP_NUM_THREADS (16 per GPU), not os.cpu_count()
     nthreads = max(1, min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16"))))
-    done, cref, secs = [], 0, 0.0
+    done, cref, secs, spent, one = [], 0, 0.0, 0.0, []
     for w, X, _ in inputs:
         t0 = time.perf_counter()
-        _, _, c, _ = oracle.grid_count(X, w["eps"], nthreads=nthreads)
-        dt = time.perf_counter() - t0
+        total, _, c, _ = oracle.grid_count(X, w["eps"], nthreads=nthreads)
+        t1 = time.perf_counter()
+        buf = np.empty((max(total, 1), 2), dtype=np.int32)
+        t2 = time.perf_counter()
+        if oracle.grid_pairs_into(X, w["eps"], buf) != total:
+            raise RuntimeError("oracle pairs disagree with its count")
+        t3 = time.perf_counter()
+        oracle.grid_count(X, w["eps"], nthreads=1)
+        t4 = time.perf_counter()
+        del buf
         cref += c
-        secs += dt
+        secs += (t1 - t0) + (t3 - t2)
+        spent += t4 - t0
         done.append(w["name"])
-        if secs > 15.0:
+        one.append({"name": w["name"], "count_s": round(t1 - t0, 3), "pairs_1thread_s": round(t3 - t2, 3),
+                    "count_1thread_s": round(t4 - t3, 3), "cand_ref": c,
+                    "count_evals_per_s": round(c / (t1 - t0)), "count_1thread_evals_per_s": round(c / (t4 - t3))})
+        if spent > budget_s:
             break
+    sw = configs.workload("small")
+    Xs = gen.make(sw["dist"], sw["n"], sw["d"], seed=sw["seed"])
+    small = {}
+    for th in (1, nthreads):
+        t0 = time.perf_counter()
+        _, _, cs, _ = oracle.grid_count(Xs, sw["eps"], nthreads=th)
+        small[f"count_{th}thread_s"] = round(time.perf_counter() - t0, 4)
+    small["cand_ref"] = cs
     return {"value": cref / secs, "unit": "distance evals/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"oracle grid count (no pair list), {nthreads} threads, data sets: {', '.join(done)}",
-            "seconds": round(secs, 2)}
+            "sample": f"oracle self-join = build + count ({nthreads} threads) + build + pair list into a "
+                      f"preallocated host buffer (1 thread), data sets: {', '.join(done)}",
+            "seconds": round(secs, 2), "per_set": one, "small_n20000_d2": small}
 
 
 def brute_compare(inputs, path, bufs, reps=3):
@@ -424,24 +464,48 @@ def main():
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "path": args.path, "cand_ref_per_step": cref, "pairs_per_step": pairs,
                    "chunk": args.chunk, "streams": max(1, args.streams)},
-        "per_dataset": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+        "per_dataset": [{k: (round(v, 4) if isinstance(v, float) and k != "eps" else v) for k, v in r.items()}
                         for r in recs[-1]],
-        "roofline": dict(roofline(recs, args.path, workload=args.workload),
-                         note="launch times measured on the caller's stream in the timed steps; with "
-                              "several streams they include sharing the GPU with the other stream's kernels"),
     }
+    # roofline of the dominant tile kernel from single-stream launches (nothing
+    # else on the GPU: the duration rocprofv3 reports for the same launches);
+    # with several streams the timed steps' launch times include sharing the
+    # GPU with the other streams' kernels, kept under "shared"
+    iso = isolated(inputs, args.path, bufs, cref_map, args.chunk) if streams else recs[-1]
+    cnt_iso = sum(r["count_kernel_ms"] for r in iso)
+    emit_iso = sum(r["emit_kernel_ms"] for r in iso)
+    kind = "emit" if emit_iso >= cnt_iso else "count"
+    roof = roofline([iso], args.path, which=kind, workload=args.workload)
+    roof["note"] = ("launch times from HIP events on the launching stream, one pass over the data sets on a "
+                    "single stream" + (" after the timed steps" if streams else " (the last timed step)"))
     if streams:
-        # the same kernel's launches with nothing else on the GPU: one more
-        # pass on a single stream after the timed steps
-        iso = []
-        one_pass(inputs, args.path, bufs, iso, chunk=args.chunk)
-        for r in iso:
-            r["cand_ref"] = cref_map[r["name"]]
-        kind = "emit" if out["roofline"]["kernel"].endswith("(pairs)") else "count"
-        ri = roofline([iso], args.path, which=kind, workload=args.workload)
-        out["roofline"]["isolated"] = {"avg_launch_ms": ri["avg_launch_ms"], "achieved": ri["achieved"],
-                                       "frac": ri["frac"],
-                                       "note": "one pass on a single stream after the timed steps"}
+        rs = roofline(recs, args.path, which=kind, workload=args.workload)
+        roof["shared"] = {"avg_launch_ms": rs["avg_launch_ms"], "achieved": rs["achieved"], "frac": rs["frac"],
+                          "note": f"the timed steps' launches, {len(streams)} streams sharing the GPU"}
+    other = "count" if kind == "emit" else "emit"
+    ro = roofline([iso], args.path, which=other, workload=args.workload)
+    roof["other_kernel"] = {k: ro[k] for k in ("kernel", "bound", "achieved", "peak", "unit", "frac",
+                                                  "avg_launch_ms")}
+    out["roofline"] = roof
+    # per-set single-stream kernel times of the FP64 MFMA, FP64 vector-ALU and
+    # FP32 MFMA paths on the same data (the MFMA-vs-vector comparison per set)
+    if args.workload in ("cfg2", "skewed", "prec") and not args.no_per_set:
+        per = {}
+        for pth in dict.fromkeys([args.path, "fp64_mfma", "fp64_valu", "fp32_mfma", "bf16x3_mfma"]):
+            if pth == args.path and iso is not recs[-1]:
+                rr = iso
+            else:
+                b2 = [None] * len(inputs)
+                one_pass(inputs, pth, b2, None, chunk=args.chunk)  # warm
+                rr = isolated(inputs, pth, b2, cref_map, args.chunk)
+                del b2
+            per[pth] = {r["name"]: {"build_ms": round(r["build_ms"], 4), "count_kernel_ms": round(r["count_kernel_ms"], 4),
+                                    "emit_kernel_ms": round(r["emit_kernel_ms"], 4),
+                                    "rechecked": r["rechecked"], "band_rel": r["band_rel"]} for r in rr}
+        names = [r["name"] for r in iso]
+        out["per_set_isolated"] = per
+        out["mfma_vs_valu_count"] = {nm: round(per["fp64_valu"][nm]["count_kernel_ms"] /
+                                               max(per["fp64_mfma"][nm]["count_kernel_ms"], 1e-9), 3) for nm in names}
     if args.workload == "brute":
         log("[bench] per-size times and the dense GEMM reference")
         per = brute_compare(inputs, args.path, bufs)

@@ -169,6 +169,20 @@ def grid_pairs(X, eps, want_d2=False):
     return total, pp, pairs[:total]
 
 
+def grid_pairs_into(X, eps, pairs):
+    """Grid self-join pair list written into a preallocated (cap, 2) int32
+    C-contiguous array (rows beyond cap are counted, not written). Returns
+    |R|."""
+    X = _pts(X)
+    n, d = X.shape
+    if pairs.dtype != np.int32 or pairs.ndim != 2 or pairs.shape[1] != 2 or not pairs.flags.c_contiguous:
+        raise ValueError("pairs must be a C-contiguous (cap, 2) int32 array")
+    t = _load().oracle_grid_pairs(_ptr(X, _f64p), n, d, eps, None, _ptr(pairs, _i32p), None, pairs.shape[0])
+    if t < 0:
+        raise ValueError("invalid input")
+    return t
+
+
 def grid_digest(X, eps, nthreads=None):
     """Grid self-join count with the pair-set checksums (test bookkeeping: the
     sums modulo 2^64 of two SplitMix64 mixes of key = i * 2^32 + j over the
