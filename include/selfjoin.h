@@ -274,7 +274,7 @@ void selfjoin_free_grid(sj_grid *g, void *stream);
  * on the same GPU from outside the library must not touch that array (it
  * cannot: its address is private to the library).
  * Limit: inputs whose worst-case need exceeds the array return
- * SJ_ERR_CAPACITY before any device work (about n <= 1.26M at d = 2, 640k
+ * SJ_ERR_CAPACITY before any device work (about n <= 1.24M at d = 2, 630k
  * at d = 4, 190k at d = 64, 57k at d = 256; selfjoin_last_error states the
  * need).
  * Errors: SJ_ERR_INVALID (bad argument or non-finite coordinate),

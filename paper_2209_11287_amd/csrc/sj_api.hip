@@ -409,11 +409,11 @@ size_t lean_need(int64_t n, int32_t d) {
     for (int j = 0; j < std::min(d, kMaxIndexDims) - 1; ++j) nr *= 3;
     auto A = [](size_t b) { return (b + 16 + 255) & ~size_t(255); };
     auto scan = [](size_t L) { return L / 256 + 4096; };
-    const size_t nb_rs = (N + 4095) / 4096 + 1;
+    const size_t sort_tiles = (N + 4095) / 4096 + 1;
     size_t need = 0;
     need += 2 * A(2048 * (size_t)d * 8) + A((2 * (size_t)d + 1) * 8);              // bounding box
     need += 2 * A(8 * N) + 2 * A(4 * N);                                             // keys, indices
-    need += 2 * A(nb_rs * 256 * 4) + 8 * scan(nb_rs * 256);                         // radix sort
+    need += A((8 * 256 + 9) * 4) + A(8 * sort_tiles * 256 * 8);                     // radix sort
     need += A(rows * dp * 8) + A(rows * da * 8) + 2 * A(rows * 8) + 3 * A(16);      // rows, norms
     need += A(std::max<size_t>(4096, N / 256 + 1) * 8);                              // norm maxima
     need += 2 * A((N + N / kTileQ + 2) * 4);                                         // flags, ids

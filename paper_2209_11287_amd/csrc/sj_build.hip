@@ -173,27 +173,6 @@ __device__ __forceinline__ unsigned long long sub_cell(double t, int64_t c, int 
     return (unsigned long long)(f < 0.0 ? 0.0 : (f > top ? top : f));
 }
 
-__global__ void k_keys(const double *__restrict__ X, int64_t n, KeyGeom geo,
-                       unsigned long long *__restrict__ key, int32_t *__restrict__ idx) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    unsigned long long kk = 0, sub = 0;
-    for (int j = 0; j < geo.k; ++j) {
-        // c = floor(fl(fl(x - lo) / w)), clamped: the same two roundings as
-        // the reference grid definition.
-        // (clamped in double before the conversion: an infinite quotient
-        // converts to nothing out of range)
-        const double t = __ddiv_rn(__dsub_rn(X[i * geo.d + j], geo.lo[j]), geo.w);
-        double q = floor(t);
-        q = !(q >= 0.0) ? 0.0 : (q > (double)(geo.m[j] - 1) ? (double)(geo.m[j] - 1) : q);
-        const int64_t c = (int64_t)q;
-        kk += (unsigned long long)c * (unsigned long long)geo.stride[j];
-        if (j == geo.k - 1) sub = sub_cell(t, c, geo.sb);
-    }
-    key[i] = (kk << geo.sb) | sub;
-    idx[i] = (int32_t)i;
-}
-
 // ----------------------------------------------------------- radix sort ----
 // Stable LSD radix sort of (64-bit key, int32 value), 8-bit digits. Each
 // block owns a tile of kThreads * kRsItems keys. Pass = per-tile digit
@@ -266,6 +245,224 @@ __global__ void k_rs_scatter(const unsigned long long *__restrict__ kin, const i
             vout[pos] = vv;
         }
         __syncthreads();
+    }
+}
+
+// ------------------------------------------------------ one-sweep sort ----
+// The build's sort of (cell key, point index): LSD radix sort, 8-bit digits,
+// one launch per digit. The key kernel also counts every digit of every key
+// (all passes' digit histograms in one read). A pass kernel takes one tile
+// of kOsTile keys (tile numbers handed out in launch order by a counter, so
+// every tile's predecessors have started), ranks its keys stably by digit
+// (wave-wide digit match, as in k_rs_scatter), publishes its per-digit counts
+// and finds the counts of all tiles before it by looking back over their
+// published words (decoupled look-back; each word = flag + count, read and
+// written as one 64-bit atomic). The tile's keys are reordered by digit in
+// LDS first, so the stores of one digit's run are contiguous.
+// Keys of at most 32 bits travel packed with their index in one 64-bit word
+// (key in the high half); the last pass then writes the key and the index
+// to separate arrays. Wider keys travel as (64-bit key, 32-bit index).
+// A look-back that does not see its predecessor's word after kOsSpin polls
+// sets *err (the host reports it) instead of waiting on; with tile numbers
+// handed out in order it cannot happen.
+constexpr int kOsItems = 16;
+constexpr int kOsTile = kThreads * kOsItems;
+constexpr int kOsMaxPasses = 8;
+constexpr unsigned long long kOsAgg = 1ull << 32;     // word flag: the tile's own count
+constexpr unsigned long long kOsIncl = 2ull << 32;    // word flag: count of this tile and all before it
+constexpr int kOsSpin = 1 << 16;
+
+enum { OS_PACKED = 0, OS_PACKED_SPLIT = 1, OS_WIDE = 2 };
+
+// Cell keys plus the digit histograms of every sort pass. Key of point i:
+// c_j = floor(fl(fl(x_j - lo_j) / w)) clamped to [0, m_j - 1] (the same two
+// roundings as the reference grid definition; clamped in double before the
+// conversion, so an infinite quotient converts to nothing out of range),
+// key = sum c_j stride_j, followed by sb sub-cell bits (the position inside
+// the cell along the last indexed dimension). hist[p][v] = keys whose digit p
+// is v (p < passes). PACKED: out[i] = key << 32 | i.
+template <bool PACKED>
+__global__ __launch_bounds__(kThreads) void k_keys_hist(const double *__restrict__ X, int64_t n, KeyGeom geo,
+                                                        unsigned long long *__restrict__ key,
+                                                        int32_t *__restrict__ idx, int passes,
+                                                        int32_t *__restrict__ hist) {
+    __shared__ int32_t h[kOsMaxPasses * 256];
+    for (int t = threadIdx.x; t < passes * 256; t += kThreads) h[t] = 0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        unsigned long long kk = 0, sub = 0;
+        for (int j = 0; j < geo.k; ++j) {
+            const double t = __ddiv_rn(__dsub_rn(X[i * geo.d + j], geo.lo[j]), geo.w);
+            double q = floor(t);
+            q = !(q >= 0.0) ? 0.0 : (q > (double)(geo.m[j] - 1) ? (double)(geo.m[j] - 1) : q);
+            const int64_t c = (int64_t)q;
+            kk += (unsigned long long)c * (unsigned long long)geo.stride[j];
+            if (j == geo.k - 1) sub = sub_cell(t, c, geo.sb);
+        }
+        const unsigned long long full = (kk << geo.sb) | sub;
+        if (PACKED) {
+            key[i] = (full << 32) | (unsigned long long)(uint32_t)i;
+        } else {
+            key[i] = full;
+            idx[i] = (int32_t)i;
+        }
+        for (int p = 0; p < passes; ++p) atomicAdd(&h[p * 256 + (int)((full >> (8 * p)) & 255u)], 1);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < passes * 256; t += kThreads)
+        if (h[t]) atomicAdd(&hist[t], h[t]);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_onesweep(const unsigned long long *__restrict__ kin,
+                                                       const int32_t *__restrict__ vin,
+                                                       unsigned long long *__restrict__ kout,
+                                                       int32_t *__restrict__ vout, int64_t n, int shift,
+                                                       const int32_t *__restrict__ hist,
+                                                       unsigned long long *__restrict__ status,
+                                                       int32_t *__restrict__ tile_ctr, int32_t *__restrict__ err) {
+    __shared__ unsigned long long skey[kOsTile];
+    __shared__ int32_t sval[MODE == OS_WIDE ? kOsTile : 1];
+    __shared__ int32_t dcnt[256];   // the tile's keys per digit
+    __shared__ int32_t dexc[256];   // their exclusive prefix: first LDS slot of each digit
+    __shared__ int32_t gbase[256];  // first output position of the tile's keys of each digit
+    __shared__ int32_t run[256];
+    __shared__ int32_t wcnt[kThreads / 64][256];
+    __shared__ int32_t wpre[kThreads / 64][256];
+    __shared__ int32_t wsum[kThreads / 64];
+    __shared__ int32_t tile_sh;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int dshift = (MODE == OS_WIDE ? 0 : 32) + shift;
+    if (tid == 0) tile_sh = atomicAdd(tile_ctr, 1);
+    dcnt[tid] = 0;
+    run[tid] = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const int tile = tile_sh;
+    const int64_t t0 = (int64_t)tile * kOsTile;
+    // the tile's keys, all loads in flight together
+    unsigned long long kk[kOsItems];
+    int32_t vv[kOsItems];
+#pragma unroll
+    for (int r = 0; r < kOsItems; ++r) {
+        const int64_t i = t0 + (int64_t)r * kThreads + tid;
+        kk[r] = i < n ? kin[i] : 0ull;
+        if (MODE == OS_WIDE) vv[r] = i < n ? vin[i] : 0;
+    }
+    // digit counts of the tile
+#pragma unroll
+    for (int r = 0; r < kOsItems; ++r)
+        if (t0 + (int64_t)r * kThreads + tid < n) atomicAdd(&dcnt[(int)((kk[r] >> dshift) & 255u)], 1);
+    __syncthreads();
+    // publish them at once (the first tile publishes its inclusive count)
+    const int agg = dcnt[tid];
+    __hip_atomic_store(&status[(int64_t)tile * 256 + tid],
+                       (tile == 0 ? kOsIncl : kOsAgg) | (unsigned long long)(uint32_t)agg, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    // exclusive prefix of the counts over digits (LDS slots) and of the
+    // pass's histogram (the digit's first output position)
+    {
+        int x = agg, y = hist[tid];
+        int xi = x, yi = y;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int a = __shfl_up(xi, o), b = __shfl_up(yi, o);
+            if (lane >= o) {
+                xi += a;
+                yi += b;
+            }
+        }
+        if (lane == 63) wsum[wave] = xi;
+        __syncthreads();
+        int xo = 0;
+        for (int w = 0; w < wave; ++w) xo += wsum[w];
+        __syncthreads();
+        if (lane == 63) wsum[wave] = yi;
+        __syncthreads();
+        int yo = 0;
+        for (int w = 0; w < wave; ++w) yo += wsum[w];
+        dexc[tid] = xo + xi - x;
+        gbase[tid] = yo + yi - y;  // completed by the look-back below
+    }
+    __syncthreads();
+    // stable ranks, round by round (round r = keys t0 + 256 r ..): digit match
+    // within the wave, per-wave counts combined per digit in LDS
+    const unsigned long long lt = lane ? ((~0ull) >> (64u - (unsigned)lane)) : 0ull;
+#pragma unroll
+    for (int r = 0; r < kOsItems; ++r) {
+        const bool valid = t0 + (int64_t)r * kThreads + tid < n;
+        const unsigned digit = valid ? (unsigned)((kk[r] >> dshift) & 255u) : 0u;
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (digit >> b) & 1u;
+            const unsigned long long m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const int rank = __popcll(peers & lt);
+        if (valid && rank == 0) wcnt[wave][digit] = __popcll(peers);
+        __syncthreads();
+        {
+            int acc = run[tid];
+#pragma unroll
+            for (int w = 0; w < kThreads / 64; ++w) {
+                wpre[w][tid] = acc;
+                acc += wcnt[w][tid];
+                wcnt[w][tid] = 0;
+            }
+            run[tid] = acc;
+        }
+        __syncthreads();
+        if (valid) {
+            const int slot = dexc[digit] + wpre[wave][digit] + rank;
+            skey[slot] = kk[r];
+            if (MODE == OS_WIDE) sval[slot] = vv[r];
+        }
+    }
+    // look back over the earlier tiles' words of this thread's digit
+    if (tile > 0) {
+        int excl = 0, spins = 0;
+        for (int k = tile - 1; k >= 0;) {
+            const unsigned long long w =
+                __hip_atomic_load(&status[(int64_t)k * 256 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long f = w & ~0xffffffffull;
+            if (f == 0ull) {
+                if (++spins > kOsSpin) {
+                    atomicOr(err, 1);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            excl += (int)(uint32_t)w;
+            if (f == kOsIncl) break;
+            --k;
+        }
+        __hip_atomic_store(&status[(int64_t)tile * 256 + tid], kOsIncl | (unsigned long long)(uint32_t)(excl + agg),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        gbase[tid] += excl;
+    }
+    __syncthreads();
+    // stores in LDS order: each digit's run of the tile is contiguous
+    const int cnt = (int)min<int64_t>(kOsTile, n - t0);
+#pragma unroll
+    for (int r = 0; r < kOsItems; ++r) {
+        const int sidx = r * kThreads + tid;
+        if (sidx < cnt) {
+            const unsigned long long k = skey[sidx];
+            const int d = (int)((k >> dshift) & 255u);
+            const int64_t pos = (int64_t)gbase[d] + (sidx - dexc[d]);
+            if (MODE == OS_PACKED) {
+                kout[pos] = k;
+            } else if (MODE == OS_PACKED_SPLIT) {
+                kout[pos] = k >> 32;
+                vout[pos] = (int32_t)(uint32_t)k;
+            } else {
+                kout[pos] = k;
+                vout[pos] = sval[sidx];
+            }
+        }
     }
 }
 
@@ -1032,12 +1229,24 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     }
     choose_geometry(g, index_dims);
 
-    // ---- G2: cell keys ----
+    // ---- G2 + G3: cell keys, then a one-sweep radix sort on the key bits in use ----
     unsigned long long *key_a = dev_alloc_n<unsigned long long>(n, s);
     unsigned long long *key_b = dev_alloc_n<unsigned long long>(n, s);
     int32_t *val_a = dev_alloc_n<int32_t>(n, s);
     int32_t *val_b = dev_alloc_n<int32_t>(n, s);
-    {
+    const int sort_bits = g.key_bits + g.sub_bits;
+    const int passes = (sort_bits + 7) / 8;
+    const bool packed = passes > 0 && sort_bits <= 32;
+    const int64_t os_tiles = std::max<int64_t>(1, (n + kOsTile - 1) / kOsTile);
+    int32_t *os_hist = dev_alloc_n<int32_t>(kOsMaxPasses * 256 + kOsMaxPasses + 1, s);  // hists, tile counters, err
+    int32_t *os_ctr = os_hist + kOsMaxPasses * 256;
+    int32_t *os_err = os_ctr + kOsMaxPasses;
+    unsigned long long *os_status =
+        passes > 0 ? dev_alloc_n<unsigned long long>((size_t)passes * os_tiles * 256, s) : nullptr;
+    fill_zero_many({{os_hist, (kOsMaxPasses * 256 + kOsMaxPasses + 1) * sizeof(int32_t)},
+                    {os_status, os_status ? (size_t)passes * os_tiles * 256 * sizeof(unsigned long long) : 0}},
+                   s);
+    if (n > 0) {
         KeyGeom geo{};
         geo.k = g.k;
         geo.d = d;
@@ -1048,28 +1257,34 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
             geo.m[j] = g.m[j];
             geo.stride[j] = g.stride[j];
         }
-        hipLaunchKernelGGL(k_keys, dim3(blocks_for(n)), dim3(kThreads), 0, s, points, n, geo, key_a, val_a);
+        const unsigned kb = std::min(blocks_for(n), 512u);
+        if (packed)
+            hipLaunchKernelGGL(k_keys_hist<true>, dim3(kb), dim3(kThreads), 0, s, points, n, geo, key_a, val_a,
+                               passes, os_hist);
+        else
+            hipLaunchKernelGGL(k_keys_hist<false>, dim3(kb), dim3(kThreads), 0, s, points, n, geo, key_a, val_a,
+                               passes, os_hist);
         SJ_HIP(hipGetLastError());
-    }
-
-    // ---- G3: radix sort on the key bits in use ----
-    {
-        const int nb = (int)std::max<int64_t>(1, (n + kRsTile - 1) / kRsTile);
-        int32_t *hist = dev_alloc_n<int32_t>((size_t)nb * 256, s);
-        int32_t *hist_ex = dev_alloc_n<int32_t>((size_t)nb * 256, s);
-        for (int shift = 0; shift < g.key_bits + g.sub_bits; shift += 8) {
-            hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kThreads), 0, s, key_a, n, shift, hist, nb);
-            SJ_HIP(hipGetLastError());
-            exclusive_scan<int32_t, int32_t>(hist, hist_ex, (int64_t)nb * 256, s);
-            hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kThreads), 0, s, key_a, val_a, key_b, val_b, n,
-                               shift, hist_ex, nb);
+        for (int p = 0; p < passes; ++p) {
+            const bool last = p == passes - 1;
+            unsigned long long *st = os_status + (size_t)p * os_tiles * 256;
+            if (!packed)
+                hipLaunchKernelGGL(k_onesweep<OS_WIDE>, dim3((unsigned)os_tiles), dim3(kThreads), 0, s, key_a, val_a,
+                                   key_b, val_b, n, 8 * p, os_hist + 256 * p, st, os_ctr + p, os_err);
+            else if (!last)
+                hipLaunchKernelGGL(k_onesweep<OS_PACKED>, dim3((unsigned)os_tiles), dim3(kThreads), 0, s, key_a,
+                                   val_a, key_b, val_b, n, 8 * p, os_hist + 256 * p, st, os_ctr + p, os_err);
+            else
+                hipLaunchKernelGGL(k_onesweep<OS_PACKED_SPLIT>, dim3((unsigned)os_tiles), dim3(kThreads), 0, s,
+                                   key_a, val_a, key_b, val_b, n, 8 * p, os_hist + 256 * p, st, os_ctr + p, os_err);
             SJ_HIP(hipGetLastError());
             std::swap(key_a, key_b);
-            std::swap(val_a, val_b);
+            // packed passes carry the index in the key word; the last one
+            // writes it to the index array
+            if (!packed || last) std::swap(val_a, val_b);
         }
-        dev_free(hist, s);
-        dev_free(hist_ex, s);
     }
+    if (os_status) dev_free(os_status, s);
     g.perm = val_a;
     dev_free(val_b, s);
 
@@ -1187,10 +1402,12 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     }
     // ---- one host sync: table sizes, candidates of the items, nmax ----
     int32_t hc[4] = {0, 0, 0, 0};
+    int32_t herr = 0;
     double hn = 0.0;
     unsigned long long hacc[2] = {0, 0};
     if (n > 0) {
         SJ_HIP(hipMemcpyAsync(hc, counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        SJ_HIP(hipMemcpyAsync(&herr, os_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         SJ_HIP(hipMemcpyAsync(&hn, g.dev_nmax, sizeof(double), hipMemcpyDeviceToHost, s));
         SJ_HIP(hipMemcpyAsync(hacc, acc, sizeof hacc, hipMemcpyDeviceToHost, s));
     }
@@ -1203,6 +1420,8 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     } else {
         SJ_HIP(hipStreamSynchronize(s));
     }
+    dev_free(os_hist, s);
+    if (herr) throw HipError{hipErrorLaunchFailure, "radix sort: a tile's look-back did not complete"};
     g.cells = hc[0];
     g.items = hc[2];
     g.nblocks = hc[3];
