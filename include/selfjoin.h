@@ -114,7 +114,26 @@ typedef struct {
     void *(*alloc)(size_t bytes, void *stream, void *ctx);
     void (*free)(void *ptr, void *stream, void *ctx);
     void *alloc_ctx;
-    int64_t reserved[4];
+    int32_t short_circuit;  /* the partial-distance short-circuit of the FP64
+                               tile paths (Section III-B; a filter, the result
+                               does not depend on it), for d > 4: 0 = the
+                               library's schedule, -1 = off, k > 0 = every k
+                               K-steps of 4 dimensions. FP64 MFMA: one check
+                               after half the K-steps for d <= 16, every k
+                               (default 4) K-steps beyond; FP64 VALU: every
+                               4k (default 4) dimensions for d > 8 (the d <= 8
+                               forms keep the query rows in registers and run
+                               without checks) */
+    int32_t dim_order;      /* order of the dimensions in the FP64 MFMA tiles
+                               (a filter choice, the result does not depend
+                               on it; the exact FP64 chain always runs in
+                               input order), for d > 4: 0 = the indexed
+                               dimensions first (a tile's candidates lie close
+                               together on them), then the others by
+                               decreasing variance (Section II-D), so the
+                               partial distance at each check grows fastest;
+                               1 = input order */
+    int64_t reserved[3];
 } sj_opts;
 
 /* Statistics of one call (all optional, pass NULL). */
@@ -139,13 +158,14 @@ typedef struct {
     double ms_emit;      /* pairs: device time of the emission kernel (the
                             recorded in-masks expanded, or the tiles re-run
                             in emission form); 0 for count */
-    int64_t tiles_pruned; /* count, d > 16: 16 x 16 tiles left early because
-                            every value's partial distance already exceeded
-                            the threshold (the short-circuit of Section
-                            III-B): FP64 MFMA after the first 16 dimensions
-                            against eps^2 + Delta, FP64 VALU every 16
-                            dimensions against eps^2 (its chain is
-                            monotone); 0 elsewhere */
+    int64_t tiles_pruned; /* 16 x 16 tiles left before their last K-step
+                            because every value's partial distance already
+                            exceeded the threshold (the short-circuit of
+                            Section III-B, see sj_opts.short_circuit): FP64
+                            MFMA against eps^2 + Delta (prefix norms at the
+                            K-step boundaries), FP64 VALU against eps^2 (its
+                            chain never decreases); 0 on the FP32 / BF16
+                            paths */
     int32_t path_run;    /* the path whose kernels ran (an sj_path): the
                             requested one unless its range guard routed the
                             call to the next exact path (see sj_path) */
@@ -274,8 +294,8 @@ void selfjoin_free_grid(sj_grid *g, void *stream);
  * on the same GPU from outside the library must not touch that array (it
  * cannot: its address is private to the library).
  * Limit: inputs whose worst-case need exceeds the array return
- * SJ_ERR_CAPACITY before any device work (about n <= 1.24M at d = 2, 630k
- * at d = 4, 190k at d = 64, 57k at d = 256; selfjoin_last_error states the
+ * SJ_ERR_CAPACITY before any device work (about n <= 1.29M at d = 2, 647k
+ * at d = 4, 175k at d = 64, 50k at d = 256; selfjoin_last_error states the
  * need).
  * Errors: SJ_ERR_INVALID (bad argument or non-finite coordinate),
  * SJ_ERR_UNSUPPORTED (low-precision path with d > 64), SJ_ERR_CAPACITY,

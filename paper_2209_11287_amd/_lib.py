@@ -48,7 +48,8 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void
 class sj_opts(ctypes.Structure):
     _fields_ = [("index_dims", ctypes.c_int32), ("tune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
-                ("reserved", ctypes.c_int64 * 4)]
+                ("short_circuit", ctypes.c_int32), ("dim_order", ctypes.c_int32),
+                ("reserved", ctypes.c_int64 * 3)]
 
 
 class sj_stats(ctypes.Structure):

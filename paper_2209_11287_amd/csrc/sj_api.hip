@@ -411,10 +411,11 @@ size_t lean_need(int64_t n, int32_t d) {
     auto scan = [](size_t L) { return L / 256 + 4096; };
     const size_t sort_tiles = (N + 4095) / 4096 + 1;
     size_t need = 0;
-    need += 2 * A(2048 * (size_t)d * 8) + A((2 * (size_t)d + 1) * 8);              // bounding box
+    need += A(4 * 2048 * (size_t)d * 8) + A((4 * (size_t)d + 1) * 8);              // bounding box, moments
     need += 2 * A(8 * N) + 2 * A(4 * N);                                             // keys, indices
     need += A((8 * 256 + 9) * 4) + A(8 * sort_tiles * 256 * 8);                     // radix sort
-    need += A(rows * dp * 8) + A(rows * da * 8) + 2 * A(rows * 8) + 3 * A(16);      // rows, norms
+    const size_t npc = d > 4 ? da / 4 - 1 : 0;
+    need += A(rows * dp * 8) + A(rows * da * 8) + A(rows * 8) + A(rows * npc * 8) + 3 * A(16);  // rows, norms
     need += A(std::max<size_t>(4096, N / 256 + 1) * 8);                              // norm maxima
     need += 2 * A((N + N / kTileQ + 2) * 4);                                         // flags, ids
     need += A(8 * (N + 1)) + 4 * A(4 * (N + 2)) + 3 * scan(N + 1);                   // cells, lines
@@ -486,10 +487,17 @@ sj_status selfjoin_build_grid(const double *points, int64_t n, int32_t d, double
     if (opts && (opts->index_dims < -1 || opts->index_dims > kMaxIndexDims))
         return invalid("index_dims must be in [-1, 4]");
     if (opts && !opts->alloc != !opts->free) return invalid("alloc and free must be given together");
+    if (opts && (opts->short_circuit < -1 || opts->short_circuit > 64))
+        return invalid("short_circuit must be in [-1, 64]");
+    if (opts && (opts->dim_order < 0 || opts->dim_order > 1)) return invalid("dim_order must be 0 or 1");
     hipStream_t s = static_cast<hipStream_t>(stream);
     sj_grid *h = nullptr;
     SJ_API_BEGIN
     h = new sj_grid();
+    if (opts) {
+        h->g.sc = opts->short_circuit;
+        h->g.dim_order = opts->dim_order;
+    }
     if (opts && opts->alloc) {
         h->g.hook.alloc = opts->alloc;
         h->g.hook.free = opts->free;

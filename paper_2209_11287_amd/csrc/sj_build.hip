@@ -93,64 +93,102 @@ void fill_ones(void *p, size_t bytes, hipStream_t s) {
 // ---------------------------------------------------------------- bbox ----
 // Each block reduces a contiguous run of rows. Threads walk the run's
 // elements with a stride that is a multiple of d, so each thread sees a single
-// dimension; per-dimension partials then go to memory.
+// dimension; per-dimension partials then go to memory. MOM: also the sums of
+// (x - x_0) and (x - x_0)^2 per dimension (x_0 = the first row's value), for
+// the variance order of the filter's dimensions (only an ordering: their
+// rounding does not matter).
+template <bool MOM>
 __global__ void k_bbox_partial(const double *__restrict__ X, int64_t n, int d, int64_t rows_per_block,
-                               double *__restrict__ pmin, double *__restrict__ pmax,
-                               int *__restrict__ bad) {
+                               double *__restrict__ pmin, double *__restrict__ pmax, double *__restrict__ psum,
+                               double *__restrict__ psq, int *__restrict__ bad) {
     __shared__ double smin[kThreads], smax[kThreads];
+    __shared__ double ssum[MOM ? kThreads : 1], ssq[MOM ? kThreads : 1];
     const int S = (kThreads / d) * d;
     const int tid = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
     const int64_t r1 = min(n, r0 + rows_per_block);
-    double mn = INFINITY, mx = -INFINITY;
+    double mn = INFINITY, mx = -INFINITY, s1 = 0.0, s2 = 0.0;
     int nonfinite = 0;
     if (tid < S && r0 < r1) {
         const int64_t e0 = r0 * d, e1 = r1 * d;
+        const double x0 = MOM ? X[tid % d] : 0.0;
 #pragma unroll 4
         for (int64_t e = e0 + tid; e < e1; e += S) {
             double v = X[e];
             nonfinite |= !isfinite(v);
             mn = fmin(mn, v);
             mx = fmax(mx, v);
+            if (MOM) {
+                const double c = v - x0;
+                s1 += c;
+                s2 = fma(c, c, s2);
+            }
         }
     }
     smin[tid] = mn;
     smax[tid] = mx;
+    if (MOM) {
+        ssum[tid] = s1;
+        ssq[tid] = s2;
+    }
     if (nonfinite) atomicOr(bad, 1);
     __syncthreads();
     if (tid < d) {
-        double a = INFINITY, b = -INFINITY;
+        double a = INFINITY, b = -INFINITY, c1 = 0.0, c2 = 0.0;
         for (int t = tid; t < S; t += d) {
             a = fmin(a, smin[t]);
             b = fmax(b, smax[t]);
+            if (MOM) {
+                c1 += ssum[t];
+                c2 += ssq[t];
+            }
         }
         pmin[(int64_t)blockIdx.x * d + tid] = a;
         pmax[(int64_t)blockIdx.x * d + tid] = b;
+        if (MOM) {
+            psum[(int64_t)blockIdx.x * d + tid] = c1;
+            psq[(int64_t)blockIdx.x * d + tid] = c2;
+        }
     }
 }
 
-__global__ void k_bbox_final(const double *__restrict__ pmin, const double *__restrict__ pmax, int nb,
-                             int d, double *__restrict__ out /* lo[d], hi[d] */) {
-    __shared__ double smin[kThreads], smax[kThreads];
+// One block per dimension j: out[j] = min, out[d + j] = max and, with the
+// moments (psum non-null), out[2d + j], out[3d + j] = their sums.
+__global__ void k_bbox_final(const double *__restrict__ pmin, const double *__restrict__ pmax,
+                             const double *__restrict__ psum, const double *__restrict__ psq, int nb, int d,
+                             double *__restrict__ out) {
+    __shared__ double smin[kThreads], smax[kThreads], s1[kThreads], s2[kThreads];
     const int j = blockIdx.x;
-    double a = INFINITY, b = -INFINITY;
+    double a = INFINITY, b = -INFINITY, c1 = 0.0, c2 = 0.0;
     for (int t = threadIdx.x; t < nb; t += blockDim.x) {
         a = fmin(a, pmin[(int64_t)t * d + j]);
         b = fmax(b, pmax[(int64_t)t * d + j]);
+        if (psum) {
+            c1 += psum[(int64_t)t * d + j];
+            c2 += psq[(int64_t)t * d + j];
+        }
     }
     smin[threadIdx.x] = a;
     smax[threadIdx.x] = b;
+    s1[threadIdx.x] = c1;
+    s2[threadIdx.x] = c2;
     __syncthreads();
     for (int w = blockDim.x / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
             smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + w]);
             smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+            s1[threadIdx.x] += s1[threadIdx.x + w];
+            s2[threadIdx.x] += s2[threadIdx.x + w];
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         out[j] = smin[0];
         out[d + j] = smax[0];
+        if (psum) {
+            out[2 * d + j] = s1[0];
+            out[3 * d + j] = s2[0];
+        }
     }
 }
 
@@ -661,9 +699,15 @@ __global__ void k_max_final(const double *__restrict__ part, int64_t nb, double 
 
 struct GatherArgs {
     int d, dp, da;
+    int npc;                 // prefix norms per row (0: none)
+    uint8_t fo[kMaxDims];    // column t of xa holds input dimension fo[t]
     double mid[kMaxDims];
 };
 
+// Sorted rows (xs, input order), centred rows in the tile order (xa: column
+// t = input dimension fo[t] minus its centre; slot d = the norm when d % 4 !=
+// 0), norms and the prefix norms over the first 4s columns, s = 1 .. npc
+// (the same FP64 chain, stopped at each K-step boundary).
 __global__ void k_gather(const double *__restrict__ X, const int32_t *__restrict__ perm, int64_t n,
                          const GatherArgs ga_v, double *__restrict__ xs,
                          double *__restrict__ xa, double *__restrict__ nrm, double *__restrict__ pn,
@@ -672,17 +716,17 @@ __global__ void k_gather(const double *__restrict__ X, const int32_t *__restrict
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double nn = 0.0;
     if (i < n) {
-        const int d = ga->d, dp = ga->dp, da = ga->da;
+        const int d = ga->d, dp = ga->dp, da = ga->da, npc = ga->npc;
         const double *src = X + (int64_t)perm[i] * d;
         double *ps = xs + i * dp;
         double *pa = xa + i * da;
+        for (int t = 0; t < d; ++t) ps[t] = src[t];
         for (int t = 0; t < d; ++t) {
-            const double v = src[t];
-            const double c = __dsub_rn(v, ga->mid[t]);
-            ps[t] = v;
+            const int u = ga->fo[t];
+            const double c = __dsub_rn(src[u], ga->mid[u]);
             pa[t] = c;
             nn = __fma_rn(c, c, nn);
-            if (pn && t == 15) pn[i] = nn;
+            if ((t & 3) == 3 && (t >> 2) < npc) pn[i * npc + (t >> 2)] = nn;
         }
         for (int t = d; t < dp; ++t) ps[t] = 0.0;
         for (int t = d; t < da; ++t) pa[t] = 0.0;
@@ -1172,6 +1216,30 @@ static void choose_geometry(Grid &g, int index_dims) {
     for (int j = 0; j < k - 1; ++j) g.nranges *= 3;
 }
 
+// Dimension order of the distance tiles. A tile's 16 candidates come from
+// one stretch of the sorted order, so they lie close together on the indexed
+// dimensions, where a neighbour cell can put all of them up to two cell sides
+// from the queries: the indexed dimensions come first (input order), and a
+// whole tile is often beyond eps after them alone. The other dimensions
+// follow by decreasing variance (ties by index), so the partial distance at
+// each later K-step boundary grows as fast as the data allows (a filter
+// choice only). An indexed dimension with a single cell bounds nothing and
+// counts as non-indexed. Identity for d <= 4 or dim_order = 1.
+static void choose_dim_order(Grid &g, const std::vector<double> &var) {
+    const int d = g.d;
+    for (int t = 0; t < d; ++t) g.fo[t] = (uint8_t)t;
+    if (d <= 4 || g.dim_order != 0) return;
+    auto bounded = [&](int j) { return j < g.k && g.m[j] > 1; };
+    std::vector<int> idx(d);
+    for (int t = 0; t < d; ++t) idx[t] = t;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+        if (bounded(a) != bounded(b)) return bounded(a);
+        if (bounded(a)) return a < b;
+        return var[a] > var[b];
+    });
+    for (int t = 0; t < d; ++t) g.fo[t] = (uint8_t)idx[t];
+}
+
 void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int index_dims,
                 hipStream_t s) {
     g.n = n;
@@ -1196,38 +1264,52 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     } evg{ev0, ev1};
     if (ev0) SJ_HIP(hipEventRecord(ev0, s));
 
-    // ---- G1: bounding box and finiteness (one host sync) ----
+    // ---- G1: bounding box, finiteness and (d > 4) moments (one host sync) ----
+    const bool mom = d > 4 && g.dim_order == 0;
+    std::vector<double> var(d, 0.0);
     if (n == 0) {
         for (int j = 0; j < d; ++j) g.lo[j] = g.hi[j] = g.mid[j] = 0.0;
     } else {
         const int64_t rows_per_block = std::max<int64_t>(1024, (n + 2047) / 2048);
         const int nb = (int)std::max<int64_t>(1, (n + rows_per_block - 1) / rows_per_block);
-        double *pmin = dev_alloc_n<double>((size_t)nb * d, s);
-        double *pmax = dev_alloc_n<double>((size_t)nb * d, s);
-        double *box = dev_alloc_n<double>(2 * (size_t)d + 1, s);
-        int *bad = reinterpret_cast<int *>(box + 2 * d);
+        const int parts = mom ? 4 : 2;
+        double *part = dev_alloc_n<double>((size_t)parts * nb * d, s);
+        double *pmin = part, *pmax = part + (size_t)nb * d;
+        double *psum = mom ? part + 2 * (size_t)nb * d : nullptr;
+        double *psq = mom ? part + 3 * (size_t)nb * d : nullptr;
+        const size_t nbox = (size_t)(mom ? 4 : 2) * d;
+        double *box = dev_alloc_n<double>(nbox + 1, s);
+        int *bad = reinterpret_cast<int *>(box + nbox);
         fill_zero(bad, sizeof(int), s);
-        hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(kThreads), 0, s, points, n, d, rows_per_block,
-                           pmin, pmax, bad);
+        if (mom)
+            hipLaunchKernelGGL(k_bbox_partial<true>, dim3(nb), dim3(kThreads), 0, s, points, n, d, rows_per_block,
+                               pmin, pmax, psum, psq, bad);
+        else
+            hipLaunchKernelGGL(k_bbox_partial<false>, dim3(nb), dim3(kThreads), 0, s, points, n, d, rows_per_block,
+                               pmin, pmax, psum, psq, bad);
         SJ_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_bbox_final, dim3(d), dim3(kThreads), 0, s, pmin, pmax, nb, d, box);
+        hipLaunchKernelGGL(k_bbox_final, dim3(d), dim3(kThreads), 0, s, pmin, pmax, psum, psq, nb, d, box);
         SJ_HIP(hipGetLastError());
-        std::vector<double> hb(2 * (size_t)d + 1);
-        SJ_HIP(hipMemcpyAsync(hb.data(), box, (2 * (size_t)d + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        std::vector<double> hb(nbox + 1);
+        SJ_HIP(hipMemcpyAsync(hb.data(), box, (nbox + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
         SJ_HIP(hipStreamSynchronize(s));
-        dev_free(pmin, s);
-        dev_free(pmax, s);
+        dev_free(part, s);
         dev_free(box, s);
         int badflag;
-        std::memcpy(&badflag, &hb[2 * d], sizeof(int));
+        std::memcpy(&badflag, &hb[nbox], sizeof(int));
         if (badflag) throw std::string("non-finite coordinate in points");
         for (int j = 0; j < d; ++j) {
             g.lo[j] = hb[j];
             g.hi[j] = hb[d + j];
             g.mid[j] = 0.5 * g.lo[j] + 0.5 * g.hi[j];  // no overflow for any finite lo, hi
+            if (mom) {
+                const double m1 = hb[2 * d + j] / (double)n;
+                var[j] = std::max(0.0, hb[3 * d + j] / (double)n - m1 * m1);
+            }
         }
     }
     choose_geometry(g, index_dims);
+    choose_dim_order(g, var);
 
     // ---- G2 + G3: cell keys, then a one-sweep radix sort on the key bits in use ----
     unsigned long long *key_a = dev_alloc_n<unsigned long long>(n, s);
@@ -1292,7 +1374,8 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     g.xs = dev_alloc_n<double>(rows * g.dp, s);
     g.xa = dev_alloc_n<double>(rows * g.da, s);
     g.nrm = dev_alloc_n<double>(rows, s);
-    if (g.da > 16) g.pn = dev_alloc_n<double>(rows, s);
+    g.npc = d > 4 ? g.da / 4 - 1 : 0;
+    if (g.npc > 0) g.pn = dev_alloc_n<double>(rows * g.npc, s);
     g.dev_nmax = dev_alloc_n<double>(1, s);
     int32_t *counters = dev_alloc_n<int32_t>(4, s);                    // ncells, nlines, nitems
     unsigned long long *acc = dev_alloc_n<unsigned long long>(2, s);  // [0] item candidates, [1] tiles
@@ -1300,7 +1383,7 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     fill_zero_many({{g.xs + (size_t)n * g.dp, (size_t)kRowPad * g.dp * sizeof(double)},
                     {g.xa + (size_t)n * g.da, (size_t)kRowPad * g.da * sizeof(double)},
                     {g.nrm + n, (size_t)kRowPad * sizeof(double)},
-                    {g.pn ? g.pn + n : nullptr, (size_t)kRowPad * sizeof(double)},
+                    {g.pn ? g.pn + (size_t)n * g.npc : nullptr, (size_t)kRowPad * g.npc * sizeof(double)},
                     {g.dev_nmax, sizeof(double)},
                     {counters, 4 * sizeof(int32_t)},
                     {acc, 2 * sizeof(unsigned long long)}},
@@ -1318,7 +1401,11 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
             ga.d = d;
             ga.dp = g.dp;
             ga.da = g.da;
-            for (int j = 0; j < d; ++j) ga.mid[j] = g.mid[j];
+            ga.npc = g.npc;
+            for (int j = 0; j < d; ++j) {
+                ga.mid[j] = g.mid[j];
+                ga.fo[j] = g.fo[j];
+            }
             hipLaunchKernelGGL(k_gather, dim3(nb), dim3(kThreads), 0, s, points, g.perm, n, ga, g.xs, g.xa, g.nrm,
                                g.pn, part);
         }

@@ -118,13 +118,15 @@ struct DevGrid {
     const double *xs;
     const double *xa;
     const double *nrm;
-    const double *pn;  // prefix norms over the first 16 dimensions (da > 16), else null
+    const double *pn;  // prefix norms of xa rows at the K-step boundaries: npc per row, else null
     const int32_t *perm;
     const Range *ranges;
     const Item *items;
     int64_t n;
     int32_t d, dp, da, nranges;
     int32_t nitems;
+    int32_t npc;   // prefix norms per row: da / 4 - 1 for d > 4, else 0
+    int32_t sc;    // short-circuit (sj_opts.short_circuit): 0 = default schedule, -1 = off, k > 0 = every k K-steps
     double eps2;
     const int64_t *tile_off;
 };
@@ -160,13 +162,22 @@ struct Grid {
     int64_t cand_ref = -1;   // C_ref (lazily computed; -1 = not yet)
     int64_t cand_items = 0;  // candidate pairs the work items evaluate
     double nmax = 0;       // max squared norm of the centred rows of xa
+    // Dimension order of the distance tiles (xa, the low-precision tiles):
+    // column t holds input dimension fo[t]. For d > 4 (unless dim_order = 1)
+    // the non-indexed dimensions come first, then the indexed ones, each by
+    // decreasing variance; identity otherwise. The exact chain on xs is
+    // always in input order.
+    uint8_t fo[kMaxDims];
+    int32_t dim_order = 0;  // sj_opts.dim_order
+    int32_t sc = 0;         // sj_opts.short_circuit: 0 = default schedule, -1 = off, k > 0 = every k K-steps
+    int32_t npc = 0;        // prefix norms per row in pn
 
     // device buffers
     double *xs = nullptr;        // sorted original coordinates, n x dp (+pad rows)
     double *xa = nullptr;        // sorted centred coordinates (+norm slot), n x da (+pad rows)
     double *nrm = nullptr;       // squared norms of xa rows (FP64 chain), n (+pad)
-    double *pn = nullptr;        // da > 16: squared norms of xa rows over their first 16
-                                 // dimensions (FP64 chain), n (+pad); else null
+    double *pn = nullptr;        // d > 4: squared norms of xa rows over their first 4s columns,
+                                 // s = 1 .. npc (FP64 chain), n (+pad) x npc; else null
     int32_t *perm = nullptr;     // sorted position -> input index
     int64_t *cell_key = nullptr; // per non-empty cell
     int32_t *cell_start = nullptr; // cells + 1 entries

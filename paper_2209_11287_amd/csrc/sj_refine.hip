@@ -242,10 +242,15 @@ __device__ __forceinline__ void tile_store(const unsigned long long w[4], int c,
 //    item), D = |q|^2 - 2 q.c, and the candidate norm moves to a per-column
 //    threshold: in iff D <= eps^2 - |c|^2.
 // KS = K-steps of 4 dimensions (0 = runtime).
-template <int KS>
+// Operand registers of a tile: every K-step, or (KS > 4, count / emit) the
+// current batch of 4.
+constexpr int m64_nb(int ks, int mode) { return (ks > 4 && mode != MODE_MEASURE) ? 4 : (ks > 0 ? ks : 1); }
+
+template <int KS, int NB>
 struct M64Tile {
-    double b[KS > 0 ? KS : 1];
-    double pn;   // KS > 4: candidate prefix norm over the first 16 dimensions
+    double b[NB];
+    double pn;   // candidate prefix norms (short-circuit): KS 2..4: at K-step KS / 2;
+                 // KS > 4: lane (g, j) holds the one at K-step 4 t + g + 1 of the batch t in registers
     double nc;   // candidate norm (no-slot form)
     int32_t c;   // sorted index of the lane's column (a valid row past the end)
     int32_t pc;  // emit: input index of that candidate
@@ -255,24 +260,28 @@ struct M64Tile {
 // Issues the loads of a tile whose column j is candidate c (n valid
 // columns); nothing here waits for them.
 template <int KS, bool SLOT, int MODE>
-__device__ __forceinline__ void m64_load(M64Tile<KS> &T, int c, int n, const DevGrid &G, int g) {
+__device__ __forceinline__ void m64_load(M64Tile<KS, m64_nb(KS, MODE)> &T, int c, int n, const DevGrid &G, int g) {
     T.c = c;
     T.n = n;
     if (KS > 0) {
-        // KS > 4 (count / emit): only the first 4 K-steps ahead of time; the
-        // rest load after the partial-distance test, for tiles that pass it
+        // KS > 4 (count / emit): only the first batch of 4 K-steps ahead of
+        // time; each further batch loads after the partial-distance tests of
+        // the one before, for tiles that pass them
         constexpr int KL = (KS > 4 && MODE != MODE_MEASURE) ? 4 : (KS > 0 ? KS : 1);
         const double *__restrict__ brow = G.xa + (int64_t)c * G.da + g;
 #pragma unroll
         for (int s = 0; s < KL; ++s) T.b[s] = brow[4 * s];
     }
     T.nc = SLOT ? 0.0 : G.nrm[c];
-    if (KS > 4 && MODE != MODE_MEASURE) T.pn = G.pn[c];  // set for every grid with da > 16
+    if (MODE != MODE_MEASURE) {  // prefix norms exist for every grid with KS >= 2
+        if (KS > 4) T.pn = G.pn[(int64_t)c * G.npc + g];
+        else if (KS >= 2) T.pn = G.pn[(int64_t)c * G.npc + (KS / 2 - 1)];
+    }
     if (MODE == MODE_EMIT) T.pc = G.perm[c];
 }
 
 template <int KS, bool SLOT>
-__device__ __forceinline__ double4_t m64_tile(const M64Tile<KS> &T, const DevGrid &G, const double *aq,
+__device__ __forceinline__ double4_t m64_tile(const M64Tile<KS, (KS > 0 ? KS : 1)> &T, const DevGrid &G, const double *aq,
                                               double4_t cinit, int g, int qa) {
     double4_t acc = cinit;
     if (KS > 0) {
@@ -308,8 +317,8 @@ __device__ __forceinline__ unsigned long long col_mask(int n) {
 // Error measurement: for every value whose exact distance is within 2 eps,
 // the difference between the Gram value and the exact value (on the same
 // side of the threshold equation), its maximum and the count above Delta.
-template <bool SLOT, int KS>
-__device__ __forceinline__ void m64_measure(double4_t acc, const M64Tile<KS> &T, int g, int j, int q0,
+template <bool SLOT, int KS, class TileT>
+__device__ __forceinline__ void m64_measure(double4_t acc, const TileT &T, int g, int j, int q0,
                                             const M64Thr &th, double delta, const DevGrid &G,
                                             unsigned long long &viol, double &maxerr) {
     if (j >= T.n) return;
@@ -331,8 +340,8 @@ __device__ __forceinline__ void m64_measure(double4_t acc, const M64Tile<KS> &T,
 // 16g + j = (query g + 4r, candidate of column j) is within eps. Values at
 // or below threshold - Delta are in, above threshold + Delta out; the rest
 // are decided by the exact FP64 chain. `band` (wave-uniform) counts them.
-template <bool SLOT, int KS>
-__device__ __forceinline__ void m64_words(double4_t acc, const M64Tile<KS> &T, int g, int q0, const M64Thr &th,
+template <bool SLOT, int KS, class TileT>
+__device__ __forceinline__ void m64_words(double4_t acc, const TileT &T, int g, int q0, const M64Thr &th,
                                           const DevGrid &G, unsigned long long &band, unsigned long long &band_in,
                                           unsigned long long w[4]) {
     double lo[4], hi[4];
@@ -416,7 +425,8 @@ __device__ __forceinline__ void nibble_count(unsigned long long nib, int tot[4])
 }
 
 template <int KS, bool SLOT, int MODE>
-__device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, double delta, int it) {
+__device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, double delta, int it,
+                                         double *tqs /* KS > 4: per-wave LDS, (KS - 1) x 16 */) {
     const int lane = threadIdx.x & 63;
     const Item I = G.items[it];
     const int q0 = uniform_i32(I.qbegin);
@@ -428,6 +438,7 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
     const double *__restrict__ xa = G.xa;
     const ItemRanges rg = load_ranges(G, it, lane);
     const double eps2 = G.eps2;
+    using Tile = M64Tile<KS, m64_nb(KS, MODE)>;
 
     // A operand (16 x K): A[i][k] = -2 q_i[k] for k < d, 1 in the norm slot.
     double aq[KS > 0 ? KS : 1];
@@ -456,21 +467,43 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
     }
     th.clo = eps2 - delta;
     th.chi = eps2 + delta;
-    // Partial-distance bound (KS > 4, Section IV's short-circuit, filter
-    // only): after the first 16 dimensions (4 K-steps) the accumulator of row
-    // r is cinit_r - 2 q.c over those dimensions, so their squared distance
-    // is acc - cinit_r + pq_r + pc with prefix norms pq_r, pc. If it exceeds
-    // eps^2 + Delta for every value of the tile (Delta also bounds the
-    // rounding of this partial form, which has fewer terms and smaller norms
-    // than the full one), no pair of the tile is within eps: the remaining
-    // K-steps are skipped. Per row: acc > tq_r - pc. Absent rows never block.
+    // Partial-distance bound (Section III-B's short-circuit, filter only).
+    // After s K-steps (s < KS: the norm slot lies in the last one) the
+    // accumulator of row r is cinit_r - 2 q.c over the first 4s columns of
+    // xa, so their squared distance is acc - cinit_r + pq_r + pc with the
+    // prefix norms pq_r, pc at s. If it exceeds eps^2 + Delta for every value
+    // of the tile, no pair of the tile is within eps (the columns' partial
+    // distances only grow; Delta bounds the rounding of this partial form as
+    // well, which has fewer terms and smaller norms than the full one), and
+    // the tile is dropped: per row, acc > tq_r(s) - pc with tq_r(s) = eps^2 +
+    // Delta + cinit_r - pq_r(s). Absent rows (tq = -inf) and columns past the
+    // item's end never block.
+    // KS 2..4: one check, after K-step KS / 2 (tq in registers); KS > 4: a
+    // check every `every` K-steps (4 by default), tq of every K-step in a
+    // per-wave LDS table [s][g][r], the candidates' prefix norms of a batch
+    // of 4 K-steps spread over the lane's row group.
+    const bool sc_on = MODE != MODE_MEASURE && KS >= 2 && G.sc != -1;
+    const int every = G.sc > 0 ? G.sc : 4;
     double tq[4];
-    if (KS > 4 && MODE != MODE_MEASURE) {
+    if (KS >= 2 && KS <= 4 && sc_on) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = g + 4 * r;
-            tq[r] = i < nq ? eps2 + delta + (SLOT ? 0.0 : th.nq[r]) - G.pn[q0 + i] : -INFINITY;
+            tq[r] = i < nq ? eps2 + delta + (SLOT ? 0.0 : th.nq[r]) - G.pn[(int64_t)(q0 + i) * G.npc + (KS / 2 - 1)]
+                           : -INFINITY;
         }
+    }
+    if (KS > 4 && sc_on) {
+        for (int e = lane; e < (KS > 4 ? KS - 1 : 1) * 16; e += 64) {
+            const int sidx = e >> 4, i = e & 15;
+            const double v = i < nq ? eps2 + delta + (SLOT ? 0.0 : G.nrm[q0 + i]) -
+                                          G.pn[(int64_t)(q0 + i) * G.npc + sidx]
+                                    : -INFINITY;
+            tqs[sidx * 16 + (i & 3) * 4 + (i >> 2)] = v;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     unsigned long long npruned = 0;  // wave-uniform
     unsigned long long ebal[4];
@@ -502,7 +535,7 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
         nib = 0;
         flushed = k0 + 16;
     };
-    auto classify = [&](const double4_t &acc, const M64Tile<KS> &T, int k) {
+    auto classify = [&](const double4_t &acc, const Tile &T, int k) {
         if (MODE == MODE_MEASURE) {
             m64_measure<SLOT, KS>(acc, T, g, j, q0, th, delta, G, viol, maxerr);
             return;
@@ -526,19 +559,68 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
         for (int t = 0; t < 4; ++t) P[t] = 64 * c + 16 * t + j;
         cand_chunk<4>(L, c, P, cand);
     };
-    auto load = [&](M64Tile<KS> &T, int k, int c) {
+    auto load = [&](Tile &T, int k, int c) {
         m64_load<KS, SLOT, MODE>(T, c, min(16, L.total - 16 * k), G, g);
     };
-    // both products first, then both classifications
-    auto run = [&](const M64Tile<KS> &TA, const M64Tile<KS> &TB, int k) {
-        const bool h1 = k + 1 < ntiles;
-        const double4_t a0 = m64_tile<KS, SLOT>(TA, G, aq, cinit, g, qa);
-        double4_t a1;
-        if (h1) a1 = m64_tile<KS, SLOT>(TB, G, aq, cinit, g, qa);
-        classify(a0, TA, k);
-        if (h1) classify(a1, TB, k + 1);
+    // a tile dropped by the partial-distance bound: no pairs, zero row bits
+    auto prune = [&](int k) {
+        ++npruned;
+        if (MODE == MODE_COUNT) {
+            nacc <<= 4;
+            if ((k & 7) == 7) nib_flush(nib, nacc, 8, (k >> 3) & 1);
+        }
     };
-    if (KS > 4) {
+    // wave-uniform: every value of the tile is beyond its row's bound
+    auto far_tile = [&](const double4_t &a, int n, const double t4[4], double pc) -> bool {
+        const bool far = j >= n || (a[0] > t4[0] - pc && a[1] > t4[1] - pc && a[2] > t4[2] - pc &&
+                                    a[3] > t4[3] - pc);
+        return __ballot(!far) == 0ull;
+    };
+    // both products first, then both classifications
+    auto run = [&](const Tile &TA, const Tile &TB, int k) {
+        const bool h1 = k + 1 < ntiles;
+        if constexpr (KS >= 2 && KS <= 4) {
+            if (sc_on) {
+                // first half of both tiles' K-steps, the bound, the rest
+                constexpr int KC = KS / 2;
+                double4_t a0 = cinit, a1 = cinit;
+#pragma unroll
+                for (int s = 0; s < KC; ++s) a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], TA.b[s], a0, 0, 0, 0);
+                if (h1) {
+#pragma unroll
+                    for (int s = 0; s < KC; ++s)
+                        a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], TB.b[s], a1, 0, 0, 0);
+                }
+                const bool x0 = far_tile(a0, TA.n, tq, TA.pn);
+                const bool x1 = h1 && far_tile(a1, TB.n, tq, TB.pn);
+                if (!x0) {
+#pragma unroll
+                    for (int s = KC; s < KS; ++s)
+                        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], TA.b[s], a0, 0, 0, 0);
+                }
+                if (h1 && !x1) {
+#pragma unroll
+                    for (int s = KC; s < KS; ++s)
+                        a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], TB.b[s], a1, 0, 0, 0);
+                }
+                if (x0) prune(k);
+                else classify(a0, TA, k);
+                if (h1) {
+                    if (x1) prune(k + 1);
+                    else classify(a1, TB, k + 1);
+                }
+                return;
+            }
+        }
+        if constexpr (KS <= 4) {  // KS > 4 runs tiles one at a time (run1)
+            const double4_t a0 = m64_tile<KS, SLOT>(TA, G, aq, cinit, g, qa);
+            double4_t a1;
+            if (h1) a1 = m64_tile<KS, SLOT>(TB, G, aq, cinit, g, qa);
+            classify(a0, TA, k);
+            if (h1) classify(a1, TB, k + 1);
+        }
+    };
+    if constexpr (KS > 4) {
         // Many K-steps (d > 16): a tile's KS MFMAs dominate, so one tile is
         // in flight while the other runs (two buffers of KS operands each).
         int have = -1;
@@ -551,44 +633,52 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
             const int t = kk & 3;
             return t == 0 ? cand[0] : t == 1 ? cand[1] : t == 2 ? cand[2] : cand[3];
         };
-        auto run1 = [&](const M64Tile<KS> &T, int k) {
+        // K-steps s + 1 after which the bound is tested (bit s + 1)
+        unsigned long long ckmask = 0;
+        if (sc_on)
+            for (int s1 = every; s1 < KS; s1 += every) ckmask |= 1ull << s1;
+        auto run1 = [&](Tile &T, int k) {
             bool dropped = false;
             double4_t a = cinit;
-            if (MODE == MODE_MEASURE) {
+            if constexpr (MODE == MODE_MEASURE) {
                 a = m64_tile<KS, SLOT>(T, G, aq, cinit, g, qa);
             } else {
+                // batches of 4 K-steps through the tile's 4 operand
+                // registers; batch 0 was loaded ahead
+                const double *__restrict__ brow = G.xa + (int64_t)T.c * G.da + g;
 #pragma unroll
-                for (int s = 0; s < 4; ++s) a = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], T.b[s], a, 0, 0, 0);
-                bool far = j >= T.n;  // columns past the item's end never block
-                if (!far) {
-                    far = true;
+                for (int bt = 0; bt < (KS > 4 ? (KS + 3) / 4 : 1); ++bt) {
+                    if (dropped) break;  // wave-uniform
+                    if (bt > 0) {
+                        // this batch's operands and candidate prefix norms
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) far = far && a[r] > tq[r] - T.pn;
-                }
-                dropped = __ballot(!far) == 0ull;
-                if (!dropped) {
-                    const double *__restrict__ brow = G.xa + (int64_t)T.c * G.da + g;
-                    double rest[KS > 4 ? KS - 4 : 1];
+                        for (int u = 0; u < 4; ++u)
+                            if (4 * bt + u < KS) T.b[u] = brow[4 * (4 * bt + u)];
+                        if (sc_on) T.pn = 4 * bt + g < G.npc ? G.pn[(int64_t)T.c * G.npc + 4 * bt + g] : 0.0;
+                    }
 #pragma unroll
-                    for (int s = 4; s < (KS > 4 ? KS : 4); ++s) rest[s - 4] = brow[4 * s];
-#pragma unroll
-                    for (int s = 4; s < (KS > 4 ? KS : 4); ++s)
-                        a = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], rest[s - 4], a, 0, 0, 0);
+                    for (int u = 0; u < 4; ++u) {
+                        const int s = 4 * bt + u;
+                        if (s >= KS) break;
+                        a = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], T.b[u & 3], a, 0, 0, 0);
+                        if (s + 1 < KS && ((ckmask >> (s + 1)) & 1ull)) {
+                            const double pc = __shfl(T.pn, 16 * u + j);
+                            const double *tp = tqs + s * 16 + 4 * g;
+                            const double t4[4] = {tp[0], tp[1], tp[2], tp[3]};
+                            if (far_tile(a, T.n, t4, pc)) {
+                                dropped = true;
+                                break;
+                            }
+                        }
+                    }
                 }
             }
-            if (dropped) {
-                ++npruned;
-                if (MODE == MODE_COUNT) {
-                    nacc <<= 4;  // the tile's four row bits are zero
-                    if ((k & 7) == 7) nib_flush(nib, nacc, 8, (k >> 3) & 1);
-                }
-            } else {
-                classify(a, T, k);
-            }
+            if (dropped) prune(k);
+            else classify(a, T, k);
             if (MODE == MODE_COUNT && (k & 15) == 15) group_done(k - 15);
         };
         const int klast = ntiles - 1;
-        M64Tile<KS> TA, TB;
+        Tile TA, TB;
         if (ntiles > 0) load(TA, 0, cand_for(0));
         for (int k = 0; k < ntiles; k += 2) {
             const int k1 = min(k + 1, klast);
@@ -605,7 +695,7 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
     // register copy waits on a load in flight). Past the item's last tile the
     // loads repeat valid rows (same instruction count on every path, so each
     // wait covers exactly the older tiles) and nothing runs.
-    M64Tile<KS> T0, T1, T2, T3;
+    Tile T0, T1, T2, T3;
     if (nchunks > 0) {
         chunk(0);
         load(T0, 0, cand[0]);
@@ -655,14 +745,18 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
 }
 
 template <int KS, bool SLOT, int MODE>
-// Six waves per SIMD (at most 80 VGPRs; a few spill in the d % 4 = 0 forms)
-// hide more of the candidate-load latency than five without the cap (~3.5 %).
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_m64(DevGrid G, RefOut R,
-                                                                                             double delta) {
+// d <= 4 (one K-step): six waves per SIMD (at most 80 VGPRs; a few spill in
+// the d % 4 = 0 form) hide more of the candidate-load latency than five
+// without the cap (~3.5 %). More K-steps: four waves (128 VGPRs, about no
+// spills); capped at six they spilled 60-200 bytes per lane and ran 1.3-1.5x
+// slower (Gaussian mixture, 1M points, d = 16, 32, 64), at five 1.2x slower.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KS == 1 ? 6 : 4, 8))) void k_m64(
+    DevGrid G, RefOut R, double delta) {
+    __shared__ double tqbuf[KS > 4 ? kWaves * (KS - 1) * 16 : 1];
     const int wv = uniform_i32(threadIdx.x >> 6);
     const int it = uniform_i32(R.item_lo + xcd_block(blockIdx.x, gridDim.x) * kWaves + wv);
     if (it >= G.nitems) return;
-    m64_item<KS, SLOT, MODE>(G, R, delta, it);
+    m64_item<KS, SLOT, MODE>(G, R, delta, it, KS > 4 ? tqbuf + wv * (KS > 4 ? KS - 1 : 1) * 16 : nullptr);
 }
 
 // --------------------------------------------------------------------- V64 --
@@ -709,6 +803,8 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
     const double eps2 = G.eps2;
     const double *__restrict__ xs = G.xs;
     const ItemRanges rg = load_ranges(G, it, lane);
+    // short-circuit interval in dimensions (0 = off): every 4 by default
+    const int cd = (MODE == MODE_MEASURE || d <= 4 || G.sc == -1) ? 0 : 4 * (G.sc > 0 ? G.sc : 1);
 
     bool rowok[4], emit_r[4];
     int qrow[4];
@@ -759,7 +855,23 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
     auto run1 = [&](const V64Tile<D> &T, int k) {
         unsigned long long w[4];
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        // Every pair's chain runs over the dimensions in order. Each step adds
+        // a non-negative square with round-to-nearest, so the chain never
+        // decreases: once every value of the tile is above eps^2 (checked
+        // every cd dimensions) the tile is out, exactly (Section III-B's
+        // short-circuit, with no margin needed); its values stay above eps^2,
+        // so the classification below gives zero bits.
+        auto all_far = [&]() -> bool {
+            bool far = true;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) far = far && (!rowok[r] || acc[r] > eps2);
+            return __ballot(!(far || j >= T.n)) == 0ull;
+        };
         if (D > 0) {
+            // d <= 8: the query rows sit in registers and the chain runs
+            // without checks (a check after 4 dimensions needs more
+            // registers than it saves: one wave fewer per SIMD, slower even
+            // where half the tiles could leave early)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -768,12 +880,8 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
                     acc[r] = __fma_rn(dl, dl, acc[r]);
                 }
         } else {
-            // Every pair's chain runs over the dimensions in order. Each step
-            // adds a non-negative square with round-to-nearest, so the chain
-            // never decreases: once every value of the tile is above eps^2
-            // (checked every 16 dimensions) the tile is out, exactly
-            // (Section IV's short-circuit, with no margin needed).
             const double *__restrict__ b = xs + (int64_t)T.c * dp;
+            int next_ck = cd > 0 ? cd : d + 1;  // dimensions after which the next check runs
             auto chain = [&](auto from_lds) {
                 for (int u0 = 0; u0 < d; u0 += 16) {
                     // the block's 16 candidate values of the lane's column
@@ -815,14 +923,12 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
                                 acc[r] = __fma_rn(dl, dl, acc[r]);
                             }
                         }
-                    }
-                    if (u0 + 16 < d) {
-                        bool far = true;
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) far = far && (!rowok[r] || acc[r] > eps2);
-                        if (__ballot(!(far || j >= T.n)) == 0ull) {
-                            ++npruned;
-                            return;
+                        if (u + 1 == next_ck) {  // wave-uniform
+                            next_ck += cd;
+                            if (u + 1 < d && all_far()) {
+                                ++npruned;
+                                return;
+                            }
                         }
                     }
                 }
@@ -1155,17 +1261,17 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BProb *__restrict__ pr
         const int it = uniform_i32(gi - (int)item_base[p]);
         if (PATHV == SJ_FP64_MFMA) {
             switch (P.ks * 2 + P.slot) {
-                case 3: m64_item<1, true, MODE>(P.G, R, P.delta, it); break;
-                case 2: m64_item<1, false, MODE>(P.G, R, P.delta, it); break;
-                case 5: m64_item<2, true, MODE>(P.G, R, P.delta, it); break;
-                case 4: m64_item<2, false, MODE>(P.G, R, P.delta, it); break;
-                case 7: m64_item<3, true, MODE>(P.G, R, P.delta, it); break;
-                case 6: m64_item<3, false, MODE>(P.G, R, P.delta, it); break;
-                case 9: m64_item<4, true, MODE>(P.G, R, P.delta, it); break;
-                case 8: m64_item<4, false, MODE>(P.G, R, P.delta, it); break;
+                case 3: m64_item<1, true, MODE>(P.G, R, P.delta, it, nullptr); break;
+                case 2: m64_item<1, false, MODE>(P.G, R, P.delta, it, nullptr); break;
+                case 5: m64_item<2, true, MODE>(P.G, R, P.delta, it, nullptr); break;
+                case 4: m64_item<2, false, MODE>(P.G, R, P.delta, it, nullptr); break;
+                case 7: m64_item<3, true, MODE>(P.G, R, P.delta, it, nullptr); break;
+                case 6: m64_item<3, false, MODE>(P.G, R, P.delta, it, nullptr); break;
+                case 9: m64_item<4, true, MODE>(P.G, R, P.delta, it, nullptr); break;
+                case 8: m64_item<4, false, MODE>(P.G, R, P.delta, it, nullptr); break;
                 default:
-                    if (P.slot) m64_item<0, true, MODE>(P.G, R, P.delta, it);
-                    else m64_item<0, false, MODE>(P.G, R, P.delta, it);
+                    if (P.slot) m64_item<0, true, MODE>(P.G, R, P.delta, it, nullptr);
+                    else m64_item<0, false, MODE>(P.G, R, P.delta, it, nullptr);
                     break;
             }
         } else {
@@ -1232,6 +1338,8 @@ DevGrid dev_grid(const Grid &g) {
     G.da = g.da;
     G.nranges = g.nranges;
     G.nitems = (int32_t)g.items;
+    G.npc = g.npc;
+    G.sc = g.npc > 0 ? g.sc : -1;
     G.eps2 = g.eps2;
     G.tile_off = g.tile_off;
     return G;

@@ -31,10 +31,10 @@ def _oracle_full(X, eps):
     return cnt, pp, pairs, d2, cref, k
 
 
-def _check_against_oracle(X, eps, path, tag, capacity=None):
-    log(f"[parity] {tag} path={path} n={X.shape[0]} d={X.shape[1]} eps={eps}")
+def _check_against_oracle(X, eps, path, tag, capacity=None, **build):
+    log(f"[parity] {tag} path={path} n={X.shape[0]} d={X.shape[1]} eps={eps} {build}")
     cnt, pp, pairs, d2, cref, k = _oracle_full(X, eps)
-    g = gpu_join(X, eps, path, want_pairs=True, want_d2=True, capacity=capacity)
+    g = gpu_join(X, eps, path, want_pairs=True, want_d2=True, capacity=capacity, **build)
     assert g["total"] == cnt, (g["total"], cnt)
     assert np.array_equal(g["per_point"], pp)
     assert g["info"]["cand_ref"] == cref
@@ -179,25 +179,36 @@ def test_parity_high_dimensions(path, d):
     _check_against_oracle(X, eps, path, f"gmm-{d}d")
 
 
+SC_CASES = [(0, 0), (1, 0), (2, 0), (0, 1), (-1, 0)]
+
+
 @pytest.mark.parametrize("path", ["fp64_mfma", "fp64_valu"])
-@pytest.mark.parametrize("d", [16, 24, 64])
-def test_short_circuit_drops_tiles_and_keeps_results(path, d):
-    """Section IV's short-circuit on clustered data, where most candidate
-    tiles of the 4-D grid neighbourhood belong to other clusters: past 16
-    dimensions the FP64 paths leave such tiles early (MFMA after its first
-    16 dimensions against eps^2 + Delta, VALU every 16 dimensions against
-    eps^2). Pair sets, counts and distances stay identical to the oracle's;
-    with d <= 16 nothing is left early."""
-    X = gen.gaussian_mixture(6000, d, clusters=40, seed=300 + d)
+@pytest.mark.parametrize("d", [8, 16, 24, 64])
+@pytest.mark.parametrize("sc,order", SC_CASES)
+def test_short_circuit_drops_tiles_and_keeps_results(path, d, sc, order):
+    """Section III-B's short-circuit on clustered data (many clusters, so that
+    the 4-D grid neighbourhood of a query holds tiles of other clusters):
+    tiles whose every partial distance is already beyond the threshold are
+    left early (MFMA against eps^2 + Delta at K-step boundaries, VALU against
+    eps^2 every 4 dimensions), for every schedule (sj_opts.short_circuit: 0 =
+    the library's, k = every k K-steps, -1 = off) and dimension order
+    (sj_opts.dim_order). Pair sets, counts and distances stay identical to
+    the oracle's."""
+    X = gen.gaussian_mixture(6000, d, clusters=300, seed=300 + d)
     eps = _eps_for(X, 20)
-    g = _check_against_oracle(X, eps, path, f"short-circuit-{d}d")
+    g = _check_against_oracle(X, eps, path, f"short-circuit-{d}d", short_circuit=sc, dim_order=order)
     tiles = g["stats"]["cand_eval"] / 256.0
     frac = g["stats"]["tiles_pruned"] / tiles
-    log(f"[short-circuit] d={d} path={path} tiles~{tiles:.0f} left early {frac:.3f}")
-    if d <= 16:
+    log(f"[short-circuit] d={d} path={path} sc={sc} order={order} tiles~{tiles:.0f} left early {frac:.3f}")
+    # test points: MFMA after K-step KS / 2 for KS <= 4, else every sc (default
+    # 4) K-steps; VALU (d > 8) every 4 sc (default 4) dimensions
+    every = sc if sc > 0 else (1 if path == "fp64_valu" else 4)
+    ks = d // 4
+    has_check = sc != -1 and (d > 8 and 4 * every < d if path == "fp64_valu" else (ks <= 4 or every < ks))
+    if not has_check:
         assert g["stats"]["tiles_pruned"] == 0
     else:
-        assert frac > 0.1
+        assert g["stats"]["tiles_pruned"] > 0
 
 
 @pytest.mark.parametrize("path", PATHS)
