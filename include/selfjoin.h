@@ -304,22 +304,35 @@ sj_status selfjoin_count_noalloc(const double *points, int64_t n, int32_t d, dou
                                  int32_t *per_point, int64_t *total, void *stream);
 
 /* ---- Batched form: B independent self-joins of uneven n and d ----------
- * All problems' work items are refined by one persistent work-queue kernel
- * that takes the costliest items first; the count pipeline (queue reset,
- * persistent kernel, per-problem prefix sums) is captured into a HIP graph
- * on first use and replayed afterwards. FP64 paths only (SJ_FP64_MFMA,
- * SJ_FP64_VALU); other paths return SJ_ERR_UNSUPPORTED. */
+ * The work items of all problems sit in one queue, grouped by d (one tile
+ * form each) and ordered by descending cost within a group. The count
+ * pipeline (counter reset, one tile kernel per form, per-problem prefix sums)
+ * and the pairs launch are each captured into a HIP graph on first use and
+ * replayed. The count pass records every problem's in-masks (up to 64 GiB;
+ * beyond, the pairs launch re-runs the tiles), so the pairs launch is one
+ * kernel that expands them. With opts->tune, the tuner picks per d the
+ * index_dims and the short-circuit setting (timing the FP64 MFMA count on the
+ * largest problem of that d; cached in tune_cache), and on the first count
+ * the schedule of the tile kernels: persistent grids of the resident waves
+ * dealing the items round-robin, or one wave per item. Every choice is
+ * result-neutral. FP64 paths only (SJ_FP64_MFMA, SJ_FP64_VALU); other paths
+ * return SJ_ERR_UNSUPPORTED. */
 typedef struct sj_batch sj_batch;
 
 /* points : host array of B device pointers, problem i is n[i] x d[i]
  *          row-major FP64 (validated like selfjoin_build_grid).
- * n, d, eps : host arrays of B entries. opts: index_dims / tune / tune_cache.
+ * n, d, eps : host arrays of B entries. opts: index_dims / short_circuit /
+ *          dim_order (every problem) or tune / tune_cache; the allocator hook
+ *          is not used by the batched form.
  * out    : host; receives the handle (release with selfjoin_batch_free). */
 sj_status selfjoin_batch_build(int32_t B, const double *const *points, const int64_t *n,
                                const int32_t *d, const double *eps, const sj_opts *opts,
                                void *stream, sj_batch **out);
 
-/* totals : host int64[B], |R| of each problem. */
+/* totals : host int64[B], |R| of each problem. stats (nullable): ms =
+ * ms_refine = device time of the count graph; ms_build = wall time of
+ * selfjoin_batch_build (grid builds, queue, in-mask buffer); cand_eval,
+ * rechecked, tiles_pruned over all problems; cand_ref = -1. */
 sj_status selfjoin_batch_count(sj_batch *b, sj_path path, int64_t *totals, sj_stats *stats,
                                void *stream);
 

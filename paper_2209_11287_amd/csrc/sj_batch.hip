@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -20,14 +21,15 @@ namespace sj {
 
 namespace {
 
-// Cost of each work item, as a descending sort key: candidates x queries x
-// K-steps; value = global item index.
+// Sort key of each work item: its problem's d in the high bits (items of one
+// tile form together), then descending cost (candidate tiles x K-steps);
+// value = global item index.
 __global__ void k_item_cost(const Item *__restrict__ items, const Range *__restrict__ ranges, int nitems,
-                            int nranges, int ksteps, int64_t base, unsigned long long *__restrict__ key,
+                            int nranges, int ksteps, int d, int64_t base, unsigned long long *__restrict__ key,
                             int32_t *__restrict__ val) {
     const int it = blockIdx.x * blockDim.x + threadIdx.x;
     if (it >= nitems) return;
-    const Item I = items[it];
+    (void)items;
     unsigned long long c = 0;
     for (int o = 0; o < nranges; ++o) {
         const Range r = ranges[(int64_t)it * nranges + o];
@@ -35,13 +37,15 @@ __global__ void k_item_cost(const Item *__restrict__ items, const Range *__restr
     }
     c *= (unsigned long long)(ksteps > 0 ? ksteps : 1);
     const unsigned long long cap = 0xffffffffull;
-    key[base + it] = cap - (c < cap ? c : cap);
+    key[base + it] = ((unsigned long long)d << 32) | (cap - (c < cap ? c : cap));
     val[base + it] = (int32_t)(base + it);
 }
 
+// Tuned choices, per path, d and size class: index_dims and the
+// short-circuit setting (sj_opts.short_circuit).
 struct TuneCache {
     std::mutex mu;
-    std::map<std::string, int> k;  // "path/d/log2n" -> index_dims
+    std::map<std::string, int> v;
 };
 TuneCache g_tune;
 
@@ -58,7 +62,7 @@ void tune_load(const char *path) {
     char key[128];
     int v;
     // one "key value" pair per line
-    while (std::fscanf(f, "%127s %d", key, &v) == 2) g_tune.k[key] = v;
+    while (std::fscanf(f, "%127s %d", key, &v) == 2) g_tune.v[key] = v;
     std::fclose(f);
 }
 
@@ -66,40 +70,54 @@ void tune_save(const char *path) {
     if (!path) return;
     FILE *f = std::fopen(path, "w");
     if (!f) return;
-    for (auto &kv : g_tune.k) std::fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
+    for (auto &kv : g_tune.v) std::fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
     std::fclose(f);
 }
 
-// Times the FP64 MFMA count kernel on one problem for k = 1..min(d, 4) and
-// returns the fastest k (result-neutral).
-int tune_index_dims(const double *pts, int64_t n, int d, double eps, hipStream_t s) {
+// Device time of the FP64 MFMA count kernel on one problem built with
+// (index_dims, short_circuit); the second of two runs.
+float time_count(const double *pts, int64_t n, int d, double eps, int k, int sc, hipStream_t s) {
+    Grid g;
+    g.sc = sc;
+    float ms = 0.f;
+    try {
+        build_grid(g, pts, n, d, eps, k, s);
+        int32_t *cnt = dev_alloc_n<int32_t>((size_t)n + 1, s);
+        RefineOut ro;
+        ro.timed = true;
+        ro.ctr = dev_alloc_n<DevCounters>(1, s);
+        refine_count(g, SJ_FP64_MFMA, cnt, ro, s);  // warm
+        ro.kt.ms();
+        refine_count(g, SJ_FP64_MFMA, cnt, ro, s);
+        ms = ro.kt.ms();
+        dev_free(cnt, s);
+        dev_free(ro.ctr, s);
+    } catch (...) {
+        free_grid(g, s);
+        throw;
+    }
+    free_grid(g, s);
+    return ms;
+}
+
+// The tile choices of one d, timed on one problem (result-neutral): first
+// index_dims = 1 .. min(d, 4) (cell geometry, so which candidates share a
+// tile), then, for d > 4, the short-circuit on (the library's schedule) or
+// off.
+void tune_problem(const double *pts, int64_t n, int d, double eps, hipStream_t s, int *k_out, int *sc_out) {
     int best_k = std::min(d, kMaxIndexDims);
     float best = 1e30f;
     for (int k = 1; k <= std::min(d, kMaxIndexDims); ++k) {
-        Grid g;
-        try {
-            build_grid(g, pts, n, d, eps, k, s);
-            int32_t *cnt = dev_alloc_n<int32_t>((size_t)n + 1, s);
-            RefineOut ro;
-            ro.timed = true;
-            ro.ctr = dev_alloc_n<DevCounters>(1, s);
-            refine_count(g, SJ_FP64_MFMA, cnt, ro, s);  // warm
-            ro.kt.ms();
-            refine_count(g, SJ_FP64_MFMA, cnt, ro, s);
-            const float ms = ro.kt.ms();
-            dev_free(cnt, s);
-            dev_free(ro.ctr, s);
-            if (ms < best) {
-                best = ms;
-                best_k = k;
-            }
-        } catch (...) {
-            free_grid(g, s);
-            throw;
+        const float ms = time_count(pts, n, d, eps, k, 0, s);
+        if (ms < best) {
+            best = ms;
+            best_k = k;
         }
-        free_grid(g, s);
     }
-    return best_k;
+    int best_sc = 0;
+    if (d > 4 && time_count(pts, n, d, eps, best_k, -1, s) < best) best_sc = -1;
+    *k_out = best_k;
+    *sc_out = best_sc;
 }
 
 }  // namespace
@@ -107,26 +125,42 @@ int tune_index_dims(const double *pts, int64_t n, int d, double eps, hipStream_t
 struct Batch {
     int B = 0;
     std::vector<Grid *> grids;
-    std::vector<int> kdims;
+    std::vector<int> kdims, scs;
     int64_t total_items = 0;
     std::vector<int64_t> item_base;       // B + 1
     int64_t *item_base_dev = nullptr;     // B + 1
-    int32_t *queue = nullptr;             // global item indices, longest first
-    int *counter = nullptr;
+    int32_t *queue = nullptr;             // global item indices: by d, longest first
+    std::vector<BatchForm> forms;         // one per distinct d
+    int sched = 0;                        // 0 = persistent grids, 1 = one wave per item
+    bool tune_sched = false;              // choose sched on the first count (timed, or from the cache)
+    std::string sched_key, tune_cache;    // the choice's cache key (batch shape) and file
     DevCounters *ctr = nullptr;
     BProb *probs_dev = nullptr;
     std::vector<BProb> probs;
     int64_t *totals_dev = nullptr;
     std::vector<int64_t> totals;
+    unsigned long long *masks = nullptr;  // every problem's in-masks (or null: pairs re-run the tiles)
+    bool masks_valid = false;
     bool counted = false;
-    // count pipeline graphs, per path
+    double ms_build = 0;                  // wall time of the grid builds and the queue
+    // graphs per path: the count pipeline, and the pairs launch (per output buffer)
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     hipStream_t graph_stream[2] = {nullptr, nullptr};
+    int graph_sched[2] = {-1, -1};
+    hipGraphExec_t pexec[2] = {nullptr, nullptr};
+    hipStream_t pgraph_stream[2] = {nullptr, nullptr};
+    int32_t *pgraph_pairs[2] = {nullptr, nullptr};
+    bool pgraph_masks[2] = {false, false};
 };
 
+constexpr int64_t kBatchMaskBudget = int64_t(64) << 30;  // largest in-mask buffer of a batch (bytes)
+
 void batch_free(Batch &b, hipStream_t s) {
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i) {
         if (b.exec[i]) (void)hipGraphExecDestroy(b.exec[i]);
+        if (b.pexec[i]) (void)hipGraphExecDestroy(b.pexec[i]);
+        b.exec[i] = b.pexec[i] = nullptr;
+    }
     for (Grid *g : b.grids) {
         if (!g) continue;
         if (g->cnt) {
@@ -141,16 +175,24 @@ void batch_free(Batch &b, hipStream_t s) {
         delete g;
     }
     b.grids.clear();
-    void *bufs[] = {b.item_base_dev, b.queue, b.counter, b.ctr, b.probs_dev, b.totals_dev};
+    void *bufs[] = {b.item_base_dev, b.queue, b.ctr, b.probs_dev, b.totals_dev, b.masks};
     for (void *p : bufs)
         if (p) dev_free(p, s);
+    b.item_base_dev = nullptr;
+    b.queue = nullptr;
+    b.ctr = nullptr;
+    b.probs_dev = nullptr;
+    b.totals_dev = nullptr;
+    b.masks = nullptr;
 }
 
 void batch_build(Batch &b, int B, const double *const *points, const int64_t *n, const int32_t *d, const double *eps,
                  const sj_opts *opts, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
     b.B = B;
     b.grids.assign(B, nullptr);
     b.kdims.assign(B, 0);
+    b.scs.assign(B, 0);
     const bool tune = opts && opts->tune;
     if (tune) {
         std::lock_guard<std::mutex> lk(g_tune.mu);
@@ -162,48 +204,94 @@ void batch_build(Batch &b, int B, const double *const *points, const int64_t *n,
         for (auto &kv : rep) {
             const int i = kv.second;
             const std::string key = tune_key(SJ_FP64_MFMA, d[i], n[i]);
-            if (!g_tune.k.count(key)) g_tune.k[key] = tune_index_dims(points[i], n[i], d[i], eps[i], s);
+            if (!g_tune.v.count(key + "/k") || !g_tune.v.count(key + "/sc")) {
+                int k = 0, sc = 0;
+                tune_problem(points[i], n[i], d[i], eps[i], s, &k, &sc);
+                g_tune.v[key + "/k"] = k;
+                g_tune.v[key + "/sc"] = sc;
+            }
         }
         tune_save(opts->tune_cache);
         for (int i = 0; i < B; ++i) {
-            auto it = g_tune.k.find(tune_key(SJ_FP64_MFMA, d[i], n[rep.count(d[i]) ? rep[d[i]] : i]));
-            b.kdims[i] = it != g_tune.k.end() ? it->second : 0;
+            const std::string key = tune_key(SJ_FP64_MFMA, d[i], n[rep.count(d[i]) ? rep[d[i]] : i]);
+            auto ik = g_tune.v.find(key + "/k");
+            auto is = g_tune.v.find(key + "/sc");
+            b.kdims[i] = ik != g_tune.v.end() ? ik->second : 0;
+            b.scs[i] = is != g_tune.v.end() ? is->second : 0;
         }
+        b.tune_sched = true;
+        if (opts->tune_cache) b.tune_cache = opts->tune_cache;
     } else if (opts) {
-        for (int i = 0; i < B; ++i) b.kdims[i] = opts->index_dims;
+        for (int i = 0; i < B; ++i) {
+            b.kdims[i] = opts->index_dims;
+            b.scs[i] = opts->short_circuit;
+        }
     }
     b.item_base.assign(B + 1, 0);
+    int64_t mask_tiles = 0;
+    std::vector<int64_t> tile_base(B + 1, 0);
     for (int i = 0; i < B; ++i) {
         b.grids[i] = new Grid();
-        build_grid(*b.grids[i], points[i], n[i], d[i], eps[i], b.kdims[i], s);
         Grid &g = *b.grids[i];
+        g.sc = b.scs[i];
+        if (opts) g.dim_order = opts->dim_order;
+        build_grid(g, points[i], n[i], d[i], eps[i], b.kdims[i], s);
         g.cnt = dev_alloc_n<int32_t>((size_t)g.n + 1, s);
         g.off = dev_alloc_n<int64_t>((size_t)g.n + 1, s);
         b.item_base[i + 1] = b.item_base[i] + g.items;
+        tile_base[i] = mask_tiles;
+        mask_tiles += g.tiles;
     }
     b.total_items = b.item_base[B];
     if (b.total_items >= (int64_t(1) << 31)) throw std::string("too many work items in one batch");
+    b.sched_key = "sched/" + std::to_string(B) + "/" + std::to_string(b.total_items);
     b.item_base_dev = dev_alloc_n<int64_t>(B + 1, s);
     SJ_HIP(hipMemcpyAsync(b.item_base_dev, b.item_base.data(), (B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    // longest-first queue
+    // the queue: items grouped by d, longest first within a group
     const int64_t T = std::max<int64_t>(1, b.total_items);
     unsigned long long *ka = dev_alloc_n<unsigned long long>(T, s), *kb = dev_alloc_n<unsigned long long>(T, s);
     int32_t *va = dev_alloc_n<int32_t>(T, s), *vb = dev_alloc_n<int32_t>(T, s);
+    int maxd = 1;
+    std::map<int, int64_t> per_d;
     for (int i = 0; i < B; ++i) {
         const Grid &g = *b.grids[i];
+        maxd = std::max(maxd, g.d);
         if (g.items == 0) continue;
+        per_d[g.d] += g.items;
         hipLaunchKernelGGL(k_item_cost, dim3((unsigned)((g.items + 255) / 256)), dim3(256), 0, s, g.item, g.ranges,
-                           (int)g.items, g.nranges, g.da >> 2, b.item_base[i], ka, va);
+                           (int)g.items, g.nranges, g.da >> 2, g.d, b.item_base[i], ka, va);
         SJ_HIP(hipGetLastError());
     }
+    int dbits = 0;
+    while ((1 << dbits) <= maxd) ++dbits;
     unsigned long long *k_sorted = ka;
     int32_t *v_sorted = va;
-    radix_sort_pairs(&k_sorted, &v_sorted, k_sorted == ka ? kb : ka, v_sorted == va ? vb : va, b.total_items, 32, s);
+    radix_sort_pairs(&k_sorted, &v_sorted, k_sorted == ka ? kb : ka, v_sorted == va ? vb : va, b.total_items,
+                     32 + dbits, s);
     b.queue = v_sorted;
     dev_free(v_sorted == va ? vb : va, s);
     dev_free(ka, s);
     dev_free(kb, s);
-    b.counter = dev_alloc_n<int>(1, s);
+    b.forms.clear();
+    int64_t pos = 0;
+    for (auto &kv : per_d) {  // ascending d, the key order
+        BatchForm f;
+        f.d = kv.first;
+        f.lo = (int32_t)pos;
+        f.hi = (int32_t)(pos + kv.second);
+        f.sched = 0;
+        b.forms.push_back(f);
+        pos += kv.second;
+    }
+    // in-masks of every problem (32 bytes per tile slot): the pairs pass then
+    // expands them instead of re-running the tiles
+    if (mask_tiles > 0 && mask_tiles * 32 <= kBatchMaskBudget) {
+        try {
+            b.masks = dev_alloc_n<unsigned long long>((size_t)mask_tiles * 4, s);
+        } catch (const OomError &) {
+            b.masks = nullptr;
+        }
+    }
     b.ctr = dev_alloc_n<DevCounters>(1, s);
     b.totals_dev = dev_alloc_n<int64_t>(B, s);
     b.probs.resize(B);
@@ -212,67 +300,129 @@ void batch_build(Batch &b, int B, const double *const *points, const int64_t *n,
         BProb &p = b.probs[i];
         p.G = make_dev_grid(g);
         p.delta = fp64_mfma_delta(g);
-        p.ks = g.da >> 2;
-        p.slot = (g.d & 3) ? 1 : 0;
         p.cnt = g.cnt;
         p.off = g.off;
         p.pout = 0;
+        p.masks = b.masks ? b.masks + 4 * tile_base[i] : nullptr;
     }
     b.probs_dev = dev_alloc_n<BProb>(B, s);
     SJ_HIP(hipMemcpyAsync(b.probs_dev, b.probs.data(), B * sizeof(BProb), hipMemcpyHostToDevice, s));
     SJ_HIP(hipStreamSynchronize(s));
     b.totals.assign(B, 0);
+    b.ms_build = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
-// Count pipeline: captured into a graph on first use per (path, stream), then
-// replayed. The graph holds only kernel nodes (no memset or copy nodes).
-float batch_count(Batch &b, sj_path path, hipStream_t s, HostCounters *hc) {
+// Captures `enqueue` (kernel nodes only: no memset or copy nodes) on the
+// stream s (a private stream for the legacy null stream, which cannot be
+// captured) into an executable graph.
+template <typename F>
+hipGraphExec_t capture(hipStream_t s, F enqueue) {
+    hipStream_t cs = s;
+    bool own = false;
+    if (!cs) {
+        SJ_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        own = true;
+    }
+    hipGraph_t graph;
+    hipGraphExec_t exec = nullptr;
+    SJ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    try {
+        enqueue(cs);
+    } catch (...) {
+        (void)hipStreamEndCapture(cs, &graph);
+        if (own) (void)hipStreamDestroy(cs);
+        throw;
+    }
+    SJ_HIP(hipStreamEndCapture(cs, &graph));
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (own) SJ_HIP(hipStreamDestroy(cs));
+    SJ_HIP(e);
+    return exec;
+}
+
+void set_sched(Batch &b, int sched) {
+    for (BatchForm &f : b.forms) f.sched = sched;
+    b.sched = sched;
+}
+
+// Count pipeline: counter reset, one kernel per tile form (recording the
+// in-masks when the batch holds them), per-problem prefix sums; captured on
+// first use per (path, stream, schedule) and replayed.
+float batch_count_graph(Batch &b, sj_path path, hipStream_t s) {
     const int pi = path == SJ_FP64_MFMA ? 1 : 0;
+    if (!b.exec[pi] || b.graph_stream[pi] != s || b.graph_sched[pi] != b.sched) {
+        if (b.exec[pi]) (void)hipGraphExecDestroy(b.exec[pi]);
+        b.exec[pi] = nullptr;
+        b.exec[pi] = capture(s, [&](hipStream_t cs) {
+            batch_reset(b.ctr, cs);
+            for (const BatchForm &f : b.forms)
+                launch_batch_form(false, f, path, b.probs_dev, b.item_base_dev, b.B, b.queue, nullptr, b.ctr, cs);
+            launch_seg_scan(b.probs_dev, b.B, b.totals_dev, cs);
+        });
+        b.graph_stream[pi] = s;
+        b.graph_sched[pi] = b.sched;
+    }
     hipEvent_t e0, e1;
     SJ_HIP(hipEventCreate(&e0));
     SJ_HIP(hipEventCreate(&e1));
-    if (!b.exec[pi] || b.graph_stream[pi] != s) {
-        if (b.exec[pi]) (void)hipGraphExecDestroy(b.exec[pi]);
-        b.exec[pi] = nullptr;
-        hipStream_t cs = s;
-        bool own = false;
-        if (!cs) {  // the legacy null stream cannot be captured: capture on a private stream
-            SJ_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-            own = true;
-        }
-        hipGraph_t graph;
-        SJ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        launch_batch(false, path, b.probs_dev, b.item_base_dev, b.B, b.queue, (int)b.total_items, b.counter, nullptr,
-                     b.ctr, cs);
-        launch_seg_scan(b.probs_dev, b.B, b.totals_dev, cs);
-        SJ_HIP(hipStreamEndCapture(cs, &graph));
-        SJ_HIP(hipGraphInstantiate(&b.exec[pi], graph, nullptr, nullptr, 0));
-        (void)hipGraphDestroy(graph);
-        if (own) SJ_HIP(hipStreamDestroy(cs));
-        b.graph_stream[pi] = s;
-    }
     SJ_HIP(hipEventRecord(e0, s));
     SJ_HIP(hipGraphLaunch(b.exec[pi], s));
     SJ_HIP(hipEventRecord(e1, s));
-    DevCounters hb{};
-    SJ_HIP(hipMemcpyAsync(b.totals.data(), b.totals_dev, b.B * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    SJ_HIP(hipMemcpyAsync(&hb, b.ctr, sizeof hb, hipMemcpyDeviceToHost, s));
-    SJ_HIP(hipStreamSynchronize(s));
+    SJ_HIP(hipEventSynchronize(e1));
     float ms = 0;
     SJ_HIP(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    return ms;
+}
+
+float batch_count(Batch &b, sj_path path, hipStream_t s, HostCounters *hc) {
+    if (b.tune_sched) {
+        // the schedule (persistent grids or one wave per item): both timed
+        // once after a warm run, the faster kept (and cached by batch shape)
+        b.tune_sched = false;
+        std::lock_guard<std::mutex> lk(g_tune.mu);
+        const std::string key = b.sched_key + "/" + std::to_string((int)path);
+        auto it = g_tune.v.find(key);
+        if (it != g_tune.v.end()) {
+            set_sched(b, it->second);
+        } else {
+            float best = 1e30f;
+            int best_s = 0;
+            for (int sc = 0; sc < 2; ++sc) {
+                set_sched(b, sc);
+                batch_count_graph(b, path, s);
+                const float ms = batch_count_graph(b, path, s);
+                if (ms < best) {
+                    best = ms;
+                    best_s = sc;
+                }
+            }
+            set_sched(b, best_s);
+            g_tune.v[key] = best_s;
+            tune_save(b.tune_cache.empty() ? nullptr : b.tune_cache.c_str());
+        }
+    }
+    const float ms = batch_count_graph(b, path, s);
+    DevCounters hb{};
+    SJ_HIP(hipMemcpyAsync(b.totals.data(), b.totals_dev, b.B * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipMemcpyAsync(&hb, b.ctr, sizeof hb, hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
     *hc = read_counters(hb);
     for (int i = 0; i < b.B; ++i) {
         b.grids[i]->total = b.totals[i];
         b.grids[i]->have_counts = true;
     }
     b.counted = true;
+    b.masks_valid = b.masks != nullptr;
     return ms;
 }
 
 // Emission of every problem's pairs into one buffer: problem i's rows at
-// [offsets[i], offsets[i + 1]).
+// [offsets[i], offsets[i + 1]). From the recorded in-masks when the batch
+// holds them (one launch over all items), else the tiles re-run in emission
+// form (one launch per tile form). Captured per (path, stream, buffer).
 float batch_pairs(Batch &b, sj_path path, int32_t *pairs, hipStream_t s) {
     int64_t off = 0;
     for (int i = 0; i < b.B; ++i) {
@@ -280,12 +430,28 @@ float batch_pairs(Batch &b, sj_path path, int32_t *pairs, hipStream_t s) {
         off += b.totals[i];
     }
     SJ_HIP(hipMemcpyAsync(b.probs_dev, b.probs.data(), b.B * sizeof(BProb), hipMemcpyHostToDevice, s));
+    const int pi = path == SJ_FP64_MFMA ? 1 : 0;
+    const bool use_masks = b.masks_valid;
+    if (!b.pexec[pi] || b.pgraph_stream[pi] != s || b.pgraph_pairs[pi] != pairs || b.pgraph_masks[pi] != use_masks) {
+        if (b.pexec[pi]) (void)hipGraphExecDestroy(b.pexec[pi]);
+        b.pexec[pi] = nullptr;
+        b.pexec[pi] = capture(s, [&](hipStream_t cs) {
+            if (use_masks) {
+                launch_batch_emit(b.probs_dev, b.item_base_dev, b.B, b.queue, (int)b.total_items, 1, pairs, cs);
+            } else {
+                for (const BatchForm &f : b.forms)
+                    launch_batch_form(true, f, path, b.probs_dev, b.item_base_dev, b.B, b.queue, pairs, b.ctr, cs);
+            }
+        });
+        b.pgraph_stream[pi] = s;
+        b.pgraph_pairs[pi] = pairs;
+        b.pgraph_masks[pi] = use_masks;
+    }
     hipEvent_t e0, e1;
     SJ_HIP(hipEventCreate(&e0));
     SJ_HIP(hipEventCreate(&e1));
     SJ_HIP(hipEventRecord(e0, s));
-    launch_batch(true, path, b.probs_dev, b.item_base_dev, b.B, b.queue, (int)b.total_items, b.counter, pairs,
-                 b.ctr, s);
+    SJ_HIP(hipGraphLaunch(b.pexec[pi], s));
     SJ_HIP(hipEventRecord(e1, s));
     SJ_HIP(hipEventSynchronize(e1));
     float ms = 0;
@@ -347,6 +513,10 @@ sj_status selfjoin_batch_build(int32_t B, const double *const *points, const int
         set_error("index_dims must be in [0, 4]");
         return SJ_ERR_INVALID;
     }
+    if (opts && (opts->short_circuit < -1 || opts->short_circuit > 64 || opts->dim_order < 0 || opts->dim_order > 1)) {
+        set_error("short_circuit must be in [-1, 64] and dim_order 0 or 1");
+        return SJ_ERR_INVALID;
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     sj_batch *h = new sj_batch();
     SJB_TRY
@@ -391,6 +561,7 @@ sj_status selfjoin_batch_count(sj_batch *bh, sj_path path, int64_t *totals, sj_s
         stats->rechecked = hc.rechecked;
         stats->rechecked_in = hc.rechecked_in;
         stats->ms = ms;
+        stats->ms_build = b.ms_build;
         stats->ms_refine = ms;
         stats->tiles_pruned = hc.pruned;
         stats->path_run = (int32_t)path;

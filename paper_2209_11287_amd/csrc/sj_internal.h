@@ -131,14 +131,23 @@ struct DevGrid {
     const int64_t *tile_off;
 };
 
-// One problem of a batch, as the persistent kernel sees it.
+// One problem of a batch, as the batch kernels see it.
 struct BProb {
     DevGrid G;
     double delta;      // FP64 MFMA band half-width
-    int32_t ks, slot;  // FP64 MFMA K-steps and norm-slot form
     int32_t *cnt;      // per-query counts (sorted order), n + 1
     int64_t *off;      // exclusive prefix of cnt, n + 1
     int64_t pout;      // first output row of this problem
+    unsigned long long *masks;  // this problem's in-masks (recorded by the count pass), or null
+};
+
+// The items of the problems of one dimensionality d (one tile form): queue
+// positions [lo, hi), longest first. sched: 0 = a persistent grid of the
+// resident waves dealing them round-robin, 1 = one wave per item.
+struct BatchForm {
+    int32_t d;
+    int32_t lo, hi;
+    int32_t sched;
 };
 
 struct Grid {
@@ -291,9 +300,11 @@ void refine_measure(Grid &g, sj_path path, double *max_err, double *max_band, in
                     hipStream_t s);
 
 // Batched form (sj_refine.hip).
-void launch_batch(bool emit, sj_path path, const BProb *probs, const int64_t *item_base, int B,
-                  const int32_t *queue, int total, int *counter, int32_t *pairs, DevCounters *ctr,
-                  hipStream_t s);
+void batch_reset(DevCounters *ctr, hipStream_t s);
+void launch_batch_form(bool emit, const BatchForm &f, sj_path path, const BProb *probs, const int64_t *item_base,
+                       int B, const int32_t *queue, int32_t *pairs, DevCounters *ctr, hipStream_t s);
+void launch_batch_emit(const BProb *probs, const int64_t *item_base, int B, const int32_t *queue, int total,
+                       int sched, int32_t *pairs, hipStream_t s);
 void launch_seg_scan(const BProb *probs, int B, int64_t *totals, hipStream_t s);
 DevGrid make_dev_grid(const Grid &g);
 double fp64_mfma_delta(const Grid &g);

@@ -1219,71 +1219,92 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7, 8))
 }
 
 // ------------------------------------------------------------------ batch --
-// Persistent work-queue kernel over the work items of many independent
-// self-joins. Waves pop global item indices (ordered by descending cost: the
-// longest items start first) and run the same per-item tile code as the
-// single-problem kernels, with that problem's grid and outputs.
-template <int MODE, int PATHV>
-__global__ __launch_bounds__(kThreads) void k_batch(const BProb *__restrict__ probs,
-                                                    const int64_t *__restrict__ item_base, int B,
-                                                    const int32_t *__restrict__ queue, int total,
-                                                    int *__restrict__ counter, int32_t *__restrict__ pairs,
-                                                    DevCounters *__restrict__ ctr) {
-    __shared__ double vbuf[PATHV == SJ_FP64_VALU ? kWaves * 16 * kV64LdsD : 1];
-    double *vq = PATHV == SJ_FP64_VALU ? vbuf + (threadIdx.x >> 6) * 16 * kV64LdsD : nullptr;
-    __shared__ double cbuf[PATHV == SJ_FP64_VALU ? kWaves * 256 : 1];
-    double *vc = PATHV == SJ_FP64_VALU ? cbuf + (threadIdx.x >> 6) * 256 : nullptr;
-    const int lane = threadIdx.x & 63;
-    for (;;) {
-        int w = 0;
-        if (lane == 0) w = atomicAdd(counter, 1);
-        w = uniform_i32(__shfl(w, 0));
-        if (w >= total) break;
+// Work items of many independent self-joins. The queue holds global item
+// indices grouped by tile form (the problems' d) and, within a form, by
+// descending cost. One launch per form: wave w of W takes queue positions
+// lo + w, lo + w + W, ... (W = the waves the grid holds: either every wave
+// the GPU keeps resident, a persistent grid dealing the longest items first
+// round-robin, or one wave per item, the dispatcher handing out items in
+// queue order). Each item runs the single-problem tile code with its
+// problem's grid and outputs.
+__device__ __forceinline__ int batch_problem(const int64_t *__restrict__ item_base, int B, int gi) {
+    int lo = 0, hi = B;  // last problem p with item_base[p] <= gi
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (item_base[mid] <= gi) lo = mid;
+        else hi = mid;
+    }
+    return uniform_i32(lo);
+}
+
+__device__ __forceinline__ RefOut batch_out(const BProb &P, int32_t *pairs, DevCounters *ctr, int mode) {
+    RefOut R{};
+    R.cnt = P.cnt;
+    R.off = P.off;
+    R.base = 0;
+    R.qlo = 0;
+    R.qhi = (int32_t)P.G.n;
+    R.pairs = pairs ? pairs + 2 * P.pout : nullptr;
+    R.d2 = nullptr;
+    R.ctr = ctr;
+    R.item_lo = 0;
+    R.masks = mode == MODE_COUNT ? P.masks : nullptr;
+    return R;
+}
+
+template <int KS, bool SLOT, int MODE>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KS == 1 ? 6 : 4, 8))) void k_batch_m64(
+    const BProb *__restrict__ probs, const int64_t *__restrict__ item_base, int B, const int32_t *__restrict__ queue,
+    int lo, int hi, int32_t *__restrict__ pairs, DevCounters *__restrict__ ctr) {
+    __shared__ double tqbuf[KS > 4 ? kWaves * (KS - 1) * 16 : 1];
+    const int wv = uniform_i32(threadIdx.x >> 6);
+    const int W = gridDim.x * kWaves;
+    for (int w = lo + uniform_i32(blockIdx.x * kWaves + wv); w < hi; w += W) {
         const int gi = queue[w];
-        int lo = 0, hi = B;  // last problem p with item_base[p] <= gi
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (item_base[mid] <= gi) lo = mid;
-            else hi = mid;
-        }
-        const int p = uniform_i32(lo);
-        const BProb P = probs[p];
-        RefOut R{};
-        R.cnt = P.cnt;
-        R.off = P.off;
-        R.base = 0;
-        R.qlo = 0;
-        R.qhi = (int32_t)P.G.n;
-        R.pairs = pairs + 2 * P.pout;
-        R.d2 = nullptr;
-        R.ctr = ctr;
-        R.item_lo = 0;
+        const int p = batch_problem(item_base, B, gi);
+        const BProb &P = probs[p];
+        const RefOut R = batch_out(P, pairs, ctr, MODE);
         const int it = uniform_i32(gi - (int)item_base[p]);
-        if (PATHV == SJ_FP64_MFMA) {
-            switch (P.ks * 2 + P.slot) {
-                case 3: m64_item<1, true, MODE>(P.G, R, P.delta, it, nullptr); break;
-                case 2: m64_item<1, false, MODE>(P.G, R, P.delta, it, nullptr); break;
-                case 5: m64_item<2, true, MODE>(P.G, R, P.delta, it, nullptr); break;
-                case 4: m64_item<2, false, MODE>(P.G, R, P.delta, it, nullptr); break;
-                case 7: m64_item<3, true, MODE>(P.G, R, P.delta, it, nullptr); break;
-                case 6: m64_item<3, false, MODE>(P.G, R, P.delta, it, nullptr); break;
-                case 9: m64_item<4, true, MODE>(P.G, R, P.delta, it, nullptr); break;
-                case 8: m64_item<4, false, MODE>(P.G, R, P.delta, it, nullptr); break;
-                default:
-                    if (P.slot) m64_item<0, true, MODE>(P.G, R, P.delta, it, nullptr);
-                    else m64_item<0, false, MODE>(P.G, R, P.delta, it, nullptr);
-                    break;
-            }
-        } else {
-            switch (P.G.d) {
-                case 1: v64_item<1, MODE>(P.G, R, it, nullptr, nullptr); break;
-                case 2: v64_item<2, MODE>(P.G, R, it, nullptr, nullptr); break;
-                case 3: v64_item<3, MODE>(P.G, R, it, nullptr, nullptr); break;
-                case 4: v64_item<4, MODE>(P.G, R, it, nullptr, nullptr); break;
-                case 8: v64_item<8, MODE>(P.G, R, it, nullptr, nullptr); break;
-                default: v64_item<0, MODE>(P.G, R, it, vq, vc); break;
-            }
-        }
+        m64_item<KS, SLOT, MODE>(P.G, R, P.delta, it, KS > 4 ? tqbuf + wv * (KS > 4 ? KS - 1 : 1) * 16 : nullptr);
+    }
+}
+
+template <int D, int MODE>
+__global__ __launch_bounds__(kThreads) void k_batch_v64(const BProb *__restrict__ probs,
+                                                        const int64_t *__restrict__ item_base, int B,
+                                                        const int32_t *__restrict__ queue, int lo, int hi,
+                                                        int32_t *__restrict__ pairs, DevCounters *__restrict__ ctr) {
+    __shared__ double qbuf[D == 0 ? kWaves * 16 * kV64LdsD : 1];
+    __shared__ double cbuf[D == 0 ? kWaves * 256 : 1];
+    const int wv = uniform_i32(threadIdx.x >> 6);
+    const int W = gridDim.x * kWaves;
+    for (int w = lo + uniform_i32(blockIdx.x * kWaves + wv); w < hi; w += W) {
+        const int gi = queue[w];
+        const int p = batch_problem(item_base, B, gi);
+        const BProb &P = probs[p];
+        const RefOut R = batch_out(P, pairs, ctr, MODE);
+        const int it = uniform_i32(gi - (int)item_base[p]);
+        v64_item<D, MODE>(P.G, R, it, D == 0 ? qbuf + wv * 16 * kV64LdsD : nullptr,
+                          D == 0 ? cbuf + wv * 256 : nullptr);
+    }
+}
+
+// Pairs of every item from the in-masks its problem's count pass recorded
+// (no distance is recomputed), at the problem's output rows.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_batch_emit(
+    const BProb *__restrict__ probs, const int64_t *__restrict__ item_base, int B, const int32_t *__restrict__ queue,
+    int lo, int hi, int32_t *__restrict__ pairs) {
+    __shared__ int32_t stage[kWaves * 256];
+    __shared__ int32_t slot[kWaves * 4 * kSlot];
+    const int wv = uniform_i32(threadIdx.x >> 6);
+    const int W = gridDim.x * kWaves;
+    for (int w = lo + uniform_i32(blockIdx.x * kWaves + wv); w < hi; w += W) {
+        const int gi = queue[w];
+        const int p = batch_problem(item_base, B, gi);
+        const BProb &P = probs[p];
+        const RefOut R = batch_out(P, pairs, nullptr, MODE_EMIT);
+        const int it = uniform_i32(gi - (int)item_base[p]);
+        mask_item<false>(P.G, R, P.masks, it, stage + 256 * wv, slot + 4 * kSlot * wv);
     }
 }
 
@@ -1318,10 +1339,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_scan(const BProb *__restrict__
     if (tid == 0) totals[blockIdx.x] = carry;
 }
 
-__global__ void k_batch_reset(int *counter, DevCounters *ctr) {
-    *counter = 0;
-    *ctr = DevCounters{};
-}
+__global__ void k_batch_reset(DevCounters *ctr) { *ctr = DevCounters{}; }
 
 DevGrid dev_grid(const Grid &g) {
     DevGrid G;
@@ -1437,27 +1455,93 @@ void launch_m64(const Grid &g, const RefOut &R, int nitems, double delta, hipStr
 
 }  // namespace
 
-void launch_batch(bool emit, sj_path path, const BProb *probs, const int64_t *item_base, int B,
-                  const int32_t *queue, int total, int *counter, int32_t *pairs, DevCounters *ctr,
-                  hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, counter, ctr);
-    SJ_HIP(hipGetLastError());
-    if (total <= 0) return;
-    int dev = 0, ncu = 256;
-    SJ_HIP(hipGetDevice(&dev));
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    const unsigned blocks = (unsigned)std::min<int64_t>((total + kWaves - 1) / kWaves, (int64_t)ncu * 8);
-#define SJ_B(M, P) hipLaunchKernelGGL((k_batch<M, P>), dim3(blocks), dim3(kThreads), 0, s, probs, item_base, B, queue, \
-                                      total, counter, pairs, ctr)
-    if (path == SJ_FP64_MFMA) {
-        if (emit) SJ_B(MODE_EMIT, SJ_FP64_MFMA);
-        else SJ_B(MODE_COUNT, SJ_FP64_MFMA);
-    } else {
-        if (emit) SJ_B(MODE_EMIT, SJ_FP64_VALU);
-        else SJ_B(MODE_COUNT, SJ_FP64_VALU);
+// Launches of the batched form (see k_batch_m64): sched 0 = a persistent
+// grid of the waves the GPU keeps resident for this kernel, 1 = one wave per
+// item.
+template <typename... P, typename... A>
+static void batch_launch(void (*kernel)(P...), int n, int sched, hipStream_t s, A... args) {
+    if (n <= 0) return;
+    int want = n;
+    if (sched == 0) {
+        int dev = 0, ncu = 256, per_cu = 0;
+        SJ_HIP(hipGetDevice(&dev));
+        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kernel), kThreads, 0) !=
+                hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        want = std::min(n, ncu * per_cu * kWaves);
     }
-#undef SJ_B
+    const unsigned blocks = (unsigned)((want + kWaves - 1) / kWaves);
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kThreads), 0, s, args...);
     SJ_HIP(hipGetLastError());
+}
+
+void batch_reset(DevCounters *ctr, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, ctr);
+    SJ_HIP(hipGetLastError());
+}
+
+template <int MODE>
+static void batch_form_mode(const BatchForm &f, sj_path path, const BProb *probs, const int64_t *item_base, int B,
+                            const int32_t *queue, int32_t *pairs, DevCounters *ctr, hipStream_t s) {
+    const int n = f.hi - f.lo;
+    if (path == SJ_FP64_MFMA) {
+#define SJ_BM(KSV, SL)                                                                                   \
+    batch_launch(k_batch_m64<KSV, SL, MODE>, n, f.sched, s, probs, item_base, B, queue, f.lo, f.hi, pairs, \
+                 ctr)
+        const bool slot = (f.d & 3) != 0;
+        const int da = slot ? ((f.d + 1 + 3) & ~3) : f.d;
+        const int ks = da >> 2;
+        if (slot) {
+            switch (ks) {
+                case 1: SJ_BM(1, true); break;
+                case 2: SJ_BM(2, true); break;
+                case 3: SJ_BM(3, true); break;
+                case 4: SJ_BM(4, true); break;
+                default: SJ_BM(0, true); break;
+            }
+        } else {
+            switch (ks) {
+                case 1: SJ_BM(1, false); break;
+                case 2: SJ_BM(2, false); break;
+                case 3: SJ_BM(3, false); break;
+                case 4: SJ_BM(4, false); break;
+                case 6: SJ_BM(6, false); break;
+                case 8: SJ_BM(8, false); break;
+                case 12: SJ_BM(12, false); break;
+                case 16: SJ_BM(16, false); break;
+                default: SJ_BM(0, false); break;
+            }
+        }
+#undef SJ_BM
+    } else {
+#define SJ_BV(DD) \
+    batch_launch(k_batch_v64<DD, MODE>, n, f.sched, s, probs, item_base, B, queue, f.lo, f.hi, pairs, ctr)
+        switch (f.d) {
+            case 1: SJ_BV(1); break;
+            case 2: SJ_BV(2); break;
+            case 3: SJ_BV(3); break;
+            case 4: SJ_BV(4); break;
+            case 5: SJ_BV(5); break;
+            case 6: SJ_BV(6); break;
+            case 7: SJ_BV(7); break;
+            case 8: SJ_BV(8); break;
+            default: SJ_BV(0); break;
+        }
+#undef SJ_BV
+    }
+}
+
+void launch_batch_form(bool emit, const BatchForm &f, sj_path path, const BProb *probs, const int64_t *item_base,
+                       int B, const int32_t *queue, int32_t *pairs, DevCounters *ctr, hipStream_t s) {
+    if (emit) batch_form_mode<MODE_EMIT>(f, path, probs, item_base, B, queue, pairs, ctr, s);
+    else batch_form_mode<MODE_COUNT>(f, path, probs, item_base, B, queue, pairs, ctr, s);
+}
+
+void launch_batch_emit(const BProb *probs, const int64_t *item_base, int B, const int32_t *queue, int total,
+                       int sched, int32_t *pairs, hipStream_t s) {
+    batch_launch(k_batch_emit, total, sched, s, probs, item_base, B, queue, 0, total, pairs);
 }
 
 DevGrid make_dev_grid(const Grid &g) { return dev_grid(g); }

@@ -322,8 +322,10 @@ class BatchHandle:
 
 
 def selfjoin_batch_build(points_list, eps_list, index_dims: int = 0, tune: bool = False, tune_cache=None,
-                         stream=None) -> BatchHandle:
-    """points_list: list of CUDA float64 (n_i, d_i) tensors; eps_list: floats."""
+                         stream=None, short_circuit: int = 0, dim_order: int = 0) -> BatchHandle:
+    """points_list: list of CUDA float64 (n_i, d_i) tensors; eps_list: floats.
+    index_dims / short_circuit / dim_order: sj_opts fields (ignored for the
+    choices the tuner makes when tune is set)."""
     torch = _torch()
     pts = [p.contiguous() for p in points_list]
     B = len(pts)
@@ -339,6 +341,8 @@ def selfjoin_batch_build(points_list, eps_list, index_dims: int = 0, tune: bool 
     es = (ctypes.c_double * max(B, 1))(*[float(e) for e in eps_list])
     opts = _lib.sj_opts()
     opts.index_dims = index_dims
+    opts.short_circuit = short_circuit
+    opts.dim_order = dim_order
     opts.tune = 1 if tune else 0
     opts.tune_cache = tune_cache.encode() if tune_cache else None
     out = ctypes.c_void_p()

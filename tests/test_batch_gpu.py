@@ -112,3 +112,58 @@ def test_batch_capacity_error():
         selfjoin_batch_pairs(b, "fp64_mfma", small)
     assert ei.value.needed == sum(totals)
     b.close()
+
+
+def test_batch_pairs_graph_replays_and_buffers():
+    """The pairs launch is a captured graph per output buffer: replays into
+    the same buffer and a capture for a second buffer give the same rows;
+    in-masks recorded by one FP64 path's count serve the other path's pairs."""
+    import torch
+
+    from paper_2209_11287_amd import (selfjoin_batch_build, selfjoin_batch_count, selfjoin_batch_free,
+                                      selfjoin_batch_pairs)
+    probs = _problems(16, seed=11)
+    pts = [torch.from_numpy(X).to("cuda:0") for X, _ in probs]
+    b = selfjoin_batch_build(pts, [e for _, e in probs])
+    totals, _ = selfjoin_batch_count(b, "fp64_valu")
+    n = max(1, sum(totals))
+    b1 = torch.empty((n, 2), dtype=torch.int32, device="cuda:0")
+    b2 = torch.full((n, 2), -1, dtype=torch.int32, device="cuda:0")
+    o1, _ = selfjoin_batch_pairs(b, "fp64_mfma", b1)
+    first = b1.clone()
+    for rep in range(3):
+        b1.fill_(-7)
+        torch.cuda.synchronize()
+        o, _ = selfjoin_batch_pairs(b, "fp64_mfma", b1)
+        assert o == o1
+        assert torch.equal(b1, first), rep
+    o2, _ = selfjoin_batch_pairs(b, "fp64_mfma", b2)
+    assert o2 == o1 and torch.equal(b2, first)
+    selfjoin_batch_free(b)
+
+
+def test_batch_tuned_schedule_and_filters_match_oracle(tmp_path):
+    """Tuned choices (index_dims, short-circuit per d, and the tile kernels'
+    schedule), the short-circuit off and the input dimension order: the
+    same per-problem totals and pair sets as the oracle."""
+    import torch
+
+    import oracle
+    from paper_2209_11287_amd import (selfjoin_batch_build, selfjoin_batch_count, selfjoin_batch_free,
+                                      selfjoin_batch_pairs)
+    probs = _problems(14, seed=13)
+    pts = [torch.from_numpy(X).to("cuda:0") for X, _ in probs]
+    eps = [e for _, e in probs]
+    want = [oracle.grid_pairs(X, e)[2] for X, e in probs]
+    for kw in ({"tune": True, "tune_cache": str(tmp_path / "t.txt")}, {"short_circuit": -1}, {"dim_order": 1},
+               {"short_circuit": 1}):
+        log(f"[batch] options {kw}")
+        b = selfjoin_batch_build(pts, eps, **kw)
+        totals, _ = selfjoin_batch_count(b, "fp64_mfma")
+        assert totals == [len(w) for w in want], kw
+        buf = torch.empty((max(1, sum(totals)), 2), dtype=torch.int32, device="cuda:0")
+        offs, _ = selfjoin_batch_pairs(b, "fp64_mfma", buf)
+        out = buf.cpu().numpy()
+        for i in range(len(probs)):
+            assert np.array_equal(pair_keys(out[offs[i]:offs[i + 1]]), pair_keys(want[i])), (kw, i)
+        selfjoin_batch_free(b)
