@@ -211,6 +211,20 @@ def test_short_circuit_drops_tiles_and_keeps_results(path, d, sc, order):
         assert g["stats"]["tiles_pruned"] > 0
 
 
+@pytest.mark.parametrize("path", LOWP)
+@pytest.mark.parametrize("d", [24, 64])
+@pytest.mark.parametrize("sc", [0, -1])
+def test_short_circuit_setting_on_low_precision_tiles(path, d, sc):
+    """The FP32 / BF16 tiles run every K-step (their time goes into staging
+    the candidate tiles, so checks at K-step boundaries saved nothing when
+    measured): any short-circuit setting gives the oracle's results and no
+    tile leaves early."""
+    X = gen.gaussian_mixture(6000, d, clusters=300, seed=500 + d)
+    eps = _eps_for(X, 20)
+    g = _check_against_oracle(X, eps, path, f"lowp-short-circuit-{d}d", short_circuit=sc)
+    assert g["stats"]["tiles_pruned"] == 0
+
+
 @pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("dist,n,d", [("expo", 2048, 16), ("uniform", 3001, 3), ("gmm", 1000, 64)])
 def test_index_free_mode_matches_oracle(path, dist, n, d):
