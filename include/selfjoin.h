@@ -304,7 +304,11 @@ sj_status selfjoin_count_noalloc(const double *points, int64_t n, int32_t d, dou
                                  int32_t *per_point, int64_t *total, void *stream);
 
 /* ---- Batched form: B independent self-joins of uneven n and d ----------
- * The work items of all problems sit in one queue, grouped by d (one tile
+ * selfjoin_batch_build builds every problem's grid in one segmented pass
+ * (one set of launches for all problems: one radix sort whose keys carry the
+ * problem index above each problem's cell key; two host synchronisations),
+ * falling back to one build per problem when the problem index does not fit
+ * above the widest cell key. The work items of all problems sit in one queue, grouped by d (one tile
  * form each) and ordered by descending cost within a group. The count
  * pipeline (counter reset, one tile kernel per form, per-problem prefix sums)
  * and the pairs launch are each captured into a HIP graph on first use and

@@ -140,6 +140,8 @@ struct Batch {
     int64_t *totals_dev = nullptr;
     std::vector<int64_t> totals;
     unsigned long long *masks = nullptr;  // every problem's in-masks (or null: pairs re-run the tiles)
+    bool segmented = false;               // grids from one segmented build (their arrays in `owned`)
+    std::vector<void *> owned;
     bool masks_valid = false;
     bool counted = false;
     double ms_build = 0;                  // wall time of the grid builds and the queue
@@ -175,6 +177,8 @@ void batch_free(Batch &b, hipStream_t s) {
         delete g;
     }
     b.grids.clear();
+    for (void *p : b.owned) dev_free(p, s);
+    b.owned.clear();
     void *bufs[] = {b.item_base_dev, b.queue, b.ctr, b.probs_dev, b.totals_dev, b.masks};
     for (void *p : bufs)
         if (p) dev_free(p, s);
@@ -230,16 +234,27 @@ void batch_build(Batch &b, int B, const double *const *points, const int64_t *n,
     b.item_base.assign(B + 1, 0);
     int64_t mask_tiles = 0;
     std::vector<int64_t> tile_base(B + 1, 0);
+    // every problem's grid in one segmented build (tile slots counted over
+    // all problems together), else one build per problem
+    std::vector<SegInput> sin(B);
+    for (int i = 0; i < B; ++i)
+        sin[i] = SegInput{points[i], n[i], d[i], eps[i], b.kdims[i], b.scs[i], opts ? opts->dim_order : 0};
+    std::vector<Grid *> gs;
+    b.segmented = build_grids_segmented(sin, gs, b.owned, s);
     for (int i = 0; i < B; ++i) {
-        b.grids[i] = new Grid();
+        if (b.segmented) {
+            b.grids[i] = gs[i];
+        } else {
+            b.grids[i] = new Grid();
+            b.grids[i]->sc = b.scs[i];
+            if (opts) b.grids[i]->dim_order = opts->dim_order;
+            build_grid(*b.grids[i], points[i], n[i], d[i], eps[i], b.kdims[i], s);
+        }
         Grid &g = *b.grids[i];
-        g.sc = b.scs[i];
-        if (opts) g.dim_order = opts->dim_order;
-        build_grid(g, points[i], n[i], d[i], eps[i], b.kdims[i], s);
         g.cnt = dev_alloc_n<int32_t>((size_t)g.n + 1, s);
         g.off = dev_alloc_n<int64_t>((size_t)g.n + 1, s);
         b.item_base[i + 1] = b.item_base[i] + g.items;
-        tile_base[i] = mask_tiles;
+        tile_base[i] = b.segmented ? 0 : mask_tiles;
         mask_tiles += g.tiles;
     }
     b.total_items = b.item_base[B];

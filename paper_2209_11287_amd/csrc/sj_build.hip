@@ -1146,6 +1146,13 @@ void exclusive_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipSt
 }
 
 void free_grid(Grid &g, hipStream_t s) {
+    if (g.borrowed) {  // the index arrays belong to a segmented build
+        g.xs = g.xa = g.nrm = g.pn = nullptr;
+        g.perm = nullptr;
+        g.ranges = nullptr;
+        g.item = nullptr;
+        g.tile_off = nullptr;
+    }
     void *bufs[] = {g.xs,   g.xa,       g.nrm,        g.perm,       g.cell_key, g.cell_start, g.ranges,
                     g.item, g.dev_nmax, g.line_first, g.line_table, g.blocks,   g.cnt,        g.off, g.ctr,
                     g.tile_off, g.masks, g.pn};
@@ -1542,6 +1549,700 @@ int64_t grid_cref(Grid &g, hipStream_t s) {
     dev_free(acc, s);
     g.cand_ref = (int64_t)h;
     return g.cand_ref;
+}
+
+// ============================================================ segmented ====
+// Grid builds of many problems at once (the batched form). Every step runs
+// over all problems in one launch: points, cells, lines and work items of
+// all problems sit in shared arrays, problem p's sorted points at
+// [pt_off[p], pt_off[p] + n_p). The sort key carries the problem index above
+// the cell key, so one radix sort orders every problem's points by its own
+// cells; each problem's cells, lines and items are then contiguous, and the
+// first element of the next problem ends the one before (the searches of a
+// problem stay inside its own cells). Two host synchronisations in all: the
+// bounding boxes (for the geometry, chosen on the host per problem), and the
+// table sizes at the end.
+namespace {
+
+struct SegProb {
+    const double *X;
+    int64_t n, pt_off;       // points; first sorted position
+    int64_t xs_off, xa_off;  // first element of the problem's rows in the shared arrays
+    int64_t row_off;         // first row of nrm (rows include kRowPad pads)
+    int64_t pn_off;          // first element of its prefix norms
+    int64_t range_base;      // first range slot of its items
+    int32_t d, dp, da, npc, nranges, mid_off;
+    KeyGeom key;
+    RangeGeom rg;
+};
+
+struct SegBlk {  // a block's share of one problem's rows
+    int32_t p;
+    int64_t r0, r1;
+};
+
+__device__ __forceinline__ int seg_find(const int64_t *__restrict__ off, int B, int64_t x) {
+    int lo = 0, hi = B;  // last p with off[p] <= x
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Bounding box and moments of one problem's row run per block (as
+// k_bbox_partial), into the block's 4 d partials.
+__global__ void k_seg_bbox_partial(const SegProb *__restrict__ P, const SegBlk *__restrict__ blk,
+                                   const int64_t *__restrict__ part_off, double *__restrict__ part,
+                                   int *__restrict__ bad) {
+    __shared__ double smin[kThreads], smax[kThreads], ssum[kThreads], ssq[kThreads];
+    const SegBlk b = blk[blockIdx.x];
+    const SegProb &q = P[b.p];
+    const int d = q.d;
+    const int S = (kThreads / d) * d;
+    const int tid = threadIdx.x;
+    double mn = INFINITY, mx = -INFINITY, s1 = 0.0, s2 = 0.0;
+    int nonfinite = 0;
+    if (tid < S && b.r0 < b.r1) {
+        const double x0 = q.X[tid % d];
+        for (int64_t e = b.r0 * d + tid; e < b.r1 * d; e += S) {
+            const double v = q.X[e];
+            nonfinite |= !isfinite(v);
+            mn = fmin(mn, v);
+            mx = fmax(mx, v);
+            const double c = v - x0;
+            s1 += c;
+            s2 = fma(c, c, s2);
+        }
+    }
+    smin[tid] = mn;
+    smax[tid] = mx;
+    ssum[tid] = s1;
+    ssq[tid] = s2;
+    if (nonfinite) atomicOr(bad, 1);
+    __syncthreads();
+    if (tid < d) {
+        double a = INFINITY, c = -INFINITY, c1 = 0.0, c2 = 0.0;
+        for (int t = tid; t < S; t += d) {
+            a = fmin(a, smin[t]);
+            c = fmax(c, smax[t]);
+            c1 += ssum[t];
+            c2 += ssq[t];
+        }
+        double *o = part + part_off[blockIdx.x];
+        o[tid] = a;
+        o[d + tid] = c;
+        o[2 * d + tid] = c1;
+        o[3 * d + tid] = c2;
+    }
+}
+
+// One block per (problem, dimension): min, max and moment sums over the
+// problem's blocks [b0, b1) into box[box_off + {0, d, 2d, 3d} + j].
+struct SegDim {
+    int32_t p, j, b0, b1;
+    int64_t box_off;
+};
+
+__global__ void k_seg_bbox_final(const SegProb *__restrict__ P, const SegDim *__restrict__ dims,
+                                 const int64_t *__restrict__ part_off, const double *__restrict__ part,
+                                 double *__restrict__ box) {
+    __shared__ double smin[kThreads], smax[kThreads], t1[kThreads], t2[kThreads];
+    const SegDim D = dims[blockIdx.x];
+    const int d = P[D.p].d;
+    double a = INFINITY, b = -INFINITY, c1 = 0.0, c2 = 0.0;
+    for (int t = D.b0 + (int)threadIdx.x; t < D.b1; t += blockDim.x) {
+        const double *o = part + part_off[t];
+        a = fmin(a, o[D.j]);
+        b = fmax(b, o[d + D.j]);
+        c1 += o[2 * d + D.j];
+        c2 += o[3 * d + D.j];
+    }
+    smin[threadIdx.x] = a;
+    smax[threadIdx.x] = b;
+    t1[threadIdx.x] = c1;
+    t2[threadIdx.x] = c2;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + w]);
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+            t1[threadIdx.x] += t1[threadIdx.x + w];
+            t2[threadIdx.x] += t2[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        box[D.box_off + D.j] = smin[0];
+        box[D.box_off + d + D.j] = smax[0];
+        box[D.box_off + 2 * d + D.j] = t1[0];
+        box[D.box_off + 3 * d + D.j] = t2[0];
+    }
+}
+
+// Keys (problem index above the problem's cell key and sub-cell bits, as
+// k_keys_hist) and values (global point index), with every pass's digit
+// histogram.
+__global__ __launch_bounds__(kThreads) void k_seg_keys_hist(const SegProb *__restrict__ P,
+                                                            const SegBlk *__restrict__ blk, int keybits,
+                                                            unsigned long long *__restrict__ key,
+                                                            int32_t *__restrict__ val, int passes,
+                                                            int32_t *__restrict__ hist) {
+    __shared__ int32_t h[kOsMaxPasses * 256];
+    for (int t = threadIdx.x; t < passes * 256; t += kThreads) h[t] = 0;
+    __syncthreads();
+    const SegBlk b = blk[blockIdx.x];
+    const SegProb &q = P[b.p];
+    const KeyGeom &geo = q.key;
+    for (int64_t i = b.r0 + threadIdx.x; i < b.r1; i += kThreads) {
+        unsigned long long kk = 0, sub = 0;
+        for (int j = 0; j < geo.k; ++j) {
+            const double t = __ddiv_rn(__dsub_rn(q.X[i * geo.d + j], geo.lo[j]), geo.w);
+            double c = floor(t);
+            c = !(c >= 0.0) ? 0.0 : (c > (double)(geo.m[j] - 1) ? (double)(geo.m[j] - 1) : c);
+            const int64_t ci = (int64_t)c;
+            kk += (unsigned long long)ci * (unsigned long long)geo.stride[j];
+            if (j == geo.k - 1) sub = sub_cell(t, ci, geo.sb);
+        }
+        const unsigned long long full = ((unsigned long long)b.p << keybits) | (kk << geo.sb) | sub;
+        key[q.pt_off + i] = full;
+        val[q.pt_off + i] = (int32_t)(q.pt_off + i);
+        for (int ps = 0; ps < passes; ++ps) atomicAdd(&h[ps * 256 + (int)((full >> (8 * ps)) & 255u)], 1);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < passes * 256; t += kThreads)
+        if (h[t]) atomicAdd(&hist[t], h[t]);
+}
+
+// Rows [0, n + kRowPad) of each problem: sorted rows (input order), centred
+// rows in the problem's tile order, norms, prefix norms and the local input
+// index (as k_gather); pad rows are zero. Also the sorted keys without the
+// problem bits, and each problem's largest norm (bit pattern, atomic max).
+__global__ void k_seg_gather(const SegProb *__restrict__ P, const SegBlk *__restrict__ blk,
+                             const unsigned long long *__restrict__ key, const int32_t *__restrict__ val,
+                             const double *__restrict__ mid_all, const uint8_t *__restrict__ fo_all, int keybits,
+                             double *__restrict__ xs_all, double *__restrict__ xa_all, double *__restrict__ nrm_all,
+                             double *__restrict__ pn_all, int32_t *__restrict__ perm_all,
+                             unsigned long long *__restrict__ skey, unsigned long long *__restrict__ nmax_bits) {
+    const SegBlk b = blk[blockIdx.x];
+    const SegProb &q = P[b.p];
+    const int d = q.d, dp = q.dp, da = q.da, npc = q.npc;
+    const double *mid = mid_all + q.mid_off;
+    const uint8_t *fo = fo_all + q.mid_off;
+    const int64_t i = b.r0 + threadIdx.x;
+    double nn = 0.0;
+    if (i < b.r1) {
+        double *ps = xs_all + q.xs_off + i * dp;
+        double *pa = xa_all + q.xa_off + i * da;
+        double *pnr = npc > 0 ? pn_all + q.pn_off + i * npc : nullptr;
+        if (i < q.n) {
+            const int64_t pos = q.pt_off + i;
+            const int32_t loc = val[pos] - (int32_t)q.pt_off;
+            perm_all[pos] = loc;
+            skey[pos] = key[pos] & ((1ull << keybits) - 1ull);
+            const double *src = q.X + (int64_t)loc * d;
+            for (int t = 0; t < d; ++t) ps[t] = src[t];
+            for (int t = 0; t < d; ++t) {
+                const int u = fo[t];
+                const double c = __dsub_rn(src[u], mid[u]);
+                pa[t] = c;
+                nn = __fma_rn(c, c, nn);
+                if ((t & 3) == 3 && (t >> 2) < npc) pnr[t >> 2] = nn;
+            }
+            for (int t = d; t < dp; ++t) ps[t] = 0.0;
+            for (int t = d; t < da; ++t) pa[t] = 0.0;
+            if (d & 3) pa[d] = nn;
+        } else {
+            for (int t = 0; t < dp; ++t) ps[t] = 0.0;
+            for (int t = 0; t < da; ++t) pa[t] = 0.0;
+            for (int t = 0; t < npc; ++t) pnr[t] = 0.0;
+        }
+        nrm_all[q.row_off + i] = nn;
+    }
+    // block maximum (every row of the block belongs to problem b.p)
+    __shared__ double red[kThreads / 64];
+    double v = nn;
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < kThreads / 64; ++w) m = fmax(m, red[w]);
+        if (m > 0.0) atomicMax(&nmax_bits[b.p], (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+// Cell starts over all problems (flag[N] = 0 ends the scan).
+__global__ void k_seg_cell_flags(const unsigned long long *__restrict__ skey, int64_t N,
+                                 const int64_t *__restrict__ pt_off, int B, const int32_t *__restrict__ sbs,
+                                 int32_t *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > N) return;
+    if (i == N) {
+        flag[i] = 0;
+        return;
+    }
+    const int p = seg_find(pt_off, B, i);
+    const int sb = sbs[p];
+    flag[i] = (i == pt_off[p] || (skey[i] >> sb) != (skey[i - 1] >> sb)) ? 1 : 0;
+}
+
+__global__ void k_seg_cell_write(const unsigned long long *__restrict__ skey, int64_t N,
+                                 const int64_t *__restrict__ pt_off, int B, const int32_t *__restrict__ sbs,
+                                 const int32_t *__restrict__ flag, const int32_t *__restrict__ cid,
+                                 int64_t *__restrict__ cell_key, int32_t *__restrict__ cell_start,
+                                 int32_t *__restrict__ cellp, int32_t *__restrict__ ncells) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    if (flag[i]) {
+        const int p = seg_find(pt_off, B, i);
+        cell_key[cid[i]] = (int64_t)(skey[i] >> sbs[p]);
+        cell_start[cid[i]] = (int32_t)i;
+        cellp[cid[i]] = p;
+    }
+    if (i == N - 1) {
+        const int32_t c = cid[i] + flag[i];
+        *ncells = c;
+        cell_start[c] = (int32_t)N;
+        cellp[c] = B;
+    }
+}
+
+// Line starts over all problems' cells; entries [ncells, len) are 0.
+__global__ void k_seg_line_flags(const int64_t *__restrict__ cell_key, const int32_t *__restrict__ cellp,
+                                 const int32_t *__restrict__ ncells_p, const int64_t *__restrict__ mlast, int64_t len,
+                                 int32_t *__restrict__ lflag) {
+    const int64_t ncells = *ncells_p;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= len) return;
+    if (c >= ncells) {
+        lflag[c] = 0;
+        return;
+    }
+    const int p = cellp[c];
+    lflag[c] = (c == 0 || cellp[c - 1] != p || cell_key[c] / mlast[p] != cell_key[c - 1] / mlast[p]) ? 1 : 0;
+}
+
+// Per problem: first cell, line and work item (entry B: the totals).
+__global__ void k_seg_offsets(const int64_t *__restrict__ pt_off, int B, const int32_t *__restrict__ cid,
+                              const int32_t *__restrict__ lid, const int32_t *__restrict__ item_off,
+                              int64_t *__restrict__ cell_off, int64_t *__restrict__ it_off) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > B) return;
+    const int32_t c = cid[pt_off[p]];
+    cell_off[p] = c;
+    it_off[p] = item_off[lid[c]];
+}
+
+// Candidate ranges of every work item of every problem (as k_item_ranges, on
+// the problem's own cells), stored as the problem's local sorted positions
+// at the problem's range slots.
+__global__ void k_seg_item_ranges(const SegProb *__restrict__ P, int B, const Item *__restrict__ items,
+                                  const int32_t *__restrict__ nitems_p, const int64_t *__restrict__ it_off,
+                                  const int64_t *__restrict__ cell_off, const int64_t *__restrict__ cell_key,
+                                  const int32_t *__restrict__ cell_start, const unsigned long long *__restrict__ skey,
+                                  Range *__restrict__ ranges) {
+    constexpr int kR = 27;  // 3^(kMaxIndexDims - 1)
+    const int64_t total = (int64_t)(*nitems_p) * kR;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t it = t / kR;
+        const int o = (int)(t - it * kR);
+        const int p = seg_find(it_off, B, it);
+        const SegProb &q = P[p];
+        const RangeGeom &geo = q.rg;
+        if (o >= geo.nranges) continue;
+        const int kl = geo.k - 1;
+        const int64_t mlast = geo.m[kl];
+        const int64_t c0g = cell_off[p];
+        const int64_t *ck = cell_key + c0g;
+        const int32_t *cs = cell_start + c0g;
+        const int64_t nc = cell_off[p + 1] - c0g;
+        const Item I = items[it];
+        const unsigned long long kf = geo.sb > 0 ? skey[I.qbegin] : 0ull;
+        const unsigned long long kb = geo.sb > 0 ? skey[I.qend - 1] : 0ull;
+        int64_t c0[kMaxIndexDims], c1[kMaxIndexDims];
+        decode_key(cell_key[I.cell_first], geo, c0);
+        decode_key(cell_key[I.cell_last], geo, c1);
+        const int64_t base = neighbour_line(c0, o, geo);
+        Range r{0, 0};
+        if (base >= 0) {
+            const int64_t lo_c = c0[kl] > 0 ? c0[kl] - 1 : 0;
+            const int64_t hi_c = c1[kl] < mlast - 1 ? c1[kl] + 1 : c1[kl];
+            r = line_segment(ck, cs, nc, nullptr, nullptr, base, mlast, lo_c, hi_c);
+            if (geo.sb > 0 && r.end > r.begin) {
+                const unsigned long long sub = (1ull << geo.sb) - 1ull;
+                const int64_t pf = (int64_t)((((kf >> geo.sb) % (unsigned long long)mlast) << geo.sb) | (kf & sub));
+                const int64_t pb = (int64_t)((((kb >> geo.sb) % (unsigned long long)mlast) << geo.sb) | (kb & sub));
+                const int64_t span = int64_t(1) << geo.sb, pmax = mlast * span - 1;
+                const int64_t plo = max(pf - span - 1, int64_t(0)), phi = min(pb + span + 1, pmax);
+                const unsigned long long klo = ((unsigned long long)base << geo.sb) + (unsigned long long)plo;
+                const unsigned long long khi = ((unsigned long long)base << geo.sb) + (unsigned long long)phi;
+                int64_t x0, x1;
+                bounds2<unsigned long long>(skey, r.begin, r.end, klo, khi, x0, x1);
+                r.begin = (int32_t)x0;
+                r.end = (int32_t)x1;
+            }
+        }
+        if (r.end > r.begin) {
+            r.begin -= (int32_t)q.pt_off;
+            r.end -= (int32_t)q.pt_off;
+        } else {
+            r.begin = r.end = 0;
+        }
+        ranges[q.range_base + (it - it_off[p]) * geo.nranges + o] = r;
+    }
+}
+
+// Per item of every problem: its in-mask tile slots (as k_item_tiles, entry
+// nitems = 0), its candidate pairs into the problem's total, and its query
+// run moved to the problem's local positions.
+__global__ void k_seg_item_tiles(const SegProb *__restrict__ P, int B, Item *__restrict__ items,
+                                 const int32_t *__restrict__ nitems_p, const int64_t *__restrict__ it_off,
+                                 const Range *__restrict__ ranges, int32_t *__restrict__ tiles,
+                                 unsigned long long *__restrict__ cand) {
+    const int64_t I = *nitems_p;
+    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it > I) return;
+    if (it == I) {
+        tiles[it] = 0;
+        return;
+    }
+    const int p = seg_find(it_off, B, it);
+    const SegProb &q = P[p];
+    const Range *rr = ranges + q.range_base + (it - it_off[p]) * q.nranges;
+    int64_t c = 0;
+    for (int o = 0; o < q.nranges; ++o) c += rr[o].end > rr[o].begin ? rr[o].end - rr[o].begin : 0;
+    const int64_t nt = (c + 15) / 16;
+    tiles[it] = (int32_t)((nt + 15) / 16 * 16);
+    Item m = items[it];
+    atomicAdd(&cand[p], (unsigned long long)(m.qend - m.qbegin) * (unsigned long long)c);
+    m.qbegin -= (int32_t)q.pt_off;
+    m.qend -= (int32_t)q.pt_off;
+    items[it] = m;
+}
+
+// Per problem: in-mask tile slots (entry B: the total).
+__global__ void k_seg_tiles(const int64_t *__restrict__ it_off, int B, const int64_t *__restrict__ tile_off,
+                            int64_t *__restrict__ ptiles) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > B) return;
+    ptiles[p] = tile_off[it_off[p]];
+}
+
+}  // namespace
+
+bool build_grids_segmented(const std::vector<SegInput> &in, std::vector<Grid *> &out, std::vector<void *> &owned,
+                           hipStream_t s) {
+    const int B = (int)in.size();
+    out.assign(B, nullptr);
+    if (B == 0) return true;
+    int pbits = 1;
+    while ((1 << pbits) < B) ++pbits;
+    // ---- phase 1: bounding boxes and moments of every problem ----
+    std::vector<SegProb> hp(B);
+    std::vector<int64_t> pt_off(B + 1, 0);
+    std::vector<SegBlk> blk;
+    std::vector<int64_t> part_off;
+    std::vector<SegDim> dims;
+    std::vector<int64_t> box_off(B + 1, 0);
+    int64_t part_total = 0;
+    for (int p = 0; p < B; ++p) {
+        const SegInput &x = in[p];
+        pt_off[p + 1] = pt_off[p] + x.n;
+        hp[p].X = x.points;
+        hp[p].n = x.n;
+        hp[p].d = x.d;
+        const int b0 = (int)blk.size();
+        const int64_t rpb = 2048;
+        for (int64_t r0 = 0; r0 < x.n; r0 += rpb) {
+            blk.push_back({p, r0, std::min(x.n, r0 + rpb)});
+            part_off.push_back(part_total);
+            part_total += 4 * (int64_t)x.d;
+        }
+        for (int j = 0; j < x.d && x.n > 0; ++j) dims.push_back({p, j, b0, (int)blk.size(), box_off[p]});
+        box_off[p + 1] = box_off[p] + 4 * (int64_t)x.d;
+    }
+    const int64_t N = pt_off[B];
+    if (N >= (int64_t(1) << 31) - (int64_t)B * kRowPad) throw std::string("too many points in one batch");
+    auto up = [&](const void *h, size_t bytes) {
+        void *d = dev_alloc(bytes + 16, s);
+        if (bytes) SJ_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
+        return d;
+    };
+    SegProb *P = static_cast<SegProb *>(up(hp.data(), B * sizeof(SegProb)));
+    std::vector<double> hbox(box_off[B] + 1, 0.0);
+    int hbad = 0;
+    {
+        SegBlk *dblk = static_cast<SegBlk *>(up(blk.data(), blk.size() * sizeof(SegBlk)));
+        int64_t *dpo = static_cast<int64_t *>(up(part_off.data(), part_off.size() * sizeof(int64_t)));
+        SegDim *ddim = static_cast<SegDim *>(up(dims.data(), dims.size() * sizeof(SegDim)));
+        double *part = dev_alloc_n<double>((size_t)std::max<int64_t>(1, part_total), s);
+        double *box = dev_alloc_n<double>((size_t)box_off[B] + 1, s);
+        int *bad = dev_alloc_n<int>(1, s);
+        fill_zero(bad, sizeof(int), s);
+        if (!blk.empty())
+            hipLaunchKernelGGL(k_seg_bbox_partial, dim3((unsigned)blk.size()), dim3(kThreads), 0, s, P, dblk, dpo,
+                               part, bad);
+        SJ_HIP(hipGetLastError());
+        if (!dims.empty())
+            hipLaunchKernelGGL(k_seg_bbox_final, dim3((unsigned)dims.size()), dim3(kThreads), 0, s, P, ddim, dpo,
+                               part, box);
+        SJ_HIP(hipGetLastError());
+        SJ_HIP(hipMemcpyAsync(hbox.data(), box, box_off[B] * sizeof(double), hipMemcpyDeviceToHost, s));
+        SJ_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+        SJ_HIP(hipStreamSynchronize(s));
+        for (void *q : {(void *)dblk, (void *)dpo, (void *)ddim, (void *)part, (void *)box, (void *)bad}) dev_free(q, s);
+    }
+    if (hbad) {
+        dev_free(P, s);
+        throw std::string("non-finite coordinate in points");
+    }
+    // ---- host: geometry and tile order per problem ----
+    int keybits = 0;
+    std::vector<double> mid_all;
+    std::vector<uint8_t> fo_all;
+    int64_t xs_tot = 0, xa_tot = 0, pn_tot = 0, rng_tot = 0;
+    std::vector<int32_t> sbs(B);
+    std::vector<int64_t> mlast(B);
+    for (int p = 0; p < B; ++p) {
+        const SegInput &x = in[p];
+        Grid *g = new Grid();
+        out[p] = g;
+        g->n = x.n;
+        g->d = x.d;
+        g->eps = x.eps;
+        g->eps2 = x.eps * x.eps;
+        g->dp = (x.d + 3) & ~3;
+        g->da = (x.d & 3) ? ((x.d + 1 + 3) & ~3) : x.d;
+        g->sc = x.sc;
+        g->dim_order = x.dim_order;
+        g->borrowed = true;
+        std::vector<double> var(x.d, 0.0);
+        const double *bx = hbox.data() + box_off[p];
+        for (int j = 0; j < x.d; ++j) {
+            if (x.n == 0) {
+                g->lo[j] = g->hi[j] = g->mid[j] = 0.0;
+                continue;
+            }
+            g->lo[j] = bx[j];
+            g->hi[j] = bx[x.d + j];
+            g->mid[j] = 0.5 * g->lo[j] + 0.5 * g->hi[j];
+            const double m1 = bx[2 * x.d + j] / (double)x.n;
+            var[j] = std::max(0.0, bx[3 * x.d + j] / (double)x.n - m1 * m1);
+        }
+        choose_geometry(*g, x.index_dims);
+        choose_dim_order(*g, var);
+        g->npc = x.d > 4 ? g->da / 4 - 1 : 0;
+        keybits = std::max(keybits, g->key_bits + g->sub_bits);
+        SegProb &q = hp[p];
+        q.pt_off = pt_off[p];
+        q.xs_off = xs_tot;
+        q.xa_off = xa_tot;
+        q.row_off = pt_off[p] + (int64_t)p * kRowPad;
+        q.pn_off = pn_tot;
+        q.range_base = rng_tot;
+        q.dp = g->dp;
+        q.da = g->da;
+        q.npc = g->npc;
+        q.nranges = g->nranges;
+        q.mid_off = (int32_t)mid_all.size();
+        for (int j = 0; j < x.d; ++j) {
+            mid_all.push_back(g->mid[j]);
+            fo_all.push_back(g->fo[j]);
+        }
+        q.key = KeyGeom{};
+        q.key.k = g->k;
+        q.key.d = x.d;
+        q.key.sb = g->sub_bits;
+        q.key.w = g->w;
+        for (int j = 0; j < g->k; ++j) {
+            q.key.lo[j] = g->lo[j];
+            q.key.m[j] = g->m[j];
+            q.key.stride[j] = g->stride[j];
+        }
+        q.rg = range_geom(*g);
+        sbs[p] = g->sub_bits;
+        mlast[p] = g->m[g->k - 1];
+        const int64_t rows = x.n + kRowPad;
+        xs_tot += rows * g->dp;
+        xa_tot += rows * g->da;
+        pn_tot += rows * g->npc;
+        rng_tot += (x.n + x.n / kTileQ + 1) * g->nranges;
+    }
+    if (pbits + keybits > 64) {  // the problem bits do not fit above the widest key: per-problem builds
+        dev_free(P, s);
+        for (Grid *g : out) delete g;
+        out.assign(B, nullptr);
+        return false;
+    }
+    SJ_HIP(hipMemcpyAsync(P, hp.data(), B * sizeof(SegProb), hipMemcpyHostToDevice, s));
+    // ---- phase 2: keys, one sort, rows, cells, lines, items, ranges, tiles ----
+    auto keep = [&](void *q) {
+        owned.push_back(q);
+        return q;
+    };
+    double *xs_all = static_cast<double *>(keep(dev_alloc_n<double>((size_t)xs_tot, s)));
+    double *xa_all = static_cast<double *>(keep(dev_alloc_n<double>((size_t)xa_tot, s)));
+    double *nrm_all = static_cast<double *>(keep(dev_alloc_n<double>((size_t)(N + (int64_t)B * kRowPad), s)));
+    double *pn_all = pn_tot > 0 ? static_cast<double *>(keep(dev_alloc_n<double>((size_t)pn_tot, s))) : nullptr;
+    int32_t *perm_all = static_cast<int32_t *>(keep(dev_alloc_n<int32_t>((size_t)N + 1, s)));
+    const int64_t items_ub = N + N / kTileQ + B + 1;
+    Item *items = static_cast<Item *>(keep(dev_alloc_n<Item>((size_t)items_ub, s)));
+    Range *ranges = static_cast<Range *>(keep(dev_alloc_n<Range>((size_t)std::max<int64_t>(1, rng_tot), s)));
+    int64_t *tile_off = static_cast<int64_t *>(keep(dev_alloc_n<int64_t>((size_t)items_ub + 1, s)));
+
+    std::vector<void *> tmp;
+    auto scratch = [&](size_t bytes) {
+        void *q = dev_alloc(bytes + 16, s);
+        tmp.push_back(q);
+        return q;
+    };
+    int64_t *d_pt_off = static_cast<int64_t *>(scratch((B + 1) * sizeof(int64_t)));
+    SJ_HIP(hipMemcpyAsync(d_pt_off, pt_off.data(), (B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    int32_t *d_sbs = static_cast<int32_t *>(up(sbs.data(), B * sizeof(int32_t)));
+    tmp.push_back(d_sbs);
+    int64_t *d_mlast = static_cast<int64_t *>(up(mlast.data(), B * sizeof(int64_t)));
+    tmp.push_back(d_mlast);
+    double *d_mid = static_cast<double *>(up(mid_all.data(), mid_all.size() * sizeof(double)));
+    tmp.push_back(d_mid);
+    uint8_t *d_fo = static_cast<uint8_t *>(up(fo_all.data(), fo_all.size()));
+    tmp.push_back(d_fo);
+    SegBlk *d_blk = static_cast<SegBlk *>(up(blk.data(), blk.size() * sizeof(SegBlk)));
+    tmp.push_back(d_blk);
+    // gather blocks: rows [0, n + kRowPad) of each problem, kThreads per block
+    std::vector<SegBlk> gblk;
+    for (int p = 0; p < B; ++p)
+        for (int64_t r0 = 0; r0 < in[p].n + kRowPad; r0 += kThreads)
+            gblk.push_back({p, r0, std::min<int64_t>(in[p].n + kRowPad, r0 + kThreads)});
+    SegBlk *d_gblk = static_cast<SegBlk *>(up(gblk.data(), gblk.size() * sizeof(SegBlk)));
+    tmp.push_back(d_gblk);
+
+    const int bits = pbits + keybits;
+    const int passes = (bits + 7) / 8;
+    unsigned long long *ka = static_cast<unsigned long long *>(scratch((size_t)(N + 1) * 8));
+    unsigned long long *kb = static_cast<unsigned long long *>(scratch((size_t)(N + 1) * 8));
+    int32_t *va = static_cast<int32_t *>(scratch((size_t)(N + 1) * 4));
+    int32_t *vb = static_cast<int32_t *>(scratch((size_t)(N + 1) * 4));
+    const int64_t os_tiles = std::max<int64_t>(1, (N + kOsTile - 1) / kOsTile);
+    int32_t *os_hist = static_cast<int32_t *>(scratch((kOsMaxPasses * 256 + kOsMaxPasses + 1) * sizeof(int32_t)));
+    int32_t *os_ctr = os_hist + kOsMaxPasses * 256;
+    int32_t *os_err = os_ctr + kOsMaxPasses;
+    unsigned long long *os_status =
+        static_cast<unsigned long long *>(scratch((size_t)passes * os_tiles * 256 * sizeof(unsigned long long)));
+    unsigned long long *nmax_bits = static_cast<unsigned long long *>(scratch((size_t)B * 8));
+    unsigned long long *cand = static_cast<unsigned long long *>(scratch((size_t)B * 8));
+    int32_t *counters = static_cast<int32_t *>(scratch(4 * sizeof(int32_t)));  // ncells, nlines, nitems
+    fill_zero_many({{os_hist, (kOsMaxPasses * 256 + kOsMaxPasses + 1) * sizeof(int32_t)},
+                    {os_status, (size_t)passes * os_tiles * 256 * sizeof(unsigned long long)},
+                    {nmax_bits, (size_t)B * 8},
+                    {cand, (size_t)B * 8},
+                    {counters, 4 * sizeof(int32_t)}},
+                   s);
+    if (!blk.empty()) {
+        hipLaunchKernelGGL(k_seg_keys_hist, dim3((unsigned)blk.size()), dim3(kThreads), 0, s, P, d_blk, keybits, ka,
+                           va, passes, os_hist);
+        SJ_HIP(hipGetLastError());
+    }
+    for (int ps = 0; ps < passes && N > 0; ++ps) {
+        unsigned long long *st = os_status + (size_t)ps * os_tiles * 256;
+        hipLaunchKernelGGL(k_onesweep<OS_WIDE>, dim3((unsigned)os_tiles), dim3(kThreads), 0, s, ka, va, kb, vb, N,
+                           8 * ps, os_hist + 256 * ps, st, os_ctr + ps, os_err);
+        SJ_HIP(hipGetLastError());
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    unsigned long long *skey = kb;  // the free key array receives the keys without the problem bits
+    hipLaunchKernelGGL(k_seg_gather, dim3((unsigned)gblk.size()), dim3(kThreads), 0, s, P, d_gblk, ka, va, d_mid,
+                       d_fo, keybits, xs_all, xa_all, nrm_all, pn_all, perm_all, skey, nmax_bits);
+    SJ_HIP(hipGetLastError());
+    // cells
+    int32_t *flag = static_cast<int32_t *>(scratch((size_t)(items_ub + 1) * 4));
+    int32_t *cid = static_cast<int32_t *>(scratch((size_t)(items_ub + 1) * 4));
+    int64_t *cell_key = static_cast<int64_t *>(scratch((size_t)(N + 1) * 8));
+    int32_t *cell_start = static_cast<int32_t *>(scratch((size_t)(N + 2) * 4));
+    int32_t *cellp = static_cast<int32_t *>(scratch((size_t)(N + 2) * 4));
+    hipLaunchKernelGGL(k_seg_cell_flags, dim3(blocks_for(N + 1)), dim3(kThreads), 0, s, skey, N, d_pt_off, B, d_sbs,
+                       flag);
+    SJ_HIP(hipGetLastError());
+    exclusive_scan<int32_t, int32_t>(flag, cid, N + 1, s);
+    hipLaunchKernelGGL(k_seg_cell_write, dim3(blocks_for(N)), dim3(kThreads), 0, s, skey, N, d_pt_off, B, d_sbs, flag,
+                       cid, cell_key, cell_start, cellp, counters + 0);
+    SJ_HIP(hipGetLastError());
+    // lines (cid is kept: it maps a problem's first point to its first cell)
+    int32_t *lflag = static_cast<int32_t *>(scratch((size_t)(N + 1) * 4));
+    int32_t *lid = static_cast<int32_t *>(scratch((size_t)(N + 1) * 4));
+    int32_t *line_first = static_cast<int32_t *>(scratch((size_t)(N + 2) * 4));
+    hipLaunchKernelGGL(k_seg_line_flags, dim3(blocks_for(N + 1)), dim3(kThreads), 0, s, cell_key, cellp, counters + 0,
+                       d_mlast, N + 1, lflag);
+    SJ_HIP(hipGetLastError());
+    exclusive_scan<int32_t, int32_t>(lflag, lid, N + 1, s);
+    hipLaunchKernelGGL(k_line_write, dim3(blocks_for(N)), dim3(kThreads), 0, s, lflag, lid, cell_start, counters + 0,
+                       line_first, counters + 1);
+    SJ_HIP(hipGetLastError());
+    int32_t *nitem = static_cast<int32_t *>(scratch((size_t)(N + 1) * 4));
+    int32_t *item_off = static_cast<int32_t *>(scratch((size_t)(N + 1) * 4));
+    fill_zero(nitem, (size_t)(N + 1) * 4, s);
+    hipLaunchKernelGGL(k_line_items, dim3(blocks_for(N)), dim3(kThreads), 0, s, line_first, cell_start, counters + 1,
+                       nitem);
+    SJ_HIP(hipGetLastError());
+    exclusive_scan<int32_t, int32_t>(nitem, item_off, N + 1, s);
+    hipLaunchKernelGGL(k_items_total, dim3(1), dim3(1), 0, s, nitem, item_off, counters + 1, counters + 2);
+    SJ_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_items, dim3(blocks_for(items_ub)), dim3(kThreads), 0, s, line_first, item_off, cell_start,
+                       counters + 1, counters + 2, items, flag);
+    SJ_HIP(hipGetLastError());
+    int64_t *cell_off = static_cast<int64_t *>(scratch((B + 1) * sizeof(int64_t)));
+    int64_t *it_off = static_cast<int64_t *>(scratch((B + 1) * sizeof(int64_t)));
+    hipLaunchKernelGGL(k_seg_offsets, dim3(blocks_for(B + 1)), dim3(kThreads), 0, s, d_pt_off, B, cid, lid, item_off,
+                       cell_off, it_off);
+    SJ_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_seg_item_ranges, dim3(2048), dim3(kThreads), 0, s, P, B, items, counters + 2, it_off,
+                       cell_off, cell_key, cell_start, skey, ranges);
+    SJ_HIP(hipGetLastError());
+    int32_t *item_tiles = static_cast<int32_t *>(scratch((size_t)(items_ub + 1) * 4));
+    hipLaunchKernelGGL(k_seg_item_tiles, dim3(blocks_for(items_ub + 1)), dim3(kThreads), 0, s, P, B, items,
+                       counters + 2, it_off, ranges, item_tiles, cand);
+    SJ_HIP(hipGetLastError());
+    exclusive_scan<int32_t, int64_t>(item_tiles, tile_off, items_ub + 1, s);
+    int64_t *ptiles = static_cast<int64_t *>(scratch((B + 1) * sizeof(int64_t)));
+    hipLaunchKernelGGL(k_seg_tiles, dim3(blocks_for(B + 1)), dim3(kThreads), 0, s, it_off, B, tile_off, ptiles);
+    SJ_HIP(hipGetLastError());
+    // ---- one host sync: per-problem items, tiles, norms, candidates ----
+    std::vector<int64_t> h_it(B + 1), h_tiles(B + 1);
+    std::vector<unsigned long long> h_nmax(B), h_cand(B);
+    int32_t herr = 0;
+    SJ_HIP(hipMemcpyAsync(h_it.data(), it_off, (B + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipMemcpyAsync(h_tiles.data(), ptiles, (B + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipMemcpyAsync(h_nmax.data(), nmax_bits, B * 8, hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipMemcpyAsync(h_cand.data(), cand, B * 8, hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipMemcpyAsync(&herr, os_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    for (void *q : tmp) dev_free(q, s);
+    dev_free(P, s);
+    if (herr) throw HipError{hipErrorLaunchFailure, "radix sort: a tile's look-back did not complete"};
+    for (int p = 0; p < B; ++p) {
+        Grid &g = *out[p];
+        const SegProb &q = hp[p];
+        g.xs = xs_all + q.xs_off;
+        g.xa = xa_all + q.xa_off;
+        g.nrm = nrm_all + q.row_off;
+        g.pn = g.npc > 0 ? pn_all + q.pn_off : nullptr;
+        g.perm = perm_all + q.pt_off;
+        g.item = items + h_it[p];
+        g.ranges = ranges + q.range_base;
+        g.tile_off = tile_off + h_it[p];  // global tile slots: the batch's in-masks are shared
+        g.items = h_it[p + 1] - h_it[p];
+        g.tiles = h_tiles[p + 1] - h_tiles[p];
+        double nm = 0.0;
+        std::memcpy(&nm, &h_nmax[p], sizeof nm);
+        g.nmax = nm;
+        g.cand_items = (int64_t)h_cand[p];
+        g.cand_ref = -1;
+        g.nblocks = 0;
+    }
+    return true;
 }
 
 }  // namespace sj

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "../../include/selfjoin.h"
 
@@ -211,6 +212,8 @@ struct Grid {
     int64_t total = 0;
     sj_path count_path = SJ_FP64_VALU;  // the path whose kernels made the cached counts
 
+    bool borrowed = false;       // xs, xa, nrm, pn, perm, item, ranges, tile_off belong to a segmented
+                                 // build (released with the batch, not by free_grid)
     AllocHook hook;              // the handle's device allocator (alloc null: the caching allocator)
     bool lean = false;           // build and count without events or in-masks, dense line table
                                  // only up to kLeanLineTable entries (static-scratch calls)
@@ -222,6 +225,22 @@ struct Grid {
 void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int index_dims,
                 hipStream_t s);
 void free_grid(Grid &g, hipStream_t s);
+
+// Segmented build of many problems (sj_build.hip): the grids of every
+// problem in one pass of launches; their index arrays are slices of shared
+// buffers appended to `owned` (released by the caller), their tile_off
+// values count the tile slots of all problems together. Returns false (and
+// builds nothing) when the problem index does not fit above the widest cell
+// key; throws like build_grid.
+struct SegInput {
+    const double *points;
+    int64_t n;
+    int32_t d;
+    double eps;
+    int32_t index_dims, sc, dim_order;
+};
+bool build_grids_segmented(const std::vector<SegInput> &in, std::vector<Grid *> &out, std::vector<void *> &owned,
+                           hipStream_t s);
 // C_ref of the reference grid, computed on first request and cached.
 int64_t grid_cref(Grid &g, hipStream_t s);
 
