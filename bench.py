@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--chunk", type=int, default=0, help="pairs per output chunk (0 = one chunk)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-set", action="store_true", help="skip the per-set single-stream path comparison")
+    ap.add_argument("--no-other", action="store_true",
+                    help="skip the short passes of the precision, 10M-point and batched workloads")
     ap.add_argument("--streams", type=int, default=3,
                     help="data sets run concurrently, one host thread and HIP stream each")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -356,20 +358,11 @@ def brute_compare(inputs, path, bufs, reps=3):
     return out
 
 
-def batched_main(args):
-    """The batched workload: 256 independent problems (n log-uniform in
-    [1e3, 2e5], d in {2, 3, 4, 8, 16}, uniform, ~32 neighbours). One step =
-    build the batch (every problem's grid, the work queue, the in-mask
-    buffer), count every problem (one graph launch), write every problem's
-    pairs (one graph launch): all of it inside the timed region. The tuner's
-    choices (index_dims and short-circuit per d, kernel schedule) are made
-    once in the warmup and cached in a temporary file."""
-    import tempfile
-
+def batched_setup():
+    """The batched workload's problems on the device, their C_ref (the work
+    unit) and algorithmic flops, computed outside any timed region."""
     import torch
-    from paper_2209_11287_amd import (selfjoin_batch_build, selfjoin_batch_count, selfjoin_batch_free,
-                                      selfjoin_batch_info, selfjoin_batch_pairs, selfjoin_build_grid,
-                                      selfjoin_free_grid, selfjoin_grid_info)
+    from paper_2209_11287_amd import selfjoin_build_grid, selfjoin_free_grid, selfjoin_grid_info
     from workloads import configs
     from workloads import generators as gen
     ws = configs.batched_workload()
@@ -378,7 +371,6 @@ def batched_main(args):
     pts = [torch.from_numpy(X).to("cuda:0") for X in host]
     eps = [w["eps"] for w in ws]
     torch.cuda.synchronize()
-    # C_ref per problem (the work unit) and the algorithmic flops, outside the timed region
     cref, flops, crefs = 0, 0, []
     for p, e in zip(pts, eps):
         g = selfjoin_build_grid(p, e)
@@ -387,57 +379,98 @@ def batched_main(args):
         cref += c
         flops += 2 * p.shape[1] * c
         selfjoin_free_grid(g)
-    cache = os.path.join(tempfile.mkdtemp(), "tune.txt")
+    return {"ws": ws, "host": host, "pts": pts, "eps": eps, "cref": cref, "flops": flops, "crefs": crefs}
 
-    def run(path):
-        buf = None
-        rec = []
-        for i in range(args.warmup + args.steps):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            b = selfjoin_batch_build(pts, eps, tune=True, tune_cache=cache)
-            totals, st = selfjoin_batch_count(b, path)
-            if buf is None:
-                buf = torch.empty((max(1, sum(totals)), 2), dtype=torch.int32, device="cuda:0")
-            _, st2 = selfjoin_batch_pairs(b, path, buf)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            ks = sorted({(p.shape[1], selfjoin_batch_info(b, j)["index_dims"]) for j, p in enumerate(pts)})
-            selfjoin_batch_free(b)
-            if i >= args.warmup:
-                rec.append({"s": t1 - t0, "build_ms": st["ms_build"], "count_ms": st["ms"], "pairs_ms": st2["ms"],
-                            "pruned": st["tiles_pruned"], "pairs": sum(totals), "cand_eval": st["cand_eval"]})
-            log(f"[bench] batched {path} step {i}: {1e3 * (t1 - t0):.1f} ms (build {st['ms_build']:.1f}, "
-                f"count {st['ms']:.1f}, pairs {st2['ms']:.1f})")
-        sec = sum(r["s"] for r in rec) / len(rec)
-        avg = {k: round(sum(r[k] for r in rec) / len(rec), 3) for k in ("build_ms", "count_ms", "pairs_ms")}
-        return sec, avg, rec[-1], ks
 
-    sec, avg, last, ks = run(args.path)
+def batched_run(B, path, steps, warmup, cache):
+    """`warmup` + `steps` steps of the batched workload on `path`. One step =
+    build the batch (every problem's grid in one segmented build, the work
+    queue, the in-mask buffer), count every problem (one graph launch), write
+    every problem's pairs (one graph launch): all inside the timed region.
+    The tuner's choices (index_dims and short-circuit per d, kernel
+    schedule) are made in the first warmup step and cached in `cache`."""
+    import torch
+    from paper_2209_11287_amd import (selfjoin_batch_build, selfjoin_batch_count, selfjoin_batch_free,
+                                      selfjoin_batch_info, selfjoin_batch_pairs)
+    pts, eps = B["pts"], B["eps"]
+    buf = None
+    rec = []
+    ks = []
+    for i in range(warmup + steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b = selfjoin_batch_build(pts, eps, tune=True, tune_cache=cache)
+        totals, st = selfjoin_batch_count(b, path)
+        if buf is None:
+            buf = torch.empty((max(1, sum(totals)), 2), dtype=torch.int32, device="cuda:0")
+        _, st2 = selfjoin_batch_pairs(b, path, buf)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ks = sorted({(p.shape[1], selfjoin_batch_info(b, j)["index_dims"]) for j, p in enumerate(pts)})
+        selfjoin_batch_free(b)
+        if i >= warmup:
+            rec.append({"s": t1 - t0, "build_ms": st["ms_build"], "count_ms": st["ms"], "pairs_ms": st2["ms"],
+                        "pruned": st["tiles_pruned"], "pairs": sum(totals), "cand_eval": st["cand_eval"]})
+        log(f"[bench] batched {path} step {i}: {1e3 * (t1 - t0):.1f} ms (build {st['ms_build']:.1f}, "
+            f"count {st['ms']:.1f}, pairs {st2['ms']:.1f})")
+    del buf
+    torch.cuda.empty_cache()
+    sec = sum(r["s"] for r in rec) / len(rec)
+    avg = {k: round(sum(r[k] for r in rec) / len(rec), 3) for k in ("build_ms", "count_ms", "pairs_ms")}
+    return sec, avg, rec[-1], ks
+
+
+def batched_roofline(B, avg, last):
     count_s = avg["count_ms"] / 1e3
-    pair_bytes = 8 * last["pairs"] + sum(8 * p.shape[0] * p.shape[1] + 4 * p.shape[0] for p in pts)
-    out = {"metric": METRIC, "value": cref / sec, "unit": "distance evals/s", "n_gpus": 1, "steps": args.steps,
+    pair_bytes = 8 * last["pairs"] + sum(8 * p.shape[0] * p.shape[1] + 4 * p.shape[0] for p in B["pts"])
+    flops = B["flops"]
+    return {"kernel": "batched count graph (one tile kernel per d)", "bound": "mfma",
+            "achieved": round(flops / count_s / 1e12, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(flops / count_s / 1e12 / FP64_PEAK_TFLOPS, 4), "traffic": None,
+            "avg_launch_ms": avg["count_ms"], "algorithmic_flops_per_launch": flops,
+            "note": "2 d C_ref flops per problem over the count graph's device time",
+            "other_kernel": {"kernel": "batched pairs graph (in-mask expansion)", "bound": "hbm",
+                             "achieved": round(pair_bytes / (avg["pairs_ms"] / 1e3) / 1e9, 1),
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(pair_bytes / (avg["pairs_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                             "avg_launch_ms": avg["pairs_ms"]}}
+
+
+def batched_summary(paths, steps, warmup):
+    """The batched workload on each of `paths`: per-step time, phases and
+    the count graph's roofline."""
+    import tempfile
+    B = batched_setup()
+    cache = os.path.join(tempfile.mkdtemp(), "tune.txt")
+    out = {"workload": WORKLOAD_TEXT["batched"], "cand_ref_per_step": B["cref"], "steps": steps, "warmup": warmup,
+           "paths": {}}
+    for pth in paths:
+        sec, avg, last, ks = batched_run(B, pth, steps, warmup, cache)
+        out["paths"][pth] = {"ms_per_step": round(sec * 1e3, 3), "value": B["cref"] / sec, "phases_ms": avg,
+                             "pairs": last["pairs"], "tiles_pruned": last["pruned"], "tuned_index_dims": ks,
+                             "roofline": batched_roofline(B, avg, last)}
+    return out
+
+
+def batched_main(args):
+    """The batched workload as the measured one (--workload batched)."""
+    import tempfile
+    B = batched_setup()
+    cache = os.path.join(tempfile.mkdtemp(), "tune.txt")
+    sec, avg, last, ks = batched_run(B, args.path, args.steps, args.warmup, cache)
+    out = {"metric": METRIC, "value": B["cref"] / sec, "unit": "distance evals/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": WORKLOAD_TEXT["batched"], "path": args.path, "cand_ref_per_step": cref,
+           "config": {"workload": WORKLOAD_TEXT["batched"], "path": args.path, "cand_ref_per_step": B["cref"],
                       "pairs_per_step": last["pairs"], "tuned_index_dims": ks},
            "phases_ms": avg, "tiles_pruned": last["pruned"], "cand_eval": last["cand_eval"],
-           "roofline": {"kernel": "batched count graph (one tile kernel per d)", "bound": "mfma",
-                        "achieved": round(flops / count_s / 1e12, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": round(flops / count_s / 1e12 / FP64_PEAK_TFLOPS, 4), "traffic": None,
-                        "avg_launch_ms": avg["count_ms"], "algorithmic_flops_per_launch": flops,
-                        "note": "2 d C_ref flops per problem over the count graph's device time",
-                        "other_kernel": {"kernel": "batched pairs graph (in-mask expansion)", "bound": "hbm",
-                                         "achieved": round(pair_bytes / (avg["pairs_ms"] / 1e3) / 1e9, 1),
-                                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                         "frac": round(pair_bytes / (avg["pairs_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-                                         "avg_launch_ms": avg["pairs_ms"]}}}
+           "roofline": batched_roofline(B, avg, last)}
     if args.compare:
-        sec2, avg2, _, _ = run(args.compare)
-        out["compare"] = {"path": args.compare, "value": cref / sec2, "ms_per_step": round(sec2 * 1e3, 3),
+        sec2, avg2, _, _ = batched_run(B, args.compare, args.steps, args.warmup, cache)
+        out["compare"] = {"path": args.compare, "value": B["cref"] / sec2, "ms_per_step": round(sec2 * 1e3, 3),
                           "phases_ms": avg2, "speedup_of_headline": round(sec2 / sec, 3)}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = batched_cpu_baseline(ws, host, crefs)
+        out["cpu_baseline"] = batched_cpu_baseline(B["ws"], B["host"], B["crefs"])
     print(json.dumps(out))
 
 
@@ -471,6 +504,52 @@ def batched_cpu_baseline(ws, host, crefs, budget_evals=1.5e9):
             "sample": f"oracle self-join (build + count on {nthreads} threads, build + pair list on one) of "
                       f"{len(taken)} of {len(ws)} batched problems (in order, up to {budget_evals:.1e} candidate "
                       f"pairs in all; d in {ds})", "seconds": round(secs, 2)}
+
+
+def other_workloads(steps=2, warmup=1):
+    """Short timed passes of the other configurations, one stream each, so
+    that one run reports them all: the precision set (1M-point Gaussian
+    mixture, d = 16, 32, 64) on the FP64 MFMA, FP32 and split-BF16 MFMA and
+    FP64 vector paths, with the low-precision paths' measured largest
+    |Gram value - exact d^2| against their band; the 10M-point exponential
+    set on the FP64 MFMA, FP32 MFMA and FP64 vector paths; the batched
+    workload on both FP64 paths. Each: build + count + full pair list per
+    step (the batched form as in --workload batched)."""
+    import torch
+    from paper_2209_11287_amd import selfjoin_build_grid, selfjoin_free_grid, selfjoin_measure_error
+    out = {}
+    for wname, paths in (("prec", ["fp64_mfma", "fp32_mfma", "bf16x3_mfma", "fp64_valu"]),
+                         ("skewed", ["fp64_mfma", "fp32_mfma", "fp64_valu"])):
+        log(f"[bench] other workload {wname}")
+        inputs = load_inputs(datasets(wname))
+        cref_map, res = {}, {}
+        for pth in paths:
+            bufs = [None] * len(inputs)
+            sec, recs = timed(inputs, pth, steps, warmup, bufs, cref_map, 0, None)
+            cref = sum(r["cand_ref"] for r in recs[0])
+            res[pth] = {"ms_per_step": round(sec * 1e3, 3), "value": cref / sec,
+                        "per_set": [{"name": r["name"], "count_kernel_ms": round(r["count_kernel_ms"], 3),
+                                     "emit_kernel_ms": round(r["emit_kernel_ms"], 3),
+                                     "build_ms": round(r["build_ms"], 3), "rechecked": r["rechecked"],
+                                     "band_rel": r["band_rel"], "pairs": r["pairs"]} for r in recs[-1]]}
+            del bufs
+            torch.cuda.empty_cache()
+            if wname == "prec" and pth in ("fp32_mfma", "bf16x3_mfma"):
+                # the tiles' largest error before the recheck, against the band
+                for r, (w, _, xt) in zip(res[pth]["per_set"], inputs):
+                    g = selfjoin_build_grid(xt, w["eps"])
+                    err, band, viol = selfjoin_measure_error(g, pth)
+                    selfjoin_free_grid(g)
+                    r["max_abs_err_d2"] = err
+                    r["band_half_width"] = band
+                    r["band_violations"] = viol
+        out[wname] = {"workload": WORKLOAD_TEXT[wname], "cand_ref_per_step": sum(cref_map.values()),
+                      "steps": steps, "warmup": warmup, "streams": 1, "paths": res}
+        del inputs
+        torch.cuda.empty_cache()
+    log("[bench] other workload batched")
+    out["batched"] = batched_summary(["fp64_mfma", "fp64_valu"], steps, warmup)
+    return out
 
 
 def main():
@@ -586,6 +665,11 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(inputs)
+    if args.workload == "cfg2" and not args.no_other:
+        del bufs
+        inputs = None
+        torch.cuda.empty_cache()
+        out["other_workloads"] = other_workloads()
     print(json.dumps(out))
 
 
