@@ -237,7 +237,7 @@ def roofline(recs, path="fp64_mfma", which=None, workload="cfg2"):
         avg_ms = emit_ms / launches
         achieved = byts / launches / (avg_ms * 1e-3) / 1e9
         kname = {"fp64_mfma": "k_m64", "fp64_valu": "k_v64", "fp32_mfma": "k_lowp<F32>",
-                 "bf16_mfma": "k_lowp<BF16>", "bf16x3_mfma": "k_lowp<BF16X3>"}[path]
+                 "bf16_mfma": "k_lowp<BF16>", "bf16x3_mfma": "k_lowp<BF16X3>", "fp8_mfma": "k_lowp<FP8>"}[path]
         return {"kernel": kname + " emit (pairs)", "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic_for("emit", path, workload), "avg_launch_ms": round(avg_ms, 4),
@@ -246,9 +246,9 @@ def roofline(recs, path="fp64_mfma", which=None, workload="cfg2"):
     avg_ms = count_ms / launches
     achieved = flops / launches / (avg_ms * 1e-3) / 1e12
     peak = {"fp64_mfma": FP64_PEAK_TFLOPS, "fp64_valu": FP64_PEAK_TFLOPS, "fp32_mfma": 157.3,
-            "bf16_mfma": 2500.0, "bf16x3_mfma": 2500.0}[path]
+            "bf16_mfma": 2500.0, "bf16x3_mfma": 2500.0, "fp8_mfma": 5000.0}[path]
     kname = {"fp64_mfma": "k_m64", "fp64_valu": "k_v64", "fp32_mfma": "k_lowp<F32>",
-             "bf16_mfma": "k_lowp<BF16>", "bf16x3_mfma": "k_lowp<BF16X3>"}[path]
+             "bf16_mfma": "k_lowp<BF16>", "bf16x3_mfma": "k_lowp<BF16X3>", "fp8_mfma": "k_lowp<FP8>"}[path]
     return {"kernel": kname + " count", "bound": "mfma" if path != "fp64_valu" else "alu",
             "achieved": round(achieved, 3),
             "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
@@ -597,7 +597,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         # tiles in the path's precision, FP64 recheck of the band
-        "dtype": {"fp32_mfma": "f32+f64", "bf16_mfma": "bf16+f64", "bf16x3_mfma": "bf16x3+f64"}.get(args.path, "f64"),
+        "dtype": {"fp32_mfma": "f32+f64", "bf16_mfma": "bf16+f64", "bf16x3_mfma": "bf16x3+f64",
+                  "fp8_mfma": "fp8+f64"}.get(args.path, "f64"),
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "path": args.path, "cand_ref_per_step": cref, "pairs_per_step": pairs,

@@ -67,16 +67,21 @@ typedef enum {
  *                 about an order of magnitude narrower than SJ_BF16_MFMA's
  *                 (the dropped lo.lo products and the FP32 accumulation set
  *                 it), same FP64 recheck.
+ *  SJ_FP8_MFMA  : FP8 (E4M3) tiles, FP32 accumulation, as a filter: its band
+ *                 is wider than eps^2 (4 significant bits), so no pair is
+ *                 accepted by the tiles alone; they reject the candidates
+ *                 beyond eps^2 + Delta and every other pair takes the FP64
+ *                 recheck.
  * (Other MFMA precisions are the paper's future work, Section V.)
  *
  * Range guards. Every path returns the exact set for every finite input; a
  * path whose arithmetic could overflow on the given data hands the call to
  * the next path down, which returns the same set (sj_stats.path_run says
  * which ran):
- *  - FP32 / BF16 / split BF16: the tiles work on centred coordinates scaled
- *    by a power of two that puts eps in [1, 2); they run when eps is in
- *    [2^-500, 2^500] and every dimension's extent (max - min) is at most
- *    2^40 eps, otherwise FP64 MFMA runs;
+ *  - FP32 / BF16 / split BF16 / FP8: the tiles work on centred coordinates
+ *    scaled by a power of two that puts eps in [1, 2); they run when eps is
+ *    in [2^-500, 2^500] and every dimension's extent (max - min) is at most
+ *    2^40 eps (FP8: 100 eps), otherwise FP64 MFMA runs;
  *  - FP64 MFMA: runs when the largest squared norm of the rows centred on
  *    the bounding-box midpoint is at most 2^1000, otherwise FP64 VALU runs
  *    (the exact chain itself, which has no range limit). */
@@ -85,7 +90,8 @@ typedef enum {
     SJ_FP64_MFMA = 1,
     SJ_FP32_MFMA = 2,
     SJ_BF16_MFMA = 3,
-    SJ_BF16X3_MFMA = 4
+    SJ_BF16X3_MFMA = 4,
+    SJ_FP8_MFMA = 5
 } sj_path;
 
 /* Build options; pass NULL for defaults. */

@@ -15,7 +15,7 @@ SJ_ERR_HIP = 3
 SJ_ERR_CAPACITY = 4
 SJ_ERR_UNSUPPORTED = 5
 
-PATHS = {"fp64_valu": 0, "fp64_mfma": 1, "fp32_mfma": 2, "bf16_mfma": 3, "bf16x3_mfma": 4}
+PATHS = {"fp64_valu": 0, "fp64_mfma": 1, "fp32_mfma": 2, "bf16_mfma": 3, "bf16x3_mfma": 4, "fp8_mfma": 5}
 PATH_NAMES = {v: k for k, v in PATHS.items()}
 
 # Every symbol include/selfjoin.h declares.

@@ -308,7 +308,7 @@ static void compute_counts(Grid &g, sj_path path, bool timed, CountRun &cr, hipS
     cr.ran = true;
     cr.hc = read_counters(hctr);
     cr.band_rel = ro.band_rel;
-    if (path == SJ_FP32_MFMA || path == SJ_BF16_MFMA || path == SJ_BF16X3_MFMA) {
+    if (is_lowp(path)) {
         const double sc = lowp_scale(g);  // the band is in the tiles' scaled units
         cr.band_rel = g.eps2 > 0 ? cr.hc.max_delta / (g.eps2 * sc * sc) : 0.0;
     }
@@ -319,7 +319,7 @@ static void compute_counts(Grid &g, sj_path path, bool timed, CountRun &cr, hipS
 // The path that runs a request: unsupported d for the low-precision tiles is
 // an error; otherwise the range guards pick the first exact path that fits.
 static sj_path path_for(const Grid &g, sj_path path) {
-    if ((path == SJ_FP32_MFMA || path == SJ_BF16_MFMA || path == SJ_BF16X3_MFMA) && g.d > kLpMaxD)
+    if (is_lowp(path) && g.d > kLpMaxD)
         throw Unsupported{"FP32/BF16 MFMA paths support d <= 64"};
     return effective_path(g, path);
 }
@@ -470,8 +470,7 @@ static sj_status invalid(const char *msg) {
 }
 
 static bool valid_path(sj_path p) {
-    return p == SJ_FP64_VALU || p == SJ_FP64_MFMA || p == SJ_FP32_MFMA || p == SJ_BF16_MFMA ||
-           p == SJ_BF16X3_MFMA;
+    return p == SJ_FP64_VALU || p == SJ_FP64_MFMA || is_lowp(p);
 }
 
 extern "C" {
@@ -652,7 +651,7 @@ sj_status selfjoin_pairs(sj_grid *gh, sj_path path, int64_t cursor, int32_t *pai
         const float ms = tm.stop(s);  // synchronises the stream
         const HostCounters he = read_counters(h);
         double brel = re.band_rel;
-        if (run == SJ_FP32_MFMA || run == SJ_BF16_MFMA || run == SJ_BF16X3_MFMA) {
+        if (is_lowp(run)) {
             const double sc = lowp_scale(g);
             brel = g.eps2 > 0 ? he.max_delta / (g.eps2 * sc * sc) : 0.0;
         }
@@ -716,7 +715,7 @@ sj_status selfjoin_count_noalloc(const double *points, int64_t n, int32_t d, dou
     if (n > 0 && !points) return invalid("points is NULL");
     if (!valid_path(path)) return invalid("unknown path");
     if (!total) return invalid("total is NULL");
-    if ((path == SJ_FP32_MFMA || path == SJ_BF16_MFMA || path == SJ_BF16X3_MFMA) && d > kLpMaxD) {
+    if (is_lowp(path) && d > kLpMaxD) {
         set_error("FP32/BF16 MFMA paths support d <= 64");
         return SJ_ERR_UNSUPPORTED;
     }

@@ -335,7 +335,11 @@ double fp64_mfma_delta(const Grid &g);
 // for a path whose guard fails runs the next path that passes (low
 // precision -> FP64 MFMA -> FP64 VALU, which is the exact chain itself).
 bool m64_in_range(const Grid &g);
-bool lowp_in_range(const Grid &g);
+bool lowp_in_range(const Grid &g, sj_path path);
+// The low-precision tile paths (FP32, BF16, split BF16, FP8: d <= 64).
+inline bool is_lowp(sj_path p) {
+    return p == SJ_FP32_MFMA || p == SJ_BF16_MFMA || p == SJ_BF16X3_MFMA || p == SJ_FP8_MFMA;
+}
 double lowp_scale(const Grid &g);
 sj_path effective_path(const Grid &g, sj_path requested);
 

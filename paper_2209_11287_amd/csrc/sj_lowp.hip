@@ -66,7 +66,7 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef short short8_t __attribute__((ext_vector_type(8)));
 
 enum { MODE_COUNT = 0, MODE_EMIT = 1, MODE_MEASURE = 2 };
-enum { PREC_F32 = 0, PREC_BF16 = 1, PREC_BF16X3 = 2 };
+enum { PREC_F32 = 0, PREC_BF16 = 1, PREC_BF16X3 = 2, PREC_FP8 = 3 };
 
 struct LpGrid {
     const double *xs;
@@ -136,11 +136,36 @@ __device__ __forceinline__ unsigned short f32_to_bf16(float f) {
 }
 __device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
 
+// FP64 -> FP8 E4M3 (the OCP "e4m3fn" form the gfx950 FP8 MFMA reads: bias
+// 7, 3 mantissa bits, largest finite 448, subnormals down to 2^-9), rounded
+// to nearest even in one step; |y| must be below 464 (the range guard keeps
+// the scaled values far below). Returns the rounded value and its bits.
+__device__ __forceinline__ double fp8_round(double y, unsigned &bits) {
+    const double ay = fabs(y);
+    const unsigned sign = y < 0.0 ? 0x80u : 0u;
+    if (ay == 0.0) {
+        bits = 0u;
+        return 0.0;
+    }
+    const int e = ilogb(ay);
+    const double spacing = e < -6 ? 0x1p-9 : ldexp(1.0, e - 3);
+    const double q = rint(ay / spacing) * spacing;  // exact quotient (power of two), RNE
+    unsigned code = 0u;
+    if (q != 0.0) {
+        const int eq = ilogb(q);
+        if (eq < -6) code = (unsigned)(q * 0x1p9);  // subnormal: exponent field 0
+        else code = ((unsigned)(eq + 7) << 3) | ((unsigned)(q * ldexp(1.0, 3 - eq)) - 8u);
+    }
+    bits = code ? (sign | code) : 0u;
+    return sign ? -q : q;
+}
+
 // Rounds an FP64 value to the tile precision; returns the rounded value as
 // a double (exact) and its storage bits (split BF16: hi in the low half, lo
 // in the high half; the value is hi + lo).
 template <int PREC>
 __device__ __forceinline__ double round_in(double y, unsigned &bits) {
+    if constexpr (PREC == PREC_FP8) return fp8_round(y, bits);
     const float f = (float)y;  // RNE
     if (PREC == PREC_F32) {
         bits = __float_as_uint(f);
@@ -169,12 +194,18 @@ __device__ __forceinline__ double lp_delta(double a2, double eps, double eps2, i
     const double u64 = 0x1p-53, u32 = 0x1p-24;
     // input rounding unit: FP32; BF16 via FP32 (two roundings); split BF16:
     // |fl32(y) - hi| <= 2^-8 |fl32(y)| and lo rounds that to 2^-8 of itself
-    const double uin = PREC == PREC_F32 ? 0x1p-24 : PREC == PREC_BF16 ? (0x1p-8 + 0x1p-24) : (0x1p-16 + 0x1p-24 + 0x1p-39);
+    // (FP8: relative 2^-4 for normal values, from FP64 in one rounding)
+    const double uin = PREC == PREC_F32    ? 0x1p-24
+                       : PREC == PREC_BF16 ? (0x1p-8 + 0x1p-24)
+                       : PREC == PREC_FP8  ? 0x1p-4
+                                           : (0x1p-16 + 0x1p-24 + 0x1p-39);
     const double eta = uin + u64 + uin * u64;
     const double ua = 2.0 * 0x1p-24;
     const double a = sqrt(a2 * (1.0 + 1e-12));
     const double epsp = eps * (1.0 + (d + 4) * u64);
-    const double e = eta * (2.0 * a + epsp) / (1.0 - 2.0 * eta) + 0x1p-122;  // conversion error at |c'| = a + tau
+    // FP8 subnormals: at most 2^-10 per coordinate, 2^-7 per vector of d <= 64, for q' and c'
+    const double e = eta * (2.0 * a + epsp) / (1.0 - 2.0 * eta) + 0x1p-122 +
+                     (PREC == PREC_FP8 ? 0x1p-6 : 0.0);  // conversion error at |c'| = a + tau
     const double tau = epsp + e;
     const double b = a + tau;  // candidates beyond cannot be near the threshold
     const double A2 = a * a, B2 = b * b;
@@ -212,13 +243,19 @@ struct Prec<PREC_BF16X3> {
 
 // K padded to the instruction's K-step; LDS row strides padded against bank
 // conflicts.
+template <>
+struct Prec<PREC_FP8> {
+    static constexpr int kstep = 32;
+    typedef long operand_t;  // 8 FP8 values
+};
+
 template <int PREC>
 constexpr int lp_kmax() {
     return PREC == PREC_F32 ? kLpMaxD : ((kLpMaxD + 31) / 32) * 32;
 }
 template <int PREC>
 constexpr int lp_stride() {  // in 32-bit words
-    return PREC == PREC_F32 ? lp_kmax<PREC>() + 1 : lp_kmax<PREC>() / 2 + 4;
+    return PREC == PREC_F32 ? lp_kmax<PREC>() + 1 : PREC == PREC_FP8 ? lp_kmax<PREC>() / 4 + 2 : lp_kmax<PREC>() / 2 + 4;
 }
 
 template <int PREC>
@@ -235,6 +272,16 @@ __device__ __forceinline__ float4_t lp_mfma<PREC_BF16>(short8_t a, short8_t b, f
 template <>
 __device__ __forceinline__ float4_t lp_mfma<PREC_BF16X3>(short8_t a, short8_t b, float4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+template <>
+__device__ __forceinline__ float4_t lp_mfma<PREC_FP8>(long a, long b, float4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+}
+
+// Reads the 8 FP8 values of one lane's K slice (8-byte aligned) from a row of bytes.
+__device__ __forceinline__ long lds_fp8x8(const uint32_t *w) {
+    return (long)((unsigned long long)w[0] | ((unsigned long long)w[1] << 32));
 }
 
 // Reads the 8 BF16 values of one lane's K slice from a row of 16-bit halves.
@@ -257,7 +304,7 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
     __shared__ double xr[kLpMaxD];                   // reference row
     // plain BF16 rechecks tens of percent of its pairs: it keeps the FP64
     // rows in LDS; the narrower-band paths read them from global memory
-    constexpr bool kRowsInLds = PREC == PREC_BF16;
+    constexpr bool kRowsInLds = PREC == PREC_BF16 || PREC == PREC_FP8;
     __shared__ double f64t[kRowsInLds ? kTC : 1][kLpMaxD + 1];
     __shared__ uint32_t lpt[kTC * STR];              // rounded, centred rows (split BF16: hi)
     __shared__ uint32_t lptl[PREC == PREC_BF16X3 ? kTC * STR : 1];  // split BF16: lo
@@ -309,6 +356,21 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
                     v = -2.0f * __uint_as_float(bits);
                 }
                 aq[s] = v;
+            } else if constexpr (PREC == PREC_FP8) {
+                unsigned long long v = 0ull;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int k = KSTEP * s + 8 * g + e;
+                    if (s < ks && j < nq && k < d) {
+                        unsigned bits;
+                        const double y = round_in<PREC>(__dsub_rn(qrow[k], xr[k]) * G.sc, bits);
+                        nq_part = __fma_rn(y, y, nq_part);
+                        unsigned b2;
+                        (void)fp8_round(-2.0 * y, b2);  // exact: -2y is an FP8 value below the range limit
+                        v |= (unsigned long long)b2 << (8 * e);
+                    }
+                }
+                aq[s] = (long)v;
             } else {
                 short8_t v, vl;
 #pragma unroll
@@ -450,6 +512,8 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
                     np = __fma_rn(y, y, np);
                     if constexpr (PREC == PREC_F32) {
                         lpt[srow * STR + k] = bits;
+                    } else if constexpr (PREC == PREC_FP8) {
+                        reinterpret_cast<unsigned char *>(lpt + srow * STR)[k] = (unsigned char)bits;
                     } else {
                         unsigned short *h = reinterpret_cast<unsigned short *>(lpt + srow * STR);
                         h[k] = (unsigned short)(bits & 0xffffu);
@@ -496,15 +560,19 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
 #pragma unroll
                 for (int s = 0; s < (KMAX + KSTEP - 1) / KSTEP; ++s) {
                     if (s >= ks) break;  // block-uniform
-                    const int o = crow * STR + (KSTEP * s + 8 * g) / 2;
-                    const short8_t bh = lds_bf16x8(lpt + o);
-                    if constexpr (PREC == PREC_BF16) {
-                        acc = lp_mfma<PREC>(aq[s], bh, acc);
+                    if constexpr (PREC == PREC_FP8) {
+                        acc = lp_mfma<PREC>(aq[s], lds_fp8x8(lpt + crow * STR + (KSTEP * s + 8 * g) / 4), acc);
                     } else {
-                        const short8_t bl = lds_bf16x8(lptl + o);
-                        acc = lp_mfma<PREC>(aql[s], bh, acc);
-                        acc = lp_mfma<PREC>(aq[s], bl, acc);
-                        acc = lp_mfma<PREC>(aq[s], bh, acc);
+                        const int o = crow * STR + (KSTEP * s + 8 * g) / 2;
+                        const short8_t bh = lds_bf16x8(lpt + o);
+                        if constexpr (PREC == PREC_BF16) {
+                            acc = lp_mfma<PREC>(aq[s], bh, acc);
+                        } else {
+                            const short8_t bl = lds_bf16x8(lptl + o);
+                            acc = lp_mfma<PREC>(aql[s], bh, acc);
+                            acc = lp_mfma<PREC>(aq[s], bl, acc);
+                            acc = lp_mfma<PREC>(aq[s], bh, acc);
+                        }
                     }
                 }
             }
@@ -637,6 +705,8 @@ void launch_lowp(const Grid &g, sj_path path, const LpOut &R, int nblocks, hipSt
         hipLaunchKernelGGL((k_lowp<PREC_F32, MODE>), dim3(nblocks), dim3(kThreads), 0, s, G, R);
     else if (path == SJ_BF16_MFMA)
         hipLaunchKernelGGL((k_lowp<PREC_BF16, MODE>), dim3(nblocks), dim3(kThreads), 0, s, G, R);
+    else if (path == SJ_FP8_MFMA)
+        hipLaunchKernelGGL((k_lowp<PREC_FP8, MODE>), dim3(nblocks), dim3(kThreads), 0, s, G, R);
     else
         hipLaunchKernelGGL((k_lowp<PREC_BF16X3, MODE>), dim3(nblocks), dim3(kThreads), 0, s, G, R);
     SJ_HIP(hipGetLastError());
@@ -646,9 +716,10 @@ void launch_lowp(const Grid &g, sj_path path, const LpOut &R, int nblocks, hipSt
 
 double lowp_scale(const Grid &g) { return std::ldexp(1.0, -std::ilogb(g.eps)); }
 
-bool lowp_in_range(const Grid &g) {
+bool lowp_in_range(const Grid &g, sj_path path) {
     if (!(g.eps >= 0x1p-500 && g.eps <= 0x1p500)) return false;
-    const double lim = std::ldexp(g.eps, 40);
+    // FP8: scaled centred values (|y| < 2 extent / eps) and -2y stay below 448
+    const double lim = path == SJ_FP8_MFMA ? 100.0 * g.eps : std::ldexp(g.eps, 40);
     for (int j = 0; j < g.d; ++j)
         if (!(g.hi[j] - g.lo[j] <= lim)) return false;  // also false for an infinite extent
     return true;

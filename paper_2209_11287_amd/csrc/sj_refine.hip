@@ -1391,7 +1391,7 @@ bool m64_in_range(const Grid &g) { return g.nmax >= 0.0 && g.nmax <= 0x1p1000; }
 
 sj_path effective_path(const Grid &g, sj_path requested) {
     sj_path p = requested;
-    if ((p == SJ_FP32_MFMA || p == SJ_BF16_MFMA || p == SJ_BF16X3_MFMA) && g.d <= kLpMaxD && !lowp_in_range(g))
+    if (is_lowp(p) && g.d <= kLpMaxD && !lowp_in_range(g, p))
         p = SJ_FP64_MFMA;
     if (p == SJ_FP64_MFMA && !m64_in_range(g)) p = SJ_FP64_VALU;
     return p;

@@ -10,8 +10,8 @@ from workloads import generators as gen
 
 pytestmark = pytest.mark.gpu
 
-PATHS = ["fp64_valu", "fp64_mfma", "fp32_mfma", "bf16_mfma", "bf16x3_mfma"]
-LOWP = ["fp32_mfma", "bf16_mfma", "bf16x3_mfma"]
+PATHS = ["fp64_valu", "fp64_mfma", "fp32_mfma", "bf16_mfma", "bf16x3_mfma", "fp8_mfma"]
+LOWP = ["fp32_mfma", "bf16_mfma", "bf16x3_mfma", "fp8_mfma"]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -286,7 +286,7 @@ def test_lowp_rejects_large_d(path):
     sj.close()
 
 
-@pytest.mark.parametrize("path", ["fp64_mfma", "fp32_mfma", "bf16_mfma", "bf16x3_mfma"])
+@pytest.mark.parametrize("path", ["fp64_mfma", "fp32_mfma", "bf16_mfma", "bf16x3_mfma", "fp8_mfma"])
 def test_mfma_error_within_band(path):
     import torch
     from paper_2209_11287_amd import SelfJoin, selfjoin_measure_error
