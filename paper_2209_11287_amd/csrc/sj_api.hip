@@ -420,7 +420,7 @@ size_t lean_need(int64_t n, int32_t d) {
     need += 2 * A((N + N / kTileQ + 2) * 4);                                         // flags, ids
     need += A(8 * (N + 1)) + 4 * A(4 * (N + 2)) + 3 * scan(N + 1);                   // cells, lines
     need += A(8 * (items_ub + 1)) + 2 * A(4 * (items_ub + 1)) + A(16 * items_ub);    // items
-    need += A(8 * items_ub * nr) + A(4 * (size_t)kLeanLineTable) + 2 * scan(items_ub + 1);
+    need += A(8 * items_ub * nr) * (d > 4 ? 2 : 1) + A(4 * (size_t)kLeanLineTable) + 2 * scan(items_ub + 1);
     need += A(4 * (N + 1)) + A(8 * (N + 1)) + A(sizeof(DevCounters)) + scan(N + 1);  // counts
     return need;
 }

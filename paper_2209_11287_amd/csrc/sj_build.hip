@@ -1036,6 +1036,42 @@ __global__ void k_item_ranges(const Item *__restrict__ items, const int32_t *__r
     block_add(acc, cand_items);
 }
 
+// d > 4: the ranges of every item become the union of its block item's
+// (up to kBlockItems consecutive items of one line, starting where bflag is
+// set): per neighbour line the smallest begin and largest end of the
+// block's non-empty ranges. A superset of each item's own candidates (the
+// tiles decide every pair), and the same list for the whole block item, so
+// the FP64 MFMA count can stage each candidate tile once for all four items.
+// Also the candidate pairs the items then see.
+__global__ void k_unite_ranges(const Item *__restrict__ items, const int32_t *__restrict__ nitems_p,
+                               const int32_t *__restrict__ bflag, int nranges, const Range *__restrict__ in,
+                               Range *__restrict__ out, unsigned long long *__restrict__ cand_items) {
+    const int64_t I = *nitems_p;
+    unsigned long long acc = 0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < I * nranges;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t it = t / nranges;
+        const int o = (int)(t - it * nranges);
+        int64_t b0 = it;
+        while (b0 > 0 && !bflag[b0]) --b0;
+        int64_t b1 = b0 + 1;
+        while (b1 < I && !bflag[b1]) ++b1;
+        Range u{0, 0};
+        bool any = false;
+        for (int64_t i = b0; i < b1; ++i) {
+            const Range r = in[i * nranges + o];
+            if (r.end <= r.begin) continue;
+            u.begin = any ? min(u.begin, r.begin) : r.begin;
+            u.end = any ? max(u.end, r.end) : r.end;
+            any = true;
+        }
+        out[t] = u;
+        const Item m = items[it];
+        acc += (unsigned long long)(m.qend - m.qbegin) * (unsigned long long)(u.end - u.begin);
+    }
+    block_add(acc, cand_items);
+}
+
 // Mask slots of each work item: its candidates (the ranges in order) form one
 // packed list of ceil(sum of range lengths / 16) tiles, and its in-masks take
 // whole groups of 16 tile slots (64 words of 64 bits per group); entry nitems
@@ -1385,7 +1421,7 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     if (g.npc > 0) g.pn = dev_alloc_n<double>(rows * g.npc, s);
     g.dev_nmax = dev_alloc_n<double>(1, s);
     int32_t *counters = dev_alloc_n<int32_t>(4, s);                    // ncells, nlines, nitems
-    unsigned long long *acc = dev_alloc_n<unsigned long long>(2, s);  // [0] item candidates, [1] tiles
+    unsigned long long *acc = dev_alloc_n<unsigned long long>(3, s);  // item candidates, tiles, united candidates
     // padding rows, nmax (n = 0), counters: one launch
     fill_zero_many({{g.xs + (size_t)n * g.dp, (size_t)kRowPad * g.dp * sizeof(double)},
                     {g.xa + (size_t)n * g.da, (size_t)kRowPad * g.da * sizeof(double)},
@@ -1393,7 +1429,7 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
                     {g.pn ? g.pn + (size_t)n * g.npc : nullptr, (size_t)kRowPad * g.npc * sizeof(double)},
                     {g.dev_nmax, sizeof(double)},
                     {counters, 4 * sizeof(int32_t)},
-                    {acc, 2 * sizeof(unsigned long long)}},
+                    {acc, 3 * sizeof(unsigned long long)}},
                    s);
     if (n > 0) {
         const unsigned nb = d <= 4 ? std::min(blocks_for(4 * n), 4096u) : blocks_for(n);
@@ -1486,6 +1522,15 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
                            g.cell_start, counters + 0, range_geom(g), g.line_table, g.line_first, key_a,
                            g.ranges, acc);
         SJ_HIP(hipGetLastError());
+        if (d > 4) {  // block items share one candidate list
+            Range *united = dev_alloc_n<Range>((size_t)items_ub * g.nranges, s);
+            hipLaunchKernelGGL(k_unite_ranges, dim3(2048), dim3(kThreads), 0, s, g.item, counters + 2, flag,
+                               g.nranges, g.ranges, united, acc + 2);
+            SJ_HIP(hipGetLastError());
+            dev_free(g.ranges, s);
+            g.ranges = united;
+            g.united = true;
+        }
         // tile offsets of the items (for the per-tile in-masks of the count pass)
         hipLaunchKernelGGL(k_item_tiles, dim3(blocks_for(items_ub + 1)), dim3(kThreads), 0, s, g.ranges,
                            counters + 2, g.nranges, item_tiles);
@@ -1498,7 +1543,7 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     int32_t hc[4] = {0, 0, 0, 0};
     int32_t herr = 0;
     double hn = 0.0;
-    unsigned long long hacc[2] = {0, 0};
+    unsigned long long hacc[3] = {0, 0, 0};
     if (n > 0) {
         SJ_HIP(hipMemcpyAsync(hc, counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         SJ_HIP(hipMemcpyAsync(&herr, os_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -1521,7 +1566,7 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     g.nblocks = hc[3];
     g.nmax = hn;
     g.cand_ref = -1;  // computed on request (grid_cref)
-    g.cand_items = (int64_t)hacc[0];
+    g.cand_items = (int64_t)(g.united ? hacc[2] : hacc[0]);
     g.tiles = (int64_t)hacc[1];
 
     dev_free(acc, s);

@@ -126,6 +126,9 @@ struct DevGrid {
     int64_t n;
     int32_t d, dp, da, nranges;
     int32_t nitems;
+    const int32_t *blocks;  // first item of each block item (+ end), or null
+    int32_t nblocks;
+    int32_t united;         // the items of each block item share one candidate list
     int32_t npc;   // prefix norms per row: da / 4 - 1 for d > 4, else 0
     int32_t sc;    // short-circuit (sj_opts.short_circuit): 0 = default schedule, -1 = off, k > 0 = every k K-steps
     double eps2;
@@ -181,6 +184,7 @@ struct Grid {
     int32_t dim_order = 0;  // sj_opts.dim_order
     int32_t sc = 0;         // sj_opts.short_circuit: 0 = default schedule, -1 = off, k > 0 = every k K-steps
     int32_t npc = 0;        // prefix norms per row in pn
+    bool united = false;    // d > 4: every item's ranges are its block item's union
 
     // device buffers
     double *xs = nullptr;        // sorted original coordinates, n x dp (+pad rows)

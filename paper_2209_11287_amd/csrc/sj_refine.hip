@@ -744,6 +744,191 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
     }
 }
 
+// Count with LDS-shared candidate tiles, d = 5 .. 16 (2 to 4 K-steps). A
+// block is one block item: up to 4 consecutive work items of one line, one
+// per wave, which carry the same candidate list (for d > 4 the build unites
+// the ranges of a block item's items). Each chunk of 4 tiles is staged once:
+// wave w loads the B operand (and the columns' norms and prefix norms) of
+// tile w of the chunk into LDS, and every wave then runs its 16 queries
+// against all four tiles from LDS, so a candidate row leaves L2 once per 64
+// queries instead of once per 16. The next chunk's loads are in flight while
+// the current one computes; one barrier per chunk. Waves of a block without
+// an item (a line's last block item) stage and wait like the others. The
+// classification, in-masks, short-circuit and counts are those of m64_item.
+constexpr int m64s_lds_doubles(int ks) { return 2 * 4 * (ks * 64 + 32); }
+
+template <int KS, bool SLOT>
+__device__ __forceinline__ void m64_block_count(const DevGrid &G, const RefOut &R, double delta, int bi,
+                                                double *__restrict__ lds) {
+    const int lane = threadIdx.x & 63;
+    const int wv = uniform_i32(threadIdx.x >> 6);
+    const int ib = uniform_i32(G.blocks[bi]), ie = uniform_i32(G.blocks[bi + 1]);
+    const bool active = ib + wv < ie;  // wave-uniform
+    const int it = active ? ib + wv : ib;
+    const Item I = G.items[it];
+    const int q0 = uniform_i32(I.qbegin);
+    const int nq = active ? uniform_i32(I.qend - I.qbegin) : 0;
+    const int d = G.d, da = G.da;
+    const int j = lane & 15, g = lane >> 4;
+    const int qa = q0 + (j < nq ? j : 0);
+    const double eps2 = G.eps2;
+    using Tile = M64Tile<KS, KS>;
+    double aq[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        const int kk = 4 * s + g;
+        aq[s] = (j < nq && kk < d) ? -2.0 * G.xa[(int64_t)qa * da + kk] : ((SLOT && kk == d) ? 1.0 : 0.0);
+    }
+    M64Thr th;
+    double4_t cinit = (double4_t){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = g + 4 * r;
+        const bool ok = i < nq;
+        const double nq_r = ok ? G.nrm[q0 + i] : 0.0;
+        th.nq[r] = nq_r;
+        th.lo[r] = ok ? eps2 - nq_r - delta : -INFINITY;
+        th.hi[r] = ok ? eps2 - nq_r + delta : -INFINITY;
+        if (!SLOT) cinit[r] = ok ? nq_r : INFINITY;
+    }
+    th.clo = eps2 - delta;
+    th.chi = eps2 + delta;
+    const bool sc_on = G.sc != -1;
+    constexpr int KC = KS / 2;
+    double tq[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = g + 4 * r;
+        tq[r] = (sc_on && i < nq) ? eps2 + delta + (SLOT ? 0.0 : th.nq[r]) - G.pn[(int64_t)(q0 + i) * G.npc + (KC - 1)]
+                                  : -INFINITY;
+    }
+    unsigned long long npruned = 0, band = 0, band_in = 0;
+    int tot[4] = {0, 0, 0, 0};
+    const bool rec = R.masks != nullptr && active;
+    const int64_t tile_base = rec ? G.tile_off[it] : 0;
+    unsigned long long nib = 0;
+    unsigned nacc = 0;
+    // the block's list: every wave walks the first item's (united) ranges
+    const ItemRanges rg = load_ranges(G, ib, lane);
+    CandList L;
+    cand_init(L, rg, lane, q0);
+    const int ntiles = L.ntiles;  // the same in every wave of the block
+    const int nchunks = (ntiles + 3) >> 2;
+    int flushed = 0;
+    auto group_done = [&](int k0) {
+        const int tg = min(ntiles - k0, 16);
+        if (tg & 7) nib_flush(nib, nacc, tg & 7, (tg - 1) >> 3);
+        nibble_count(nib, tot);
+        if (rec) R.masks[(tile_base + k0) * 4 + lane] = nib;
+        nib = 0;
+        flushed = k0 + 16;
+    };
+    int cc[4], cn[4];  // sorted indices of the lane's column in the current / next chunk's tiles
+    auto chunk = [&](int c, int out[4]) {
+        int P[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) P[t] = 64 * c + 16 * t + j;
+        cand_chunk<4>(L, c, P, out);
+    };
+    // staging registers: this wave's tile of a chunk (tile wv)
+    double sb[KS], sx = 0.0;
+    auto stage_load = [&](const int col4[4]) {
+        const int col = wv == 0 ? col4[0] : wv == 1 ? col4[1] : wv == 2 ? col4[2] : col4[3];
+        const double *__restrict__ brow = G.xa + (int64_t)col * da + g;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) sb[s] = brow[4 * s];
+        // lanes of row group 0: the column's norm (no slot); group 1: its prefix norm
+        if (g == 0) sx = SLOT ? 0.0 : G.nrm[col];
+        else if (g == 1) sx = G.pn[(int64_t)col * G.npc + (KC - 1)];
+    };
+    auto stage_store = [&](int buf) {
+        double *t = lds + (buf * 4 + wv) * (KS * 64 + 32);
+#pragma unroll
+        for (int s = 0; s < KS; ++s) t[s * 64 + lane] = sb[s];
+        if (g < 2) t[KS * 64 + g * 16 + j] = sx;
+    };
+    if (nchunks > 0) {
+        chunk(0, cc);
+        stage_load(cc);
+        stage_store(0);
+    }
+    __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {  // block-uniform trip count
+        const int buf = c & 1;
+        const bool more = c + 1 < nchunks;
+        if (more) {
+            chunk(c + 1, cn);
+            stage_load(cn);  // in flight during this chunk's tiles
+        }
+        if (active) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int k = 4 * c + t;
+                if (k >= ntiles) break;
+                const double *tl = lds + (buf * 4 + t) * (KS * 64 + 32);
+                Tile T;
+                T.c = cc[t];
+                T.n = min(16, L.total - 16 * k);
+#pragma unroll
+                for (int s = 0; s < KS; ++s) T.b[s] = tl[s * 64 + lane];
+                T.nc = tl[KS * 64 + j];
+                T.pn = tl[KS * 64 + 16 + j];
+                double4_t a = cinit;
+#pragma unroll
+                for (int s = 0; s < KC; ++s) a = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], T.b[s], a, 0, 0, 0);
+                bool far = false;
+                if (sc_on) {
+                    const bool f = j >= T.n || (a[0] > tq[0] - T.pn && a[1] > tq[1] - T.pn && a[2] > tq[2] - T.pn &&
+                                                a[3] > tq[3] - T.pn);
+                    far = __ballot(!f) == 0ull;
+                }
+                if (far) {
+                    ++npruned;
+                    nacc <<= 4;
+                } else {
+#pragma unroll
+                    for (int s = KC; s < KS; ++s) a = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], T.b[s], a, 0, 0, 0);
+                    unsigned long long w[4];
+                    m64_words<SLOT, KS>(a, T, g, q0, th, G, band, band_in, w);
+                    nib_push(nacc, w);
+                }
+                if ((k & 7) == 7) nib_flush(nib, nacc, 8, (k >> 3) & 1);
+                if ((k & 15) == 15) group_done(k - 15);
+            }
+        }
+        if (more) stage_store(buf ^ 1);
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 4; ++t) cc[t] = cn[t];
+    }
+    if (!active) return;
+    if (flushed < ntiles) group_done(flushed);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        int v = tot[r];
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 8);
+        if (j == 0 && g + 4 * r < nq) R.cnt[q0 + g + 4 * r] = v;
+    }
+    if (lane == 0) {
+        if (npruned) atomicAdd(&R.ctr->pruned, npruned);
+        if (band) {
+            atomicAdd(&R.ctr->rechecked, band);
+            atomicAdd(&R.ctr->rechecked_in, band_in);
+        }
+    }
+}
+
+template <int KS, bool SLOT>
+__global__ __launch_bounds__(kThreads) void k_m64s(DevGrid G, RefOut R, double delta, int nblocks) {
+    __shared__ double lds[m64s_lds_doubles(KS)];
+    const int bi = xcd_block(blockIdx.x, gridDim.x);
+    if (bi >= nblocks) return;  // whole block
+    m64_block_count<KS, SLOT>(G, R, delta, bi, lds);
+}
+
 template <int KS, bool SLOT, int MODE>
 // d <= 4 (one K-step): six waves per SIMD (at most 80 VGPRs; a few spill in
 // the d % 4 = 0 form) hide more of the candidate-load latency than five
@@ -1356,6 +1541,9 @@ DevGrid dev_grid(const Grid &g) {
     G.da = g.da;
     G.nranges = g.nranges;
     G.nitems = (int32_t)g.items;
+    G.blocks = g.blocks;
+    G.nblocks = (int32_t)g.nblocks;
+    G.united = g.united ? 1 : 0;
     G.npc = g.npc;
     G.sc = g.npc > 0 ? g.sc : -1;
     G.eps2 = g.eps2;
@@ -1427,6 +1615,24 @@ void launch_m64(const Grid &g, const RefOut &R, int nitems, double delta, hipStr
     if (!blocks) return;
     const bool slot = (g.d & 3) != 0;
     const int ks = g.da >> 2;
+    // count of every item, 2 to 4 K-steps, united block items: LDS-shared tiles
+    if (MODE == MODE_COUNT && g.united && g.nblocks > 0 && ks >= 2 && ks <= 4 && R.item_lo == 0 &&
+        nitems == (int)g.items) {
+        const unsigned nb = (unsigned)g.nblocks;
+#define SJ_M64S(KSV, SL) hipLaunchKernelGGL((k_m64s<KSV, SL>), dim3(nb), dim3(kThreads), 0, s, G, R, delta, (int)nb)
+        if (slot) {
+            if (ks == 2) SJ_M64S(2, true);
+            else if (ks == 3) SJ_M64S(3, true);
+            else SJ_M64S(4, true);
+        } else {
+            if (ks == 2) SJ_M64S(2, false);
+            else if (ks == 3) SJ_M64S(3, false);
+            else SJ_M64S(4, false);
+        }
+#undef SJ_M64S
+        SJ_HIP(hipGetLastError());
+        return;
+    }
 #define SJ_M64(KSV, SL) hipLaunchKernelGGL((k_m64<KSV, SL, MODE>), dim3(blocks), dim3(kThreads), 0, s, G, R, delta)
     if (slot) {
         switch (ks) {
