@@ -41,6 +41,26 @@ __global__ void k_item_cost(const Item *__restrict__ items, const Range *__restr
     val[base + it] = (int32_t)(base + it);
 }
 
+// Sort key of each block item of a problem counted with LDS-shared tiles
+// (FP64 MFMA, d = 5 .. 16): d in the high bits, then descending cost (its
+// list's tiles x K-steps x items); value = global block index.
+__global__ void k_block_cost(const int32_t *__restrict__ blocks, int item_base, const Range *__restrict__ ranges,
+                             int nranges, int nb, int ksteps, int d, int64_t base, unsigned long long *__restrict__ key,
+                             int32_t *__restrict__ val) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const int it0 = blocks[b] - item_base, ni = blocks[b + 1] - blocks[b];
+    unsigned long long c = 0;
+    for (int o = 0; o < nranges; ++o) {
+        const Range r = ranges[(int64_t)it0 * nranges + o];
+        c += (unsigned long long)(r.end > r.begin ? r.end - r.begin : 0);
+    }
+    c = (c + 15) / 16 * (unsigned long long)ksteps * (unsigned long long)ni;
+    const unsigned long long cap = 0xffffffffull;
+    key[base + b] = ((unsigned long long)d << 32) | (cap - (c < cap ? c : cap));
+    val[base + b] = (int32_t)(base + b);
+}
+
 // Tuned choices, per path, d and size class: index_dims and the
 // short-circuit setting (sj_opts.short_circuit).
 struct TuneCache {
@@ -130,6 +150,8 @@ struct Batch {
     std::vector<int64_t> item_base;       // B + 1
     int64_t *item_base_dev = nullptr;     // B + 1
     int32_t *queue = nullptr;             // global item indices: by d, longest first
+    int32_t *bqueue = nullptr;            // global block item indices (LDS-shared FP64 MFMA count), same order
+    int64_t *block_base_dev = nullptr;    // B + 1: first global block item of each problem
     std::vector<BatchForm> forms;         // one per distinct d
     int sched = 0;                        // 0 = persistent grids, 1 = one wave per item
     bool tune_sched = false;              // choose sched on the first count (timed, or from the cache)
@@ -179,9 +201,11 @@ void batch_free(Batch &b, hipStream_t s) {
     b.grids.clear();
     for (void *p : b.owned) dev_free(p, s);
     b.owned.clear();
-    void *bufs[] = {b.item_base_dev, b.queue, b.ctr, b.probs_dev, b.totals_dev, b.masks};
+    void *bufs[] = {b.item_base_dev, b.queue, b.ctr, b.probs_dev, b.totals_dev, b.masks, b.bqueue, b.block_base_dev};
     for (void *p : bufs)
         if (p) dev_free(p, s);
+    b.bqueue = nullptr;
+    b.block_base_dev = nullptr;
     b.item_base_dev = nullptr;
     b.queue = nullptr;
     b.ctr = nullptr;
@@ -287,14 +311,53 @@ void batch_build(Batch &b, int B, const double *const *points, const int64_t *n,
     dev_free(v_sorted == va ? vb : va, s);
     dev_free(ka, s);
     dev_free(kb, s);
+    // block queue: the block items of the problems whose FP64 MFMA count
+    // stages tiles in LDS (2 to 4 K-steps, united lists), by d, longest first
+    std::vector<int64_t> bbase(B + 1, 0);
+    std::map<int, int64_t> per_d_blocks;
+    auto lds_form = [](const Grid &g) {
+        const int ks = g.da >> 2;
+        return g.united && g.blocks && g.nblocks > 0 && ks >= 2 && ks <= 4;
+    };
+    for (int i = 0; i < B; ++i) {
+        const Grid &g = *b.grids[i];
+        const int64_t nb = lds_form(g) ? g.nblocks : 0;
+        bbase[i + 1] = bbase[i] + nb;
+        if (nb) per_d_blocks[g.d] += nb;
+    }
+    if (bbase[B] > 0) {
+        const int64_t NB = bbase[B];
+        unsigned long long *bka = dev_alloc_n<unsigned long long>(NB, s), *bkb = dev_alloc_n<unsigned long long>(NB, s);
+        int32_t *bva = dev_alloc_n<int32_t>(NB, s), *bvb = dev_alloc_n<int32_t>(NB, s);
+        for (int i = 0; i < B; ++i) {
+            const Grid &g = *b.grids[i];
+            if (bbase[i + 1] == bbase[i]) continue;
+            hipLaunchKernelGGL(k_block_cost, dim3((unsigned)((g.nblocks + 255) / 256)), dim3(256), 0, s, g.blocks,
+                               g.item_base, g.ranges, g.nranges, (int)g.nblocks, g.da >> 2, g.d, bbase[i], bka, bva);
+            SJ_HIP(hipGetLastError());
+        }
+        unsigned long long *bks = bka;
+        int32_t *bvs = bva;
+        radix_sort_pairs(&bks, &bvs, bks == bka ? bkb : bka, bvs == bva ? bvb : bva, NB, 32 + dbits, s);
+        b.bqueue = bvs;
+        dev_free(bvs == bva ? bvb : bva, s);
+        dev_free(bka, s);
+        dev_free(bkb, s);
+        b.block_base_dev = dev_alloc_n<int64_t>(B + 1, s);
+        SJ_HIP(hipMemcpyAsync(b.block_base_dev, bbase.data(), (B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    }
     b.forms.clear();
-    int64_t pos = 0;
+    int64_t pos = 0, bpos = 0;
     for (auto &kv : per_d) {  // ascending d, the key order
         BatchForm f;
         f.d = kv.first;
         f.lo = (int32_t)pos;
         f.hi = (int32_t)(pos + kv.second);
         f.sched = 0;
+        const int64_t nb = per_d_blocks.count(kv.first) ? per_d_blocks[kv.first] : 0;
+        f.blo = (int32_t)bpos;
+        f.bhi = (int32_t)(bpos + nb);
+        bpos += nb;
         b.forms.push_back(f);
         pos += kv.second;
     }
@@ -372,7 +435,8 @@ float batch_count_graph(Batch &b, sj_path path, hipStream_t s) {
         b.exec[pi] = capture(s, [&](hipStream_t cs) {
             batch_reset(b.ctr, cs);
             for (const BatchForm &f : b.forms)
-                launch_batch_form(false, f, path, b.probs_dev, b.item_base_dev, b.B, b.queue, nullptr, b.ctr, cs);
+                launch_batch_form(false, f, path, b.probs_dev, b.item_base_dev, b.B, b.queue, nullptr, b.ctr, cs,
+                                  b.block_base_dev, b.bqueue);
             launch_seg_scan(b.probs_dev, b.B, b.totals_dev, cs);
         });
         b.graph_stream[pi] = s;

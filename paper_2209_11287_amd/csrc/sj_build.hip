@@ -1188,6 +1188,7 @@ void free_grid(Grid &g, hipStream_t s) {
         g.ranges = nullptr;
         g.item = nullptr;
         g.tile_off = nullptr;
+        g.blocks = nullptr;
     }
     void *bufs[] = {g.xs,   g.xa,       g.nrm,        g.perm,       g.cell_key, g.cell_start, g.ranges,
                     g.item, g.dev_nmax, g.line_first, g.line_table, g.blocks,   g.cnt,        g.off, g.ctr,
@@ -1968,6 +1969,50 @@ __global__ void k_seg_item_tiles(const SegProb *__restrict__ P, int B, Item *__r
     items[it] = m;
 }
 
+// The united ranges of every problem with d > 4 (as k_unite_ranges, at the
+// problem's range slots; blocks never cross a line, hence never a problem);
+// others copied.
+__global__ void k_seg_unite(const SegProb *__restrict__ P, int B, const int32_t *__restrict__ nitems_p,
+                            const int64_t *__restrict__ it_off, const int32_t *__restrict__ bflag,
+                            const Range *__restrict__ in, Range *__restrict__ out) {
+    constexpr int kR = 27;
+    const int64_t I = *nitems_p;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < I * kR; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t it = t / kR;
+        const int o = (int)(t - it * kR);
+        const int p = seg_find(it_off, B, it);
+        const SegProb &q = P[p];
+        if (o >= q.nranges) continue;
+        const int64_t base = q.range_base - it_off[p] * q.nranges;  // slot of global item i: base + i nranges
+        if (q.d <= 4) {
+            out[base + it * q.nranges + o] = in[base + it * q.nranges + o];
+            continue;
+        }
+        int64_t b0 = it;
+        while (b0 > it_off[p] && !bflag[b0]) --b0;
+        int64_t b1 = b0 + 1;
+        while (b1 < it_off[p + 1] && !bflag[b1]) ++b1;
+        Range u{0, 0};
+        bool any = false;
+        for (int64_t i = b0; i < b1; ++i) {
+            const Range r = in[base + i * q.nranges + o];
+            if (r.end <= r.begin) continue;
+            u.begin = any ? min(u.begin, r.begin) : r.begin;
+            u.end = any ? max(u.end, r.end) : r.end;
+            any = true;
+        }
+        out[base + it * q.nranges + o] = u;
+    }
+}
+
+// Per problem: first block item (entry B: the total).
+__global__ void k_seg_block_off(const int64_t *__restrict__ it_off, int B, const int32_t *__restrict__ bid,
+                                int64_t *__restrict__ bl_off) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > B) return;
+    bl_off[p] = bid[it_off[p]];
+}
+
 // Per problem: in-mask tile slots (entry B: the total).
 __global__ void k_seg_tiles(const int64_t *__restrict__ it_off, int B, const int64_t *__restrict__ tile_off,
                             int64_t *__restrict__ ptiles) {
@@ -2136,6 +2181,7 @@ bool build_grids_segmented(const std::vector<SegInput> &in, std::vector<Grid *> 
     const int64_t items_ub = N + N / kTileQ + B + 1;
     Item *items = static_cast<Item *>(keep(dev_alloc_n<Item>((size_t)items_ub, s)));
     Range *ranges = static_cast<Range *>(keep(dev_alloc_n<Range>((size_t)std::max<int64_t>(1, rng_tot), s)));
+    int32_t *blocks = static_cast<int32_t *>(keep(dev_alloc_n<int32_t>((size_t)items_ub + 1, s)));
     int64_t *tile_off = static_cast<int64_t *>(keep(dev_alloc_n<int64_t>((size_t)items_ub + 1, s)));
 
     std::vector<void *> tmp;
@@ -2243,8 +2289,21 @@ bool build_grids_segmented(const std::vector<SegInput> &in, std::vector<Grid *> 
     hipLaunchKernelGGL(k_seg_offsets, dim3(blocks_for(B + 1)), dim3(kThreads), 0, s, d_pt_off, B, cid, lid, item_off,
                        cell_off, it_off);
     SJ_HIP(hipGetLastError());
+    Range *ranges_raw = static_cast<Range *>(scratch((size_t)std::max<int64_t>(1, rng_tot) * sizeof(Range)));
     hipLaunchKernelGGL(k_seg_item_ranges, dim3(2048), dim3(kThreads), 0, s, P, B, items, counters + 2, it_off,
-                       cell_off, cell_key, cell_start, skey, ranges);
+                       cell_off, cell_key, cell_start, skey, ranges_raw);
+    SJ_HIP(hipGetLastError());
+    // block items (k_items left their start flags in `flag`) and united ranges for d > 4
+    int32_t *bid = static_cast<int32_t *>(scratch((size_t)(items_ub + 1) * 4));
+    exclusive_scan<int32_t, int32_t>(flag, bid, items_ub, s);
+    hipLaunchKernelGGL(k_blocks, dim3(blocks_for(items_ub)), dim3(kThreads), 0, s, flag, bid, counters + 2, blocks,
+                       counters + 3);
+    SJ_HIP(hipGetLastError());
+    int64_t *bl_off = static_cast<int64_t *>(scratch((B + 1) * sizeof(int64_t)));
+    hipLaunchKernelGGL(k_seg_block_off, dim3(blocks_for(B + 1)), dim3(kThreads), 0, s, it_off, B, bid, bl_off);
+    SJ_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_seg_unite, dim3(2048), dim3(kThreads), 0, s, P, B, counters + 2, it_off, flag, ranges_raw,
+                       ranges);
     SJ_HIP(hipGetLastError());
     int32_t *item_tiles = static_cast<int32_t *>(scratch((size_t)(items_ub + 1) * 4));
     hipLaunchKernelGGL(k_seg_item_tiles, dim3(blocks_for(items_ub + 1)), dim3(kThreads), 0, s, P, B, items,
@@ -2255,11 +2314,12 @@ bool build_grids_segmented(const std::vector<SegInput> &in, std::vector<Grid *> 
     hipLaunchKernelGGL(k_seg_tiles, dim3(blocks_for(B + 1)), dim3(kThreads), 0, s, it_off, B, tile_off, ptiles);
     SJ_HIP(hipGetLastError());
     // ---- one host sync: per-problem items, tiles, norms, candidates ----
-    std::vector<int64_t> h_it(B + 1), h_tiles(B + 1);
+    std::vector<int64_t> h_it(B + 1), h_tiles(B + 1), h_bl(B + 1);
     std::vector<unsigned long long> h_nmax(B), h_cand(B);
     int32_t herr = 0;
     SJ_HIP(hipMemcpyAsync(h_it.data(), it_off, (B + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipMemcpyAsync(h_tiles.data(), ptiles, (B + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipMemcpyAsync(h_bl.data(), bl_off, (B + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     SJ_HIP(hipMemcpyAsync(h_nmax.data(), nmax_bits, B * 8, hipMemcpyDeviceToHost, s));
     SJ_HIP(hipMemcpyAsync(h_cand.data(), cand, B * 8, hipMemcpyDeviceToHost, s));
     SJ_HIP(hipMemcpyAsync(&herr, os_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -2285,7 +2345,10 @@ bool build_grids_segmented(const std::vector<SegInput> &in, std::vector<Grid *> 
         g.nmax = nm;
         g.cand_items = (int64_t)h_cand[p];
         g.cand_ref = -1;
-        g.nblocks = 0;
+        g.blocks = blocks + h_bl[p];  // global item indices: item_base below
+        g.nblocks = h_bl[p + 1] - h_bl[p];
+        g.item_base = (int32_t)h_it[p];
+        g.united = g.d > 4;
     }
     return true;
 }

@@ -126,7 +126,8 @@ struct DevGrid {
     int64_t n;
     int32_t d, dp, da, nranges;
     int32_t nitems;
-    const int32_t *blocks;  // first item of each block item (+ end), or null
+    const int32_t *blocks;  // first item of each block item (+ end), plus item_base, or null
+    int32_t item_base;      // offset of the item indices in blocks (segmented builds: the problem's first item)
     int32_t nblocks;
     int32_t united;         // the items of each block item share one candidate list
     int32_t npc;   // prefix norms per row: da / 4 - 1 for d > 4, else 0
@@ -152,6 +153,7 @@ struct BatchForm {
     int32_t d;
     int32_t lo, hi;
     int32_t sched;
+    int32_t blo, bhi;  // FP64 MFMA count, d = 5 .. 16: its block items' positions in the block queue
 };
 
 struct Grid {
@@ -185,6 +187,7 @@ struct Grid {
     int32_t sc = 0;         // sj_opts.short_circuit: 0 = default schedule, -1 = off, k > 0 = every k K-steps
     int32_t npc = 0;        // prefix norms per row in pn
     bool united = false;    // d > 4: every item's ranges are its block item's union
+    int32_t item_base = 0;  // blocks[] holds item indices plus this (segmented builds)
 
     // device buffers
     double *xs = nullptr;        // sorted original coordinates, n x dp (+pad rows)
@@ -325,7 +328,8 @@ void refine_measure(Grid &g, sj_path path, double *max_err, double *max_band, in
 // Batched form (sj_refine.hip).
 void batch_reset(DevCounters *ctr, hipStream_t s);
 void launch_batch_form(bool emit, const BatchForm &f, sj_path path, const BProb *probs, const int64_t *item_base,
-                       int B, const int32_t *queue, int32_t *pairs, DevCounters *ctr, hipStream_t s);
+                       int B, const int32_t *queue, int32_t *pairs, DevCounters *ctr, hipStream_t s,
+                       const int64_t *block_base = nullptr, const int32_t *bqueue = nullptr);
 void launch_batch_emit(const BProb *probs, const int64_t *item_base, int B, const int32_t *queue, int total,
                        int sched, int32_t *pairs, hipStream_t s);
 void launch_seg_scan(const BProb *probs, int B, int64_t *totals, hipStream_t s);

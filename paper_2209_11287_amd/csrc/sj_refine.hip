@@ -762,7 +762,7 @@ __device__ __forceinline__ void m64_block_count(const DevGrid &G, const RefOut &
                                                 double *__restrict__ lds) {
     const int lane = threadIdx.x & 63;
     const int wv = uniform_i32(threadIdx.x >> 6);
-    const int ib = uniform_i32(G.blocks[bi]), ie = uniform_i32(G.blocks[bi + 1]);
+    const int ib = uniform_i32(G.blocks[bi] - G.item_base), ie = uniform_i32(G.blocks[bi + 1] - G.item_base);
     const bool active = ib + wv < ie;  // wave-uniform
     const int it = active ? ib + wv : ib;
     const Item I = G.items[it];
@@ -1474,6 +1474,24 @@ __global__ __launch_bounds__(kThreads) void k_batch_v64(const BProb *__restrict_
     }
 }
 
+// FP64 MFMA count of the block items of many problems (d = 5 .. 16, united
+// candidate lists): as k_m64s, one block item per block at a time, the block
+// queue's positions [lo, hi) taken round-robin by the grid's blocks.
+template <int KS, bool SLOT>
+__global__ __launch_bounds__(kThreads) void k_batch_m64s(const BProb *__restrict__ probs,
+                                                         const int64_t *__restrict__ block_base, int B,
+                                                         const int32_t *__restrict__ bqueue, int lo, int hi,
+                                                         DevCounters *__restrict__ ctr) {
+    __shared__ double lds[m64s_lds_doubles(KS)];
+    for (int w = lo + (int)blockIdx.x; w < hi; w += (int)gridDim.x) {  // block-uniform
+        const int gb = bqueue[w];
+        const int p = batch_problem(block_base, B, gb);
+        const BProb &P = probs[p];
+        const RefOut R = batch_out(P, nullptr, ctr, MODE_COUNT);
+        m64_block_count<KS, SLOT>(P.G, R, P.delta, uniform_i32(gb - (int)block_base[p]), lds);
+    }
+}
+
 // Pairs of every item from the in-masks its problem's count pass recorded
 // (no distance is recomputed), at the problem's output rows.
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_batch_emit(
@@ -1542,6 +1560,7 @@ DevGrid dev_grid(const Grid &g) {
     G.nranges = g.nranges;
     G.nitems = (int32_t)g.items;
     G.blocks = g.blocks;
+    G.item_base = g.item_base;
     G.nblocks = (int32_t)g.nblocks;
     G.united = g.united ? 1 : 0;
     G.npc = g.npc;
@@ -1740,7 +1759,26 @@ static void batch_form_mode(const BatchForm &f, sj_path path, const BProb *probs
 }
 
 void launch_batch_form(bool emit, const BatchForm &f, sj_path path, const BProb *probs, const int64_t *item_base,
-                       int B, const int32_t *queue, int32_t *pairs, DevCounters *ctr, hipStream_t s) {
+                       int B, const int32_t *queue, int32_t *pairs, DevCounters *ctr, hipStream_t s,
+                       const int64_t *block_base, const int32_t *bqueue) {
+    if (!emit && path == SJ_FP64_MFMA && bqueue && f.bhi > f.blo) {
+        const bool slot = (f.d & 3) != 0;
+        const int ks = (slot ? ((f.d + 1 + 3) & ~3) : f.d) >> 2;
+        const int nb = f.bhi - f.blo;
+#define SJ_BS(KSV, SL) \
+    batch_launch(k_batch_m64s<KSV, SL>, 4 * nb, f.sched, s, probs, block_base, B, bqueue, f.blo, f.bhi, ctr)
+        if (slot) {
+            if (ks == 2) SJ_BS(2, true);
+            else if (ks == 3) SJ_BS(3, true);
+            else SJ_BS(4, true);
+        } else {
+            if (ks == 2) SJ_BS(2, false);
+            else if (ks == 3) SJ_BS(3, false);
+            else SJ_BS(4, false);
+        }
+#undef SJ_BS
+        return;
+    }
     if (emit) batch_form_mode<MODE_EMIT>(f, path, probs, item_base, B, queue, pairs, ctr, s);
     else batch_form_mode<MODE_COUNT>(f, path, probs, item_base, B, queue, pairs, ctr, s);
 }
