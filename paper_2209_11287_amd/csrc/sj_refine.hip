@@ -793,8 +793,8 @@ __device__ __forceinline__ void m64_block_count(const DevGrid &G, const RefOut &
     }
     th.clo = eps2 - delta;
     th.chi = eps2 + delta;
-    const bool sc_on = G.sc != -1;
-    constexpr int KC = KS / 2;
+    const bool sc_on = KS >= 2 && G.sc != -1;  // one check, after K-step KS / 2
+    constexpr int KC = KS >= 2 ? KS / 2 : 1;
     double tq[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -839,7 +839,7 @@ __device__ __forceinline__ void m64_block_count(const DevGrid &G, const RefOut &
         for (int s = 0; s < KS; ++s) sb[s] = brow[4 * s];
         // lanes of row group 0: the column's norm (no slot); group 1: its prefix norm
         if (g == 0) sx = SLOT ? 0.0 : G.nrm[col];
-        else if (g == 1) sx = G.pn[(int64_t)col * G.npc + (KC - 1)];
+        else if (g == 1 && KS >= 2) sx = G.pn[(int64_t)col * G.npc + (KC - 1)];
     };
     auto stage_store = [&](int buf) {
         double *t = lds + (buf * 4 + wv) * (KS * 64 + 32);
@@ -875,7 +875,8 @@ __device__ __forceinline__ void m64_block_count(const DevGrid &G, const RefOut &
                 T.pn = tl[KS * 64 + 16 + j];
                 double4_t a = cinit;
 #pragma unroll
-                for (int s = 0; s < KC; ++s) a = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], T.b[s], a, 0, 0, 0);
+                for (int s = 0; s < (KS >= 2 ? KC : 0); ++s)
+                    a = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], T.b[s], a, 0, 0, 0);
                 bool far = false;
                 if (sc_on) {
                     const bool f = j >= T.n || (a[0] > tq[0] - T.pn && a[1] > tq[1] - T.pn && a[2] > tq[2] - T.pn &&
@@ -887,7 +888,8 @@ __device__ __forceinline__ void m64_block_count(const DevGrid &G, const RefOut &
                     nacc <<= 4;
                 } else {
 #pragma unroll
-                    for (int s = KC; s < KS; ++s) a = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], T.b[s], a, 0, 0, 0);
+                    for (int s = (KS >= 2 ? KC : 0); s < KS; ++s)
+                        a = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], T.b[s], a, 0, 0, 0);
                     unsigned long long w[4];
                     m64_words<SLOT, KS>(a, T, g, q0, th, G, band, band_in, w);
                     nib_push(nacc, w);
