@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--chunk", type=int, default=0, help="pairs per output chunk (0 = one chunk)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-set", action="store_true", help="skip the per-set single-stream path comparison")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the achievable-peak microbenchmarks (selfjoin_probe_peaks)")
     ap.add_argument("--no-other", action="store_true",
                     help="skip the short passes of the precision, 10M-point and batched workloads")
     ap.add_argument("--streams", type=int, default=3,
@@ -254,6 +256,31 @@ def roofline(recs, path="fp64_mfma", which=None, workload="cfg2"):
             "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
             "traffic": traffic_for("count", path, workload), "avg_launch_ms": round(avg_ms, 4),
             "algorithmic_flops_per_launch": round(flops / launches)}
+
+
+PEAK_KEY = {("mfma", "fp64_mfma"): "fp64_mfma_tflops", ("alu", "fp64_valu"): "fp64_valu_tflops",
+            ("mfma", "fp32_mfma"): "fp32_mfma_tflops", ("mfma", "bf16_mfma"): "bf16_mfma_tflops",
+            ("mfma", "bf16x3_mfma"): "bf16_mfma_tflops", ("mfma", "fp8_mfma"): "fp8_mfma_tflops"}
+
+
+def measured_peaks():
+    """Achievable peaks of this GPU from the library's microbenchmarks
+    (matrix forms, FP64 vector FMA, HBM read and copy over 4 GiB buffers)."""
+    import paper_2209_11287_amd as pkg
+    return {k: round(v, 1) for k, v in pkg.selfjoin_probe_peaks(4 << 30).items()}
+
+
+def with_achievable(roof, peaks, path):
+    """Adds the measured achievable peak of the roofline's unit (the HBM copy
+    rate for an HBM-bound kernel) and the fraction of it reached."""
+    if not peaks:
+        return roof
+    key = "hbm_copy_gbs" if roof["bound"] == "hbm" else PEAK_KEY.get((roof["bound"], path))
+    if key:
+        roof["achievable_peak"] = peaks[key]
+        roof["achievable_source"] = key
+        roof["frac_achievable"] = round(roof["achieved"] / peaks[key], 4)
+    return roof
 
 
 def isolated(inputs, path, bufs, cref_map, chunk=0):
@@ -465,6 +492,10 @@ def batched_main(args):
                       "pairs_per_step": last["pairs"], "tuned_index_dims": ks},
            "phases_ms": avg, "tiles_pruned": last["pruned"], "cand_eval": last["cand_eval"],
            "roofline": batched_roofline(B, avg, last)}
+    if not args.no_peaks:
+        out["peaks_measured"] = measured_peaks()
+        with_achievable(out["roofline"], out["peaks_measured"], args.path)
+        with_achievable(out["roofline"]["other_kernel"], out["peaks_measured"], args.path)
     if args.compare:
         sec2, avg2, _, _ = batched_run(B, args.compare, args.steps, args.warmup, cache)
         out["compare"] = {"path": args.compare, "value": B["cref"] / sec2, "ms_per_step": round(sec2 * 1e3, 3),
@@ -625,6 +656,11 @@ def main():
     ro = roofline([iso], args.path, which=other, workload=args.workload)
     roof["other_kernel"] = {k: ro[k] for k in ("kernel", "bound", "achieved", "peak", "unit", "frac",
                                                   "avg_launch_ms")}
+    if not args.no_peaks:
+        log("[bench] achievable peaks (microbenchmarks)")
+        out["peaks_measured"] = measured_peaks()
+        with_achievable(roof, out["peaks_measured"], args.path)
+        with_achievable(roof["other_kernel"], out["peaks_measured"], args.path)
     out["roofline"] = roof
     # per-set single-stream kernel times of the FP64 MFMA, FP64 vector-ALU and
     # FP32 MFMA paths on the same data (the MFMA-vs-vector comparison per set)

@@ -358,6 +358,37 @@ sj_status selfjoin_batch_info(const sj_batch *b, int32_t i, int32_t *index_dims,
 
 void selfjoin_batch_free(sj_batch *b, void *stream);
 
+/* ---- Achievable peaks (measurement utility, not on the join path) -------
+ * Short microbenchmarks of this GPU, the measured denominators beside the
+ * published peaks when the distance kernels are placed on their roofline
+ * (the roofline of the work unit C_ref: 2 d flops per distance on the matrix
+ * or vector unit, or the bytes the pairs pass must move):
+ *  fp64_mfma_tflops : v_mfma_f64_16x16x4f64 (the FP64 MFMA tiles)
+ *  fp32_mfma_tflops : v_mfma_f32_16x16x4f32 (the FP32 tiles)
+ *  bf16_mfma_tflops : v_mfma_f32_16x16x32_bf16 (BF16 and split-BF16 tiles)
+ *  fp8_mfma_tflops  : v_mfma_f32_16x16x32_fp8_fp8 (FP8 tiles)
+ *  fp64_valu_tflops : v_fma_f64 (the FP64 vector path), 2 flops per FMA
+ *  hbm_read_gbs     : streaming read of `bytes`
+ *  hbm_copy_gbs     : streaming copy of `bytes` (read and written bytes)
+ * Matrix forms: 1024 blocks of 4 waves, every wave running four independent
+ * accumulator chains, so the unit never waits on a result; FMA: 16 waves
+ * per SIMD, eight chains each; HBM: 16-byte non-temporal loads / stores.
+ * Each figure is the best of three timed launches after one warmup.
+ * bytes : size of each of the two bandwidth buffers (>= 16; 0 skips the
+ *         bandwidth probes and leaves their fields 0). Take it well above
+ *         the 256 MB last-level cache (1 GiB is typical); the two buffers
+ *         are allocated from the runtime (not through the allocator hook)
+ *         and freed before return.
+ * Returns after the stream work has finished. Errors: SJ_ERR_INVALID
+ * (out NULL, bytes < 0), SJ_ERR_OOM, SJ_ERR_HIP. */
+typedef struct {
+    double fp64_mfma_tflops, fp32_mfma_tflops, bf16_mfma_tflops, fp8_mfma_tflops;
+    double fp64_valu_tflops;
+    double hbm_read_gbs, hbm_copy_gbs;
+} sj_peaks;
+
+sj_status selfjoin_probe_peaks(int64_t bytes, sj_peaks *out, void *stream);
+
 /* Static text for a status. */
 const char *selfjoin_status_string(sj_status s);
 

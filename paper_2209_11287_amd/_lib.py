@@ -37,6 +37,7 @@ EXPORTS = [
     "selfjoin_batch_info",
     "selfjoin_batch_free",
     "selfjoin_count_noalloc",
+    "selfjoin_probe_peaks",
 ]
 
 
@@ -88,6 +89,15 @@ class sj_grid_info(ctypes.Structure):
         ("cand_ref", ctypes.c_int64),
         ("cand_items", ctypes.c_int64),
     ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class sj_peaks(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in (
+        "fp64_mfma_tflops", "fp32_mfma_tflops", "bf16_mfma_tflops", "fp8_mfma_tflops", "fp64_valu_tflops",
+        "hbm_read_gbs", "hbm_copy_gbs")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -153,6 +163,8 @@ def load():
     lib.selfjoin_count_noalloc.restype = ctypes.c_int
     lib.selfjoin_count_noalloc.argtypes = [_vp, _i64, ctypes.c_int32, ctypes.c_double, ctypes.c_int, _vp, _i64p,
                                            _vp]
+    lib.selfjoin_probe_peaks.restype = ctypes.c_int
+    lib.selfjoin_probe_peaks.argtypes = [_i64, ctypes.POINTER(sj_peaks), _vp]
     _lib = lib
     return lib
 

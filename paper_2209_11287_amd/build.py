@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libselfjoin.so")
-SOURCES = ["sj_api.hip", "sj_build.hip", "sj_refine.hip", "sj_lowp.hip", "sj_batch.hip"]
+SOURCES = ["sj_api.hip", "sj_build.hip", "sj_refine.hip", "sj_lowp.hip", "sj_batch.hip", "sj_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

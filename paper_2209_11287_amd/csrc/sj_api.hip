@@ -473,6 +473,11 @@ static bool valid_path(sj_path p) {
     return p == SJ_FP64_VALU || p == SJ_FP64_MFMA || is_lowp(p);
 }
 
+namespace sj {
+// Achievable peaks of the GPU (microbenchmarks, sj_probe.hip).
+void probe_peaks(int64_t bytes, sj_peaks &out, hipStream_t s);
+}  // namespace sj
+
 extern "C" {
 
 sj_status selfjoin_build_grid(const double *points, int64_t n, int32_t d, double eps, const sj_opts *opts,
@@ -765,6 +770,19 @@ const char *selfjoin_status_string(sj_status s) {
 }
 
 const char *selfjoin_last_error(void) { return last_error(); }
+
+sj_status selfjoin_probe_peaks(int64_t bytes, sj_peaks *out, void *stream) {
+    set_error("");
+    if (!out) return invalid("out is NULL");
+    if (bytes < 0 || (bytes > 0 && bytes < 16)) return invalid("bytes must be 0 or >= 16");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SJ_API_BEGIN
+    sj_peaks r{};
+    probe_peaks(bytes, r, s);
+    *out = r;
+    return SJ_OK;
+    SJ_API_END
+}
 
 const char *selfjoin_version(void) { return "selfjoin-mi355x 0.2 (gfx950)"; }
 

@@ -245,6 +245,18 @@ def selfjoin_grid_info(g: GridHandle, stream=None) -> dict:
     return info.as_dict()
 
 
+def selfjoin_probe_peaks(bytes_: int = 1 << 30, device: int = 0, stream=None) -> dict:
+    """Achievable peaks of the GPU (matrix forms, FP64 vector FMA, HBM read
+    and copy), measured by the library's microbenchmarks."""
+    torch = _torch()
+    lib = _lib.load()
+    out = _lib.sj_peaks()
+    with torch.cuda.device(device):
+        st = lib.selfjoin_probe_peaks(int(bytes_), ctypes.byref(out), _stream_ptr(stream))
+    check(st, "selfjoin_probe_peaks")
+    return out.as_dict()
+
+
 def selfjoin_free_grid(g: GridHandle, stream=None):
     g.close(stream)
 

@@ -130,3 +130,11 @@ def test_batch_calls_reject_invalid_arguments(lib):
     assert lib.selfjoin_batch_pairs(None, 1, None, 0, offs, None, None) == _lib.SJ_ERR_INVALID
     assert lib.selfjoin_batch_info(None, 0, None, None) == _lib.SJ_ERR_INVALID
     lib.selfjoin_batch_free(None, None)
+
+
+def test_peak_probe_rejects_invalid_arguments(lib):
+    out = _lib.sj_peaks()
+    assert lib.selfjoin_probe_peaks(1 << 20, None, None) == _lib.SJ_ERR_INVALID
+    assert lib.selfjoin_probe_peaks(-1, ctypes.byref(out), None) == _lib.SJ_ERR_INVALID
+    assert lib.selfjoin_probe_peaks(8, ctypes.byref(out), None) == _lib.SJ_ERR_INVALID
+    assert lib.selfjoin_last_error()
