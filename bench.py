@@ -537,6 +537,43 @@ def batched_cpu_baseline(ws, host, crefs, budget_evals=1.5e9):
                       f"pairs in all; d in {ds})", "seconds": round(secs, 2)}
 
 
+def symmetric_counts(reps=3):
+    """Count-only use (per-point counts, as DBSCAN's core test needs): the
+    count kernel with the full stencil and with the half stencil
+    (sj_opts.symmetric) on the same grids, FP64 MFMA and FP64 vector paths,
+    the six 2M-point sets and the precision set; best of `reps` kernel times
+    (HIP events around the launch); the totals must agree."""
+    import torch
+    from paper_2209_11287_amd import selfjoin_build_grid, selfjoin_count, selfjoin_free_grid
+    out = {}
+    for wname in ("cfg2", "prec"):
+        log(f"[bench] symmetric count {wname}")
+        rows = []
+        for w, _, xt in load_inputs(datasets(wname)):
+            row = {"name": w["name"]}
+            for pth in ("fp64_mfma", "fp64_valu"):
+                res = {}
+                for sym in (0, 1):
+                    g = selfjoin_build_grid(xt, w["eps"], symmetric=sym)
+                    best, tot, ev = None, None, None
+                    for _ in range(reps + 1):
+                        t, _, st = selfjoin_count(g, pth)
+                        best = st["ms_refine"] if best is None else min(best, st["ms_refine"])
+                        tot, ev = t, st["cand_eval"]
+                    selfjoin_free_grid(g)
+                    res[sym] = (best, tot, ev)
+                if res[0][1] != res[1][1]:
+                    raise RuntimeError(f"symmetric count differs on {w['name']} {pth}")
+                row[pth] = {"count_kernel_ms": round(res[0][0], 4), "symmetric_ms": round(res[1][0], 4),
+                            "speedup": round(res[0][0] / max(res[1][0], 1e-9), 3),
+                            "cand_eval": res[0][2], "symmetric_cand_eval": res[1][2]}
+            rows.append(row)
+            del xt
+            torch.cuda.empty_cache()
+        out[wname] = rows
+    return out
+
+
 def other_workloads(steps=2, warmup=1):
     """Short timed passes of the other configurations, one stream each, so
     that one run reports them all: the precision set (1M-point Gaussian
@@ -580,6 +617,7 @@ def other_workloads(steps=2, warmup=1):
         torch.cuda.empty_cache()
     log("[bench] other workload batched")
     out["batched"] = batched_summary(["fp64_mfma", "fp64_valu"], steps, warmup)
+    out["symmetric_count"] = symmetric_counts()
     return out
 
 

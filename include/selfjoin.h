@@ -139,7 +139,24 @@ typedef struct {
                                decreasing variance (Section II-D), so the
                                partial distance at each check grows fastest;
                                1 = input order */
-    int64_t reserved[3];
+    int32_t symmetric;      /* half-stencil count on the FP64 paths (0 = off,
+                               1 = on; the result does not depend on it): the
+                               count pass of SJ_FP64_MFMA / SJ_FP64_VALU meets
+                               each pair within eps once, from its smaller
+                               index in the grid's order (a work item keeps
+                               only the candidates from its first query on,
+                               and a value counts only for a candidate after
+                               its query), and adds it to both points' counts
+                               (to the candidate by a device atomic per tile
+                               column), with 1 for the point itself: about
+                               half the distance tiles. For count-only use
+                               (selfjoin_count, selfjoin_core_points): the
+                               count then records no in-masks, so a following
+                               selfjoin_pairs / selfjoin_knn evaluates its
+                               tiles again (full stencil). The low-precision
+                               paths and the batched form ignore it. */
+    int32_t reserved32;
+    int64_t reserved[2];
 } sj_opts;
 
 /* Statistics of one call (all optional, pass NULL). */
@@ -148,7 +165,8 @@ typedef struct {
                             stencil of the reference grid (work unit);
                             -1 until selfjoin_grid_info has computed it */
     int64_t cand_eval;   /* candidate pairs the path evaluated, tile padding
-                            excluded */
+                            excluded (a half-stencil count: the pairs after
+                            each work item's first query) */
     int64_t pairs;       /* |R| for count; pairs written for pairs */
     int64_t rechecked;   /* pairs of this call's tile kernels whose fast value
                             fell inside the error band and were re-evaluated

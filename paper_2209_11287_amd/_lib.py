@@ -50,7 +50,8 @@ class sj_opts(ctypes.Structure):
     _fields_ = [("index_dims", ctypes.c_int32), ("tune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
                 ("short_circuit", ctypes.c_int32), ("dim_order", ctypes.c_int32),
-                ("reserved", ctypes.c_int64 * 3)]
+                ("symmetric", ctypes.c_int32), ("reserved32", ctypes.c_int32),
+                ("reserved", ctypes.c_int64 * 2)]
 
 
 class sj_stats(ctypes.Structure):

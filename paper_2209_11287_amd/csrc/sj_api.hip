@@ -273,6 +273,7 @@ struct CountRun {
     HostCounters hc;
     double band_rel = 0;
     float ms_refine = 0;
+    int64_t cand_eval = -1;  // half-stencil count: the candidate pairs it evaluated
 };
 
 // Computes per-query counts with `path` (range-checked) into the handle's
@@ -288,10 +289,14 @@ static void compute_counts(Grid &g, sj_path path, bool timed, CountRun &cr, hipS
     ro.ctr = g.ctr;
     // FP64 count passes record per-tile in-masks; emission then reuses them
     const bool fp64 = path == SJ_FP64_VALU || path == SJ_FP64_MFMA;
+    // half stencil (FP64 paths): counts accumulate from zero, no in-masks
+    const bool sym = fp64 && g.sym != 0;
     g.masks_valid = false;
-    if (fp64 && !g.lean && !g.masks && g.tiles > 0 && g.tiles * 32 <= kMaskBudget)
+    if (fp64 && !sym && !g.lean && !g.masks && g.tiles > 0 && g.tiles * 32 <= kMaskBudget)
         g.masks = dev_alloc_n<unsigned long long>((size_t)g.tiles * 4, s);
-    ro.masks = fp64 ? g.masks : nullptr;
+    ro.masks = fp64 && !sym ? g.masks : nullptr;
+    ro.sym = sym;
+    if (sym && g.n > 0) fill_zero(g.cnt, (size_t)g.n * sizeof(int32_t), s);
     hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, g.cnt + g.n, 0);
     SJ_HIP(hipGetLastError());
     if (g.n > 0) refine_count(g, path, g.cnt, ro, s);
@@ -313,6 +318,7 @@ static void compute_counts(Grid &g, sj_path path, bool timed, CountRun &cr, hipS
         cr.band_rel = g.eps2 > 0 ? cr.hc.max_delta / (g.eps2 * sc * sc) : 0.0;
     }
     cr.ms_refine = ro.kt.ms();
+    cr.cand_eval = sym ? (int64_t)hctr.spare[0] : -1;
     g.have_counts = true;
 }
 
@@ -329,7 +335,7 @@ static void fill_stats(sj_stats *st, const Grid &g, int64_t pairs, const CountRu
     if (!st) return;
     std::memset(st, 0, sizeof *st);
     st->cand_ref = g.cand_ref;  // -1 until selfjoin_grid_info computed it
-    st->cand_eval = g.cand_items;
+    st->cand_eval = cr.ran && cr.cand_eval >= 0 ? cr.cand_eval : g.cand_items;
     st->pairs = pairs;
     st->rechecked = (cr.ran ? cr.hc.rechecked : 0) + (emit_ctr ? emit_ctr->rechecked : 0);
     st->rechecked_in = (cr.ran ? cr.hc.rechecked_in : 0) + (emit_ctr ? emit_ctr->rechecked_in : 0);
@@ -494,6 +500,7 @@ sj_status selfjoin_build_grid(const double *points, int64_t n, int32_t d, double
     if (opts && (opts->short_circuit < -1 || opts->short_circuit > 64))
         return invalid("short_circuit must be in [-1, 64]");
     if (opts && (opts->dim_order < 0 || opts->dim_order > 1)) return invalid("dim_order must be 0 or 1");
+    if (opts && (opts->symmetric < 0 || opts->symmetric > 1)) return invalid("symmetric must be 0 or 1");
     hipStream_t s = static_cast<hipStream_t>(stream);
     sj_grid *h = nullptr;
     SJ_API_BEGIN
@@ -501,6 +508,7 @@ sj_status selfjoin_build_grid(const double *points, int64_t n, int32_t d, double
     if (opts) {
         h->g.sc = opts->short_circuit;
         h->g.dim_order = opts->dim_order;
+        h->g.sym = opts->symmetric;
     }
     if (opts && opts->alloc) {
         h->g.hook.alloc = opts->alloc;

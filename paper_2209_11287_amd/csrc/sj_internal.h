@@ -185,6 +185,7 @@ struct Grid {
     uint8_t fo[kMaxDims];
     int32_t dim_order = 0;  // sj_opts.dim_order
     int32_t sc = 0;         // sj_opts.short_circuit: 0 = default schedule, -1 = off, k > 0 = every k K-steps
+    int32_t sym = 0;        // sj_opts.symmetric: half-stencil count on the FP64 paths
     int32_t npc = 0;        // prefix norms per row in pn
     bool united = false;    // d > 4: every item's ranges are its block item's union
     int32_t item_base = 0;  // blocks[] holds item indices plus this (segmented builds)
@@ -299,6 +300,8 @@ struct RefineOut {
     unsigned long long *masks = nullptr;   // per-tile in-masks to record (FP64 count), nullable
     double band_rel = 0;     // largest band half-width / eps^2
     int64_t cand_eval = 0;
+    bool sym = false;        // FP64 count: half stencil (counts zeroed by the caller); the
+                             // candidate pairs it evaluates land in ctr->spare[0]
 };
 
 // Host copy of a launch's counters (one device-to-host copy with the

@@ -55,7 +55,9 @@ struct RefOut {
     unsigned long long *masks;    // count: per-tile in-masks to record (nullable)
 };
 
-enum { MODE_COUNT = 0, MODE_EMIT = 1, MODE_MEASURE = 2 };
+// MODE_SYM: the count with the half stencil (sym_cut / sym_mask below).
+enum { MODE_COUNT = 0, MODE_EMIT = 1, MODE_MEASURE = 2, MODE_SYM = 3 };
+constexpr bool is_count(int mode) { return mode == MODE_COUNT || mode == MODE_SYM; }
 
 // Blocks go round-robin over the 8 XCDs (hardware block b runs on XCD b % 8).
 // Logical blocks come in chunks of kXcdChunk consecutive ones, so spatially
@@ -230,6 +232,57 @@ __device__ __forceinline__ void tile_store(const unsigned long long w[4], int c,
     }
 }
 
+// Half-stencil count (symmetric evaluation, FP64 paths): each pair within
+// eps is met once, from its smaller sorted index. A work item keeps only the
+// candidates at or after its first query q0 (the ranges are cut at q0: a
+// line with a smaller key lies wholly before the item's line in the sorted
+// order, a larger one wholly after it), and a value (query i, candidate c)
+// counts only for c > i, which matters only where the candidates are the
+// item's own queries (or, on a shared block list, its block's earlier ones).
+// The row sums go to the queries as before; each tile's column sums go to
+// its candidates by atomics; every point adds 1 for itself.
+__device__ __forceinline__ void sym_cut(ItemRanges &rg, int q0) {
+    rg.rb = max(rg.rb, q0);
+    rg.re = max(rg.re, rg.rb);
+}
+
+// Clears the values (query q0 + g + 4r, candidate c) with c <= that query;
+// only tiles holding a candidate below q0 + 16 have any (wave-uniform test).
+__device__ __forceinline__ void sym_mask(unsigned long long w[4], int c, int n, int q0, int g, int j) {
+    if (__ballot(j < n && c < q0 + 16) == 0ull) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) w[r] &= __ballot(c > q0 + g + 4 * r);
+}
+
+// The tile's pairs of the lane's column (its four row bits are the low
+// nibble of the accumulator right after nib_push), summed over the four row
+// groups, added to the candidate's count.
+__device__ __forceinline__ void sym_columns(unsigned nacc, int c, int32_t *cnt, int lane) {
+    int v = __popc(nacc & 0xFu);
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    if (lane < 16 && v) atomicAdd(cnt + c, v);
+}
+
+// Per-query count of a finished item: the row sums reduced over the 16
+// lanes of each row group; with the half stencil they are added (other
+// items add their column sums to the same entries) with the point itself.
+template <bool SYM>
+__device__ __forceinline__ void write_counts(const int tot[4], const RefOut &R, int q0, int nq, int g, int j) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        int v = tot[r];
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 8);
+        if (j == 0 && g + 4 * r < nq) {
+            if (SYM) atomicAdd(R.cnt + q0 + g + 4 * r, v + 1);
+            else R.cnt[q0 + g + 4 * r] = v;
+        }
+    }
+}
+
 // --------------------------------------------------------------------- M64 --
 // One v_mfma_f64_16x16x4f64 per K-step: rows = the item's 16 queries (the A
 // operand, loaded once per item), columns = 16 candidates (the B operand,
@@ -343,7 +396,7 @@ __device__ __forceinline__ void m64_measure(double4_t acc, const TileT &T, int g
 template <bool SLOT, int KS, class TileT>
 __device__ __forceinline__ void m64_words(double4_t acc, const TileT &T, int g, int q0, const M64Thr &th,
                                           const DevGrid &G, unsigned long long &band, unsigned long long &band_in,
-                                          unsigned long long w[4]) {
+                                          unsigned long long w[4], bool sym = false) {
     double lo[4], hi[4];
     if (SLOT) {
 #pragma unroll
@@ -371,6 +424,15 @@ __device__ __forceinline__ void m64_words(double4_t acc, const TileT &T, int g, 
         for (int r = 0; r < 4; ++r) {
             w[r] &= cm;
             m[r] &= cm;
+        }
+    }
+    if (sym) {  // half stencil: only candidates after the query
+        unsigned long long keep[4] = {~0ull, ~0ull, ~0ull, ~0ull};
+        sym_mask(keep, T.c, T.n, q0, g, threadIdx.x & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            w[r] &= keep[r];
+            m[r] &= keep[r];
         }
     }
     if (__builtin_expect(((m[0] ^ w[0]) | (m[1] ^ w[1]) | (m[2] ^ w[2]) | (m[3] ^ w[3])) != 0ull, 0)) {
@@ -436,7 +498,9 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
     const int g = lane >> 4;   // K index of the operands; row group of the result
     const int qa = q0 + (j < nq ? j : 0);
     const double *__restrict__ xa = G.xa;
-    const ItemRanges rg = load_ranges(G, it, lane);
+    ItemRanges rg = load_ranges(G, it, lane);
+    constexpr bool sym = MODE == MODE_SYM;
+    if (sym) sym_cut(rg, q0);
     const double eps2 = G.eps2;
     using Tile = M64Tile<KS, m64_nb(KS, MODE)>;
 
@@ -541,13 +605,14 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
             return;
         }
         unsigned long long w[4];
-        m64_words<SLOT, KS>(acc, T, g, q0, th, G, band, band_in, w);
+        m64_words<SLOT, KS>(acc, T, g, q0, th, G, band, band_in, w, sym);
         if (MODE == MODE_EMIT) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) w[r] &= ebal[r];
             tile_store(w, T.c, T.pc, ro, g, j, G, R, q0);
         } else {
             nib_push(nacc, w);
+            if (sym) sym_columns(nacc, T.c, R.cnt, lane);
             if ((k & 7) == 7) nib_flush(nib, nacc, 8, (k >> 3) & 1);
         }
     };
@@ -565,7 +630,7 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
     // a tile dropped by the partial-distance bound: no pairs, zero row bits
     auto prune = [&](int k) {
         ++npruned;
-        if (MODE == MODE_COUNT) {
+        if (is_count(MODE)) {
             nacc <<= 4;
             if ((k & 7) == 7) nib_flush(nib, nacc, 8, (k >> 3) & 1);
         }
@@ -675,7 +740,7 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
             }
             if (dropped) prune(k);
             else classify(a, T, k);
-            if (MODE == MODE_COUNT && (k & 15) == 15) group_done(k - 15);
+            if (is_count(MODE) && (k & 15) == 15) group_done(k - 15);
         };
         const int klast = ntiles - 1;
         Tile TA, TB;
@@ -711,21 +776,13 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
         load(T0, k + 4, cand[0]);
         load(T1, k + 5, cand[1]);
         run(T2, T3, k + 2);
-        if (MODE == MODE_COUNT && (c & 3) == 3) group_done(k - 12);
+        if (is_count(MODE) && (c & 3) == 3) group_done(k - 12);
     }
     }
-    if (MODE == MODE_COUNT) {
+    if (is_count(MODE)) {
         if (flushed < ntiles) group_done(flushed);  // the last, partial group
         // the 16 lanes of row group g hold the columns of queries g + 4r
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int v = tot[r];
-            v += __shfl_xor(v, 1);
-            v += __shfl_xor(v, 2);
-            v += __shfl_xor(v, 4);
-            v += __shfl_xor(v, 8);
-            if (j == 0 && g + 4 * r < nq) R.cnt[q0 + g + 4 * r] = v;
-        }
+        write_counts<sym>(tot, R, q0, nq, g, j);
         if (lane == 0 && npruned) atomicAdd(&R.ctr->pruned, npruned);
     }
     if (MODE != MODE_MEASURE && lane == 0 && band) {
@@ -757,7 +814,7 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
 // classification, in-masks, short-circuit and counts are those of m64_item.
 constexpr int m64s_lds_doubles(int ks) { return 2 * 4 * (ks * 64 + 32); }
 
-template <int KS, bool SLOT>
+template <int KS, bool SLOT, bool SYM>
 __device__ __forceinline__ void m64_block_count(const DevGrid &G, const RefOut &R, double delta, int bi,
                                                 double *__restrict__ lds) {
     const int lane = threadIdx.x & 63;
@@ -808,8 +865,12 @@ __device__ __forceinline__ void m64_block_count(const DevGrid &G, const RefOut &
     const int64_t tile_base = rec ? G.tile_off[it] : 0;
     unsigned long long nib = 0;
     unsigned nacc = 0;
-    // the block's list: every wave walks the first item's (united) ranges
-    const ItemRanges rg = load_ranges(G, ib, lane);
+    // the block's list: every wave walks the first item's (united) ranges;
+    // half stencil: cut at the block's first query, and each wave keeps the
+    // candidates after its own queries (sym_mask)
+    ItemRanges rg = load_ranges(G, ib, lane);
+    constexpr bool sym = SYM;
+    if (sym) sym_cut(rg, uniform_i32(G.items[ib].qbegin));
     CandList L;
     cand_init(L, rg, lane, q0);
     const int ntiles = L.ntiles;  // the same in every wave of the block
@@ -891,8 +952,9 @@ __device__ __forceinline__ void m64_block_count(const DevGrid &G, const RefOut &
                     for (int s = (KS >= 2 ? KC : 0); s < KS; ++s)
                         a = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[s], T.b[s], a, 0, 0, 0);
                     unsigned long long w[4];
-                    m64_words<SLOT, KS>(a, T, g, q0, th, G, band, band_in, w);
+                    m64_words<SLOT, KS>(a, T, g, q0, th, G, band, band_in, w, sym);
                     nib_push(nacc, w);
+                    if (sym) sym_columns(nacc, T.c, R.cnt, lane);
                 }
                 if ((k & 7) == 7) nib_flush(nib, nacc, 8, (k >> 3) & 1);
                 if ((k & 15) == 15) group_done(k - 15);
@@ -905,15 +967,7 @@ __device__ __forceinline__ void m64_block_count(const DevGrid &G, const RefOut &
     }
     if (!active) return;
     if (flushed < ntiles) group_done(flushed);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        int v = tot[r];
-        v += __shfl_xor(v, 1);
-        v += __shfl_xor(v, 2);
-        v += __shfl_xor(v, 4);
-        v += __shfl_xor(v, 8);
-        if (j == 0 && g + 4 * r < nq) R.cnt[q0 + g + 4 * r] = v;
-    }
+    write_counts<SYM>(tot, R, q0, nq, g, j);
     if (lane == 0) {
         if (npruned) atomicAdd(&R.ctr->pruned, npruned);
         if (band) {
@@ -923,12 +977,12 @@ __device__ __forceinline__ void m64_block_count(const DevGrid &G, const RefOut &
     }
 }
 
-template <int KS, bool SLOT>
+template <int KS, bool SLOT, bool SYM>
 __global__ __launch_bounds__(kThreads) void k_m64s(DevGrid G, RefOut R, double delta, int nblocks) {
     __shared__ double lds[m64s_lds_doubles(KS)];
     const int bi = xcd_block(blockIdx.x, gridDim.x);
     if (bi >= nblocks) return;  // whole block
-    m64_block_count<KS, SLOT>(G, R, delta, bi, lds);
+    m64_block_count<KS, SLOT, SYM>(G, R, delta, bi, lds);
 }
 
 template <int KS, bool SLOT, int MODE>
@@ -989,7 +1043,9 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
     const int dp = G.dp;
     const double eps2 = G.eps2;
     const double *__restrict__ xs = G.xs;
-    const ItemRanges rg = load_ranges(G, it, lane);
+    ItemRanges rg = load_ranges(G, it, lane);
+    constexpr bool sym = MODE == MODE_SYM;
+    if (sym) sym_cut(rg, q0);
     // short-circuit interval in dimensions (0 = off): every 4 by default
     const int cd = (MODE == MODE_MEASURE || d <= 4 || G.sc == -1) ? 0 : 4 * (G.sc > 0 ? G.sc : 1);
 
@@ -1130,12 +1186,14 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
 #pragma unroll
             for (int r = 0; r < 4; ++r) w[r] &= cm;
         }
+        if (sym) sym_mask(w, T.c, T.n, q0, g, j);
         if (MODE == MODE_EMIT) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) w[r] &= ebal[r];
             tile_store(w, T.c, T.pc, ro, g, j, G, R, q0);
         } else {
             nib_push(nacc, w);
+            if (sym) sym_columns(nacc, T.c, R.cnt, lane);
             if ((k & 7) == 7) nib_flush(nib, nacc, 8, (k >> 3) & 1);
         }
     };
@@ -1168,19 +1226,11 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
         load(T0, k + 4, cand[0]);
         load(T1, k + 5, cand[1]);
         run(T2, T3, k + 2);
-        if (MODE == MODE_COUNT && (c & 3) == 3) group_done(k - 12);
+        if (is_count(MODE) && (c & 3) == 3) group_done(k - 12);
     }
-    if (MODE == MODE_COUNT) {
+    if (is_count(MODE)) {
         if (flushed < ntiles) group_done(flushed);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int v = tot[r];
-            v += __shfl_xor(v, 1);
-            v += __shfl_xor(v, 2);
-            v += __shfl_xor(v, 4);
-            v += __shfl_xor(v, 8);
-            if (j == 0 && g + 4 * r < nq) R.cnt[q0 + g + 4 * r] = v;
-        }
+        write_counts<sym>(tot, R, q0, nq, g, j);
         if (lane == 0 && npruned) atomicAdd(&R.ctr->pruned, npruned);
     }
 }
@@ -1490,7 +1540,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_m64s(const BProb *__restrict
         const int p = batch_problem(block_base, B, gb);
         const BProb &P = probs[p];
         const RefOut R = batch_out(P, nullptr, ctr, MODE_COUNT);
-        m64_block_count<KS, SLOT>(P.G, R, P.delta, uniform_i32(gb - (int)block_base[p]), lds);
+        m64_block_count<KS, SLOT, false>(P.G, R, P.delta, uniform_i32(gb - (int)block_base[p]), lds);
     }
 }
 
@@ -1637,10 +1687,10 @@ void launch_m64(const Grid &g, const RefOut &R, int nitems, double delta, hipStr
     const bool slot = (g.d & 3) != 0;
     const int ks = g.da >> 2;
     // count of every item, 2 to 4 K-steps, united block items: LDS-shared tiles
-    if (MODE == MODE_COUNT && g.united && g.nblocks > 0 && ks >= 2 && ks <= 4 && R.item_lo == 0 &&
+    if (is_count(MODE) && g.united && g.nblocks > 0 && ks >= 2 && ks <= 4 && R.item_lo == 0 &&
         nitems == (int)g.items) {
         const unsigned nb = (unsigned)g.nblocks;
-#define SJ_M64S(KSV, SL) hipLaunchKernelGGL((k_m64s<KSV, SL>), dim3(nb), dim3(kThreads), 0, s, G, R, delta, (int)nb)
+#define SJ_M64S(KSV, SL) hipLaunchKernelGGL((k_m64s<KSV, SL, MODE == MODE_SYM>), dim3(nb), dim3(kThreads), 0, s, G, R, delta, (int)nb)
         if (slot) {
             if (ks == 2) SJ_M64S(2, true);
             else if (ks == 3) SJ_M64S(3, true);
@@ -1810,6 +1860,28 @@ HostCounters read_counters(const DevCounters &c) {
     return h;
 }
 
+namespace {
+
+// Candidate pairs a half-stencil count evaluates: per item, its ranges cut
+// at its first query, times its queries (grid-stride over item x range; one
+// atomic per wave).
+__global__ __launch_bounds__(kThreads) void k_sym_cand(DevGrid G, unsigned long long *out) {
+    unsigned long long acc = 0;
+    const int64_t total = (int64_t)G.nitems * G.nranges;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t it = t / G.nranges;
+        const Item I = G.items[it];
+        const Range r = G.ranges[t];
+        const int32_t b = max(r.begin, I.qbegin);
+        if (r.end > b) acc += (unsigned long long)(I.qend - I.qbegin) * (unsigned long long)(r.end - b);
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
+}
+
+}  // namespace
+
 // Enqueues the count kernel of `path` (already range-checked); its counters
 // land in ro.ctr (device, zeroed here), read back by the caller with the
 // total.
@@ -1820,16 +1892,23 @@ void refine_count(Grid &g, sj_path path, int32_t *cnt_sorted, RefineOut &ro, hip
     R.ctr = ro.ctr;
     R.item_lo = 0;
     R.masks = ro.masks;
+    const bool sym = ro.sym && (path == SJ_FP64_VALU || path == SJ_FP64_MFMA);
     ro.cand_eval = g.cand_items;
+    if (sym && g.items > 0) {
+        hipLaunchKernelGGL(k_sym_cand, dim3(64), dim3(kThreads), 0, s, dev_grid(g), &ro.ctr->spare[0]);
+        SJ_HIP(hipGetLastError());
+    }
     if (path == SJ_FP64_VALU) {
         ro.kt.start(ro.timed, s);
-        launch_v64<MODE_COUNT>(g, R, (int)g.items, s);
+        if (sym) launch_v64<MODE_SYM>(g, R, (int)g.items, s);
+        else launch_v64<MODE_COUNT>(g, R, (int)g.items, s);
         ro.kt.stop(s);
         ro.band_rel = 0.0;
     } else if (path == SJ_FP64_MFMA) {
         const double delta = m64_delta(g);
         ro.kt.start(ro.timed, s);
-        launch_m64<MODE_COUNT>(g, R, (int)g.items, delta, s);
+        if (sym) launch_m64<MODE_SYM>(g, R, (int)g.items, delta, s);
+        else launch_m64<MODE_COUNT>(g, R, (int)g.items, delta, s);
         ro.kt.stop(s);
         ro.band_rel = g.eps2 > 0 ? delta / g.eps2 : 0.0;
     } else {

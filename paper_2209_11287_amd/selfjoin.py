@@ -89,11 +89,11 @@ class TorchAllocHook:
 
 
 def selfjoin_build_grid(points, eps: float, index_dims: int = 0, stream=None, torch_alloc: bool = False,
-                        short_circuit: int = 0, dim_order: int = 0) -> GridHandle:
+                        short_circuit: int = 0, dim_order: int = 0, symmetric: int = 0) -> GridHandle:
     """points: CUDA float64 tensor (n, d), C-contiguous. torch_alloc: every
     device buffer of the handle comes from torch's caching allocator through
-    the sj_opts allocator hook. short_circuit, dim_order: sj_opts fields of
-    the same names (filter choices; the result does not depend on them)."""
+    the sj_opts allocator hook. short_circuit, dim_order, symmetric: sj_opts
+    fields of the same names (the result does not depend on them)."""
     torch = _torch()
     if not isinstance(points, torch.Tensor) or not points.is_cuda:
         raise ValueError("points must be a CUDA tensor")
@@ -105,6 +105,7 @@ def selfjoin_build_grid(points, eps: float, index_dims: int = 0, stream=None, to
     opts.index_dims = index_dims
     opts.short_circuit = short_circuit
     opts.dim_order = dim_order
+    opts.symmetric = symmetric
     hook = TorchAllocHook(points.device) if torch_alloc else None
     if hook is not None:
         opts.alloc = hook.alloc
@@ -264,9 +265,10 @@ def selfjoin_free_grid(g: GridHandle, stream=None):
 class SelfJoin:
     """Convenience wrapper: grid + count + all pairs."""
 
-    def __init__(self, points, eps, index_dims=0, stream=None, torch_alloc=False, short_circuit=0, dim_order=0):
+    def __init__(self, points, eps, index_dims=0, stream=None, torch_alloc=False, short_circuit=0, dim_order=0,
+                 symmetric=0):
         self.grid = selfjoin_build_grid(points, eps, index_dims, stream, torch_alloc=torch_alloc,
-                                        short_circuit=short_circuit, dim_order=dim_order)
+                                        short_circuit=short_circuit, dim_order=dim_order, symmetric=symmetric)
         self.stream = stream
 
     def count(self, path="fp64_mfma", per_point=False):

@@ -18,13 +18,14 @@ def pair_keys(pairs) -> np.ndarray:
 
 
 def gpu_join(X: np.ndarray, eps: float, path: str, want_pairs=True, want_d2=False, capacity=None,
-             index_dims=0, short_circuit=0, dim_order=0):
+             index_dims=0, short_circuit=0, dim_order=0, symmetric=0):
     """Runs build + count (+ pairs) on cuda:0. Returns dict of host arrays."""
     import torch
     from paper_2209_11287_amd import SelfJoin, selfjoin_grid_info
 
     xt = torch.from_numpy(np.ascontiguousarray(X)).to("cuda:0")
-    sj = SelfJoin(xt, eps, index_dims=index_dims, short_circuit=short_circuit, dim_order=dim_order)
+    sj = SelfJoin(xt, eps, index_dims=index_dims, short_circuit=short_circuit, dim_order=dim_order,
+                  symmetric=symmetric)
     try:
         total, pp, st = sj.count(path, per_point=True)
         out = {"total": total, "per_point": pp.cpu().numpy() if pp is not None else None, "stats": st,
