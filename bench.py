@@ -25,6 +25,7 @@ import argparse
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -178,7 +179,10 @@ def one_pass(inputs, path, bufs, collect=None, cref=None, chunk=0, streams=None,
         collect.extend(rec)
 
 
-def timed(inputs, path, steps, warmup, bufs, cref, chunk=0, streams=None):
+def timed(inputs, path, steps, warmup, bufs, cref, chunk=0, streams=None, step_ms=None):
+    """Mean seconds per timed step and the per-step records; `step_ms` (list,
+    optional) receives each timed step's own wall time in ms (every step ends
+    with its work finished)."""
     import torch
     cost = [0.0] * len(inputs)
     for i in range(warmup):
@@ -189,8 +193,12 @@ def timed(inputs, path, steps, warmup, bufs, cref, chunk=0, streams=None):
     recs = []
     t0 = time.perf_counter()
     for _ in range(steps):
+        ts = time.perf_counter()
         rec = []
         one_pass(inputs, path, bufs, rec, chunk=chunk, streams=streams, order=order)
+        if step_ms is not None:
+            torch.cuda.synchronize()
+            step_ms.append((time.perf_counter() - ts) * 1e3)
         for r in rec:
             r["cand_ref"] = cref[r["name"]]
         recs.append(rec)
@@ -651,7 +659,9 @@ def main():
     streams = [torch.cuda.Stream() for _ in range(max(1, args.streams))] if args.streams > 1 else None
     log(f"[bench] path {args.path}: warmup {args.warmup}, steps {args.steps}, streams {max(1, args.streams)}")
     cref_map = {}
-    sec, recs = timed(inputs, args.path, args.steps, max(1, args.warmup), bufs, cref_map, args.chunk, streams)
+    step_ms = []
+    sec, recs = timed(inputs, args.path, args.steps, max(1, args.warmup), bufs, cref_map, args.chunk, streams,
+                      step_ms=step_ms)
     cref = sum(r["cand_ref"] for r in recs[0])
     pairs = sum(r["pairs"] for r in recs[0])
     out = {
@@ -662,6 +672,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(sec * 1e3, 3),
+        "step_ms": {"min": round(min(step_ms), 3), "median": round(statistics.median(step_ms), 3),
+                    "max": round(max(step_ms), 3)},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
