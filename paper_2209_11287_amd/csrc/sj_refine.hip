@@ -498,11 +498,34 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
     const int g = lane >> 4;   // K index of the operands; row group of the result
     const int qa = q0 + (j < nq ? j : 0);
     const double *__restrict__ xa = G.xa;
-    ItemRanges rg = load_ranges(G, it, lane);
     constexpr bool sym = MODE == MODE_SYM;
-    if (sym) sym_cut(rg, q0);
     const double eps2 = G.eps2;
     using Tile = M64Tile<KS, m64_nb(KS, MODE)>;
+    const bool sc_on = MODE != MODE_MEASURE && KS >= 2 && G.sc != -1;
+
+    // The item's loads first, all unconditional (indices clamped to valid
+    // rows), so that one wait covers them: its ranges, the A operand rows,
+    // the rows' norms and (one short-circuit check) prefix norms.
+    const Range rx = G.ranges[(int64_t)it * G.nranges + min(lane, G.nranges - 1)];
+    double xq[KS > 0 ? KS : 1];
+    if (KS > 0) {
+#pragma unroll
+        for (int s = 0; s < (KS > 0 ? KS : 1); ++s) xq[s] = xa[(int64_t)qa * da + 4 * s + g];  // 4s + g < da
+    }
+    double nrm4[4], pn4[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int qr = q0 + min(g + 4 * r, nq - 1);
+        nrm4[r] = G.nrm[qr];
+        pn4[r] = (KS >= 2 && KS <= 4 && sc_on) ? G.pn[(int64_t)qr * G.npc + (KS / 2 - 1)] : 0.0;
+    }
+    ItemRanges rg;
+    rg.nr = G.nranges;
+    rg.rb = lane < rg.nr ? rx.begin : 0;
+    rg.re = lane < rg.nr ? rx.end : 0;
+    // the bounds are settled here, before any tile load (see load_ranges)
+    __asm__ volatile("" : "+v"(rg.rb), "+v"(rg.re));
+    if (sym) sym_cut(rg, q0);
 
     // A operand (16 x K): A[i][k] = -2 q_i[k] for k < d, 1 in the norm slot.
     double aq[KS > 0 ? KS : 1];
@@ -510,7 +533,7 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
 #pragma unroll
         for (int s = 0; s < (KS > 0 ? KS : 1); ++s) {
             const int kk = 4 * s + g;
-            aq[s] = (j < nq && kk < d) ? -2.0 * xa[(int64_t)qa * da + kk] : ((SLOT && kk == d) ? 1.0 : 0.0);
+            aq[s] = (j < nq && kk < d) ? -2.0 * xq[s] : ((SLOT && kk == d) ? 1.0 : 0.0);
         }
     }
     // rows of this lane: queries g + 4r
@@ -521,7 +544,7 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
     for (int r = 0; r < 4; ++r) {
         const int i = g + 4 * r;
         const bool ok = i < nq;
-        const double nq_r = ok ? G.nrm[q0 + i] : 0.0;
+        const double nq_r = ok ? nrm4[r] : 0.0;
         th.nq[r] = nq_r;
         const double thr = eps2 - nq_r;
         th.lo[r] = ok ? thr - delta : -INFINITY;
@@ -546,15 +569,13 @@ __device__ __forceinline__ void m64_item(const DevGrid &G, const RefOut &R, doub
     // check every `every` K-steps (4 by default), tq of every K-step in a
     // per-wave LDS table [s][g][r], the candidates' prefix norms of a batch
     // of 4 K-steps spread over the lane's row group.
-    const bool sc_on = MODE != MODE_MEASURE && KS >= 2 && G.sc != -1;
     const int every = G.sc > 0 ? G.sc : 4;
     double tq[4];
     if (KS >= 2 && KS <= 4 && sc_on) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = g + 4 * r;
-            tq[r] = i < nq ? eps2 + delta + (SLOT ? 0.0 : th.nq[r]) - G.pn[(int64_t)(q0 + i) * G.npc + (KS / 2 - 1)]
-                           : -INFINITY;
+            tq[r] = i < nq ? eps2 + delta + (SLOT ? 0.0 : th.nq[r]) - pn4[r] : -INFINITY;
         }
     }
     if (KS > 4 && sc_on) {
@@ -1043,12 +1064,12 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
     const int dp = G.dp;
     const double eps2 = G.eps2;
     const double *__restrict__ xs = G.xs;
-    ItemRanges rg = load_ranges(G, it, lane);
     constexpr bool sym = MODE == MODE_SYM;
-    if (sym) sym_cut(rg, q0);
     // short-circuit interval in dimensions (0 = off): every 4 by default
     const int cd = (MODE == MODE_MEASURE || d <= 4 || G.sc == -1) ? 0 : 4 * (G.sc > 0 ? G.sc : 1);
 
+    // the item's loads first (ranges, query rows), one wait for them all
+    const Range rx = G.ranges[(int64_t)it * G.nranges + min(lane, G.nranges - 1)];
     bool rowok[4], emit_r[4];
     int qrow[4];
     double xq[4][D > 0 ? D : 1];
@@ -1063,6 +1084,13 @@ __device__ __forceinline__ void v64_item(const DevGrid &G, const RefOut &R, int 
             for (int u = 0; u < (D > 0 ? D : 1); ++u) xq[r][u] = xs[(int64_t)qrow[r] * dp + u];
         }
     }
+    ItemRanges rg;
+    rg.nr = G.nranges;
+    rg.rb = lane < rg.nr ? rx.begin : 0;
+    rg.re = lane < rg.nr ? rx.end : 0;
+    // the bounds are settled here, before any tile load (see load_ranges)
+    __asm__ volatile("" : "+v"(rg.rb), "+v"(rg.re));
+    if (sym) sym_cut(rg, q0);
     const bool use_lds = D == 0 && qlds != nullptr && d <= kV64LdsD;
     if (use_lds) {
         for (int i = 0; i < nq; ++i)
