@@ -1443,23 +1443,44 @@ __device__ __forceinline__ void mask_item(const DevGrid &G, const RefOut &R, con
     const int nq = uniform_i32(I.qend - I.qbegin);
     const int j = lane & 15;
     const int g = lane >> 4;
-    const ItemRanges rg = load_ranges(G, it, lane);
+    // the item's loads first, all unconditional (indices clamped to valid
+    // rows), one wait for them all: its ranges, its rows' output offsets
+    // and input indices, its first in-mask slot
+    const Range rx = G.ranges[(int64_t)it * G.nranges + min(lane, G.nranges - 1)];
     bool emit_r[4];
     unsigned erows = 0;  // rows of this lane that this launch emits
+    int64_t offr[4];
+    int32_t pqr[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = g + 4 * r;
+        const int q = q0 + min(i, nq - 1);
+        offr[r] = R.off[q];
+        pqr[r] = G.perm[q];
         emit_r[r] = i < nq && q0 + i >= R.qlo && q0 + i < R.qhi;
         erows |= emit_r[r] ? 1u << r : 0u;
     }
+    const int64_t toff = G.tile_off[it];
+    ItemRanges rg;
+    rg.nr = G.nranges;
+    rg.rb = lane < rg.nr ? rx.begin : 0;
+    rg.re = lane < rg.nr ? rx.end : 0;
+    // the bounds are settled here, before the group loads (see load_ranges)
+    __asm__ volatile("" : "+v"(rg.rb), "+v"(rg.re));
     const unsigned long long ekeep = 0x1111111111111111ull * erows;
-    RowOut ro;
-    row_out_init(ro, emit_r, G, R, q0, g, j);
+    RowOut ro;  // as row_out_init
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        ro.qb[r] = emit_r[r] ? offr[r] - R.base : 0;
+        ro.pq[r] = emit_r[r] ? pqr[r] : 0;
+        ro.cur[r] = 0;
+    }
+    ro.jlt = (1u << j) - 1u;
     int64_t base[4] = {ro.qb[0], ro.qb[1], ro.qb[2], ro.qb[3]};
     CandList L;
     cand_init(L, rg, lane, q0);
     const int ngroups = (L.ntiles + 15) >> 4;
-    const unsigned long long *mb = masks + G.tile_off[it] * 4;
+    const unsigned long long *mb = masks + toff * 4;
     MaskBatch nxt;
     if (ngroups > 0) mask_batch_load<D2>(nxt, L, mb, G, 0, lane);
     for (int gi = 0; gi < ngroups; ++gi) {
