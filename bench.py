@@ -691,6 +691,11 @@ def main():
     # else on the GPU: the duration rocprofv3 reports for the same launches);
     # with several streams the timed steps' launch times include sharing the
     # GPU with the other streams' kernels, kept under "shared"
+    if streams:
+        # one untimed pass on the single stream first: the library's caching
+        # allocator keeps blocks per stream, so a first pass there would time
+        # fresh allocations (and their first touch) instead of the kernels
+        one_pass(inputs, args.path, bufs, None, chunk=args.chunk)
     iso = isolated(inputs, args.path, bufs, cref_map, args.chunk) if streams else recs[-1]
     cnt_iso = sum(r["count_kernel_ms"] for r in iso)
     emit_iso = sum(r["emit_kernel_ms"] for r in iso)
