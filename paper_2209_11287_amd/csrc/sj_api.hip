@@ -292,6 +292,8 @@ static void compute_counts(Grid &g, sj_path path, bool timed, CountRun &cr, hipS
     // half stencil (FP64 paths): counts accumulate from zero, no in-masks
     const bool sym = fp64 && g.sym != 0;
     g.masks_valid = false;
+    g.lp_masks_valid = false;
+    ro.record_lp = is_lowp(path) && !g.lean;
     if (fp64 && !sym && !g.lean && !g.masks && g.tiles > 0 && g.tiles * 32 <= kMaskBudget)
         g.masks = dev_alloc_n<unsigned long long>((size_t)g.tiles * 4, s);
     ro.masks = fp64 && !sym ? g.masks : nullptr;
@@ -309,6 +311,7 @@ static void compute_counts(Grid &g, sj_path path, bool timed, CountRun &cr, hipS
     SJ_HIP(hipStreamSynchronize(s));
     g.total = total;
     g.masks_valid = ro.masks != nullptr;
+    g.lp_masks_valid = ro.record_lp && g.lp_masks != nullptr;
     g.count_path = path;
     cr.ran = true;
     cr.hc = read_counters(hctr);

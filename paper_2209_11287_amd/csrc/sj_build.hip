@@ -1192,7 +1192,7 @@ void free_grid(Grid &g, hipStream_t s) {
     }
     void *bufs[] = {g.xs,   g.xa,       g.nrm,        g.perm,       g.cell_key, g.cell_start, g.ranges,
                     g.item, g.dev_nmax, g.line_first, g.line_table, g.blocks,   g.cnt,        g.off, g.ctr,
-                    g.tile_off, g.masks, g.pn};
+                    g.tile_off, g.masks, g.pn, g.lp_goff, g.lp_masks};
     for (void *p : bufs)
         if (p) dev_free(p, s);
     g.xs = g.xa = g.nrm = g.pn = nullptr;
@@ -1211,6 +1211,10 @@ void free_grid(Grid &g, hipStream_t s) {
     g.tile_off = nullptr;
     g.masks = nullptr;
     g.masks_valid = false;
+    g.lp_goff = nullptr;
+    g.lp_masks = nullptr;
+    g.lp_groups = -1;
+    g.lp_masks_valid = false;
 }
 
 // Host-side reading of the grid geometry; identical arithmetic to the

@@ -210,6 +210,15 @@ struct Grid {
     // word r, bit 16g + j = query g + 4r of the item, candidate j of the tile)
     unsigned long long *masks = nullptr;
     bool masks_valid = false;
+    // in-masks written by the low-precision count passes (after their FP64
+    // recheck, so exact): per block item, its 64-candidate tiles in groups
+    // of 4; per group 4 waves x 64 lanes x 64 bits (bit 4 (4 t + s) + r of
+    // lane (g, j) = query 4g + r of the wave's item, candidate 16 s + j of
+    // tile t of the group); lp_goff = first group of each block item (+ total)
+    int64_t *lp_goff = nullptr;
+    int64_t lp_groups = -1;      // -1 until the layout is computed
+    unsigned long long *lp_masks = nullptr;
+    bool lp_masks_valid = false;
     double *dev_nmax = nullptr;  // device copy of nmax
 
     // cached per-query counts (sorted order) and their exclusive prefix sums
@@ -298,6 +307,7 @@ struct RefineOut {
     KernelTimer kt;          // those events
     DevCounters *ctr = nullptr;            // device counters (zeroed by the launcher)
     unsigned long long *masks = nullptr;   // per-tile in-masks to record (FP64 count), nullable
+    bool record_lp = false;  // low-precision count: record its in-masks (layout and buffer on the grid)
     double band_rel = 0;     // largest band half-width / eps^2
     int64_t cand_eval = 0;
     bool sym = false;        // FP64 count: half stencil (counts zeroed by the caller); the

@@ -46,6 +46,11 @@
 // D <= thr - Delta are in, D > thr + Delta out, the rest are re-evaluated
 // with the exact FP64 chain on the original coordinates: the result is the
 // exact set.
+//
+// In-masks. The count pass records each wave's final in-bits (after the
+// recheck, so exact) per 64-candidate tile of its block item, and a pairs
+// pass then expands them (MODE_MASKEMIT: no staging, no distances) in the
+// count's tile order, instead of running the tiles again.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -65,7 +70,8 @@ constexpr int kRing = 512;
 typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef short short8_t __attribute__((ext_vector_type(8)));
 
-enum { MODE_COUNT = 0, MODE_EMIT = 1, MODE_MEASURE = 2 };
+// MODE_MASKEMIT: the pairs of a count's recorded in-masks.
+enum { MODE_COUNT = 0, MODE_EMIT = 1, MODE_MEASURE = 2, MODE_MASKEMIT = 3 };
 enum { PREC_F32 = 0, PREC_BF16 = 1, PREC_BF16X3 = 2, PREC_FP8 = 3 };
 
 struct LpGrid {
@@ -91,7 +97,36 @@ struct LpOut {
     double *d2;
     DevCounters *ctr;              // rechecks, band widths (scaled units), measurements
     int32_t block_lo;              // first block item of this launch
+    unsigned long long *masks;     // count: in-masks to record (nullable); MODE_MASKEMIT: to expand
+    const int64_t *goff;           // first mask group of each block item
 };
+
+// The block item's candidate list along neighbour line o (lane o < nranges):
+// from the smallest begin to the largest end of its items' ranges.
+__device__ __forceinline__ void block_span(const LpGrid &G, int ib, int ie, int o, int &rb, int &re) {
+    rb = G.ranges[(int64_t)ib * G.nranges + o].begin;
+    re = G.ranges[(int64_t)ib * G.nranges + o].end;
+    for (int it = ib + 1; it < ie; ++it) {
+        const Range r = G.ranges[(int64_t)it * G.nranges + o];
+        rb = min(rb, r.begin);
+        re = max(re, r.end);
+    }
+}
+
+// Mask groups of each block item: its 64-candidate tiles (per neighbour
+// line, ceil(length / 64)) in groups of 4.
+__global__ __launch_bounds__(kThreads) void k_lp_groups(LpGrid G, int32_t *__restrict__ groups) {
+    const int bi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bi >= G.nblocks) return;
+    const int ib = G.blocks[bi], ie = G.blocks[bi + 1];
+    int tiles = 0;
+    for (int o = 0; o < G.nranges; ++o) {
+        int rb, re;
+        block_span(G, ib, ie, o, rb, re);
+        if (re > rb) tiles += (re - rb + kTC - 1) / kTC;
+    }
+    groups[bi] = (tiles + 3) >> 2;
+}
 
 __device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -296,20 +331,26 @@ __device__ __forceinline__ short8_t lds_bf16x8(const uint32_t *w) {
     return v;
 }
 
+// The FP32 and split-BF16 counts fit four waves per SIMD (at most 128
+// VGPRs) with the in-mask recording as without it.
 template <int PREC, int MODE>
-__global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(MODE == MODE_COUNT && (PREC == PREC_F32 || PREC == PREC_BF16X3) ? 4 : 1, 8)))
+void k_lowp(LpGrid G, LpOut R) {
     constexpr int KMAX = lp_kmax<PREC>();
     constexpr int STR = lp_stride<PREC>();
     constexpr int KSTEP = Prec<PREC>::kstep;
-    __shared__ double xr[kLpMaxD];                   // reference row
+    constexpr bool kTiles = MODE != MODE_MASKEMIT;   // stage and compute tiles
+    constexpr bool kEmit = MODE == MODE_EMIT || MODE == MODE_MASKEMIT;
+    __shared__ double xr[kTiles ? kLpMaxD : 1];      // reference row
     // plain BF16 rechecks tens of percent of its pairs: it keeps the FP64
     // rows in LDS; the narrower-band paths read them from global memory
-    constexpr bool kRowsInLds = PREC == PREC_BF16 || PREC == PREC_FP8;
+    constexpr bool kRowsInLds = kTiles && (PREC == PREC_BF16 || PREC == PREC_FP8);
     __shared__ double f64t[kRowsInLds ? kTC : 1][kLpMaxD + 1];
-    __shared__ uint32_t lpt[kTC * STR];              // rounded, centred rows (split BF16: hi)
-    __shared__ uint32_t lptl[PREC == PREC_BF16X3 ? kTC * STR : 1];  // split BF16: lo
-    __shared__ float nc32[kTC];                      // their norms (FP32, accumulator init)
-    __shared__ uint32_t ring_lds[MODE == MODE_EMIT ? kWaves * 3 * kRing : 1];
+    __shared__ uint32_t lpt[kTiles ? kTC * STR : 1];  // rounded, centred rows (split BF16: hi)
+    __shared__ uint32_t lptl[kTiles && PREC == PREC_BF16X3 ? kTC * STR : 1];  // split BF16: lo
+    __shared__ float nc32[kTiles ? kTC : 1];         // their norms (FP32, accumulator init)
+    __shared__ uint32_t ring_lds[kEmit ? kWaves * 3 * kRing : 1];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -322,9 +363,11 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
     const int ks = K / KSTEP;
 
     // reference point: the block's first query
-    const int qref = G.items[ib].qbegin;
-    if (tid < d) xr[tid] = G.xs[(int64_t)qref * dp + tid];
-    __syncthreads();
+    if constexpr (kTiles) {
+        const int qref = G.items[ib].qbegin;
+        if (tid < d) xr[tid] = G.xs[(int64_t)qref * dp + tid];
+        __syncthreads();
+    }
 
     // this wave's queries
     const bool has_q = ib + wv < ie;
@@ -342,7 +385,7 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
     typename Prec<PREC>::operand_t aq[(KMAX + KSTEP - 1) / KSTEP];
     short8_t aql[PREC == PREC_BF16X3 ? (KMAX + KSTEP - 1) / KSTEP : 1];  // split BF16: -2 lo
     double nq_part = 0.0;
-    {
+    if constexpr (kTiles) {
         const double *qrow = G.xs + (int64_t)(q0 + (j < nq ? j : 0)) * dp;
 #pragma unroll
         for (int s = 0; s < (KMAX + KSTEP - 1) / KSTEP; ++s) {
@@ -409,22 +452,22 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
         const double thr = G.eps2_s - v;
         lo[r] = i < nq ? (float)(thr - dlt[r]) : -INFINITY;
         hi[r] = i < nq ? (float)(thr + dlt[r]) : -INFINITY;
-        if (i < nq) maxdelta = fmax(maxdelta, dlt[r]);
+        if (kTiles && i < nq) maxdelta = fmax(maxdelta, dlt[r]);
     }
     // emission state
     bool emit_r[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = 4 * g + r;
-        emit_r[r] = MODE == MODE_EMIT && i < nq && q0 + i >= R.qlo && q0 + i < R.qhi;
+        emit_r[r] = kEmit && i < nq && q0 + i >= R.qlo && q0 + i < R.qhi;
     }
     int64_t pbase_lane = -1;
     int32_t pq_lane = 0;
-    if (MODE == MODE_EMIT && lane < nq && q0 + lane >= R.qlo && q0 + lane < R.qhi) {
+    if (kEmit && lane < nq && q0 + lane >= R.qlo && q0 + lane < R.qhi) {
         pbase_lane = R.off[q0 + lane] - R.base;
         pq_lane = G.perm[q0 + lane];
     }
-    uint32_t *rcand = ring_lds + (MODE == MODE_EMIT ? wv * 3 * kRing : 0);
+    uint32_t *rcand = ring_lds + (kEmit ? wv * 3 * kRing : 0);
     uint32_t *rrel = rcand + kRing;
     uint32_t *rcol = rrel + kRing;
     int head = 0, tail = 0;
@@ -453,15 +496,16 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
     // per neighbour line, the span of the block's items' ranges (the items'
     // ranges may be cut to their own coordinate extents)
     int rb = 0, re = 0;
-    if (lane < G.nranges) {
-        rb = G.ranges[(int64_t)ib * G.nranges + lane].begin;
-        re = G.ranges[(int64_t)ib * G.nranges + lane].end;
-        for (int it = ib + 1; it < ie; ++it) {
-            const Range r = G.ranges[(int64_t)it * G.nranges + lane];
-            rb = min(rb, r.begin);
-            re = max(re, r.end);
-        }
-    }
+    if (lane < G.nranges) block_span(G, ib, ie, lane, rb, re);
+    // in-masks: this wave's words of the block item's groups (4 tiles each)
+    const bool rec = MODE == MODE_COUNT && R.masks != nullptr && has_q;
+    // first word of this wave (wave-uniform; lane l adds l)
+    const int64_t mbase = (MODE == MODE_COUNT || MODE == MODE_MASKEMIT) && R.masks
+                              ? ((int64_t)__builtin_amdgcn_readfirstlane((int)(R.goff[bi] >> 32)) << 32 |
+                                 (uint32_t)__builtin_amdgcn_readfirstlane((int)R.goff[bi])) * (kWaves * 64) + wv * 64
+                              : 0;
+    unsigned long long mword = 0;
+    int tix = 0;  // tiles of the block item so far (block-uniform)
     // Tiles of 64 candidates over the block's ranges, in order. The next
     // tile's FP64 rows are loaded into registers while the current one is
     // computed; 4 threads per row, thread `part` holding dimensions
@@ -488,6 +532,50 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
             pre[cc] = (rowok && k < d) ? src[k] : 0.0;
         }
     };
+    if constexpr (MODE == MODE_MASKEMIT) {
+        // expand the count's in-masks: the same tile walk, one word per
+        // group of 4 tiles, no staging and no block synchronisation
+        if (!has_q) return;
+        bool more = advance();
+        while (more) {
+            const int t = t_next;
+            const int nvalid = min(kTC, e_next - t_next);
+            if ((tix & 3) == 0) mword = R.masks[mbase + (int64_t)(tix >> 2) * (kWaves * 64) + lane];
+            for (int sub = 0; sub < kTC / 16; ++sub) {
+                if (16 * sub >= nvalid) break;
+                const int crow = 16 * sub + j;
+                const unsigned inm = (unsigned)(mword >> (4 * (4 * (tix & 3) + sub))) & 0xFu;
+                unsigned long long bal[4];
+                int base_e = 0;
+                int pre[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    bal[r] = __ballot(emit_r[r] && ((inm >> r) & 1u));
+                    pre[r] = base_e + __popcll(bal[r] & lt);
+                    base_e += __popcll(bal[r]);
+                }
+                if (base_e) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        if (emit_r[r] && ((inm >> r) & 1u)) {
+                            const int e = (tail + pre[r]) & (kRing - 1);
+                            rcand[e] = (uint32_t)(t + crow);
+                            rrel[e] = (uint32_t)(cur[r] + __popcll(bal[r] & lt & grp));
+                            rcol[e] = (uint32_t)(4 * g + r);
+                        }
+                    }
+                    tail += base_e;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) cur[r] += __popcll(bal[r] & grp);
+                    while (tail - head >= 64) flush(64);
+                }
+            }
+            ++tix;
+            more = advance();
+        }
+        if (tail > head) flush(tail - head);
+        return;
+    }
     bool have = advance();
     if (have) prefetch();
     while (have) {
@@ -531,6 +619,7 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
         __syncthreads();
         have = advance();
         if (have) prefetch();  // in flight during this tile's MFMAs
+        const int tcur = tix++;
         if (!has_q) continue;
         for (int sub = 0; sub < kTC / 16; ++sub) {
             if (16 * sub >= nvalid) break;
@@ -640,7 +729,12 @@ __global__ __launch_bounds__(kThreads) void k_lowp(LpGrid G, LpOut R) {
             } else {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) cnt[r] += (inm >> r) & 1u;
+                if (rec) mword |= (unsigned long long)inm << (4 * (4 * (tcur & 3) + sub));
             }
+        }
+        if (rec && ((tcur & 3) == 3 || !have)) {  // the group's last tile, or the list's
+            R.masks[mbase + (int64_t)(tcur >> 2) * (kWaves * 64) + lane] = mword;
+            mword = 0;
         }
     }
     if (MODE == MODE_EMIT && has_q && tail > head) flush(tail - head);
@@ -725,14 +819,46 @@ bool lowp_in_range(const Grid &g, sj_path path) {
     return true;
 }
 
+namespace {
+
+// The in-mask layout of a grid (once per grid: it depends only on the block
+// items and their ranges): groups per block item, their exclusive prefix
+// (one host sync for the total), and the buffer if it fits the budget.
+void lp_mask_layout(Grid &g, hipStream_t s) {
+    if (g.lp_groups >= 0) return;
+    const int64_t nb = g.nblocks;
+    g.lp_goff = dev_alloc_n<int64_t>((size_t)nb + 1, s);
+    int32_t *groups = dev_alloc_n<int32_t>((size_t)nb + 1, s);
+    fill_zero(groups + nb, sizeof(int32_t), s);  // the scan's last entry: the total
+    if (nb > 0) {
+        hipLaunchKernelGGL(k_lp_groups, dim3((unsigned)((nb + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                           lp_grid(g), groups);
+        SJ_HIP(hipGetLastError());
+    }
+    exclusive_scan_i32_to_i64(groups, g.lp_goff, nb + 1, s);
+    int64_t total = 0;
+    SJ_HIP(hipMemcpyAsync(&total, g.lp_goff + nb, sizeof total, hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    dev_free(groups, s);
+    g.lp_groups = total;
+    const int64_t bytes = total * kWaves * 64 * (int64_t)sizeof(unsigned long long);
+    if (total > 0 && bytes <= kMaskBudget) g.lp_masks = dev_alloc_n<unsigned long long>((size_t)bytes / 8, s);
+}
+
+}  // namespace
+
 // Count: per-query counts into cnt_sorted; counters (band half-widths in
-// the tiles' scaled units) in ro.ctr, zeroed here.
+// the tiles' scaled units) in ro.ctr, zeroed here. With ro.record_lp the
+// pass records its in-masks on the grid (g.lp_masks, if they fit).
 void lowp_count(Grid &g, sj_path path, int32_t *cnt_sorted, RefineOut &ro, hipStream_t s) {
+    if (ro.record_lp) lp_mask_layout(g, s);
     fill_zero(ro.ctr, sizeof(DevCounters), s);
     LpOut R{};
     R.cnt = cnt_sorted;
     R.ctr = ro.ctr;
     R.block_lo = 0;
+    R.masks = ro.record_lp ? g.lp_masks : nullptr;
+    R.goff = g.lp_goff;
     ro.kt.start(ro.timed, s);
     launch_lowp<MODE_COUNT>(g, path, R, (int)g.nblocks, s);
     ro.kt.stop(s);
@@ -752,7 +878,13 @@ void lowp_pairs(Grid &g, sj_path path, const ChunkPlan &p, int64_t qlo, int32_t 
     fill_zero(ro.ctr, sizeof(DevCounters), s);
     R.block_lo = (int32_t)p.block_lo;
     ro.kt.start(ro.timed, s);
-    launch_lowp<MODE_EMIT>(g, path, R, (int)(p.block_hi - p.block_lo), s);
+    if (g.lp_masks_valid && g.lp_masks) {  // expand the count's in-masks
+        R.masks = g.lp_masks;
+        R.goff = g.lp_goff;
+        launch_lowp<MODE_MASKEMIT>(g, path, R, (int)(p.block_hi - p.block_lo), s);
+    } else {
+        launch_lowp<MODE_EMIT>(g, path, R, (int)(p.block_hi - p.block_lo), s);
+    }
     ro.kt.stop(s);
 }
 

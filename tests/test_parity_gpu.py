@@ -397,3 +397,39 @@ def test_knn_rejects_bad_arguments():
         assert int(found.min()) >= 0 and int(found.max()) <= 4
     finally:
         sj.close()
+
+
+@pytest.mark.parametrize("path", LOWP)
+@pytest.mark.parametrize("d", [3, 16])
+def test_low_precision_pairs_from_masks_and_from_tiles(path, d):
+    # after a count on the same path the pairs pass expands the count's
+    # in-masks; after an FP64 count it runs the tiles again: both the exact
+    # set, whole and in chunks
+    import torch
+
+    import oracle
+    from paper_2209_11287_amd import selfjoin_build_grid, selfjoin_count, selfjoin_pairs
+    X = gen.make("gmm", 3001, d, seed=40 + d)
+    eps = _eps_for(X, 20)
+    _, pp, op = oracle.grid_pairs(X, eps)
+    xt = torch.from_numpy(X).to("cuda:0")
+    for count_path in (path, "fp64_valu"):
+        log(f"[lp-masks] path={path} d={d} count_path={count_path}")
+        g = selfjoin_build_grid(xt, eps)
+        try:
+            total, per, _ = selfjoin_count(g, count_path, per_point=True)
+            assert total == len(op)
+            assert np.array_equal(per.cpu().numpy(), pp)
+            buf = torch.empty((total, 2), dtype=torch.int32, device="cuda:0")
+            w, nxt, _ = selfjoin_pairs(g, path, 0, buf, None, total)
+            assert (w, nxt) == (total, X.shape[0])
+            assert np.array_equal(pair_keys(buf.cpu().numpy()), pair_keys(op))
+            cap = int(pp.max()) + 7
+            small = torch.empty((cap, 2), dtype=torch.int32, device="cuda:0")
+            got, cursor = [], 0
+            while cursor < X.shape[0]:
+                w, cursor, _ = selfjoin_pairs(g, path, cursor, small, None, cap)
+                got.append(small[:w].cpu().numpy())
+            assert np.array_equal(pair_keys(np.concatenate(got)), pair_keys(op))
+        finally:
+            g.close()

@@ -128,15 +128,22 @@ def test_pairs_pass_reports_its_own_rechecks(path):
         buf = torch.empty((total, 2), dtype=torch.int32, device="cuda:0")
         wr, nxt, st_p = selfjoin_pairs(sj.grid, path, 0, buf, None, total)
         assert wr == total and nxt == X.shape[0]
+        # after a count on the same path the pairs pass expands its in-masks:
+        # no tile runs, no recheck
+        assert st_p["rechecked"] == 0 and st_p["rechecked_in"] == 0
+        assert st_p["ms_refine"] == 0.0 and st_p["ms_emit"] > 0  # counts were cached
+        # after an FP64 count the pairs pass re-runs the tiles, so it meets
+        # the same band pairs as the low-precision count
+        sj.count("fp64_valu")
+        wr2, _, st_p2 = selfjoin_pairs(sj.grid, path, 0, buf, None, total)
+        assert wr2 == total
         log(f"[stats] {path} count rechecked={st_c['rechecked']} in={st_c['rechecked_in']} "
-            f"pairs rechecked={st_p['rechecked']} in={st_p['rechecked_in']}")
-        # the emission pass re-runs the tiles, so it meets the same band pairs
-        assert st_p["rechecked"] == st_c["rechecked"]
-        assert st_p["rechecked_in"] == st_c["rechecked_in"]
+            f"pairs (tiles) rechecked={st_p2['rechecked']} in={st_p2['rechecked_in']}")
+        assert st_p2["rechecked"] == st_c["rechecked"]
+        assert st_p2["rechecked_in"] == st_c["rechecked_in"]
         if path != "fp32_mfma":  # the BF16 bands are wide enough to catch pairs here
             assert st_c["rechecked"] > 0
         assert 0 <= st_c["rechecked_in"] <= st_c["rechecked"]
-        assert st_p["ms_refine"] == 0.0 and st_p["ms_emit"] > 0  # counts were cached
     finally:
         sj.close()
 
