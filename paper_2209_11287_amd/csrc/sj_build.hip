@@ -736,6 +736,84 @@ __global__ void k_gather(const double *__restrict__ X, const int32_t *__restrict
     block_max_out(nn, nmax_part);
 }
 
+// The same rows, norms and prefix norms as k_gather (the same FP64
+// operations in the same order, so the same bits) for 5 <= d <= 64, with
+// every row read and written whole by one wave instruction: one wave per
+// block, 32 rows per block staged in LDS. Lane t handles column t of a row
+// (raw value, then the centred value of input dimension fo[t]); the norm
+// chain runs per row in one lane over the staged columns in order, and the
+// prefix norms leave through LDS as whole rows too.
+constexpr int kGatherRows = 32;
+constexpr int kGatherLdsD = 64;
+
+__global__ __launch_bounds__(64) void k_gather_lds(const double *__restrict__ X, const int32_t *__restrict__ perm,
+                                                   int64_t n, const GatherArgs ga_v, double *__restrict__ xs,
+                                                   double *__restrict__ xa, double *__restrict__ nrm,
+                                                   double *__restrict__ pn, double *__restrict__ nmax_part) {
+    __shared__ double row[kGatherRows][kGatherLdsD + 1];  // +1: a column of the rows falls in distinct banks
+    const GatherArgs *ga = &ga_v;
+    const int lane = threadIdx.x;
+    const int d = ga->d, dp = ga->dp, da = ga->da, npc = ga->npc;
+    // this lane's column: its input dimension and centre (uniform loop, no
+    // lane-indexed access to the argument block)
+    int my_fo = 0;
+    double my_mid = 0.0;
+    for (int t = 0; t < d; ++t) {
+        const int u = ga->fo[t];
+        const double m = ga->mid[u];
+        if (lane == t) {
+            my_fo = u;
+            my_mid = m;
+        }
+    }
+    const int64_t i0 = (int64_t)blockIdx.x * kGatherRows;
+    const int nr = (int)min<int64_t>(kGatherRows, n - i0);
+    // rows in, whole; sorted rows out, whole
+    for (int r = 0; r < nr; ++r) {
+        const int64_t src = (int64_t)perm[i0 + r] * d;
+        const double v = lane < d ? X[src + lane] : 0.0;
+        if (lane < d) row[r][lane] = v;
+        if (lane < dp) xs[(i0 + r) * dp + lane] = v;  // zero past d
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // centred rows in the tile order, whole (in place: each row's permuted
+    // reads complete before its writes; one wave)
+    for (int r = 0; r < nr; ++r) {
+        const double c = lane < d ? __dsub_rn(row[r][my_fo], my_mid) : 0.0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < d) row[r][lane] = c;
+        if (lane < da && !((d & 3) && lane == d)) xa[(i0 + r) * da + lane] = c;  // slot d: the norm, below
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // the norm chain of row `lane`; prefix norms back into the row's first
+    // npc columns (each written after the columns it covers were read)
+    double nn = 0.0;
+    if (lane < nr) {
+        for (int t = 0; t < d; ++t) {
+            const double c = row[lane][t];
+            nn = __fma_rn(c, c, nn);
+            if ((t & 3) == 3 && (t >> 2) < npc) row[lane][t >> 2] = nn;
+        }
+        nrm[i0 + lane] = nn;
+        if (d & 3) xa[(i0 + lane) * da + d] = nn;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (npc > 0)
+        for (int r = 0; r < nr; ++r)
+            if (lane < npc) pn[(i0 + r) * npc + lane] = row[r][lane];
+    double v = nn;
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    if (lane == 0) nmax_part[blockIdx.x] = v;
+}
+
 // d <= 4 (dp = da = 4): four lanes per point, lane t = dimension t, so each
 // wave stores 16 whole rows of xs and of xa contiguously. Same values as
 // k_gather (the norm chain runs over the dimensions in order in every lane).
@@ -1437,7 +1515,10 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
                     {acc, 3 * sizeof(unsigned long long)}},
                    s);
     if (n > 0) {
-        const unsigned nb = d <= 4 ? std::min(blocks_for(4 * n), 4096u) : blocks_for(n);
+        const bool lds_rows = d > 4 && d <= kGatherLdsD;
+        const unsigned nb = d <= 4 ? std::min(blocks_for(4 * n), 4096u)
+                            : lds_rows ? (unsigned)((n + kGatherRows - 1) / kGatherRows)
+                                       : blocks_for(n);
         double *part = dev_alloc_n<double>(nb, s);
         if (d <= 4) {
             Mid4 mid{};
@@ -1454,8 +1535,12 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
                 ga.mid[j] = g.mid[j];
                 ga.fo[j] = g.fo[j];
             }
-            hipLaunchKernelGGL(k_gather, dim3(nb), dim3(kThreads), 0, s, points, g.perm, n, ga, g.xs, g.xa, g.nrm,
-                               g.pn, part);
+            if (lds_rows)
+                hipLaunchKernelGGL(k_gather_lds, dim3(nb), dim3(64), 0, s, points, g.perm, n, ga, g.xs, g.xa, g.nrm,
+                                   g.pn, part);
+            else
+                hipLaunchKernelGGL(k_gather, dim3(nb), dim3(kThreads), 0, s, points, g.perm, n, ga, g.xs, g.xa,
+                                   g.nrm, g.pn, part);
         }
         SJ_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kThreads), 0, s, part, (int64_t)nb, g.dev_nmax);
