@@ -737,12 +737,14 @@ __global__ void k_gather(const double *__restrict__ X, const int32_t *__restrict
 }
 
 // The same rows, norms and prefix norms as k_gather (the same FP64
-// operations in the same order, so the same bits) for 5 <= d <= 64, with
+// operations in the same order, so the same bits) for 16 <= d <= 64, with
 // every row read and written whole by one wave instruction: one wave per
 // block, 32 rows per block staged in LDS. Lane t handles column t of a row
 // (raw value, then the centred value of input dimension fo[t]); the norm
 // chain runs per row in one lane over the staged columns in order, and the
-// prefix norms leave through LDS as whole rows too.
+// prefix norms leave through LDS as whole rows too. With fewer dimensions a
+// row per lane (k_gather) needs far fewer memory instructions for the same
+// bytes.
 constexpr int kGatherRows = 32;
 constexpr int kGatherLdsD = 64;
 
@@ -1515,7 +1517,7 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
                     {acc, 3 * sizeof(unsigned long long)}},
                    s);
     if (n > 0) {
-        const bool lds_rows = d > 4 && d <= kGatherLdsD;
+        const bool lds_rows = d >= 16 && d <= kGatherLdsD;
         const unsigned nb = d <= 4 ? std::min(blocks_for(4 * n), 4096u)
                             : lds_rows ? (unsigned)((n + kGatherRows - 1) / kGatherRows)
                                        : blocks_for(n);
