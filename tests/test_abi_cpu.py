@@ -138,3 +138,13 @@ def test_peak_probe_rejects_invalid_arguments(lib):
     assert lib.selfjoin_probe_peaks(-1, ctypes.byref(out), None) == _lib.SJ_ERR_INVALID
     assert lib.selfjoin_probe_peaks(8, ctypes.byref(out), None) == _lib.SJ_ERR_INVALID
     assert lib.selfjoin_last_error()
+
+
+@pytest.mark.parametrize("field,value", [("short_circuit", -2), ("short_circuit", 65), ("dim_order", 2),
+                                         ("dim_order", -1), ("symmetric", 2), ("symmetric", -1)])
+def test_build_rejects_out_of_range_options(lib, field, value):
+    opts = _lib.sj_opts()
+    setattr(opts, field, value)
+    h = ctypes.c_void_p()
+    assert lib.selfjoin_build_grid(FAKE, 10, 2, 0.1, ctypes.byref(opts), None, ctypes.byref(h)) == _lib.SJ_ERR_INVALID
+    assert field in lib.selfjoin_last_error().decode()
