@@ -28,7 +28,7 @@ NSAMPLE = 48
 GOLD_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize.json")
 GOLD = json.load(open(GOLD_PATH)) if os.path.exists(GOLD_PATH) else {}
 
-ALL_PATHS = ["fp64_mfma", "fp64_valu", "fp32_mfma", "bf16_mfma", "bf16x3_mfma"]
+ALL_PATHS = ["fp64_mfma", "fp64_valu", "fp32_mfma", "bf16_mfma", "bf16x3_mfma", "fp8_mfma"]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -140,7 +140,7 @@ def test_prec_full_size(name, path):
         f"path_run={st['path_run']}")
 
 
-@pytest.mark.parametrize("path", ["fp32_mfma", "bf16_mfma", "bf16x3_mfma", "fp64_mfma"])
+@pytest.mark.parametrize("path", ["fp32_mfma", "bf16_mfma", "bf16x3_mfma", "fp8_mfma", "fp64_mfma"])
 @pytest.mark.parametrize("name", configs.PREC)
 def test_prec_band_holds_full_size(name, path):
     """The error band of the tile path covers every candidate pair's
