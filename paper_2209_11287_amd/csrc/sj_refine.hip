@@ -1913,8 +1913,9 @@ namespace {
 
 // Candidate pairs a half-stencil count evaluates: per item, its ranges cut
 // at its first query, times its queries (grid-stride over item x range; one
-// atomic per wave).
+// atomic per block: same-address atomics serialise).
 __global__ __launch_bounds__(kThreads) void k_sym_cand(DevGrid G, unsigned long long *out) {
+    __shared__ unsigned long long part[kWaves];
     unsigned long long acc = 0;
     const int64_t total = (int64_t)G.nitems * G.nranges;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
@@ -1926,7 +1927,13 @@ __global__ __launch_bounds__(kThreads) void k_sym_cand(DevGrid G, unsigned long 
         if (r.end > b) acc += (unsigned long long)(I.qend - I.qbegin) * (unsigned long long)(r.end - b);
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long sum = 0;
+        for (int w = 0; w < kWaves; ++w) sum += part[w];
+        if (sum) atomicAdd(out, sum);
+    }
 }
 
 }  // namespace
