@@ -8,8 +8,8 @@ grid index, count R, and write the full pair list to device memory. Inputs
 are resident in HBM before the timed region. The six independent joins are
 taken by --streams host threads from a shared queue (longest first), one HIP
 stream each (default 3), so one set's small build kernels overlap another's
-refine kernels; the per-launch kernel times of the roofline then include that
-sharing.
+refine kernels. The roofline comes from a single-stream pass after the timed
+steps (the launches' own times); the shared-GPU launch times sit beside it.
 
 metric: distance evaluations per second = C_ref / step time, where C_ref is
 the number of ordered candidate pairs of the full 3^k stencil of the
@@ -17,7 +17,7 @@ reference grid (an implementation-independent work unit), plus the
 self-join time. The FP64 MFMA path is the headline; the FP64 vector-ALU path
 runs beside it on the same data (--compare).
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--path fp64_mfma]
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--path fp64_mfma]
 """
 from __future__ import annotations
 
@@ -56,8 +56,8 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--path", default="fp64_mfma")
     ap.add_argument("--compare", default="fp64_valu", help="second path timed on the same data ('none' = none)")
     ap.add_argument("--workload", default="cfg2", choices=["cfg2", "small", "prec", "skewed", "batched", "brute"])
