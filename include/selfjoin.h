@@ -211,7 +211,8 @@ typedef struct {
  *  points : device, n x d row-major FP64, read during the call's stream work;
  *           the library copies what it needs (sorted), so the caller may
  *           release `points` once the stream has passed this call.
- *  n      : 0 <= n < 2^31 (n = 0 gives an empty index).
+ *  n      : 0 <= n <= 2,000,000,000 (n = 0 gives an empty index; the bound
+ *           keeps work-item and row indices below 2^31).
  *  d      : 1 <= d <= 256.
  *  eps    : finite, > 0.
  *  opts   : host, nullable.

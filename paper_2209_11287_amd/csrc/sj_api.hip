@@ -493,7 +493,7 @@ sj_status selfjoin_build_grid(const double *points, int64_t n, int32_t d, double
                               void *stream, sj_grid **out) {
     set_error("");
     if (!out) return invalid("out is NULL");
-    if (n < 0 || n >= (int64_t(1) << 31)) return invalid("n must be in [0, 2^31)");
+    if (n < 0 || n > kMaxPoints) return invalid("n must be in [0, 2,000,000,000]");
     if (d < 1 || d > kMaxDims) return invalid("d must be in [1, 256]");
     if (!(eps > 0.0) || !std::isfinite(eps)) return invalid("eps must be finite and > 0");
     if (n > 0 && !points) return invalid("points is NULL");
@@ -725,7 +725,7 @@ void selfjoin_free_grid(sj_grid *gh, void *stream) {
 sj_status selfjoin_count_noalloc(const double *points, int64_t n, int32_t d, double eps, sj_path path,
                                  int32_t *per_point, int64_t *total, void *stream) {
     set_error("");
-    if (n < 0 || n >= (int64_t(1) << 31)) return invalid("n must be in [0, 2^31)");
+    if (n < 0 || n > kMaxPoints) return invalid("n must be in [0, 2,000,000,000]");
     if (d < 1 || d > kMaxDims) return invalid("d must be in [1, 256]");
     if (!(eps > 0.0) || !std::isfinite(eps)) return invalid("eps must be finite and > 0");
     if (n > 0 && !points) return invalid("points is NULL");

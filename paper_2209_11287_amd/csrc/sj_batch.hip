@@ -582,7 +582,7 @@ sj_status selfjoin_batch_build(int32_t B, const double *const *points, const int
         return SJ_ERR_INVALID;
     }
     for (int i = 0; i < B; ++i) {
-        if (n[i] < 0 || n[i] >= (int64_t(1) << 31) || d[i] < 1 || d[i] > kMaxDims || !(eps[i] > 0.0) ||
+        if (n[i] < 0 || n[i] > kMaxPoints || d[i] < 1 || d[i] > kMaxDims || !(eps[i] > 0.0) ||
             !std::isfinite(eps[i]) || (n[i] > 0 && !points[i])) {
             set_error("invalid arguments for batch problem " + std::to_string(i));
             return SJ_ERR_INVALID;

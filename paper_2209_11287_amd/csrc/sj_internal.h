@@ -14,6 +14,9 @@ namespace sj {
 
 constexpr int kMaxIndexDims = 4;   // default k = min(d, kMaxIndexDims)
 constexpr int kMaxDims = 256;
+// Largest n of one grid: the work items (up to n + n / 16 + 1) and the rows
+// with their padding stay below 2^31 (int32 indices on the device).
+constexpr int64_t kMaxPoints = 2000000000;
 constexpr int kTileQ = 16;         // queries per work item (one wave)
 constexpr int kRowPad = 64;        // extra zeroed rows after every point array
 constexpr int kBlockItems = 4;     // work items per block item (low-precision paths)

@@ -59,7 +59,7 @@ def _build(lib, ptr, n, d, eps, index_dims=0, out=True):
 FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
 
 
-@pytest.mark.parametrize("n,d,eps", [(-1, 2, 0.1), (1 << 31, 2, 0.1), (10, 0, 0.1), (10, 257, 0.1),
+@pytest.mark.parametrize("n,d,eps", [(-1, 2, 0.1), (1 << 31, 2, 0.1), (2_000_000_001, 2, 0.1), (10, 0, 0.1), (10, 257, 0.1),
                                      (10, 2, 0.0), (10, 2, -1.0), (10, 2, math.nan), (10, 2, math.inf)])
 def test_build_rejects_invalid_arguments(lib, n, d, eps):
     assert _build(lib, FAKE, n, d, eps) == _lib.SJ_ERR_INVALID
