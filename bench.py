@@ -471,11 +471,11 @@ def batched_roofline(B, avg, last):
                              "avg_launch_ms": avg["pairs_ms"]}}
 
 
-def batched_summary(paths, steps, warmup):
+def batched_summary(paths, steps, warmup, B=None):
     """The batched workload on each of `paths`: per-step time, phases and
     the count graph's roofline."""
     import tempfile
-    B = batched_setup()
+    B = B or batched_setup()
     cache = os.path.join(tempfile.mkdtemp(), "tune.txt")
     out = {"workload": WORKLOAD_TEXT["batched"], "cand_ref_per_step": B["cref"], "steps": steps, "warmup": warmup,
            "paths": {}}
@@ -545,15 +545,42 @@ def batched_cpu_baseline(ws, host, crefs, budget_evals=1.5e9):
                       f"pairs in all; d in {ds})", "seconds": round(secs, 2)}
 
 
-def symmetric_counts(reps=3):
+def symmetric_counts(reps=3, B=None):
     """Count-only use (per-point counts, as DBSCAN's core test needs): the
     count kernel with the full stencil and with the half stencil
     (sj_opts.symmetric) on the same grids, FP64 MFMA and FP64 vector paths,
     the six 2M-point sets and the precision set; best of `reps` kernel times
-    (HIP events around the launch); the totals must agree."""
+    (HIP events around the launch); the totals must agree. With the batched
+    workload's problems (B, from batched_setup), its count graph the same
+    way (tuned builds, the device time of the graph launch)."""
+    import tempfile
+
     import torch
-    from paper_2209_11287_amd import selfjoin_build_grid, selfjoin_count, selfjoin_free_grid
+    from paper_2209_11287_amd import (selfjoin_batch_build, selfjoin_batch_count, selfjoin_batch_free,
+                                      selfjoin_build_grid, selfjoin_count, selfjoin_free_grid)
     out = {}
+    if B is not None:
+        log("[bench] symmetric count batched")
+        cache = os.path.join(tempfile.mkdtemp(), "tune.txt")
+        res = {}
+        for pth in ("fp64_mfma", "fp64_valu"):
+            r = {}
+            for sym in (0, 1):
+                b = selfjoin_batch_build(B["pts"], B["eps"], tune=True, tune_cache=cache, symmetric=sym)
+                best, tot, ev = None, None, None
+                for _ in range(reps + 1):
+                    t, st = selfjoin_batch_count(b, pth)
+                    best = st["ms"] if best is None else min(best, st["ms"])
+                    tot, ev = t, st["cand_eval"]
+                selfjoin_batch_free(b)
+                r[sym] = (best, tot, ev)
+            if r[0][1] != r[1][1]:
+                raise RuntimeError(f"symmetric batched count differs on {pth}")
+            res[pth] = {"count_graph_ms": round(r[0][0], 3), "symmetric_ms": round(r[1][0], 3),
+                        "speedup": round(r[0][0] / max(r[1][0], 1e-9), 3), "cand_eval": r[0][2],
+                        "symmetric_cand_eval": r[1][2]}
+        out["batched"] = res
+        torch.cuda.empty_cache()
     for wname in ("cfg2", "prec"):
         log(f"[bench] symmetric count {wname}")
         rows = []
@@ -624,8 +651,10 @@ def other_workloads(steps=2, warmup=1):
         del inputs
         torch.cuda.empty_cache()
     log("[bench] other workload batched")
-    out["batched"] = batched_summary(["fp64_mfma", "fp64_valu"], steps, warmup)
-    out["symmetric_count"] = symmetric_counts()
+    B = batched_setup()
+    out["batched"] = batched_summary(["fp64_mfma", "fp64_valu"], steps, warmup, B)
+    out["symmetric_count"] = symmetric_counts(B=B)
+    del B
     return out
 
 

@@ -153,8 +153,11 @@ typedef struct {
                                (selfjoin_count, selfjoin_core_points): the
                                count then records no in-masks, so a following
                                selfjoin_pairs / selfjoin_knn evaluates its
-                               tiles again (full stencil). The low-precision
-                               paths and the batched form ignore it. */
+                               tiles again (full stencil). The batched form
+                               (selfjoin_batch_build) takes it for every
+                               problem: no in-mask buffer, and
+                               selfjoin_batch_pairs re-runs the tiles. The
+                               low-precision paths ignore it. */
     int32_t reserved32;
     int64_t reserved[2];
 } sj_opts;
@@ -351,8 +354,9 @@ typedef struct sj_batch sj_batch;
 /* points : host array of B device pointers, problem i is n[i] x d[i]
  *          row-major FP64 (validated like selfjoin_build_grid).
  * n, d, eps : host arrays of B entries. opts: index_dims / short_circuit /
- *          dim_order (every problem) or tune / tune_cache; the allocator hook
- *          is not used by the batched form.
+ *          dim_order (every problem) or tune / tune_cache; symmetric (the
+ *          half-stencil count for every problem, with no in-mask buffer);
+ *          the allocator hook is not used by the batched form.
  * out    : host; receives the handle (release with selfjoin_batch_free). */
 sj_status selfjoin_batch_build(int32_t B, const double *const *points, const int64_t *n,
                                const int32_t *d, const double *eps, const sj_opts *opts,

@@ -166,6 +166,9 @@ struct Batch {
     std::vector<void *> owned;
     bool masks_valid = false;
     bool counted = false;
+    bool sym = false;                     // half-stencil count (sj_opts.symmetric): no in-masks
+    int64_t max_n = 0;                    // largest problem
+    int64_t sym_cand = -1;                // candidate pairs the half-stencil count evaluates (on first use)
     double ms_build = 0;                  // wall time of the grid builds and the queue
     // graphs per path: the count pipeline, and the pairs launch (per output buffer)
     hipGraphExec_t exec[2] = {nullptr, nullptr};
@@ -218,6 +221,7 @@ void batch_build(Batch &b, int B, const double *const *points, const int64_t *n,
                  const sj_opts *opts, hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
     b.B = B;
+    b.sym = opts && opts->symmetric;
     b.grids.assign(B, nullptr);
     b.kdims.assign(B, 0);
     b.scs.assign(B, 0);
@@ -278,6 +282,7 @@ void batch_build(Batch &b, int B, const double *const *points, const int64_t *n,
         g.cnt = dev_alloc_n<int32_t>((size_t)g.n + 1, s);
         g.off = dev_alloc_n<int64_t>((size_t)g.n + 1, s);
         b.item_base[i + 1] = b.item_base[i] + g.items;
+        b.max_n = std::max(b.max_n, g.n);
         tile_base[i] = b.segmented ? 0 : mask_tiles;
         mask_tiles += g.tiles;
     }
@@ -362,8 +367,9 @@ void batch_build(Batch &b, int B, const double *const *points, const int64_t *n,
         pos += kv.second;
     }
     // in-masks of every problem (32 bytes per tile slot): the pairs pass then
-    // expands them instead of re-running the tiles
-    if (mask_tiles > 0 && mask_tiles * 32 <= kBatchMaskBudget) {
+    // expands them instead of re-running the tiles (a half-stencil count
+    // records none)
+    if (!b.sym && mask_tiles > 0 && mask_tiles * 32 <= kBatchMaskBudget) {
         try {
             b.masks = dev_alloc_n<unsigned long long>((size_t)mask_tiles * 4, s);
         } catch (const OomError &) {
@@ -424,9 +430,10 @@ void set_sched(Batch &b, int sched) {
     b.sched = sched;
 }
 
-// Count pipeline: counter reset, one kernel per tile form (recording the
-// in-masks when the batch holds them), per-problem prefix sums; captured on
-// first use per (path, stream, schedule) and replayed.
+// Count pipeline: counter reset (and, for the half stencil, the per-point
+// counts), one kernel per tile form (recording the in-masks when the batch
+// holds them), per-problem prefix sums; captured on first use per (path,
+// stream, schedule) and replayed.
 float batch_count_graph(Batch &b, sj_path path, hipStream_t s) {
     const int pi = path == SJ_FP64_MFMA ? 1 : 0;
     if (!b.exec[pi] || b.graph_stream[pi] != s || b.graph_sched[pi] != b.sched) {
@@ -434,8 +441,9 @@ float batch_count_graph(Batch &b, sj_path path, hipStream_t s) {
         b.exec[pi] = nullptr;
         b.exec[pi] = capture(s, [&](hipStream_t cs) {
             batch_reset(b.ctr, cs);
+            if (b.sym) launch_batch_zero_counts(b.probs_dev, b.B, b.max_n, cs);
             for (const BatchForm &f : b.forms)
-                launch_batch_form(false, f, path, b.probs_dev, b.item_base_dev, b.B, b.queue, nullptr, b.ctr, cs,
+                launch_batch_form(false, b.sym, f, path, b.probs_dev, b.item_base_dev, b.B, b.queue, nullptr, b.ctr, cs,
                                   b.block_base_dev, b.bqueue);
             launch_seg_scan(b.probs_dev, b.B, b.totals_dev, cs);
         });
@@ -462,7 +470,7 @@ float batch_count(Batch &b, sj_path path, hipStream_t s, HostCounters *hc) {
         // once after a warm run, the faster kept (and cached by batch shape)
         b.tune_sched = false;
         std::lock_guard<std::mutex> lk(g_tune.mu);
-        const std::string key = b.sched_key + "/" + std::to_string((int)path);
+        const std::string key = b.sched_key + "/" + std::to_string((int)path) + (b.sym ? "/sym" : "");
         auto it = g_tune.v.find(key);
         if (it != g_tune.v.end()) {
             set_sched(b, it->second);
@@ -494,7 +502,7 @@ float batch_count(Batch &b, sj_path path, hipStream_t s, HostCounters *hc) {
         b.grids[i]->have_counts = true;
     }
     b.counted = true;
-    b.masks_valid = b.masks != nullptr;
+    b.masks_valid = b.masks != nullptr && !b.sym;
     return ms;
 }
 
@@ -519,7 +527,7 @@ float batch_pairs(Batch &b, sj_path path, int32_t *pairs, hipStream_t s) {
                 launch_batch_emit(b.probs_dev, b.item_base_dev, b.B, b.queue, (int)b.total_items, 1, pairs, cs);
             } else {
                 for (const BatchForm &f : b.forms)
-                    launch_batch_form(true, f, path, b.probs_dev, b.item_base_dev, b.B, b.queue, pairs, b.ctr, cs);
+                    launch_batch_form(true, false, f, path, b.probs_dev, b.item_base_dev, b.B, b.queue, pairs, b.ctr, cs);
             }
         });
         b.pgraph_stream[pi] = s;
@@ -596,6 +604,10 @@ sj_status selfjoin_batch_build(int32_t B, const double *const *points, const int
         set_error("short_circuit must be in [-1, 64] and dim_order 0 or 1");
         return SJ_ERR_INVALID;
     }
+    if (opts && (opts->symmetric < 0 || opts->symmetric > 1)) {
+        set_error("symmetric must be 0 or 1");
+        return SJ_ERR_INVALID;
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     sj_batch *h = new sj_batch();
     SJB_TRY
@@ -631,6 +643,24 @@ sj_status selfjoin_batch_count(sj_batch *bh, sj_path path, int64_t *totals, sj_s
         totals[i] = b.totals[i];
         sum += b.totals[i];
         cev += b.grids[i]->cand_items;
+    }
+    if (stats && b.sym) {
+        if (b.sym_cand < 0) {  // ranges cut at each item's first query (once per batch)
+            unsigned long long *acc = dev_alloc_n<unsigned long long>(1, s);
+            unsigned long long h = 0;
+            try {
+                fill_zero(acc, sizeof h, s);
+                for (const Grid *g : b.grids) launch_sym_cand(*g, acc, s);
+                SJ_HIP(hipMemcpyAsync(&h, acc, sizeof h, hipMemcpyDeviceToHost, s));
+                SJ_HIP(hipStreamSynchronize(s));
+            } catch (...) {
+                dev_free(acc, s);
+                throw;
+            }
+            dev_free(acc, s);
+            b.sym_cand = (int64_t)h;
+        }
+        cev = b.sym_cand;
     }
     if (stats) {
         std::memset(stats, 0, sizeof *stats);

@@ -343,9 +343,14 @@ void refine_measure(Grid &g, sj_path path, double *max_err, double *max_band, in
 
 // Batched form (sj_refine.hip).
 void batch_reset(DevCounters *ctr, hipStream_t s);
-void launch_batch_form(bool emit, const BatchForm &f, sj_path path, const BProb *probs, const int64_t *item_base,
-                       int B, const int32_t *queue, int32_t *pairs, DevCounters *ctr, hipStream_t s,
-                       const int64_t *block_base = nullptr, const int32_t *bqueue = nullptr);
+// sym: the count with the half stencil (FP64 paths; counts added into
+// per-point arrays zeroed by launch_batch_zero_counts, no in-masks).
+void launch_batch_form(bool emit, bool sym, const BatchForm &f, sj_path path, const BProb *probs,
+                       const int64_t *item_base, int B, const int32_t *queue, int32_t *pairs, DevCounters *ctr,
+                       hipStream_t s, const int64_t *block_base = nullptr, const int32_t *bqueue = nullptr);
+void launch_batch_zero_counts(const BProb *probs, int B, int64_t max_n, hipStream_t s);
+// Adds to *acc the candidate pairs a half-stencil count of g evaluates.
+void launch_sym_cand(const Grid &g, unsigned long long *acc, hipStream_t s);
 void launch_batch_emit(const BProb *probs, const int64_t *item_base, int B, const int32_t *queue, int total,
                        int sched, int32_t *pairs, hipStream_t s);
 void launch_seg_scan(const BProb *probs, int B, int64_t *totals, hipStream_t s);

@@ -1578,7 +1578,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_v64(const BProb *__restrict_
 // FP64 MFMA count of the block items of many problems (d = 5 .. 16, united
 // candidate lists): as k_m64s, one block item per block at a time, the block
 // queue's positions [lo, hi) taken round-robin by the grid's blocks.
-template <int KS, bool SLOT>
+template <int KS, bool SLOT, bool SYM>
 __global__ __launch_bounds__(kThreads) void k_batch_m64s(const BProb *__restrict__ probs,
                                                          const int64_t *__restrict__ block_base, int B,
                                                          const int32_t *__restrict__ bqueue, int lo, int hi,
@@ -1588,8 +1588,20 @@ __global__ __launch_bounds__(kThreads) void k_batch_m64s(const BProb *__restrict
         const int gb = bqueue[w];
         const int p = batch_problem(block_base, B, gb);
         const BProb &P = probs[p];
-        const RefOut R = batch_out(P, nullptr, ctr, MODE_COUNT);
-        m64_block_count<KS, SLOT, false>(P.G, R, P.delta, uniform_i32(gb - (int)block_base[p]), lds);
+        const RefOut R = batch_out(P, nullptr, ctr, SYM ? MODE_SYM : MODE_COUNT);
+        m64_block_count<KS, SLOT, SYM>(P.G, R, P.delta, uniform_i32(gb - (int)block_base[p]), lds);
+    }
+}
+
+// Every problem's per-point counts set to zero before a half-stencil count
+// adds into them (a kernel, so that the count graph holds no memset node):
+// problems blockIdx.y, blockIdx.y + gridDim.y, ..., each swept along x.
+__global__ __launch_bounds__(kThreads) void k_batch_zero_cnt(const BProb *__restrict__ probs, int B) {
+    for (int p = (int)blockIdx.y; p < B; p += (int)gridDim.y) {
+        int32_t *const c = probs[p].cnt;
+        const int64_t n = probs[p].G.n;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+            c[i] = 0;
     }
 }
 
@@ -1859,15 +1871,18 @@ static void batch_form_mode(const BatchForm &f, sj_path path, const BProb *probs
     }
 }
 
-void launch_batch_form(bool emit, const BatchForm &f, sj_path path, const BProb *probs, const int64_t *item_base,
-                       int B, const int32_t *queue, int32_t *pairs, DevCounters *ctr, hipStream_t s,
-                       const int64_t *block_base, const int32_t *bqueue) {
+void launch_batch_form(bool emit, bool sym, const BatchForm &f, sj_path path, const BProb *probs,
+                       const int64_t *item_base, int B, const int32_t *queue, int32_t *pairs, DevCounters *ctr,
+                       hipStream_t s, const int64_t *block_base, const int32_t *bqueue) {
     if (!emit && path == SJ_FP64_MFMA && bqueue && f.bhi > f.blo) {
         const bool slot = (f.d & 3) != 0;
         const int ks = (slot ? ((f.d + 1 + 3) & ~3) : f.d) >> 2;
         const int nb = f.bhi - f.blo;
-#define SJ_BS(KSV, SL) \
-    batch_launch(k_batch_m64s<KSV, SL>, 4 * nb, f.sched, s, probs, block_base, B, bqueue, f.blo, f.bhi, ctr)
+#define SJ_BS(KSV, SL)                                                                                           \
+    sym ? batch_launch(k_batch_m64s<KSV, SL, true>, 4 * nb, f.sched, s, probs, block_base, B, bqueue, f.blo, f.bhi, \
+                       ctr)                                                                                      \
+        : batch_launch(k_batch_m64s<KSV, SL, false>, 4 * nb, f.sched, s, probs, block_base, B, bqueue, f.blo,    \
+                       f.bhi, ctr)
         if (slot) {
             if (ks == 2) SJ_BS(2, true);
             else if (ks == 3) SJ_BS(3, true);
@@ -1881,7 +1896,16 @@ void launch_batch_form(bool emit, const BatchForm &f, sj_path path, const BProb 
         return;
     }
     if (emit) batch_form_mode<MODE_EMIT>(f, path, probs, item_base, B, queue, pairs, ctr, s);
+    else if (sym) batch_form_mode<MODE_SYM>(f, path, probs, item_base, B, queue, pairs, ctr, s);
     else batch_form_mode<MODE_COUNT>(f, path, probs, item_base, B, queue, pairs, ctr, s);
+}
+
+void launch_batch_zero_counts(const BProb *probs, int B, int64_t max_n, hipStream_t s) {
+    if (B <= 0 || max_n <= 0) return;
+    const int64_t bx = std::min<int64_t>(1024, (max_n + 4 * kThreads - 1) / (4 * kThreads));
+    hipLaunchKernelGGL(k_batch_zero_cnt, dim3((unsigned)bx, (unsigned)std::min(B, 1024)), dim3(kThreads), 0, s, probs,
+                       B);
+    SJ_HIP(hipGetLastError());
 }
 
 void launch_batch_emit(const BProb *probs, const int64_t *item_base, int B, const int32_t *queue, int total,
@@ -1938,6 +1962,12 @@ __global__ __launch_bounds__(kThreads) void k_sym_cand(DevGrid G, unsigned long 
 
 }  // namespace
 
+void launch_sym_cand(const Grid &g, unsigned long long *acc, hipStream_t s) {
+    if (g.items <= 0) return;
+    hipLaunchKernelGGL(k_sym_cand, dim3(64), dim3(kThreads), 0, s, dev_grid(g), acc);
+    SJ_HIP(hipGetLastError());
+}
+
 // Enqueues the count kernel of `path` (already range-checked); its counters
 // land in ro.ctr (device, zeroed here), read back by the caller with the
 // total.
@@ -1950,10 +1980,7 @@ void refine_count(Grid &g, sj_path path, int32_t *cnt_sorted, RefineOut &ro, hip
     R.masks = ro.masks;
     const bool sym = ro.sym && (path == SJ_FP64_VALU || path == SJ_FP64_MFMA);
     ro.cand_eval = g.cand_items;
-    if (sym && g.items > 0) {
-        hipLaunchKernelGGL(k_sym_cand, dim3(64), dim3(kThreads), 0, s, dev_grid(g), &ro.ctr->spare[0]);
-        SJ_HIP(hipGetLastError());
-    }
+    if (sym) launch_sym_cand(g, &ro.ctr->spare[0], s);
     if (path == SJ_FP64_VALU) {
         ro.kt.start(ro.timed, s);
         if (sym) launch_v64<MODE_SYM>(g, R, (int)g.items, s);

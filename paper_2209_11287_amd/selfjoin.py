@@ -336,10 +336,13 @@ class BatchHandle:
 
 
 def selfjoin_batch_build(points_list, eps_list, index_dims: int = 0, tune: bool = False, tune_cache=None,
-                         stream=None, short_circuit: int = 0, dim_order: int = 0) -> BatchHandle:
+                         stream=None, short_circuit: int = 0, dim_order: int = 0,
+                         symmetric: int = 0) -> BatchHandle:
     """points_list: list of CUDA float64 (n_i, d_i) tensors; eps_list: floats.
     index_dims / short_circuit / dim_order: sj_opts fields (ignored for the
-    choices the tuner makes when tune is set)."""
+    choices the tuner makes when tune is set); symmetric: the half-stencil
+    count for every problem (no in-masks: the pairs launch re-runs the
+    tiles)."""
     torch = _torch()
     pts = [p.contiguous() for p in points_list]
     B = len(pts)
@@ -357,6 +360,7 @@ def selfjoin_batch_build(points_list, eps_list, index_dims: int = 0, tune: bool 
     opts.index_dims = index_dims
     opts.short_circuit = short_circuit
     opts.dim_order = dim_order
+    opts.symmetric = symmetric
     opts.tune = 1 if tune else 0
     opts.tune_cache = tune_cache.encode() if tune_cache else None
     out = ctypes.c_void_p()

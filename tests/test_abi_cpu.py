@@ -124,6 +124,13 @@ def test_batch_calls_reject_invalid_arguments(lib):
     es[0] = float("nan")
     assert lib.selfjoin_batch_build(2, ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p)), ns, ds, es,
                                     ctypes.byref(opts), None, ctypes.byref(h)) == _lib.SJ_ERR_INVALID
+    # symmetric outside {0, 1} (every problem valid)
+    es[0] = 0.1
+    opts.symmetric = 2
+    assert lib.selfjoin_batch_build(2, ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p)), ns, ds, es,
+                                    ctypes.byref(opts), None, ctypes.byref(h)) == _lib.SJ_ERR_INVALID
+    assert b"symmetric" in lib.selfjoin_last_error()
+    opts.symmetric = 0
     tot = (ctypes.c_int64 * 1)()
     assert lib.selfjoin_batch_count(None, 1, tot, None, None) == _lib.SJ_ERR_INVALID
     offs = (ctypes.c_int64 * 2)()

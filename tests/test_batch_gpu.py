@@ -167,3 +167,74 @@ def test_batch_tuned_schedule_and_filters_match_oracle(tmp_path):
         for i in range(len(probs)):
             assert np.array_equal(pair_keys(out[offs[i]:offs[i + 1]]), pair_keys(want[i])), (kw, i)
         selfjoin_batch_free(b)
+
+
+@pytest.mark.parametrize("path", ["fp64_mfma", "fp64_valu"])
+def test_batch_symmetric_count_matches_oracle(path, tmp_path):
+    """The half-stencil count for every problem (sj_opts.symmetric), with the
+    library's schedule and with the tuned one: the oracle's totals, the same
+    on graph replays with eager work between them; fewer candidate pairs
+    evaluated than the full stencil's; and a later pairs launch (the tiles
+    re-run, as the count recorded no in-masks) writes the oracle's pair set
+    of each problem at the offsets the half-stencil counts gave."""
+    import torch
+
+    import oracle
+    from paper_2209_11287_amd import (selfjoin_batch_build, selfjoin_batch_count, selfjoin_batch_free,
+                                      selfjoin_batch_pairs)
+    probs = _problems(20, seed=17)
+    # tiny problems: one point, two points within eps, a handful of points
+    rng = np.random.default_rng(17)
+    probs += [(rng.random((1, 3)), 0.1), (np.array([[0.0, 0.0], [0.05, 0.0]]), 0.1), (rng.random((5, 8)), 0.7)]
+    pts = [torch.from_numpy(X).to("cuda:0") for X, _ in probs]
+    eps = [e for _, e in probs]
+    want = [oracle.grid_pairs(X, e)[2] for X, e in probs]
+    full = selfjoin_batch_build(pts, eps)
+    _, st_full = selfjoin_batch_count(full, path)
+    selfjoin_batch_free(full)
+    for kw in ({}, {"tune": True, "tune_cache": str(tmp_path / "t.txt")}):
+        log(f"[batch] symmetric path={path} options {kw}")
+        b = selfjoin_batch_build(pts, eps, symmetric=1, **kw)
+        totals, st = selfjoin_batch_count(b, path)
+        assert totals == [len(w) for w in want], kw
+        assert 0 < st["cand_eval"] < st_full["cand_eval"], kw
+        for rep in range(3):
+            junk = torch.randn(1 << 20, device="cuda:0").sum().item()
+            del junk
+            torch.cuda.synchronize()
+            again, _ = selfjoin_batch_count(b, path)
+            assert again == totals, (kw, rep)
+        buf = torch.empty((max(1, sum(totals)), 2), dtype=torch.int32, device="cuda:0")
+        offs, _ = selfjoin_batch_pairs(b, path, buf)
+        out = buf.cpu().numpy()
+        for i in range(len(probs)):
+            assert np.array_equal(pair_keys(out[offs[i]:offs[i + 1]]), pair_keys(want[i])), (kw, i)
+        selfjoin_batch_free(b)
+
+
+@pytest.mark.parametrize("symmetric", [0, 1])
+@pytest.mark.parametrize("path", ["fp64_mfma", "fp64_valu"])
+def test_batch_with_empty_problems(path, symmetric):
+    """Problems with no points among non-empty ones (d = 2, 3, 8, 16): zero
+    totals and empty output rows for them, the oracle's pair sets for the
+    others."""
+    import torch
+
+    import oracle
+    from paper_2209_11287_amd import (selfjoin_batch_build, selfjoin_batch_count, selfjoin_batch_free,
+                                      selfjoin_batch_pairs)
+    rng = np.random.default_rng(1)
+    probs = [(np.zeros((0, 3)), 0.1), (rng.random((200, 3)), 0.1), (np.zeros((0, 16)), 0.5),
+             (rng.random((300, 8)), 0.4), (np.zeros((0, 2)), 0.1)]
+    pts = [torch.from_numpy(X).to("cuda:0") for X, _ in probs]
+    want = [oracle.grid_pairs(X, e)[2] for X, e in probs]
+    b = selfjoin_batch_build(pts, [e for _, e in probs], symmetric=symmetric)
+    totals, _ = selfjoin_batch_count(b, path)
+    assert totals == [len(w) for w in want]
+    assert totals[0] == totals[2] == totals[4] == 0
+    buf = torch.empty((max(1, sum(totals)), 2), dtype=torch.int32, device="cuda:0")
+    offs, _ = selfjoin_batch_pairs(b, path, buf)
+    out = buf.cpu().numpy()
+    for i in range(len(probs)):
+        assert np.array_equal(pair_keys(out[offs[i]:offs[i + 1]]), pair_keys(want[i])), i
+    selfjoin_batch_free(b)
