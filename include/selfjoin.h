@@ -365,7 +365,9 @@ sj_status selfjoin_batch_build(int32_t B, const double *const *points, const int
 /* totals : host int64[B], |R| of each problem. stats (nullable): ms =
  * ms_refine = device time of the count graph; ms_build = wall time of
  * selfjoin_batch_build (grid builds, queue, in-mask buffer); cand_eval,
- * rechecked, tiles_pruned over all problems; cand_ref = -1. */
+ * rechecked, tiles_pruned over all problems (cand_eval of a half-stencil
+ * batch: counted by one extra pass over the ranges on the first call that
+ * asks for stats); cand_ref = -1. */
 sj_status selfjoin_batch_count(sj_batch *b, sj_path path, int64_t *totals, sj_stats *stats,
                                void *stream);
 
