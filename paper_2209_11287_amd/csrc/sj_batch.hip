@@ -25,15 +25,17 @@ namespace {
 // tile form together), then descending cost (candidate tiles x K-steps);
 // value = global item index.
 __global__ void k_item_cost(const Item *__restrict__ items, const Range *__restrict__ ranges, int nitems,
-                            int nranges, int ksteps, int d, int64_t base, unsigned long long *__restrict__ key,
+                            int nranges, int ksteps, int d, bool sym, int64_t base, unsigned long long *__restrict__ key,
                             int32_t *__restrict__ val) {
     const int it = blockIdx.x * blockDim.x + threadIdx.x;
     if (it >= nitems) return;
-    (void)items;
+    // half stencil: the ranges as the count cuts them (from the first query on)
+    const int32_t cut = sym ? items[it].qbegin : INT32_MIN;
     unsigned long long c = 0;
     for (int o = 0; o < nranges; ++o) {
         const Range r = ranges[(int64_t)it * nranges + o];
-        c += (unsigned long long)((r.end - r.begin + 15) / 16);
+        const int32_t b = max(r.begin, cut);
+        c += (unsigned long long)(r.end > b ? (r.end - b + 15) / 16 : 0);
     }
     c *= (unsigned long long)(ksteps > 0 ? ksteps : 1);
     const unsigned long long cap = 0xffffffffull;
@@ -43,17 +45,20 @@ __global__ void k_item_cost(const Item *__restrict__ items, const Range *__restr
 
 // Sort key of each block item of a problem counted with LDS-shared tiles
 // (FP64 MFMA, d = 5 .. 16): d in the high bits, then descending cost (its
-// list's tiles x K-steps x items); value = global block index.
-__global__ void k_block_cost(const int32_t *__restrict__ blocks, int item_base, const Range *__restrict__ ranges,
-                             int nranges, int nb, int ksteps, int d, int64_t base, unsigned long long *__restrict__ key,
-                             int32_t *__restrict__ val) {
+// list's tiles x K-steps x items; half stencil: the list cut at the block's
+// first query); value = global block index.
+__global__ void k_block_cost(const int32_t *__restrict__ blocks, int item_base, const Item *__restrict__ items,
+                             const Range *__restrict__ ranges, int nranges, int nb, int ksteps, int d, bool sym,
+                             int64_t base, unsigned long long *__restrict__ key, int32_t *__restrict__ val) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nb) return;
     const int it0 = blocks[b] - item_base, ni = blocks[b + 1] - blocks[b];
+    const int32_t cut = sym ? items[it0].qbegin : INT32_MIN;
     unsigned long long c = 0;
     for (int o = 0; o < nranges; ++o) {
         const Range r = ranges[(int64_t)it0 * nranges + o];
-        c += (unsigned long long)(r.end > r.begin ? r.end - r.begin : 0);
+        const int32_t rb = max(r.begin, cut);
+        c += (unsigned long long)(r.end > rb ? r.end - rb : 0);
     }
     c = (c + 15) / 16 * (unsigned long long)ksteps * (unsigned long long)ni;
     const unsigned long long cap = 0xffffffffull;
@@ -303,7 +308,7 @@ void batch_build(Batch &b, int B, const double *const *points, const int64_t *n,
         if (g.items == 0) continue;
         per_d[g.d] += g.items;
         hipLaunchKernelGGL(k_item_cost, dim3((unsigned)((g.items + 255) / 256)), dim3(256), 0, s, g.item, g.ranges,
-                           (int)g.items, g.nranges, g.da >> 2, g.d, b.item_base[i], ka, va);
+                           (int)g.items, g.nranges, g.da >> 2, g.d, b.sym, b.item_base[i], ka, va);
         SJ_HIP(hipGetLastError());
     }
     int dbits = 0;
@@ -338,7 +343,8 @@ void batch_build(Batch &b, int B, const double *const *points, const int64_t *n,
             const Grid &g = *b.grids[i];
             if (bbase[i + 1] == bbase[i]) continue;
             hipLaunchKernelGGL(k_block_cost, dim3((unsigned)((g.nblocks + 255) / 256)), dim3(256), 0, s, g.blocks,
-                               g.item_base, g.ranges, g.nranges, (int)g.nblocks, g.da >> 2, g.d, bbase[i], bka, bva);
+                               g.item_base, g.item, g.ranges, g.nranges, (int)g.nblocks, g.da >> 2, g.d, b.sym,
+                               bbase[i], bka, bva);
             SJ_HIP(hipGetLastError());
         }
         unsigned long long *bks = bka;
