@@ -998,8 +998,13 @@ __device__ __forceinline__ void m64_block_count(const DevGrid &G, const RefOut &
     }
 }
 
+// Five waves per SIMD (at most 96 VGPRs; the full-stencil forms do not
+// spill) took the d = 16 count of a 1M-point Gaussian mixture from 9.5 to
+// 8.8 ms against four, and the batched d = 8, 16 counts (k_batch_m64s) 7 %
+// lower; six spill, and ran no faster in the batched form.
 template <int KS, bool SLOT, bool SYM>
-__global__ __launch_bounds__(kThreads) void k_m64s(DevGrid G, RefOut R, double delta, int nblocks) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_m64s(DevGrid G, RefOut R,
+                                                                                             double delta, int nblocks) {
     __shared__ double lds[m64s_lds_doubles(KS)];
     const int bi = xcd_block(blockIdx.x, gridDim.x);
     if (bi >= nblocks) return;  // whole block
@@ -1579,10 +1584,9 @@ __global__ __launch_bounds__(kThreads) void k_batch_v64(const BProb *__restrict_
 // candidate lists): as k_m64s, one block item per block at a time, the block
 // queue's positions [lo, hi) taken round-robin by the grid's blocks.
 template <int KS, bool SLOT, bool SYM>
-__global__ __launch_bounds__(kThreads) void k_batch_m64s(const BProb *__restrict__ probs,
-                                                         const int64_t *__restrict__ block_base, int B,
-                                                         const int32_t *__restrict__ bqueue, int lo, int hi,
-                                                         DevCounters *__restrict__ ctr) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_batch_m64s(
+    const BProb *__restrict__ probs, const int64_t *__restrict__ block_base, int B, const int32_t *__restrict__ bqueue,
+    int lo, int hi, DevCounters *__restrict__ ctr) {
     __shared__ double lds[m64s_lds_doubles(KS)];
     for (int w = lo + (int)blockIdx.x; w < hi; w += (int)gridDim.x) {  // block-uniform
         const int gb = bqueue[w];
