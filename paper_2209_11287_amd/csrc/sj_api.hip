@@ -21,6 +21,10 @@ thread_local std::string g_err;
 
 __global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
 
+// The count's total (the last entry of the offsets' exclusive scan) beside
+// its counters, so that one copy brings both to the host.
+__global__ void k_total_to_ctr(const int64_t *total, DevCounters *ctr) { ctr->spare[1] = (unsigned long long)*total; }
+
 // Core flags in the input order and their number (one counter atomic per
 // block).
 __global__ void k_core_flags(const int32_t *__restrict__ cnt, const int32_t *__restrict__ perm, int64_t n,
@@ -304,11 +308,13 @@ static void compute_counts(Grid &g, sj_path path, bool timed, CountRun &cr, hipS
     if (g.n > 0) refine_count(g, path, g.cnt, ro, s);
     else fill_zero(g.ctr, sizeof(DevCounters), s);
     exclusive_scan_i32_to_i64(g.cnt, g.off, g.n + 1, s);
-    int64_t total = 0;  // total and the counters: one sync
+    // the total and the counters: one copy, one sync
+    hipLaunchKernelGGL(k_total_to_ctr, dim3(1), dim3(1), 0, s, g.off + g.n, g.ctr);
+    SJ_HIP(hipGetLastError());
     DevCounters hctr{};
-    SJ_HIP(hipMemcpyAsync(&total, g.off + g.n, sizeof total, hipMemcpyDeviceToHost, s));
     SJ_HIP(hipMemcpyAsync(&hctr, g.ctr, sizeof hctr, hipMemcpyDeviceToHost, s));
     SJ_HIP(hipStreamSynchronize(s));
+    const int64_t total = (int64_t)hctr.spare[1];
     g.total = total;
     g.masks_valid = ro.masks != nullptr;
     g.lp_masks_valid = ro.record_lp && g.lp_masks != nullptr;

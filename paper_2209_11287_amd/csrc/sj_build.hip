@@ -82,6 +82,29 @@ static void fill_zero_many(std::initializer_list<std::pair<void *, size_t>> segs
     SJ_HIP(hipGetLastError());
 }
 
+// What the host reads back after the grid build's device work: the table
+// sizes, the radix sort's error flag, the largest squared norm and the
+// item candidate / tile totals.
+struct BuildReadback {
+    int32_t c[4];  // ncells, nlines, nitems, nblocks
+    int32_t err;
+    int32_t pad;
+    double nmax;
+    unsigned long long acc[3];  // item candidates, tiles, united candidates
+};
+
+__global__ void k_build_readback(const int32_t *__restrict__ counters, const int32_t *__restrict__ err,
+                                 const double *__restrict__ nmax, const unsigned long long *__restrict__ acc,
+                                 BuildReadback *__restrict__ out) {
+    BuildReadback r;
+    for (int i = 0; i < 4; ++i) r.c[i] = counters[i];
+    r.err = *err;
+    r.pad = 0;
+    r.nmax = *nmax;
+    for (int i = 0; i < 3; ++i) r.acc[i] = acc[i];
+    *out = r;
+}
+
 void fill_ones(void *p, size_t bytes, hipStream_t s) {
     if (!bytes) return;
     unsigned blocks = (unsigned)std::min<size_t>((bytes + kThreads - 1) / kThreads, 4096);
@@ -1631,17 +1654,20 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
         hipLaunchKernelGGL(k_tiles_total, dim3(1), dim3(1), 0, s, g.tile_off, counters + 2, acc + 1);
         SJ_HIP(hipGetLastError());
     }
-    // ---- one host sync: table sizes, candidates of the items, nmax ----
-    int32_t hc[4] = {0, 0, 0, 0};
-    int32_t herr = 0;
-    double hn = 0.0;
-    unsigned long long hacc[3] = {0, 0, 0};
+    // ---- one host sync: table sizes, candidates of the items, nmax (gathered
+    // on the device into one block, so that one copy brings them all) ----
+    BuildReadback rb{};
+    BuildReadback *rb_dev = nullptr;
     if (n > 0) {
-        SJ_HIP(hipMemcpyAsync(hc, counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        SJ_HIP(hipMemcpyAsync(&herr, os_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        SJ_HIP(hipMemcpyAsync(&hn, g.dev_nmax, sizeof(double), hipMemcpyDeviceToHost, s));
-        SJ_HIP(hipMemcpyAsync(hacc, acc, sizeof hacc, hipMemcpyDeviceToHost, s));
+        rb_dev = dev_alloc_n<BuildReadback>(1, s);
+        hipLaunchKernelGGL(k_build_readback, dim3(1), dim3(1), 0, s, counters, os_err, g.dev_nmax, acc, rb_dev);
+        SJ_HIP(hipGetLastError());
+        SJ_HIP(hipMemcpyAsync(&rb, rb_dev, sizeof rb, hipMemcpyDeviceToHost, s));
     }
+    const int32_t *hc = rb.c;
+    const int32_t herr = rb.err;
+    const double hn = rb.nmax;
+    const unsigned long long *hacc = rb.acc;
     if (ev1) {
         SJ_HIP(hipEventRecord(ev1, s));
         SJ_HIP(hipEventSynchronize(ev1));
@@ -1661,6 +1687,7 @@ void build_grid(Grid &g, const double *points, int64_t n, int d, double eps, int
     g.cand_items = (int64_t)(g.united ? hacc[2] : hacc[0]);
     g.tiles = (int64_t)hacc[1];
 
+    if (rb_dev) dev_free(rb_dev, s);
     dev_free(acc, s);
     dev_free(item_tiles, s);
     dev_free(key_a, s);
