@@ -238,3 +238,32 @@ def test_batch_with_empty_problems(path, symmetric):
     for i in range(len(probs)):
         assert np.array_equal(pair_keys(out[offs[i]:offs[i + 1]]), pair_keys(want[i])), i
     selfjoin_batch_free(b)
+
+
+@pytest.mark.parametrize("symmetric", [0, 1])
+def test_batch_of_many_tiny_problems(symmetric):
+    """1100 problems of 0 to 40 points (d = 2, 3, 8): more problems than the
+    per-point-count reset kernel's grid rows (1024) and the oracle's totals
+    and pair sets for every problem."""
+    import torch
+
+    import oracle
+    from paper_2209_11287_amd import (selfjoin_batch_build, selfjoin_batch_count, selfjoin_batch_free,
+                                      selfjoin_batch_pairs)
+    rng = np.random.default_rng(23)
+    probs = []
+    for i in range(1100):
+        n = int(rng.integers(0, 41))
+        d = (2, 3, 8)[i % 3]
+        probs.append((rng.random((n, d)), 0.35 if d == 8 else 0.15))
+    pts = [torch.from_numpy(X).to("cuda:0") for X, _ in probs]
+    want = [oracle.grid_pairs(X, e)[2] for X, e in probs]
+    b = selfjoin_batch_build(pts, [e for _, e in probs], symmetric=symmetric)
+    totals, _ = selfjoin_batch_count(b, "fp64_mfma")
+    assert totals == [len(w) for w in want]
+    buf = torch.empty((max(1, sum(totals)), 2), dtype=torch.int32, device="cuda:0")
+    offs, _ = selfjoin_batch_pairs(b, "fp64_mfma", buf)
+    out = buf.cpu().numpy()
+    for i in range(len(probs)):
+        assert np.array_equal(pair_keys(out[offs[i]:offs[i + 1]]), pair_keys(want[i])), i
+    selfjoin_batch_free(b)
