@@ -267,3 +267,36 @@ def test_batch_of_many_tiny_problems(symmetric):
     for i in range(len(probs)):
         assert np.array_equal(pair_keys(out[offs[i]:offs[i + 1]]), pair_keys(want[i])), i
     selfjoin_batch_free(b)
+
+
+@pytest.mark.parametrize("symmetric", [0, 1])
+@pytest.mark.parametrize("path", ["fp64_mfma", "fp64_valu"])
+def test_batch_ties_and_duplicates(path, symmetric):
+    """Integer-lattice problems with eps = 1 (pairs at exactly eps), every
+    point of a problem present twice or more, and one problem of a single
+    repeated point, in one batch (d = 2, 3, 8, 16): the oracle's totals and
+    pair sets."""
+    import torch
+
+    import oracle
+    from paper_2209_11287_amd import (selfjoin_batch_build, selfjoin_batch_count, selfjoin_batch_free,
+                                      selfjoin_batch_pairs)
+    rng = np.random.default_rng(29)
+    probs = []
+    for d, side, n in ((2, 30, 900), (3, 10, 700), (8, 3, 600), (16, 2, 400)):
+        L = rng.integers(0, side, size=(n, d)).astype(np.float64)
+        X = np.concatenate([L, L[: n // 3]])
+        probs.append((X[rng.permutation(X.shape[0])], 1.0))
+    probs.append((np.full((300, 3), 0.25), 0.5))
+    pts = [torch.from_numpy(X).to("cuda:0") for X, _ in probs]
+    want = [oracle.grid_pairs(X, e)[2] for X, e in probs]
+    b = selfjoin_batch_build(pts, [e for _, e in probs], symmetric=symmetric)
+    totals, _ = selfjoin_batch_count(b, path)
+    assert totals == [len(w) for w in want]
+    assert totals[-1] == 300 * 300
+    buf = torch.empty((max(1, sum(totals)), 2), dtype=torch.int32, device="cuda:0")
+    offs, _ = selfjoin_batch_pairs(b, path, buf)
+    out = buf.cpu().numpy()
+    for i in range(len(probs)):
+        assert np.array_equal(pair_keys(out[offs[i]:offs[i + 1]]), pair_keys(want[i])), i
+    selfjoin_batch_free(b)
